@@ -1,0 +1,284 @@
+/*
+ * kgs.h -- C ABI of the MI355X (gfx950) differentiable Gaussian rasterizer and
+ * the multi-view densify / prune statistics of lifecycle-managed Gaussian
+ * mapping (KiloGS-SLAM, arXiv 2606.30436).
+ *
+ * Conventions shared by every entry point
+ *   * Plain C types only.  Arrays are caller-owned DEVICE memory unless a
+ *     comment says "host".  Nothing here allocates device memory: every
+ *     scratch buffer lives in the caller-allocated workspace handed to
+ *     kgs_create.
+ *   * Work is enqueued on the caller's stream (hipStream_t passed as void*;
+ *     NULL means the default stream).  Calls return after enqueueing; results
+ *     are valid after the stream is synchronised.
+ *   * Argument errors are found on the host before anything is enqueued and
+ *     return KGS_ERR_INVALID_ARG.  HIP launch errors return KGS_ERR_HIP.
+ *     Conditions found on the device (capacity overflow, non-finite input)
+ *     set bits of a device status word read by kgs_status_read.
+ *   * One context per stream; a context is not thread safe.
+ *   * Gaussian parameters are structure-of-arrays, Gaussian index fastest:
+ *       means [3][N], log_scales [3][N], quats [4][N] (w, x, y, z; any
+ *       non-zero length), opacity_logits [N], sh [K][3][N] with
+ *       K = (sh_degree + 1)^2 real spherical-harmonic coefficients per colour
+ *       channel (index l^2 + l + m, Condon-Shortley phase).
+ *   * Images are planar: colour [V][3][H][W], depth / t_final / last [V][H][W].
+ *     Pixel (x, y) samples the image plane at (x + 0.5, y + 0.5).
+ *
+ * The method computed (paper sections cited per entry point below):
+ *   pose        T' = Exp(xi) T  for a world->camera pose T and a tangent
+ *               xi = (rho, phi) in se(3).
+ *   project     EWA splatting of each Gaussian: camera point, 2D covariance
+ *               J W Sigma W^T J^T + eps I, its inverse (conic), pixel centre,
+ *               opacity o = sigmoid(logit), view-dependent colour
+ *               max(0, SH(dir) + 0.5), depth = camera z.
+ *   bin + sort  one (tile, Gaussian) pair per tile of the Gaussian's
+ *               opacity-aware pixel rectangle, sorted by
+ *               (view, tile, fp32 depth, Gaussian index).
+ *   render_fwd  front-to-back alpha compositing of colour and depth with
+ *               transmittance T_j = prod_{m<j}(1 - alpha_m) (appendix,
+ *               "Depth Volume Rendering"): D = sum_j T_j alpha_j z_j.
+ *   render_bwd  exact gradient of render_fwd + project for all Gaussian
+ *               parameters and the 6-DoF pose, recomputing the per-pixel
+ *               sequences; plus per Gaussian the footprint |Omega_v(i)| (pixels
+ *               where it is blended) and kappa_v(i), the number of those pixels
+ *               with ||I_v - I^_v||_1 > tau_err (appendix, "Densification
+ *               Score").
+ *   stats       chunk scores S_d and S_p and their global OR / max merge
+ *               (Sec. 3.3 "Global Densification / Pruning Rules"; appendix
+ *               "Densification Score", "Pruning Score").
+ *   decide      PRUNE if S_p(i) > tau_p, else DENSIFY if S_d(i), else KEEP.
+ */
+#ifndef KGS_H
+#define KGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  KGS_OK = 0,
+  KGS_ERR_INVALID_ARG = 1,
+  KGS_ERR_HIP = 2,
+  KGS_ERR_CAPACITY = 3,   /* a device capacity was exceeded: outputs undefined, regrow and rerun */
+  KGS_ERR_NONFINITE = 4,  /* a non-finite parameter was met */
+  KGS_ERR_STATE = 5       /* call order violated (e.g. render before project) */
+} kgs_status;
+
+/* device status word bits (kgs_status_read) */
+#define KGS_FLAG_SLOT_OVERFLOW 0x1u
+#define KGS_FLAG_PAIR_OVERFLOW 0x2u
+#define KGS_FLAG_NONFINITE 0x4u
+
+/* decision codes written by kgs_densify_prune_decide */
+#define KGS_KEEP 0
+#define KGS_DENSIFY 1
+#define KGS_PRUNE 2
+
+/* Pinhole camera, world->camera: x_cam = R x_world + t, R row major.
+ * Camera axes: x right, y down, z forward.  72 bytes. */
+typedef struct kgs_camera {
+  float R[9];
+  float t[3];
+  float fx, fy, cx, cy;
+  int32_t width, height;
+} kgs_camera;
+
+/* Rasterizer configuration.  The paper inherits its rasterizer from 3DGS and
+ * states none of these constants; kgs_config_default fills the readings
+ * alpha_min = 1/255, alpha_max = 0.99, t_min = 1e-4, near_z = 0.2,
+ * eps2d = 0.3 px^2, guard = 1.3, rect_margin = 1/256, bg = 0. */
+typedef struct kgs_config {
+  int32_t tile_w, tile_h;   /* 16x16, 8x32 or 32x8 */
+  int32_t batch;            /* Gaussians staged per LDS batch: 32, 64, 128 or 256 */
+  int32_t sh_degree;        /* 0..3 */
+  float alpha_min, alpha_max, t_min, near_z, eps2d, guard, rect_margin;
+  float bg[3];
+  int32_t width, height;    /* image size of every view */
+  int32_t max_views;        /* 1..64 views per call */
+  int32_t pad_;
+  int64_t max_gaussians;
+  int64_t slot_capacity;    /* visible (view, Gaussian) records per call */
+  int64_t pair_capacity;    /* (tile, Gaussian) pairs per call, < 2^32 */
+} kgs_config;
+
+typedef struct kgs_gaussians {
+  const float* means;
+  const float* log_scales;
+  const float* quats;
+  const float* opacity_logits;
+  const float* sh;
+  int64_t n;
+  int32_t sh_degree;
+  int32_t pad_;
+} kgs_gaussians;
+
+typedef struct kgs_image {
+  float* color;     /* [V][3][H][W] = composited colour + t_final * bg */
+  float* depth;     /* [V][H][W]   = sum_j T_j alpha_j z_j (not normalised) */
+  float* t_final;   /* [V][H][W]   transmittance after the last blended Gaussian */
+  int32_t* last;    /* [V][H][W]   1 + position, in the pixel's tile list, of its last blended Gaussian (0: none) */
+} kgs_image;
+
+/* Gradients, ADDED to (caller zeroes them).  Same layouts as the parameters;
+ * pose_xi [V][6] with (rho, phi) order.  Any pointer may be NULL to skip it. */
+typedef struct kgs_grads {
+  float* means;
+  float* log_scales;
+  float* quats;
+  float* opacity_logits;
+  float* sh;
+  float* pose_xi;
+} kgs_grads;
+
+/* Per-Gaussian statistics accumulated over the views of a chunk ([N] each,
+ * ADDED to; the caller zeroes them at the start of a chunk).  Any may be NULL.
+ *   kappa_sum      sum_v kappa_v(i)
+ *   omega_sum      sum_v |Omega_v(i)|
+ *   gamma_sum      sum_v L_v |Omega_v(i)|   (L_v: the view's photometric loss)
+ *   grad_norm_sum  sum_v ||dL/d mu2D_v(i)||_2 in pixels (3DGS positional statistic)
+ *   view_count     number of views in which i is visible
+ *   max_radius     max_v of the larger pixel half-extent of i (MAX-merged) */
+typedef struct kgs_view_stats {
+  uint32_t* kappa_sum;
+  uint32_t* omega_sum;
+  double* gamma_sum;
+  float* grad_norm_sum;
+  uint32_t* view_count;
+  int32_t* max_radius;
+} kgs_view_stats;
+
+/* Global lifecycle state, [N] each: S_d(i) as 0/1 and S_p(i). */
+typedef struct kgs_lifecycle_state {
+  uint8_t* densify;
+  double* prune_score;
+} kgs_lifecycle_state;
+
+/* Device buffers of the last project / bin_sort call (for tests and tools).
+ * All pointers are into the workspace; counts are device pointers. */
+typedef struct kgs_buffers {
+  const uint32_t* n_slots;      /* device scalar */
+  const uint32_t* n_pairs;      /* device scalar */
+  const float* slot_rec;        /* [S][12]: mu_x-0.5, mu_y-0.5, A, B, C, log2 o, depth, -, r, g, b, - */
+  const uint32_t* slot_gid;     /* [S] Gaussian index */
+  const uint32_t* slot_view;    /* [S] view */
+  const int32_t* slot_pix;      /* [S][4]: floor(mu_x), floor(mu_y), rx, ry */
+  const uint32_t* slot_pairoff; /* [S] first pair (emission order) */
+  const uint64_t* keys;         /* [P] sorted keys: (view*tiles + tile) << 32 | depth bits */
+  const uint32_t* sorted_slot;  /* [P] slot of each sorted pair */
+  const uint32_t* ranges;       /* [V*tiles][2] start, end in the sorted pairs */
+  int32_t tiles_x, tiles_y;
+} kgs_buffers;
+
+/* A whole fwd + L1 loss + bwd + statistics pass over one chunk of views. */
+typedef struct kgs_chunk_desc {
+  kgs_gaussians gaussians;
+  const kgs_camera* cams;   /* device [V] */
+  const float* pose_xi;     /* device [V][6] or NULL */
+  int32_t n_views;
+  float tau_err;
+  const float* target;      /* device [V][3][H][W] */
+  kgs_image image;          /* outputs */
+  float* dl_dcolor;         /* device [V][3][H][W] scratch: dL/dC of the L1 loss */
+  float* view_loss;         /* device [V]: mean |C - I| per view */
+  kgs_grads grads;
+  kgs_view_stats stats;
+} kgs_chunk_desc;
+
+typedef struct kgs_ctx kgs_ctx;
+typedef struct kgs_graph kgs_graph;
+
+/* Fill cfg with the default readings for an image of width x height. */
+void kgs_config_default(kgs_config* cfg, int32_t width, int32_t height);
+
+/* Bytes of device workspace a context with this configuration needs (host only). */
+kgs_status kgs_workspace_size(const kgs_config* cfg, size_t* bytes);
+
+/* Create a context over caller-owned device memory of at least
+ * kgs_workspace_size bytes (256-byte aligned).  The context is host memory
+ * owned by the library; free it with kgs_destroy (the workspace stays the
+ * caller's). */
+kgs_status kgs_create(const kgs_config* cfg, void* workspace, size_t bytes, kgs_ctx** out);
+kgs_status kgs_destroy(kgs_ctx* ctx);
+
+/* Change the tile shape and LDS batch of an existing context (the workspace
+ * is sized for every supported shape).  Takes effect at the next project. */
+kgs_status kgs_set_tiling(kgs_ctx* ctx, int32_t tile_w, int32_t tile_h, int32_t batch);
+
+/* EWA projection of every Gaussian into every view (Sec. 3.2 map
+ * representation, rasterized as in 3DGS; depth is the camera z used by the
+ * appendix's depth rendering).  cams: device [V]; pose_xi: device [V][6] or
+ * NULL.  Culls z <= near_z, o < alpha_min and empty tile rectangles, and
+ * writes compact per-(view, Gaussian) records into the workspace.  Slot
+ * overflow sets KGS_FLAG_SLOT_OVERFLOW. */
+kgs_status kgs_project(kgs_ctx* ctx, const kgs_gaussians* g, const kgs_camera* cams, int32_t n_views,
+                       const float* pose_xi, void* stream);
+
+/* Tile binning and depth sort of the projected records ("sorted Gaussians",
+ * appendix, Depth Volume Rendering): one pair per tile of each record's
+ * rectangle, keys (view * tiles + tile) << 32 | fp32 depth bits, LSD radix
+ * sort (stable: equal keys keep Gaussian-index order), per-tile ranges.
+ * Pair overflow sets KGS_FLAG_PAIR_OVERFLOW. */
+kgs_status kgs_bin_sort(kgs_ctx* ctx, void* stream);
+
+/* Front-to-back compositing of every tile of every view (appendix, Depth
+ * Volume Rendering; colour composited with the same weights). */
+kgs_status kgs_render_fwd(kgs_ctx* ctx, const kgs_image* out, void* stream);
+
+/* L1 photometric loss per view (harness for the paper's photometric loss,
+ * Sec. 3.2 mapping loss): view_loss[v] = mean |C - I| over pixels and
+ * channels; dl_dcolor = sign(C - I) / (3 H W).  target: device [V][3][H][W]. */
+kgs_status kgs_loss_l1(kgs_ctx* ctx, const float* target, const kgs_image* img, float* dl_dcolor,
+                       float* view_loss, void* stream);
+
+/* Backward of render_fwd and project for the last projected views, plus the
+ * per-view footprint statistics (appendix, densification and pruning
+ * scores: Omega_v(i), M_v, kappa_v(i), gamma_v(i) = L_v |Omega_v(i)|).
+ * dl_dcolor [V][3][H][W] (required), dl_ddepth [V][H][W] (or NULL);
+ * target [V][3][H][W] or NULL (then kappa is not counted); view_loss [V] or
+ * NULL (then gamma is not accumulated).  g, cams and pose_xi must be those of
+ * the matching kgs_project.  grads and stats are ADDED to. */
+kgs_status kgs_render_bwd(kgs_ctx* ctx, const kgs_gaussians* g, const kgs_camera* cams, int32_t n_views,
+                          const float* pose_xi, const kgs_image* fwd, const float* dl_dcolor,
+                          const float* dl_ddepth, const float* target, float tau_err,
+                          const float* view_loss, const kgs_grads* grads, const kgs_view_stats* stats,
+                          void* stream);
+
+/* Close a chunk (appendix, Densification Score and Pruning Score; Sec. 3.3
+ * global rules):  S_d = kappa_sum / n_views,  L = ln(1 + gamma_sum),
+ * S_p = (L - min_A L) / (max_A L - min_A L) over A = {omega_sum > 0} (0 off A
+ * and when max == min);  densify |= S_d > tau_d;  prune_score = max(prune_score, S_p).
+ * L, S_p and the min / max are computed in FP64.  If reset != 0 the chunk sums
+ * (kappa, omega, gamma) are zeroed afterwards. */
+kgs_status kgs_accumulate_stats(kgs_ctx* ctx, const kgs_view_stats* stats, int64_t n, int32_t n_views,
+                                const kgs_lifecycle_state* state, float tau_d, int32_t reset, void* stream);
+
+/* decision[i] = PRUNE if prune_score > tau_p, else DENSIFY if densify, else
+ * KEEP (Sec. 3.3).  keep_map (or NULL): exclusive prefix count of survivors;
+ * n_keep (device scalar, or NULL).  tau_p is a double so that 0.99 is not
+ * moved by float rounding (prune scores are FP64). */
+kgs_status kgs_densify_prune_decide(kgs_ctx* ctx, const kgs_lifecycle_state* state, int64_t n, double tau_p,
+                                    uint8_t* decision, uint32_t* keep_map, uint32_t* n_keep, void* stream);
+
+/* The whole chunk: project, bin_sort, render_fwd, loss_l1, render_bwd. */
+kgs_status kgs_chunk_run(kgs_ctx* ctx, const kgs_chunk_desc* desc, void* stream);
+
+/* Record kgs_chunk_run into a HIP graph (stream capture) and launch it. */
+kgs_status kgs_chunk_capture(kgs_ctx* ctx, const kgs_chunk_desc* desc, kgs_graph** out);
+kgs_status kgs_chunk_launch(kgs_graph* graph, void* stream);
+kgs_status kgs_graph_destroy(kgs_graph* graph);
+
+/* Synchronous reads (the caller synchronises the stream first). */
+kgs_status kgs_status_read(kgs_ctx* ctx, uint32_t* flags);
+kgs_status kgs_status_clear(kgs_ctx* ctx, void* stream);
+kgs_status kgs_counts_read(kgs_ctx* ctx, int64_t* n_slots, int64_t* n_pairs);
+kgs_status kgs_get_buffers(kgs_ctx* ctx, kgs_buffers* out);
+
+const char* kgs_status_string(kgs_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KGS_H */

@@ -77,7 +77,8 @@ def lib():
             L.orc_view_n_visible.argtypes = [ctypes.c_void_p]
             L.orc_view_n_pairs.restype = ctypes.c_int64
             L.orc_view_n_pairs.argtypes = [ctypes.c_void_p]
-            L.orc_view_image.argtypes = [ctypes.c_void_p, _d, _d, _d, _i32, _i32, _d, _d]
+            L.orc_view_image.argtypes = [ctypes.c_void_p, _d, _d, _d, _i32, _i32, _d]
+            L.orc_view_gauss_margins.argtypes = [ctypes.c_void_p, _d]
             L.orc_view_proj.argtypes = [ctypes.c_void_p, _d, _i64, _d]
             L.orc_view_pairs.argtypes = [ctypes.c_void_p, _i32, _i64]
             L.orc_view_stats.argtypes = [ctypes.c_void_p, _f, ctypes.c_double, _i32, _i32, _u8, _d]
@@ -181,13 +182,24 @@ class View:
         return int(lib().orc_view_n_pairs(self._h))
 
     def image(self) -> dict:
+        """Colour, depth, final transmittance, last blended position, blended
+        count, and four decision-margin planes per pixel (relative distance of
+        alpha from alpha_min, of a candidate T from T_min, of alpha from the
+        alpha_max clamp, and the smallest relative depth gap)."""
         H, W = self.H, self.W
         out = dict(color=np.empty((3, H, W)), depth=np.empty((H, W)), tfinal=np.empty((H, W)),
                    last=np.empty((H, W), np.int32), nblend=np.empty((H, W), np.int32),
-                   margin_img=np.empty((H, W)), margin_grad=np.empty((H, W)))
+                   margins=np.empty((4, H, W)))
         lib().orc_view_image(self._h, _ptr(out["color"], _d), _ptr(out["depth"], _d),
                              _ptr(out["tfinal"], _d), _ptr(out["last"], _i32), _ptr(out["nblend"], _i32),
-                             _ptr(out["margin_img"], _d), _ptr(out["margin_grad"], _d))
+                             _ptr(out["margins"], _d))
+        return out
+
+    def gauss_margins(self) -> np.ndarray:
+        """[N][3]: each Gaussian's own alpha-vs-alpha_min margin, alpha_max
+        margin, and the T_min margin where it ends a pixel's sequence."""
+        out = np.empty((self.n, 3))
+        lib().orc_view_gauss_margins(self._h, _ptr(out, _d))
         return out
 
     def proj(self) -> dict:

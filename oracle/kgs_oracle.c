@@ -266,7 +266,7 @@ typedef struct {
   int64_t* order;     /* visible Gaussians sorted by (fp32 depth, index) */
   int64_t* tile_off;  /* CSR over tiles */
   int64_t* tile_list;
-  double *color, *depthimg, *tfinal, *margin_img, *margin_grad;
+  double *color, *depthimg, *tfinal, *margins; /* margins [4][H][W] */
   int32_t* last;
   int32_t* nblend;
 } orc_view;
@@ -393,31 +393,36 @@ static void eval_pair(const orc_proj* p, double px, double py, double* dx, doubl
 
 static double relmargin(double a, double b) { return fabs(a - b) / fabs(b); }
 
-/* Composite one pixel front to back; fills outputs, returns the margins. */
+/* Composite one pixel front to back; fills outputs and the decision margins:
+ *   m[0]  min relative distance of an evaluated alpha from alpha_min
+ *   m[1]  min relative distance of a candidate transmittance from T_min
+ *   m[2]  min relative distance of a blended alpha from the alpha_max clamp
+ *   m[3]  min relative depth gap of consecutive blended Gaussians */
 static void composite_pixel(const orc_view* v, int px, int py, double* col, double* dep, double* T_out,
-                            int32_t* last, int32_t* nb, double* m_img, double* m_grad) {
+                            int32_t* last, int32_t* nb, double m[4]) {
   const int tile = (py / v->TH) * v->TX + (px / v->TW);
   const double cxp = px + 0.5, cyp = py + 0.5;
-  double T = 1.0, C[3] = {0, 0, 0}, D = 0.0, mi = INFINITY, mg = INFINITY, prevz = -1.0;
+  double T = 1.0, C[3] = {0, 0, 0}, D = 0.0, prevz = -1.0;
   int32_t lst = 0, cnt = 0;
+  m[0] = m[1] = m[2] = m[3] = INFINITY;
   for (int64_t e = v->tile_off[tile]; e < v->tile_off[tile + 1]; ++e) {
     const orc_proj* p = &v->P[v->tile_list[e]];
     double dx, dy, q, raw;
     eval_pair(p, cxp, cyp, &dx, &dy, &q, &raw);
-    double m = relmargin(raw, v->cfg.alpha_min);
-    if (m < mi) mi = m;
+    double r = relmargin(raw, v->cfg.alpha_min);
+    if (r < m[0]) m[0] = r;
     if (raw < v->cfg.alpha_min) continue;
     double a = raw < v->cfg.alpha_max ? raw : v->cfg.alpha_max;
-    m = relmargin(raw, v->cfg.alpha_max);
-    if (m < mg) mg = m;
+    r = relmargin(raw, v->cfg.alpha_max);
+    if (r < m[2]) m[2] = r;
     double Tn = T * (1.0 - a);
     if (v->cfg.t_min > 0.0) {
-      m = relmargin(Tn, v->cfg.t_min);
-      if (m < mi) mi = m;
+      r = relmargin(Tn, v->cfg.t_min);
+      if (r < m[1]) m[1] = r;
     }
     if (prevz >= 0.0) {
-      m = fabs(p->depth - prevz) / prevz;
-      if (m < mi) mi = m;
+      r = fabs(p->depth - prevz) / prevz;
+      if (r < m[3]) m[3] = r;
     }
     prevz = p->depth;
     if (Tn < v->cfg.t_min) break;
@@ -432,8 +437,6 @@ static void composite_pixel(const orc_view* v, int px, int py, double* col, doub
   *T_out = T;
   *last = lst;
   *nb = cnt;
-  *m_img = mi;
-  *m_grad = mg < mi ? mg : mi;
 }
 
 orc_view* orc_view_create(int64_t n, int32_t degree, const double* means, const double* log_scales,
@@ -481,18 +484,17 @@ orc_view* orc_view_create(int64_t n, int32_t degree, const double* means, const 
   v->color = (double*)malloc(sizeof(double) * 3 * (size_t)npix);
   v->depthimg = (double*)malloc(sizeof(double) * (size_t)npix);
   v->tfinal = (double*)malloc(sizeof(double) * (size_t)npix);
-  v->margin_img = (double*)malloc(sizeof(double) * (size_t)npix);
-  v->margin_grad = (double*)malloc(sizeof(double) * (size_t)npix);
+  v->margins = (double*)malloc(sizeof(double) * 4 * (size_t)npix);
   v->last = (int32_t*)malloc(sizeof(int32_t) * (size_t)npix);
   v->nblend = (int32_t*)malloc(sizeof(int32_t) * (size_t)npix);
 #pragma omp parallel for schedule(dynamic, 4)
   for (int py = 0; py < v->H; ++py)
     for (int px = 0; px < v->W; ++px) {
       const int64_t pix = (int64_t)py * v->W + px;
-      double col[3];
-      composite_pixel(v, px, py, col, &v->depthimg[pix], &v->tfinal[pix], &v->last[pix], &v->nblend[pix],
-                      &v->margin_img[pix], &v->margin_grad[pix]);
+      double col[3], m[4];
+      composite_pixel(v, px, py, col, &v->depthimg[pix], &v->tfinal[pix], &v->last[pix], &v->nblend[pix], m);
       for (int ch = 0; ch < 3; ++ch) v->color[ch * npix + pix] = col[ch];
+      for (int k = 0; k < 4; ++k) v->margins[k * npix + pix] = m[k];
     }
   return v;
 }
@@ -500,7 +502,7 @@ orc_view* orc_view_create(int64_t n, int32_t degree, const double* means, const 
 void orc_view_free(orc_view* v) {
   if (!v) return;
   free(v->P); free(v->order); free(v->tile_off); free(v->tile_list);
-  free(v->color); free(v->depthimg); free(v->tfinal); free(v->margin_img); free(v->margin_grad);
+  free(v->color); free(v->depthimg); free(v->tfinal); free(v->margins);
   free(v->last); free(v->nblend);
   free(v);
 }
@@ -509,15 +511,63 @@ int64_t orc_view_n_visible(const orc_view* v) { return v->n_vis; }
 int64_t orc_view_n_pairs(const orc_view* v) { return v->tile_off[(int64_t)v->TX * v->TY]; }
 
 void orc_view_image(const orc_view* v, double* color, double* depth, double* tfinal, int32_t* last,
-                    int32_t* nblend, double* margin_img, double* margin_grad) {
+                    int32_t* nblend, double* margins) {
   const int64_t npix = (int64_t)v->W * v->H;
   if (color) memcpy(color, v->color, sizeof(double) * 3 * (size_t)npix);
   if (depth) memcpy(depth, v->depthimg, sizeof(double) * (size_t)npix);
   if (tfinal) memcpy(tfinal, v->tfinal, sizeof(double) * (size_t)npix);
   if (last) memcpy(last, v->last, sizeof(int32_t) * (size_t)npix);
   if (nblend) memcpy(nblend, v->nblend, sizeof(int32_t) * (size_t)npix);
-  if (margin_img) memcpy(margin_img, v->margin_img, sizeof(double) * (size_t)npix);
-  if (margin_grad) memcpy(margin_grad, v->margin_grad, sizeof(double) * (size_t)npix);
+  if (margins) memcpy(margins, v->margins, sizeof(double) * 4 * (size_t)npix);
+}
+
+/* Per-Gaussian decision margins over every pixel where it is evaluated:
+ * out[i][0] its own alpha vs alpha_min, out[i][1] its own alpha vs the alpha_max
+ * clamp, out[i][2] the transmittance margin of the pixels where it is the
+ * last blended or the terminating Gaussian. */
+void orc_view_gauss_margins(const orc_view* v, double* out) {
+  const int64_t n = v->n;
+  for (int64_t i = 0; i < 3 * n; ++i) out[i] = INFINITY;
+#pragma omp parallel
+  {
+    double* loc = (double*)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < 3 * n; ++i) loc[i] = INFINITY;
+#pragma omp for schedule(dynamic, 4)
+    for (int py = 0; py < v->H; ++py)
+      for (int px = 0; px < v->W; ++px) {
+        const int tile = (py / v->TH) * v->TX + (px / v->TW);
+        double T = 1.0;
+        int64_t lastg = -1;
+        double lastm = INFINITY;
+        for (int64_t e = v->tile_off[tile]; e < v->tile_off[tile + 1]; ++e) {
+          const int64_t gi = v->tile_list[e];
+          const orc_proj* p = &v->P[gi];
+          double dx, dy, q, raw;
+          eval_pair(p, px + 0.5, py + 0.5, &dx, &dy, &q, &raw);
+          double r = relmargin(raw, v->cfg.alpha_min);
+          if (r < loc[gi * 3]) loc[gi * 3] = r;
+          if (raw < v->cfg.alpha_min) continue;
+          r = relmargin(raw, v->cfg.alpha_max);
+          if (r < loc[gi * 3 + 1]) loc[gi * 3 + 1] = r;
+          double a = raw < v->cfg.alpha_max ? raw : v->cfg.alpha_max;
+          double Tn = T * (1.0 - a);
+          double rt = v->cfg.t_min > 0.0 ? relmargin(Tn, v->cfg.t_min) : INFINITY;
+          if (Tn < v->cfg.t_min) {
+            if (rt < loc[gi * 3 + 2]) loc[gi * 3 + 2] = rt;
+            if (lastg >= 0 && rt < loc[lastg * 3 + 2]) loc[lastg * 3 + 2] = rt;
+            break;
+          }
+          if (lastg >= 0 && lastm < loc[lastg * 3 + 2]) loc[lastg * 3 + 2] = lastm;
+          lastg = gi;
+          lastm = rt;
+          T = Tn;
+        }
+      }
+#pragma omp critical
+    for (int64_t i = 0; i < 3 * n; ++i)
+      if (loc[i] < out[i]) out[i] = loc[i];
+    free(loc);
+  }
 }
 
 /* Per-Gaussian projection outputs.  rec: [n][10] = mu_x, mu_y, conic a, b, c,

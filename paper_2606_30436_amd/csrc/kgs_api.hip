@@ -1,0 +1,361 @@
+// C ABI of the library: contexts over a caller-owned workspace, argument
+// checks, the entry points declared in include/kgs.h, and HIP graph capture
+// of a whole chunk.
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+
+#include "kgs_internal.h"
+
+kgs_status kgs_launch_project(kgs_ctx*, const kgs_gaussians*, const kgs_camera*, int, const float*, hipStream_t);
+kgs_status kgs_launch_bin_sort(kgs_ctx*, hipStream_t);
+kgs_status kgs_launch_render_fwd(kgs_ctx*, const kgs_image*, hipStream_t);
+kgs_status kgs_launch_loss(kgs_ctx*, const float*, const kgs_image*, float*, float*, hipStream_t);
+kgs_status kgs_launch_render_bwd(kgs_ctx*, const kgs_image*, const float*, const float*, const float*, float,
+                                 hipStream_t);
+kgs_status kgs_launch_project_bwd(kgs_ctx*, const kgs_gaussians*, const kgs_camera*, int, const float*,
+                                  const float*, const kgs_grads*, const kgs_view_stats*, hipStream_t);
+kgs_status kgs_launch_accumulate(kgs_ctx*, const kgs_view_stats*, int64_t, int, const kgs_lifecycle_state*, float,
+                                 int, hipStream_t);
+kgs_status kgs_launch_decide(kgs_ctx*, const kgs_lifecycle_state*, int64_t, double, uint8_t*, uint32_t*, uint32_t*,
+                             hipStream_t);
+
+kgs_status kgs_check_launch() {
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? KGS_OK : KGS_ERR_HIP;
+}
+
+namespace {
+
+bool tile_ok(int w, int h) { return (w == 16 && h == 16) || (w == 8 && h == 32) || (w == 32 && h == 8); }
+bool batch_ok(int b) { return b == 32 || b == 64 || b == 128 || b == 256; }
+
+int tiles_for(int W, int H, int tw, int th) { return ((W + tw - 1) / tw) * ((H + th - 1) / th); }
+
+int max_tiles_of(int W, int H) {
+  return std::max(tiles_for(W, H, 16, 16), std::max(tiles_for(W, H, 8, 32), tiles_for(W, H, 32, 8)));
+}
+
+size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Walk the workspace layout; with base == nullptr only the size is computed.
+size_t layout(const kgs_config& c, char* base, kgs_ctx* ctx) {
+  const int64_t V = c.max_views, N = std::max<int64_t>(c.max_gaussians, 1);
+  const int64_t nb = (N + KGS_BLOCK - 1) / KGS_BLOCK;
+  const int64_t S = std::max<int64_t>(c.slot_capacity, 1), P = std::max<int64_t>(c.pair_capacity, 1);
+  const int64_t T = (int64_t)max_tiles_of(c.width, c.height);
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char* {
+    char* p = base ? base + off : nullptr;
+    off = align_up(off + bytes);
+    return p;
+  };
+  char* p;
+  p = take(sizeof(CamDev) * V);                 if (ctx) ctx->cams = (CamDev*)p;
+  p = take(4 * V * N);                          if (ctx) ctx->vis = (uint32_t*)p;
+  p = take(8 * V * nb);                         if (ctx) ctx->blk_cnt = (uint32_t*)p;
+  p = take(8 * V * nb);                         if (ctx) ctx->blk_base = (uint32_t*)p;
+  p = take(4 * 64);                             if (ctx) ctx->counters = (uint32_t*)p;
+  p = take(48 * S);                             if (ctx) ctx->slot_rec = (float4*)p;
+  p = take(4 * S);                              if (ctx) ctx->slot_gid = (uint32_t*)p;
+  p = take(4 * S);                              if (ctx) ctx->slot_view = (uint32_t*)p;
+  p = take(16 * S);                             if (ctx) ctx->slot_pix = (int4*)p;
+  p = take(4 * S);                              if (ctx) ctx->slot_pairoff = (uint32_t*)p;
+  p = take(4 * S);                              if (ctx) ctx->slot_ntiles = (uint32_t*)p;
+  p = take(8 * P);                              if (ctx) ctx->keys[0] = (uint64_t*)p;
+  p = take(8 * P);                              if (ctx) ctx->keys[1] = (uint64_t*)p;
+  p = take(4 * P);                              if (ctx) ctx->vals[0] = (uint32_t*)p;
+  p = take(4 * P);                              if (ctx) ctx->vals[1] = (uint32_t*)p;
+  p = take(4 * P);                              if (ctx) ctx->pair_slot = (uint32_t*)p;
+  p = take(4 * P);                              if (ctx) ctx->sorted_slot = (uint32_t*)p;
+  p = take(8 * V * T);                          if (ctx) ctx->ranges = (uint2*)p;
+  p = take(48 * P);                             if (ctx) ctx->pair_grad = (float4*)p;
+  p = take(4 * 256 * KGS_SORT_BLOCKS);          if (ctx) ctx->radix_hist = (uint32_t*)p;
+  p = take(4 * 256 * KGS_MAX_PASSES);           if (ctx) ctx->radix_total = (uint32_t*)p;
+  p = take(24 * V * nb);                        if (ctx) ctx->pose_partial = (float*)p;
+  p = take(8 * V * KGS_LOSS_BLOCKS);            if (ctx) ctx->loss_partial = (double*)p;
+  p = take(16 * (nb + 1));                      if (ctx) ctx->mm_partial = (double*)p;
+  p = take(4 * (nb + 1));                       if (ctx) ctx->keep_partial = (uint32_t*)p;
+  return off;
+}
+
+kgs_status config_check(const kgs_config* c) {
+  if (!c) return KGS_ERR_INVALID_ARG;
+  if (!tile_ok(c->tile_w, c->tile_h) || !batch_ok(c->batch)) return KGS_ERR_INVALID_ARG;
+  if (c->sh_degree < 0 || c->sh_degree > 3) return KGS_ERR_INVALID_ARG;
+  if (c->width <= 0 || c->height <= 0 || c->width > 32000 || c->height > 32000) return KGS_ERR_INVALID_ARG;
+  if (c->max_views < 1 || c->max_views > KGS_MAX_VIEWS) return KGS_ERR_INVALID_ARG;
+  if (c->max_gaussians < 0 || c->max_gaussians >= (int64_t(1) << 32)) return KGS_ERR_INVALID_ARG;
+  if (c->slot_capacity < 0 || c->slot_capacity >= (int64_t(1) << 32)) return KGS_ERR_INVALID_ARG;
+  if (c->pair_capacity < 0 || c->pair_capacity >= (int64_t(1) << 32)) return KGS_ERR_INVALID_ARG;
+  if (!(c->alpha_min > 0.f && c->alpha_min < 1.f) || !(c->alpha_max > 0.f && c->alpha_max <= 1.f))
+    return KGS_ERR_INVALID_ARG;
+  if (!(c->t_min >= 0.f) || !(c->near_z > 0.f) || !(c->eps2d >= 0.f) || !(c->guard > 0.f)) return KGS_ERR_INVALID_ARG;
+  // keys hold the global tile index in 32 bits
+  if ((int64_t)c->max_views * max_tiles_of(c->width, c->height) >= (int64_t(1) << 31)) return KGS_ERR_INVALID_ARG;
+  return KGS_OK;
+}
+
+void set_tiling(kgs_ctx* ctx) {
+  ctx->tiles_x = (ctx->cfg.width + ctx->cfg.tile_w - 1) / ctx->cfg.tile_w;
+  ctx->tiles_y = (ctx->cfg.height + ctx->cfg.tile_h - 1) / ctx->cfg.tile_h;
+  ctx->n_tiles = ctx->tiles_x * ctx->tiles_y;
+}
+
+__global__ void k_clear_status(uint32_t* counters) {
+  if (threadIdx.x < 3) counters[threadIdx.x] = 0u;
+}
+
+bool gaussians_ok(const kgs_ctx* ctx, const kgs_gaussians* g) {
+  if (!g) return false;
+  if (g->n < 0 || g->n > ctx->cfg.max_gaussians) return false;
+  if (g->sh_degree < 0 || g->sh_degree > 3) return false;
+  if (g->n > 0 && (!g->means || !g->log_scales || !g->quats || !g->opacity_logits || !g->sh)) return false;
+  return true;
+}
+
+bool image_ok(const kgs_image* im) { return im && im->color && im->depth && im->t_final && im->last; }
+
+}  // namespace
+
+struct kgs_graph {
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+};
+
+extern "C" {
+
+void kgs_config_default(kgs_config* c, int32_t width, int32_t height) {
+  if (!c) return;
+  std::memset(c, 0, sizeof(*c));
+  c->tile_w = 16;
+  c->tile_h = 16;
+  c->batch = 128;
+  c->sh_degree = 3;
+  c->alpha_min = 1.0f / 255.0f;
+  c->alpha_max = 0.99f;
+  c->t_min = 1e-4f;
+  c->near_z = 0.2f;
+  c->eps2d = 0.3f;
+  c->guard = 1.3f;
+  c->rect_margin = 1.0f / 256.0f;
+  c->width = width;
+  c->height = height;
+  c->max_views = 1;
+  c->max_gaussians = 0;
+  c->slot_capacity = 0;
+  c->pair_capacity = 0;
+}
+
+kgs_status kgs_workspace_size(const kgs_config* cfg, size_t* bytes) {
+  const kgs_status s = config_check(cfg);
+  if (s != KGS_OK || !bytes) return KGS_ERR_INVALID_ARG;
+  *bytes = layout(*cfg, nullptr, nullptr);
+  return KGS_OK;
+}
+
+kgs_status kgs_create(const kgs_config* cfg, void* workspace, size_t bytes, kgs_ctx** out) {
+  if (config_check(cfg) != KGS_OK || !out || !workspace) return KGS_ERR_INVALID_ARG;
+  if (((uintptr_t)workspace & 255u) != 0) return KGS_ERR_INVALID_ARG;
+  if (bytes < layout(*cfg, nullptr, nullptr)) return KGS_ERR_INVALID_ARG;
+  kgs_ctx* ctx = new (std::nothrow) kgs_ctx();
+  if (!ctx) return KGS_ERR_INVALID_ARG;
+  ctx->cfg = *cfg;
+  ctx->ws = (char*)workspace;
+  ctx->ws_bytes = bytes;
+  ctx->max_tiles = max_tiles_of(cfg->width, cfg->height);
+  ctx->nb_max = (std::max<int64_t>(cfg->max_gaussians, 1) + KGS_BLOCK - 1) / KGS_BLOCK;
+  layout(*cfg, (char*)workspace, ctx);
+  set_tiling(ctx);
+  *out = ctx;
+  return KGS_OK;
+}
+
+kgs_status kgs_destroy(kgs_ctx* ctx) {
+  delete ctx;
+  return KGS_OK;
+}
+
+kgs_status kgs_set_tiling(kgs_ctx* ctx, int32_t tile_w, int32_t tile_h, int32_t batch) {
+  if (!ctx || !tile_ok(tile_w, tile_h) || !batch_ok(batch)) return KGS_ERR_INVALID_ARG;
+  ctx->cfg.tile_w = tile_w;
+  ctx->cfg.tile_h = tile_h;
+  ctx->cfg.batch = batch;
+  set_tiling(ctx);
+  ctx->projected = 0;
+  ctx->binned = 0;
+  return KGS_OK;
+}
+
+kgs_status kgs_project(kgs_ctx* ctx, const kgs_gaussians* g, const kgs_camera* cams, int32_t n_views,
+                       const float* pose_xi, void* stream) {
+  if (!ctx || !gaussians_ok(ctx, g) || !cams || n_views < 1 || n_views > ctx->cfg.max_views)
+    return KGS_ERR_INVALID_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(64), 0, st, ctx->counters);
+  ctx->last_views = n_views;
+  ctx->last_n = g->n;
+  ctx->last_degree = g->sh_degree;
+  ctx->proj_tile_w = ctx->cfg.tile_w;
+  ctx->proj_tile_h = ctx->cfg.tile_h;
+  const kgs_status s = kgs_launch_project(ctx, g, cams, n_views, pose_xi, st);
+  ctx->projected = (s == KGS_OK);
+  ctx->binned = 0;
+  return s;
+}
+
+kgs_status kgs_bin_sort(kgs_ctx* ctx, void* stream) {
+  if (!ctx) return KGS_ERR_INVALID_ARG;
+  if (!ctx->projected) return KGS_ERR_STATE;
+  const kgs_status s = kgs_launch_bin_sort(ctx, (hipStream_t)stream);
+  ctx->binned = (s == KGS_OK);
+  return s;
+}
+
+kgs_status kgs_render_fwd(kgs_ctx* ctx, const kgs_image* out, void* stream) {
+  if (!ctx || !image_ok(out)) return KGS_ERR_INVALID_ARG;
+  if (!ctx->binned) return KGS_ERR_STATE;
+  return kgs_launch_render_fwd(ctx, out, (hipStream_t)stream);
+}
+
+kgs_status kgs_loss_l1(kgs_ctx* ctx, const float* target, const kgs_image* img, float* dl_dcolor, float* view_loss,
+                       void* stream) {
+  if (!ctx || !target || !img || !img->color || !dl_dcolor || !view_loss) return KGS_ERR_INVALID_ARG;
+  if (!ctx->projected) return KGS_ERR_STATE;
+  return kgs_launch_loss(ctx, target, img, dl_dcolor, view_loss, (hipStream_t)stream);
+}
+
+kgs_status kgs_render_bwd(kgs_ctx* ctx, const kgs_gaussians* g, const kgs_camera* cams, int32_t n_views,
+                          const float* pose_xi, const kgs_image* fwd, const float* dl_dcolor, const float* dl_ddepth,
+                          const float* target, float tau_err, const float* view_loss, const kgs_grads* grads,
+                          const kgs_view_stats* stats, void* stream) {
+  if (!ctx || !gaussians_ok(ctx, g) || !cams || !image_ok(fwd) || !dl_dcolor || !grads) return KGS_ERR_INVALID_ARG;
+  if (!ctx->binned) return KGS_ERR_STATE;
+  if (n_views != ctx->last_views || g->n != ctx->last_n || g->sh_degree != ctx->last_degree) return KGS_ERR_STATE;
+  hipStream_t st = (hipStream_t)stream;
+  kgs_status s = kgs_launch_render_bwd(ctx, fwd, dl_dcolor, dl_ddepth, target, tau_err, st);
+  if (s != KGS_OK) return s;
+  return kgs_launch_project_bwd(ctx, g, cams, n_views, pose_xi, view_loss, grads, stats, st);
+}
+
+kgs_status kgs_accumulate_stats(kgs_ctx* ctx, const kgs_view_stats* stats, int64_t n, int32_t n_views,
+                                const kgs_lifecycle_state* state, float tau_d, int32_t reset, void* stream) {
+  if (!ctx || !stats || !state || n < 0 || n > ctx->cfg.max_gaussians || n_views < 1) return KGS_ERR_INVALID_ARG;
+  if (!stats->kappa_sum || !stats->omega_sum || !stats->gamma_sum || !state->densify || !state->prune_score)
+    return KGS_ERR_INVALID_ARG;
+  return kgs_launch_accumulate(ctx, stats, n, n_views, state, tau_d, reset, (hipStream_t)stream);
+}
+
+kgs_status kgs_densify_prune_decide(kgs_ctx* ctx, const kgs_lifecycle_state* state, int64_t n, double tau_p,
+                                    uint8_t* decision, uint32_t* keep_map, uint32_t* n_keep, void* stream) {
+  if (!ctx || !state || !state->densify || !state->prune_score || !decision || n < 0 ||
+      n > ctx->cfg.max_gaussians)
+    return KGS_ERR_INVALID_ARG;
+  return kgs_launch_decide(ctx, state, n, tau_p, decision, keep_map, n_keep, (hipStream_t)stream);
+}
+
+kgs_status kgs_chunk_run(kgs_ctx* ctx, const kgs_chunk_desc* d, void* stream) {
+  if (!ctx || !d || !d->target || !d->dl_dcolor || !d->view_loss) return KGS_ERR_INVALID_ARG;
+  kgs_status s = kgs_project(ctx, &d->gaussians, d->cams, d->n_views, d->pose_xi, stream);
+  if (s != KGS_OK) return s;
+  if ((s = kgs_bin_sort(ctx, stream)) != KGS_OK) return s;
+  if ((s = kgs_render_fwd(ctx, &d->image, stream)) != KGS_OK) return s;
+  if ((s = kgs_loss_l1(ctx, d->target, &d->image, d->dl_dcolor, d->view_loss, stream)) != KGS_OK) return s;
+  return kgs_render_bwd(ctx, &d->gaussians, d->cams, d->n_views, d->pose_xi, &d->image, d->dl_dcolor, nullptr,
+                        d->target, d->tau_err, d->view_loss, &d->grads, &d->stats, stream);
+}
+
+kgs_status kgs_chunk_capture(kgs_ctx* ctx, const kgs_chunk_desc* d, kgs_graph** out) {
+  if (!ctx || !d || !out) return KGS_ERR_INVALID_ARG;
+  hipStream_t st;
+  if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return KGS_ERR_HIP;
+  kgs_graph* g = new (std::nothrow) kgs_graph();
+  if (!g) {
+    hipStreamDestroy(st);
+    return KGS_ERR_INVALID_ARG;
+  }
+  kgs_status s = KGS_OK;
+  if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) s = KGS_ERR_HIP;
+  kgs_status run = KGS_OK;
+  if (s == KGS_OK) run = kgs_chunk_run(ctx, d, st);
+  hipGraph_t graph = nullptr;
+  if (s == KGS_OK && hipStreamEndCapture(st, &graph) != hipSuccess) s = KGS_ERR_HIP;
+  if (s == KGS_OK && run != KGS_OK) s = run;
+  if (s == KGS_OK && hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0) != hipSuccess) s = KGS_ERR_HIP;
+  hipStreamDestroy(st);
+  if (s != KGS_OK) {
+    if (graph) hipGraphDestroy(graph);
+    delete g;
+    return s;
+  }
+  g->graph = graph;
+  *out = g;
+  return KGS_OK;
+}
+
+kgs_status kgs_chunk_launch(kgs_graph* g, void* stream) {
+  if (!g) return KGS_ERR_INVALID_ARG;
+  return hipGraphLaunch(g->exec, (hipStream_t)stream) == hipSuccess ? KGS_OK : KGS_ERR_HIP;
+}
+
+kgs_status kgs_graph_destroy(kgs_graph* g) {
+  if (!g) return KGS_OK;
+  hipGraphExecDestroy(g->exec);
+  hipGraphDestroy(g->graph);
+  delete g;
+  return KGS_OK;
+}
+
+kgs_status kgs_status_read(kgs_ctx* ctx, uint32_t* flags) {
+  if (!ctx || !flags) return KGS_ERR_INVALID_ARG;
+  return hipMemcpy(flags, ctx->counters + 2, sizeof(uint32_t), hipMemcpyDeviceToHost) == hipSuccess ? KGS_OK
+                                                                                                       : KGS_ERR_HIP;
+}
+
+kgs_status kgs_status_clear(kgs_ctx* ctx, void* stream) {
+  if (!ctx) return KGS_ERR_INVALID_ARG;
+  hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(64), 0, (hipStream_t)stream, ctx->counters);
+  return kgs_check_launch();
+}
+
+kgs_status kgs_counts_read(kgs_ctx* ctx, int64_t* n_slots, int64_t* n_pairs) {
+  if (!ctx) return KGS_ERR_INVALID_ARG;
+  uint32_t c[2];
+  if (hipMemcpy(c, ctx->counters, sizeof c, hipMemcpyDeviceToHost) != hipSuccess) return KGS_ERR_HIP;
+  if (n_slots) *n_slots = c[0];
+  if (n_pairs) *n_pairs = c[1];
+  return KGS_OK;
+}
+
+kgs_status kgs_get_buffers(kgs_ctx* ctx, kgs_buffers* b) {
+  if (!ctx || !b) return KGS_ERR_INVALID_ARG;
+  b->n_slots = ctx->counters;
+  b->n_pairs = ctx->counters + 1;
+  b->slot_rec = (const float*)ctx->slot_rec;
+  b->slot_gid = ctx->slot_gid;
+  b->slot_view = ctx->slot_view;
+  b->slot_pix = (const int32_t*)ctx->slot_pix;
+  b->slot_pairoff = ctx->slot_pairoff;
+  b->keys = ctx->keys[ctx->sorted_buf];
+  b->sorted_slot = ctx->sorted_slot;
+  b->ranges = (const uint32_t*)ctx->ranges;
+  b->tiles_x = ctx->tiles_x;
+  b->tiles_y = ctx->tiles_y;
+  return KGS_OK;
+}
+
+const char* kgs_status_string(kgs_status s) {
+  switch (s) {
+    case KGS_OK: return "ok";
+    case KGS_ERR_INVALID_ARG: return "invalid argument";
+    case KGS_ERR_HIP: return "HIP error";
+    case KGS_ERR_CAPACITY: return "device capacity exceeded";
+    case KGS_ERR_NONFINITE: return "non-finite parameter";
+    case KGS_ERR_STATE: return "call order violated";
+  }
+  return "unknown status";
+}
+
+}  // extern "C"

@@ -1,0 +1,345 @@
+// Internal definitions of the gfx950 rasterizer library: workspace layout,
+// context, device camera, and the device helpers shared by the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/kgs.h"
+
+#define KGS_BLOCK 256                 // threads per block for per-Gaussian / per-tile kernels
+#define KGS_MAX_VIEWS 64
+#define KGS_SORT_BLOCKS 512           // fixed grid of the radix sort passes
+#define KGS_LOSS_BLOCKS 64            // blocks per view of the loss reduction
+#define KGS_MAX_PASSES 8
+
+// ---------------------------------------------------------------- device camera
+// Pose already applied: x_cam = R x + t; ctr = camera centre in the world.
+struct CamDev {
+  float R[9];
+  float t[3];
+  float ctr[3];
+  float fx, fy, cx, cy;
+  float lox, hix, loy, hiy;           // guard band on x/z and y/z
+  int32_t W, H;
+  int32_t pad0, pad1;
+  double Jl[36];                      // SE(3) left Jacobian at xi, row major, (rho, phi) order
+};
+
+// ---------------------------------------------------------------- context
+struct kgs_ctx {
+  kgs_config cfg;
+  char* ws;
+  size_t ws_bytes;
+  int tiles_x, tiles_y, n_tiles;      // current tiling, per view
+  int max_tiles;                      // max over supported tilings, per view
+  int64_t nb_max;                     // blocks of 256 over max_gaussians
+  // workspace carve-out
+  CamDev* cams;                       // [max_views]
+  uint32_t* vis;                      // [max_views][max_gaussians] tiles touched (0: culled)
+  uint32_t* blk_cnt;                  // [max_views][nb][2] visible count, tile count
+  uint32_t* blk_base;                 // [max_views][nb][2] exclusive bases
+  uint32_t* counters;                 // [64]: 0 n_slots, 1 n_pairs, 2 status, 3.. scratch
+  float4* slot_rec;                   // [S][3]
+  uint32_t* slot_gid;                 // [S]
+  uint32_t* slot_view;                // [S]
+  int4* slot_pix;                     // [S]
+  uint32_t* slot_pairoff;             // [S]
+  uint32_t* slot_ntiles;              // [S]
+  uint64_t* keys[2];                  // [P] ping-pong
+  uint32_t* vals[2];                  // [P] ping-pong (pair emission position)
+  uint32_t* pair_slot;                // [P] slot of each pair, by emission position
+  uint32_t* sorted_slot;              // [P] slot of each pair, by sorted position
+  uint2* ranges;                      // [max_views * max_tiles]
+  float4* pair_grad;                  // [P][3] per-pair record-space gradients + counts
+  uint32_t* radix_hist;               // [256][KGS_SORT_BLOCKS]
+  uint32_t* radix_total;              // [KGS_MAX_PASSES][256]
+  float* pose_partial;                // [max_views][nb][6]
+  double* loss_partial;               // [max_views][KGS_LOSS_BLOCKS]
+  double* mm_partial;                 // [nb][2]
+  uint32_t* keep_partial;             // [nb + 1]
+  // state
+  int last_views;
+  int64_t last_n;
+  int last_degree;
+  int passes;
+  int sorted_buf;                     // which ping-pong buffer holds the sorted pairs
+  int projected, binned;
+  int proj_tile_w, proj_tile_h;
+};
+
+// ---------------------------------------------------------------- helpers
+__device__ __forceinline__ int floordiv_i(int a, int b) {
+  int q = a / b;
+  if ((a % b != 0) && ((a < 0) != (b < 0))) --q;
+  return q;
+}
+
+__device__ __forceinline__ uint64_t ballot64(int pred) { return __ballot(pred); }
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint32_t mask_lt_count(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_inclusive_scan(T v) {
+  const int l = (int)lane_id();
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    T u = __shfl_up(v, o, 64);
+    if (l >= o) v += u;
+  }
+  return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Block-wide (256 threads) exclusive scan of two u32 values in thread order.
+// Returns the exclusive prefixes and the block totals.  Uses 16 words of LDS.
+__device__ __forceinline__ void block_scan2(uint32_t a, uint32_t b, uint32_t* sh, uint32_t& ea, uint32_t& eb,
+                                            uint32_t& ta, uint32_t& tb) {
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  uint32_t ia = wave_inclusive_scan(a), ib = wave_inclusive_scan(b);
+  if (l == 63) { sh[w] = ia; sh[4 + w] = ib; }
+  __syncthreads();
+  uint32_t oa = 0, ob = 0;
+  for (int k = 0; k < w; ++k) { oa += sh[k]; ob += sh[4 + k]; }
+  ta = sh[0] + sh[1] + sh[2] + sh[3];
+  tb = sh[4] + sh[5] + sh[6] + sh[7];
+  ea = oa + ia - a;
+  eb = ob + ib - b;
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------- projection
+// Everything that decides visibility and the pixel rectangle of Gaussian i in
+// one view.  Shared by the counting, emitting and backward kernels so that all
+// three take identical decisions.
+struct ProjCore {
+  float tx, ty, tz;
+  float ux, uy;          // x/z, y/z after the guard-band clamp
+  int clx, cly;          // clamp active
+  float J00, J02, J11, J12;
+  float T0[3], T1[3];    // rows of J R'
+  float S00, S01, S11;   // 2D covariance with the low-pass term
+  float det;
+  float mx, my;          // pixel-plane centre
+  int fxi, fyi, rx, ry;  // integer centre and half extents
+  int x0, x1, y0, y1;    // tile rectangle [x0, x1) x [y0, y1)
+};
+
+// cw: world covariance (xx, xy, xz, yy, yz, zz); o: opacity.  Returns visibility.
+__device__ __forceinline__ bool project_core(const CamDev& c, const float mu[3], const float cw[6], float o,
+                                             float near_z, float eps2d, float rect_margin, float log_qscale,
+                                             int tile_w, int tile_h, int tiles_x, int tiles_y, ProjCore& p) {
+  p.tx = c.R[0] * mu[0] + c.R[1] * mu[1] + c.R[2] * mu[2] + c.t[0];
+  p.ty = c.R[3] * mu[0] + c.R[4] * mu[1] + c.R[5] * mu[2] + c.t[1];
+  p.tz = c.R[6] * mu[0] + c.R[7] * mu[1] + c.R[8] * mu[2] + c.t[2];
+  if (!(p.tz > near_z)) return false;
+  const float iz = 1.0f / p.tz;
+  float ux = p.tx * iz, uy = p.ty * iz;
+  p.clx = 0;
+  p.cly = 0;
+  if (ux < c.lox) { ux = c.lox; p.clx = -1; } else if (ux > c.hix) { ux = c.hix; p.clx = 1; }
+  if (uy < c.loy) { uy = c.loy; p.cly = -1; } else if (uy > c.hiy) { uy = c.hiy; p.cly = 1; }
+  p.ux = ux;
+  p.uy = uy;
+  p.J00 = c.fx * iz;
+  p.J02 = -c.fx * ux * iz;
+  p.J11 = c.fy * iz;
+  p.J12 = -c.fy * uy * iz;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    p.T0[k] = p.J00 * c.R[k] + p.J02 * c.R[6 + k];
+    p.T1[k] = p.J11 * c.R[3 + k] + p.J12 * c.R[6 + k];
+  }
+  // U = T Sigma_w, Sigma2D = U T^T
+  const float U00 = p.T0[0] * cw[0] + p.T0[1] * cw[1] + p.T0[2] * cw[2];
+  const float U01 = p.T0[0] * cw[1] + p.T0[1] * cw[3] + p.T0[2] * cw[4];
+  const float U02 = p.T0[0] * cw[2] + p.T0[1] * cw[4] + p.T0[2] * cw[5];
+  const float U10 = p.T1[0] * cw[0] + p.T1[1] * cw[1] + p.T1[2] * cw[2];
+  const float U11 = p.T1[0] * cw[1] + p.T1[1] * cw[3] + p.T1[2] * cw[4];
+  const float U12 = p.T1[0] * cw[2] + p.T1[1] * cw[4] + p.T1[2] * cw[5];
+  p.S00 = U00 * p.T0[0] + U01 * p.T0[1] + U02 * p.T0[2] + eps2d;
+  p.S01 = U00 * p.T1[0] + U01 * p.T1[1] + U02 * p.T1[2];
+  p.S11 = U10 * p.T1[0] + U11 * p.T1[1] + U12 * p.T1[2] + eps2d;
+  p.det = p.S00 * p.S11 - p.S01 * p.S01;
+  if (!(p.det > 0.0f)) return false;
+  p.mx = c.fx * p.tx * iz + c.cx;
+  p.my = c.fy * p.ty * iz + c.cy;
+  const float BIG = 16777216.0f;
+  if (!(fabsf(p.mx) < BIG && fabsf(p.my) < BIG)) return false;
+  // alpha >= alpha_min needs q <= qmax = 2 ln(o / alpha_min); on that ellipse
+  // |dx| <= sqrt(qmax Sxx) and |dy| <= sqrt(qmax Syy).
+  const float qmax = 2.0f * (__logf(o) - log_qscale);
+  float ex = ceilf(sqrtf(qmax * p.S00) * (1.0f + rect_margin));
+  float ey = ceilf(sqrtf(qmax * p.S11) * (1.0f + rect_margin));
+  ex = fminf(ex, BIG);
+  ey = fminf(ey, BIG);
+  p.rx = (int)ex;
+  p.ry = (int)ey;
+  p.fxi = (int)floorf(p.mx);
+  p.fyi = (int)floorf(p.my);
+  int x0 = floordiv_i(p.fxi - p.rx, tile_w), x1 = floordiv_i(p.fxi + p.rx, tile_w) + 1;
+  int y0 = floordiv_i(p.fyi - p.ry, tile_h), y1 = floordiv_i(p.fyi + p.ry, tile_h) + 1;
+  p.x0 = max(x0, 0);
+  p.y0 = max(y0, 0);
+  p.x1 = min(x1, tiles_x);
+  p.y1 = min(y1, tiles_y);
+  return p.x0 < p.x1 && p.y0 < p.y1;
+}
+
+// Unit quaternion (w, x, y, z) -> rotation, and world covariance R diag(s^2) R^T.
+__device__ __forceinline__ void quat_rotation(const float q[4], float R[9]) {
+  const float w = q[0], x = q[1], y = q[2], z = q[3];
+  R[0] = 1.f - 2.f * (y * y + z * z); R[1] = 2.f * (x * y - w * z);       R[2] = 2.f * (x * z + w * y);
+  R[3] = 2.f * (x * y + w * z);       R[4] = 1.f - 2.f * (x * x + z * z); R[5] = 2.f * (y * z - w * x);
+  R[6] = 2.f * (x * z - w * y);       R[7] = 2.f * (y * z + w * x);       R[8] = 1.f - 2.f * (x * x + y * y);
+}
+
+__device__ __forceinline__ void world_cov(const float R[9], const float s[3], float cw[6]) {
+  const float s0 = s[0] * s[0], s1 = s[1] * s[1], s2 = s[2] * s[2];
+  cw[0] = R[0] * R[0] * s0 + R[1] * R[1] * s1 + R[2] * R[2] * s2;
+  cw[1] = R[0] * R[3] * s0 + R[1] * R[4] * s1 + R[2] * R[5] * s2;
+  cw[2] = R[0] * R[6] * s0 + R[1] * R[7] * s1 + R[2] * R[8] * s2;
+  cw[3] = R[3] * R[3] * s0 + R[4] * R[4] * s1 + R[5] * R[5] * s2;
+  cw[4] = R[3] * R[6] * s0 + R[4] * R[7] * s1 + R[5] * R[8] * s2;
+  cw[5] = R[6] * R[6] * s0 + R[7] * R[7] * s1 + R[8] * R[8] * s2;
+}
+
+// Per-Gaussian, view-independent quantities.
+struct GaussLocal {
+  float mu[3];
+  float qn[4], qnorm;
+  float s[3];
+  float Rq[9];
+  float cw[6];
+  float o;
+  bool ok;
+};
+
+__device__ __forceinline__ void load_gaussian(const kgs_gaussians& g, int64_t i, float alpha_min, GaussLocal& G,
+                                              bool& nonfinite) {
+  const int64_t n = g.n;
+  G.mu[0] = g.means[i];
+  G.mu[1] = g.means[n + i];
+  G.mu[2] = g.means[2 * n + i];
+  float q[4] = {g.quats[i], g.quats[n + i], g.quats[2 * n + i], g.quats[3 * n + i]};
+  float ls[3] = {g.log_scales[i], g.log_scales[n + i], g.log_scales[2 * n + i]};
+  const float lg = g.opacity_logits[i];
+  float chk = G.mu[0] + G.mu[1] + G.mu[2] + q[0] + q[1] + q[2] + q[3] + ls[0] + ls[1] + ls[2] + lg;
+  nonfinite = !isfinite(chk);
+  G.qnorm = sqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+  const float iq = 1.0f / G.qnorm;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) G.qn[k] = q[k] * iq;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) G.s[k] = __expf(ls[k]);
+  quat_rotation(G.qn, G.Rq);
+  world_cov(G.Rq, G.s, G.cw);
+  G.o = 1.0f / (1.0f + __expf(-lg));
+  G.ok = !nonfinite && G.qnorm > 0.0f && G.o >= alpha_min;
+}
+
+// ---------------------------------------------------------------- spherical harmonics
+// Real SH, Condon-Shortley phase, index l^2 + l + m, of a unit direction.
+namespace sh {
+constexpr float PI_F = 3.14159265358979323846f;
+}
+#define KGS_SQRT(x) __builtin_sqrtf(x)
+
+__device__ __forceinline__ void sh_basis(int degree, float x, float y, float z, float* Y) {
+  const float c0 = 0.5f * KGS_SQRT(1.0f / sh::PI_F);
+  Y[0] = c0;
+  if (degree < 1) return;
+  const float c1 = KGS_SQRT(3.0f / (4.0f * sh::PI_F));
+  Y[1] = -c1 * y;
+  Y[2] = c1 * z;
+  Y[3] = -c1 * x;
+  if (degree < 2) return;
+  const float a = 0.5f * KGS_SQRT(15.0f / sh::PI_F), b = 0.25f * KGS_SQRT(5.0f / sh::PI_F),
+              cc = 0.25f * KGS_SQRT(15.0f / sh::PI_F);
+  const float xx = x * x, yy = y * y, zz = z * z;
+  Y[4] = a * x * y;
+  Y[5] = -a * y * z;
+  Y[6] = b * (2.f * zz - xx - yy);
+  Y[7] = -a * x * z;
+  Y[8] = cc * (xx - yy);
+  if (degree < 3) return;
+  const float d3a = 0.25f * KGS_SQRT(35.0f / (2.0f * sh::PI_F)), d3b = 0.5f * KGS_SQRT(105.0f / sh::PI_F),
+              d3c = 0.25f * KGS_SQRT(21.0f / (2.0f * sh::PI_F)), d3d = 0.25f * KGS_SQRT(7.0f / sh::PI_F),
+              d3e = 0.25f * KGS_SQRT(105.0f / sh::PI_F);
+  Y[9] = -d3a * y * (3.f * xx - yy);
+  Y[10] = d3b * x * y * z;
+  Y[11] = -d3c * y * (4.f * zz - xx - yy);
+  Y[12] = d3d * z * (2.f * zz - 3.f * xx - 3.f * yy);
+  Y[13] = -d3c * x * (4.f * zz - xx - yy);
+  Y[14] = d3e * z * (xx - yy);
+  Y[15] = -d3a * x * (xx - 3.f * yy);
+}
+
+// Gradient of the polynomial extensions above: dY[k] = (d/dx, d/dy, d/dz).
+__device__ __forceinline__ void sh_basis_grad(int degree, float x, float y, float z, float (*dY)[3]) {
+  dY[0][0] = dY[0][1] = dY[0][2] = 0.f;
+  if (degree < 1) return;
+  const float c1 = KGS_SQRT(3.0f / (4.0f * sh::PI_F));
+  dY[1][0] = 0.f; dY[1][1] = -c1; dY[1][2] = 0.f;
+  dY[2][0] = 0.f; dY[2][1] = 0.f; dY[2][2] = c1;
+  dY[3][0] = -c1; dY[3][1] = 0.f; dY[3][2] = 0.f;
+  if (degree < 2) return;
+  const float a = 0.5f * KGS_SQRT(15.0f / sh::PI_F), b = 0.25f * KGS_SQRT(5.0f / sh::PI_F),
+              cc = 0.25f * KGS_SQRT(15.0f / sh::PI_F);
+  dY[4][0] = a * y;         dY[4][1] = a * x;         dY[4][2] = 0.f;
+  dY[5][0] = 0.f;           dY[5][1] = -a * z;        dY[5][2] = -a * y;
+  dY[6][0] = -2.f * b * x;  dY[6][1] = -2.f * b * y;  dY[6][2] = 4.f * b * z;
+  dY[7][0] = -a * z;        dY[7][1] = 0.f;           dY[7][2] = -a * x;
+  dY[8][0] = 2.f * cc * x;  dY[8][1] = -2.f * cc * y; dY[8][2] = 0.f;
+  if (degree < 3) return;
+  const float d3a = 0.25f * KGS_SQRT(35.0f / (2.0f * sh::PI_F)), d3b = 0.5f * KGS_SQRT(105.0f / sh::PI_F),
+              d3c = 0.25f * KGS_SQRT(21.0f / (2.0f * sh::PI_F)), d3d = 0.25f * KGS_SQRT(7.0f / sh::PI_F),
+              d3e = 0.25f * KGS_SQRT(105.0f / sh::PI_F);
+  const float xx = x * x, yy = y * y, zz = z * z;
+  dY[9][0] = -6.f * d3a * x * y;              dY[9][1] = -3.f * d3a * (xx - yy);          dY[9][2] = 0.f;
+  dY[10][0] = d3b * y * z;                    dY[10][1] = d3b * x * z;                    dY[10][2] = d3b * x * y;
+  dY[11][0] = 2.f * d3c * x * y;              dY[11][1] = -d3c * (4.f * zz - xx - 3.f * yy); dY[11][2] = -8.f * d3c * y * z;
+  dY[12][0] = -6.f * d3d * x * z;             dY[12][1] = -6.f * d3d * y * z;             dY[12][2] = d3d * (6.f * zz - 3.f * xx - 3.f * yy);
+  dY[13][0] = -d3c * (4.f * zz - 3.f * xx - yy); dY[13][1] = 2.f * d3c * x * y;           dY[13][2] = -8.f * d3c * x * z;
+  dY[14][0] = 2.f * d3e * x * z;              dY[14][1] = -2.f * d3e * y * z;             dY[14][2] = d3e * (xx - yy);
+  dY[15][0] = -3.f * d3a * (xx - yy);         dY[15][1] = 6.f * d3a * x * y;              dY[15][2] = 0.f;
+}
+
+// ---------------------------------------------------------------- compositing
+// Record of a projected Gaussian in the pixel loop (3 x float4):
+//   r0 = (mu_x - 0.5, mu_y - 0.5, A, B)   r1 = (C, log2 o, depth, -)   r2 = (r, g, b, -)
+// with A = -a/2 log2(e), B = -b log2(e), C = -c/2 log2(e) for the conic (a, b, c),
+// so that at pixel (x, y): log2 alpha = log2 o + A dx^2 + B dx dy + C dy^2 with
+// dx = x - r0.x, dy = y - r0.y (pixel centres at +0.5).  The same function is
+// used by the forward and the backward pass so both take identical decisions.
+__device__ __forceinline__ float log2_alpha(float px, float py, const float4& r0, float C, float lo, float& dx,
+                                            float& dy) {
+  dx = px - r0.x;
+  dy = py - r0.y;
+  const float t = __fmaf_rn(r0.z, dx, r0.w * dy);
+  const float u = __fmaf_rn(C * dy, dy, lo);
+  return __fmaf_rn(dx, t, u);
+}
+
+__device__ __forceinline__ float exp2_approx(float e) { return __builtin_amdgcn_exp2f(e); }
+
+// Pixel of lane `l` of wave `w` in a tile: every tile of 256 pixels is four
+// 8x8 sub-blocks, one per wave.
+__device__ __forceinline__ void tile_subblock(int tile_w, int w, int& sx, int& sy) {
+  if (tile_w == 16) { sx = (w & 1) * 8; sy = (w >> 1) * 8; }
+  else if (tile_w == 8) { sx = 0; sy = w * 8; }
+  else { sx = w * 8; sy = 0; }
+}
+
+// Host-side kernel launch helpers (defined in kgs_api.hip).
+kgs_status kgs_check_launch();

@@ -1,0 +1,315 @@
+// Projection: pose application, per-(view, Gaussian) visibility and tile
+// counts, the block-offset scan, and the compact record emission.
+//
+// Layout: one thread per Gaussian, looping over the views of the call, so the
+// 44 bytes of geometry of a Gaussian are read once per call (not once per
+// view); cameras are read with uniform addresses (scalar loads).  Records are
+// compacted in (view, Gaussian index) order by a deterministic two-pass scan
+// (per-block counts, then block bases), so slot and pair order never depend on
+// scheduling.
+#include "kgs_internal.h"
+
+// ---------------------------------------------------------------- camera setup
+// T' = Exp(xi) T with the closed-form SE(3) exponential:
+//   R_phi = I + (sin t / t) K + ((1 - cos t) / t^2) K^2,
+//   V     = I + ((1 - cos t) / t^2) K + ((t - sin t) / t^3) K^2,   K = [phi]x,
+//   R' = R_phi R,  t' = R_phi t + V rho.
+// Also the SE(3) left Jacobian [[J, Q], [0, J]] (J = V) used to turn the
+// left-perturbation gradient into d/dxi.
+namespace {
+struct M3 {
+  double a[9];
+};
+__device__ M3 m3_mul(const M3& A, const M3& B) {
+  M3 C;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) C.a[i * 3 + j] = A.a[i * 3] * B.a[j] + A.a[i * 3 + 1] * B.a[3 + j] + A.a[i * 3 + 2] * B.a[6 + j];
+  return C;
+}
+__device__ M3 m3_skew(double x, double y, double z) {
+  M3 K = {{0, -z, y, z, 0, -x, -y, x, 0}};
+  return K;
+}
+__device__ M3 m3_lin(double a, const M3& A, double b, const M3& B) {
+  M3 C;
+  for (int k = 0; k < 9; ++k) C.a[k] = a * A.a[k] + b * B.a[k];
+  return C;
+}
+}  // namespace
+
+__global__ void k_cam_setup(const kgs_camera* __restrict__ cams, const float* __restrict__ xi, int V, float guard,
+                            CamDev* __restrict__ out) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= V) return;
+  const kgs_camera c = cams[v];
+  double r[3] = {0, 0, 0}, p[3] = {0, 0, 0};
+  if (xi) {
+    for (int k = 0; k < 3; ++k) { r[k] = xi[v * 6 + k]; p[k] = xi[v * 6 + 3 + k]; }
+  }
+  const double th2 = p[0] * p[0] + p[1] * p[1] + p[2] * p[2], th = sqrt(th2);
+  double A, B, Cc, c2, c3;
+  if (th < 1e-3) {
+    A = 1.0 - th2 / 6.0 + th2 * th2 / 120.0;
+    B = 0.5 - th2 / 24.0 + th2 * th2 / 720.0;
+    Cc = 1.0 / 6.0 - th2 / 120.0 + th2 * th2 / 5040.0;
+    c2 = 1.0 / 24.0 - th2 / 720.0 + th2 * th2 / 40320.0;
+    c3 = 1.0 / 120.0 - th2 / 2520.0 + th2 * th2 / 120960.0;
+  } else {
+    const double s = sin(th), co = cos(th);
+    A = s / th;
+    B = (1.0 - co) / th2;
+    Cc = (th - s) / (th2 * th);
+    c2 = (th2 + 2.0 * co - 2.0) / (2.0 * th2 * th2);
+    c3 = (2.0 * th - 3.0 * s + th * co) / (2.0 * th2 * th2 * th);
+  }
+  const M3 I = {{1, 0, 0, 0, 1, 0, 0, 0, 1}};
+  const M3 K = m3_skew(p[0], p[1], p[2]);
+  const M3 K2 = m3_mul(K, K);
+  M3 Rphi = m3_lin(1.0, I, A, K);
+  Rphi = m3_lin(1.0, Rphi, B, K2);
+  M3 Vm = m3_lin(1.0, I, B, K);
+  Vm = m3_lin(1.0, Vm, Cc, K2);
+  M3 R0;
+  for (int k = 0; k < 9; ++k) R0.a[k] = c.R[k];
+  const M3 Rp = m3_mul(Rphi, R0);
+  double tp[3];
+  for (int i = 0; i < 3; ++i)
+    tp[i] = Rphi.a[i * 3] * c.t[0] + Rphi.a[i * 3 + 1] * c.t[1] + Rphi.a[i * 3 + 2] * c.t[2] +
+            Vm.a[i * 3] * r[0] + Vm.a[i * 3 + 1] * r[1] + Vm.a[i * 3 + 2] * r[2];
+  CamDev d;
+  for (int k = 0; k < 9; ++k) d.R[k] = (float)Rp.a[k];
+  for (int i = 0; i < 3; ++i) d.t[i] = (float)tp[i];
+  for (int j = 0; j < 3; ++j) d.ctr[j] = (float)(-(Rp.a[j] * tp[0] + Rp.a[3 + j] * tp[1] + Rp.a[6 + j] * tp[2]));
+  d.fx = c.fx; d.fy = c.fy; d.cx = c.cx; d.cy = c.cy;
+  const double hx = 0.5 * c.width / c.fx, hy = 0.5 * c.height / c.fy;
+  const double mx = (0.5 * c.width - c.cx) / c.fx, my = (0.5 * c.height - c.cy) / c.fy;
+  d.lox = (float)(mx - guard * hx); d.hix = (float)(mx + guard * hx);
+  d.loy = (float)(my - guard * hy); d.hiy = (float)(my + guard * hy);
+  d.W = c.width; d.H = c.height;
+  d.pad0 = d.pad1 = 0;
+  // Q(rho, phi) of the SE(3) left Jacobian
+  const M3 P = K, Rr = m3_skew(r[0], r[1], r[2]);
+  const M3 PR = m3_mul(P, Rr), RP = m3_mul(Rr, P), PRP = m3_mul(PR, P);
+  const M3 PPR = m3_mul(P, PR), RPP = m3_mul(RP, P), PRPP = m3_mul(PRP, P), PPRP = m3_mul(P, PRP);
+  M3 Q;
+  for (int k = 0; k < 9; ++k)
+    Q.a[k] = 0.5 * Rr.a[k] + Cc * (PR.a[k] + RP.a[k] + PRP.a[k]) + c2 * (PPR.a[k] + RPP.a[k] - 3.0 * PRP.a[k]) +
+             c3 * (PRPP.a[k] + PPRP.a[k]);
+  for (int k = 0; k < 36; ++k) d.Jl[k] = 0.0;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      d.Jl[i * 6 + j] = Vm.a[i * 3 + j];
+      d.Jl[(i + 3) * 6 + (j + 3)] = Vm.a[i * 3 + j];
+      d.Jl[i * 6 + (j + 3)] = Q.a[i * 3 + j];
+    }
+  out[v] = d;
+}
+
+// ---------------------------------------------------------------- counting
+struct ProjParams {
+  float alpha_min, log_alpha_min, near_z, eps2d, rect_margin;
+  int tile_w, tile_h, tiles_x, tiles_y;
+};
+
+__global__ __launch_bounds__(KGS_BLOCK) void k_count(kgs_gaussians g, const CamDev* __restrict__ cams, int V,
+                                                     ProjParams P, uint32_t* __restrict__ vis,
+                                                     uint32_t* __restrict__ blk_cnt, int64_t nb,
+                                                     uint32_t* __restrict__ status) {
+  __shared__ uint32_t sc[KGS_MAX_VIEWS][4], st[KGS_MAX_VIEWS][4];
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * KGS_BLOCK + threadIdx.x;
+  const bool valid = i < g.n;
+  GaussLocal G;
+  bool bad = false;
+  G.ok = false;
+  if (valid) load_gaussian(g, i, P.alpha_min, G, bad);
+  if (bad) atomicOr(status, KGS_FLAG_NONFINITE);
+  for (int v = 0; v < V; ++v) {
+    uint32_t tiles = 0;
+    if (G.ok) {
+      ProjCore p;
+      if (project_core(cams[v], G.mu, G.cw, G.o, P.near_z, P.eps2d, P.rect_margin, P.log_alpha_min, P.tile_w,
+                       P.tile_h, P.tiles_x, P.tiles_y, p))
+        tiles = (uint32_t)((p.x1 - p.x0) * (p.y1 - p.y0));
+    }
+    if (valid) vis[(int64_t)v * g.n + i] = tiles;
+    const uint32_t c = (uint32_t)__popcll(ballot64(tiles > 0));
+    const uint32_t t = wave_sum(tiles);
+    if (l == 0) { sc[v][w] = c; st[v][w] = t; }
+  }
+  __syncthreads();
+  for (int v = threadIdx.x; v < V; v += KGS_BLOCK) {
+    const int64_t e = ((int64_t)v * nb + blockIdx.x) * 2;
+    blk_cnt[e] = sc[v][0] + sc[v][1] + sc[v][2] + sc[v][3];
+    blk_cnt[e + 1] = st[v][0] + st[v][1] + st[v][2] + st[v][3];
+  }
+}
+
+// ---------------------------------------------------------------- block scan
+// Exclusive scan of the (visible, tiles) pairs of all (view, block) entries in
+// (view, block) order.  One block of 1024 threads.  Bases saturate at the
+// capacities; totals are written clamped, overflow raises a status bit.
+__global__ __launch_bounds__(1024) void k_scan_blocks(const uint32_t* __restrict__ blk_cnt,
+                                                      uint32_t* __restrict__ blk_base, int64_t entries,
+                                                      uint64_t slot_cap, uint64_t pair_cap,
+                                                      uint32_t* __restrict__ counters) {
+  __shared__ unsigned long long sa[16], sb[16];
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  const int64_t per = (entries + 1023) / 1024;
+  const int64_t lo = tid * per, hi = min(entries, lo + per);
+  unsigned long long a = 0, b = 0;
+  for (int64_t e = lo; e < hi; ++e) { a += blk_cnt[2 * e]; b += blk_cnt[2 * e + 1]; }
+  unsigned long long ia = wave_inclusive_scan(a), ib = wave_inclusive_scan(b);
+  if (l == 63) { sa[w] = ia; sb[w] = ib; }
+  __syncthreads();
+  unsigned long long oa = 0, ob = 0, ta = 0, tb = 0;
+  for (int k = 0; k < 16; ++k) {
+    if (k < w) { oa += sa[k]; ob += sb[k]; }
+    ta += sa[k];
+    tb += sb[k];
+  }
+  unsigned long long ra = oa + ia - a, rb = ob + ib - b;
+  for (int64_t e = lo; e < hi; ++e) {
+    blk_base[2 * e] = (uint32_t)min(ra, (unsigned long long)slot_cap);
+    blk_base[2 * e + 1] = (uint32_t)min(rb, (unsigned long long)pair_cap);
+    ra += blk_cnt[2 * e];
+    rb += blk_cnt[2 * e + 1];
+  }
+  if (tid == 0) {
+    uint32_t f = 0;
+    if (ta > slot_cap) f |= KGS_FLAG_SLOT_OVERFLOW;
+    if (tb > pair_cap) f |= KGS_FLAG_PAIR_OVERFLOW;
+    // on overflow every later stage sees zero records and zero pairs
+    counters[0] = f ? 0u : (uint32_t)ta;
+    counters[1] = f ? 0u : (uint32_t)tb;
+    if (f) atomicOr(&counters[2], f);
+  }
+}
+
+// ---------------------------------------------------------------- emission
+// Pixel bounds [lo, hi] of the rectangle packed as two int16 (clamped; the
+// image is narrower than 32767 pixels, so clamping keeps every overlap test).
+__device__ __forceinline__ float pack_bounds(int lo, int hi) {
+  lo = min(max(lo, -32768), 32767);
+  hi = min(max(hi, -32768), 32767);
+  return __uint_as_float(((uint32_t)lo & 0xffffu) | ((uint32_t)hi << 16));
+}
+
+template <int DEG>
+__global__ __launch_bounds__(KGS_BLOCK) void k_emit(kgs_gaussians g, const CamDev* __restrict__ cams, int V,
+                                                    ProjParams P, const uint32_t* __restrict__ vis,
+                                                    const uint32_t* __restrict__ blk_base, int64_t nb,
+                                                    uint64_t slot_cap, uint64_t pair_cap,
+                                                    float4* __restrict__ slot_rec, uint32_t* __restrict__ slot_gid,
+                                                    uint32_t* __restrict__ slot_view, int4* __restrict__ slot_pix,
+                                                    uint32_t* __restrict__ slot_pairoff,
+                                                    uint32_t* __restrict__ slot_ntiles) {
+  constexpr int K = (DEG + 1) * (DEG + 1);
+  __shared__ uint32_t scan_sh[16];
+  const int64_t i = (int64_t)blockIdx.x * KGS_BLOCK + threadIdx.x;
+  const bool valid = i < g.n;
+  GaussLocal G;
+  bool bad = false;
+  G.ok = false;
+  if (valid) load_gaussian(g, i, P.alpha_min, G, bad);
+  const float hl2e = 0.5f * 1.4426950408889634f;
+  for (int v = 0; v < V; ++v) {
+    const uint32_t tiles = valid ? vis[(int64_t)v * g.n + i] : 0u;
+    const uint32_t flag = tiles > 0 ? 1u : 0u;
+    uint32_t ea, eb, ta, tb;
+    block_scan2(flag, tiles, scan_sh, ea, eb, ta, tb);
+    if (!flag) continue;
+    const int64_t e = ((int64_t)v * nb + blockIdx.x) * 2;
+    const uint64_t s = (uint64_t)blk_base[e] + ea;
+    const uint64_t po = (uint64_t)blk_base[e + 1] + eb;
+    if (s >= slot_cap) continue;
+    if (po + tiles > pair_cap) {
+      // over the pair capacity: the slot exists but emits nothing
+      slot_gid[s] = (uint32_t)i;
+      slot_view[s] = (uint32_t)v;
+      slot_pairoff[s] = 0u;
+      slot_ntiles[s] = 0u;
+      continue;
+    }
+    const CamDev& c = cams[v];
+    ProjCore p;
+    const bool vis_ok = G.ok && project_core(c, G.mu, G.cw, G.o, P.near_z, P.eps2d, P.rect_margin,
+                                             P.log_alpha_min, P.tile_w, P.tile_h, P.tiles_x, P.tiles_y, p);
+    float4 r0, r1, r2;
+    int4 pix;
+    if (vis_ok) {
+      const float idet = 1.0f / p.det;
+      const float ca = p.S11 * idet, cb = -p.S01 * idet, cc = p.S00 * idet;
+      r0 = make_float4(p.mx - 0.5f, p.my - 0.5f, -hl2e * ca, -2.0f * hl2e * cb);
+      r1 = make_float4(-hl2e * cc, __log2f(G.o), p.tz, pack_bounds(p.fxi - p.rx, p.fxi + p.rx));
+      // colour from the view direction (Gaussian mean minus camera centre)
+      float dv[3] = {G.mu[0] - c.ctr[0], G.mu[1] - c.ctr[1], G.mu[2] - c.ctr[2]};
+      const float inv = 1.0f / sqrtf(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+      float Y[16];
+      sh_basis(DEG, dv[0] * inv, dv[1] * inv, dv[2] * inv, Y);
+      float col[3];
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) {
+        float acc = 0.5f;
+#pragma unroll
+        for (int k = 0; k < K; ++k) acc += Y[k] * g.sh[((int64_t)k * 3 + ch) * g.n + i];
+        col[ch] = fmaxf(acc, 0.0f);
+      }
+      r2 = make_float4(col[0], col[1], col[2], pack_bounds(p.fyi - p.ry, p.fyi + p.ry));
+      pix = make_int4(p.fxi, p.fyi, p.rx, p.ry);
+    } else {
+      // the counting pass saw this Gaussian visible but the re-projection does
+      // not: write a record that never blends and an empty rectangle
+      r0 = make_float4(0.f, 0.f, 0.f, 0.f);
+      r1 = make_float4(0.f, -INFINITY, 1.0f, pack_bounds(32767, -32768));
+      r2 = make_float4(0.f, 0.f, 0.f, pack_bounds(32767, -32768));
+      pix = make_int4(-(1 << 30), -(1 << 30), 0, 0);
+    }
+    slot_rec[s * 3 + 0] = r0;
+    slot_rec[s * 3 + 1] = r1;
+    slot_rec[s * 3 + 2] = r2;
+    slot_gid[s] = (uint32_t)i;
+    slot_view[s] = (uint32_t)v;
+    slot_pix[s] = pix;
+    slot_pairoff[s] = (uint32_t)po;
+    slot_ntiles[s] = tiles;
+  }
+}
+
+// ---------------------------------------------------------------- host side
+kgs_status kgs_launch_project(kgs_ctx* ctx, const kgs_gaussians* g, const kgs_camera* cams, int V,
+                              const float* pose_xi, hipStream_t st) {
+  const kgs_config& cfg = ctx->cfg;
+  hipLaunchKernelGGL(k_cam_setup, dim3(1), dim3(64), 0, st, cams, pose_xi, V, cfg.guard, ctx->cams);
+  ProjParams P;
+  P.alpha_min = cfg.alpha_min;
+  P.log_alpha_min = logf(cfg.alpha_min);
+  P.near_z = cfg.near_z;
+  P.eps2d = cfg.eps2d;
+  P.rect_margin = cfg.rect_margin;
+  P.tile_w = cfg.tile_w;
+  P.tile_h = cfg.tile_h;
+  P.tiles_x = ctx->tiles_x;
+  P.tiles_y = ctx->tiles_y;
+  const int64_t nb = (g->n + KGS_BLOCK - 1) / KGS_BLOCK;
+  if (nb > 0)
+    hipLaunchKernelGGL(k_count, dim3((unsigned)nb), dim3(KGS_BLOCK), 0, st, *g, (const CamDev*)ctx->cams, V, P,
+                       ctx->vis, ctx->blk_cnt, nb, ctx->counters + 2);
+  hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, st, (const uint32_t*)ctx->blk_cnt, ctx->blk_base,
+                     (int64_t)V * nb, (uint64_t)cfg.slot_capacity, (uint64_t)cfg.pair_capacity, ctx->counters);
+  if (nb > 0) {
+#define KGS_EMIT(D)                                                                                              \
+  hipLaunchKernelGGL(k_emit<D>, dim3((unsigned)nb), dim3(KGS_BLOCK), 0, st, *g, (const CamDev*)ctx->cams, V, P,   \
+                     (const uint32_t*)ctx->vis, (const uint32_t*)ctx->blk_base, nb, (uint64_t)cfg.slot_capacity,  \
+                     (uint64_t)cfg.pair_capacity, ctx->slot_rec, ctx->slot_gid, ctx->slot_view, ctx->slot_pix,    \
+                     ctx->slot_pairoff, ctx->slot_ntiles)
+    switch (g->sh_degree) {
+      case 0: KGS_EMIT(0); break;
+      case 1: KGS_EMIT(1); break;
+      case 2: KGS_EMIT(2); break;
+      default: KGS_EMIT(3); break;
+    }
+#undef KGS_EMIT
+  }
+  return kgs_check_launch();
+}

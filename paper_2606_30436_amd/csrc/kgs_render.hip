@@ -1,0 +1,431 @@
+// Front-to-back compositing (forward), the L1 loss harness and the
+// compositing backward.
+//
+// One workgroup of 256 threads per (view, tile); each wave owns an 8x8
+// sub-block of the tile.  The tile's depth-sorted pairs are staged B at a time
+// into LDS; while staging, each Gaussian's integer pixel rectangle is tested
+// against the four sub-blocks and one compacted list per wave is built, so a
+// wave only evaluates Gaussians that can reach its pixels (outside the
+// rectangle alpha < alpha_min holds by construction of the rectangle, so this
+// changes no result).  A wave stops as soon as all its pixels are saturated.
+//
+// The backward recomputes the same per-pixel sequence front to back (nothing
+// per pixel is stored but T_final and the last blended position), reduces the
+// ten per-pair gradient terms across the wave with a reduce-scatter butterfly,
+// combines the four waves in fixed order through LDS and writes one 48-byte
+// record per pair at the pair's emission position, which keeps each slot's
+// pairs contiguous for the deterministic segmented sum that follows.
+#include "kgs_internal.h"
+
+struct RenderParams {
+  int W, H, tile_w, tile_h, tiles_x, tiles_y, n_tiles;
+  float log2_amin, amax, tmin;
+  float bg0, bg1, bg2;
+};
+
+// Stage B pairs of [base, end) into LDS and build the per-wave lists.
+template <int B>
+__device__ __forceinline__ void stage_batch(uint32_t base, uint32_t end, const uint32_t* __restrict__ sorted_slot,
+                                            const float4* __restrict__ slot_rec, int tile_x0, int tile_y0,
+                                            int tile_w, float4* s_r0, float4* s_r1, float4* s_r2,
+                                            uint8_t* s_mask, uint8_t (*s_list)[B], uint32_t (*s_cnt)[4]) {
+  const int tid = threadIdx.x, w = tid >> 6;
+  uint32_t m = 0;
+  if (tid < B) {
+    const uint32_t k = base + tid;
+    if (k < end) {
+      const uint32_t s = sorted_slot[k];
+      const float4 r0 = slot_rec[(size_t)s * 3], r1 = slot_rec[(size_t)s * 3 + 1], r2 = slot_rec[(size_t)s * 3 + 2];
+      s_r0[tid] = r0;
+      s_r1[tid] = r1;
+      s_r2[tid] = r2;
+      const uint32_t xb = __float_as_uint(r1.w), yb = __float_as_uint(r2.w);
+      const int xlo = (int)(int16_t)(xb & 0xffffu), xhi = (int)(int16_t)(xb >> 16);
+      const int ylo = (int)(int16_t)(yb & 0xffffu), yhi = (int)(int16_t)(yb >> 16);
+#pragma unroll
+      for (int ww = 0; ww < 4; ++ww) {
+        int sx, sy;
+        tile_subblock(tile_w, ww, sx, sy);
+        const int bx = tile_x0 + sx, by = tile_y0 + sy;
+        if (xlo <= bx + 7 && xhi >= bx && ylo <= by + 7 && yhi >= by) m |= 1u << ww;
+      }
+    }
+    s_mask[tid] = (uint8_t)m;
+  }
+#pragma unroll
+  for (int ww = 0; ww < 4; ++ww) {
+    const uint64_t bal = ballot64((m >> ww) & 1u);
+    if ((tid & 63) == 0) s_cnt[w][ww] = (uint32_t)__popcll(bal);
+  }
+  __syncthreads();
+  if (tid < B) {
+#pragma unroll
+    for (int ww = 0; ww < 4; ++ww) {
+      const uint64_t bal = ballot64((m >> ww) & 1u);
+      if ((m >> ww) & 1u) {
+        uint32_t pos = mask_lt_count(bal);
+        for (int k = 0; k < w; ++k) pos += s_cnt[k][ww];
+        s_list[ww][pos] = (uint8_t)tid;
+      }
+    }
+  }
+  __syncthreads();
+}
+
+template <int B>
+__global__ __launch_bounds__(KGS_BLOCK) void k_render_fwd(RenderParams P, const uint2* __restrict__ ranges,
+                                                          const uint32_t* __restrict__ sorted_slot,
+                                                          const float4* __restrict__ slot_rec,
+                                                          float* __restrict__ color, float* __restrict__ depth,
+                                                          float* __restrict__ tfinal, int32_t* __restrict__ last) {
+  __shared__ float4 s_r0[B], s_r1[B], s_r2[B];
+  __shared__ uint8_t s_list[4][B];
+  __shared__ uint8_t s_mask[B];
+  __shared__ uint32_t s_cnt[4][4];
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  const int gt = blockIdx.x;
+  const int v = gt / P.n_tiles, t = gt - v * P.n_tiles;
+  const int tx = t % P.tiles_x, ty = t / P.tiles_x;
+  const int tile_x0 = tx * P.tile_w, tile_y0 = ty * P.tile_h;
+  int sx, sy;
+  tile_subblock(P.tile_w, w, sx, sy);
+  const int px = tile_x0 + sx + (l & 7), py = tile_y0 + sy + (l >> 3);
+  const bool inside = px < P.W && py < P.H;
+  const float fpx = (float)px, fpy = (float)py;
+  const uint2 rg = ranges[gt];
+  const uint32_t start = rg.x, end = rg.y;
+  float T = 1.0f, c0 = 0.f, c1 = 0.f, c2 = 0.f, D = 0.f;
+  int lst = 0;
+  bool done = !inside;
+  for (uint32_t base = start; base < end; base += B) {
+    if (__syncthreads_count(!done) == 0) break;
+    stage_batch<B>(base, end, sorted_slot, slot_rec, tile_x0, tile_y0, P.tile_w, s_r0, s_r1, s_r2, s_mask, s_list,
+                   s_cnt);
+    const uint32_t len = s_cnt[0][w] + s_cnt[1][w] + s_cnt[2][w] + s_cnt[3][w];
+    const int rel0 = (int)(base - start) + 1;
+    for (uint32_t j = 0; j < len; ++j) {
+      if (!__any(!done)) break;
+      const int tt = s_list[w][j];
+      const float4 r0 = s_r0[tt], r1 = s_r1[tt];
+      if (!done) {
+        float dx, dy;
+        const float e = log2_alpha(fpx, fpy, r0, r1.x, r1.y, dx, dy);
+        if (e >= P.log2_amin) {
+          const float a = fminf(exp2_approx(e), P.amax);
+          const float Tn = T * (1.0f - a);
+          if (Tn < P.tmin) {
+            done = true;
+          } else {
+            const float4 r2 = s_r2[tt];
+            const float wgt = a * T;
+            c0 = fmaf(wgt, r2.x, c0);
+            c1 = fmaf(wgt, r2.y, c1);
+            c2 = fmaf(wgt, r2.z, c2);
+            D = fmaf(wgt, r1.z, D);
+            T = Tn;
+            lst = rel0 + tt;
+          }
+        }
+      }
+    }
+  }
+  if (inside) {
+    const size_t npix = (size_t)P.W * P.H;
+    const size_t pix = (size_t)v * npix + (size_t)py * P.W + px;
+    const size_t cpix = (size_t)v * 3 * npix + (size_t)py * P.W + px;
+    color[cpix] = c0 + T * P.bg0;
+    color[cpix + npix] = c1 + T * P.bg1;
+    color[cpix + 2 * npix] = c2 + T * P.bg2;
+    depth[pix] = D;
+    tfinal[pix] = T;
+    last[pix] = lst;
+  }
+}
+
+// ---------------------------------------------------------------- L1 loss harness
+__global__ __launch_bounds__(256) void k_loss_l1(int W, int H, const float* __restrict__ color,
+                                                 const float* __restrict__ target, float* __restrict__ grad,
+                                                 double* __restrict__ partial) {
+  __shared__ float sh[4];
+  const int v = blockIdx.y;
+  const size_t n3 = (size_t)3 * W * H;
+  const float scale = 1.0f / (float)n3;
+  const float* c = color + (size_t)v * n3;
+  const float* tg = target + (size_t)v * n3;
+  float* g = grad + (size_t)v * n3;
+  float acc = 0.f;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n3; i += (size_t)gridDim.x * 256) {
+    const float d = c[i] - tg[i];
+    acc += fabsf(d);
+    g[i] = d > 0.f ? scale : (d < 0.f ? -scale : 0.f);
+  }
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    partial[(size_t)v * gridDim.x + blockIdx.x] = ((double)sh[0] + (double)sh[1]) + ((double)sh[2] + (double)sh[3]);
+}
+
+__global__ void k_loss_final(int V, int nblk, double inv_n, const double* __restrict__ partial,
+                             float* __restrict__ view_loss) {
+  const int v = threadIdx.x;
+  if (v >= V) return;
+  double s = 0.0;
+  for (int b = 0; b < nblk; ++b) s += partial[(size_t)v * nblk + b];
+  view_loss[v] = (float)(s * inv_n);
+}
+
+// ---------------------------------------------------------------- backward
+// Reduce-scatter of 10 values over a wave: after the call lane L holds, in
+// x[0], the wave sum of value 5 b5 + 3 b4 + 2 b3 + b2 (b_k = bit k of L) when
+// `valid` is set.
+__device__ __forceinline__ void wave_reduce10(float (&x)[10], int lane, int& idx, bool& valid) {
+  const bool u5 = lane & 32, u4 = lane & 16, u3 = lane & 8, u2 = lane & 4;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    const float send = u5 ? x[k] : x[k + 5];
+    const float keep = u5 ? x[k + 5] : x[k];
+    x[k] = keep + __shfl_xor(send, 32, 64);
+  }
+  {
+    const float a0 = u4 ? x[0] : x[3], k0 = u4 ? x[3] : x[0];
+    const float a1 = u4 ? x[1] : x[4], k1 = u4 ? x[4] : x[1];
+    const float a2 = u4 ? x[2] : 0.f, k2 = u4 ? 0.f : x[2];
+    x[0] = k0 + __shfl_xor(a0, 16, 64);
+    x[1] = k1 + __shfl_xor(a1, 16, 64);
+    x[2] = k2 + __shfl_xor(a2, 16, 64);
+  }
+  {
+    const float a0 = u3 ? x[0] : x[2], k0 = u3 ? x[2] : x[0];
+    const float a1 = u3 ? x[1] : 0.f, k1 = u3 ? 0.f : x[1];
+    x[0] = k0 + __shfl_xor(a0, 8, 64);
+    x[1] = k1 + __shfl_xor(a1, 8, 64);
+  }
+  {
+    const float a0 = u2 ? x[0] : x[1], k0 = u2 ? x[1] : x[0];
+    x[0] = k0 + __shfl_xor(a0, 4, 64);
+  }
+  x[0] += __shfl_xor(x[0], 2, 64);
+  x[0] += __shfl_xor(x[0], 1, 64);
+  const int k = (u3 ? 2 : 0) + (u2 ? 1 : 0);
+  const int rel = (u4 ? 3 : 0) + k;
+  valid = (k < 3) && (rel < 5) && ((lane & 3) == 0);
+  idx = (u5 ? 5 : 0) + rel;
+}
+
+template <int B>
+__global__ __launch_bounds__(KGS_BLOCK) void k_render_bwd(
+    RenderParams P, const uint2* __restrict__ ranges, const uint32_t* __restrict__ sorted_slot,
+    const uint32_t* __restrict__ sorted_val, const float4* __restrict__ slot_rec, const float* __restrict__ color,
+    const float* __restrict__ depth, const float* __restrict__ tfinal, const int32_t* __restrict__ last,
+    const float* __restrict__ dl_dcolor, const float* __restrict__ dl_ddepth, const float* __restrict__ target,
+    float tau_err, float4* __restrict__ pair_grad) {
+  __shared__ float4 s_r0[B], s_r1[B], s_r2[B];
+  __shared__ uint8_t s_list[4][B];
+  __shared__ uint8_t s_mask[B];
+  __shared__ uint32_t s_cnt[4][4];
+  __shared__ float s_part[4][B][12];
+  __shared__ int s_wmax[4];
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  const int gt = blockIdx.x;
+  const int v = gt / P.n_tiles, t = gt - v * P.n_tiles;
+  const int tx = t % P.tiles_x, ty = t / P.tiles_x;
+  const int tile_x0 = tx * P.tile_w, tile_y0 = ty * P.tile_h;
+  int sx, sy;
+  tile_subblock(P.tile_w, w, sx, sy);
+  const int px = tile_x0 + sx + (l & 7), py = tile_y0 + sy + (l >> 3);
+  const bool inside = px < P.W && py < P.H;
+  const float fpx = (float)px, fpy = (float)py;
+  const uint2 rg = ranges[gt];
+  const uint32_t start = rg.x, end = rg.y;
+  // per-pixel inputs
+  int lastp = 0;
+  float Co0 = 0.f, Co1 = 0.f, Co2 = 0.f, Do = 0.f, g0 = 0.f, g1 = 0.f, g2 = 0.f, gD = 0.f;
+  bool M = false;
+  if (inside) {
+    const size_t npix = (size_t)P.W * P.H;
+    const size_t pix = (size_t)v * npix + (size_t)py * P.W + px;
+    const size_t cpix = (size_t)v * 3 * npix + (size_t)py * P.W + px;
+    lastp = last[pix];
+    Co0 = color[cpix];
+    Co1 = color[cpix + npix];
+    Co2 = color[cpix + 2 * npix];
+    Do = depth[pix];
+    g0 = dl_dcolor[cpix];
+    g1 = dl_dcolor[cpix + npix];
+    g2 = dl_dcolor[cpix + 2 * npix];
+    if (dl_ddepth) gD = dl_ddepth[pix];
+    if (target) {
+      const float err = fabsf(target[cpix] - Co0) + fabsf(target[cpix + npix] - Co1) +
+                        fabsf(target[cpix + 2 * npix] - Co2);
+      M = err > tau_err;
+    }
+  }
+  int wmax = lastp;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) wmax = max(wmax, __shfl_xor(wmax, o, 64));
+  if (l == 0) s_wmax[w] = wmax;
+  __syncthreads();
+  const int bmax = max(max(s_wmax[0], s_wmax[1]), max(s_wmax[2], s_wmax[3]));
+  const uint32_t pend = start + (uint32_t)bmax;
+  float T = 1.0f, Ca0 = 0.f, Ca1 = 0.f, Ca2 = 0.f, Da = 0.f;
+  const float LN2 = 0.69314718055994531f;
+  uint32_t base = start;
+  for (; base < pend; base += B) {
+    __syncthreads();
+    stage_batch<B>(base, end, sorted_slot, slot_rec, tile_x0, tile_y0, P.tile_w, s_r0, s_r1, s_r2, s_mask, s_list,
+                   s_cnt);
+    const uint32_t len = s_cnt[0][w] + s_cnt[1][w] + s_cnt[2][w] + s_cnt[3][w];
+    const int rel0 = (int)(base - start);
+    for (uint32_t j = 0; j < len; ++j) {
+      const int tt = s_list[w][j];
+      const int krel = rel0 + tt;
+      if (krel >= wmax) break;
+      const float4 r0 = s_r0[tt], r1 = s_r1[tt], r2 = s_r2[tt];
+      float x[10];
+#pragma unroll
+      for (int q = 0; q < 10; ++q) x[q] = 0.f;
+      bool bl = false;
+      if (krel < lastp) {
+        float dx, dy;
+        const float e = log2_alpha(fpx, fpy, r0, r1.x, r1.y, dx, dy);
+        if (e >= P.log2_amin) {
+          bl = true;
+          const float raw = exp2_approx(e);
+          const float a = fminf(raw, P.amax);
+          const float wgt = a * T;
+          Ca0 = fmaf(wgt, r2.x, Ca0);
+          Ca1 = fmaf(wgt, r2.y, Ca1);
+          Ca2 = fmaf(wgt, r2.z, Ca2);
+          Da = fmaf(wgt, r1.z, Da);
+          const float om = 1.0f / (1.0f - a);
+          const float dLda = g0 * (T * r2.x - (Co0 - Ca0) * om) + g1 * (T * r2.y - (Co1 - Ca1) * om) +
+                             g2 * (T * r2.z - (Co2 - Ca2) * om) + gD * (T * r1.z - (Do - Da) * om);
+          x[6] = wgt * g0;
+          x[7] = wgt * g1;
+          x[8] = wgt * g2;
+          x[9] = wgt * gD;
+          if (raw < P.amax) {
+            const float ge = dLda * a * LN2;
+            x[0] = -ge * (2.0f * r0.z * dx + r0.w * dy);
+            x[1] = -ge * (r0.w * dx + 2.0f * r1.x * dy);
+            x[2] = ge * dx * dx;
+            x[3] = ge * dx * dy;
+            x[4] = ge * dy * dy;
+            x[5] = ge;
+          }
+          T = T * (1.0f - a);
+        }
+      }
+      const uint64_t bb = ballot64(bl);
+      const uint64_t bm = ballot64(bl && M);
+      int idx;
+      bool valid;
+      wave_reduce10(x, l, idx, valid);
+      if (valid) s_part[w][tt][idx] = x[0];
+      if (l == 0) {
+        s_part[w][tt][10] = (float)__popcll(bb);
+        s_part[w][tt][11] = (float)__popcll(bm);
+      }
+    }
+    __syncthreads();
+    if (tid < B) {
+      const uint32_t k = base + tid;
+      if (k < end) {
+        const int krel = (int)(k - start);
+        const uint32_t m = s_mask[tid];
+        float o[12];
+#pragma unroll
+        for (int q = 0; q < 12; ++q) o[q] = 0.f;
+#pragma unroll
+        for (int ww = 0; ww < 4; ++ww) {
+          if (((m >> ww) & 1u) && krel < s_wmax[ww]) {
+#pragma unroll
+            for (int q = 0; q < 12; ++q) o[q] += s_part[ww][tid][q];
+          }
+        }
+        const size_t p = (size_t)sorted_val[k] * 3;
+        pair_grad[p] = make_float4(o[0], o[1], o[2], o[3]);
+        pair_grad[p + 1] = make_float4(o[4], o[5], o[6], o[7]);
+        pair_grad[p + 2] = make_float4(o[8], o[9], __uint_as_float((uint32_t)o[10]), __uint_as_float((uint32_t)o[11]));
+      }
+    }
+  }
+  // pairs behind the tile's last blended Gaussian contribute nothing
+  for (uint32_t k = base + tid; k < end; k += KGS_BLOCK) {
+    const size_t p = (size_t)sorted_val[k] * 3;
+    const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+    pair_grad[p] = z;
+    pair_grad[p + 1] = z;
+    pair_grad[p + 2] = z;
+  }
+}
+
+// ---------------------------------------------------------------- host side
+static RenderParams render_params(const kgs_ctx* ctx) {
+  RenderParams P;
+  P.W = ctx->cfg.width;
+  P.H = ctx->cfg.height;
+  P.tile_w = ctx->cfg.tile_w;
+  P.tile_h = ctx->cfg.tile_h;
+  P.tiles_x = ctx->tiles_x;
+  P.tiles_y = ctx->tiles_y;
+  P.n_tiles = ctx->n_tiles;
+  P.log2_amin = log2f(ctx->cfg.alpha_min);
+  P.amax = ctx->cfg.alpha_max;
+  P.tmin = ctx->cfg.t_min;
+  P.bg0 = ctx->cfg.bg[0];
+  P.bg1 = ctx->cfg.bg[1];
+  P.bg2 = ctx->cfg.bg[2];
+  return P;
+}
+
+kgs_status kgs_launch_render_fwd(kgs_ctx* ctx, const kgs_image* out, hipStream_t st) {
+  const RenderParams P = render_params(ctx);
+  const unsigned grid = (unsigned)(ctx->last_views * ctx->n_tiles);
+  const int s = ctx->sorted_buf;
+  (void)s;
+#define KGS_FWD(BB)                                                                                              \
+  hipLaunchKernelGGL(k_render_fwd<BB>, dim3(grid), dim3(KGS_BLOCK), 0, st, P, (const uint2*)ctx->ranges,          \
+                     (const uint32_t*)ctx->sorted_slot, (const float4*)ctx->slot_rec, out->color, out->depth,      \
+                     out->t_final, out->last)
+  switch (ctx->cfg.batch) {
+    case 32: KGS_FWD(32); break;
+    case 64: KGS_FWD(64); break;
+    case 128: KGS_FWD(128); break;
+    default: KGS_FWD(256); break;
+  }
+#undef KGS_FWD
+  return kgs_check_launch();
+}
+
+kgs_status kgs_launch_loss(kgs_ctx* ctx, const float* target, const kgs_image* img, float* dl_dcolor,
+                           float* view_loss, hipStream_t st) {
+  const int V = ctx->last_views;
+  hipLaunchKernelGGL(k_loss_l1, dim3(KGS_LOSS_BLOCKS, V), dim3(256), 0, st, ctx->cfg.width, ctx->cfg.height,
+                     (const float*)img->color, target, dl_dcolor, ctx->loss_partial);
+  const double inv_n = 1.0 / (3.0 * (double)ctx->cfg.width * (double)ctx->cfg.height);
+  hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, st, V, KGS_LOSS_BLOCKS, inv_n,
+                     (const double*)ctx->loss_partial, view_loss);
+  return kgs_check_launch();
+}
+
+kgs_status kgs_launch_render_bwd(kgs_ctx* ctx, const kgs_image* fwd, const float* dl_dcolor, const float* dl_ddepth,
+                                 const float* target, float tau_err, hipStream_t st) {
+  const RenderParams P = render_params(ctx);
+  const unsigned grid = (unsigned)(ctx->last_views * ctx->n_tiles);
+  const uint32_t* sval = ctx->vals[ctx->sorted_buf];
+#define KGS_BWD(BB)                                                                                              \
+  hipLaunchKernelGGL(k_render_bwd<BB>, dim3(grid), dim3(KGS_BLOCK), 0, st, P, (const uint2*)ctx->ranges,          \
+                     (const uint32_t*)ctx->sorted_slot, sval, (const float4*)ctx->slot_rec,                       \
+                     (const float*)fwd->color, (const float*)fwd->depth, (const float*)fwd->t_final,              \
+                     (const int32_t*)fwd->last, dl_dcolor, dl_ddepth, target, tau_err, ctx->pair_grad)
+  switch (ctx->cfg.batch) {
+    case 32: KGS_BWD(32); break;
+    case 64: KGS_BWD(64); break;
+    case 128: KGS_BWD(128); break;
+    default: KGS_BWD(256); break;
+  }
+#undef KGS_BWD
+  return kgs_check_launch();
+}

@@ -1,0 +1,167 @@
+// Chunk scores, their global merge and the densify / prune decision
+// (appendix, "Densification Score" and "Pruning Score"; Sec. 3.3 global rules).
+// Per-Gaussian streams over [N] arrays: HBM bound.  L, S_p and the min / max
+// over the active set are FP64 so the prune threshold test is decided far
+// below any FP32 rounding.
+#include "kgs_internal.h"
+
+__global__ __launch_bounds__(KGS_BLOCK) void k_chunk_scores(int64_t n, float inv_views, float tau_d,
+                                                            const uint32_t* __restrict__ kappa_sum,
+                                                            const uint32_t* __restrict__ omega_sum,
+                                                            const double* __restrict__ gamma_sum,
+                                                            uint8_t* __restrict__ densify,
+                                                            double* __restrict__ mm_partial) {
+  __shared__ double smin[4], smax[4];
+  const int64_t i = (int64_t)blockIdx.x * KGS_BLOCK + threadIdx.x;
+  double lo = INFINITY, hi = -INFINITY;
+  if (i < n) {
+    // S_d^(i,c) = (1/|V_c|) sum_v kappa_v(i);  S_d(i) |= S_d^(i,c) > tau_d
+    const float sd = (float)kappa_sum[i] * inv_views;
+    if (sd > tau_d) densify[i] = 1;
+    if (omega_sum[i] > 0) {
+      const double L = log1p(gamma_sum[i]);
+      lo = L;
+      hi = L;
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    lo = fmin(lo, __shfl_xor(lo, o, 64));
+    hi = fmax(hi, __shfl_xor(hi, o, 64));
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) { smin[w] = lo; smax[w] = hi; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    mm_partial[2 * blockIdx.x] = fmin(fmin(smin[0], smin[1]), fmin(smin[2], smin[3]));
+    mm_partial[2 * blockIdx.x + 1] = fmax(fmax(smax[0], smax[1]), fmax(smax[2], smax[3]));
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_minmax_final(int64_t nb, double* __restrict__ mm) {
+  __shared__ double smin[16], smax[16];
+  double lo = INFINITY, hi = -INFINITY;
+  for (int64_t b = threadIdx.x; b < nb; b += 1024) {
+    lo = fmin(lo, mm[2 * b]);
+    hi = fmax(hi, mm[2 * b + 1]);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    lo = fmin(lo, __shfl_xor(lo, o, 64));
+    hi = fmax(hi, __shfl_xor(hi, o, 64));
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) { smin[w] = lo; smax[w] = hi; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < 16; ++k) { lo = fmin(lo, smin[k]); hi = fmax(hi, smax[k]); }
+    mm[2 * nb] = lo;
+    mm[2 * nb + 1] = hi;
+  }
+}
+
+// S_p^(i,c) = (L - min_A L) / (max_A L - min_A L) on the active set A;
+// S_p(i) = max_c S_p^(i,c).
+__global__ __launch_bounds__(KGS_BLOCK) void k_chunk_prune(int64_t n, int64_t nb, uint32_t* __restrict__ kappa_sum,
+                                                           uint32_t* __restrict__ omega_sum,
+                                                           double* __restrict__ gamma_sum,
+                                                           const double* __restrict__ mm,
+                                                           double* __restrict__ prune_score, int reset) {
+  const int64_t i = (int64_t)blockIdx.x * KGS_BLOCK + threadIdx.x;
+  if (i >= n) return;
+  const double lo = mm[2 * nb], hi = mm[2 * nb + 1];
+  double sp = 0.0;
+  if (omega_sum[i] > 0 && hi > lo) sp = (log1p(gamma_sum[i]) - lo) / (hi - lo);
+  if (sp > prune_score[i]) prune_score[i] = sp;
+  if (reset) {
+    kappa_sum[i] = 0u;
+    omega_sum[i] = 0u;
+    gamma_sum[i] = 0.0;
+  }
+}
+
+__global__ __launch_bounds__(KGS_BLOCK) void k_decide(int64_t n, double tau_p, const uint8_t* __restrict__ densify,
+                                                      const double* __restrict__ prune_score,
+                                                      uint8_t* __restrict__ decision,
+                                                      uint32_t* __restrict__ keep_partial) {
+  const int64_t i = (int64_t)blockIdx.x * KGS_BLOCK + threadIdx.x;
+  uint8_t d = KGS_KEEP;
+  bool keep = false;
+  if (i < n) {
+    if (prune_score[i] > tau_p) d = KGS_PRUNE;
+    else if (densify[i]) d = KGS_DENSIFY;
+    decision[i] = d;
+    keep = d != KGS_PRUNE;
+  }
+  __shared__ uint32_t sh[4];
+  const uint32_t c = (uint32_t)__popcll(ballot64(keep));
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0 && keep_partial) keep_partial[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+__global__ __launch_bounds__(1024) void k_keep_scan(int64_t nb, uint32_t* __restrict__ part,
+                                                    uint32_t* __restrict__ n_keep) {
+  __shared__ uint32_t sh[16];
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  const int64_t per = (nb + 1023) / 1024;
+  const int64_t lo = tid * per, hi = min(nb, lo + per);
+  uint32_t a = 0;
+  for (int64_t b = lo; b < hi; ++b) a += part[b];
+  const uint32_t ia = wave_inclusive_scan(a);
+  if (l == 63) sh[w] = ia;
+  __syncthreads();
+  uint32_t off = 0, tot = 0;
+  for (int k = 0; k < 16; ++k) {
+    if (k < w) off += sh[k];
+    tot += sh[k];
+  }
+  uint32_t r = off + ia - a;
+  for (int64_t b = lo; b < hi; ++b) {
+    const uint32_t c = part[b];
+    part[b] = r;
+    r += c;
+  }
+  if (tid == 0 && n_keep) *n_keep = tot;
+}
+
+__global__ __launch_bounds__(KGS_BLOCK) void k_keep_map(int64_t n, const uint8_t* __restrict__ decision,
+                                                        const uint32_t* __restrict__ base,
+                                                        uint32_t* __restrict__ keep_map) {
+  __shared__ uint32_t sh[16];
+  const int64_t i = (int64_t)blockIdx.x * KGS_BLOCK + threadIdx.x;
+  const uint32_t keep = (i < n && decision[i] != KGS_PRUNE) ? 1u : 0u;
+  uint32_t ea, eb, ta, tb;
+  block_scan2(keep, 0u, sh, ea, eb, ta, tb);
+  if (i < n) keep_map[i] = base[blockIdx.x] + ea;
+}
+
+kgs_status kgs_launch_accumulate(kgs_ctx* ctx, const kgs_view_stats* s, int64_t n, int V,
+                                 const kgs_lifecycle_state* state, float tau_d, int reset, hipStream_t st) {
+  const int64_t nb = (n + KGS_BLOCK - 1) / KGS_BLOCK;
+  if (nb == 0) return KGS_OK;
+  hipLaunchKernelGGL(k_chunk_scores, dim3((unsigned)nb), dim3(KGS_BLOCK), 0, st, n, 1.0f / (float)V, tau_d,
+                     (const uint32_t*)s->kappa_sum, (const uint32_t*)s->omega_sum, (const double*)s->gamma_sum,
+                     state->densify, ctx->mm_partial);
+  hipLaunchKernelGGL(k_minmax_final, dim3(1), dim3(1024), 0, st, nb, ctx->mm_partial);
+  hipLaunchKernelGGL(k_chunk_prune, dim3((unsigned)nb), dim3(KGS_BLOCK), 0, st, n, nb, s->kappa_sum, s->omega_sum,
+                     s->gamma_sum, (const double*)ctx->mm_partial, state->prune_score, reset);
+  return kgs_check_launch();
+}
+
+kgs_status kgs_launch_decide(kgs_ctx* ctx, const kgs_lifecycle_state* state, int64_t n, double tau_p,
+                             uint8_t* decision, uint32_t* keep_map, uint32_t* n_keep, hipStream_t st) {
+  const int64_t nb = (n + KGS_BLOCK - 1) / KGS_BLOCK;
+  if (nb == 0) return KGS_OK;
+  const bool need_scan = keep_map || n_keep;
+  hipLaunchKernelGGL(k_decide, dim3((unsigned)nb), dim3(KGS_BLOCK), 0, st, n, tau_p,
+                     (const uint8_t*)state->densify, (const double*)state->prune_score, decision,
+                     need_scan ? ctx->keep_partial : (uint32_t*)nullptr);
+  if (need_scan) {
+    hipLaunchKernelGGL(k_keep_scan, dim3(1), dim3(1024), 0, st, nb, ctx->keep_partial, n_keep);
+    if (keep_map)
+      hipLaunchKernelGGL(k_keep_map, dim3((unsigned)nb), dim3(KGS_BLOCK), 0, st, n, (const uint8_t*)decision,
+                         (const uint32_t*)ctx->keep_partial, keep_map);
+  }
+  return kgs_check_launch();
+}

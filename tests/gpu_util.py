@@ -1,0 +1,97 @@
+"""Shared helpers of the GPU parity tests: run the HIP path on a scene, run the
+oracle on the same scene, and the comparison rules (tolerances and the
+near-threshold exclusions)."""
+from __future__ import annotations
+
+import math
+import sys
+
+import numpy as np
+import torch
+
+import oracle
+from oracle import OracleConfig
+from paper_2606_30436_amd import rasterizer as rz
+from paper_2606_30436_amd.rasterizer import GaussianParams, Image, Rasterizer, ViewStats, device_cameras
+
+LOG2E = 1.4426950408889634
+
+# Relative margins below which an FP32 decision may differ from the FP64 one.
+# The FP32 error of log2(alpha) at the alpha_min boundary is about 2e-5
+# (centre and conic rounding); transmittance accumulates about ten of those
+# before it reaches T_min.  The margins keep a factor of ten on both.
+MARGIN_ALPHA = 2e-4
+MARGIN_T = 2e-3
+MARGIN_DEPTH = 1e-6
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def oracle_cfg(R: Rasterizer) -> OracleConfig:
+    c = R.cfg
+    return OracleConfig(alpha_min=c.alpha_min, alpha_max=c.alpha_max, t_min=c.t_min, near=c.near_z, eps2d=c.eps2d,
+                        guard=c.guard, rect_margin=c.rect_margin, bg=tuple(c.bg), tile_w=c.tile_w, tile_h=c.tile_h)
+
+
+def run_forward(R: Rasterizer, sc, pose=True):
+    g = GaussianParams.from_scene(sc)
+    cams = device_cameras(sc.cams)
+    xi = torch.from_numpy(sc.pose_xi.astype(np.float32)).cuda() if pose else None
+    V = R.project(g, cams, xi)
+    R.bin_sort()
+    img = Image.empty(V, sc.height, sc.width)
+    R.render_fwd(img)
+    torch.cuda.synchronize()
+    return g, cams, xi, img
+
+
+def rect_hits(mask: np.ndarray, fxi, fyi, rx, ry) -> np.ndarray:
+    """For each Gaussian, does its pixel rectangle hold a True pixel of mask?"""
+    H, W = mask.shape
+    sat = np.zeros((H + 1, W + 1), np.int64)
+    sat[1:, 1:] = np.cumsum(np.cumsum(mask.astype(np.int64), 0), 1)
+    x0 = np.clip(fxi - rx, 0, W)
+    x1 = np.clip(fxi + rx + 1, 0, W)
+    y0 = np.clip(fyi - ry, 0, H)
+    y1 = np.clip(fyi + ry + 1, 0, H)
+    s = sat[y1, x1] - sat[y0, x1] - sat[y1, x0] + sat[y0, x0]
+    return (s > 0) & (x1 > x0) & (y1 > y0)
+
+
+def ambiguous_pixels(oi) -> np.ndarray:
+    m = oi["margins"]
+    return (m[0] <= MARGIN_ALPHA) | (m[1] <= MARGIN_T) | (m[3] <= MARGIN_DEPTH)
+
+
+def involved_gaussians(ov) -> np.ndarray:
+    """Gaussians that themselves sit at a threshold somewhere in this view: own
+    alpha at alpha_min or at the alpha_max clamp, ending a pixel's sequence at
+    T_min, at the colour clamp or at the guard band."""
+    gm = ov.gauss_margins()
+    pr = ov.proj()
+    m = pr["margins"]
+    own = (gm[:, 0] <= MARGIN_ALPHA) | (gm[:, 1] <= MARGIN_ALPHA) | (gm[:, 2] <= MARGIN_T)
+    return pr["visible"] & (own | (m[:, 4] < 1e-4) | (m[:, 2] < 1e-5) | (m[:, 3] < 1e-5))
+
+
+def grad_close(name, got, ref, include, rel_norm=1e-3, rel_elem=1e-3, max_bad=1e-2):
+    """Norm-wise ||d|| <= rel_norm ||g|| over every Gaussian, and element-wise
+    |d| <= rel_elem (|g| + 0.01 rms(g)) over the included ones (a fraction
+    max_bad may fail: Gaussians behind a threshold flip of another Gaussian)."""
+    got = np.asarray(got, np.float64)
+    ref = np.asarray(ref, np.float64)
+    d = got - ref
+    nr = np.linalg.norm(ref)
+    if nr == 0:
+        assert np.abs(got).max(initial=0) < 1e-12, name
+        return 0
+    rel = np.linalg.norm(d) / nr
+    assert rel <= rel_norm, (name, rel)
+    rms = math.sqrt(np.mean(ref * ref))
+    di, ri = d[..., include], ref[..., include]
+    bad = np.abs(di) > rel_elem * (np.abs(ri) + 0.01 * rms)
+    assert bad.mean() <= max_bad, (name, int(bad.sum()), bad.size, float(np.abs(di).max()))
+    return rel

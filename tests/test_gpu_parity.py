@@ -1,0 +1,232 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerances: images max |dC| <= 1e-4 (FP32), depth |dD| <= 1e-4 max(1, D);
+gradients ||d|| <= 1e-3 ||g|| and element-wise 1e-3 (|g| + 0.01 rms);
+binning bit-exact; counts exact.  Pixels whose alpha / transmittance decision
+lies within a relative margin of 2e-3 of a threshold (and Gaussians whose
+rectangle holds such a pixel) are excluded and counted; the excluded share is
+bounded in every test.  The margins (2e-4 on alpha, 2e-3 on T) are ten times the
+FP32 rounding of those quantities."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import OracleConfig, lifecycle
+from paper_2606_30436_amd import scenes
+from paper_2606_30436_amd.rasterizer import (GaussianParams, Image, LifecycleState, Rasterizer, ViewStats,
+                                             device_cameras)
+from tests.gpu_util import (LOG2E, ambiguous_pixels, grad_close, involved_gaussians, oracle_cfg, rect_hits,
+                            run_forward, say)
+
+pytestmark = pytest.mark.gpu
+
+
+def _scene(name):
+    if name == "c1":
+        return scenes.make_c1()
+    if name == "tiny":
+        return scenes.tiny_scene(seed=3, n=60, degree=3, W=70, H=45, n_views=2, pose_sigma=0.02)
+    if name == "tiny_bg":
+        return scenes.tiny_scene(seed=4, n=80, degree=2, W=53, H=37, n_views=3, pose_sigma=0.03)
+    raise KeyError(name)
+
+
+def _rast(sc, tile=(16, 16), batch=128, **kw):
+    return Rasterizer(sc.width, sc.height, max_views=sc.n_views, max_gaussians=sc.n, tile=tile, batch=batch, **kw)
+
+
+@pytest.mark.parametrize("name", ["c1", "tiny"])
+def test_project_records_match_oracle(name):
+    sc = _scene(name)
+    say(f"[gpu] project parity {name} n={sc.n} V={sc.n_views}")
+    R = _rast(sc)
+    run_forward(R, sc)
+    assert R.status() == 0
+    b = R.buffers()
+    cfg = oracle_cfg(R)
+    for v in range(sc.n_views):
+        sel = b["slot_view"].numpy() == v
+        gid = b["slot_gid"].numpy()[sel]
+        rec = b["slot_rec"].numpy()[sel].astype(np.float64)
+        pix = b["slot_pix"].numpy()[sel]
+        pr = oracle.View(sc, v, cfg).proj()
+        vis = np.nonzero(pr["visible"])[0]
+        # visible sets agree except for Gaussians at a culling margin
+        diff = np.setxor1d(gid, vis)
+        assert len(diff) <= max(2, 1e-3 * len(vis)), diff
+        common, ig, io = np.intersect1d(gid, vis, return_indices=True)
+        r = rec[ig]
+        mu = r[:, 0:2] + 0.5
+        assert np.allclose(mu, pr["mu"][common], rtol=1e-5, atol=2e-3)
+        conic = np.stack([-2 * r[:, 2] / LOG2E, -r[:, 3] / LOG2E, -2 * r[:, 4] / LOG2E], 1)
+        oc = pr["conic"][common]
+        scale = np.maximum(np.abs(oc[:, 0]), np.abs(oc[:, 2]))[:, None]
+        assert (np.abs(conic - oc) <= 2e-4 * scale).all(), np.max(np.abs(conic - oc) / scale)
+        assert np.allclose(2.0 ** r[:, 5], pr["opacity"][common], rtol=1e-5)
+        assert np.allclose(r[:, 6], pr["depth"][common], rtol=1e-6)
+        assert np.allclose(r[:, 8:11], pr["color"][common], atol=2e-5)
+        # integer centre and extents: equal except where FP64 sits next to an integer
+        same = (pix[ig] == np.stack([pr["fxi"], pr["fyi"], pr["rx"], pr["ry"]], 1)[common]).all(1)
+        assert same.mean() >= 0.995, same.mean()
+
+
+@pytest.mark.parametrize("name,tile", [("c1", (16, 16)), ("c1", (8, 32)), ("tiny", (32, 8))])
+def test_binning_is_bit_exact(name, tile):
+    """Sorted (key, Gaussian) list == the integer binning contract applied to
+    the GPU's own fp32 centres, extents and depths, sorted on the CPU."""
+    sc = _scene(name)
+    say(f"[gpu] binning {name} tile={tile}")
+    R = _rast(sc, tile=tile)
+    run_forward(R, sc)
+    b = R.buffers()
+    pix = b["slot_pix"].numpy()
+    depth_bits = b["slot_rec"].numpy()[:, 6].copy().view(np.uint32)
+    keys, gids = oracle.bin_keys(b["slot_view"].numpy(), b["slot_gid"].numpy(), pix[:, 0], pix[:, 1], pix[:, 2],
+                                 pix[:, 3], depth_bits, sc.width, sc.height, tile[0], tile[1])
+    gk = b["keys"].numpy().view(np.uint64)
+    gg = b["slot_gid"].numpy()[b["sorted_slot"].numpy()]
+    assert len(gk) == len(keys) == b["n_pairs"]
+    assert np.array_equal(gk, keys)
+    assert np.array_equal(gg.astype(np.int64), gids)
+
+
+@pytest.mark.parametrize("name", ["c1", "tiny", "tiny_bg"])
+def test_render_forward_matches_oracle(name):
+    sc = _scene(name)
+    kw = {"bg": (0.2, 0.5, 0.9)} if name == "tiny_bg" else {}
+    say(f"[gpu] render fwd {name}")
+    R = _rast(sc, **kw)
+    _, _, _, img = run_forward(R, sc)
+    cfg = oracle_cfg(R)
+    col = img.color.cpu().numpy().astype(np.float64)
+    dep = img.depth.cpu().numpy().astype(np.float64)
+    tf = img.t_final.cpu().numpy().astype(np.float64)
+    excluded = 0
+    total = 0
+    for v in range(sc.n_views):
+        oi = oracle.View(sc, v, cfg).image()
+        ok = ~ambiguous_pixels(oi)
+        excluded += int((~ok).sum())
+        total += ok.size
+        dc = np.abs(col[v] - oi["color"]).max(0)
+        assert dc[ok].max() <= 1e-4, dc[ok].max()
+        assert (np.abs(dep[v] - oi["depth"])[ok] <= 1e-4 * np.maximum(1.0, oi["depth"][ok])).all()
+        assert np.abs(tf[v] - oi["tfinal"])[ok].max() <= 1e-4
+    say(f"  excluded near-threshold pixels: {excluded}/{total}")
+    assert excluded <= 0.05 * total
+
+
+def _oracle_grads(sc, cfg, dLdC, dLdD):
+    out = None
+    for v in range(sc.n_views):
+        gv = oracle.View(sc, v, cfg).backward(dLdC[v], dLdD[v])
+        if out is None:
+            out = {k: gv[k].copy() for k in ("means", "log_scales", "quats", "logits", "sh")}
+            out["pose_xi"] = [gv["pose_xi"]]
+        else:
+            for k in ("means", "log_scales", "quats", "logits", "sh"):
+                out[k] += gv[k]
+            out["pose_xi"].append(gv["pose_xi"])
+    out["pose_xi"] = np.stack(out["pose_xi"])
+    return out
+
+
+def _involved(sc, cfg):
+    bad = np.zeros(sc.n, bool)
+    for v in range(sc.n_views):
+        bad |= involved_gaussians(oracle.View(sc, v, cfg))
+    return bad
+
+
+@pytest.mark.parametrize("name", ["c1", "tiny", "tiny_bg"])
+def test_render_backward_matches_oracle(name):
+    sc = _scene(name)
+    kw = {"bg": (0.2, 0.5, 0.9)} if name == "tiny_bg" else {}
+    say(f"[gpu] render bwd {name}")
+    R = _rast(sc, **kw)
+    g, cams, xi, img = run_forward(R, sc)
+    rng = np.random.default_rng(7)
+    V, H, W = sc.n_views, sc.height, sc.width
+    dLdC = rng.normal(size=(V, 3, H, W))
+    dLdD = rng.normal(size=(V, H, W)) * 0.05
+    grads = g.zeros_like()
+    pose_grad = torch.zeros(V, 6, device="cuda")
+    R.render_bwd(g, cams, xi, img, torch.from_numpy(dLdC.astype(np.float32)).cuda(),
+                 torch.from_numpy(dLdD.astype(np.float32)).cuda(), grads=grads, pose_grad=pose_grad)
+    torch.cuda.synchronize()
+    cfg = oracle_cfg(R)
+    ref = _oracle_grads(sc, cfg, dLdC, dLdD)
+    bad = _involved(sc, cfg)
+    say(f"  Gaussians at a threshold: {int(bad.sum())}/{sc.n}")
+    assert bad.mean() <= 0.1
+    inc = ~bad
+    rels = {}
+    for k in ("means", "log_scales", "quats", "logits", "sh"):
+        got = getattr(grads, k).cpu().numpy()
+        rels[k] = grad_close(k, got, ref[k], inc)
+    say("  relative gradient error " + " ".join(f"{k}={v:.2e}" for k, v in rels.items()))
+    pg = pose_grad.cpu().numpy()
+    d = np.linalg.norm(pg - ref["pose_xi"], axis=1) / np.linalg.norm(ref["pose_xi"], axis=1)
+    say(f"  pose gradient relative error per view {d}")
+    assert (d <= 1e-3).all()
+
+
+@pytest.mark.parametrize("name", ["c1", "tiny"])
+def test_statistics_match_oracle(name):
+    """|Omega_v(i)| and kappa_v(i) exact, away from threshold pixels."""
+    sc = _scene(name)
+    say(f"[gpu] statistics {name}")
+    R = _rast(sc)
+    g, cams, xi, img = run_forward(R, sc)
+    V = sc.n_views
+    target = torch.from_numpy(sc.target.astype(np.float32)).cuda()
+    dl = torch.empty_like(img.color)
+    loss = torch.empty(V, device="cuda")
+    R.loss_l1(target, img, dl, loss)
+    st = ViewStats.zeros(sc.n)
+    grads = g.zeros_like()
+    R.render_bwd(g, cams, xi, img, dl, target=target, tau_err=0.1, view_loss=loss, grads=grads, stats=st)
+    torch.cuda.synchronize()
+    cfg = oracle_cfg(R)
+    om = np.zeros(sc.n, np.int64)
+    ka = np.zeros(sc.n, np.int64)
+    bad = _involved(sc, cfg)
+    lossv = loss.cpu().numpy()
+    col = img.color.cpu().numpy()
+    for v in range(V):
+        ov = oracle.View(sc, v, cfg)
+        s = ov.stats(sc.target[v], 0.1)
+        om += s["omega"]
+        ka += s["kappa"]
+        pr = ov.proj()
+        bad |= rect_hits(s["mask_margin"] < 1e-4, pr["fxi"], pr["fyi"], pr["rx"], pr["ry"]) & pr["visible"]
+        ref_loss = np.abs(col[v].astype(np.float64) - sc.target[v]).mean()
+        assert lossv[v] == pytest.approx(ref_loss, rel=1e-5)
+    inc = ~bad
+    gom = st.omega_sum.cpu().numpy()
+    gka = st.kappa_sum.cpu().numpy()
+    mism = ((gom != om) | (gka != ka)) & inc
+    say(f"  excluded {int(bad.sum())}/{sc.n}, count mismatches {int(mism.sum())}")
+    assert mism.sum() <= max(1, 1e-3 * inc.sum())
+    assert (gka <= gom).all()
+    gam = st.gamma_sum.cpu().numpy()
+    # gamma = sum_v L_v |Omega_v|, with the GPU's own per-view losses
+    assert gam.sum() > 0
+
+
+def test_tile_shapes_and_batches_give_identical_images():
+    sc = _scene("c1")
+    say("[gpu] tile invariance")
+    ref = None
+    for tile in ((16, 16), (8, 32), (32, 8)):
+        for batch in (32, 256):
+            R = _rast(sc, tile=tile, batch=batch)
+            _, _, _, img = run_forward(R, sc)
+            c = img.color.cpu().numpy()
+            if ref is None:
+                ref = c
+            else:
+                assert np.array_equal(c, ref), (tile, batch)
