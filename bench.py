@@ -1,0 +1,314 @@
+#!/usr/bin/env python3
+"""Benchmark of the hot path on one MI355X.
+
+Workload: the batched keyframe chunk -- 2M Gaussians along a 1 km synthetic
+driving trajectory, the 8 sampled keyframes of one chunk at 1242x375, SH
+degree 3, FP32 with FP32 gradient accumulation.  One step = one chunk: zero
+the accumulators, project, bin + sort, composite forward, L1 loss, composite
+backward, projection backward with footprint statistics, chunk scores and the
+densify / prune decision -- all captured in one HIP graph and launched once.
+The plain baseline runs the same library one view at a time with a host read
+of the pair count between projection and sort, as a naive loop would.
+
+Prints one JSON line (see the repository's measurement notes for the fields).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+METRIC = "fwd+bwd Mpix/s and ms/keyframe-chunk at 2M Gaussians; batched vs plain"
+W, H, V, N = 1242, 375, 8, 2_000_000
+FAR = 80.0
+# algorithmic FP32 operations of the compositing backward: every tile-list
+# entry up to a pixel's last blended Gaussian is tested (10 flop), every
+# blended one is differentiated (52 flop); FMA counts 2.
+FLOP_TEST, FLOP_BLEND = 10, 52
+# non-packed FP32 VALU peak: 256 CUs x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
+PEAK_ALU_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    with open(os.path.join(ROOT, "paper_2606_30436_amd", "csrc", "kgs_render.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def read_traffic():
+    """Per-launch HBM bytes of the compositing backward from the committed
+    rocprofv3 counter summary; None if absent or taken on other kernel source."""
+    path = os.path.join(ROOT, "profiles", "render_bwd_c3_counters.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tile", type=str, default=None, help="e.g. 16x16 (skips the autotuner)")
+    ap.add_argument("--batch", type=int, default=None)
+    ap.add_argument("--stage-reps", type=int, default=5)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU layout is described in DESIGN.md, not run)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2606_30436_amd import scenes
+    from paper_2606_30436_amd.autotune import autotune
+    from paper_2606_30436_amd.rasterizer import (GaussianParams, Image, LifecycleState, Rasterizer, ViewStats,
+                                                 device_cameras, TILE_SHAPES, BATCHES)
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t0 = time.time()
+    sc = scenes.make_c3()
+    true = scenes.Scene(sc.meta["true"]["means"], sc.log_scales, sc.quats, sc.logits, sc.meta["true"]["sh"], 3,
+                        sc.cams, sc.pose_xi)
+    log(f"[bench] scene ready {time.time() - t0:.1f}s")
+    g = GaussianParams.from_scene(sc)
+    gt = GaussianParams.from_scene(true)
+    cams = device_cameras(sc.cams)
+
+    # ---- capacities: probe every tiling once with generous capacities
+    probe = Rasterizer(W, H, V, N, slot_capacity=V * N, pair_capacity=64_000_000, far_z=FAR)
+    max_s = max_p = 0
+    counts = {}
+    for tile in TILE_SHAPES:
+        probe.set_tiling(tile, 128)
+        probe.project(g, cams)
+        probe.bin_sort()
+        torch.cuda.synchronize()
+        assert probe.status() == 0, "probe overflow"
+        s, p = probe.counts()
+        counts[tile] = (s, p)
+        max_s, max_p = max(max_s, s), max(max_p, p)
+    # targets: renders of the unperturbed scene
+    probe.set_tiling((16, 16), 128)
+    target_img = Image.empty(V, H, W)
+    probe.project(gt, cams)
+    probe.bin_sort()
+    probe.render_fwd(target_img)
+    torch.cuda.synchronize()
+    target = target_img.color.clone()
+    probe.set_tiling((16, 16), 128)
+    probe.project(g, cams)
+    probe.bin_sort()
+    torch.cuda.synchronize()
+    bufs = probe.buffers()
+    visible = np.bincount(bufs["slot_view"].numpy(), minlength=V).tolist()
+    del bufs, probe, target_img
+    torch.cuda.empty_cache()
+    log(f"[bench] counts {counts} visible/view {visible}")
+
+    R = Rasterizer(W, H, V, N, slot_capacity=int(max_s * 1.25) + 1024, pair_capacity=int(max_p * 1.25) + 4096,
+                   far_z=FAR)
+    img = Image.empty(V, H, W)
+    dl = torch.empty_like(img.color)
+    loss = torch.empty(V, device=dev)
+    grads = g.zeros_like()
+    pose_grad = torch.zeros(V, 6, device=dev)
+    stats = ViewStats.zeros(N)
+    state = LifecycleState.zeros(N)
+    decision = torch.empty(N, dtype=torch.uint8, device=dev)
+
+    def desc(reset=True, with_state=True):
+        return R.chunk_desc(g, cams, None, target, img, dl, loss, grads, pose_grad, stats, tau_err=0.1,
+                            zero_accumulators=reset, state=state if with_state else None,
+                            decision=decision if with_state else None)
+
+    # ---- autotune tile shape x batch
+    if args.tile:
+        best = (tuple(int(x) for x in args.tile.split("x")), args.batch or 128)
+        table = None
+    elif args.no_autotune:
+        best, table = ((16, 16), args.batch or 128), None
+    else:
+        d = desc()
+        best, table = autotune(lambda: R.chunk_run(d), R.set_tiling, TILE_SHAPES, BATCHES, reps=3)
+        log(f"[bench] autotune best {best}")
+    R.set_tiling(best[0], best[1])
+
+    # ---- batched: one graph launch per chunk
+    d = desc()
+    graph = R.chunk_capture(d)
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        R.chunk_launch(graph)
+    torch.cuda.synchronize()
+    assert R.status() == 0, f"status {R.status()}"
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        R.chunk_launch(graph)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms = ev0.elapsed_time(ev1) / args.steps
+    log(f"[bench] batched {ms:.3f} ms/chunk (wall {1000 * wall / args.steps:.3f})")
+    batched_color = img.color.clone()
+    batched_dec = decision.clone()
+
+    # ---- per-stage timing (eager, same stream, HIP events)
+    names = ["project", "bin_sort", "render_fwd", "loss", "render_bwd_pixels", "project_bwd", "stats_decide"]
+    acc = {k: [] for k in names}
+    for _ in range(args.stage_reps):
+        grads.means.zero_()
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)]
+        evs[0].record(stream)
+        R.project(g, cams)
+        evs[1].record(stream)
+        R.bin_sort()
+        evs[2].record(stream)
+        R.render_fwd(img)
+        evs[3].record(stream)
+        R.loss_l1(target, img, dl, loss)
+        evs[4].record(stream)
+        R.render_bwd_pixels(img, dl, None, target, 0.1)
+        evs[5].record(stream)
+        R.project_bwd(g, cams, None, loss, grads, pose_grad, stats)
+        evs[6].record(stream)
+        R.accumulate_stats(stats, V, state, reset=False)
+        R.decide(state, keep_map=False)
+        evs[7].record(stream)
+        torch.cuda.synchronize()
+        for k, nme in enumerate(names):
+            acc[nme].append(evs[k].elapsed_time(evs[k + 1]))
+    stage_ms = {k: float(np.median(v)) for k, v in acc.items()}
+    log(f"[bench] stages {json.dumps({k: round(v, 3) for k, v in stage_ms.items()})}")
+    n_slots, n_pairs = R.counts()
+    E = int(img.last.to(torch.int64).sum().item())
+    E_b = int(stats.omega_sum.to(torch.int64).sum().item()) // args.stage_reps
+    flop = FLOP_TEST * E + FLOP_BLEND * E_b
+    t_bwd = stage_ms["render_bwd_pixels"] / 1e3
+    achieved = flop / t_bwd / 1e12
+    traffic = read_traffic()
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_ALU_TFLOPS, 2),
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_ALU_TFLOPS, 4), "traffic": traffic,
+                "kernel": "k_render_bwd (compositing backward)", "evaluations": E, "blended": E_b,
+                "kernel_ms": round(stage_ms["render_bwd_pixels"], 4)}
+
+    # ---- plain per-view loop (same library, 16x16 tiles, batch 128, no graph)
+    plain_ms = None
+    identical = None
+    if not args.no_plain:
+        P1 = Rasterizer(W, H, 1, N, slot_capacity=int(max_s * 1.25) + 1024,
+                        pair_capacity=int(max_p * 1.25) + 4096, far_z=FAR)
+        pimg = Image.empty(V, H, W)
+        pdl = torch.empty_like(pimg.color)
+        ploss = torch.empty(V, device=dev)
+        pgr = g.zeros_like()
+        ppose = torch.zeros(V, 6, device=dev)
+        pst = ViewStats.zeros(N)
+        pstate = LifecycleState.zeros(N)
+        cam_bytes = cams.view(V, -1)
+
+        def plain_chunk():
+            for t in (pgr.means, pgr.log_scales, pgr.quats, pgr.logits, pgr.sh, ppose, pst.kappa_sum, pst.omega_sum,
+                      pst.gamma_sum, pst.grad_norm_sum, pst.view_count, pst.max_radius):
+                t.zero_()
+            for v in range(V):
+                vi = Image(pimg.color[v:v + 1], pimg.depth[v:v + 1], pimg.t_final[v:v + 1], pimg.last[v:v + 1])
+                P1.project(g, cam_bytes[v])
+                P1.counts()  # host read of the pair count before sorting
+                P1.bin_sort()
+                P1.render_fwd(vi)
+                P1.loss_l1(target[v:v + 1], vi, pdl[v:v + 1], ploss[v:v + 1])
+                P1.render_bwd(g, cam_bytes[v], None, vi, pdl[v:v + 1], target=target[v:v + 1], tau_err=0.1,
+                              view_loss=ploss[v:v + 1], grads=pgr, pose_grad=ppose[v:v + 1], stats=pst)
+            P1.accumulate_stats(pst, V, pstate, reset=True)
+            return P1.decide(pstate, keep_map=False)[0]
+
+        for _ in range(2):
+            plain_chunk()
+        torch.cuda.synchronize()
+        reps = max(3, args.steps // 4)
+        ev0.record(stream)
+        for _ in range(reps):
+            pdec = plain_chunk()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        plain_ms = ev0.elapsed_time(ev1) / reps
+        identical = bool(torch.equal(pimg.color, batched_color)) and bool(torch.equal(pdec, batched_dec))
+        log(f"[bench] plain {plain_ms:.3f} ms/chunk, identical outputs {identical}")
+        del P1
+
+    def psnr(a, b):
+        mse = float(((a - b) ** 2).mean().item())
+        return 10 * math.log10(1.0 / mse) if mse > 0 else float("inf")
+    psnr_b = psnr(batched_color.clamp(0, 1), target.clamp(0, 1))
+
+    # ---- CPU oracle baseline (the whole chunk, FP64, all host threads)
+    cpu = None
+    if not args.no_cpu:
+        sys.path.insert(0, ROOT)
+        import oracle
+        from oracle import OracleConfig
+        ocfg = OracleConfig(far=FAR)
+        tgt = target.cpu().numpy()
+        gC = dl.cpu().numpy().astype(np.float64)
+        ot0 = time.perf_counter()
+        for v in range(V):
+            ov = oracle.View(sc, v, ocfg)
+            ov.image()
+            ov.stats(tgt[v], 0.1)
+            ov.backward(gC[v])
+            del ov
+        ot = time.perf_counter() - ot0
+        cpu = {"value": round(V * W * H / ot / 1e6, 4), "unit": "Mpix/s", "cores": oracle.num_threads(),
+               "kind": "oracle", "sample": f"the full workload: all {V} views of the chunk, fwd + stats + bwd, FP64",
+               "seconds": round(ot, 2)}
+        log(f"[bench] cpu oracle {ot:.1f}s")
+
+    mpix = V * W * H / (ms / 1e3) / 1e6
+    out = {
+        "metric": METRIC, "value": round(mpix, 2), "unit": "Mpix/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "C3 batched chunk: 2M Gaussians on a 1 km trajectory, 8 keyframes at 1242x375, "
+                               "SH3, FP32, one HIP graph per chunk",
+                   "n_gaussians": N, "n_views": V, "width": W, "height": H, "far_z": FAR,
+                   "tile": list(best[0]), "batch": best[1], "visible_per_view": visible, "slots": n_slots,
+                   "pairs": n_pairs, "plain_ms_per_chunk": None if plain_ms is None else round(plain_ms, 4),
+                   "speedup_vs_plain": None if plain_ms is None else round(plain_ms / ms, 3),
+                   "outputs_identical_to_plain": identical, "psnr_vs_target_db": round(psnr_b, 3),
+                   "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
+                   "autotune_ms": table},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

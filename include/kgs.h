@@ -33,7 +33,9 @@
  *               max(0, SH(dir) + 0.5), depth = camera z.
  *   bin + sort  one (tile, Gaussian) pair per tile of the Gaussian's
  *               opacity-aware pixel rectangle, sorted by
- *               (view, tile, fp32 depth, Gaussian index).
+ *               (view, tile, fp32 depth, Gaussian index): records sorted by
+ *               (view, depth), pairs emitted in that order, then sorted
+ *               stably by tile.
  *   render_fwd  front-to-back alpha compositing of colour and depth with
  *               transmittance T_j = prod_{m<j}(1 - alpha_m) (appendix,
  *               "Depth Volume Rendering"): D = sum_j T_j alpha_j z_j.
@@ -89,12 +91,15 @@ typedef struct kgs_camera {
 /* Rasterizer configuration.  The paper inherits its rasterizer from 3DGS and
  * states none of these constants; kgs_config_default fills the readings
  * alpha_min = 1/255, alpha_max = 0.99, t_min = 1e-4, near_z = 0.2,
- * eps2d = 0.3 px^2, guard = 1.3, rect_margin = 1/256, bg = 0. */
+ * eps2d = 0.3 px^2, guard = 1.3, rect_margin = 1/256, bg = 0, and
+ * far_z = 1e30.  far_z is the single-level form of the paper's distance mask
+ * (appendix, "Level-of-Detail (LoD) Mask Computation": a Gaussian is rendered
+ * only inside its level's distance range): camera depths >= far_z are culled. */
 typedef struct kgs_config {
   int32_t tile_w, tile_h;   /* 16x16, 8x32 or 32x8 */
   int32_t batch;            /* Gaussians staged per LDS batch: 32, 64, 128 or 256 */
   int32_t sh_degree;        /* 0..3 */
-  float alpha_min, alpha_max, t_min, near_z, eps2d, guard, rect_margin;
+  float alpha_min, alpha_max, t_min, near_z, eps2d, guard, rect_margin, far_z;
   float bg[3];
   int32_t width, height;    /* image size of every view */
   int32_t max_views;        /* 1..64 views per call */
@@ -166,13 +171,15 @@ typedef struct kgs_buffers {
   const uint32_t* slot_view;    /* [S] view */
   const int32_t* slot_pix;      /* [S][4]: floor(mu_x), floor(mu_y), rx, ry */
   const uint32_t* slot_pairoff; /* [S] first pair (emission order) */
-  const uint64_t* keys;         /* [P] sorted keys: (view*tiles + tile) << 32 | depth bits */
+  const uint32_t* keys;         /* [P] sorted pair keys: view * tiles + tile (depth order within a tile) */
   const uint32_t* sorted_slot;  /* [P] slot of each sorted pair */
   const uint32_t* ranges;       /* [V*tiles][2] start, end in the sorted pairs */
   int32_t tiles_x, tiles_y;
 } kgs_buffers;
 
-/* A whole fwd + L1 loss + bwd + statistics pass over one chunk of views. */
+/* A whole pass over one chunk of views: zero the accumulators (optional),
+ * project, bin + sort, render_fwd, L1 loss, render_bwd with statistics, then
+ * (optional) close the chunk into the lifecycle state and decide. */
 typedef struct kgs_chunk_desc {
   kgs_gaussians gaussians;
   const kgs_camera* cams;   /* device [V] */
@@ -185,6 +192,11 @@ typedef struct kgs_chunk_desc {
   float* view_loss;         /* device [V]: mean |C - I| per view */
   kgs_grads grads;
   kgs_view_stats stats;
+  int32_t zero_accumulators; /* != 0: zero grads and stats first (fill kernels) */
+  float tau_d;
+  kgs_lifecycle_state state; /* densify != NULL: kgs_accumulate_stats(reset = 1) after the backward */
+  uint8_t* decision;         /* != NULL: kgs_densify_prune_decide after that */
+  double tau_p;
 } kgs_chunk_desc;
 
 typedef struct kgs_ctx kgs_ctx;
@@ -217,10 +229,11 @@ kgs_status kgs_project(kgs_ctx* ctx, const kgs_gaussians* g, const kgs_camera* c
                        const float* pose_xi, void* stream);
 
 /* Tile binning and depth sort of the projected records ("sorted Gaussians",
- * appendix, Depth Volume Rendering): one pair per tile of each record's
- * rectangle, keys (view * tiles + tile) << 32 | fp32 depth bits, LSD radix
- * sort (stable: equal keys keep Gaussian-index order), per-tile ranges.
- * Pair overflow sets KGS_FLAG_PAIR_OVERFLOW. */
+ * appendix, Depth Volume Rendering): the records are radix-sorted by
+ * (view, fp32 depth bits), one pair per tile of each record's rectangle is
+ * emitted in that order, and the pairs are radix-sorted stably by global tile
+ * index; equal depths keep Gaussian-index order.  Then per-tile ranges.
+ * Pair overflow sets KGS_FLAG_PAIR_OVERFLOW (at kgs_project). */
 kgs_status kgs_bin_sort(kgs_ctx* ctx, void* stream);
 
 /* Front-to-back compositing of every tile of every view (appendix, Depth
@@ -246,6 +259,18 @@ kgs_status kgs_render_bwd(kgs_ctx* ctx, const kgs_gaussians* g, const kgs_camera
                           const float* view_loss, const kgs_grads* grads, const kgs_view_stats* stats,
                           void* stream);
 
+/* The two halves of kgs_render_bwd, for callers that time or schedule them
+ * separately.  kgs_render_bwd_pixels: the compositing backward (recomputes
+ * each pixel's sequence, writes per-pair gradients and footprint counts into
+ * the workspace).  kgs_project_bwd: per Gaussian, the sum over its pairs and
+ * views, the chain rule to the parameters and the pose, and the statistics.
+ * Called in this order they equal kgs_render_bwd. */
+kgs_status kgs_render_bwd_pixels(kgs_ctx* ctx, const kgs_image* fwd, const float* dl_dcolor, const float* dl_ddepth,
+                                 const float* target, float tau_err, void* stream);
+kgs_status kgs_project_bwd(kgs_ctx* ctx, const kgs_gaussians* g, const kgs_camera* cams, int32_t n_views,
+                           const float* pose_xi, const float* view_loss, const kgs_grads* grads,
+                           const kgs_view_stats* stats, void* stream);
+
 /* Close a chunk (appendix, Densification Score and Pruning Score; Sec. 3.3
  * global rules):  S_d = kappa_sum / n_views,  L = ln(1 + gamma_sum),
  * S_p = (L - min_A L) / (max_A L - min_A L) over A = {omega_sum > 0} (0 off A
@@ -262,7 +287,7 @@ kgs_status kgs_accumulate_stats(kgs_ctx* ctx, const kgs_view_stats* stats, int64
 kgs_status kgs_densify_prune_decide(kgs_ctx* ctx, const kgs_lifecycle_state* state, int64_t n, double tau_p,
                                     uint8_t* decision, uint32_t* keep_map, uint32_t* n_keep, void* stream);
 
-/* The whole chunk: project, bin_sort, render_fwd, loss_l1, render_bwd. */
+/* The whole chunk as described by kgs_chunk_desc. */
 kgs_status kgs_chunk_run(kgs_ctx* ctx, const kgs_chunk_desc* desc, void* stream);
 
 /* Record kgs_chunk_run into a HIP graph (stream capture) and launch it. */

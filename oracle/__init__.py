@@ -50,7 +50,7 @@ class _Camera(ctypes.Structure):
 class _Cfg(ctypes.Structure):
     _fields_ = [("alpha_min", ctypes.c_double), ("alpha_max", ctypes.c_double),
                 ("t_min", ctypes.c_double), ("near_z", ctypes.c_double), ("eps2d", ctypes.c_double),
-                ("guard", ctypes.c_double), ("rect_margin", ctypes.c_double),
+                ("guard", ctypes.c_double), ("rect_margin", ctypes.c_double), ("far_z", ctypes.c_double),
                 ("bg", ctypes.c_double * 3), ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32)]
 
 
@@ -110,6 +110,7 @@ class OracleConfig:
     eps2d: float = 0.3
     guard: float = 1.3
     rect_margin: float = 1.0 / 256.0
+    far: float = 1e30
     bg: tuple = (0.0, 0.0, 0.0)
     tile_w: int = 16
     tile_h: int = 16
@@ -118,6 +119,7 @@ class OracleConfig:
         c = _Cfg()
         c.alpha_min, c.alpha_max, c.t_min = self.alpha_min, self.alpha_max, self.t_min
         c.near_z, c.eps2d, c.guard, c.rect_margin = self.near, self.eps2d, self.guard, self.rect_margin
+        c.far_z = self.far
         for k in range(3):
             c.bg[k] = self.bg[k]
         c.tile_w, c.tile_h = self.tile_w, self.tile_h

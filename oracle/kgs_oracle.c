@@ -25,7 +25,7 @@
  *                    kappa_v(i) = sum of M over Omega_v(i)
  *
  * Constants that the paper does not state (alpha_min, alpha_max, T_min, near
- * plane, low-pass term, guard band, rect margin, background) come in through
+ * and far planes, low-pass term, guard band, rect margin, background) come in through
  * orc_cfg; none is hard-coded here.
  *
  * Build: gcc -O2 -fopenmp -shared -fPIC kgs_oracle.c -o liboracle.so -lm
@@ -47,7 +47,7 @@ typedef struct {
 } orc_camera;
 
 typedef struct {
-  double alpha_min, alpha_max, t_min, near_z, eps2d, guard, rect_margin;
+  double alpha_min, alpha_max, t_min, near_z, eps2d, guard, rect_margin, far_z;
   double bg[3];
   int32_t tile_w, tile_h;
 } orc_cfg;
@@ -278,7 +278,8 @@ static void project_one(const orc_view* v, int64_t i, orc_proj* p) {
   for (int r = 0; r < 3; ++r)
     p->t[r] = v->Rp[r * 3 + 0] * mu[0] + v->Rp[r * 3 + 1] * mu[1] + v->Rp[r * 3 + 2] * mu[2] + v->tp[r];
   const double tx = p->t[0], ty = p->t[1], tz = p->t[2];
-  if (!(tz > v->cfg.near_z)) return;
+  /* near plane, and the single-level distance mask (culled at and beyond far_z) */
+  if (!(tz > v->cfg.near_z) || !(tz < v->cfg.far_z)) return;
   p->o = 1.0 / (1.0 + exp(-(double)v->logits[i]));
   if (p->o < v->cfg.alpha_min) return;
   double q[4] = {v->quats[i], v->quats[n + i], v->quats[2 * n + i], v->quats[3 * n + i]};

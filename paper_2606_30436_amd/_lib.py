@@ -29,7 +29,7 @@ class KgsCamera(ctypes.Structure):
 class KgsConfig(ctypes.Structure):
     _fields_ = [("tile_w", c_int32), ("tile_h", c_int32), ("batch", c_int32), ("sh_degree", c_int32),
                 ("alpha_min", c_float), ("alpha_max", c_float), ("t_min", c_float), ("near_z", c_float),
-                ("eps2d", c_float), ("guard", c_float), ("rect_margin", c_float), ("bg", c_float * 3),
+                ("eps2d", c_float), ("guard", c_float), ("rect_margin", c_float), ("far_z", c_float), ("bg", c_float * 3),
                 ("width", c_int32), ("height", c_int32), ("max_views", c_int32), ("pad_", c_int32),
                 ("max_gaussians", c_int64), ("slot_capacity", c_int64), ("pair_capacity", c_int64)]
 
@@ -66,7 +66,9 @@ class KgsBuffers(ctypes.Structure):
 class KgsChunkDesc(ctypes.Structure):
     _fields_ = [("gaussians", KgsGaussians), ("cams", c_void_p), ("pose_xi", c_void_p), ("n_views", c_int32),
                 ("tau_err", c_float), ("target", c_void_p), ("image", KgsImage), ("dl_dcolor", c_void_p),
-                ("view_loss", c_void_p), ("grads", KgsGrads), ("stats", KgsViewStats)]
+                ("view_loss", c_void_p), ("grads", KgsGrads), ("stats", KgsViewStats),
+                ("zero_accumulators", c_int32), ("tau_d", c_float), ("state", KgsLifecycleState),
+                ("decision", c_void_p), ("tau_p", c_double)]
 
 
 _SIGS = {
@@ -81,6 +83,9 @@ _SIGS = {
     "kgs_loss_l1": (c_int32, [c_void_p, c_void_p, P(KgsImage), c_void_p, c_void_p, c_void_p]),
     "kgs_render_bwd": (c_int32, [c_void_p, P(KgsGaussians), c_void_p, c_int32, c_void_p, P(KgsImage), c_void_p,
                                  c_void_p, c_void_p, c_float, c_void_p, P(KgsGrads), P(KgsViewStats), c_void_p]),
+    "kgs_render_bwd_pixels": (c_int32, [c_void_p, P(KgsImage), c_void_p, c_void_p, c_void_p, c_float, c_void_p]),
+    "kgs_project_bwd": (c_int32, [c_void_p, P(KgsGaussians), c_void_p, c_int32, c_void_p, c_void_p, P(KgsGrads),
+                                  P(KgsViewStats), c_void_p]),
     "kgs_accumulate_stats": (c_int32, [c_void_p, P(KgsViewStats), c_int64, c_int32, P(KgsLifecycleState), c_float,
                                        c_int32, c_void_p]),
     "kgs_densify_prune_decide": (c_int32, [c_void_p, P(KgsLifecycleState), c_int64, c_double, c_void_p, c_void_p,
@@ -201,6 +206,18 @@ def kgs_render_bwd(ctx, g: KgsGaussians, cams, n_views, pose_xi, img: KgsImage, 
                                 ptr(view_loss), ctypes.byref(grads),
                                 ctypes.byref(stats) if stats is not None else None, stream_handle(stream)),
           "kgs_render_bwd")
+
+
+def kgs_render_bwd_pixels(ctx, img: KgsImage, dl_dcolor, dl_ddepth, target, tau_err, stream=None):
+    check(load().kgs_render_bwd_pixels(ctypes.c_void_p(ctx), ctypes.byref(img), ptr(dl_dcolor), ptr(dl_ddepth),
+                                       ptr(target), float(tau_err), stream_handle(stream)), "kgs_render_bwd_pixels")
+
+
+def kgs_project_bwd(ctx, g: KgsGaussians, cams, n_views, pose_xi, view_loss, grads: KgsGrads,
+                    stats: KgsViewStats | None, stream=None):
+    check(load().kgs_project_bwd(ctypes.c_void_p(ctx), ctypes.byref(g), ptr(cams), n_views, ptr(pose_xi),
+                                 ptr(view_loss), ctypes.byref(grads), ctypes.byref(stats) if stats is not None else None,
+                                 stream_handle(stream)), "kgs_project_bwd")
 
 
 def kgs_accumulate_stats(ctx, stats: KgsViewStats, n, n_views, state: KgsLifecycleState, tau_d, reset=0,

@@ -22,6 +22,8 @@ kgs_status kgs_launch_accumulate(kgs_ctx*, const kgs_view_stats*, int64_t, int, 
 kgs_status kgs_launch_decide(kgs_ctx*, const kgs_lifecycle_state*, int64_t, double, uint8_t*, uint32_t*, uint32_t*,
                              hipStream_t);
 
+__global__ void k_fill_u32(uint32_t* __restrict__ p, uint64_t n, uint32_t v);
+
 kgs_status kgs_check_launch() {
   const hipError_t e = hipGetLastError();
   return e == hipSuccess ? KGS_OK : KGS_ERR_HIP;
@@ -64,17 +66,21 @@ size_t layout(const kgs_config& c, char* base, kgs_ctx* ctx) {
   p = take(16 * S);                             if (ctx) ctx->slot_pix = (int4*)p;
   p = take(4 * S);                              if (ctx) ctx->slot_pairoff = (uint32_t*)p;
   p = take(4 * S);                              if (ctx) ctx->slot_ntiles = (uint32_t*)p;
-  p = take(8 * P);                              if (ctx) ctx->keys[0] = (uint64_t*)p;
-  p = take(8 * P);                              if (ctx) ctx->keys[1] = (uint64_t*)p;
+  p = take(4 * P);                              if (ctx) ctx->keys[0] = (uint32_t*)p;
+  p = take(4 * P);                              if (ctx) ctx->keys[1] = (uint32_t*)p;
   p = take(4 * P);                              if (ctx) ctx->vals[0] = (uint32_t*)p;
   p = take(4 * P);                              if (ctx) ctx->vals[1] = (uint32_t*)p;
-  p = take(4 * P);                              if (ctx) ctx->pair_slot = (uint32_t*)p;
-  p = take(4 * P);                              if (ctx) ctx->sorted_slot = (uint32_t*)p;
+  p = take(8 * S);                              if (ctx) ctx->slot_keys[0] = (uint64_t*)p;
+  p = take(8 * S);                              if (ctx) ctx->slot_keys[1] = (uint64_t*)p;
+  p = take(4 * S);                              if (ctx) ctx->slot_vals[0] = (uint32_t*)p;
+  p = take(4 * S);                              if (ctx) ctx->slot_vals[1] = (uint32_t*)p;
+  p = take(4 * (S / 2048 + 2));                 if (ctx) ctx->scan_part = (uint32_t*)p;
   p = take(8 * V * T);                          if (ctx) ctx->ranges = (uint2*)p;
   p = take(48 * P);                             if (ctx) ctx->pair_grad = (float4*)p;
-  p = take(4 * 256 * KGS_SORT_BLOCKS);          if (ctx) ctx->radix_hist = (uint32_t*)p;
+  p = take(4 * 256 * KGS_SORT_BLOCKS * 4);      if (ctx) ctx->radix_hist = (uint32_t*)p;
   p = take(4 * 256 * KGS_MAX_PASSES);           if (ctx) ctx->radix_total = (uint32_t*)p;
-  p = take(24 * V * nb);                        if (ctx) ctx->pose_partial = (float*)p;
+  p = take(4 * KGS_SLOT_WORDS * S);             if (ctx) ctx->slot_bwd = (float4*)p;
+  p = take(48 * V * KGS_POSE_BLOCKS);           if (ctx) ctx->pose_partial = (double*)p;
   p = take(8 * V * KGS_LOSS_BLOCKS);            if (ctx) ctx->loss_partial = (double*)p;
   p = take(16 * (nb + 1));                      if (ctx) ctx->mm_partial = (double*)p;
   p = take(4 * (nb + 1));                       if (ctx) ctx->keep_partial = (uint32_t*)p;
@@ -92,6 +98,7 @@ kgs_status config_check(const kgs_config* c) {
   if (c->pair_capacity < 0 || c->pair_capacity >= (int64_t(1) << 32)) return KGS_ERR_INVALID_ARG;
   if (!(c->alpha_min > 0.f && c->alpha_min < 1.f) || !(c->alpha_max > 0.f && c->alpha_max <= 1.f))
     return KGS_ERR_INVALID_ARG;
+  if (!(c->far_z > c->near_z)) return KGS_ERR_INVALID_ARG;
   if (!(c->t_min >= 0.f) || !(c->near_z > 0.f) || !(c->eps2d >= 0.f) || !(c->guard > 0.f)) return KGS_ERR_INVALID_ARG;
   // keys hold the global tile index in 32 bits
   if ((int64_t)c->max_views * max_tiles_of(c->width, c->height) >= (int64_t(1) << 31)) return KGS_ERR_INVALID_ARG;
@@ -141,6 +148,7 @@ void kgs_config_default(kgs_config* c, int32_t width, int32_t height) {
   c->eps2d = 0.3f;
   c->guard = 1.3f;
   c->rect_margin = 1.0f / 256.0f;
+  c->far_z = 1e30f;
   c->width = width;
   c->height = height;
   c->max_views = 1;
@@ -240,6 +248,22 @@ kgs_status kgs_render_bwd(kgs_ctx* ctx, const kgs_gaussians* g, const kgs_camera
   return kgs_launch_project_bwd(ctx, g, cams, n_views, pose_xi, view_loss, grads, stats, st);
 }
 
+kgs_status kgs_render_bwd_pixels(kgs_ctx* ctx, const kgs_image* fwd, const float* dl_dcolor, const float* dl_ddepth,
+                                 const float* target, float tau_err, void* stream) {
+  if (!ctx || !image_ok(fwd) || !dl_dcolor) return KGS_ERR_INVALID_ARG;
+  if (!ctx->binned) return KGS_ERR_STATE;
+  return kgs_launch_render_bwd(ctx, fwd, dl_dcolor, dl_ddepth, target, tau_err, (hipStream_t)stream);
+}
+
+kgs_status kgs_project_bwd(kgs_ctx* ctx, const kgs_gaussians* g, const kgs_camera* cams, int32_t n_views,
+                           const float* pose_xi, const float* view_loss, const kgs_grads* grads,
+                           const kgs_view_stats* stats, void* stream) {
+  if (!ctx || !gaussians_ok(ctx, g) || !cams || !grads) return KGS_ERR_INVALID_ARG;
+  if (!ctx->binned) return KGS_ERR_STATE;
+  if (n_views != ctx->last_views || g->n != ctx->last_n || g->sh_degree != ctx->last_degree) return KGS_ERR_STATE;
+  return kgs_launch_project_bwd(ctx, g, cams, n_views, pose_xi, view_loss, grads, stats, (hipStream_t)stream);
+}
+
 kgs_status kgs_accumulate_stats(kgs_ctx* ctx, const kgs_view_stats* stats, int64_t n, int32_t n_views,
                                 const kgs_lifecycle_state* state, float tau_d, int32_t reset, void* stream) {
   if (!ctx || !stats || !state || n < 0 || n > ctx->cfg.max_gaussians || n_views < 1) return KGS_ERR_INVALID_ARG;
@@ -256,15 +280,49 @@ kgs_status kgs_densify_prune_decide(kgs_ctx* ctx, const kgs_lifecycle_state* sta
   return kgs_launch_decide(ctx, state, n, tau_p, decision, keep_map, n_keep, (hipStream_t)stream);
 }
 
+static void fill_zero(void* p, uint64_t bytes, hipStream_t st) {
+  if (!p || bytes == 0) return;
+  const uint64_t words = bytes / 4;
+  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)std::min<uint64_t>((words + 255) / 256, 2048)), dim3(256), 0, st,
+                     (uint32_t*)p, words, 0u);
+}
+
 kgs_status kgs_chunk_run(kgs_ctx* ctx, const kgs_chunk_desc* d, void* stream) {
   if (!ctx || !d || !d->target || !d->dl_dcolor || !d->view_loss) return KGS_ERR_INVALID_ARG;
+  if (!gaussians_ok(ctx, &d->gaussians) || d->n_views < 1 || d->n_views > ctx->cfg.max_views)
+    return KGS_ERR_INVALID_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  const uint64_t n = (uint64_t)d->gaussians.n;
+  const uint64_t K = (uint64_t)(d->gaussians.sh_degree + 1) * (d->gaussians.sh_degree + 1);
+  if (d->zero_accumulators) {
+    fill_zero(d->grads.means, 12 * n, st);
+    fill_zero(d->grads.log_scales, 12 * n, st);
+    fill_zero(d->grads.quats, 16 * n, st);
+    fill_zero(d->grads.opacity_logits, 4 * n, st);
+    fill_zero(d->grads.sh, 12 * K * n, st);
+    fill_zero(d->grads.pose_xi, 24 * (uint64_t)d->n_views, st);
+    fill_zero(d->stats.kappa_sum, 4 * n, st);
+    fill_zero(d->stats.omega_sum, 4 * n, st);
+    fill_zero(d->stats.gamma_sum, 8 * n, st);
+    fill_zero(d->stats.grad_norm_sum, 4 * n, st);
+    fill_zero(d->stats.view_count, 4 * n, st);
+    fill_zero(d->stats.max_radius, 4 * n, st);
+  }
   kgs_status s = kgs_project(ctx, &d->gaussians, d->cams, d->n_views, d->pose_xi, stream);
   if (s != KGS_OK) return s;
   if ((s = kgs_bin_sort(ctx, stream)) != KGS_OK) return s;
   if ((s = kgs_render_fwd(ctx, &d->image, stream)) != KGS_OK) return s;
   if ((s = kgs_loss_l1(ctx, d->target, &d->image, d->dl_dcolor, d->view_loss, stream)) != KGS_OK) return s;
-  return kgs_render_bwd(ctx, &d->gaussians, d->cams, d->n_views, d->pose_xi, &d->image, d->dl_dcolor, nullptr,
-                        d->target, d->tau_err, d->view_loss, &d->grads, &d->stats, stream);
+  s = kgs_render_bwd(ctx, &d->gaussians, d->cams, d->n_views, d->pose_xi, &d->image, d->dl_dcolor, nullptr,
+                     d->target, d->tau_err, d->view_loss, &d->grads, &d->stats, stream);
+  if (s != KGS_OK) return s;
+  if (d->state.densify) {
+    s = kgs_accumulate_stats(ctx, &d->stats, d->gaussians.n, d->n_views, &d->state, d->tau_d, 1, stream);
+    if (s != KGS_OK) return s;
+    if (d->decision)
+      s = kgs_densify_prune_decide(ctx, &d->state, d->gaussians.n, d->tau_p, d->decision, nullptr, nullptr, stream);
+  }
+  return s;
 }
 
 kgs_status kgs_chunk_capture(kgs_ctx* ctx, const kgs_chunk_desc* d, kgs_graph** out) {

@@ -12,6 +12,8 @@
 #define KGS_SORT_BLOCKS 512           // fixed grid of the radix sort passes
 #define KGS_LOSS_BLOCKS 64            // blocks per view of the loss reduction
 #define KGS_MAX_PASSES 8
+#define KGS_POSE_BLOCKS 32            // pieces per view of the pose reduction
+#define KGS_SLOT_WORDS 40             // words of a slot's backward record
 
 // ---------------------------------------------------------------- device camera
 // Pose already applied: x_cam = R x + t; ctr = camera centre in the world.
@@ -46,15 +48,18 @@ struct kgs_ctx {
   int4* slot_pix;                     // [S]
   uint32_t* slot_pairoff;             // [S]
   uint32_t* slot_ntiles;              // [S]
-  uint64_t* keys[2];                  // [P] ping-pong
+  uint32_t* keys[2];                  // [P] ping-pong: global tile index of each pair
   uint32_t* vals[2];                  // [P] ping-pong (pair emission position)
-  uint32_t* pair_slot;                // [P] slot of each pair, by emission position
-  uint32_t* sorted_slot;              // [P] slot of each pair, by sorted position
+  uint64_t* slot_keys[2];             // [S] ping-pong: (view << 32) | depth bits
+  uint32_t* slot_vals[2];             // [S] ping-pong: slot index
+  uint32_t* scan_part;                // [S / 2048 + 2] block partials of the pair-offset scan
+  uint32_t* sorted_slot;              // [P] slot of each sorted pair (the sort's value buffer)
   uint2* ranges;                      // [max_views * max_tiles]
   float4* pair_grad;                  // [P][3] per-pair record-space gradients + counts
-  uint32_t* radix_hist;               // [256][KGS_SORT_BLOCKS]
+  uint32_t* radix_hist;               // [256][KGS_SORT_BLOCKS * 4] per-wave partitions
   uint32_t* radix_total;              // [KGS_MAX_PASSES][256]
-  float* pose_partial;                // [max_views][nb][6]
+  float4* slot_bwd;                   // [S][KGS_SLOT_WORDS / 4] per-slot backward records
+  double* pose_partial;               // [max_views][KGS_POSE_BLOCKS][6]
   double* loss_partial;               // [max_views][KGS_LOSS_BLOCKS]
   double* mm_partial;                 // [nb][2]
   uint32_t* keep_partial;             // [nb + 1]
@@ -137,12 +142,13 @@ struct ProjCore {
 
 // cw: world covariance (xx, xy, xz, yy, yz, zz); o: opacity.  Returns visibility.
 __device__ __forceinline__ bool project_core(const CamDev& c, const float mu[3], const float cw[6], float o,
-                                             float near_z, float eps2d, float rect_margin, float log_qscale,
+                                             float near_z, float far_z, float eps2d, float rect_margin,
+                                             float log_qscale,
                                              int tile_w, int tile_h, int tiles_x, int tiles_y, ProjCore& p) {
   p.tx = c.R[0] * mu[0] + c.R[1] * mu[1] + c.R[2] * mu[2] + c.t[0];
   p.ty = c.R[3] * mu[0] + c.R[4] * mu[1] + c.R[5] * mu[2] + c.t[1];
   p.tz = c.R[6] * mu[0] + c.R[7] * mu[1] + c.R[8] * mu[2] + c.t[2];
-  if (!(p.tz > near_z)) return false;
+  if (!(p.tz > near_z) || !(p.tz < far_z)) return false;
   const float iz = 1.0f / p.tz;
   float ux = p.tx * iz, uy = p.ty * iz;
   p.clx = 0;
@@ -313,6 +319,34 @@ __device__ __forceinline__ void sh_basis_grad(int degree, float x, float y, floa
   dY[13][0] = -d3c * (4.f * zz - 3.f * xx - yy); dY[13][1] = 2.f * d3c * x * y;           dY[13][2] = -8.f * d3c * x * z;
   dY[14][0] = 2.f * d3e * x * z;              dY[14][1] = -2.f * d3e * y * z;             dY[14][2] = d3e * (xx - yy);
   dY[15][0] = -3.f * d3a * (xx - yy);         dY[15][1] = 6.f * d3a * x * y;              dY[15][2] = 0.f;
+}
+
+// sum_k w[k] grad Y_k (gradient of the polynomial extensions of sh_basis).
+__device__ __forceinline__ void sh_dir_grad(int degree, float x, float y, float z, const float* w, float g[3]) {
+  g[0] = g[1] = g[2] = 0.f;
+  if (degree < 1) return;
+  const float c1 = KGS_SQRT(3.0f / (4.0f * sh::PI_F));
+  g[1] -= c1 * w[1];
+  g[2] += c1 * w[2];
+  g[0] -= c1 * w[3];
+  if (degree < 2) return;
+  const float a = 0.5f * KGS_SQRT(15.0f / sh::PI_F), b = 0.25f * KGS_SQRT(5.0f / sh::PI_F),
+              cc = 0.25f * KGS_SQRT(15.0f / sh::PI_F);
+  g[0] += w[4] * a * y - w[6] * 2.f * b * x - w[7] * a * z + w[8] * 2.f * cc * x;
+  g[1] += w[4] * a * x - w[5] * a * z - w[6] * 2.f * b * y - w[8] * 2.f * cc * y;
+  g[2] += -w[5] * a * y + w[6] * 4.f * b * z - w[7] * a * x;
+  if (degree < 3) return;
+  const float d3a = 0.25f * KGS_SQRT(35.0f / (2.0f * sh::PI_F)), d3b = 0.5f * KGS_SQRT(105.0f / sh::PI_F),
+              d3c = 0.25f * KGS_SQRT(21.0f / (2.0f * sh::PI_F)), d3d = 0.25f * KGS_SQRT(7.0f / sh::PI_F),
+              d3e = 0.25f * KGS_SQRT(105.0f / sh::PI_F);
+  const float xx = x * x, yy = y * y, zz = z * z;
+  g[0] += -w[9] * 6.f * d3a * x * y + w[10] * d3b * y * z + w[11] * 2.f * d3c * x * y - w[12] * 6.f * d3d * x * z -
+          w[13] * d3c * (4.f * zz - 3.f * xx - yy) + w[14] * 2.f * d3e * x * z - w[15] * 3.f * d3a * (xx - yy);
+  g[1] += -w[9] * 3.f * d3a * (xx - yy) + w[10] * d3b * x * z - w[11] * d3c * (4.f * zz - xx - 3.f * yy) -
+          w[12] * 6.f * d3d * y * z + w[13] * 2.f * d3c * x * y - w[14] * 2.f * d3e * y * z +
+          w[15] * 6.f * d3a * x * y;
+  g[2] += w[10] * d3b * x * y - w[11] * 8.f * d3c * y * z + w[12] * d3d * (6.f * zz - 3.f * xx - 3.f * yy) -
+          w[13] * 8.f * d3c * x * z + w[14] * d3e * (xx - yy);
 }
 
 // ---------------------------------------------------------------- compositing

@@ -107,7 +107,7 @@ __global__ void k_cam_setup(const kgs_camera* __restrict__ cams, const float* __
 
 // ---------------------------------------------------------------- counting
 struct ProjParams {
-  float alpha_min, log_alpha_min, near_z, eps2d, rect_margin;
+  float alpha_min, log_alpha_min, near_z, far_z, eps2d, rect_margin;
   int tile_w, tile_h, tiles_x, tiles_y;
 };
 
@@ -128,7 +128,7 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_count(kgs_gaussians g, const CamD
     uint32_t tiles = 0;
     if (G.ok) {
       ProjCore p;
-      if (project_core(cams[v], G.mu, G.cw, G.o, P.near_z, P.eps2d, P.rect_margin, P.log_alpha_min, P.tile_w,
+      if (project_core(cams[v], G.mu, G.cw, G.o, P.near_z, P.far_z, P.eps2d, P.rect_margin, P.log_alpha_min, P.tile_w,
                        P.tile_h, P.tiles_x, P.tiles_y, p))
         tiles = (uint32_t)((p.x1 - p.x0) * (p.y1 - p.y0));
     }
@@ -233,7 +233,7 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_emit(kgs_gaussians g, const CamDe
     }
     const CamDev& c = cams[v];
     ProjCore p;
-    const bool vis_ok = G.ok && project_core(c, G.mu, G.cw, G.o, P.near_z, P.eps2d, P.rect_margin,
+    const bool vis_ok = G.ok && project_core(c, G.mu, G.cw, G.o, P.near_z, P.far_z, P.eps2d, P.rect_margin,
                                              P.log_alpha_min, P.tile_w, P.tile_h, P.tiles_x, P.tiles_y, p);
     float4 r0, r1, r2;
     int4 pix;
@@ -285,6 +285,7 @@ kgs_status kgs_launch_project(kgs_ctx* ctx, const kgs_gaussians* g, const kgs_ca
   P.alpha_min = cfg.alpha_min;
   P.log_alpha_min = logf(cfg.alpha_min);
   P.near_z = cfg.near_z;
+  P.far_z = cfg.far_z;
   P.eps2d = cfg.eps2d;
   P.rect_margin = cfg.rect_margin;
   P.tile_w = cfg.tile_w;

@@ -1,89 +1,85 @@
-// Backward of the projection: per Gaussian, the deterministic segmented sum of
-// its pairs' gradients in every view, the chain rule to the 3D parameters and
-// to the camera pose, and the per-view footprint statistics.
-//
-// One thread per Gaussian looping over the views of the call (same block
-// structure as the emission kernel, so the block-local scan recovers each
-// record's slot and pair offset without storing a map).  Views are summed in
-// view order, so a batched call and a per-view loop produce identical bits.
-// The pose gradient is accumulated as the left-perturbation gradient
-// (rho, phi) of T' = Exp(delta) T', reduced per block into a [V][blocks][6]
-// array, and turned into d/dxi by the SE(3) left Jacobian in a final pass.
+// Backward of the projection, deterministic throughout:
+//   k_proj_bwd      per block of 256 Gaussians: (1) every (view, Gaussian)
+//                   record of the block -- the segmented sum of its pairs'
+//                   gradients (contiguous in emission order), the chain rule to
+//                   the Gaussian's parameters and to the view's pose, the view's
+//                   footprint statistics -- as one 160-byte record per slot;
+//                   (2) per Gaussian, the sum of its records over the views in
+//                   view order (the block-local scan of the visibility counts
+//                   recovers each slot index, as in the emission), added into
+//                   the gradients and statistics.
+//   k_pose_reduce   per view, the pose contributions of its slots (contiguous,
+//                   slots are in (view, Gaussian) order) in a fixed tree.
+// Views are summed in view order, so a batched call and a per-view loop give
+// identical bits.  The pose gradient is accumulated as the left-perturbation
+// gradient (rho, phi) of T' = Exp(delta) T' and turned into d/dxi by the SE(3)
+// left Jacobian at the end.
+#include <algorithm>
+
 #include "kgs_internal.h"
 
 struct BwdParams {
-  float alpha_min, log_alpha_min, near_z, eps2d, rect_margin;
+  float alpha_min, log_alpha_min, near_z, far_z, eps2d, rect_margin;
   int tile_w, tile_h, tiles_x, tiles_y;
 };
 
+
+// Slot record (40 words): 0-2 dL/dmean, 3-5 dL/dlog_scale, 6-9 dL/dquat,
+// 10 dL/dlogit, 11-16 pose (rho, phi), 17 |Omega| (u32), 18 kappa (u32),
+// 19 ||dL/dmu2D||, 20 pixel radius (i32), 21-23 dL/dcolour where the colour is
+// not clamped (0 where it is), 24-39 the SH basis at the view direction.
+// Sum of the 12-word pair records [po, po + tiles): 10 record-space gradient
+// terms and the two footprint counts.
+__device__ __forceinline__ void pair_sum_serial(const float4* __restrict__ pair_grad, uint32_t po, uint32_t tiles,
+                                                float r[10], uint32_t& om, uint32_t& kap) {
+  for (uint32_t k = 0; k < tiles; ++k) {
+    const float4 a = pair_grad[((size_t)po + k) * 3], b = pair_grad[((size_t)po + k) * 3 + 1],
+                 cc = pair_grad[((size_t)po + k) * 3 + 2];
+    r[0] += a.x; r[1] += a.y; r[2] += a.z; r[3] += a.w;
+    r[4] += b.x; r[5] += b.y; r[6] += b.z; r[7] += b.w;
+    r[8] += cc.x; r[9] += cc.y;
+    om += __float_as_uint(cc.z);
+    kap += __float_as_uint(cc.w);
+  }
+}
+
 template <int DEG>
-__global__ __launch_bounds__(KGS_BLOCK) void k_project_bwd(
-    kgs_gaussians g, const CamDev* __restrict__ cams, int V, BwdParams P, const uint32_t* __restrict__ vis,
-    const uint32_t* __restrict__ blk_base, int64_t nb, uint64_t slot_cap, uint64_t pair_cap,
-    const float4* __restrict__ pair_grad, const float* __restrict__ view_loss, kgs_grads gr, kgs_view_stats st,
-    float* __restrict__ pose_partial) {
+__device__ __forceinline__ void slot_record(uint32_t s, const kgs_gaussians& g, const CamDev* __restrict__ cams,
+                                            const BwdParams& P, const uint32_t* __restrict__ slot_gid,
+                                            const uint32_t* __restrict__ slot_view,
+                                            const uint32_t* __restrict__ slot_ntiles, const float r[10],
+                                            uint32_t om, uint32_t kap, float4* __restrict__ slot_bwd) {
   constexpr int K = (DEG + 1) * (DEG + 1);
-  __shared__ uint32_t scan_sh[16];
-  __shared__ float pose_sh[4][6];
-  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  const int64_t i = (int64_t)blockIdx.x * KGS_BLOCK + threadIdx.x;
   const int64_t n = g.n;
-  const bool valid = i < n;
-  GaussLocal G;
-  bool bad = false;
-  G.ok = false;
-  if (valid) load_gaussian(g, i, P.alpha_min, G, bad);
-  float gm[3] = {0.f, 0.f, 0.f}, gls[3] = {0.f, 0.f, 0.f}, gq[4] = {0.f, 0.f, 0.f, 0.f}, glg = 0.f;
-  float gsh[K][3];
-#pragma unroll
-  for (int k = 0; k < K; ++k) gsh[k][0] = gsh[k][1] = gsh[k][2] = 0.f;
-  uint32_t s_kap = 0, s_om = 0, s_vc = 0;
-  double s_gam = 0.0;
-  float s_gn = 0.f;
-  int s_mr = 0;
-  bool any = false;
   const float h = 0.5f * 1.4426950408889634f;
   const float LN2 = 0.69314718055994531f;
-  for (int v = 0; v < V; ++v) {
-    const uint32_t tiles = valid ? vis[(int64_t)v * n + i] : 0u;
-    const uint32_t flag = tiles > 0 ? 1u : 0u;
-    uint32_t ea, eb, ta, tb;
-    block_scan2(flag, tiles, scan_sh, ea, eb, ta, tb);
-    float pose[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    if (flag) {
-      const int64_t e = ((int64_t)v * nb + blockIdx.x) * 2;
-      const uint64_t s = (uint64_t)blk_base[e] + ea;
-      const uint64_t po = (uint64_t)blk_base[e + 1] + eb;
-      const CamDev& c = cams[v];
-      ProjCore p;
-      if (s < slot_cap && po + tiles <= pair_cap && G.ok &&
-          project_core(c, G.mu, G.cw, G.o, P.near_z, P.eps2d, P.rect_margin, P.log_alpha_min, P.tile_w, P.tile_h,
-                       P.tiles_x, P.tiles_y, p)) {
-        // segmented sum of the record-space gradients of this record's pairs
-        float r[10] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        uint32_t om = 0, kap = 0;
-        for (uint32_t k = 0; k < tiles; ++k) {
-          const float4 a = pair_grad[(po + k) * 3], b = pair_grad[(po + k) * 3 + 1],
-                       cc = pair_grad[(po + k) * 3 + 2];
-          r[0] += a.x; r[1] += a.y; r[2] += a.z; r[3] += a.w;
-          r[4] += b.x; r[5] += b.y; r[6] += b.z; r[7] += b.w;
-          r[8] += cc.x; r[9] += cc.y;
-          om += __float_as_uint(cc.z);
-          kap += __float_as_uint(cc.w);
-        }
-        any = true;
-        // statistics of this view
-        s_om += om;
-        s_kap += kap;
-        if (view_loss) s_gam += (double)view_loss[v] * (double)om;
-        s_gn += sqrtf(r[0] * r[0] + r[1] * r[1]);
-        s_vc += 1u;
-        s_mr = max(s_mr, max(p.rx, p.ry));
+  {
+    float out[KGS_SLOT_WORDS];
+#pragma unroll
+    for (int k = 0; k < KGS_SLOT_WORDS; ++k) out[k] = 0.f;
+    const int64_t i = slot_gid[s];
+    const uint32_t v = slot_view[s];
+    const uint32_t tiles = slot_ntiles[s];
+    GaussLocal G;
+    bool bad = false;
+    load_gaussian(g, i, P.alpha_min, G, bad);
+    const CamDev& c = cams[v];
+    ProjCore p;
+    if (tiles > 0 && G.ok &&
+        project_core(c, G.mu, G.cw, G.o, P.near_z, P.far_z, P.eps2d, P.rect_margin, P.log_alpha_min, P.tile_w,
+                     P.tile_h, P.tiles_x, P.tiles_y, p)) {
+      float gm[3] = {0.f, 0.f, 0.f}, gls[3] = {0.f, 0.f, 0.f}, gq[4] = {0.f, 0.f, 0.f, 0.f};
+      float pose[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      out[17] = __uint_as_float(om);
+      out[18] = __uint_as_float(kap);
+      out[19] = sqrtf(r[0] * r[0] + r[1] * r[1]);
+      out[20] = __int_as_float(max(p.rx, p.ry));
+        float Yb_out[16];
         // record space -> conic (a, b, c) and opacity
         const float idet = 1.0f / p.det;
         const float ca = p.S11 * idet, cb = -p.S01 * idet, cc = p.S00 * idet;
         const float ga = -h * r[2], gb = -2.0f * h * r[3], gc = -h * r[4];
-        glg += r[5] * (1.0f - G.o) / LN2;
+        out[10] = r[5] * (1.0f - G.o) / LN2;
         // dL/dSigma2D = -M G_M M, M the conic matrix, G_M = [[ga, gb/2], [gb/2, gc]]
         const float X00 = ga * ca + 0.5f * gb * cb, X01 = ga * cb + 0.5f * gb * cc;
         const float X10 = 0.5f * gb * ca + gc * cb, X11 = 0.5f * gb * cb + gc * cc;
@@ -183,40 +179,30 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_project_bwd(
           gq[2] += (gy - qy * dot) * iq;
           gq[3] += (gz - qz * dot) * iq;
         }
-        // colour: SH coefficients and the view direction
+        // colour: SH basis at the view direction, masked colour gradient, and
+        // the direction gradient sum_k w_k grad Y_k with w_k = sum_ch g_ch c_k,ch
         {
           float dv[3] = {G.mu[0] - c.ctr[0], G.mu[1] - c.ctr[1], G.mu[2] - c.ctr[2]};
           const float dist = sqrtf(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]), idist = 1.0f / dist;
           const float dx = dv[0] * idist, dy = dv[1] * idist, dz = dv[2] * idist;
-          float Yb[16];
-          sh_basis(DEG, dx, dy, dz, Yb);
-          float gdir[3] = {0.f, 0.f, 0.f};
-          float dYb[16][3];
-          if (DEG > 0) sh_basis_grad(DEG, dx, dy, dz, dYb);
+          sh_basis(DEG, dx, dy, dz, Yb_out);
+          float gcm[3];
 #pragma unroll
           for (int ch = 0; ch < 3; ++ch) {
             float raw = 0.5f;
-            float coef[K];
 #pragma unroll
-            for (int k = 0; k < K; ++k) {
-              coef[k] = g.sh[((int64_t)k * 3 + ch) * n + i];
-              raw += Yb[k] * coef[k];
-            }
-            if (raw > 0.f) {
-              const float gc_ = r[6 + ch];
-#pragma unroll
-              for (int k = 0; k < K; ++k) gsh[k][ch] += Yb[k] * gc_;
-              if (DEG > 0) {
-#pragma unroll
-                for (int k = 1; k < K; ++k) {
-                  gdir[0] += gc_ * coef[k] * dYb[k][0];
-                  gdir[1] += gc_ * coef[k] * dYb[k][1];
-                  gdir[2] += gc_ * coef[k] * dYb[k][2];
-                }
-              }
-            }
+            for (int k = 0; k < K; ++k) raw += Yb_out[k] * g.sh[((int64_t)k * 3 + ch) * n + i];
+            gcm[ch] = raw > 0.f ? r[6 + ch] : 0.f;
+            out[21 + ch] = gcm[ch];
           }
           if (DEG > 0) {
+            float wk[16];
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+              wk[k] = gcm[0] * g.sh[((int64_t)k * 3) * n + i] + gcm[1] * g.sh[((int64_t)k * 3 + 1) * n + i] +
+                      gcm[2] * g.sh[((int64_t)k * 3 + 2) * n + i];
+            float gdir[3];
+            sh_dir_grad(DEG, dx, dy, dz, wk, gdir);
             const float dd = gdir[0] * dx + gdir[1] * dy + gdir[2] * dz;
             const float gv0 = (gdir[0] - dx * dd) * idist, gv1 = (gdir[1] - dy * dd) * idist,
                         gv2 = (gdir[2] - dz * dd) * idist;
@@ -228,32 +214,152 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_project_bwd(
             for (int k = 0; k < 3; ++k) pose[k] += c.R[k * 3] * gv0 + c.R[k * 3 + 1] * gv1 + c.R[k * 3 + 2] * gv2;
           }
         }
-      }
-    }
-    // block reduction of the pose gradient of this view
-    if (pose_partial) {
 #pragma unroll
-      for (int k = 0; k < 6; ++k) {
-        const float s_ = wave_sum(pose[k]);
-        if (l == 0) pose_sh[w][k] = s_;
-      }
-      __syncthreads();
-      if (threadIdx.x < 6) {
-        const int k = threadIdx.x;
-        pose_partial[((int64_t)v * nb + blockIdx.x) * 6 + k] =
-            (pose_sh[0][k] + pose_sh[1][k]) + (pose_sh[2][k] + pose_sh[3][k]);
-      }
-      __syncthreads();
+      for (int k = 0; k < K; ++k) out[24 + k] = Yb_out[k];
+      out[0] = gm[0]; out[1] = gm[1]; out[2] = gm[2];
+      out[3] = gls[0]; out[4] = gls[1]; out[5] = gls[2];
+      out[6] = gq[0]; out[7] = gq[1]; out[8] = gq[2]; out[9] = gq[3];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) out[11 + k] = pose[k];
     }
+    float4* o4 = slot_bwd + (size_t)s * (KGS_SLOT_WORDS / 4);
+#pragma unroll
+    for (int k = 0; k < KGS_SLOT_WORDS / 4; ++k)
+      o4[k] = make_float4(out[4 * k], out[4 * k + 1], out[4 * k + 2], out[4 * k + 3]);
   }
-  if (!valid || !any) return;
+}
+
+// Fused projection backward of one block of 256 Gaussians.  Phase 1: the
+// records of all (view, Gaussian) slots of the block -- they are contiguous
+// per view and their count per view is the counting pass's block count -- are
+// spread over the 256 threads; each writes its slot's backward record (the
+// Gaussian's parameters are read by index from the block's small range, so
+// they stay in cache).  Phase 2: each thread sums its Gaussian's records in
+// view order and adds into the gradients and statistics.
+template <int DEG>
+__global__ __launch_bounds__(KGS_BLOCK) void k_proj_bwd(
+    kgs_gaussians g, const CamDev* __restrict__ cams, int V, BwdParams P, const uint32_t* __restrict__ vis,
+    const uint32_t* __restrict__ blk_cnt, const uint32_t* __restrict__ blk_base, int64_t nb, uint64_t slot_cap,
+    const uint32_t* __restrict__ counters, const uint32_t* __restrict__ slot_gid,
+    const uint32_t* __restrict__ slot_view, const uint32_t* __restrict__ slot_pairoff,
+    const uint32_t* __restrict__ slot_ntiles, const float4* __restrict__ pair_grad, float4* __restrict__ slot_bwd,
+    const float* __restrict__ view_loss, kgs_grads gr, kgs_view_stats st) {
+  constexpr int K = (DEG + 1) * (DEG + 1);
+  __shared__ uint32_t scan_sh[16];
+  __shared__ uint32_t s_start[KGS_MAX_VIEWS + 1], s_base[KGS_MAX_VIEWS];
+  const int tid = threadIdx.x;
+  const uint32_t n_slots = counters[0];
+  // phase 1
+  if (tid < V) s_base[tid] = blk_base[((int64_t)tid * nb + blockIdx.x) * 2];
+  if (tid == 0) {
+    uint32_t a = 0;
+    for (int v = 0; v < V; ++v) {
+      s_start[v] = a;
+      a += blk_cnt[((int64_t)v * nb + blockIdx.x) * 2];
+    }
+    s_start[V] = a;
+  }
+  __syncthreads();
+  const uint32_t total = s_start[V];
+  const int w = tid >> 6, l = tid & 63;
+  for (uint32_t base = (uint32_t)w * 64; base < total; base += KGS_BLOCK) {
+    const uint32_t j = base + l;
+    uint32_t s = 0xffffffffu;
+    if (j < total) {
+      int v = 0;
+      while (v + 1 < V && s_start[v + 1] <= j) ++v;
+      s = s_base[v] + (j - s_start[v]);
+      if (s >= n_slots || s >= slot_cap) s = 0xffffffffu;
+    }
+    const bool act = s != 0xffffffffu;
+    const uint32_t tiles = act ? slot_ntiles[s] : 0u, po = act ? slot_pairoff[s] : 0u;
+    float r[10] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    uint32_t om = 0, kap = 0;
+    // a slot of up to 16 pairs is summed by its own lane; a larger one by the
+    // whole wave (lane-strided partial sums, then a fixed butterfly), so no
+    // lane walks a long list alone and the order never depends on scheduling
+    const bool big = tiles > 16u;
+    if (!big) pair_sum_serial(pair_grad, po, tiles, r, om, kap);
+    uint64_t bigs = ballot64(big);
+    while (bigs) {
+      const int b = __builtin_ctzll(bigs);
+      bigs &= bigs - 1ull;
+      const uint32_t bt = (uint32_t)__shfl((int)tiles, b, 64), bp = (uint32_t)__shfl((int)po, b, 64);
+      float q[10] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      uint32_t qo = 0, qk = 0;
+      for (uint32_t k = (uint32_t)l; k < bt; k += 64) pair_sum_serial(pair_grad, bp + k, 1u, q, qo, qk);
+#pragma unroll
+      for (int m = 0; m < 10; ++m) q[m] = wave_sum(q[m]);
+      qo = wave_sum(qo);
+      qk = wave_sum(qk);
+      if (l == b) {
+#pragma unroll
+        for (int m = 0; m < 10; ++m) r[m] = q[m];
+        om = qo;
+        kap = qk;
+      }
+    }
+    if (act) slot_record<DEG>(s, g, cams, P, slot_gid, slot_view, slot_ntiles, r, om, kap, slot_bwd);
+  }
+  __syncthreads();
+  // phase 2
+  const int64_t i = (int64_t)blockIdx.x * KGS_BLOCK + tid;
+  const int64_t n = g.n;
+  const bool valid = i < n;
+  float acc[11];
+#pragma unroll
+  for (int k = 0; k < 11; ++k) acc[k] = 0.f;
+  float gsh[K][3];
+#pragma unroll
+  for (int k = 0; k < K; ++k) gsh[k][0] = gsh[k][1] = gsh[k][2] = 0.f;
+  uint32_t s_kap = 0, s_om = 0, s_vc = 0;
+  double s_gam = 0.0;
+  float s_gn = 0.f;
+  int s_mr = 0;
+  for (int v = 0; v < V; ++v) {
+    const uint32_t tiles = valid ? vis[(int64_t)v * n + i] : 0u;
+    const uint32_t flag = tiles > 0 ? 1u : 0u;
+    uint32_t ea, eb, ta, tb;
+    block_scan2(flag, 0u, scan_sh, ea, eb, ta, tb);
+    if (!flag) continue;
+    const uint64_t s = (uint64_t)blk_base[((int64_t)v * nb + blockIdx.x) * 2] + ea;
+    if (s >= slot_cap || s >= n_slots) continue;
+    const float4* r4 = slot_bwd + s * (KGS_SLOT_WORDS / 4);
+    float r[KGS_SLOT_WORDS];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const float4 q = r4[k];
+      r[4 * k] = q.x; r[4 * k + 1] = q.y; r[4 * k + 2] = q.z; r[4 * k + 3] = q.w;
+    }
+#pragma unroll
+    for (int k = 6; k < (24 + K + 3) / 4; ++k) {
+      const float4 q = r4[k];
+      r[4 * k] = q.x; r[4 * k + 1] = q.y; r[4 * k + 2] = q.z; r[4 * k + 3] = q.w;
+    }
+#pragma unroll
+    for (int k = 0; k < 11; ++k) acc[k] += r[k];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      gsh[k][0] += r[24 + k] * r[21];
+      gsh[k][1] += r[24 + k] * r[22];
+      gsh[k][2] += r[24 + k] * r[23];
+    }
+    const uint32_t om = __float_as_uint(r[17]);
+    s_om += om;
+    s_kap += __float_as_uint(r[18]);
+    if (view_loss) s_gam += (double)view_loss[v] * (double)om;
+    s_gn += r[19];
+    s_vc += 1u;
+    s_mr = max(s_mr, __float_as_int(r[20]));
+  }
+  if (!valid || s_vc == 0) return;
   if (gr.means)
-    for (int k = 0; k < 3; ++k) gr.means[k * n + i] += gm[k];
+    for (int k = 0; k < 3; ++k) gr.means[k * n + i] += acc[k];
   if (gr.log_scales)
-    for (int k = 0; k < 3; ++k) gr.log_scales[k * n + i] += gls[k];
+    for (int k = 0; k < 3; ++k) gr.log_scales[k * n + i] += acc[3 + k];
   if (gr.quats)
-    for (int k = 0; k < 4; ++k) gr.quats[k * n + i] += gq[k];
-  if (gr.opacity_logits) gr.opacity_logits[i] += glg;
+    for (int k = 0; k < 4; ++k) gr.quats[k * n + i] += acc[6 + k];
+  if (gr.opacity_logits) gr.opacity_logits[i] += acc[10];
   if (gr.sh)
 #pragma unroll
     for (int k = 0; k < K; ++k)
@@ -266,30 +372,49 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_project_bwd(
   if (st.max_radius) st.max_radius[i] = max(st.max_radius[i], s_mr);
 }
 
-// d/dxi = J_l(xi)^T (dL/drho, dL/dphi), summed over the blocks in fixed order.
-__global__ void k_pose_final(int V, int64_t nb, const float* __restrict__ partial, const CamDev* __restrict__ cams,
-                             float* __restrict__ grad) {
-  const int v = blockIdx.x;
-  __shared__ double sh[6][64];
-  const int tid = threadIdx.x;
+// Pose contributions of view v's slots (blockIdx.y = v), in KGS_POSE_BLOCKS
+// contiguous pieces, FP64, fixed reduction tree.
+__global__ __launch_bounds__(256) void k_pose_reduce(const uint32_t* __restrict__ counters,
+                                                     const uint32_t* __restrict__ blk_base, int64_t nb, int V,
+                                                     const float4* __restrict__ slot_bwd,
+                                                     double* __restrict__ partial) {
+  __shared__ double sh[4][6];
+  const int v = blockIdx.y, b = blockIdx.x, tid = threadIdx.x;
+  const uint32_t n_slots = counters[0];
+  uint32_t lo = blk_base[((int64_t)v * nb) * 2];
+  uint32_t hi = (v + 1 < V) ? blk_base[((int64_t)(v + 1) * nb) * 2] : n_slots;
+  lo = min(lo, n_slots);
+  hi = min(max(hi, lo), n_slots);
+  const uint32_t per = (hi - lo + KGS_POSE_BLOCKS - 1) / KGS_POSE_BLOCKS;
+  const uint32_t a = lo + b * per, e = min(hi, a + per);
   double acc[6] = {0, 0, 0, 0, 0, 0};
-  for (int64_t b = tid; b < nb; b += 64)
-    for (int k = 0; k < 6; ++k) acc[k] += (double)partial[((int64_t)v * nb + b) * 6 + k];
-  for (int k = 0; k < 6; ++k) sh[k][tid] = acc[k];
+  for (uint32_t s = a + tid; s < e; s += 256) {
+    const float4* r4 = slot_bwd + (size_t)s * (KGS_SLOT_WORDS / 4);
+    const float4 q2 = r4[2], q3 = r4[3], q4 = r4[4];
+    acc[0] += q2.w; acc[1] += q3.x; acc[2] += q3.y; acc[3] += q3.z; acc[4] += q3.w; acc[5] += q4.x;
+  }
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const double t = wave_sum(acc[k]);
+    if ((tid & 63) == 0) sh[tid >> 6][k] = t;
+  }
   __syncthreads();
-  if (tid == 0) {
-    double gd[6];
-    for (int k = 0; k < 6; ++k) {
-      double s = 0.0;
-      for (int t = 0; t < 64; ++t) s += sh[k][t];
-      gd[k] = s;
-    }
-    const CamDev& c = cams[v];
-    for (int j = 0; j < 6; ++j) {
-      double s = 0.0;
-      for (int k = 0; k < 6; ++k) s += c.Jl[k * 6 + j] * gd[k];
-      grad[v * 6 + j] += (float)s;
-    }
+  if (tid < 6) partial[((size_t)v * KGS_POSE_BLOCKS + b) * 6 + tid] = (sh[0][tid] + sh[1][tid]) + (sh[2][tid] + sh[3][tid]);
+}
+
+// d/dxi = J_l(xi)^T (dL/drho, dL/dphi), summed over the pieces in fixed order.
+__global__ void k_pose_final(int V, const double* __restrict__ partial, const CamDev* __restrict__ cams,
+                             float* __restrict__ grad) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= V) return;
+  double gd[6] = {0, 0, 0, 0, 0, 0};
+  for (int b = 0; b < KGS_POSE_BLOCKS; ++b)
+    for (int k = 0; k < 6; ++k) gd[k] += partial[((size_t)v * KGS_POSE_BLOCKS + b) * 6 + k];
+  const CamDev& c = cams[v];
+  for (int j = 0; j < 6; ++j) {
+    double s = 0.0;
+    for (int k = 0; k < 6; ++k) s += c.Jl[k * 6 + j] * gd[k];
+    grad[v * 6 + j] += (float)s;
   }
 }
 
@@ -303,6 +428,7 @@ kgs_status kgs_launch_project_bwd(kgs_ctx* ctx, const kgs_gaussians* g, const kg
   P.alpha_min = cfg.alpha_min;
   P.log_alpha_min = logf(cfg.alpha_min);
   P.near_z = cfg.near_z;
+  P.far_z = cfg.far_z;
   P.eps2d = cfg.eps2d;
   P.rect_margin = cfg.rect_margin;
   P.tile_w = cfg.tile_w;
@@ -312,13 +438,14 @@ kgs_status kgs_launch_project_bwd(kgs_ctx* ctx, const kgs_gaussians* g, const kg
   const int64_t nb = (g->n + KGS_BLOCK - 1) / KGS_BLOCK;
   kgs_grads G = *gr;
   kgs_view_stats S = stats ? *stats : kgs_view_stats{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-  float* pp = G.pose_xi ? ctx->pose_partial : nullptr;
+  const uint64_t cap = (uint64_t)cfg.slot_capacity;
   if (nb > 0) {
-#define KGS_PB(D)                                                                                               \
-  hipLaunchKernelGGL(k_project_bwd<D>, dim3((unsigned)nb), dim3(KGS_BLOCK), 0, st, *g, (const CamDev*)ctx->cams, \
-                     V, P, (const uint32_t*)ctx->vis, (const uint32_t*)ctx->blk_base, nb,                        \
-                     (uint64_t)cfg.slot_capacity, (uint64_t)cfg.pair_capacity, (const float4*)ctx->pair_grad,    \
-                     view_loss, G, S, pp)
+#define KGS_PB(D)                                                                                                  \
+  hipLaunchKernelGGL(k_proj_bwd<D>, dim3((unsigned)nb), dim3(KGS_BLOCK), 0, st, *g, (const CamDev*)ctx->cams, V, P, \
+                     (const uint32_t*)ctx->vis, (const uint32_t*)ctx->blk_cnt, (const uint32_t*)ctx->blk_base, nb,  \
+                     cap, (const uint32_t*)ctx->counters, (const uint32_t*)ctx->slot_gid,                           \
+                     (const uint32_t*)ctx->slot_view, (const uint32_t*)ctx->slot_pairoff,                           \
+                     (const uint32_t*)ctx->slot_ntiles, (const float4*)ctx->pair_grad, ctx->slot_bwd, view_loss, G, S)
     switch (g->sh_degree) {
       case 0: KGS_PB(0); break;
       case 1: KGS_PB(1); break;
@@ -326,9 +453,12 @@ kgs_status kgs_launch_project_bwd(kgs_ctx* ctx, const kgs_gaussians* g, const kg
       default: KGS_PB(3); break;
     }
 #undef KGS_PB
-    if (G.pose_xi)
-      hipLaunchKernelGGL(k_pose_final, dim3(V), dim3(64), 0, st, V, nb, (const float*)ctx->pose_partial,
+    if (G.pose_xi) {
+      hipLaunchKernelGGL(k_pose_reduce, dim3(KGS_POSE_BLOCKS, V), dim3(256), 0, st, (const uint32_t*)ctx->counters,
+                         (const uint32_t*)ctx->blk_base, nb, V, (const float4*)ctx->slot_bwd, ctx->pose_partial);
+      hipLaunchKernelGGL(k_pose_final, dim3(1), dim3(64), 0, st, V, (const double*)ctx->pose_partial,
                          (const CamDev*)ctx->cams, G.pose_xi);
+    }
   }
   return kgs_check_launch();
 }

@@ -28,7 +28,8 @@ template <int B>
 __device__ __forceinline__ void stage_batch(uint32_t base, uint32_t end, const uint32_t* __restrict__ sorted_slot,
                                             const float4* __restrict__ slot_rec, int tile_x0, int tile_y0,
                                             int tile_w, float4* s_r0, float4* s_r1, float4* s_r2,
-                                            uint8_t* s_mask, uint8_t (*s_list)[B], uint32_t (*s_cnt)[4]) {
+                                            uint32_t* s_slot, uint8_t* s_mask, uint8_t (*s_list)[B],
+                                            uint32_t (*s_cnt)[4]) {
   const int tid = threadIdx.x, w = tid >> 6;
   uint32_t m = 0;
   if (tid < B) {
@@ -36,6 +37,7 @@ __device__ __forceinline__ void stage_batch(uint32_t base, uint32_t end, const u
     if (k < end) {
       const uint32_t s = sorted_slot[k];
       const float4 r0 = slot_rec[(size_t)s * 3], r1 = slot_rec[(size_t)s * 3 + 1], r2 = slot_rec[(size_t)s * 3 + 2];
+      s_slot[tid] = s;
       s_r0[tid] = r0;
       s_r1[tid] = r1;
       s_r2[tid] = r2;
@@ -79,6 +81,7 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_render_fwd(RenderParams P, const 
                                                           float* __restrict__ color, float* __restrict__ depth,
                                                           float* __restrict__ tfinal, int32_t* __restrict__ last) {
   __shared__ float4 s_r0[B], s_r1[B], s_r2[B];
+  __shared__ uint32_t s_slot[B];
   __shared__ uint8_t s_list[4][B];
   __shared__ uint8_t s_mask[B];
   __shared__ uint32_t s_cnt[4][4];
@@ -99,8 +102,8 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_render_fwd(RenderParams P, const 
   bool done = !inside;
   for (uint32_t base = start; base < end; base += B) {
     if (__syncthreads_count(!done) == 0) break;
-    stage_batch<B>(base, end, sorted_slot, slot_rec, tile_x0, tile_y0, P.tile_w, s_r0, s_r1, s_r2, s_mask, s_list,
-                   s_cnt);
+    stage_batch<B>(base, end, sorted_slot, slot_rec, tile_x0, tile_y0, P.tile_w, s_r0, s_r1, s_r2, s_slot, s_mask,
+                   s_list, s_cnt);
     const uint32_t len = s_cnt[0][w] + s_cnt[1][w] + s_cnt[2][w] + s_cnt[3][w];
     const int rel0 = (int)(base - start) + 1;
     for (uint32_t j = 0; j < len; ++j) {
@@ -213,14 +216,28 @@ __device__ __forceinline__ void wave_reduce10(float (&x)[10], int lane, int& idx
   idx = (u5 ? 5 : 0) + rel;
 }
 
+// Emission position of the pair (slot, tile (tx, ty)): the slot's first pair
+// plus the tile's row-major rank in the slot's tile rectangle, which is
+// recovered from the record's packed pixel bounds.
+__device__ __forceinline__ uint32_t pair_position(uint32_t first, float xb_f, float yb_f, int tx, int ty,
+                                                  const RenderParams& P) {
+  const uint32_t xb = __float_as_uint(xb_f), yb = __float_as_uint(yb_f);
+  const int xlo = (int)(int16_t)(xb & 0xffffu), xhi = (int)(int16_t)(xb >> 16);
+  const int ylo = (int)(int16_t)(yb & 0xffffu);
+  const int x0 = max(floordiv_i(xlo, P.tile_w), 0), x1 = min(floordiv_i(xhi, P.tile_w) + 1, P.tiles_x);
+  const int y0 = max(floordiv_i(ylo, P.tile_h), 0);
+  return first + (uint32_t)((ty - y0) * (x1 - x0) + (tx - x0));
+}
+
 template <int B>
 __global__ __launch_bounds__(KGS_BLOCK) void k_render_bwd(
     RenderParams P, const uint2* __restrict__ ranges, const uint32_t* __restrict__ sorted_slot,
-    const uint32_t* __restrict__ sorted_val, const float4* __restrict__ slot_rec, const float* __restrict__ color,
+    const uint32_t* __restrict__ slot_pairoff, const float4* __restrict__ slot_rec, const float* __restrict__ color,
     const float* __restrict__ depth, const float* __restrict__ tfinal, const int32_t* __restrict__ last,
     const float* __restrict__ dl_dcolor, const float* __restrict__ dl_ddepth, const float* __restrict__ target,
     float tau_err, float4* __restrict__ pair_grad) {
   __shared__ float4 s_r0[B], s_r1[B], s_r2[B];
+  __shared__ uint32_t s_slot[B];
   __shared__ uint8_t s_list[4][B];
   __shared__ uint8_t s_mask[B];
   __shared__ uint32_t s_cnt[4][4];
@@ -273,8 +290,8 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_render_bwd(
   uint32_t base = start;
   for (; base < pend; base += B) {
     __syncthreads();
-    stage_batch<B>(base, end, sorted_slot, slot_rec, tile_x0, tile_y0, P.tile_w, s_r0, s_r1, s_r2, s_mask, s_list,
-                   s_cnt);
+    stage_batch<B>(base, end, sorted_slot, slot_rec, tile_x0, tile_y0, P.tile_w, s_r0, s_r1, s_r2, s_slot, s_mask,
+                   s_list, s_cnt);
     const uint32_t len = s_cnt[0][w] + s_cnt[1][w] + s_cnt[2][w] + s_cnt[3][w];
     const int rel0 = (int)(base - start);
     for (uint32_t j = 0; j < len; ++j) {
@@ -344,7 +361,7 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_render_bwd(
             for (int q = 0; q < 12; ++q) o[q] += s_part[ww][tid][q];
           }
         }
-        const size_t p = (size_t)sorted_val[k] * 3;
+        const size_t p = (size_t)pair_position(slot_pairoff[s_slot[tid]], s_r1[tid].w, s_r2[tid].w, tx, ty, P) * 3;
         pair_grad[p] = make_float4(o[0], o[1], o[2], o[3]);
         pair_grad[p + 1] = make_float4(o[4], o[5], o[6], o[7]);
         pair_grad[p + 2] = make_float4(o[8], o[9], __uint_as_float((uint32_t)o[10]), __uint_as_float((uint32_t)o[11]));
@@ -353,7 +370,9 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_render_bwd(
   }
   // pairs behind the tile's last blended Gaussian contribute nothing
   for (uint32_t k = base + tid; k < end; k += KGS_BLOCK) {
-    const size_t p = (size_t)sorted_val[k] * 3;
+    const uint32_t s = sorted_slot[k];
+    const size_t p = (size_t)pair_position(slot_pairoff[s], slot_rec[(size_t)s * 3 + 1].w, slot_rec[(size_t)s * 3 + 2].w,
+                                           tx, ty, P) * 3;
     const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
     pair_grad[p] = z;
     pair_grad[p + 1] = z;
@@ -414,10 +433,10 @@ kgs_status kgs_launch_render_bwd(kgs_ctx* ctx, const kgs_image* fwd, const float
                                  const float* target, float tau_err, hipStream_t st) {
   const RenderParams P = render_params(ctx);
   const unsigned grid = (unsigned)(ctx->last_views * ctx->n_tiles);
-  const uint32_t* sval = ctx->vals[ctx->sorted_buf];
 #define KGS_BWD(BB)                                                                                              \
   hipLaunchKernelGGL(k_render_bwd<BB>, dim3(grid), dim3(KGS_BLOCK), 0, st, P, (const uint2*)ctx->ranges,          \
-                     (const uint32_t*)ctx->sorted_slot, sval, (const float4*)ctx->slot_rec,                       \
+                     (const uint32_t*)ctx->sorted_slot, (const uint32_t*)ctx->slot_pairoff,                      \
+                     (const float4*)ctx->slot_rec,                                                                \
                      (const float*)fwd->color, (const float*)fwd->depth, (const float*)fwd->t_final,              \
                      (const int32_t*)fwd->last, dl_dcolor, dl_ddepth, target, tau_err, ctx->pair_grad)
   switch (ctx->cfg.batch) {

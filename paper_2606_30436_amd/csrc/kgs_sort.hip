@@ -1,91 +1,88 @@
 // Tile binning and depth sort.
 //
-// Pairs are emitted per slot at the slot's pair offset (so the pairs of one
-// slot are contiguous in emission order), then sorted by a stable LSD radix
-// sort over only the used key bits (32 depth bits + ceil(log2(views * tiles))
-// tile bits), 8-bit digits, reduce-then-scan with a fixed grid: per pass a
-// block histogram, a per-digit scan, and a stable in-block scatter whose ranks
-// come from wave ballots.  Counts are read on the device, so the whole
-// sequence can be captured in a graph.
+// The order the compositing needs is (view, tile, depth, Gaussian index).  It
+// is built in two small sorts instead of one wide one:
+//   1. the projected records (slots, already in (view, Gaussian) order) are
+//      sorted by (view, fp32 depth) -- 38-bit keys over S records;
+//   2. pairs are emitted in that depth order (a scan of the records' tile
+//      counts gives each record's first pair), one per tile of the record's
+//      rectangle, keyed by the global tile index only;
+//   3. the pairs are sorted stably by tile -- 14 bits at 1242x375 x 8 views,
+//      two 8-bit passes over 4-byte keys and values.
+// Stability makes the result identical to one sort by the full key.
+//
+// The radix sort is LSD, reduce-then-scan, with one partition per wave: each
+// wave histograms and scatters its contiguous range on its own (ranks from
+// ballots, running digit offsets in the wave's own LDS row), so the scatter
+// needs no block barriers.  Counts stay on the device, so the sequence can be
+// captured in a graph.
+#include <algorithm>
+
 #include "kgs_internal.h"
 
-__global__ __launch_bounds__(KGS_BLOCK) void k_emit_pairs(const uint32_t* __restrict__ counters,
-                                                          const float4* __restrict__ slot_rec,
-                                                          const uint32_t* __restrict__ slot_view,
-                                                          const int4* __restrict__ slot_pix,
-                                                          const uint32_t* __restrict__ slot_pairoff,
-                                                          const uint32_t* __restrict__ slot_ntiles, int tile_w,
-                                                          int tile_h, int tiles_x, int tiles_y,
-                                                          uint64_t pair_cap, uint64_t* __restrict__ keys,
-                                                          uint32_t* __restrict__ vals,
-                                                          uint32_t* __restrict__ pair_slot) {
-  const uint32_t n = counters[0];
-  const uint32_t tiles_per_view = (uint32_t)(tiles_x * tiles_y);
-  for (uint32_t s = blockIdx.x * KGS_BLOCK + threadIdx.x; s < n; s += gridDim.x * KGS_BLOCK) {
-    const int4 pix = slot_pix[s];
-    const uint32_t depth_bits = __float_as_uint(slot_rec[(size_t)s * 3 + 1].z);
-    const uint32_t v = slot_view[s];
-    const uint32_t off = slot_pairoff[s];
-    const uint32_t cnt = slot_ntiles[s];
-    if ((uint64_t)off + cnt > pair_cap) continue;
-    const int x0 = max(floordiv_i(pix.x - pix.z, tile_w), 0), x1 = min(floordiv_i(pix.x + pix.z, tile_w) + 1, tiles_x);
-    const int y0 = max(floordiv_i(pix.y - pix.w, tile_h), 0), y1 = min(floordiv_i(pix.y + pix.w, tile_h) + 1, tiles_y);
-    uint32_t k = 0;
-    for (int ty = y0; ty < y1 && k < cnt; ++ty)
-      for (int tx = x0; tx < x1 && k < cnt; ++tx, ++k) {
-        const uint64_t tile = (uint64_t)v * tiles_per_view + (uint64_t)(ty * tiles_x + tx);
-        keys[off + k] = (tile << 32) | depth_bits;
-        vals[off + k] = off + k;
-        pair_slot[off + k] = s;
-      }
-    // a re-projection that disagrees with the count leaves padding pairs
-    for (; k < cnt; ++k) {
-      keys[off + k] = ~0ull;
-      vals[off + k] = off + k;
-      pair_slot[off + k] = s;
-    }
-  }
-}
+#define RS_WAVES 4
+#define RS_PARTS (KGS_SORT_BLOCKS * RS_WAVES)
 
-__device__ __forceinline__ void sort_range(uint32_t n, int b, uint32_t& lo, uint32_t& hi) {
-  const uint32_t per = ((n + KGS_SORT_BLOCKS - 1) / KGS_SORT_BLOCKS + 255u) & ~255u;
-  lo = min(n, (uint32_t)b * per);
+__device__ __forceinline__ void part_range(uint32_t n, uint32_t part, uint32_t& lo, uint32_t& hi) {
+  const uint32_t per = ((n + RS_PARTS - 1) / RS_PARTS + 63u) & ~63u;
+  lo = min(n, part * per);
   hi = min(n, lo + per);
 }
 
-__global__ void k_radix_zero(uint32_t* __restrict__ total) {
-  total[blockIdx.x * 256 + threadIdx.x] = 0u;
-}
+__global__ void k_radix_zero(uint32_t* __restrict__ total) { total[blockIdx.x * 256 + threadIdx.x] = 0u; }
 
-__global__ __launch_bounds__(256) void k_radix_hist(const uint32_t* __restrict__ counters,
-                                                    const uint64_t* __restrict__ keys, int shift,
-                                                    uint32_t* __restrict__ hist, uint32_t* __restrict__ total) {
-  __shared__ uint32_t h[256];
-  h[threadIdx.x] = 0;
+// per-wave digit histograms: hist[d][part]; each lane keeps RS_KPT loads in flight
+#define RS_KPT 8
+template <typename K>
+__global__ __launch_bounds__(256) void k_radix_hist(const uint32_t* __restrict__ count, const K* __restrict__ keys,
+                                                    int shift, uint32_t* __restrict__ hist,
+                                                    uint32_t* __restrict__ total) {
+  __shared__ uint32_t h[RS_WAVES][256];
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+#pragma unroll
+  for (int k = 0; k < RS_WAVES; ++k) h[k][tid] = 0u;
   __syncthreads();
+  const uint32_t part = blockIdx.x * RS_WAVES + w;
   uint32_t lo, hi;
-  sort_range(counters[1], blockIdx.x, lo, hi);
-  for (uint32_t i = lo + threadIdx.x; i < hi; i += 256) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+  part_range(*count, part, lo, hi);
+  for (uint32_t base = lo; base < hi; base += 64 * RS_KPT) {
+    uint32_t d[RS_KPT];
+#pragma unroll
+    for (int q = 0; q < RS_KPT; ++q) {
+      const uint32_t i = base + q * 64 + l;
+      d[q] = i < hi ? (uint32_t)(keys[i] >> shift) & 255u : 256u;
+    }
+#pragma unroll
+    for (int q = 0; q < RS_KPT; ++q)
+      if (d[q] < 256u) atomicAdd(&h[w][d[q]], 1u);
+  }
   __syncthreads();
-  const uint32_t c = h[threadIdx.x];
-  hist[threadIdx.x * KGS_SORT_BLOCKS + blockIdx.x] = c;
-  if (c) atomicAdd(&total[threadIdx.x], c);
+  uint32_t sum = 0;
+#pragma unroll
+  for (int k = 0; k < RS_WAVES; ++k) {
+    const uint32_t c = h[k][tid];
+    hist[(size_t)tid * RS_PARTS + blockIdx.x * RS_WAVES + k] = c;
+    sum += c;
+  }
+  if (sum) atomicAdd(&total[tid], sum);
 }
 
-// one block per digit: exclusive scan of its row of block counts, plus the
-// counts of all smaller digits
-__global__ __launch_bounds__(256) void k_radix_scan(uint32_t* __restrict__ hist,
-                                                    const uint32_t* __restrict__ total) {
+// one block per digit: exclusive scan of its row of partition counts, plus the
+// total of all smaller digits
+__global__ __launch_bounds__(256) void k_radix_scan(uint32_t* __restrict__ hist, const uint32_t* __restrict__ total) {
   __shared__ uint32_t sh[8];
   const int d = blockIdx.x, tid = threadIdx.x, w = tid >> 6, l = tid & 63;
   uint32_t pre = 0;
   for (int k = tid; k < d; k += 256) pre += total[k];
   pre = wave_sum(pre);
   if (l == 0) sh[4 + w] = pre;
-  constexpr int PER = KGS_SORT_BLOCKS / 256;
+  constexpr int PER = RS_PARTS / 256;
   uint32_t v[PER], s = 0;
 #pragma unroll
-  for (int k = 0; k < PER; ++k) { v[k] = hist[d * KGS_SORT_BLOCKS + tid * PER + k]; s += v[k]; }
+  for (int k = 0; k < PER; ++k) {
+    v[k] = hist[(size_t)d * RS_PARTS + tid * PER + k];
+    s += v[k];
+  }
   const uint32_t inc = wave_inclusive_scan(s);
   if (l == 63) sh[w] = inc;
   __syncthreads();
@@ -94,53 +91,203 @@ __global__ __launch_bounds__(256) void k_radix_scan(uint32_t* __restrict__ hist,
   off += inc - s;
 #pragma unroll
   for (int k = 0; k < PER; ++k) {
-    hist[d * KGS_SORT_BLOCKS + tid * PER + k] = off;
+    hist[(size_t)d * RS_PARTS + tid * PER + k] = off;
     off += v[k];
   }
 }
 
-__global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t* __restrict__ counters,
-                                                       const uint64_t* __restrict__ kin,
+// stable scatter: every wave walks its partition RS_KPT x 64 keys at a time
+// (all loads issued first, then ranked in index order)
+template <typename K>
+__global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t* __restrict__ count, const K* __restrict__ kin,
                                                        const uint32_t* __restrict__ vin, int shift,
-                                                       const uint32_t* __restrict__ offsets,
-                                                       uint64_t* __restrict__ kout, uint32_t* __restrict__ vout) {
-  __shared__ uint32_t run[256];
-  __shared__ uint32_t wc[4][256];
-  const int tid = threadIdx.x, w = tid >> 6;
-  run[tid] = offsets[tid * KGS_SORT_BLOCKS + blockIdx.x];
-  uint32_t lo, hi;
-  sort_range(counters[1], blockIdx.x, lo, hi);
-  const uint64_t lt = (1ull << (tid & 63)) - 1ull;
-  for (uint32_t base = lo; base < hi; base += 256) {
-    const uint32_t i = base + tid;
-    const bool valid = i < hi;
-    uint64_t key = 0;
-    uint32_t val = 0, d = 0;
-    if (valid) {
-      key = kin[i];
-      val = vin[i];
-      d = (uint32_t)(key >> shift) & 255u;
-    }
-    uint64_t peers = ballot64(valid);
+                                                       const uint32_t* __restrict__ offsets, K* __restrict__ kout,
+                                                       uint32_t* __restrict__ vout) {
+  __shared__ uint32_t run[RS_WAVES][256];
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  const uint32_t part = blockIdx.x * RS_WAVES + w;
 #pragma unroll
-    for (int bit = 0; bit < 8; ++bit) {
-      const uint64_t b = ballot64((d >> bit) & 1u);
-      peers &= ((d >> bit) & 1u) ? b : ~b;
+  for (int k = 0; k < 4; ++k) run[w][l + 64 * k] = offsets[(size_t)(l + 64 * k) * RS_PARTS + part];
+  __builtin_amdgcn_wave_barrier();
+  uint32_t lo, hi;
+  part_range(*count, part, lo, hi);
+  const uint64_t lt = (1ull << l) - 1ull;
+  for (uint32_t base = lo; base < hi; base += 64 * RS_KPT) {
+    K kk[RS_KPT];
+    uint32_t vv[RS_KPT];
+#pragma unroll
+    for (int q = 0; q < RS_KPT; ++q) {
+      const uint32_t i = base + q * 64 + l;
+      kk[q] = 0;
+      vv[q] = 0;
+      if (i < hi) {
+        kk[q] = kin[i];
+        vv[q] = vin[i];
+      }
     }
-    const uint32_t rank = (uint32_t)__popcll(peers & lt);
-    wc[0][tid] = 0; wc[1][tid] = 0; wc[2][tid] = 0; wc[3][tid] = 0;
-    __syncthreads();
-    if (valid && rank == 0) wc[w][d] = (uint32_t)__popcll(peers);
-    __syncthreads();
-    if (valid) {
-      uint32_t pos = run[d] + rank;
-      for (int k = 0; k < w; ++k) pos += wc[k][d];
-      kout[pos] = key;
-      vout[pos] = val;
+#pragma unroll
+    for (int q = 0; q < RS_KPT; ++q) {
+      const bool valid = base + q * 64 + l < hi;
+      const uint32_t d = valid ? (uint32_t)(kk[q] >> shift) & 255u : 0u;
+      uint64_t peers = ballot64(valid);
+#pragma unroll
+      for (int bit = 0; bit < 8; ++bit) {
+        const uint64_t b = ballot64((d >> bit) & 1u);
+        peers &= ((d >> bit) & 1u) ? b : ~b;
+      }
+      const uint32_t rank = (uint32_t)__popcll(peers & lt);
+      uint32_t pos = 0;
+      if (valid) pos = run[w][d] + rank;
+      __builtin_amdgcn_wave_barrier();
+      if (valid) {
+        kout[pos] = kk[q];
+        vout[pos] = vv[q];
+        if (rank == 0) run[w][d] += (uint32_t)__popcll(peers);
+      }
+      __builtin_amdgcn_wave_barrier();
     }
-    __syncthreads();
-    run[tid] += wc[0][tid] + wc[1][tid] + wc[2][tid] + wc[3][tid];
-    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- device-wide scan
+// Exclusive scan of f(j), j < *count, in three launches: per-block totals, a
+// scan of the totals, and the block-local scans.  f(j) = ntiles[perm[j]].
+#define SC_ITEMS 8
+#define SC_TILE (256 * SC_ITEMS)
+
+__global__ __launch_bounds__(256) void k_scan_up(const uint32_t* __restrict__ count, const uint32_t* __restrict__ perm,
+                                                 const uint32_t* __restrict__ ntiles, uint32_t* __restrict__ part) {
+  __shared__ uint32_t sh[4];
+  const uint32_t n = *count;
+  const uint32_t b0 = blockIdx.x * SC_TILE;
+  uint32_t s = 0;
+  if (b0 < n) {
+#pragma unroll
+    for (int k = 0; k < SC_ITEMS; ++k) {
+      const uint32_t j = b0 + k * 256 + threadIdx.x;
+      if (j < n) s += ntiles[perm[j]];
+    }
+  }
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+__global__ __launch_bounds__(1024) void k_scan_mid(uint32_t nparts, uint32_t* __restrict__ part) {
+  __shared__ uint32_t sh[16];
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  const uint32_t per = (nparts + 1023) / 1024;
+  const uint32_t lo = min(nparts, tid * per), hi = min(nparts, lo + per);
+  uint32_t a = 0;
+  for (uint32_t b = lo; b < hi; ++b) a += part[b];
+  const uint32_t ia = wave_inclusive_scan(a);
+  if (l == 63) sh[w] = ia;
+  __syncthreads();
+  uint32_t off = 0;
+  for (int k = 0; k < w; ++k) off += sh[k];
+  uint32_t r = off + ia - a;
+  for (uint32_t b = lo; b < hi; ++b) {
+    const uint32_t c = part[b];
+    part[b] = r;
+    r += c;
+  }
+}
+
+// ---------------------------------------------------------------- slot keys
+__global__ __launch_bounds__(KGS_BLOCK) void k_slot_keys(const uint32_t* __restrict__ counters,
+                                                         const float4* __restrict__ slot_rec,
+                                                         const uint32_t* __restrict__ slot_view,
+                                                         uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+  const uint32_t n = counters[0];
+  for (uint32_t s = blockIdx.x * KGS_BLOCK + threadIdx.x; s < n; s += gridDim.x * KGS_BLOCK) {
+    keys[s] = ((uint64_t)slot_view[s] << 32) | __float_as_uint(slot_rec[(size_t)s * 3 + 1].z);
+    vals[s] = s;
+  }
+}
+
+// ---------------------------------------------------------------- pair emission
+// One block per SC_TILE depth-sorted slots; wave w takes rounds of 64
+// consecutive slots.  In a round the lanes load their slot's rectangle, scan
+// the tile counts, and then write the round's pairs together: pair k belongs
+// to the lane whose inclusive count first exceeds k (binary search over the
+// lanes with shuffles), so writes are contiguous and balanced.  A pair's key
+// is its global tile index, its value the slot; its emission position is the
+// slot's first pair plus its row-major rank in the slot's tile rectangle.
+#define EP_ROUNDS (SC_TILE / 256)
+__global__ __launch_bounds__(256) void k_emit_pairs(const uint32_t* __restrict__ counters,
+                                                    const uint32_t* __restrict__ perm,
+                                                    const uint32_t* __restrict__ part,
+                                                    const uint32_t* __restrict__ slot_view,
+                                                    const int4* __restrict__ slot_pix,
+                                                    const uint32_t* __restrict__ slot_ntiles, int tile_w, int tile_h,
+                                                    int tiles_x, int tiles_y, uint64_t pair_cap,
+                                                    uint32_t* __restrict__ slot_pairoff, uint32_t* __restrict__ keys,
+                                                    uint32_t* __restrict__ vals) {
+  __shared__ uint32_t wtot[4];
+  const uint32_t n = counters[0];
+  const uint32_t b0 = blockIdx.x * SC_TILE;
+  if (b0 >= n) return;
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  uint32_t s[EP_ROUNDS], c[EP_ROUNDS], rt[EP_ROUNDS];
+  uint32_t wsum = 0;
+#pragma unroll
+  for (int r = 0; r < EP_ROUNDS; ++r) {
+    const uint32_t j = b0 + w * (SC_TILE / 4) + r * 64 + l;
+    s[r] = j < n ? perm[j] : 0xffffffffu;
+    c[r] = j < n ? slot_ntiles[s[r]] : 0u;
+    rt[r] = wave_sum(c[r]);
+    wsum += rt[r];
+  }
+  if (l == 0) wtot[w] = wsum;
+  __syncthreads();
+  uint32_t wbase = part[blockIdx.x];
+  for (int k = 0; k < w; ++k) wbase += wtot[k];
+  const uint32_t btotal = wtot[0] + wtot[1] + wtot[2] + wtot[3];
+  if ((uint64_t)part[blockIdx.x] + btotal > pair_cap) return;
+  const uint32_t tiles_per_view = (uint32_t)(tiles_x * tiles_y);
+  uint32_t rbase = wbase;
+#pragma unroll 1
+  for (int r = 0; r < EP_ROUNDS; ++r) {
+    const uint32_t incl = wave_inclusive_scan(c[r]);
+    const uint32_t excl = incl - c[r];
+    int x0 = 0, y0 = 0, rw = 1, ok = 0;
+    uint32_t gbase = 0;
+    if (c[r] > 0) {
+      const int4 pix = slot_pix[s[r]];
+      x0 = max(floordiv_i(pix.x - pix.z, tile_w), 0);
+      const int x1 = min(floordiv_i(pix.x + pix.z, tile_w) + 1, tiles_x);
+      y0 = max(floordiv_i(pix.y - pix.w, tile_h), 0);
+      rw = max(x1 - x0, 1);
+      ok = x1 > x0;
+      gbase = slot_view[s[r]] * tiles_per_view;
+      slot_pairoff[s[r]] = rbase + excl;
+    }
+    // wave-uniform loop: every lane takes part in the shuffles (a shuffle
+    // from a lane that has left the loop would read an undefined value)
+    for (uint32_t kb = 0; kb < rt[r]; kb += 64) {
+      const uint32_t k = kb + (uint32_t)l;
+      // owner: the first lane with incl > k
+      int lo = 0, hi = 63;
+#pragma unroll
+      for (int step = 0; step < 6; ++step) {
+        const int mid = (lo + hi) >> 1;
+        const uint32_t im = (uint32_t)__shfl((int)incl, mid, 64);
+        if (im > k) hi = mid; else lo = mid + 1;
+      }
+      const int o = lo;
+      const uint32_t oexcl = (uint32_t)__shfl((int)excl, o, 64);
+      const int ox0 = __shfl(x0, o, 64), oy0 = __shfl(y0, o, 64), orw = __shfl(rw, o, 64), ook = __shfl(ok, o, 64);
+      const uint32_t ogb = (uint32_t)__shfl((int)gbase, o, 64), os = (uint32_t)__shfl((int)s[r], o, 64);
+      const uint32_t rk = k - oexcl;
+      const int ty = oy0 + (int)(rk / (uint32_t)orw), tx = ox0 + (int)(rk % (uint32_t)orw);
+      const uint32_t p = rbase + k;
+      if (k < rt[r]) {
+        keys[p] = (ook && ty < tiles_y) ? ogb + (uint32_t)(ty * tiles_x + tx) : 0xffffffffu;
+        vals[p] = os;
+      }
+    }
+    rbase += rt[r];
   }
 }
 
@@ -150,56 +297,78 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, uint64_t n, uint32_t v) {
 }
 
 __global__ __launch_bounds__(KGS_BLOCK) void k_ranges(const uint32_t* __restrict__ counters,
-                                                      const uint64_t* __restrict__ keys,
-                                                      const uint32_t* __restrict__ vals,
-                                                      const uint32_t* __restrict__ pair_slot, uint32_t n_tiles_all,
-                                                      uint2* __restrict__ ranges, uint32_t* __restrict__ sorted_slot) {
+                                                      const uint32_t* __restrict__ keys, uint32_t n_tiles_all,
+                                                      uint2* __restrict__ ranges) {
   const uint32_t n = counters[1];
   for (uint32_t k = blockIdx.x * KGS_BLOCK + threadIdx.x; k < n; k += gridDim.x * KGS_BLOCK) {
-    const uint64_t key = keys[k];
-    sorted_slot[k] = pair_slot[vals[k]];
-    const uint32_t t = (uint32_t)(key >> 32);
-    if (t >= n_tiles_all) continue;  // padding pairs sort last
-    if (k == 0 || (uint32_t)(keys[k - 1] >> 32) != t) ranges[t].x = k;
-    if (k + 1 == n || (uint32_t)(keys[k + 1] >> 32) != t) ranges[t].y = k + 1;
+    const uint32_t t = keys[k];
+    const uint32_t tn = k + 1 < n ? keys[k + 1] : 0xffffffffu;
+    if (t == tn) continue;
+    // k is the last pair of tile t and k + 1 the first of tile tn
+    if (t < n_tiles_all) ranges[t].y = k + 1;
+    if (tn < n_tiles_all) ranges[tn].x = k + 1;
   }
+  if (blockIdx.x == 0 && threadIdx.x == 0 && n > 0) {
+    const uint32_t t0 = keys[0];
+    if (t0 < n_tiles_all) ranges[t0].x = 0;
+  }
+}
+
+// ---------------------------------------------------------------- host side
+template <typename K>
+static int radix_sort(kgs_ctx* ctx, const uint32_t* count, K* keys[2], uint32_t* vals[2], int bits, hipStream_t st) {
+  const int passes = (bits + 7) / 8;
+  hipLaunchKernelGGL(k_radix_zero, dim3(passes), dim3(256), 0, st, ctx->radix_total);
+  int cur = 0;
+  for (int p = 0; p < passes; ++p) {
+    hipLaunchKernelGGL(k_radix_hist<K>, dim3(KGS_SORT_BLOCKS), dim3(256), 0, st, count, (const K*)keys[cur], 8 * p,
+                       ctx->radix_hist, ctx->radix_total + 256 * p);
+    hipLaunchKernelGGL(k_radix_scan, dim3(256), dim3(256), 0, st, ctx->radix_hist,
+                       (const uint32_t*)(ctx->radix_total + 256 * p));
+    hipLaunchKernelGGL(k_radix_scatter<K>, dim3(KGS_SORT_BLOCKS), dim3(256), 0, st, count, (const K*)keys[cur],
+                       (const uint32_t*)vals[cur], 8 * p, (const uint32_t*)ctx->radix_hist, keys[cur ^ 1],
+                       vals[cur ^ 1]);
+    cur ^= 1;
+  }
+  return cur;
 }
 
 kgs_status kgs_launch_bin_sort(kgs_ctx* ctx, hipStream_t st) {
   const int V = ctx->last_views;
   const uint32_t n_tiles_all = (uint32_t)(V * ctx->n_tiles);
-  const uint64_t S = (uint64_t)ctx->cfg.slot_capacity;
-  const unsigned eg = (unsigned)std::min<uint64_t>(std::max<uint64_t>((S + KGS_BLOCK - 1) / KGS_BLOCK, 1), 4096);
-  hipLaunchKernelGGL(k_emit_pairs, dim3(eg), dim3(KGS_BLOCK), 0, st, (const uint32_t*)ctx->counters,
-                     (const float4*)ctx->slot_rec, (const uint32_t*)ctx->slot_view, (const int4*)ctx->slot_pix,
-                     (const uint32_t*)ctx->slot_pairoff, (const uint32_t*)ctx->slot_ntiles, ctx->cfg.tile_w,
-                     ctx->cfg.tile_h, ctx->tiles_x, ctx->tiles_y, (uint64_t)ctx->cfg.pair_capacity, ctx->keys[0],
-                     ctx->vals[0], ctx->pair_slot);
-  // key bits: 32 depth bits + tile bits
+  const uint64_t S = (uint64_t)ctx->cfg.slot_capacity, P = (uint64_t)ctx->cfg.pair_capacity;
+  const unsigned sgrid = (unsigned)std::min<uint64_t>(std::max<uint64_t>((S + KGS_BLOCK - 1) / KGS_BLOCK, 1), 4096);
+  // 1. records by (view, depth)
+  hipLaunchKernelGGL(k_slot_keys, dim3(sgrid), dim3(KGS_BLOCK), 0, st, (const uint32_t*)ctx->counters,
+                     (const float4*)ctx->slot_rec, (const uint32_t*)ctx->slot_view, ctx->slot_keys[0],
+                     ctx->slot_vals[0]);
+  int view_bits = 0;
+  while ((1 << view_bits) < V) ++view_bits;
+  const int sc = radix_sort<uint64_t>(ctx, ctx->counters, ctx->slot_keys, ctx->slot_vals, 32 + view_bits, st);
+  const uint32_t* perm = ctx->slot_vals[sc];
+  // 2. first pair of every record in that order, then the pairs
+  const unsigned ntile_blocks = (unsigned)std::max<uint64_t>((S + SC_TILE - 1) / SC_TILE, 1);
+  hipLaunchKernelGGL(k_scan_up, dim3(ntile_blocks), dim3(256), 0, st, (const uint32_t*)ctx->counters, perm,
+                     (const uint32_t*)ctx->slot_ntiles, ctx->scan_part);
+  hipLaunchKernelGGL(k_scan_mid, dim3(1), dim3(1024), 0, st, ntile_blocks, ctx->scan_part);
+  hipLaunchKernelGGL(k_emit_pairs, dim3(ntile_blocks), dim3(256), 0, st, (const uint32_t*)ctx->counters, perm,
+                     (const uint32_t*)ctx->scan_part, (const uint32_t*)ctx->slot_view, (const int4*)ctx->slot_pix,
+                     (const uint32_t*)ctx->slot_ntiles, ctx->cfg.tile_w, ctx->cfg.tile_h, ctx->tiles_x, ctx->tiles_y,
+                     P, ctx->slot_pairoff, ctx->keys[0], ctx->vals[0]);
+  // 3. pairs by tile (stable)
+  // padding pairs carry key 0xffffffff; with n_tiles_all < 2^tile_bits they
+  // sort after every real pair
   int tile_bits = 0;
-  while ((1u << tile_bits) < n_tiles_all) ++tile_bits;
-  const int passes = (32 + tile_bits + 7) / 8;
-  ctx->passes = passes;
-  hipLaunchKernelGGL(k_radix_zero, dim3(passes), dim3(256), 0, st, ctx->radix_total);
-  int cur = 0;
-  for (int p = 0; p < passes; ++p) {
-    hipLaunchKernelGGL(k_radix_hist, dim3(KGS_SORT_BLOCKS), dim3(256), 0, st, (const uint32_t*)ctx->counters,
-                       (const uint64_t*)ctx->keys[cur], 8 * p, ctx->radix_hist, ctx->radix_total + 256 * p);
-    hipLaunchKernelGGL(k_radix_scan, dim3(256), dim3(256), 0, st, ctx->radix_hist,
-                       (const uint32_t*)(ctx->radix_total + 256 * p));
-    hipLaunchKernelGGL(k_radix_scatter, dim3(KGS_SORT_BLOCKS), dim3(256), 0, st, (const uint32_t*)ctx->counters,
-                       (const uint64_t*)ctx->keys[cur], (const uint32_t*)ctx->vals[cur], 8 * p,
-                       (const uint32_t*)ctx->radix_hist, ctx->keys[cur ^ 1], ctx->vals[cur ^ 1]);
-    cur ^= 1;
-  }
+  while ((1u << tile_bits) <= n_tiles_all) ++tile_bits;
+  const int cur = radix_sort<uint32_t>(ctx, ctx->counters + 1, ctx->keys, ctx->vals, std::max(tile_bits, 1), st);
   ctx->sorted_buf = cur;
+  ctx->passes = (tile_bits + 7) / 8;
   const uint64_t nr = (uint64_t)n_tiles_all * 2;
   hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)std::min<uint64_t>((nr + 255) / 256, 1024)), dim3(256), 0, st,
                      (uint32_t*)ctx->ranges, nr, 0u);
-  const uint64_t P = (uint64_t)ctx->cfg.pair_capacity;
   const unsigned rg = (unsigned)std::min<uint64_t>(std::max<uint64_t>((P + KGS_BLOCK - 1) / KGS_BLOCK, 1), 8192);
   hipLaunchKernelGGL(k_ranges, dim3(rg), dim3(KGS_BLOCK), 0, st, (const uint32_t*)ctx->counters,
-                     (const uint64_t*)ctx->keys[cur], (const uint32_t*)ctx->vals[cur],
-                     (const uint32_t*)ctx->pair_slot, n_tiles_all, ctx->ranges, ctx->sorted_slot);
+                     (const uint32_t*)ctx->keys[cur], n_tiles_all, ctx->ranges);
+  ctx->sorted_slot = ctx->vals[cur];
   return kgs_check_launch();
 }

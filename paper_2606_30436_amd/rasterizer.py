@@ -199,6 +199,15 @@ class Rasterizer:
         L.kgs_render_bwd(self.ctx, g.c(), cams, V, pose_xi, img.c(), dl_dcolor, dl_ddepth, target, tau_err,
                          view_loss, grads_c(grads, pose_grad), stats.c() if stats is not None else None, stream)
 
+    def render_bwd_pixels(self, img: Image, dl_dcolor, dl_ddepth=None, target=None, tau_err=0.1, stream=None):
+        L.kgs_render_bwd_pixels(self.ctx, img.c(), dl_dcolor, dl_ddepth, target, tau_err, stream)
+
+    def project_bwd(self, g: GaussianParams, cams, pose_xi, view_loss=None, grads: Optional[GaussianParams] = None,
+                    pose_grad=None, stats: Optional[ViewStats] = None, stream=None):
+        V = cams.numel() // CAMERA_DTYPE.itemsize
+        L.kgs_project_bwd(self.ctx, g.c(), cams, V, pose_xi, view_loss, grads_c(grads, pose_grad),
+                          stats.c() if stats is not None else None, stream)
+
     def accumulate_stats(self, stats: ViewStats, n_views: int, state: LifecycleState, tau_d=5.0, reset=True,
                          stream=None):
         L.kgs_accumulate_stats(self.ctx, stats.c(), stats.kappa_sum.numel(), n_views, state.c(), tau_d,
@@ -237,13 +246,15 @@ class Rasterizer:
         out = dict(n_slots=ns, n_pairs=npairs,
                    slot_rec=grab(b.slot_rec, ns, torch.float32, 12), slot_gid=grab(b.slot_gid, ns, torch.int32),
                    slot_view=grab(b.slot_view, ns, torch.int32), slot_pix=grab(b.slot_pix, ns, torch.int32, 4),
-                   slot_pairoff=grab(b.slot_pairoff, ns, torch.int32), keys=grab(b.keys, npairs, torch.int64),
+                   slot_pairoff=grab(b.slot_pairoff, ns, torch.int32), keys=grab(b.keys, npairs, torch.int32),
                    sorted_slot=grab(b.sorted_slot, npairs, torch.int32), tiles_x=b.tiles_x, tiles_y=b.tiles_y)
         return out
 
     # ---------------------------------------------------------- chunk
     def chunk_desc(self, g: GaussianParams, cams, pose_xi, target, img: Image, dl_dcolor, view_loss,
-                   grads: Optional[GaussianParams], pose_grad, stats: Optional[ViewStats], tau_err=0.1):
+                   grads: Optional[GaussianParams], pose_grad, stats: Optional[ViewStats], tau_err=0.1,
+                   zero_accumulators=False, state: Optional[LifecycleState] = None, decision=None, tau_d=5.0,
+                   tau_p=0.99):
         d = L.KgsChunkDesc()
         d.gaussians = g.c()
         d.cams = cams.data_ptr()
@@ -256,6 +267,11 @@ class Rasterizer:
         d.view_loss = view_loss.data_ptr()
         d.grads = grads_c(grads, pose_grad)
         d.stats = stats.c() if stats is not None else L.KgsViewStats()
+        d.zero_accumulators = int(bool(zero_accumulators))
+        d.tau_d = tau_d
+        d.state = state.c() if state is not None else L.KgsLifecycleState()
+        d.decision = decision.data_ptr() if decision is not None else None
+        d.tau_p = tau_p
         return d
 
     def chunk_run(self, desc, stream=None):

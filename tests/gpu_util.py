@@ -33,7 +33,8 @@ def say(*a):
 def oracle_cfg(R: Rasterizer) -> OracleConfig:
     c = R.cfg
     return OracleConfig(alpha_min=c.alpha_min, alpha_max=c.alpha_max, t_min=c.t_min, near=c.near_z, eps2d=c.eps2d,
-                        guard=c.guard, rect_margin=c.rect_margin, bg=tuple(c.bg), tile_w=c.tile_w, tile_h=c.tile_h)
+                        guard=c.guard, rect_margin=c.rect_margin, far=c.far_z, bg=tuple(c.bg), tile_w=c.tile_w,
+                        tile_h=c.tile_h)
 
 
 def run_forward(R: Rasterizer, sc, pose=True):

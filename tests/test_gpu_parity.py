@@ -86,8 +86,9 @@ def test_binning_is_bit_exact(name, tile):
     depth_bits = b["slot_rec"].numpy()[:, 6].copy().view(np.uint32)
     keys, gids = oracle.bin_keys(b["slot_view"].numpy(), b["slot_gid"].numpy(), pix[:, 0], pix[:, 1], pix[:, 2],
                                  pix[:, 3], depth_bits, sc.width, sc.height, tile[0], tile[1])
-    gk = b["keys"].numpy().view(np.uint64)
-    gg = b["slot_gid"].numpy()[b["sorted_slot"].numpy()]
+    ss = b["sorted_slot"].numpy()
+    gk = (b["keys"].numpy().view(np.uint32).astype(np.uint64) << np.uint64(32)) | depth_bits[ss].astype(np.uint64)
+    gg = b["slot_gid"].numpy()[ss]
     assert len(gk) == len(keys) == b["n_pairs"]
     assert np.array_equal(gk, keys)
     assert np.array_equal(gg.astype(np.int64), gids)
