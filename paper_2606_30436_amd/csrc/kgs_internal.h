@@ -52,7 +52,7 @@ struct kgs_ctx {
   uint32_t* vals[2];                  // [P] ping-pong (pair emission position)
   uint64_t* slot_keys[2];             // [S] ping-pong: (view << 32) | depth bits
   uint32_t* slot_vals[2];             // [S] ping-pong: slot index
-  uint32_t* scan_part;                // [S / 2048 + 2] block partials of the pair-offset scan
+  uint32_t* scan_part;                // [S / 64 + 2] group partials of the pair-offset scan
   uint32_t* sorted_slot;              // [P] slot of each sorted pair (the sort's value buffer)
   uint2* ranges;                      // [max_views * max_tiles]
   float4* pair_grad;                  // [P][3] per-pair record-space gradients + counts

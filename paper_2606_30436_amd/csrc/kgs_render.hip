@@ -335,6 +335,11 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_render_bwd(
         }
       }
       const uint64_t bb = ballot64(bl);
+      if (bb == 0ull) {
+        // no pixel of this wave blends the Gaussian: its partial is zero
+        if (l < 12) s_part[w][tt][l] = 0.f;
+        continue;
+      }
       const uint64_t bm = ballot64(bl && M);
       int idx;
       bool valid;

@@ -149,29 +149,23 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t* __restric
   }
 }
 
-// ---------------------------------------------------------------- device-wide scan
-// Exclusive scan of f(j), j < *count, in three launches: per-block totals, a
-// scan of the totals, and the block-local scans.  f(j) = ntiles[perm[j]].
-#define SC_ITEMS 8
-#define SC_TILE (256 * SC_ITEMS)
-
-__global__ __launch_bounds__(256) void k_scan_up(const uint32_t* __restrict__ count, const uint32_t* __restrict__ perm,
-                                                 const uint32_t* __restrict__ ntiles, uint32_t* __restrict__ part) {
-  __shared__ uint32_t sh[4];
+// ---------------------------------------------------------------- group scan
+// The depth-sorted slots are cut into groups of 64; a group's pairs are
+// contiguous.  k_group_sum: tile count of every group (one wave per group);
+// k_scan_mid: exclusive scan of the group sums (one block).
+__global__ __launch_bounds__(256) void k_group_sum(const uint32_t* __restrict__ count,
+                                                   const uint32_t* __restrict__ perm,
+                                                   const uint32_t* __restrict__ ntiles, uint32_t n_groups,
+                                                   uint32_t* __restrict__ part) {
   const uint32_t n = *count;
-  const uint32_t b0 = blockIdx.x * SC_TILE;
-  uint32_t s = 0;
-  if (b0 < n) {
-#pragma unroll
-    for (int k = 0; k < SC_ITEMS; ++k) {
-      const uint32_t j = b0 + k * 256 + threadIdx.x;
-      if (j < n) s += ntiles[perm[j]];
-    }
+  const uint32_t l = threadIdx.x & 63;
+  const uint32_t waves = gridDim.x * 4;
+  for (uint32_t g = blockIdx.x * 4 + (threadIdx.x >> 6); g < n_groups; g += waves) {
+    const uint32_t j = g * 64 + l;
+    const uint32_t c = j < n ? ntiles[perm[j]] : 0u;
+    const uint32_t t = wave_sum(c);
+    if (l == 0) part[g] = t;
   }
-  s = wave_sum(s);
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) part[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
 }
 
 __global__ __launch_bounds__(1024) void k_scan_mid(uint32_t nparts, uint32_t* __restrict__ part) {
@@ -207,67 +201,60 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_slot_keys(const uint32_t* __restr
 }
 
 // ---------------------------------------------------------------- pair emission
-// One block per SC_TILE depth-sorted slots; wave w takes rounds of 64
-// consecutive slots.  In a round the lanes load their slot's rectangle, scan
-// the tile counts, and then write the round's pairs together: pair k belongs
-// to the lane whose inclusive count first exceeds k (binary search over the
-// lanes with shuffles), so writes are contiguous and balanced.  A pair's key
-// is its global tile index, its value the slot; its emission position is the
-// slot's first pair plus its row-major rank in the slot's tile rectangle.
-#define EP_ROUNDS (SC_TILE / 256)
+// Waves take the 64-slot groups grid-stride (so the large near-camera
+// Gaussians, which cluster at the start of every view's depth order, spread
+// over the whole grid).  In a group the lanes load their slot's rectangle and
+// scan the tile counts; then the wave writes the group's pairs together: pair
+// k belongs to the lane whose inclusive count first exceeds k (binary search
+// over the lanes with shuffles), so writes are contiguous.  A pair's key is its
+// global tile index, its value the slot; its emission position is the slot's
+// first pair plus its row-major rank in the slot's tile rectangle.
+__device__ __forceinline__ uint32_t udiv_small(uint32_t a, uint32_t b) {
+  uint32_t q = (uint32_t)((float)a * __frcp_rn((float)b));
+  while (q * b > a) --q;
+  while ((q + 1) * b <= a) ++q;
+  return q;
+}
+
 __global__ __launch_bounds__(256) void k_emit_pairs(const uint32_t* __restrict__ counters,
                                                     const uint32_t* __restrict__ perm,
-                                                    const uint32_t* __restrict__ part,
+                                                    const uint32_t* __restrict__ part, uint32_t n_groups,
                                                     const uint32_t* __restrict__ slot_view,
                                                     const int4* __restrict__ slot_pix,
                                                     const uint32_t* __restrict__ slot_ntiles, int tile_w, int tile_h,
                                                     int tiles_x, int tiles_y, uint64_t pair_cap,
                                                     uint32_t* __restrict__ slot_pairoff, uint32_t* __restrict__ keys,
                                                     uint32_t* __restrict__ vals) {
-  __shared__ uint32_t wtot[4];
   const uint32_t n = counters[0];
-  const uint32_t b0 = blockIdx.x * SC_TILE;
-  if (b0 >= n) return;
-  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
-  uint32_t s[EP_ROUNDS], c[EP_ROUNDS], rt[EP_ROUNDS];
-  uint32_t wsum = 0;
-#pragma unroll
-  for (int r = 0; r < EP_ROUNDS; ++r) {
-    const uint32_t j = b0 + w * (SC_TILE / 4) + r * 64 + l;
-    s[r] = j < n ? perm[j] : 0xffffffffu;
-    c[r] = j < n ? slot_ntiles[s[r]] : 0u;
-    rt[r] = wave_sum(c[r]);
-    wsum += rt[r];
-  }
-  if (l == 0) wtot[w] = wsum;
-  __syncthreads();
-  uint32_t wbase = part[blockIdx.x];
-  for (int k = 0; k < w; ++k) wbase += wtot[k];
-  const uint32_t btotal = wtot[0] + wtot[1] + wtot[2] + wtot[3];
-  if ((uint64_t)part[blockIdx.x] + btotal > pair_cap) return;
+  const int l = threadIdx.x & 63;
+  const uint32_t waves = gridDim.x * 4;
   const uint32_t tiles_per_view = (uint32_t)(tiles_x * tiles_y);
-  uint32_t rbase = wbase;
-#pragma unroll 1
-  for (int r = 0; r < EP_ROUNDS; ++r) {
-    const uint32_t incl = wave_inclusive_scan(c[r]);
-    const uint32_t excl = incl - c[r];
+  for (uint32_t g = blockIdx.x * 4 + (threadIdx.x >> 6); g < n_groups; g += waves) {
+    const uint32_t j = g * 64 + (uint32_t)l;
+    if (g * 64 >= n) break;
+    const uint32_t s = j < n ? perm[j] : 0u;
+    const uint32_t c = j < n ? slot_ntiles[s] : 0u;
+    const uint32_t incl = wave_inclusive_scan(c);
+    const uint32_t excl = incl - c;
+    const uint32_t tot = (uint32_t)__shfl((int)incl, 63, 64);
+    const uint32_t rbase = part[g];
+    if ((uint64_t)rbase + tot > pair_cap) continue;
     int x0 = 0, y0 = 0, rw = 1, ok = 0;
     uint32_t gbase = 0;
-    if (c[r] > 0) {
-      const int4 pix = slot_pix[s[r]];
+    if (c > 0) {
+      const int4 pix = slot_pix[s];
       x0 = max(floordiv_i(pix.x - pix.z, tile_w), 0);
       const int x1 = min(floordiv_i(pix.x + pix.z, tile_w) + 1, tiles_x);
       y0 = max(floordiv_i(pix.y - pix.w, tile_h), 0);
       rw = max(x1 - x0, 1);
       ok = x1 > x0;
-      gbase = slot_view[s[r]] * tiles_per_view;
-      slot_pairoff[s[r]] = rbase + excl;
+      gbase = slot_view[s] * tiles_per_view;
+      slot_pairoff[s] = rbase + excl;
     }
     // wave-uniform loop: every lane takes part in the shuffles (a shuffle
     // from a lane that has left the loop would read an undefined value)
-    for (uint32_t kb = 0; kb < rt[r]; kb += 64) {
+    for (uint32_t kb = 0; kb < tot; kb += 64) {
       const uint32_t k = kb + (uint32_t)l;
-      // owner: the first lane with incl > k
       int lo = 0, hi = 63;
 #pragma unroll
       for (int step = 0; step < 6; ++step) {
@@ -278,16 +265,16 @@ __global__ __launch_bounds__(256) void k_emit_pairs(const uint32_t* __restrict__
       const int o = lo;
       const uint32_t oexcl = (uint32_t)__shfl((int)excl, o, 64);
       const int ox0 = __shfl(x0, o, 64), oy0 = __shfl(y0, o, 64), orw = __shfl(rw, o, 64), ook = __shfl(ok, o, 64);
-      const uint32_t ogb = (uint32_t)__shfl((int)gbase, o, 64), os = (uint32_t)__shfl((int)s[r], o, 64);
-      const uint32_t rk = k - oexcl;
-      const int ty = oy0 + (int)(rk / (uint32_t)orw), tx = ox0 + (int)(rk % (uint32_t)orw);
-      const uint32_t p = rbase + k;
-      if (k < rt[r]) {
+      const uint32_t ogb = (uint32_t)__shfl((int)gbase, o, 64), os = (uint32_t)__shfl((int)s, o, 64);
+      if (k < tot) {
+        const uint32_t rk = k - oexcl;
+        const uint32_t qy = udiv_small(rk, (uint32_t)orw);
+        const int ty = oy0 + (int)qy, tx = ox0 + (int)(rk - qy * (uint32_t)orw);
+        const uint32_t p = rbase + k;
         keys[p] = (ook && ty < tiles_y) ? ogb + (uint32_t)(ty * tiles_x + tx) : 0xffffffffu;
         vals[p] = os;
       }
     }
-    rbase += rt[r];
   }
 }
 
@@ -347,14 +334,15 @@ kgs_status kgs_launch_bin_sort(kgs_ctx* ctx, hipStream_t st) {
   const int sc = radix_sort<uint64_t>(ctx, ctx->counters, ctx->slot_keys, ctx->slot_vals, 32 + view_bits, st);
   const uint32_t* perm = ctx->slot_vals[sc];
   // 2. first pair of every record in that order, then the pairs
-  const unsigned ntile_blocks = (unsigned)std::max<uint64_t>((S + SC_TILE - 1) / SC_TILE, 1);
-  hipLaunchKernelGGL(k_scan_up, dim3(ntile_blocks), dim3(256), 0, st, (const uint32_t*)ctx->counters, perm,
-                     (const uint32_t*)ctx->slot_ntiles, ctx->scan_part);
-  hipLaunchKernelGGL(k_scan_mid, dim3(1), dim3(1024), 0, st, ntile_blocks, ctx->scan_part);
-  hipLaunchKernelGGL(k_emit_pairs, dim3(ntile_blocks), dim3(256), 0, st, (const uint32_t*)ctx->counters, perm,
-                     (const uint32_t*)ctx->scan_part, (const uint32_t*)ctx->slot_view, (const int4*)ctx->slot_pix,
-                     (const uint32_t*)ctx->slot_ntiles, ctx->cfg.tile_w, ctx->cfg.tile_h, ctx->tiles_x, ctx->tiles_y,
-                     P, ctx->slot_pairoff, ctx->keys[0], ctx->vals[0]);
+  const uint32_t n_groups = (uint32_t)((S + 63) / 64);
+  const unsigned eg = (unsigned)std::min<uint64_t>(std::max<uint64_t>((n_groups + 3) / 4, 1), 2048);
+  hipLaunchKernelGGL(k_group_sum, dim3(eg), dim3(256), 0, st, (const uint32_t*)ctx->counters, perm,
+                     (const uint32_t*)ctx->slot_ntiles, n_groups, ctx->scan_part);
+  hipLaunchKernelGGL(k_scan_mid, dim3(1), dim3(1024), 0, st, n_groups, ctx->scan_part);
+  hipLaunchKernelGGL(k_emit_pairs, dim3(eg), dim3(256), 0, st, (const uint32_t*)ctx->counters, perm,
+                     (const uint32_t*)ctx->scan_part, n_groups, (const uint32_t*)ctx->slot_view,
+                     (const int4*)ctx->slot_pix, (const uint32_t*)ctx->slot_ntiles, ctx->cfg.tile_w, ctx->cfg.tile_h,
+                     ctx->tiles_x, ctx->tiles_y, P, ctx->slot_pairoff, ctx->keys[0], ctx->vals[0]);
   // 3. pairs by tile (stable)
   // padding pairs carry key 0xffffffff; with n_tiles_all < 2^tile_bits they
   // sort after every real pair
