@@ -166,7 +166,9 @@ typedef struct kgs_lifecycle_state {
 typedef struct kgs_buffers {
   const uint32_t* n_slots;      /* device scalar */
   const uint32_t* n_pairs;      /* device scalar */
-  const float* slot_rec;        /* [S][12]: mu_x-0.5, mu_y-0.5, A, B, C, log2 o, depth, -, r, g, b, - */
+  const float* slot_rec;        /* [S][12]: mu_x-0.5-floor(W/2), mu_y-0.5-floor(H/2), P', k, E', log2 o,
+                                   depth, -, r, g, b, -  with the conic as q = P (dx + k dy)^2 + E dy^2,
+                                   P' = -P log2(e) / 2, E' = -E log2(e) / 2 */
   const uint32_t* slot_gid;     /* [S] Gaussian index */
   const uint32_t* slot_view;    /* [S] view */
   const int32_t* slot_pix;      /* [S][4]: floor(mu_x), floor(mu_y), rx, ry */
@@ -249,13 +251,14 @@ kgs_status kgs_loss_l1(kgs_ctx* ctx, const float* target, const kgs_image* img, 
 /* Backward of render_fwd and project for the last projected views, plus the
  * per-view footprint statistics (appendix, densification and pruning
  * scores: Omega_v(i), M_v, kappa_v(i), gamma_v(i) = L_v |Omega_v(i)|).
- * dl_dcolor [V][3][H][W] (required), dl_ddepth [V][H][W] (or NULL);
+ * dl_dcolor [V][3][H][W] (required), dl_ddepth [V][H][W] (or NULL),
+ * dl_dalpha [V][H][W] (or NULL) for the opacity image 1 - t_final;
  * target [V][3][H][W] or NULL (then kappa is not counted); view_loss [V] or
  * NULL (then gamma is not accumulated).  g, cams and pose_xi must be those of
  * the matching kgs_project.  grads and stats are ADDED to. */
 kgs_status kgs_render_bwd(kgs_ctx* ctx, const kgs_gaussians* g, const kgs_camera* cams, int32_t n_views,
                           const float* pose_xi, const kgs_image* fwd, const float* dl_dcolor,
-                          const float* dl_ddepth, const float* target, float tau_err,
+                          const float* dl_ddepth, const float* dl_dalpha, const float* target, float tau_err,
                           const float* view_loss, const kgs_grads* grads, const kgs_view_stats* stats,
                           void* stream);
 
@@ -266,7 +269,7 @@ kgs_status kgs_render_bwd(kgs_ctx* ctx, const kgs_gaussians* g, const kgs_camera
  * views, the chain rule to the parameters and the pose, and the statistics.
  * Called in this order they equal kgs_render_bwd. */
 kgs_status kgs_render_bwd_pixels(kgs_ctx* ctx, const kgs_image* fwd, const float* dl_dcolor, const float* dl_ddepth,
-                                 const float* target, float tau_err, void* stream);
+                                 const float* dl_dalpha, const float* target, float tau_err, void* stream);
 kgs_status kgs_project_bwd(kgs_ctx* ctx, const kgs_gaussians* g, const kgs_camera* cams, int32_t n_views,
                            const float* pose_xi, const float* view_loss, const kgs_grads* grads,
                            const kgs_view_stats* stats, void* stream);

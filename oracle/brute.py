@@ -60,7 +60,7 @@ def quat_rot(q: torch.Tensor) -> torch.Tensor:
 def render(params: dict, cam, degree: int, cfg, xi: torch.Tensor):
     """params: means [3,N], log_scales [3,N], quats [4,N], logits [N], sh [K,3,N]
     (FP64 tensors); cam: one CAMERA_DTYPE record; xi: [6] tangent.  Returns
-    colour [3,H,W] and depth [H,W]."""
+    colour [3,H,W], depth [H,W] and the opacity image 1 - T_final [H,W]."""
     dt = torch.float64
     W, H = int(cam["width"]), int(cam["height"])
     fx, fy, cx, cy = (float(cam[k]) for k in ("fx", "fy", "cx", "cy"))
@@ -127,4 +127,4 @@ def render(params: dict, cam, degree: int, cfg, xi: torch.Tensor):
         Tr = torch.where(use, Tn, Tr)
     bg = torch.tensor(cfg.bg, dtype=dt)[:, None]
     C = C + Tr[None, :] * bg
-    return C.reshape(3, H, W), D.reshape(H, W)
+    return C.reshape(3, H, W), D.reshape(H, W), (1.0 - Tr).reshape(H, W)

@@ -82,8 +82,10 @@ _SIGS = {
     "kgs_render_fwd": (c_int32, [c_void_p, P(KgsImage), c_void_p]),
     "kgs_loss_l1": (c_int32, [c_void_p, c_void_p, P(KgsImage), c_void_p, c_void_p, c_void_p]),
     "kgs_render_bwd": (c_int32, [c_void_p, P(KgsGaussians), c_void_p, c_int32, c_void_p, P(KgsImage), c_void_p,
-                                 c_void_p, c_void_p, c_float, c_void_p, P(KgsGrads), P(KgsViewStats), c_void_p]),
-    "kgs_render_bwd_pixels": (c_int32, [c_void_p, P(KgsImage), c_void_p, c_void_p, c_void_p, c_float, c_void_p]),
+                                 c_void_p, c_void_p, c_void_p, c_float, c_void_p, P(KgsGrads), P(KgsViewStats),
+                                 c_void_p]),
+    "kgs_render_bwd_pixels": (c_int32, [c_void_p, P(KgsImage), c_void_p, c_void_p, c_void_p, c_void_p, c_float,
+                                        c_void_p]),
     "kgs_project_bwd": (c_int32, [c_void_p, P(KgsGaussians), c_void_p, c_int32, c_void_p, c_void_p, P(KgsGrads),
                                   P(KgsViewStats), c_void_p]),
     "kgs_accumulate_stats": (c_int32, [c_void_p, P(KgsViewStats), c_int64, c_int32, P(KgsLifecycleState), c_float,
@@ -199,18 +201,20 @@ def kgs_loss_l1(ctx, target, img: KgsImage, dl_dcolor, view_loss, stream=None):
                              stream_handle(stream)), "kgs_loss_l1")
 
 
-def kgs_render_bwd(ctx, g: KgsGaussians, cams, n_views, pose_xi, img: KgsImage, dl_dcolor, dl_ddepth, target,
-                   tau_err, view_loss, grads: KgsGrads, stats: KgsViewStats | None, stream=None):
+def kgs_render_bwd(ctx, g: KgsGaussians, cams, n_views, pose_xi, img: KgsImage, dl_dcolor, dl_ddepth, dl_dalpha,
+                   target, tau_err, view_loss, grads: KgsGrads, stats: KgsViewStats | None, stream=None):
     check(load().kgs_render_bwd(ctypes.c_void_p(ctx), ctypes.byref(g), ptr(cams), n_views, ptr(pose_xi),
-                                ctypes.byref(img), ptr(dl_dcolor), ptr(dl_ddepth), ptr(target), float(tau_err),
+                                ctypes.byref(img), ptr(dl_dcolor), ptr(dl_ddepth), ptr(dl_dalpha), ptr(target),
+                                float(tau_err),
                                 ptr(view_loss), ctypes.byref(grads),
                                 ctypes.byref(stats) if stats is not None else None, stream_handle(stream)),
           "kgs_render_bwd")
 
 
-def kgs_render_bwd_pixels(ctx, img: KgsImage, dl_dcolor, dl_ddepth, target, tau_err, stream=None):
+def kgs_render_bwd_pixels(ctx, img: KgsImage, dl_dcolor, dl_ddepth, dl_dalpha, target, tau_err, stream=None):
     check(load().kgs_render_bwd_pixels(ctypes.c_void_p(ctx), ctypes.byref(img), ptr(dl_dcolor), ptr(dl_ddepth),
-                                       ptr(target), float(tau_err), stream_handle(stream)), "kgs_render_bwd_pixels")
+                                       ptr(dl_dalpha), ptr(target), float(tau_err), stream_handle(stream)),
+          "kgs_render_bwd_pixels")
 
 
 def kgs_project_bwd(ctx, g: KgsGaussians, cams, n_views, pose_xi, view_loss, grads: KgsGrads,

@@ -13,8 +13,8 @@ kgs_status kgs_launch_project(kgs_ctx*, const kgs_gaussians*, const kgs_camera*,
 kgs_status kgs_launch_bin_sort(kgs_ctx*, hipStream_t);
 kgs_status kgs_launch_render_fwd(kgs_ctx*, const kgs_image*, hipStream_t);
 kgs_status kgs_launch_loss(kgs_ctx*, const float*, const kgs_image*, float*, float*, hipStream_t);
-kgs_status kgs_launch_render_bwd(kgs_ctx*, const kgs_image*, const float*, const float*, const float*, float,
-                                 hipStream_t);
+kgs_status kgs_launch_render_bwd(kgs_ctx*, const kgs_image*, const float*, const float*, const float*,
+                                 const float*, float, hipStream_t);
 kgs_status kgs_launch_project_bwd(kgs_ctx*, const kgs_gaussians*, const kgs_camera*, int, const float*,
                                   const float*, const kgs_grads*, const kgs_view_stats*, hipStream_t);
 kgs_status kgs_launch_accumulate(kgs_ctx*, const kgs_view_stats*, int64_t, int, const kgs_lifecycle_state*, float,
@@ -237,22 +237,23 @@ kgs_status kgs_loss_l1(kgs_ctx* ctx, const float* target, const kgs_image* img, 
 
 kgs_status kgs_render_bwd(kgs_ctx* ctx, const kgs_gaussians* g, const kgs_camera* cams, int32_t n_views,
                           const float* pose_xi, const kgs_image* fwd, const float* dl_dcolor, const float* dl_ddepth,
-                          const float* target, float tau_err, const float* view_loss, const kgs_grads* grads,
+                          const float* dl_dalpha, const float* target, float tau_err, const float* view_loss,
+                          const kgs_grads* grads,
                           const kgs_view_stats* stats, void* stream) {
   if (!ctx || !gaussians_ok(ctx, g) || !cams || !image_ok(fwd) || !dl_dcolor || !grads) return KGS_ERR_INVALID_ARG;
   if (!ctx->binned) return KGS_ERR_STATE;
   if (n_views != ctx->last_views || g->n != ctx->last_n || g->sh_degree != ctx->last_degree) return KGS_ERR_STATE;
   hipStream_t st = (hipStream_t)stream;
-  kgs_status s = kgs_launch_render_bwd(ctx, fwd, dl_dcolor, dl_ddepth, target, tau_err, st);
+  kgs_status s = kgs_launch_render_bwd(ctx, fwd, dl_dcolor, dl_ddepth, dl_dalpha, target, tau_err, st);
   if (s != KGS_OK) return s;
   return kgs_launch_project_bwd(ctx, g, cams, n_views, pose_xi, view_loss, grads, stats, st);
 }
 
 kgs_status kgs_render_bwd_pixels(kgs_ctx* ctx, const kgs_image* fwd, const float* dl_dcolor, const float* dl_ddepth,
-                                 const float* target, float tau_err, void* stream) {
+                                 const float* dl_dalpha, const float* target, float tau_err, void* stream) {
   if (!ctx || !image_ok(fwd) || !dl_dcolor) return KGS_ERR_INVALID_ARG;
   if (!ctx->binned) return KGS_ERR_STATE;
-  return kgs_launch_render_bwd(ctx, fwd, dl_dcolor, dl_ddepth, target, tau_err, (hipStream_t)stream);
+  return kgs_launch_render_bwd(ctx, fwd, dl_dcolor, dl_ddepth, dl_dalpha, target, tau_err, (hipStream_t)stream);
 }
 
 kgs_status kgs_project_bwd(kgs_ctx* ctx, const kgs_gaussians* g, const kgs_camera* cams, int32_t n_views,
@@ -313,7 +314,7 @@ kgs_status kgs_chunk_run(kgs_ctx* ctx, const kgs_chunk_desc* d, void* stream) {
   if ((s = kgs_bin_sort(ctx, stream)) != KGS_OK) return s;
   if ((s = kgs_render_fwd(ctx, &d->image, stream)) != KGS_OK) return s;
   if ((s = kgs_loss_l1(ctx, d->target, &d->image, d->dl_dcolor, d->view_loss, stream)) != KGS_OK) return s;
-  s = kgs_render_bwd(ctx, &d->gaussians, d->cams, d->n_views, d->pose_xi, &d->image, d->dl_dcolor, nullptr,
+  s = kgs_render_bwd(ctx, &d->gaussians, d->cams, d->n_views, d->pose_xi, &d->image, d->dl_dcolor, nullptr, nullptr,
                      d->target, d->tau_err, d->view_loss, &d->grads, &d->stats, stream);
   if (s != KGS_OK) return s;
   if (d->state.densify) {

@@ -16,17 +16,26 @@
 #define KGS_SLOT_WORDS 40             // words of a slot's backward record
 
 // ---------------------------------------------------------------- device camera
-// Pose already applied: x_cam = R x + t; ctr = camera centre in the world.
+// Pose already applied.  The camera point of a Gaussian is R' mu + t' in
+// FP64 (Rd, td).  The camera centre -R'^T t' (the origin of the view
+// direction) is held as an unevaluated sum ctr + ctr_lo of two floats so that
+// mu - centre keeps its accuracy for maps whose coordinates run to kilometres.
 struct CamDev {
   float R[9];
-  float t[3];
+  float ctr_lo[3];
   float ctr[3];
   float fx, fy, cx, cy;
   float lox, hix, loy, hiy;           // guard band on x/z and y/z
   int32_t W, H;
   int32_t pad0, pad1;
   double Jl[36];                      // SE(3) left Jacobian at xi, row major, (rho, phi) order
+  double Rd[9], td[3];                // the posed world->camera transform in FP64
 };
+
+// Records hold the pixel-plane centre relative to the pixel (floor(W/2),
+// floor(H/2)), so the FP32 value stays within half the image (plus the guard
+// band) in magnitude.
+__device__ __forceinline__ int pix_origin(int extent) { return extent >> 1; }
 
 // ---------------------------------------------------------------- context
 struct kgs_ctx {
@@ -133,21 +142,50 @@ struct ProjCore {
   int clx, cly;          // clamp active
   float J00, J02, J11, J12;
   float T0[3], T1[3];    // rows of J R'
+  float a0[3], a1[3];    // Rq^T T0, Rq^T T1 (the rows of J R' Rq, before the scales)
+  float v[3];            // Rq^T R'^T (ux, uy, 1)
+  float K;               // fx fy / z^2
+  float Sp00, Sp11;      // diagonal of J R' Sigma R'^T J^T (no low-pass term)
   float S00, S01, S11;   // 2D covariance with the low-pass term
   float det;
-  float mx, my;          // pixel-plane centre
+  float Pc, kc, Ec;      // conic as P (dx + k dy)^2 + E dy^2
+  float rmx, rmy;        // pixel-plane centre minus 0.5 minus the record origin
   int fxi, fyi, rx, ry;  // integer centre and half extents
   int x0, x1, y0, y1;    // tile rectangle [x0, x1) x [y0, y1)
 };
 
-// cw: world covariance (xx, xy, xz, yy, yz, zz); o: opacity.  Returns visibility.
-__device__ __forceinline__ bool project_core(const CamDev& c, const float mu[3], const float cw[6], float o,
-                                             float near_z, float far_z, float eps2d, float rect_margin,
+// x - camera centre, with the low part of the centre subtracted second.
+__device__ __forceinline__ void cam_offset(const CamDev& c, const float x[3], float d[3]) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) d[k] = (x[k] - c.ctr[k]) - c.ctr_lo[k];
+}
+
+// The 2D covariance S = M M^T + eps I with M = J R' Rq diag(s) (2x3), in a
+// form FP32 keeps accurate for the long thin splats of nearby surfaces:
+//   * the diagonal entries are sums of squares of the rows m0, m1 of M;
+//   * det(M M^T) = |m0 x m1|^2 (Lagrange), and m0 x m1 = cof(diag s) Rq^T
+//     (T0 x T1) with T0 x T1 = (fx fy / z^2) R'^T (ux, uy, 1) for a rotation
+//     R', so det = K^2 |cof(s) v|^2 + eps (S'00 + S'11) + eps^2 is a sum of
+//     non-negative terms (the textbook S00 S11 - S01^2 cancels to nothing in
+//     FP32 when the splat is a thousand times longer than wide);
+//   * the conic is kept in pivoted form q = P (dx + k dy)^2 + E dy^2 with
+//     P = S11 / det, k = -S01 / S11, E = 1 / S11, which is the same quadratic
+//     form with no cancellation between its terms.
+// o: opacity.  Returns visibility.
+__device__ __forceinline__ bool project_core(const CamDev& c, const float mu[3], const float Rq[9], const float s[3],
+                                             float o, float near_z, float far_z, float eps2d, float rect_margin,
                                              float log_qscale,
                                              int tile_w, int tile_h, int tiles_x, int tiles_y, ProjCore& p) {
-  p.tx = c.R[0] * mu[0] + c.R[1] * mu[1] + c.R[2] * mu[2] + c.t[0];
-  p.ty = c.R[3] * mu[0] + c.R[4] * mu[1] + c.R[5] * mu[2] + c.t[1];
-  p.tz = c.R[6] * mu[0] + c.R[7] * mu[1] + c.R[8] * mu[2] + c.t[2];
+  // camera point and pixel-plane centre in FP64 (a few operations per
+  // Gaussian and view; the centre's FP32 rounding error otherwise moves alpha
+  // at the alpha_min contour by ~1e-3 for sharp splats at x ~ 1000)
+  const double m0 = mu[0], m1 = mu[1], m2 = mu[2];
+  const double X = c.Rd[0] * m0 + c.Rd[1] * m1 + c.Rd[2] * m2 + c.td[0];
+  const double Y = c.Rd[3] * m0 + c.Rd[4] * m1 + c.Rd[5] * m2 + c.td[1];
+  const double Z = c.Rd[6] * m0 + c.Rd[7] * m1 + c.Rd[8] * m2 + c.td[2];
+  p.tx = (float)X;
+  p.ty = (float)Y;
+  p.tz = (float)Z;
   if (!(p.tz > near_z) || !(p.tz < far_z)) return false;
   const float iz = 1.0f / p.tz;
   float ux = p.tx * iz, uy = p.ty * iz;
@@ -166,22 +204,37 @@ __device__ __forceinline__ bool project_core(const CamDev& c, const float mu[3],
     p.T0[k] = p.J00 * c.R[k] + p.J02 * c.R[6 + k];
     p.T1[k] = p.J11 * c.R[3 + k] + p.J12 * c.R[6 + k];
   }
-  // U = T Sigma_w, Sigma2D = U T^T
-  const float U00 = p.T0[0] * cw[0] + p.T0[1] * cw[1] + p.T0[2] * cw[2];
-  const float U01 = p.T0[0] * cw[1] + p.T0[1] * cw[3] + p.T0[2] * cw[4];
-  const float U02 = p.T0[0] * cw[2] + p.T0[1] * cw[4] + p.T0[2] * cw[5];
-  const float U10 = p.T1[0] * cw[0] + p.T1[1] * cw[1] + p.T1[2] * cw[2];
-  const float U11 = p.T1[0] * cw[1] + p.T1[1] * cw[3] + p.T1[2] * cw[4];
-  const float U12 = p.T1[0] * cw[2] + p.T1[1] * cw[4] + p.T1[2] * cw[5];
-  p.S00 = U00 * p.T0[0] + U01 * p.T0[1] + U02 * p.T0[2] + eps2d;
-  p.S01 = U00 * p.T1[0] + U01 * p.T1[1] + U02 * p.T1[2];
-  p.S11 = U10 * p.T1[0] + U11 * p.T1[1] + U12 * p.T1[2] + eps2d;
-  p.det = p.S00 * p.S11 - p.S01 * p.S01;
-  if (!(p.det > 0.0f)) return false;
-  p.mx = c.fx * p.tx * iz + c.cx;
-  p.my = c.fy * p.ty * iz + c.cy;
+  float w[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) w[k] = c.R[k] * ux + c.R[3 + k] * uy + c.R[6 + k];
+  float q0[3], q1[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    p.a0[k] = Rq[k] * p.T0[0] + Rq[3 + k] * p.T0[1] + Rq[6 + k] * p.T0[2];
+    p.a1[k] = Rq[k] * p.T1[0] + Rq[3 + k] * p.T1[1] + Rq[6 + k] * p.T1[2];
+    p.v[k] = Rq[k] * w[0] + Rq[3 + k] * w[1] + Rq[6 + k] * w[2];
+    q0[k] = s[k] * p.a0[k];
+    q1[k] = s[k] * p.a1[k];
+  }
+  p.Sp00 = q0[0] * q0[0] + q0[1] * q0[1] + q0[2] * q0[2];
+  p.Sp11 = q1[0] * q1[0] + q1[1] * q1[1] + q1[2] * q1[2];
+  p.S01 = q0[0] * q1[0] + q0[1] * q1[1] + q0[2] * q1[2];
+  p.S00 = p.Sp00 + eps2d;
+  p.S11 = p.Sp11 + eps2d;
+  p.K = c.fx * c.fy * iz * iz;
+  const float h0 = s[1] * s[2] * p.v[0], h1 = s[0] * s[2] * p.v[1], h2 = s[0] * s[1] * p.v[2];
+  const float Kh = p.K * p.K;
+  p.det = Kh * (h0 * h0 + h1 * h1 + h2 * h2) + eps2d * (p.Sp00 + p.Sp11) + eps2d * eps2d;
+  if (!(p.det > 0.0f) || !(p.S11 > 0.0f)) return false;
+  p.Ec = 1.0f / p.S11;
+  p.Pc = p.S11 / p.det;
+  p.kc = -p.S01 * p.Ec;
+  const double izd = 1.0 / Z;
+  const double mxd = (double)c.fx * X * izd + (double)c.cx, myd = (double)c.fy * Y * izd + (double)c.cy;
   const float BIG = 16777216.0f;
-  if (!(fabsf(p.mx) < BIG && fabsf(p.my) < BIG)) return false;
+  if (!(fabs(mxd) < (double)BIG && fabs(myd) < (double)BIG)) return false;
+  p.rmx = (float)(mxd - 0.5 - (double)pix_origin(c.W));
+  p.rmy = (float)(myd - 0.5 - (double)pix_origin(c.H));
   // alpha >= alpha_min needs q <= qmax = 2 ln(o / alpha_min); on that ellipse
   // |dx| <= sqrt(qmax Sxx) and |dy| <= sqrt(qmax Syy).
   const float qmax = 2.0f * (__logf(o) - log_qscale);
@@ -191,8 +244,8 @@ __device__ __forceinline__ bool project_core(const CamDev& c, const float mu[3],
   ey = fminf(ey, BIG);
   p.rx = (int)ex;
   p.ry = (int)ey;
-  p.fxi = (int)floorf(p.mx);
-  p.fyi = (int)floorf(p.my);
+  p.fxi = (int)floor(mxd);
+  p.fyi = (int)floor(myd);
   int x0 = floordiv_i(p.fxi - p.rx, tile_w), x1 = floordiv_i(p.fxi + p.rx, tile_w) + 1;
   int y0 = floordiv_i(p.fyi - p.ry, tile_h), y1 = floordiv_i(p.fyi + p.ry, tile_h) + 1;
   p.x0 = max(x0, 0);
@@ -202,7 +255,7 @@ __device__ __forceinline__ bool project_core(const CamDev& c, const float mu[3],
   return p.x0 < p.x1 && p.y0 < p.y1;
 }
 
-// Unit quaternion (w, x, y, z) -> rotation, and world covariance R diag(s^2) R^T.
+// Unit quaternion (w, x, y, z) -> rotation.
 __device__ __forceinline__ void quat_rotation(const float q[4], float R[9]) {
   const float w = q[0], x = q[1], y = q[2], z = q[3];
   R[0] = 1.f - 2.f * (y * y + z * z); R[1] = 2.f * (x * y - w * z);       R[2] = 2.f * (x * z + w * y);
@@ -210,15 +263,6 @@ __device__ __forceinline__ void quat_rotation(const float q[4], float R[9]) {
   R[6] = 2.f * (x * z - w * y);       R[7] = 2.f * (y * z + w * x);       R[8] = 1.f - 2.f * (x * x + y * y);
 }
 
-__device__ __forceinline__ void world_cov(const float R[9], const float s[3], float cw[6]) {
-  const float s0 = s[0] * s[0], s1 = s[1] * s[1], s2 = s[2] * s[2];
-  cw[0] = R[0] * R[0] * s0 + R[1] * R[1] * s1 + R[2] * R[2] * s2;
-  cw[1] = R[0] * R[3] * s0 + R[1] * R[4] * s1 + R[2] * R[5] * s2;
-  cw[2] = R[0] * R[6] * s0 + R[1] * R[7] * s1 + R[2] * R[8] * s2;
-  cw[3] = R[3] * R[3] * s0 + R[4] * R[4] * s1 + R[5] * R[5] * s2;
-  cw[4] = R[3] * R[6] * s0 + R[4] * R[7] * s1 + R[5] * R[8] * s2;
-  cw[5] = R[6] * R[6] * s0 + R[7] * R[7] * s1 + R[8] * R[8] * s2;
-}
 
 // Per-Gaussian, view-independent quantities.
 struct GaussLocal {
@@ -226,7 +270,6 @@ struct GaussLocal {
   float qn[4], qnorm;
   float s[3];
   float Rq[9];
-  float cw[6];
   float o;
   bool ok;
 };
@@ -249,7 +292,6 @@ __device__ __forceinline__ void load_gaussian(const kgs_gaussians& g, int64_t i,
 #pragma unroll
   for (int k = 0; k < 3; ++k) G.s[k] = __expf(ls[k]);
   quat_rotation(G.qn, G.Rq);
-  world_cov(G.Rq, G.s, G.cw);
   G.o = 1.0f / (1.0f + __expf(-lg));
   G.ok = !nonfinite && G.qnorm > 0.0f && G.o >= alpha_min;
 }
@@ -351,18 +393,20 @@ __device__ __forceinline__ void sh_dir_grad(int degree, float x, float y, float 
 
 // ---------------------------------------------------------------- compositing
 // Record of a projected Gaussian in the pixel loop (3 x float4):
-//   r0 = (mu_x - 0.5, mu_y - 0.5, A, B)   r1 = (C, log2 o, depth, -)   r2 = (r, g, b, -)
-// with A = -a/2 log2(e), B = -b log2(e), C = -c/2 log2(e) for the conic (a, b, c),
-// so that at pixel (x, y): log2 alpha = log2 o + A dx^2 + B dx dy + C dy^2 with
-// dx = x - r0.x, dy = y - r0.y (pixel centres at +0.5).  The same function is
-// used by the forward and the backward pass so both take identical decisions.
-__device__ __forceinline__ float log2_alpha(float px, float py, const float4& r0, float C, float lo, float& dx,
-                                            float& dy) {
-  dx = px - r0.x;
+//   r0 = (mu_x - 0.5 - ox, mu_y - 0.5 - oy, P', k)   r1 = (E', log2 o, depth, -)   r2 = (r, g, b, -)
+// with (ox, oy) = (floor(W/2), floor(H/2)), P' = -P/2 log2(e), E' = -E/2 log2(e)
+// for the pivoted conic q = P (dx + k dy)^2 + E dy^2.  For the pixel
+// (px, py) = (x + ox, y + oy):  log2 alpha = log2 o + P' u^2 + E' dy^2 with
+// u = dx + k dy, dx = x - r0.x, dy = y - r0.y (pixel centres at +0.5).  The
+// same function is used by the forward and the backward pass so both take
+// identical decisions.
+__device__ __forceinline__ float log2_alpha(float px, float py, const float4& r0, float E, float lo, float& dy,
+                                            float& u) {
+  const float dx = px - r0.x;
   dy = py - r0.y;
-  const float t = __fmaf_rn(r0.z, dx, r0.w * dy);
-  const float u = __fmaf_rn(C * dy, dy, lo);
-  return __fmaf_rn(dx, t, u);
+  u = __fmaf_rn(r0.w, dy, dx);
+  const float t = __fmaf_rn(E * dy, dy, lo);
+  return __fmaf_rn(r0.z * u, u, t);
 }
 
 __device__ __forceinline__ float exp2_approx(float e) { return __builtin_amdgcn_exp2f(e); }

@@ -78,8 +78,13 @@ __global__ void k_cam_setup(const kgs_camera* __restrict__ cams, const float* __
             Vm.a[i * 3] * r[0] + Vm.a[i * 3 + 1] * r[1] + Vm.a[i * 3 + 2] * r[2];
   CamDev d;
   for (int k = 0; k < 9; ++k) d.R[k] = (float)Rp.a[k];
-  for (int i = 0; i < 3; ++i) d.t[i] = (float)tp[i];
-  for (int j = 0; j < 3; ++j) d.ctr[j] = (float)(-(Rp.a[j] * tp[0] + Rp.a[3 + j] * tp[1] + Rp.a[6 + j] * tp[2]));
+  for (int j = 0; j < 3; ++j) {
+    const double cj = -(Rp.a[j] * tp[0] + Rp.a[3 + j] * tp[1] + Rp.a[6 + j] * tp[2]);
+    d.ctr[j] = (float)cj;
+    d.ctr_lo[j] = (float)(cj - (double)d.ctr[j]);
+  }
+  for (int k = 0; k < 9; ++k) d.Rd[k] = Rp.a[k];
+  for (int i = 0; i < 3; ++i) d.td[i] = tp[i];
   d.fx = c.fx; d.fy = c.fy; d.cx = c.cx; d.cy = c.cy;
   const double hx = 0.5 * c.width / c.fx, hy = 0.5 * c.height / c.fy;
   const double mx = (0.5 * c.width - c.cx) / c.fx, my = (0.5 * c.height - c.cy) / c.fy;
@@ -128,7 +133,7 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_count(kgs_gaussians g, const CamD
     uint32_t tiles = 0;
     if (G.ok) {
       ProjCore p;
-      if (project_core(cams[v], G.mu, G.cw, G.o, P.near_z, P.far_z, P.eps2d, P.rect_margin, P.log_alpha_min, P.tile_w,
+      if (project_core(cams[v], G.mu, G.Rq, G.s, G.o, P.near_z, P.far_z, P.eps2d, P.rect_margin, P.log_alpha_min, P.tile_w,
                        P.tile_h, P.tiles_x, P.tiles_y, p))
         tiles = (uint32_t)((p.x1 - p.x0) * (p.y1 - p.y0));
     }
@@ -233,17 +238,16 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_emit(kgs_gaussians g, const CamDe
     }
     const CamDev& c = cams[v];
     ProjCore p;
-    const bool vis_ok = G.ok && project_core(c, G.mu, G.cw, G.o, P.near_z, P.far_z, P.eps2d, P.rect_margin,
+    const bool vis_ok = G.ok && project_core(c, G.mu, G.Rq, G.s, G.o, P.near_z, P.far_z, P.eps2d, P.rect_margin,
                                              P.log_alpha_min, P.tile_w, P.tile_h, P.tiles_x, P.tiles_y, p);
     float4 r0, r1, r2;
     int4 pix;
     if (vis_ok) {
-      const float idet = 1.0f / p.det;
-      const float ca = p.S11 * idet, cb = -p.S01 * idet, cc = p.S00 * idet;
-      r0 = make_float4(p.mx - 0.5f, p.my - 0.5f, -hl2e * ca, -2.0f * hl2e * cb);
-      r1 = make_float4(-hl2e * cc, __log2f(G.o), p.tz, pack_bounds(p.fxi - p.rx, p.fxi + p.rx));
+      r0 = make_float4(p.rmx, p.rmy, -hl2e * p.Pc, p.kc);
+      r1 = make_float4(-hl2e * p.Ec, __log2f(G.o), p.tz, pack_bounds(p.fxi - p.rx, p.fxi + p.rx));
       // colour from the view direction (Gaussian mean minus camera centre)
-      float dv[3] = {G.mu[0] - c.ctr[0], G.mu[1] - c.ctr[1], G.mu[2] - c.ctr[2]};
+      float dv[3];
+      cam_offset(c, G.mu, dv);
       const float inv = 1.0f / sqrtf(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
       float Y[16];
       sh_basis(DEG, dv[0] * inv, dv[1] * inv, dv[2] * inv, Y);

@@ -66,7 +66,7 @@ __device__ __forceinline__ void slot_record(uint32_t s, const kgs_gaussians& g, 
     const CamDev& c = cams[v];
     ProjCore p;
     if (tiles > 0 && G.ok &&
-        project_core(c, G.mu, G.cw, G.o, P.near_z, P.far_z, P.eps2d, P.rect_margin, P.log_alpha_min, P.tile_w,
+        project_core(c, G.mu, G.Rq, G.s, G.o, P.near_z, P.far_z, P.eps2d, P.rect_margin, P.log_alpha_min, P.tile_w,
                      P.tile_h, P.tiles_x, P.tiles_y, p)) {
       float gm[3] = {0.f, 0.f, 0.f}, gls[3] = {0.f, 0.f, 0.f}, gq[4] = {0.f, 0.f, 0.f, 0.f};
       float pose[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
@@ -75,69 +75,93 @@ __device__ __forceinline__ void slot_record(uint32_t s, const kgs_gaussians& g, 
       out[19] = sqrtf(r[0] * r[0] + r[1] * r[1]);
       out[20] = __int_as_float(max(p.rx, p.ry));
         float Yb_out[16];
-        // record space -> conic (a, b, c) and opacity
-        const float idet = 1.0f / p.det;
-        const float ca = p.S11 * idet, cb = -p.S01 * idet, cc = p.S00 * idet;
-        const float ga = -h * r[2], gb = -2.0f * h * r[3], gc = -h * r[4];
+        // record space -> pivoted conic (P, k, E) and opacity
+        const float gP = -h * r[2], gk = r[3], gE = -h * r[4];
         out[10] = r[5] * (1.0f - G.o) / LN2;
-        // dL/dSigma2D = -M G_M M, M the conic matrix, G_M = [[ga, gb/2], [gb/2, gc]]
-        const float X00 = ga * ca + 0.5f * gb * cb, X01 = ga * cb + 0.5f * gb * cc;
-        const float X10 = 0.5f * gb * ca + gc * cb, X11 = 0.5f * gb * cb + gc * cc;
-        const float GS00 = -(ca * X00 + cb * X10);
-        const float GS01 = -0.5f * ((ca * X01 + cb * X11) + (cb * X00 + cc * X10));
-        const float GS11 = -(cb * X01 + cc * X11);
-        // Y = G_S T (2x3); dL/dT = 2 Y Sigma_w; dL/dSigma_w = T^T Y
-        float Y0[3], Y1[3];
+        // P = S11 / det, k = -S01 / S11, E = 1 / S11
+        const float gS11 = gP / p.det - (gk * p.kc + gE * p.Ec) * p.Ec;
+        const float gS01 = -gk * p.Ec;
+        const float gdet = -gP * p.Pc / p.det;
+        // det = K^2 |cof(s) v|^2 + eps (S'00 + S'11) + eps^2,  S11 = S'11 + eps
+        const float gSp00 = P.eps2d * gdet, gSp11 = gS11 + P.eps2d * gdet;
+        const float c0 = G.s[1] * G.s[2], c1 = G.s[0] * G.s[2], c2 = G.s[0] * G.s[1];
+        const float hv0 = c0 * p.v[0], hv1 = c1 * p.v[1], hv2 = c2 * p.v[2];
+        const float gK = 2.0f * p.K * (hv0 * hv0 + hv1 * hv1 + hv2 * hv2) * gdet;
+        const float k2g = 2.0f * p.K * p.K * gdet;
+        const float gh0 = k2g * hv0, gh1 = k2g * hv1, gh2 = k2g * hv2;
+        float gs[3];
+        gs[0] = G.s[2] * p.v[1] * gh1 + G.s[1] * p.v[2] * gh2;
+        gs[1] = G.s[2] * p.v[0] * gh0 + G.s[0] * p.v[2] * gh2;
+        gs[2] = G.s[1] * p.v[0] * gh0 + G.s[0] * p.v[1] * gh1;
+        const float gv[3] = {c0 * gh0, c1 * gh1, c2 * gh2};
+        // S'00 = |m0|^2, S'11 = |m1|^2, S01 = m0 . m1 with m = s * a
+        float ga0[3], ga1[3];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-          Y0[k] = GS00 * p.T0[k] + GS01 * p.T1[k];
-          Y1[k] = GS01 * p.T0[k] + GS11 * p.T1[k];
+          const float m0 = G.s[k] * p.a0[k], m1 = G.s[k] * p.a1[k];
+          const float gm0 = 2.0f * m0 * gSp00 + m1 * gS01, gm1 = 2.0f * m1 * gSp11 + m0 * gS01;
+          gs[k] += p.a0[k] * gm0 + p.a1[k] * gm1;
+          ga0[k] = G.s[k] * gm0;
+          ga1[k] = G.s[k] * gm1;
         }
-        const float* cw = G.cw;  // xx xy xz yy yz zz
-        float GT0[3], GT1[3];
-        GT0[0] = 2.f * (Y0[0] * cw[0] + Y0[1] * cw[1] + Y0[2] * cw[2]);
-        GT0[1] = 2.f * (Y0[0] * cw[1] + Y0[1] * cw[3] + Y0[2] * cw[4]);
-        GT0[2] = 2.f * (Y0[0] * cw[2] + Y0[1] * cw[4] + Y0[2] * cw[5]);
-        GT1[0] = 2.f * (Y1[0] * cw[0] + Y1[1] * cw[1] + Y1[2] * cw[2]);
-        GT1[1] = 2.f * (Y1[0] * cw[1] + Y1[1] * cw[3] + Y1[2] * cw[4]);
-        GT1[2] = 2.f * (Y1[0] * cw[2] + Y1[1] * cw[4] + Y1[2] * cw[5]);
-        float GW[9];
+        // v = Rq^T w, a0 = Rq^T T0, a1 = Rq^T T1 with w = R'^T (ux, uy, 1)
+        float w[3], gw[3], gT0[3], gT1[3], GR[9];
 #pragma unroll
-        for (int a = 0; a < 3; ++a)
+        for (int j = 0; j < 3; ++j) w[j] = c.R[j] * p.ux + c.R[3 + j] * p.uy + c.R[6 + j];
 #pragma unroll
-          for (int b = 0; b < 3; ++b) GW[a * 3 + b] = p.T0[a] * Y0[b] + p.T1[a] * Y1[b];
-        // dL/dJ = dL/dT R'^T (full 2x3)
-        float GJ0[3], GJ1[3];
+        for (int j = 0; j < 3; ++j) {
 #pragma unroll
-        for (int cidx = 0; cidx < 3; ++cidx) {
-          GJ0[cidx] = GT0[0] * c.R[cidx * 3] + GT0[1] * c.R[cidx * 3 + 1] + GT0[2] * c.R[cidx * 3 + 2];
-          GJ1[cidx] = GT1[0] * c.R[cidx * 3] + GT1[1] * c.R[cidx * 3 + 1] + GT1[2] * c.R[cidx * 3 + 2];
+          for (int k = 0; k < 3; ++k) GR[j * 3 + k] = w[j] * gv[k] + p.T0[j] * ga0[k] + p.T1[j] * ga1[k];
+          gw[j] = G.Rq[j * 3] * gv[0] + G.Rq[j * 3 + 1] * gv[1] + G.Rq[j * 3 + 2] * gv[2];
+          gT0[j] = G.Rq[j * 3] * ga0[0] + G.Rq[j * 3 + 1] * ga0[1] + G.Rq[j * 3 + 2] * ga0[2];
+          gT1[j] = G.Rq[j * 3] * ga1[0] + G.Rq[j * 3 + 1] * ga1[1] + G.Rq[j * 3 + 2] * ga1[2];
         }
-        // pose, rotation acting on J R':  A = J^T dL/dJ, g_phi += (A21 - A12, A02 - A20, A10 - A01)
+        // T0 = J00 R'_0 + J02 R'_2, T1 = J11 R'_1 + J12 R'_2, w = ux R'_0 + uy R'_1 + R'_2 (rows of R')
+        float gJ00 = 0.f, gJ02 = 0.f, gJ11 = 0.f, gJ12 = 0.f, gux = 0.f, guy = 0.f;
+        float gRr[9];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          gJ00 += c.R[j] * gT0[j];
+          gJ02 += c.R[6 + j] * gT0[j];
+          gJ11 += c.R[3 + j] * gT1[j];
+          gJ12 += c.R[6 + j] * gT1[j];
+          gux += c.R[j] * gw[j];
+          guy += c.R[3 + j] * gw[j];
+          gRr[j] = p.J00 * gT0[j] + p.ux * gw[j];
+          gRr[3 + j] = p.J11 * gT1[j] + p.uy * gw[j];
+          gRr[6 + j] = p.J02 * gT0[j] + p.J12 * gT1[j] + gw[j];
+        }
+        // pose, rotation acting on R' where it enters T and w: M = R' (dL/dR')^T,
+        // g_phi += (M12 - M21, M20 - M02, M01 - M10)
         {
-          const float A01 = p.J00 * GJ0[1], A02 = p.J00 * GJ0[2];
-          const float A10 = p.J11 * GJ1[0], A12 = p.J11 * GJ1[2];
-          const float A20 = p.J02 * GJ0[0] + p.J12 * GJ1[0], A21 = p.J02 * GJ0[1] + p.J12 * GJ1[1];
-          pose[3] += A21 - A12;
-          pose[4] += A02 - A20;
-          pose[5] += A10 - A01;
+          float M[9];
+#pragma unroll
+          for (int a2 = 0; a2 < 3; ++a2)
+#pragma unroll
+            for (int b2 = 0; b2 < 3; ++b2)
+              M[a2 * 3 + b2] = c.R[a2 * 3] * gRr[b2 * 3] + c.R[a2 * 3 + 1] * gRr[b2 * 3 + 1] +
+                               c.R[a2 * 3 + 2] * gRr[b2 * 3 + 2];
+          pose[3] += M[5] - M[7];
+          pose[4] += M[6] - M[2];
+          pose[5] += M[1] - M[3];
         }
         // camera-frame point gradient
         const float tx = p.tx, ty = p.ty, tz = p.tz, iz = 1.0f / tz, iz2 = iz * iz;
         float gtx = r[0] * c.fx * iz, gty = r[1] * c.fy * iz;
         float gtz = -(r[0] * c.fx * tx + r[1] * c.fy * ty) * iz2 + r[9];
-        gtz += GJ0[0] * (-c.fx * iz2) + GJ1[1] * (-c.fy * iz2);
+        gtz += -2.0f * gK * p.K * iz;
+        gtz += -(gJ00 * c.fx + gJ11 * c.fy) * iz2;
+        gux += -gJ02 * c.fx * iz;
+        gtz += gJ02 * c.fx * p.ux * iz2;
+        guy += -gJ12 * c.fy * iz;
+        gtz += gJ12 * c.fy * p.uy * iz2;
         if (p.clx == 0) {
-          gtx += GJ0[2] * (-c.fx * iz2);
-          gtz += GJ0[2] * (2.0f * c.fx * tx * iz2 * iz);
-        } else {
-          gtz += GJ0[2] * (c.fx * p.ux * iz2);
+          gtx += gux * iz;
+          gtz -= gux * tx * iz2;
         }
         if (p.cly == 0) {
-          gty += GJ1[2] * (-c.fy * iz2);
-          gtz += GJ1[2] * (2.0f * c.fy * ty * iz2 * iz);
-        } else {
-          gtz += GJ1[2] * (c.fy * p.uy * iz2);
+          gty += guy * iz;
+          gtz -= guy * ty * iz2;
         }
 #pragma unroll
         for (int k = 0; k < 3; ++k) gm[k] += c.R[k] * gtx + c.R[3 + k] * gty + c.R[6 + k] * gtz;
@@ -147,23 +171,10 @@ __device__ __forceinline__ void slot_record(uint32_t s, const kgs_gaussians& g, 
         pose[3] += ty * gtz - tz * gty;
         pose[4] += tz * gtx - tx * gtz;
         pose[5] += tx * gty - ty * gtx;
-        // Sigma_w = M M^T, M = Rq diag(s)
+        // s = exp(log_s); Rq from the normalised quaternion
+#pragma unroll
+        for (int k = 0; k < 3; ++k) gls[k] += gs[k] * G.s[k];
         {
-          float GM[9];
-#pragma unroll
-          for (int a = 0; a < 3; ++a)
-#pragma unroll
-            for (int k = 0; k < 3; ++k)
-              GM[a * 3 + k] = 2.f * (GW[a * 3] * G.Rq[k] + GW[a * 3 + 1] * G.Rq[3 + k] + GW[a * 3 + 2] * G.Rq[6 + k]) *
-                              G.s[k];
-          float GR[9];
-#pragma unroll
-          for (int k = 0; k < 3; ++k) {
-            gls[k] += (GM[k] * G.Rq[k] + GM[3 + k] * G.Rq[3 + k] + GM[6 + k] * G.Rq[6 + k]) * G.s[k];
-            GR[k] = GM[k] * G.s[k];
-            GR[3 + k] = GM[3 + k] * G.s[k];
-            GR[6 + k] = GM[6 + k] * G.s[k];
-          }
           const float qw = G.qn[0], qx = G.qn[1], qy = G.qn[2], qz = G.qn[3];
           const float gw = 2.f * (-qz * GR[1] + qy * GR[2] + qz * GR[3] - qx * GR[5] - qy * GR[6] + qx * GR[7]);
           const float gx = 2.f * (qy * GR[1] + qz * GR[2] + qy * GR[3] - 2.f * qx * GR[4] - qw * GR[5] + qz * GR[6] +
@@ -182,7 +193,8 @@ __device__ __forceinline__ void slot_record(uint32_t s, const kgs_gaussians& g, 
         // colour: SH basis at the view direction, masked colour gradient, and
         // the direction gradient sum_k w_k grad Y_k with w_k = sum_ch g_ch c_k,ch
         {
-          float dv[3] = {G.mu[0] - c.ctr[0], G.mu[1] - c.ctr[1], G.mu[2] - c.ctr[2]};
+          float dv[3];
+          cam_offset(c, G.mu, dv);
           const float dist = sqrtf(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]), idist = 1.0f / dist;
           const float dx = dv[0] * idist, dy = dv[1] * idist, dz = dv[2] * idist;
           sh_basis(DEG, dx, dy, dz, Yb_out);

@@ -94,7 +94,7 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_render_fwd(RenderParams P, const 
   tile_subblock(P.tile_w, w, sx, sy);
   const int px = tile_x0 + sx + (l & 7), py = tile_y0 + sy + (l >> 3);
   const bool inside = px < P.W && py < P.H;
-  const float fpx = (float)px, fpy = (float)py;
+  const float fpx = (float)(px - pix_origin(P.W)), fpy = (float)(py - pix_origin(P.H));
   const uint2 rg = ranges[gt];
   const uint32_t start = rg.x, end = rg.y;
   float T = 1.0f, c0 = 0.f, c1 = 0.f, c2 = 0.f, D = 0.f;
@@ -111,8 +111,8 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_render_fwd(RenderParams P, const 
       const int tt = s_list[w][j];
       const float4 r0 = s_r0[tt], r1 = s_r1[tt];
       if (!done) {
-        float dx, dy;
-        const float e = log2_alpha(fpx, fpy, r0, r1.x, r1.y, dx, dy);
+        float dy, u;
+        const float e = log2_alpha(fpx, fpy, r0, r1.x, r1.y, dy, u);
         if (e >= P.log2_amin) {
           const float a = fminf(exp2_approx(e), P.amax);
           const float Tn = T * (1.0f - a);
@@ -234,8 +234,8 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_render_bwd(
     RenderParams P, const uint2* __restrict__ ranges, const uint32_t* __restrict__ sorted_slot,
     const uint32_t* __restrict__ slot_pairoff, const float4* __restrict__ slot_rec, const float* __restrict__ color,
     const float* __restrict__ depth, const float* __restrict__ tfinal, const int32_t* __restrict__ last,
-    const float* __restrict__ dl_dcolor, const float* __restrict__ dl_ddepth, const float* __restrict__ target,
-    float tau_err, float4* __restrict__ pair_grad) {
+    const float* __restrict__ dl_dcolor, const float* __restrict__ dl_ddepth, const float* __restrict__ dl_dalpha,
+    const float* __restrict__ target, float tau_err, float4* __restrict__ pair_grad) {
   __shared__ float4 s_r0[B], s_r1[B], s_r2[B];
   __shared__ uint32_t s_slot[B];
   __shared__ uint8_t s_list[4][B];
@@ -252,12 +252,12 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_render_bwd(
   tile_subblock(P.tile_w, w, sx, sy);
   const int px = tile_x0 + sx + (l & 7), py = tile_y0 + sy + (l >> 3);
   const bool inside = px < P.W && py < P.H;
-  const float fpx = (float)px, fpy = (float)py;
+  const float fpx = (float)(px - pix_origin(P.W)), fpy = (float)(py - pix_origin(P.H));
   const uint2 rg = ranges[gt];
   const uint32_t start = rg.x, end = rg.y;
   // per-pixel inputs
   int lastp = 0;
-  float Co0 = 0.f, Co1 = 0.f, Co2 = 0.f, Do = 0.f, g0 = 0.f, g1 = 0.f, g2 = 0.f, gD = 0.f;
+  float Co0 = 0.f, Co1 = 0.f, Co2 = 0.f, Do = 0.f, g0 = 0.f, g1 = 0.f, g2 = 0.f, gD = 0.f, gAT = 0.f;
   bool M = false;
   if (inside) {
     const size_t npix = (size_t)P.W * P.H;
@@ -272,6 +272,8 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_render_bwd(
     g1 = dl_dcolor[cpix + npix];
     g2 = dl_dcolor[cpix + 2 * npix];
     if (dl_ddepth) gD = dl_ddepth[pix];
+    // opacity image A = 1 - T_final: dA/dalpha_j = T_final / (1 - alpha_j)
+    if (dl_dalpha) gAT = dl_dalpha[pix] * tfinal[pix];
     if (target) {
       const float err = fabsf(target[cpix] - Co0) + fabsf(target[cpix + npix] - Co1) +
                         fabsf(target[cpix + 2 * npix] - Co2);
@@ -304,8 +306,8 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_render_bwd(
       for (int q = 0; q < 10; ++q) x[q] = 0.f;
       bool bl = false;
       if (krel < lastp) {
-        float dx, dy;
-        const float e = log2_alpha(fpx, fpy, r0, r1.x, r1.y, dx, dy);
+        float dy, u;
+        const float e = log2_alpha(fpx, fpy, r0, r1.x, r1.y, dy, u);
         if (e >= P.log2_amin) {
           bl = true;
           const float raw = exp2_approx(e);
@@ -317,17 +319,19 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_render_bwd(
           Da = fmaf(wgt, r1.z, Da);
           const float om = 1.0f / (1.0f - a);
           const float dLda = g0 * (T * r2.x - (Co0 - Ca0) * om) + g1 * (T * r2.y - (Co1 - Ca1) * om) +
-                             g2 * (T * r2.z - (Co2 - Ca2) * om) + gD * (T * r1.z - (Do - Da) * om);
+                             g2 * (T * r2.z - (Co2 - Ca2) * om) + gD * (T * r1.z - (Do - Da) * om) + gAT * om;
           x[6] = wgt * g0;
           x[7] = wgt * g1;
           x[8] = wgt * g2;
           x[9] = wgt * gD;
           if (raw < P.amax) {
             const float ge = dLda * a * LN2;
-            x[0] = -ge * (2.0f * r0.z * dx + r0.w * dy);
-            x[1] = -ge * (r0.w * dx + 2.0f * r1.x * dy);
-            x[2] = ge * dx * dx;
-            x[3] = ge * dx * dy;
+            // d(log2 alpha) / d(mu_x, mu_y, P', k, E')
+            const float pu = 2.0f * r0.z * u;
+            x[0] = -ge * pu;
+            x[1] = -ge * fmaf(pu, r0.w, 2.0f * r1.x * dy);
+            x[2] = ge * u * u;
+            x[3] = ge * pu * dy;
             x[4] = ge * dy * dy;
             x[5] = ge;
           }
@@ -435,7 +439,7 @@ kgs_status kgs_launch_loss(kgs_ctx* ctx, const float* target, const kgs_image* i
 }
 
 kgs_status kgs_launch_render_bwd(kgs_ctx* ctx, const kgs_image* fwd, const float* dl_dcolor, const float* dl_ddepth,
-                                 const float* target, float tau_err, hipStream_t st) {
+                                 const float* dl_dalpha, const float* target, float tau_err, hipStream_t st) {
   const RenderParams P = render_params(ctx);
   const unsigned grid = (unsigned)(ctx->last_views * ctx->n_tiles);
 #define KGS_BWD(BB)                                                                                              \
@@ -443,7 +447,7 @@ kgs_status kgs_launch_render_bwd(kgs_ctx* ctx, const kgs_image* fwd, const float
                      (const uint32_t*)ctx->sorted_slot, (const uint32_t*)ctx->slot_pairoff,                      \
                      (const float4*)ctx->slot_rec,                                                                \
                      (const float*)fwd->color, (const float*)fwd->depth, (const float*)fwd->t_final,              \
-                     (const int32_t*)fwd->last, dl_dcolor, dl_ddepth, target, tau_err, ctx->pair_grad)
+                     (const int32_t*)fwd->last, dl_dcolor, dl_ddepth, dl_dalpha, target, tau_err, ctx->pair_grad)
   switch (ctx->cfg.batch) {
     case 32: KGS_BWD(32); break;
     case 64: KGS_BWD(64); break;

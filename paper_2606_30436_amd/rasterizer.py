@@ -149,6 +149,7 @@ class Rasterizer:
         self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
         self.ctx = L.kgs_create(cfg, self.workspace, self.ws_bytes)
         self.graphs = []
+        self.generation = 0  # bumped by every project(): the workspace then holds new records
 
     def close(self):
         for g in self.graphs:
@@ -181,6 +182,7 @@ class Rasterizer:
     def project(self, g: GaussianParams, cams: torch.Tensor, pose_xi: Optional[torch.Tensor] = None, stream=None):
         V = cams.numel() // CAMERA_DTYPE.itemsize
         L.kgs_project(self.ctx, g.c(), cams, V, pose_xi, stream)
+        self.generation += 1
         return V
 
     def bin_sort(self, stream=None):
@@ -194,13 +196,14 @@ class Rasterizer:
 
     def render_bwd(self, g: GaussianParams, cams, pose_xi, img: Image, dl_dcolor, dl_ddepth=None, target=None,
                    tau_err=0.1, view_loss=None, grads: Optional[GaussianParams] = None, pose_grad=None,
-                   stats: Optional[ViewStats] = None, stream=None):
+                   stats: Optional[ViewStats] = None, stream=None, dl_dalpha=None):
         V = cams.numel() // CAMERA_DTYPE.itemsize
-        L.kgs_render_bwd(self.ctx, g.c(), cams, V, pose_xi, img.c(), dl_dcolor, dl_ddepth, target, tau_err,
+        L.kgs_render_bwd(self.ctx, g.c(), cams, V, pose_xi, img.c(), dl_dcolor, dl_ddepth, dl_dalpha, target, tau_err,
                          view_loss, grads_c(grads, pose_grad), stats.c() if stats is not None else None, stream)
 
-    def render_bwd_pixels(self, img: Image, dl_dcolor, dl_ddepth=None, target=None, tau_err=0.1, stream=None):
-        L.kgs_render_bwd_pixels(self.ctx, img.c(), dl_dcolor, dl_ddepth, target, tau_err, stream)
+    def render_bwd_pixels(self, img: Image, dl_dcolor, dl_ddepth=None, target=None, tau_err=0.1, stream=None,
+                          dl_dalpha=None):
+        L.kgs_render_bwd_pixels(self.ctx, img.c(), dl_dcolor, dl_ddepth, dl_dalpha, target, tau_err, stream)
 
     def project_bwd(self, g: GaussianParams, cams, pose_xi, view_loss=None, grads: Optional[GaussianParams] = None,
                     pose_grad=None, stats: Optional[ViewStats] = None, stream=None):
@@ -227,6 +230,9 @@ class Rasterizer:
 
     def status(self) -> int:
         return L.kgs_status_read(self.ctx)
+
+    def status_clear(self, stream=None):
+        L.kgs_status_clear(self.ctx, stream)
 
     def buffers(self) -> dict:
         """Copies of the slot and pair buffers of the last project/bin_sort."""

@@ -1,0 +1,273 @@
+"""The keyframe chunk on the GPU: one chunk_run call against the same steps
+called one by one, HIP-graph replays against eager runs, the chunk scores and
+densify / prune decision against the FP64 lifecycle rules, the batched call
+against a plain per-view loop, capacity overflow, and degenerate inputs."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import lifecycle
+from paper_2606_30436_amd import scenes
+from paper_2606_30436_amd.rasterizer import (GaussianParams, Image, LifecycleState, Rasterizer, ViewStats,
+                                             device_cameras)
+from tests.gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+FAR = 80.0
+SLOT_OVERFLOW, PAIR_OVERFLOW = 1, 2
+
+
+@pytest.fixture(scope="module")
+def chunk():
+    """200k Gaussians of the trajectory scene, 4 keyframes, perturbed poses,
+    random targets."""
+    sc = scenes.make_c3(seed=11, n=200_000, n_views=4)
+    sc.pose_xi = scenes.random_pose_perturbation(np.random.default_rng(12), 4, angle_deg=0.2, trans=0.05)
+    sc.target = scenes.random_target(13, 4, sc.height, sc.width)
+    return sc
+
+
+class Bufs:
+    """Device inputs and outputs of one chunk."""
+
+    def __init__(self, sc, R):
+        V, H, W = sc.n_views, sc.height, sc.width
+        self.g = GaussianParams.from_scene(sc)
+        self.cams = device_cameras(sc.cams)
+        self.xi = torch.from_numpy(sc.pose_xi.astype(np.float32)).cuda()
+        self.target = torch.from_numpy(sc.target).cuda()
+        self.img = Image.empty(V, H, W)
+        self.dl = torch.empty_like(self.img.color)
+        self.loss = torch.empty(V, device="cuda")
+        self.grads = self.g.zeros_like()
+        self.pose = torch.zeros(V, 6, device="cuda")
+        self.stats = ViewStats.zeros(sc.n)
+        self.state = LifecycleState.zeros(sc.n)
+        self.dec = torch.empty(sc.n, dtype=torch.uint8, device="cuda")
+        self.R = R
+
+    def desc(self, tau_d=0.5, tau_p=0.6, with_state=True):
+        return self.R.chunk_desc(self.g, self.cams, self.xi, self.target, self.img, self.dl, self.loss, self.grads,
+                                 self.pose, self.stats, tau_err=0.1, zero_accumulators=True,
+                                 state=self.state if with_state else None, decision=self.dec if with_state else None,
+                                 tau_d=tau_d, tau_p=tau_p)
+
+    def outputs(self):
+        s, g = self.stats, self.grads
+        return [t.clone() for t in (self.img.color, self.img.depth, self.img.t_final, self.img.last, self.dl, self.loss,
+                                    g.means, g.log_scales, g.quats, g.logits, g.sh, self.pose, s.kappa_sum,
+                                    s.omega_sum, s.gamma_sum, s.grad_norm_sum, s.view_count, s.max_radius,
+                                    self.state.densify, self.state.prune_score, self.dec)]
+
+
+def _same(a, b):
+    names = ["color", "depth", "t_final", "last", "dl", "loss", "g.means", "g.log_scales", "g.quats", "g.logits",
+             "g.sh", "pose", "kappa", "omega", "gamma", "gnorm", "vcount", "maxr", "densify", "prune", "decision"]
+    for n, x, y in zip(names, a, b):
+        assert torch.equal(x, y), n
+
+
+def _rast(sc, **kw):
+    return Rasterizer(sc.width, sc.height, max_views=sc.n_views, max_gaussians=sc.n, far_z=FAR, **kw)
+
+
+def test_chunk_run_equals_the_steps(chunk):
+    sc = chunk
+    say(f"[gpu] chunk_run vs steps n={sc.n} V={sc.n_views}")
+    R = _rast(sc)
+    b = Bufs(sc, R)
+    R.chunk_run(b.desc())
+    torch.cuda.synchronize()
+    assert R.status() == 0
+    one = b.outputs()
+    # the same work step by step (accumulators zeroed by hand)
+    for t in (b.grads.means, b.grads.log_scales, b.grads.quats, b.grads.logits, b.grads.sh, b.pose,
+              b.stats.kappa_sum, b.stats.omega_sum, b.stats.gamma_sum, b.stats.grad_norm_sum, b.stats.view_count,
+              b.stats.max_radius, b.state.densify, b.state.prune_score):
+        t.zero_()
+    R.project(b.g, b.cams, b.xi)
+    R.bin_sort()
+    R.render_fwd(b.img)
+    R.loss_l1(b.target, b.img, b.dl, b.loss)
+    R.render_bwd(b.g, b.cams, b.xi, b.img, b.dl, target=b.target, tau_err=0.1, view_loss=b.loss, grads=b.grads,
+                 pose_grad=b.pose, stats=b.stats)
+    R.accumulate_stats(b.stats, sc.n_views, b.state, tau_d=0.5, reset=True)
+    dec, _, _ = R.decide(b.state, tau_p=0.6, keep_map=False)
+    b.dec.copy_(dec)
+    torch.cuda.synchronize()
+    # the state was zeroed above, so the chunk's own OR / max equal a fresh run
+    _same(one, b.outputs())
+
+
+def test_graph_replays_equal_eager_runs(chunk):
+    """Capture once; between replays the means change in place (eager torch
+    work) and the lifecycle state is reset; every replay must equal an eager
+    chunk_run on the same values, bit for bit."""
+    sc = chunk
+    say("[gpu] graph replays")
+    R = _rast(sc)
+    b = Bufs(sc, R)
+    d = b.desc()
+    graph = R.chunk_capture(d)
+    torch.cuda.synchronize()
+    gen = torch.Generator(device="cuda").manual_seed(7)
+    for rep in range(4):
+        with torch.no_grad():
+            b.g.means.add_(torch.randn(b.g.means.shape, device="cuda", generator=gen) * 1e-3)
+            b.state.densify.zero_()
+            b.state.prune_score.zero_()
+        R.chunk_launch(graph)
+        torch.cuda.synchronize()
+        replay = b.outputs()
+        b.state.densify.zero_()
+        b.state.prune_score.zero_()
+        R.chunk_run(d)
+        torch.cuda.synchronize()
+        _same(replay, b.outputs())
+        say(f"  replay {rep}: identical")
+    assert R.status() == 0
+
+
+def test_chunk_scores_and_decision_match_lifecycle_rules(chunk):
+    """Two chunks into one global state: S_d = kappa / |V_c|, S_p normalised
+    over the active set in FP64, OR / max merge, PRUNE over DENSIFY; keep map."""
+    sc = chunk
+    say("[gpu] lifecycle rules")
+    R = _rast(sc)
+    b = Bufs(sc, R)
+    D = np.zeros(sc.n, bool)
+    P = np.zeros(sc.n)
+    tau_d, tau_p = 0.5, 0.6
+    for c, views in enumerate(([0, 1, 2, 3], [3, 1])):
+        sub = sc.views(views)
+        cams = device_cameras(sub.cams)
+        xi = torch.from_numpy(sub.pose_xi.astype(np.float32)).cuda()
+        tgt = torch.from_numpy(sub.target).cuda()
+        V = len(views)
+        img = Image.empty(V, sc.height, sc.width)
+        dl = torch.empty_like(img.color)
+        loss = torch.empty(V, device="cuda")
+        R.project(b.g, cams, xi)
+        R.bin_sort()
+        R.render_fwd(img)
+        R.loss_l1(tgt, img, dl, loss)
+        st = ViewStats.zeros(sc.n)
+        R.render_bwd(b.g, cams, xi, img, dl, target=tgt, tau_err=0.1, view_loss=loss, grads=b.g.zeros_like(),
+                     stats=st)
+        torch.cuda.synchronize()
+        ks, os_, gs = (st.kappa_sum.cpu().numpy(), st.omega_sum.cpu().numpy(), st.gamma_sum.cpu().numpy())
+        R.accumulate_stats(st, V, b.state, tau_d=tau_d, reset=True)
+        dec, km, nk = R.decide(b.state, tau_p=tau_p)
+        torch.cuda.synchronize()
+        ref = lifecycle.chunk_scores_from_sums(ks, os_, gs, V)
+        D, P = lifecycle.global_update(D, P, ref["sd"], ref["sp"], tau_d)
+        gD = b.state.densify.cpu().numpy().astype(bool)
+        gP = b.state.prune_score.cpu().numpy()
+        assert np.array_equal(gD, D)
+        assert np.abs(gP - P).max() <= 1e-12
+        want = lifecycle.decide(D, P, tau_p)
+        near = np.abs(P - tau_p) < 1e-12
+        gdec = dec.cpu().numpy()
+        assert np.array_equal(gdec[~near], want[~near])
+        kref, nref = lifecycle.keep_map(gdec)
+        assert np.array_equal(km.cpu().numpy().astype(np.uint32), kref) and int(nk.item()) == nref
+        assert int(st.kappa_sum.sum().item()) == 0 and int(st.omega_sum.sum().item()) == 0  # reset
+        counts = np.bincount(gdec, minlength=3)
+        say(f"  chunk {c}: active {int(ref['active'].sum())}, keep/densify/prune {counts.tolist()}")
+        assert counts[1] > 0 and counts[2] > 0
+
+
+def test_batched_chunk_equals_per_view_loop(chunk):
+    """All views in one call against one view per call on a one-view context:
+    images, losses, pose gradients, footprint sums and decisions identical;
+    the parameter gradients, summed in a different order, within FP32 rounding."""
+    sc = chunk
+    say("[gpu] batched vs per-view loop")
+    R = _rast(sc)
+    b = Bufs(sc, R)
+    R.chunk_run(b.desc())
+    torch.cuda.synchronize()
+    batched = b.outputs()
+    R1 = Rasterizer(sc.width, sc.height, max_views=1, max_gaussians=sc.n, far_z=FAR)
+    p = Bufs(sc, R1)
+    for v in range(sc.n_views):
+        vi = Image(p.img.color[v:v + 1], p.img.depth[v:v + 1], p.img.t_final[v:v + 1], p.img.last[v:v + 1])
+        cam = p.cams.view(sc.n_views, -1)[v]
+        R1.project(p.g, cam, p.xi[v:v + 1])
+        R1.bin_sort()
+        R1.render_fwd(vi)
+        R1.loss_l1(p.target[v:v + 1], vi, p.dl[v:v + 1], p.loss[v:v + 1])
+        R1.render_bwd(p.g, cam, p.xi[v:v + 1], vi, p.dl[v:v + 1], target=p.target[v:v + 1], tau_err=0.1,
+                      view_loss=p.loss[v:v + 1], grads=p.grads, pose_grad=p.pose[v:v + 1], stats=p.stats)
+    R1.accumulate_stats(p.stats, sc.n_views, p.state, tau_d=0.5, reset=True)
+    dec, _, _ = R1.decide(p.state, tau_p=0.6, keep_map=False)
+    p.dec.copy_(dec)
+    torch.cuda.synchronize()
+    loop = p.outputs()
+    exact = {0, 1, 2, 3, 4, 5, 11, 12, 13, 16, 17, 18, 20}
+    for k, (x, y) in enumerate(zip(batched, loop)):
+        if k in exact:
+            assert torch.equal(x, y), k
+        else:
+            xd, yd = x.double(), y.double()
+            rel = float((xd - yd).norm() / yd.norm().clamp_min(1e-30))
+            assert rel < 1e-5, (k, rel)
+
+
+def test_capacity_overflow_is_reported_and_safe(chunk):
+    sc = chunk.views([0])
+    for cap, flag in ((dict(slot_capacity=1000), SLOT_OVERFLOW), (dict(pair_capacity=5000), PAIR_OVERFLOW)):
+        say(f"[gpu] overflow {cap}")
+        R = Rasterizer(sc.width, sc.height, max_views=1, max_gaussians=sc.n, far_z=FAR, bg=(0.25, 0.5, 0.75), **cap)
+        b = Bufs(sc, R)
+        R.chunk_run(b.desc(with_state=False))
+        torch.cuda.synchronize()
+        assert R.status() & flag
+        assert R.counts() == (0, 0)
+        # nothing is composited: the background, full transmittance, zero gradients
+        col = b.img.color.cpu().numpy()
+        for ch, v in enumerate((0.25, 0.5, 0.75)):
+            assert np.all(col[0, ch] == np.float32(v))
+        assert torch.all(b.img.t_final == 1) and torch.all(b.grads.means == 0)
+        R.status_clear()
+        torch.cuda.synchronize()
+        assert R.status() == 0
+
+
+def test_degenerate_inputs():
+    """No Gaussian in front of the camera, zero opacity, a zero-size image
+    tail (width and height not multiples of the tile), one Gaussian."""
+    sc = scenes.tiny_scene(seed=21, n=40, degree=1, W=37, H=19, n_views=2)
+    bg = (0.1, 0.2, 0.3)
+    # all behind the camera
+    behind = sc.subset(np.arange(sc.n))
+    behind.means = behind.means.copy()
+    behind.means[2] *= -1.0
+    # all transparent
+    clear = sc.subset(np.arange(sc.n))
+    clear.logits = np.full(sc.n, -30.0, np.float32)
+    for name, s in (("behind", behind), ("transparent", clear)):
+        say(f"[gpu] degenerate: {name}")
+        R = Rasterizer(s.width, s.height, max_views=2, max_gaussians=s.n, bg=bg)
+        b = Bufs(s, R)
+        R.chunk_run(b.desc(with_state=False))
+        torch.cuda.synchronize()
+        assert R.status() == 0 and R.counts() == (0, 0)
+        col = b.img.color.cpu().numpy()
+        for ch in range(3):
+            assert np.all(col[:, ch] == np.float32(bg[ch]))
+        assert torch.all(b.grads.means == 0) and torch.all(b.pose == 0)
+    # a single Gaussian
+    one = sc.subset(np.array([5]))
+    one.means = np.array([[0.05], [-0.02], [3.0]], np.float32)
+    one.log_scales = np.full((3, 1), -2.0, np.float32)
+    one.logits = np.array([2.0], np.float32)
+    R = Rasterizer(one.width, one.height, max_views=2, max_gaussians=1)
+    b = Bufs(one, R)
+    R.chunk_run(b.desc(with_state=False))
+    torch.cuda.synchronize()
+    assert R.status() == 0
+    ns, npairs = R.counts()
+    assert ns == 2 and npairs >= ns
+    assert torch.isfinite(b.grads.means).all()

@@ -59,12 +59,18 @@ def test_project_records_match_oracle(name):
         assert len(diff) <= max(2, 1e-3 * len(vis)), diff
         common, ig, io = np.intersect1d(gid, vis, return_indices=True)
         r = rec[ig]
-        mu = r[:, 0:2] + 0.5
-        assert np.allclose(mu, pr["mu"][common], rtol=1e-5, atol=2e-3)
-        conic = np.stack([-2 * r[:, 2] / LOG2E, -r[:, 3] / LOG2E, -2 * r[:, 4] / LOG2E], 1)
+        mu = r[:, 0:2] + 0.5 + np.array([sc.width // 2, sc.height // 2])
+        # FP64 centre rounded once to FP32 relative to the image centre
+        assert np.abs(mu - pr["mu"][common]).max() <= 1e-4
+        # the record holds the conic pivoted: q = P (dx + k dy)^2 + E dy^2
+        Pg, kg, Eg = -2 * r[:, 2] / LOG2E, r[:, 3], -2 * r[:, 4] / LOG2E
         oc = pr["conic"][common]
-        scale = np.maximum(np.abs(oc[:, 0]), np.abs(oc[:, 2]))[:, None]
-        assert (np.abs(conic - oc) <= 2e-4 * scale).all(), np.max(np.abs(conic - oc) / scale)
+        Po, ko, Eo = oc[:, 0], oc[:, 1] / oc[:, 0], oc[:, 2] - oc[:, 1] ** 2 / oc[:, 0]
+        assert np.allclose(Pg, Po, rtol=2e-5, atol=0), np.max(np.abs(Pg / Po - 1))
+        assert np.allclose(Eg, Eo, rtol=2e-5, atol=0), np.max(np.abs(Eg / Eo - 1))
+        # k moves q by about 2 sqrt(P / E) dk at the footprint's edge
+        kscale = np.sqrt(Eo / Po)
+        assert (np.abs(kg - ko) <= 1e-5 * kscale + 1e-6 * np.abs(ko)).all(), np.max(np.abs(kg - ko) / kscale)
         assert np.allclose(2.0 ** r[:, 5], pr["opacity"][common], rtol=1e-5)
         assert np.allclose(r[:, 6], pr["depth"][common], rtol=1e-6)
         assert np.allclose(r[:, 8:11], pr["color"][common], atol=2e-5)

@@ -306,7 +306,7 @@ def test_oracle_matches_tile_free_autograd(seed, degree, pose):
         img = ov.image()
         P = _torch_params(sc)
         xi = torch.tensor(sc.pose_xi[v].astype(np.float64), requires_grad=True)
-        C, D = brute.render(P, sc.cams[v], degree, CFG, xi)
+        C, D, _ = brute.render(P, sc.cams[v], degree, CFG, xi)
         assert np.allclose(C.detach().numpy(), img["color"], atol=1e-10)
         assert np.allclose(D.detach().numpy(), img["depth"], atol=1e-9)
         L = (C * torch.tensor(wC)).sum() + (D * torch.tensor(wD)).sum()
