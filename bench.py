@@ -48,7 +48,7 @@ def kernel_source_hash() -> str:
 def read_traffic():
     """Per-launch HBM bytes of the compositing backward from the committed
     rocprofv3 counter summary; None if absent or taken on other kernel source."""
-    path = os.path.join(ROOT, "profiles", "render_bwd_c3_counters.txt")
+    path = os.path.join(ROOT, "profiles", "k_render_bwd_2M_8view_chunk_counters.txt")
     if not os.path.exists(path):
         return None
     vals = {}
@@ -75,6 +75,8 @@ def main():
     ap.add_argument("--tile", type=str, default=None, help="e.g. 16x16 (skips the autotuner)")
     ap.add_argument("--batch", type=int, default=None)
     ap.add_argument("--stage-reps", type=int, default=5)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only copy BYTES device-to-device three times (HBM counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only; --gpus {args.gpus} is not supported "
@@ -89,6 +91,15 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.copy_probe:
+        src = torch.ones(args.copy_probe, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": args.copy_probe, "copies": 3}), flush=True)
+        return
     t0 = time.time()
     sc = scenes.make_c3()
     true = scenes.Scene(sc.meta["true"]["means"], sc.log_scales, sc.quats, sc.logits, sc.meta["true"]["sh"], 3,
@@ -295,8 +306,8 @@ def main():
         "metric": METRIC, "value": round(mpix, 2), "unit": "Mpix/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "C3 batched chunk: 2M Gaussians on a 1 km trajectory, 8 keyframes at 1242x375, "
-                               "SH3, FP32, one HIP graph per chunk",
+        "config": {"workload": "batched keyframe chunk: 2M Gaussians on a 1 km trajectory, 8 keyframes at "
+                               "1242x375, SH3, FP32, one HIP graph per chunk",
                    "n_gaussians": N, "n_views": V, "width": W, "height": H, "far_z": FAR,
                    "tile": list(best[0]), "batch": best[1], "visible_per_view": visible, "slots": n_slots,
                    "pairs": n_pairs, "plain_ms_per_chunk": None if plain_ms is None else round(plain_ms, 4),
