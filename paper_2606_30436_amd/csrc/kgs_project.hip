@@ -152,41 +152,61 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_count(kgs_gaussians g, const CamD
 
 // ---------------------------------------------------------------- block scan
 // Exclusive scan of the (visible, tiles) pairs of all (view, block) entries in
-// (view, block) order.  One block of 1024 threads.  Bases saturate at the
-// capacities; totals are written clamped, overflow raises a status bit.
+// (view, block) order.  One block of 1024 threads walks the array in rounds of
+// 4096 entries (each thread four consecutive entries, so loads and stores are
+// coalesced), carrying the running totals.  Bases saturate at the capacities;
+// totals are written clamped, overflow raises a status bit.
 __global__ __launch_bounds__(1024) void k_scan_blocks(const uint32_t* __restrict__ blk_cnt,
                                                       uint32_t* __restrict__ blk_base, int64_t entries,
                                                       uint64_t slot_cap, uint64_t pair_cap,
                                                       uint32_t* __restrict__ counters) {
+  constexpr int E = 4;
   __shared__ unsigned long long sa[16], sb[16];
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
-  const int64_t per = (entries + 1023) / 1024;
-  const int64_t lo = tid * per, hi = min(entries, lo + per);
-  unsigned long long a = 0, b = 0;
-  for (int64_t e = lo; e < hi; ++e) { a += blk_cnt[2 * e]; b += blk_cnt[2 * e + 1]; }
-  unsigned long long ia = wave_inclusive_scan(a), ib = wave_inclusive_scan(b);
-  if (l == 63) { sa[w] = ia; sb[w] = ib; }
-  __syncthreads();
-  unsigned long long oa = 0, ob = 0, ta = 0, tb = 0;
-  for (int k = 0; k < 16; ++k) {
-    if (k < w) { oa += sa[k]; ob += sb[k]; }
-    ta += sa[k];
-    tb += sb[k];
-  }
-  unsigned long long ra = oa + ia - a, rb = ob + ib - b;
-  for (int64_t e = lo; e < hi; ++e) {
-    blk_base[2 * e] = (uint32_t)min(ra, (unsigned long long)slot_cap);
-    blk_base[2 * e + 1] = (uint32_t)min(rb, (unsigned long long)pair_cap);
-    ra += blk_cnt[2 * e];
-    rb += blk_cnt[2 * e + 1];
+  unsigned long long ca = 0, cb = 0;
+  for (int64_t base = 0; base < entries; base += 1024 * E) {
+    const int64_t e0 = base + (int64_t)tid * E;
+    uint32_t va[E], vb[E];
+    unsigned long long a = 0, b = 0;
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      const bool in = e0 + k < entries;
+      va[k] = in ? blk_cnt[2 * (e0 + k)] : 0u;
+      vb[k] = in ? blk_cnt[2 * (e0 + k) + 1] : 0u;
+      a += va[k];
+      b += vb[k];
+    }
+    const unsigned long long ia = wave_inclusive_scan(a), ib = wave_inclusive_scan(b);
+    if (l == 63) { sa[w] = ia; sb[w] = ib; }
+    __syncthreads();
+    unsigned long long oa = ca, ob = cb, ta = 0, tb = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      if (k < w) { oa += sa[k]; ob += sb[k]; }
+      ta += sa[k];
+      tb += sb[k];
+    }
+    unsigned long long ra = oa + ia - a, rb = ob + ib - b;
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      if (e0 + k < entries) {
+        blk_base[2 * (e0 + k)] = (uint32_t)min(ra, (unsigned long long)slot_cap);
+        blk_base[2 * (e0 + k) + 1] = (uint32_t)min(rb, (unsigned long long)pair_cap);
+      }
+      ra += va[k];
+      rb += vb[k];
+    }
+    ca += ta;
+    cb += tb;
+    __syncthreads();
   }
   if (tid == 0) {
     uint32_t f = 0;
-    if (ta > slot_cap) f |= KGS_FLAG_SLOT_OVERFLOW;
-    if (tb > pair_cap) f |= KGS_FLAG_PAIR_OVERFLOW;
+    if (ca > slot_cap) f |= KGS_FLAG_SLOT_OVERFLOW;
+    if (cb > pair_cap) f |= KGS_FLAG_PAIR_OVERFLOW;
     // on overflow every later stage sees zero records and zero pairs
-    counters[0] = f ? 0u : (uint32_t)ta;
-    counters[1] = f ? 0u : (uint32_t)tb;
+    counters[0] = f ? 0u : (uint32_t)ca;
+    counters[1] = f ? 0u : (uint32_t)cb;
     if (f) atomicOr(&counters[2], f);
   }
 }

@@ -104,32 +104,27 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_render_fwd(RenderParams P, const 
     if (__syncthreads_count(!done) == 0) break;
     stage_batch<B>(base, end, sorted_slot, slot_rec, tile_x0, tile_y0, P.tile_w, s_r0, s_r1, s_r2, s_slot, s_mask,
                    s_list, s_cnt);
-    const uint32_t len = s_cnt[0][w] + s_cnt[1][w] + s_cnt[2][w] + s_cnt[3][w];
+    const uint32_t len = __builtin_amdgcn_readfirstlane(s_cnt[0][w] + s_cnt[1][w] + s_cnt[2][w] + s_cnt[3][w]);
     const int rel0 = (int)(base - start) + 1;
     for (uint32_t j = 0; j < len; ++j) {
       if (!__any(!done)) break;
-      const int tt = s_list[w][j];
-      const float4 r0 = s_r0[tt], r1 = s_r1[tt];
-      if (!done) {
-        float dy, u;
-        const float e = log2_alpha(fpx, fpy, r0, r1.x, r1.y, dy, u);
-        if (e >= P.log2_amin) {
-          const float a = fminf(exp2_approx(e), P.amax);
-          const float Tn = T * (1.0f - a);
-          if (Tn < P.tmin) {
-            done = true;
-          } else {
-            const float4 r2 = s_r2[tt];
-            const float wgt = a * T;
-            c0 = fmaf(wgt, r2.x, c0);
-            c1 = fmaf(wgt, r2.y, c1);
-            c2 = fmaf(wgt, r2.z, c2);
-            D = fmaf(wgt, r1.z, D);
-            T = Tn;
-            lst = rel0 + tt;
-          }
-        }
-      }
+      const int tt = __builtin_amdgcn_readfirstlane(s_list[w][j]);  // same entry for the whole wave
+      const float4 r0 = s_r0[tt], r1 = s_r1[tt], r2 = s_r2[tt];
+      float dy, u;
+      const float e = log2_alpha(fpx, fpy, r0, r1.x, r1.y, dy, u);
+      const bool hit = !done && e >= P.log2_amin;
+      const float a = hit ? fminf(exp2_approx(e), P.amax) : 0.f;
+      const float Tn = T * (1.0f - a);
+      const bool stop = hit && Tn < P.tmin;
+      done = done || stop;
+      const bool take = hit && !stop;
+      const float wgt = take ? a * T : 0.f;
+      c0 = fmaf(wgt, r2.x, c0);
+      c1 = fmaf(wgt, r2.y, c1);
+      c2 = fmaf(wgt, r2.z, c2);
+      D = fmaf(wgt, r1.z, D);
+      T = take ? Tn : T;
+      lst = take ? rel0 + tt : lst;
     }
   }
   if (inside) {
@@ -182,38 +177,52 @@ __global__ void k_loss_final(int V, int nblk, double inv_n, const double* __rest
 // Reduce-scatter of 10 values over a wave: after the call lane L holds, in
 // x[0], the wave sum of value 5 b5 + 3 b4 + 2 b3 + b2 (b_k = bit k of L) when
 // `valid` is set.
+__device__ __forceinline__ float f_swap_sum32(float lo_keep, float hi_keep) {
+  // lanes 0-31 end with the wave-half sum of lo_keep, lanes 32-63 of hi_keep
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(lo_keep), __float_as_uint(hi_keep), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+__device__ __forceinline__ float f_swap_sum16(float even_keep, float odd_keep) {
+  // 16-lane rows 0 and 2 end with even_keep summed over row pairs, rows 1 and 3 with odd_keep
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(even_keep), __float_as_uint(odd_keep), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+template <int CTRL>
+__device__ __forceinline__ float f_dpp(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+
+// Reduce-scatter of ten per-lane values over the wave.  Each step pairs every
+// lane with a partner whose lane bit b differs (lane halves, row pairs, the
+// mirrored lane of a 16-lane row, the mirrored lane of an 8-lane half-row);
+// the lane keeps the values its bit selects and adds the partner's copy.  The
+// two pairings inside a quad then complete the sums.  Lanes with valid set
+// hold the full wave sum of value idx.
 __device__ __forceinline__ void wave_reduce10(float (&x)[10], int lane, int& idx, bool& valid) {
-  const bool u5 = lane & 32, u4 = lane & 16, u3 = lane & 8, u2 = lane & 4;
+  const bool u4 = lane & 16, u3 = lane & 8, u2 = lane & 4;
 #pragma unroll
-  for (int k = 0; k < 5; ++k) {
-    const float send = u5 ? x[k] : x[k + 5];
-    const float keep = u5 ? x[k + 5] : x[k];
-    x[k] = keep + __shfl_xor(send, 32, 64);
+  for (int k = 0; k < 5; ++k) x[k] = f_swap_sum32(x[k], x[k + 5]);
+  x[0] = f_swap_sum16(x[0], x[3]);
+  x[1] = f_swap_sum16(x[1], x[4]);
+  x[2] = f_swap_sum16(x[2], 0.f);
+  {
+    const float s0 = u3 ? x[0] : x[2], k0 = u3 ? x[2] : x[0];
+    const float s1 = u3 ? x[1] : 0.f, k1 = u3 ? 0.f : x[1];
+    x[0] = k0 + f_dpp<0x140>(s0);  // row_mirror: lane 15 - i of the row
+    x[1] = k1 + f_dpp<0x140>(s1);
   }
   {
-    const float a0 = u4 ? x[0] : x[3], k0 = u4 ? x[3] : x[0];
-    const float a1 = u4 ? x[1] : x[4], k1 = u4 ? x[4] : x[1];
-    const float a2 = u4 ? x[2] : 0.f, k2 = u4 ? 0.f : x[2];
-    x[0] = k0 + __shfl_xor(a0, 16, 64);
-    x[1] = k1 + __shfl_xor(a1, 16, 64);
-    x[2] = k2 + __shfl_xor(a2, 16, 64);
+    const float s0 = u2 ? x[0] : x[1], k0 = u2 ? x[1] : x[0];
+    x[0] = k0 + f_dpp<0x141>(s0);  // row_half_mirror: lane 7 - i of the half-row
   }
-  {
-    const float a0 = u3 ? x[0] : x[2], k0 = u3 ? x[2] : x[0];
-    const float a1 = u3 ? x[1] : 0.f, k1 = u3 ? 0.f : x[1];
-    x[0] = k0 + __shfl_xor(a0, 8, 64);
-    x[1] = k1 + __shfl_xor(a1, 8, 64);
-  }
-  {
-    const float a0 = u2 ? x[0] : x[1], k0 = u2 ? x[1] : x[0];
-    x[0] = k0 + __shfl_xor(a0, 4, 64);
-  }
-  x[0] += __shfl_xor(x[0], 2, 64);
-  x[0] += __shfl_xor(x[0], 1, 64);
+  x[0] += f_dpp<0xB1>(x[0]);       // quad_perm [1, 0, 3, 2]
+  x[0] += f_dpp<0x4E>(x[0]);       // quad_perm [2, 3, 0, 1]
   const int k = (u3 ? 2 : 0) + (u2 ? 1 : 0);
   const int rel = (u4 ? 3 : 0) + k;
   valid = (k < 3) && (rel < 5) && ((lane & 3) == 0);
-  idx = (u5 ? 5 : 0) + rel;
+  idx = ((lane & 32) ? 5 : 0) + rel;
 }
 
 // Emission position of the pair (slot, tile (tx, ty)): the slot's first pair
@@ -283,6 +292,7 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_render_bwd(
   int wmax = lastp;
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) wmax = max(wmax, __shfl_xor(wmax, o, 64));
+  wmax = __builtin_amdgcn_readfirstlane(wmax);
   if (l == 0) s_wmax[w] = wmax;
   __syncthreads();
   const int bmax = max(max(s_wmax[0], s_wmax[1]), max(s_wmax[2], s_wmax[3]));
@@ -294,56 +304,51 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_render_bwd(
     __syncthreads();
     stage_batch<B>(base, end, sorted_slot, slot_rec, tile_x0, tile_y0, P.tile_w, s_r0, s_r1, s_r2, s_slot, s_mask,
                    s_list, s_cnt);
-    const uint32_t len = s_cnt[0][w] + s_cnt[1][w] + s_cnt[2][w] + s_cnt[3][w];
+    const uint32_t len = __builtin_amdgcn_readfirstlane(s_cnt[0][w] + s_cnt[1][w] + s_cnt[2][w] + s_cnt[3][w]);
     const int rel0 = (int)(base - start);
     for (uint32_t j = 0; j < len; ++j) {
-      const int tt = s_list[w][j];
+      const int tt = __builtin_amdgcn_readfirstlane(s_list[w][j]);  // same entry for the whole wave
       const int krel = rel0 + tt;
       if (krel >= wmax) break;
-      const float4 r0 = s_r0[tt], r1 = s_r1[tt], r2 = s_r2[tt];
-      float x[10];
-#pragma unroll
-      for (int q = 0; q < 10; ++q) x[q] = 0.f;
-      bool bl = false;
-      if (krel < lastp) {
-        float dy, u;
-        const float e = log2_alpha(fpx, fpy, r0, r1.x, r1.y, dy, u);
-        if (e >= P.log2_amin) {
-          bl = true;
-          const float raw = exp2_approx(e);
-          const float a = fminf(raw, P.amax);
-          const float wgt = a * T;
-          Ca0 = fmaf(wgt, r2.x, Ca0);
-          Ca1 = fmaf(wgt, r2.y, Ca1);
-          Ca2 = fmaf(wgt, r2.z, Ca2);
-          Da = fmaf(wgt, r1.z, Da);
-          const float om = 1.0f / (1.0f - a);
-          const float dLda = g0 * (T * r2.x - (Co0 - Ca0) * om) + g1 * (T * r2.y - (Co1 - Ca1) * om) +
-                             g2 * (T * r2.z - (Co2 - Ca2) * om) + gD * (T * r1.z - (Do - Da) * om) + gAT * om;
-          x[6] = wgt * g0;
-          x[7] = wgt * g1;
-          x[8] = wgt * g2;
-          x[9] = wgt * gD;
-          if (raw < P.amax) {
-            const float ge = dLda * a * LN2;
-            // d(log2 alpha) / d(mu_x, mu_y, P', k, E')
-            const float pu = 2.0f * r0.z * u;
-            x[0] = -ge * pu;
-            x[1] = -ge * fmaf(pu, r0.w, 2.0f * r1.x * dy);
-            x[2] = ge * u * u;
-            x[3] = ge * pu * dy;
-            x[4] = ge * dy * dy;
-            x[5] = ge;
-          }
-          T = T * (1.0f - a);
-        }
-      }
+      const float4 r0 = s_r0[tt], r1 = s_r1[tt];
+      float dy, u;
+      const float e = log2_alpha(fpx, fpy, r0, r1.x, r1.y, dy, u);
+      const bool bl = krel < lastp && e >= P.log2_amin;
       const uint64_t bb = ballot64(bl);
       if (bb == 0ull) {
         // no pixel of this wave blends the Gaussian: its partial is zero
         if (l < 12) s_part[w][tt][l] = 0.f;
         continue;
       }
+      // from here every lane computes; lanes that do not blend carry a = 0,
+      // which zeroes all their terms and leaves T and the running sums alone
+      const float4 r2 = s_r2[tt];
+      const float raw = exp2_approx(e);
+      const float a = bl ? fminf(raw, P.amax) : 0.f;
+      const float wgt = a * T;
+      Ca0 = fmaf(wgt, r2.x, Ca0);
+      Ca1 = fmaf(wgt, r2.y, Ca1);
+      Ca2 = fmaf(wgt, r2.z, Ca2);
+      Da = fmaf(wgt, r1.z, Da);
+      const float om = __builtin_amdgcn_rcpf(1.0f - a);
+      const float dLda = g0 * (T * r2.x - (Co0 - Ca0) * om) + g1 * (T * r2.y - (Co1 - Ca1) * om) +
+                         g2 * (T * r2.z - (Co2 - Ca2) * om) + gD * (T * r1.z - (Do - Da) * om) + gAT * om;
+      float x[10];
+      x[6] = wgt * g0;
+      x[7] = wgt * g1;
+      x[8] = wgt * g2;
+      x[9] = wgt * gD;
+      // the clamp at alpha_max cuts the derivative of alpha in o and q
+      const float ge = raw < P.amax ? dLda * a * LN2 : 0.f;
+      // d(log2 alpha) / d(mu_x, mu_y, P', k, E')
+      const float pu = 2.0f * r0.z * u;
+      x[0] = -ge * pu;
+      x[1] = -ge * fmaf(pu, r0.w, 2.0f * r1.x * dy);
+      x[2] = ge * u * u;
+      x[3] = ge * pu * dy;
+      x[4] = ge * dy * dy;
+      x[5] = ge;
+      T = T * (1.0f - a);
       const uint64_t bm = ballot64(bl && M);
       int idx;
       bool valid;

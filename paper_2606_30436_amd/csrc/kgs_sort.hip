@@ -152,7 +152,8 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t* __restric
 // ---------------------------------------------------------------- group scan
 // The depth-sorted slots are cut into groups of 64; a group's pairs are
 // contiguous.  k_group_sum: tile count of every group (one wave per group);
-// k_scan_mid: exclusive scan of the group sums (one block).
+// k_scan_mid: exclusive scan of the group sums (one block, coalesced rounds);
+// k_slot_offsets: each record's first pair.
 __global__ __launch_bounds__(256) void k_group_sum(const uint32_t* __restrict__ count,
                                                    const uint32_t* __restrict__ perm,
                                                    const uint32_t* __restrict__ ntiles, uint32_t n_groups,
@@ -169,22 +170,61 @@ __global__ __launch_bounds__(256) void k_group_sum(const uint32_t* __restrict__ 
 }
 
 __global__ __launch_bounds__(1024) void k_scan_mid(uint32_t nparts, uint32_t* __restrict__ part) {
+  constexpr uint32_t E = 4;
   __shared__ uint32_t sh[16];
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
-  const uint32_t per = (nparts + 1023) / 1024;
-  const uint32_t lo = min(nparts, tid * per), hi = min(nparts, lo + per);
-  uint32_t a = 0;
-  for (uint32_t b = lo; b < hi; ++b) a += part[b];
-  const uint32_t ia = wave_inclusive_scan(a);
-  if (l == 63) sh[w] = ia;
-  __syncthreads();
-  uint32_t off = 0;
-  for (int k = 0; k < w; ++k) off += sh[k];
-  uint32_t r = off + ia - a;
-  for (uint32_t b = lo; b < hi; ++b) {
-    const uint32_t c = part[b];
-    part[b] = r;
-    r += c;
+  uint32_t carry = 0;
+  for (uint32_t base = 0; base < nparts; base += 1024 * E) {
+    const uint32_t i0 = base + (uint32_t)tid * E;
+    uint32_t v[E], a = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < E; ++k) {
+      v[k] = i0 + k < nparts ? part[i0 + k] : 0u;
+      a += v[k];
+    }
+    const uint32_t ia = wave_inclusive_scan(a);
+    if (l == 63) sh[w] = ia;
+    __syncthreads();
+    uint32_t off = carry, tot = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      if (k < w) off += sh[k];
+      tot += sh[k];
+    }
+    uint32_t r = off + ia - a;
+#pragma unroll
+    for (uint32_t k = 0; k < E; ++k) {
+      if (i0 + k < nparts) part[i0 + k] = r;
+      r += v[k];
+    }
+    carry += tot;
+    __syncthreads();
+  }
+}
+
+// First pair of every record in depth order: pref[j] = part[g] + the exclusive
+// scan of the tile counts inside the 64-record group g = j / 64; the same value
+// is the record's slot_pairoff.
+__global__ __launch_bounds__(256) void k_slot_offsets(const uint32_t* __restrict__ counters,
+                                                      const uint32_t* __restrict__ perm,
+                                                      const uint32_t* __restrict__ part, uint32_t n_groups,
+                                                      const uint32_t* __restrict__ ntiles, uint64_t pair_cap,
+                                                      uint32_t* __restrict__ pref,
+                                                      uint32_t* __restrict__ slot_pairoff) {
+  const uint32_t n = counters[0];
+  const uint32_t l = threadIdx.x & 63;
+  const uint32_t waves = gridDim.x * 4;
+  for (uint32_t g = blockIdx.x * 4 + (threadIdx.x >> 6); g < n_groups; g += waves) {
+    if (g * 64 >= n) break;
+    const uint32_t j = g * 64 + l;
+    const uint32_t s = j < n ? perm[j] : 0u;
+    const uint32_t c = j < n ? ntiles[s] : 0u;
+    const uint32_t incl = wave_inclusive_scan(c);
+    const uint64_t off = min((uint64_t)part[g] + (incl - c), pair_cap);
+    if (j < n) {
+      pref[j] = (uint32_t)off;
+      slot_pairoff[s] = (uint32_t)off;
+    }
   }
 }
 
@@ -201,14 +241,16 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_slot_keys(const uint32_t* __restr
 }
 
 // ---------------------------------------------------------------- pair emission
-// Waves take the 64-slot groups grid-stride (so the large near-camera
-// Gaussians, which cluster at the start of every view's depth order, spread
-// over the whole grid).  In a group the lanes load their slot's rectangle and
-// scan the tile counts; then the wave writes the group's pairs together: pair
-// k belongs to the lane whose inclusive count first exceeds k (binary search
-// over the lanes with shuffles), so writes are contiguous.  A pair's key is its
-// global tile index, its value the slot; its emission position is the slot's
-// first pair plus its row-major rank in the slot's tile rectangle.
+// Balanced by pairs: each round a block takes the next EP_CHUNK pairs.  Two
+// waves find (64-way search over pref) the records that own the first and the
+// last pair, the block stages those records' first-pair offsets in LDS, and
+// each thread emits EP_PPT consecutive pairs, walking forward from a binary
+// search in LDS.  A pair's key is its global tile index, its value the record;
+// pair k of a record is the k-th tile of its rectangle in row-major order, so
+// its emission position is the record's first pair plus that rank.
+#define EP_PPT 8
+#define EP_CHUNK (256 * EP_PPT)
+
 __device__ __forceinline__ uint32_t udiv_small(uint32_t a, uint32_t b) {
   uint32_t q = (uint32_t)((float)a * __frcp_rn((float)b));
   while (q * b > a) --q;
@@ -216,65 +258,117 @@ __device__ __forceinline__ uint32_t udiv_small(uint32_t a, uint32_t b) {
   return q;
 }
 
+// Last j in [0, n) with pref[j] <= target, for a whole wave (pref[0] = 0).
+__device__ __forceinline__ uint32_t wave_search_last_le(const uint32_t* __restrict__ pref, uint32_t n,
+                                                        uint32_t target) {
+  const uint32_t l = threadIdx.x & 63;
+  uint32_t lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const uint32_t step = (hi - lo + 63) / 64;
+    const uint32_t pos = lo + l * step;
+    const bool le = pos < hi && pref[pos] <= target;
+    const uint64_t bal = ballot64(le);
+    const uint32_t last = 63u - (uint32_t)__clzll((long long)bal);
+    lo = lo + last * step;
+    hi = min(hi, lo + step);
+  }
+  return lo;
+}
+
+struct EmitSlot {
+  uint32_t s, gbase;
+  int x0, y0, rw;
+};
+
+__device__ __forceinline__ EmitSlot emit_slot(uint32_t s, const uint32_t* __restrict__ slot_view,
+                                              const int4* __restrict__ slot_pix, int tile_w, int tile_h,
+                                              int tiles_x, uint32_t tiles_per_view) {
+  const int4 pix = slot_pix[s];
+  EmitSlot e;
+  e.s = s;
+  e.x0 = max(floordiv_i(pix.x - pix.z, tile_w), 0);
+  const int x1 = min(floordiv_i(pix.x + pix.z, tile_w) + 1, tiles_x);
+  e.y0 = max(floordiv_i(pix.y - pix.w, tile_h), 0);
+  e.rw = max(x1 - e.x0, 1);
+  e.gbase = slot_view[s] * tiles_per_view;
+  return e;
+}
+
 __global__ __launch_bounds__(256) void k_emit_pairs(const uint32_t* __restrict__ counters,
                                                     const uint32_t* __restrict__ perm,
-                                                    const uint32_t* __restrict__ part, uint32_t n_groups,
+                                                    const uint32_t* __restrict__ pref,
                                                     const uint32_t* __restrict__ slot_view,
-                                                    const int4* __restrict__ slot_pix,
-                                                    const uint32_t* __restrict__ slot_ntiles, int tile_w, int tile_h,
-                                                    int tiles_x, int tiles_y, uint64_t pair_cap,
-                                                    uint32_t* __restrict__ slot_pairoff, uint32_t* __restrict__ keys,
+                                                    const int4* __restrict__ slot_pix, int tile_w, int tile_h,
+                                                    int tiles_x, int tiles_y, uint32_t* __restrict__ keys,
                                                     uint32_t* __restrict__ vals) {
-  const uint32_t n = counters[0];
-  const int l = threadIdx.x & 63;
-  const uint32_t waves = gridDim.x * 4;
+  __shared__ uint32_t s_pref[EP_CHUNK + 1];
+  __shared__ uint32_t s_j[2];
+  const uint32_t n = counters[0], np = counters[1];
+  const int tid = threadIdx.x;
   const uint32_t tiles_per_view = (uint32_t)(tiles_x * tiles_y);
-  for (uint32_t g = blockIdx.x * 4 + (threadIdx.x >> 6); g < n_groups; g += waves) {
-    const uint32_t j = g * 64 + (uint32_t)l;
-    if (g * 64 >= n) break;
-    const uint32_t s = j < n ? perm[j] : 0u;
-    const uint32_t c = j < n ? slot_ntiles[s] : 0u;
-    const uint32_t incl = wave_inclusive_scan(c);
-    const uint32_t excl = incl - c;
-    const uint32_t tot = (uint32_t)__shfl((int)incl, 63, 64);
-    const uint32_t rbase = part[g];
-    if ((uint64_t)rbase + tot > pair_cap) continue;
-    int x0 = 0, y0 = 0, rw = 1, ok = 0;
-    uint32_t gbase = 0;
-    if (c > 0) {
-      const int4 pix = slot_pix[s];
-      x0 = max(floordiv_i(pix.x - pix.z, tile_w), 0);
-      const int x1 = min(floordiv_i(pix.x + pix.z, tile_w) + 1, tiles_x);
-      y0 = max(floordiv_i(pix.y - pix.w, tile_h), 0);
-      rw = max(x1 - x0, 1);
-      ok = x1 > x0;
-      gbase = slot_view[s] * tiles_per_view;
-      slot_pairoff[s] = rbase + excl;
+  for (uint64_t P0 = (uint64_t)blockIdx.x * EP_CHUNK; P0 < np; P0 += (uint64_t)gridDim.x * EP_CHUNK) {
+    const uint32_t p0 = (uint32_t)P0;
+    const uint32_t p1 = (uint32_t)min<uint64_t>(P0 + EP_CHUNK, np) - 1u;
+    if (tid < 128) {
+      const uint32_t j = wave_search_last_le(pref, n, tid < 64 ? p0 : p1);
+      if ((tid & 63) == 0) s_j[tid >> 6] = j;
     }
-    // wave-uniform loop: every lane takes part in the shuffles (a shuffle
-    // from a lane that has left the loop would read an undefined value)
-    for (uint32_t kb = 0; kb < tot; kb += 64) {
-      const uint32_t k = kb + (uint32_t)l;
-      int lo = 0, hi = 63;
+    __syncthreads();
+    const uint32_t jlo = s_j[0];
+    // every record in [jlo, jhi] owns a pair of the chunk, so there are at
+    // most EP_CHUNK of them; the clamp only keeps LDS in bounds
+    const uint32_t cnt = min(s_j[1] - jlo + 1u, (uint32_t)EP_CHUNK);
+    for (uint32_t k = tid; k < cnt; k += 256) s_pref[k] = pref[jlo + k];
+    if (tid == 0) s_pref[cnt] = 0xffffffffu;
+    __syncthreads();
+    const uint32_t pa = p0 + (uint32_t)tid * EP_PPT;
+    if (pa <= p1) {
+      uint32_t a = 0, b = cnt;
+      while (b - a > 1) {
+        const uint32_t mid = (a + b) >> 1;
+        if (s_pref[mid] <= pa) a = mid; else b = mid;
+      }
+      uint32_t jj = a, first = s_pref[jj], next = s_pref[jj + 1];
+      EmitSlot e = emit_slot(perm[jlo + jj], slot_view, slot_pix, tile_w, tile_h, tiles_x, tiles_per_view);
+      uint32_t ko[EP_PPT], vo[EP_PPT];
 #pragma unroll
-      for (int step = 0; step < 6; ++step) {
-        const int mid = (lo + hi) >> 1;
-        const uint32_t im = (uint32_t)__shfl((int)incl, mid, 64);
-        if (im > k) hi = mid; else lo = mid + 1;
+      for (int i = 0; i < EP_PPT; ++i) {
+        const uint32_t p = pa + (uint32_t)i;
+        ko[i] = 0xffffffffu;
+        vo[i] = 0u;
+        if (p <= p1) {
+          if (p >= next) {
+            while (p >= next) {
+              ++jj;
+              first = next;
+              next = s_pref[jj + 1];
+            }
+            e = emit_slot(perm[jlo + jj], slot_view, slot_pix, tile_w, tile_h, tiles_x, tiles_per_view);
+          }
+          const uint32_t rk = p - first;
+          const uint32_t qy = udiv_small(rk, (uint32_t)e.rw);
+          const int ty = e.y0 + (int)qy, tx = e.x0 + (int)(rk - qy * (uint32_t)e.rw);
+          ko[i] = ty < tiles_y ? e.gbase + (uint32_t)(ty * tiles_x + tx) : 0xffffffffu;
+          vo[i] = e.s;
+        }
       }
-      const int o = lo;
-      const uint32_t oexcl = (uint32_t)__shfl((int)excl, o, 64);
-      const int ox0 = __shfl(x0, o, 64), oy0 = __shfl(y0, o, 64), orw = __shfl(rw, o, 64), ook = __shfl(ok, o, 64);
-      const uint32_t ogb = (uint32_t)__shfl((int)gbase, o, 64), os = (uint32_t)__shfl((int)s, o, 64);
-      if (k < tot) {
-        const uint32_t rk = k - oexcl;
-        const uint32_t qy = udiv_small(rk, (uint32_t)orw);
-        const int ty = oy0 + (int)qy, tx = ox0 + (int)(rk - qy * (uint32_t)orw);
-        const uint32_t p = rbase + k;
-        keys[p] = (ook && ty < tiles_y) ? ogb + (uint32_t)(ty * tiles_x + tx) : 0xffffffffu;
-        vals[p] = os;
+      if (pa + EP_PPT - 1 <= p1) {
+        uint4* k4 = reinterpret_cast<uint4*>(keys + pa);
+        uint4* v4 = reinterpret_cast<uint4*>(vals + pa);
+        k4[0] = make_uint4(ko[0], ko[1], ko[2], ko[3]);
+        k4[1] = make_uint4(ko[4], ko[5], ko[6], ko[7]);
+        v4[0] = make_uint4(vo[0], vo[1], vo[2], vo[3]);
+        v4[1] = make_uint4(vo[4], vo[5], vo[6], vo[7]);
+      } else {
+#pragma unroll
+        for (int i = 0; i < EP_PPT; ++i)
+          if (pa + (uint32_t)i <= p1) {
+            keys[pa + i] = ko[i];
+            vals[pa + i] = vo[i];
+          }
       }
     }
+    __syncthreads();
   }
 }
 
@@ -339,10 +433,15 @@ kgs_status kgs_launch_bin_sort(kgs_ctx* ctx, hipStream_t st) {
   hipLaunchKernelGGL(k_group_sum, dim3(eg), dim3(256), 0, st, (const uint32_t*)ctx->counters, perm,
                      (const uint32_t*)ctx->slot_ntiles, n_groups, ctx->scan_part);
   hipLaunchKernelGGL(k_scan_mid, dim3(1), dim3(1024), 0, st, n_groups, ctx->scan_part);
-  hipLaunchKernelGGL(k_emit_pairs, dim3(eg), dim3(256), 0, st, (const uint32_t*)ctx->counters, perm,
-                     (const uint32_t*)ctx->scan_part, n_groups, (const uint32_t*)ctx->slot_view,
-                     (const int4*)ctx->slot_pix, (const uint32_t*)ctx->slot_ntiles, ctx->cfg.tile_w, ctx->cfg.tile_h,
-                     ctx->tiles_x, ctx->tiles_y, P, ctx->slot_pairoff, ctx->keys[0], ctx->vals[0]);
+  uint32_t* pref = reinterpret_cast<uint32_t*>(ctx->slot_keys[sc ^ 1]);  // free after the record sort
+  hipLaunchKernelGGL(k_slot_offsets, dim3(eg), dim3(256), 0, st, (const uint32_t*)ctx->counters, perm,
+                     (const uint32_t*)ctx->scan_part, n_groups, (const uint32_t*)ctx->slot_ntiles, P, pref,
+                     ctx->slot_pairoff);
+  const uint64_t chunks = (P + EP_CHUNK - 1) / EP_CHUNK;
+  const unsigned pg = (unsigned)std::min<uint64_t>(std::max<uint64_t>(chunks, 1), 4096);
+  hipLaunchKernelGGL(k_emit_pairs, dim3(pg), dim3(256), 0, st, (const uint32_t*)ctx->counters, perm,
+                     (const uint32_t*)pref, (const uint32_t*)ctx->slot_view, (const int4*)ctx->slot_pix,
+                     ctx->cfg.tile_w, ctx->cfg.tile_h, ctx->tiles_x, ctx->tiles_y, ctx->keys[0], ctx->vals[0]);
   // 3. pairs by tile (stable)
   // padding pairs carry key 0xffffffff; with n_tiles_all < 2^tile_bits they
   // sort after every real pair
