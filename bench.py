@@ -45,9 +45,10 @@ def kernel_source_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def read_traffic():
+def read_traffic(tile, batch):
     """Per-launch HBM bytes of the compositing backward from the committed
-    rocprofv3 counter summary; None if absent or taken on other kernel source."""
+    rocprofv3 counter summary; None if absent, taken on other kernel source or
+    on another tile shape / LDS batch than the one timed."""
     path = os.path.join(ROOT, "profiles", "k_render_bwd_2M_8view_chunk_counters.txt")
     if not os.path.exists(path):
         return None
@@ -57,6 +58,8 @@ def read_traffic():
             k, v = line.split("=", 1)
             vals[k.strip()] = v.strip()
     if vals.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    if vals.get("tile") != f"{tile[0]}x{tile[1]}" or vals.get("batch") != str(batch):
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])
@@ -223,7 +226,7 @@ def main():
     flop = FLOP_TEST * E + FLOP_BLEND * E_b
     t_bwd = stage_ms["render_bwd_pixels"] / 1e3
     achieved = flop / t_bwd / 1e12
-    traffic = read_traffic()
+    traffic = read_traffic(best[0], best[1])
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_ALU_TFLOPS, 2),
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_ALU_TFLOPS, 4), "traffic": traffic,
                 "kernel": "k_render_bwd (compositing backward)", "evaluations": E, "blended": E_b,

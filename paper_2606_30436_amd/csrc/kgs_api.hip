@@ -74,12 +74,19 @@ size_t layout(const kgs_config& c, char* base, kgs_ctx* ctx) {
   p = take(8 * S);                              if (ctx) ctx->slot_keys[1] = (uint64_t*)p;
   p = take(4 * S);                              if (ctx) ctx->slot_vals[0] = (uint32_t*)p;
   p = take(4 * S);                              if (ctx) ctx->slot_vals[1] = (uint32_t*)p;
-  p = take(4 * (S / 64 + 2));                   if (ctx) ctx->scan_part = (uint32_t*)p;
+  p = take(4 * (S / 64 + 2));                   if (ctx) ctx->group_part = (uint32_t*)p;
   p = take(8 * V * T);                          if (ctx) ctx->ranges = (uint2*)p;
   p = take(48 * P);                             if (ctx) ctx->pair_grad = (float4*)p;
   p = take(4 * 256 * KGS_SORT_BLOCKS * 4);      if (ctx) ctx->radix_hist = (uint32_t*)p;
   p = take(4 * 256 * KGS_MAX_PASSES);           if (ctx) ctx->radix_total = (uint32_t*)p;
   p = take(4 * KGS_SLOT_WORDS * S);             if (ctx) ctx->slot_bwd = (float4*)p;
+  p = take(4 * S);                              if (ctx) ctx->big_list = (uint32_t*)p;
+  p = take(24 * S);                             if (ctx) ctx->slot_pose = (float2*)p;
+  {
+    const int64_t st = std::max(kgs_scan_tiles(V * nb), kgs_scan_tiles(S / 64 + 2)) + 1;
+    p = take(16 * st);                          if (ctx) ctx->scan_part = (unsigned long long*)p;
+    p = take(16);                               if (ctx) ctx->scan_totals = (unsigned long long*)p;
+  }
   p = take(48 * V * KGS_POSE_BLOCKS);           if (ctx) ctx->pose_partial = (double*)p;
   p = take(8 * V * KGS_LOSS_BLOCKS);            if (ctx) ctx->loss_partial = (double*)p;
   p = take(16 * (nb + 1));                      if (ctx) ctx->mm_partial = (double*)p;

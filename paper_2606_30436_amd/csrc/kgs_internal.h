@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "../../include/kgs.h"
 
 #define KGS_BLOCK 256                 // threads per block for per-Gaussian / per-tile kernels
@@ -14,6 +16,8 @@
 #define KGS_MAX_PASSES 8
 #define KGS_POSE_BLOCKS 32            // pieces per view of the pose reduction
 #define KGS_SLOT_WORDS 40             // words of a slot's backward record
+#define KGS_SMALL_SLOT 8              // pair count up to which one lane sums a slot's pairs
+#define KGS_CNT_BIG 4                 // counters[] word: number of queued large slots
 
 // ---------------------------------------------------------------- device camera
 // Pose already applied.  The camera point of a Gaussian is R' mu + t' in
@@ -47,7 +51,7 @@ struct kgs_ctx {
   int64_t nb_max;                     // blocks of 256 over max_gaussians
   // workspace carve-out
   CamDev* cams;                       // [max_views]
-  uint32_t* vis;                      // [max_views][max_gaussians] tiles touched (0: culled)
+  uint32_t* vis;                      // [V][N] tile count after counting; slot index + 1 (0: none) after emission
   uint32_t* blk_cnt;                  // [max_views][nb][2] visible count, tile count
   uint32_t* blk_base;                 // [max_views][nb][2] exclusive bases
   uint32_t* counters;                 // [64]: 0 n_slots, 1 n_pairs, 2 status, 3.. scratch
@@ -61,13 +65,17 @@ struct kgs_ctx {
   uint32_t* vals[2];                  // [P] ping-pong (pair emission position)
   uint64_t* slot_keys[2];             // [S] ping-pong: (view << 32) | depth bits
   uint32_t* slot_vals[2];             // [S] ping-pong: slot index
-  uint32_t* scan_part;                // [S / 64 + 2] group partials of the pair-offset scan
+  uint32_t* group_part;               // [S / 64 + 2] group partials of the pair-offset scan
   uint32_t* sorted_slot;              // [P] slot of each sorted pair (the sort's value buffer)
   uint2* ranges;                      // [max_views * max_tiles]
   float4* pair_grad;                  // [P][3] per-pair record-space gradients + counts
   uint32_t* radix_hist;               // [256][KGS_SORT_BLOCKS * 4] per-wave partitions
   uint32_t* radix_total;              // [KGS_MAX_PASSES][256]
   float4* slot_bwd;                   // [S][KGS_SLOT_WORDS / 4] per-slot backward records
+  uint32_t* big_list;                 // [S] slots whose pairs are summed by a whole wave
+  float2* slot_pose;                  // [S][3] pose contributions (rho, phi) of every slot
+  unsigned long long* scan_part;      // tile sums of the device-wide scans
+  unsigned long long* scan_totals;    // [2] their totals
   double* pose_partial;               // [max_views][KGS_POSE_BLOCKS][6]
   double* loss_partial;               // [max_views][KGS_LOSS_BLOCKS]
   double* mm_partial;                 // [nb][2]
@@ -78,6 +86,7 @@ struct kgs_ctx {
   int last_degree;
   int passes;
   int sorted_buf;                     // which ping-pong buffer holds the sorted pairs
+  const uint32_t* perm;               // slots in (view, depth) order, from the last bin_sort
   int projected, binned;
   int proj_tile_w, proj_tile_h;
 };
@@ -421,3 +430,10 @@ __device__ __forceinline__ void tile_subblock(int tile_w, int w, int& sx, int& s
 
 // Host-side kernel launch helpers (defined in kgs_api.hip).
 kgs_status kgs_check_launch();
+
+// Device-wide exclusive scan (kgs_scan.hip): W (1 or 2) interleaved u32 values
+// per entry, u64 accumulation, outputs clamped at cap0 / cap1; in may equal
+// out.  part needs W * kgs_scan_tiles(entries) u64, totals W u64.
+int64_t kgs_scan_tiles(int64_t entries);
+void kgs_launch_scan(const uint32_t* in, uint32_t* out, int64_t entries, int W, unsigned long long cap0,
+                     unsigned long long cap1, unsigned long long* part, unsigned long long* totals, hipStream_t st);

@@ -151,64 +151,19 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_count(kgs_gaussians g, const CamD
 }
 
 // ---------------------------------------------------------------- block scan
-// Exclusive scan of the (visible, tiles) pairs of all (view, block) entries in
-// (view, block) order.  One block of 1024 threads walks the array in rounds of
-// 4096 entries (each thread four consecutive entries, so loads and stores are
-// coalesced), carrying the running totals.  Bases saturate at the capacities;
-// totals are written clamped, overflow raises a status bit.
-__global__ __launch_bounds__(1024) void k_scan_blocks(const uint32_t* __restrict__ blk_cnt,
-                                                      uint32_t* __restrict__ blk_base, int64_t entries,
-                                                      uint64_t slot_cap, uint64_t pair_cap,
-                                                      uint32_t* __restrict__ counters) {
-  constexpr int E = 4;
-  __shared__ unsigned long long sa[16], sb[16];
-  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
-  unsigned long long ca = 0, cb = 0;
-  for (int64_t base = 0; base < entries; base += 1024 * E) {
-    const int64_t e0 = base + (int64_t)tid * E;
-    uint32_t va[E], vb[E];
-    unsigned long long a = 0, b = 0;
-#pragma unroll
-    for (int k = 0; k < E; ++k) {
-      const bool in = e0 + k < entries;
-      va[k] = in ? blk_cnt[2 * (e0 + k)] : 0u;
-      vb[k] = in ? blk_cnt[2 * (e0 + k) + 1] : 0u;
-      a += va[k];
-      b += vb[k];
-    }
-    const unsigned long long ia = wave_inclusive_scan(a), ib = wave_inclusive_scan(b);
-    if (l == 63) { sa[w] = ia; sb[w] = ib; }
-    __syncthreads();
-    unsigned long long oa = ca, ob = cb, ta = 0, tb = 0;
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      if (k < w) { oa += sa[k]; ob += sb[k]; }
-      ta += sa[k];
-      tb += sb[k];
-    }
-    unsigned long long ra = oa + ia - a, rb = ob + ib - b;
-#pragma unroll
-    for (int k = 0; k < E; ++k) {
-      if (e0 + k < entries) {
-        blk_base[2 * (e0 + k)] = (uint32_t)min(ra, (unsigned long long)slot_cap);
-        blk_base[2 * (e0 + k) + 1] = (uint32_t)min(rb, (unsigned long long)pair_cap);
-      }
-      ra += va[k];
-      rb += vb[k];
-    }
-    ca += ta;
-    cb += tb;
-    __syncthreads();
-  }
-  if (tid == 0) {
-    uint32_t f = 0;
-    if (ca > slot_cap) f |= KGS_FLAG_SLOT_OVERFLOW;
-    if (cb > pair_cap) f |= KGS_FLAG_PAIR_OVERFLOW;
-    // on overflow every later stage sees zero records and zero pairs
-    counters[0] = f ? 0u : (uint32_t)ca;
-    counters[1] = f ? 0u : (uint32_t)cb;
-    if (f) atomicOr(&counters[2], f);
-  }
+// The (visible, tiles) pairs of all (view, block) entries are scanned in
+// (view, block) order by the device-wide scan (bases saturate at the
+// capacities); this sets the record and pair totals, or on overflow zero
+// totals and a status bit, so that every later stage sees nothing.
+__global__ void k_scan_finish(const unsigned long long* __restrict__ totals, uint64_t slot_cap, uint64_t pair_cap,
+                              uint32_t* __restrict__ counters) {
+  const unsigned long long ta = totals[0], tb = totals[1];
+  uint32_t f = 0;
+  if (ta > slot_cap) f |= KGS_FLAG_SLOT_OVERFLOW;
+  if (tb > pair_cap) f |= KGS_FLAG_PAIR_OVERFLOW;
+  counters[0] = f ? 0u : (uint32_t)ta;
+  counters[1] = f ? 0u : (uint32_t)tb;
+  if (f) atomicOr(&counters[2], f);
 }
 
 // ---------------------------------------------------------------- emission
@@ -222,7 +177,7 @@ __device__ __forceinline__ float pack_bounds(int lo, int hi) {
 
 template <int DEG>
 __global__ __launch_bounds__(KGS_BLOCK) void k_emit(kgs_gaussians g, const CamDev* __restrict__ cams, int V,
-                                                    ProjParams P, const uint32_t* __restrict__ vis,
+                                                    ProjParams P, uint32_t* __restrict__ vis,
                                                     const uint32_t* __restrict__ blk_base, int64_t nb,
                                                     uint64_t slot_cap, uint64_t pair_cap,
                                                     float4* __restrict__ slot_rec, uint32_t* __restrict__ slot_gid,
@@ -247,6 +202,8 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_emit(kgs_gaussians g, const CamDe
     const int64_t e = ((int64_t)v * nb + blockIdx.x) * 2;
     const uint64_t s = (uint64_t)blk_base[e] + ea;
     const uint64_t po = (uint64_t)blk_base[e + 1] + eb;
+    // from here on vis[v][i] names the slot (index + 1), for the backward gather
+    vis[(int64_t)v * g.n + i] = s < slot_cap ? (uint32_t)(s + 1) : 0u;
     if (s >= slot_cap) continue;
     if (po + tiles > pair_cap) {
       // over the pair capacity: the slot exists but emits nothing
@@ -320,12 +277,14 @@ kgs_status kgs_launch_project(kgs_ctx* ctx, const kgs_gaussians* g, const kgs_ca
   if (nb > 0)
     hipLaunchKernelGGL(k_count, dim3((unsigned)nb), dim3(KGS_BLOCK), 0, st, *g, (const CamDev*)ctx->cams, V, P,
                        ctx->vis, ctx->blk_cnt, nb, ctx->counters + 2);
-  hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, st, (const uint32_t*)ctx->blk_cnt, ctx->blk_base,
-                     (int64_t)V * nb, (uint64_t)cfg.slot_capacity, (uint64_t)cfg.pair_capacity, ctx->counters);
+  kgs_launch_scan(ctx->blk_cnt, ctx->blk_base, (int64_t)V * nb, 2, (unsigned long long)cfg.slot_capacity,
+                  (unsigned long long)cfg.pair_capacity, ctx->scan_part, ctx->scan_totals, st);
+  hipLaunchKernelGGL(k_scan_finish, dim3(1), dim3(1), 0, st, (const unsigned long long*)ctx->scan_totals,
+                     (uint64_t)cfg.slot_capacity, (uint64_t)cfg.pair_capacity, ctx->counters);
   if (nb > 0) {
 #define KGS_EMIT(D)                                                                                              \
   hipLaunchKernelGGL(k_emit<D>, dim3((unsigned)nb), dim3(KGS_BLOCK), 0, st, *g, (const CamDev*)ctx->cams, V, P,   \
-                     (const uint32_t*)ctx->vis, (const uint32_t*)ctx->blk_base, nb, (uint64_t)cfg.slot_capacity,  \
+                     ctx->vis, (const uint32_t*)ctx->blk_base, nb, (uint64_t)cfg.slot_capacity,  \
                      (uint64_t)cfg.pair_capacity, ctx->slot_rec, ctx->slot_gid, ctx->slot_view, ctx->slot_pix,    \
                      ctx->slot_pairoff, ctx->slot_ntiles)
     switch (g->sh_degree) {

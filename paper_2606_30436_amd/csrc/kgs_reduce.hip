@@ -1,13 +1,12 @@
 // Backward of the projection, deterministic throughout:
-//   k_proj_bwd      per block of 256 Gaussians: (1) every (view, Gaussian)
-//                   record of the block -- the segmented sum of its pairs'
-//                   gradients (contiguous in emission order), the chain rule to
-//                   the Gaussian's parameters and to the view's pose, the view's
-//                   footprint statistics -- as one 160-byte record per slot;
-//                   (2) per Gaussian, the sum of its records over the views in
-//                   view order (the block-local scan of the visibility counts
-//                   recovers each slot index, as in the emission), added into
-//                   the gradients and statistics.
+//   k_pair_sum_*    per slot, the sum of its pairs' gradient records (they
+//                   are contiguous in emission order);
+//   k_slot_bwd      per slot, from its pair sum, the chain rule to the
+//                   Gaussian's parameters and to the view's pose, and the
+//                   view's footprint statistics, as one 160-byte record;
+//   k_gauss_gather  per Gaussian, the sum of its records over the views in
+//                   view order (the emission left each (view, Gaussian) slot
+//                   index in vis), added into the gradients and statistics;
 //   k_pose_reduce   per view, the pose contributions of its slots (contiguous,
 //                   slots are in (view, Gaussian) order) in a fixed tree.
 // Views are summed in view order, so a batched call and a per-view loop give
@@ -28,18 +27,151 @@ struct BwdParams {
 // 10 dL/dlogit, 11-16 pose (rho, phi), 17 |Omega| (u32), 18 kappa (u32),
 // 19 ||dL/dmu2D||, 20 pixel radius (i32), 21-23 dL/dcolour where the colour is
 // not clamped (0 where it is), 24-39 the SH basis at the view direction.
-// Sum of the 12-word pair records [po, po + tiles): 10 record-space gradient
-// terms and the two footprint counts.
-__device__ __forceinline__ void pair_sum_serial(const float4* __restrict__ pair_grad, uint32_t po, uint32_t tiles,
-                                                float r[10], uint32_t& om, uint32_t& kap) {
-  for (uint32_t k = 0; k < tiles; ++k) {
-    const float4 a = pair_grad[((size_t)po + k) * 3], b = pair_grad[((size_t)po + k) * 3 + 1],
-                 cc = pair_grad[((size_t)po + k) * 3 + 2];
-    r[0] += a.x; r[1] += a.y; r[2] += a.z; r[3] += a.w;
-    r[4] += b.x; r[5] += b.y; r[6] += b.z; r[7] += b.w;
-    r[8] += cc.x; r[9] += cc.y;
-    om += __float_as_uint(cc.z);
-    kap += __float_as_uint(cc.w);
+// ---------------------------------------------------------------- pair sums
+// Per-slot sums of the 12-word pair records [po, po + tiles) (10 record-space
+// gradient terms and the two footprint counts), written into words 0-11 of the
+// slot's backward record.  A slot of up to KGS_SMALL_SLOT pairs is summed by
+// one lane in pair order, four pairs in flight; a larger one is queued and
+// summed by a whole wave (lane-strided partial sums, then a fixed butterfly).
+// Either way the order depends only on the slot's pair count, never on
+// scheduling.
+__device__ __forceinline__ void add_pair(const float4& a, const float4& b, const float4& c, float r[10], uint32_t& om,
+                                         uint32_t& kap) {
+  r[0] += a.x; r[1] += a.y; r[2] += a.z; r[3] += a.w;
+  r[4] += b.x; r[5] += b.y; r[6] += b.z; r[7] += b.w;
+  r[8] += c.x; r[9] += c.y;
+  om += __float_as_uint(c.z);
+  kap += __float_as_uint(c.w);
+}
+
+__device__ __forceinline__ void store_sum(float4* __restrict__ rec, const float r[10], uint32_t om, uint32_t kap) {
+  rec[0] = make_float4(r[0], r[1], r[2], r[3]);
+  rec[1] = make_float4(r[4], r[5], r[6], r[7]);
+  rec[2] = make_float4(r[8], r[9], __uint_as_float(om), __uint_as_float(kap));
+}
+
+__global__ void k_zero_word(uint32_t* __restrict__ w) { *w = 0u; }
+
+__global__ __launch_bounds__(256) void k_pair_sum_small(uint32_t* __restrict__ counters,
+                                                        const uint32_t* __restrict__ perm,
+                                                        const uint32_t* __restrict__ slot_pairoff,
+                                                        const uint32_t* __restrict__ slot_ntiles,
+                                                        const float4* __restrict__ pair_grad,
+                                                        float4* __restrict__ slot_bwd, uint32_t* __restrict__ big_list) {
+  __shared__ uint32_t s_wcnt[4], s_base;
+  const uint32_t n = counters[0];
+  const int l = threadIdx.x & 63;
+  // records are walked in depth order, whose pairs are contiguous in memory,
+  // so neighbouring lanes read neighbouring pair records
+  for (uint32_t j0 = blockIdx.x * 256u; j0 < n; j0 += gridDim.x * 256u) {
+    const uint32_t j = j0 + threadIdx.x;
+    const bool act = j < n;
+    const uint32_t s = act ? perm[j] : 0u;
+    const uint32_t t = act ? slot_ntiles[s] : 0u;
+    const bool big = t > KGS_SMALL_SLOT;
+    // queue the large slots: one reservation per block (a single counter
+    // taking one atomic per wave is a serialisation point)
+    const uint64_t bal = ballot64(big);
+    const int w = threadIdx.x >> 6;
+    if (l == 0) s_wcnt[w] = (uint32_t)__popcll(bal);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const uint32_t tot = s_wcnt[0] + s_wcnt[1] + s_wcnt[2] + s_wcnt[3];
+      s_base = tot ? atomicAdd(&counters[KGS_CNT_BIG], tot) : 0u;
+    }
+    __syncthreads();
+    if (big) {
+      uint32_t off = s_base + mask_lt_count(bal);
+      for (int k = 0; k < w; ++k) off += s_wcnt[k];
+      big_list[off] = s;
+    }
+    __syncthreads();
+    if (!act || big) continue;
+    const float4* pg = pair_grad + (size_t)slot_pairoff[s] * 3;
+    float r[10] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    uint32_t om = 0, kap = 0;
+    for (uint32_t k = 0; k < t; k += 4) {
+      float4 q[4][3];
+#pragma unroll
+      for (uint32_t i = 0; i < 4; ++i) {
+        const bool in = k + i < t;
+        const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+        q[i][0] = in ? pg[(k + i) * 3] : z;
+        q[i][1] = in ? pg[(k + i) * 3 + 1] : z;
+        q[i][2] = in ? pg[(k + i) * 3 + 2] : z;
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) add_pair(q[i][0], q[i][1], q[i][2], r, om, kap);
+    }
+    store_sum(slot_bwd + (size_t)s * (KGS_SLOT_WORDS / 4), r, om, kap);
+  }
+}
+
+__device__ __forceinline__ float swap_sum32(float lo_keep, float hi_keep) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(lo_keep), __float_as_uint(hi_keep), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+__device__ __forceinline__ float swap_sum16(float even_keep, float odd_keep) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(even_keep), __float_as_uint(odd_keep), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+
+// Reduce-scatter of twelve per-lane values over the wave (lane halves, row
+// pairs, mirrored lanes of a row, of a half-row, then the quad): afterwards a
+// lane with valid set holds the wave sum of value idx.
+__device__ __forceinline__ void wave_reduce12(float (&x)[12], int lane, int& idx, bool& valid) {
+  const bool u3 = lane & 8, u2 = lane & 4;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) x[k] = swap_sum32(x[k], x[k + 6]);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) x[k] = swap_sum16(x[k], x[k + 3]);
+  {
+    const float s0 = u3 ? x[0] : x[2], k0 = u3 ? x[2] : x[0];
+    const float s1 = u3 ? x[1] : 0.f, k1 = u3 ? 0.f : x[1];
+    x[0] = k0 + dpp_f<0x140>(s0);
+    x[1] = k1 + dpp_f<0x140>(s1);
+  }
+  {
+    const float s0 = u2 ? x[0] : x[1], k0 = u2 ? x[1] : x[0];
+    x[0] = k0 + dpp_f<0x141>(s0);
+  }
+  x[0] += dpp_f<0xB1>(x[0]);
+  x[0] += dpp_f<0x4E>(x[0]);
+  const int k = (u3 ? 2 : 0) + (u2 ? 1 : 0);
+  valid = k < 3 && (lane & 3) == 0;
+  idx = ((lane & 32) ? 6 : 0) + ((lane & 16) ? 3 : 0) + k;
+}
+
+__global__ __launch_bounds__(256) void k_pair_sum_big(const uint32_t* __restrict__ counters,
+                                                      const uint32_t* __restrict__ big_list,
+                                                      const uint32_t* __restrict__ slot_pairoff,
+                                                      const uint32_t* __restrict__ slot_ntiles,
+                                                      const float4* __restrict__ pair_grad,
+                                                      float4* __restrict__ slot_bwd) {
+  const uint32_t nbig = counters[KGS_CNT_BIG];
+  const int l = threadIdx.x & 63;
+  for (uint32_t q = blockIdx.x * 4 + (threadIdx.x >> 6); q < nbig; q += gridDim.x * 4) {
+    const uint32_t s = big_list[q];
+    const uint32_t t = slot_ntiles[s];
+    const float4* pg = pair_grad + (size_t)slot_pairoff[s] * 3;
+    float r[10] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    uint32_t om = 0, kap = 0;
+    for (uint32_t k = (uint32_t)l; k < t; k += 64) add_pair(pg[k * 3], pg[k * 3 + 1], pg[k * 3 + 2], r, om, kap);
+    // counts stay below 2^24, so they travel through the float reduction exactly
+    float x[12] = {r[0], r[1], r[2], r[3], r[4], r[5], r[6], r[7], r[8], r[9], (float)om, (float)kap};
+    int idx;
+    bool valid;
+    wave_reduce12(x, l, idx, valid);
+    if (valid) {
+      float* rec = reinterpret_cast<float*>(slot_bwd + (size_t)s * (KGS_SLOT_WORDS / 4));
+      rec[idx] = idx < 10 ? x[0] : __uint_as_float((uint32_t)x[0]);
+    }
   }
 }
 
@@ -48,7 +180,8 @@ __device__ __forceinline__ void slot_record(uint32_t s, const kgs_gaussians& g, 
                                             const BwdParams& P, const uint32_t* __restrict__ slot_gid,
                                             const uint32_t* __restrict__ slot_view,
                                             const uint32_t* __restrict__ slot_ntiles, const float r[10],
-                                            uint32_t om, uint32_t kap, float4* __restrict__ slot_bwd) {
+                                            uint32_t om, uint32_t kap, float4* __restrict__ slot_bwd,
+                                            float2* __restrict__ slot_pose) {
   constexpr int K = (DEG + 1) * (DEG + 1);
   const int64_t n = g.n;
   const float h = 0.5f * 1.4426950408889634f;
@@ -238,86 +371,46 @@ __device__ __forceinline__ void slot_record(uint32_t s, const kgs_gaussians& g, 
 #pragma unroll
     for (int k = 0; k < KGS_SLOT_WORDS / 4; ++k)
       o4[k] = make_float4(out[4 * k], out[4 * k + 1], out[4 * k + 2], out[4 * k + 3]);
+    // the pose contributions again, packed, for the per-view reduction
+    float2* p2 = slot_pose + (size_t)s * 3;
+    p2[0] = make_float2(out[11], out[12]);
+    p2[1] = make_float2(out[13], out[14]);
+    p2[2] = make_float2(out[15], out[16]);
   }
 }
 
-// Fused projection backward of one block of 256 Gaussians.  Phase 1: the
-// records of all (view, Gaussian) slots of the block -- they are contiguous
-// per view and their count per view is the counting pass's block count -- are
-// spread over the 256 threads; each writes its slot's backward record (the
-// Gaussian's parameters are read by index from the block's small range, so
-// they stay in cache).  Phase 2: each thread sums its Gaussian's records in
-// view order and adds into the gradients and statistics.
+// Chain rule of every slot, one thread per slot: the pair sum (words 0-11 of
+// its record) becomes the full 160-byte backward record.
 template <int DEG>
-__global__ __launch_bounds__(KGS_BLOCK) void k_proj_bwd(
-    kgs_gaussians g, const CamDev* __restrict__ cams, int V, BwdParams P, const uint32_t* __restrict__ vis,
-    const uint32_t* __restrict__ blk_cnt, const uint32_t* __restrict__ blk_base, int64_t nb, uint64_t slot_cap,
-    const uint32_t* __restrict__ counters, const uint32_t* __restrict__ slot_gid,
-    const uint32_t* __restrict__ slot_view, const uint32_t* __restrict__ slot_pairoff,
-    const uint32_t* __restrict__ slot_ntiles, const float4* __restrict__ pair_grad, float4* __restrict__ slot_bwd,
-    const float* __restrict__ view_loss, kgs_grads gr, kgs_view_stats st) {
-  constexpr int K = (DEG + 1) * (DEG + 1);
-  __shared__ uint32_t scan_sh[16];
-  __shared__ uint32_t s_start[KGS_MAX_VIEWS + 1], s_base[KGS_MAX_VIEWS];
-  const int tid = threadIdx.x;
+__global__ __launch_bounds__(KGS_BLOCK) void k_slot_bwd(kgs_gaussians g, const CamDev* __restrict__ cams,
+                                                        BwdParams P, const uint32_t* __restrict__ counters,
+                                                        const uint32_t* __restrict__ slot_gid,
+                                                        const uint32_t* __restrict__ slot_view,
+                                                        const uint32_t* __restrict__ slot_ntiles,
+                                                        float4* __restrict__ slot_bwd,
+                                                        float2* __restrict__ slot_pose) {
   const uint32_t n_slots = counters[0];
-  // phase 1
-  if (tid < V) s_base[tid] = blk_base[((int64_t)tid * nb + blockIdx.x) * 2];
-  if (tid == 0) {
-    uint32_t a = 0;
-    for (int v = 0; v < V; ++v) {
-      s_start[v] = a;
-      a += blk_cnt[((int64_t)v * nb + blockIdx.x) * 2];
-    }
-    s_start[V] = a;
+  for (uint32_t s = blockIdx.x * KGS_BLOCK + threadIdx.x; s < n_slots; s += gridDim.x * KGS_BLOCK) {
+    const float4* q = slot_bwd + (size_t)s * (KGS_SLOT_WORDS / 4);
+    const float4 a = q[0], b = q[1], c = q[2];
+    const float r[10] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x, c.y};
+    slot_record<DEG>(s, g, cams, P, slot_gid, slot_view, slot_ntiles, r, __float_as_uint(c.z),
+                     __float_as_uint(c.w), slot_bwd, slot_pose);
   }
-  __syncthreads();
-  const uint32_t total = s_start[V];
-  const int w = tid >> 6, l = tid & 63;
-  for (uint32_t base = (uint32_t)w * 64; base < total; base += KGS_BLOCK) {
-    const uint32_t j = base + l;
-    uint32_t s = 0xffffffffu;
-    if (j < total) {
-      int v = 0;
-      while (v + 1 < V && s_start[v + 1] <= j) ++v;
-      s = s_base[v] + (j - s_start[v]);
-      if (s >= n_slots || s >= slot_cap) s = 0xffffffffu;
-    }
-    const bool act = s != 0xffffffffu;
-    const uint32_t tiles = act ? slot_ntiles[s] : 0u, po = act ? slot_pairoff[s] : 0u;
-    float r[10] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    uint32_t om = 0, kap = 0;
-    // a slot of up to 16 pairs is summed by its own lane; a larger one by the
-    // whole wave (lane-strided partial sums, then a fixed butterfly), so no
-    // lane walks a long list alone and the order never depends on scheduling
-    const bool big = tiles > 16u;
-    if (!big) pair_sum_serial(pair_grad, po, tiles, r, om, kap);
-    uint64_t bigs = ballot64(big);
-    while (bigs) {
-      const int b = __builtin_ctzll(bigs);
-      bigs &= bigs - 1ull;
-      const uint32_t bt = (uint32_t)__shfl((int)tiles, b, 64), bp = (uint32_t)__shfl((int)po, b, 64);
-      float q[10] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-      uint32_t qo = 0, qk = 0;
-      for (uint32_t k = (uint32_t)l; k < bt; k += 64) pair_sum_serial(pair_grad, bp + k, 1u, q, qo, qk);
-#pragma unroll
-      for (int m = 0; m < 10; ++m) q[m] = wave_sum(q[m]);
-      qo = wave_sum(qo);
-      qk = wave_sum(qk);
-      if (l == b) {
-#pragma unroll
-        for (int m = 0; m < 10; ++m) r[m] = q[m];
-        om = qo;
-        kap = qk;
-      }
-    }
-    if (act) slot_record<DEG>(s, g, cams, P, slot_gid, slot_view, slot_ntiles, r, om, kap, slot_bwd);
-  }
-  __syncthreads();
-  // phase 2
-  const int64_t i = (int64_t)blockIdx.x * KGS_BLOCK + tid;
-  const int64_t n = g.n;
-  const bool valid = i < n;
+}
+
+// Per Gaussian, the sum of its slot records over the views in view order
+// (vis names each view's slot), added into the gradients and statistics.
+template <int DEG>
+__global__ __launch_bounds__(KGS_BLOCK) void k_gauss_gather(int64_t n, int V, const uint32_t* __restrict__ vis,
+                                                            const uint32_t* __restrict__ counters,
+                                                            const float4* __restrict__ slot_bwd,
+                                                            const float* __restrict__ view_loss, kgs_grads gr,
+                                                            kgs_view_stats st) {
+  constexpr int K = (DEG + 1) * (DEG + 1);
+  const int64_t i = (int64_t)blockIdx.x * KGS_BLOCK + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t n_slots = counters[0];
   float acc[11];
 #pragma unroll
   for (int k = 0; k < 11; ++k) acc[k] = 0.f;
@@ -329,22 +422,12 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_proj_bwd(
   float s_gn = 0.f;
   int s_mr = 0;
   for (int v = 0; v < V; ++v) {
-    const uint32_t tiles = valid ? vis[(int64_t)v * n + i] : 0u;
-    const uint32_t flag = tiles > 0 ? 1u : 0u;
-    uint32_t ea, eb, ta, tb;
-    block_scan2(flag, 0u, scan_sh, ea, eb, ta, tb);
-    if (!flag) continue;
-    const uint64_t s = (uint64_t)blk_base[((int64_t)v * nb + blockIdx.x) * 2] + ea;
-    if (s >= slot_cap || s >= n_slots) continue;
-    const float4* r4 = slot_bwd + s * (KGS_SLOT_WORDS / 4);
+    const uint32_t u = vis[(int64_t)v * n + i];
+    if (u == 0u || u > n_slots) continue;
+    const float4* r4 = slot_bwd + (size_t)(u - 1u) * (KGS_SLOT_WORDS / 4);
     float r[KGS_SLOT_WORDS];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) {
-      const float4 q = r4[k];
-      r[4 * k] = q.x; r[4 * k + 1] = q.y; r[4 * k + 2] = q.z; r[4 * k + 3] = q.w;
-    }
-#pragma unroll
-    for (int k = 6; k < (24 + K + 3) / 4; ++k) {
+    for (int k = 0; k < (24 + K + 3) / 4; ++k) {
       const float4 q = r4[k];
       r[4 * k] = q.x; r[4 * k + 1] = q.y; r[4 * k + 2] = q.z; r[4 * k + 3] = q.w;
     }
@@ -364,7 +447,7 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_proj_bwd(
     s_vc += 1u;
     s_mr = max(s_mr, __float_as_int(r[20]));
   }
-  if (!valid || s_vc == 0) return;
+  if (s_vc == 0) return;
   if (gr.means)
     for (int k = 0; k < 3; ++k) gr.means[k * n + i] += acc[k];
   if (gr.log_scales)
@@ -388,7 +471,7 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_proj_bwd(
 // contiguous pieces, FP64, fixed reduction tree.
 __global__ __launch_bounds__(256) void k_pose_reduce(const uint32_t* __restrict__ counters,
                                                      const uint32_t* __restrict__ blk_base, int64_t nb, int V,
-                                                     const float4* __restrict__ slot_bwd,
+                                                     const float2* __restrict__ slot_pose,
                                                      double* __restrict__ partial) {
   __shared__ double sh[4][6];
   const int v = blockIdx.y, b = blockIdx.x, tid = threadIdx.x;
@@ -401,9 +484,9 @@ __global__ __launch_bounds__(256) void k_pose_reduce(const uint32_t* __restrict_
   const uint32_t a = lo + b * per, e = min(hi, a + per);
   double acc[6] = {0, 0, 0, 0, 0, 0};
   for (uint32_t s = a + tid; s < e; s += 256) {
-    const float4* r4 = slot_bwd + (size_t)s * (KGS_SLOT_WORDS / 4);
-    const float4 q2 = r4[2], q3 = r4[3], q4 = r4[4];
-    acc[0] += q2.w; acc[1] += q3.x; acc[2] += q3.y; acc[3] += q3.z; acc[4] += q3.w; acc[5] += q4.x;
+    const float2* p2 = slot_pose + (size_t)s * 3;
+    const float2 a = p2[0], b = p2[1], c = p2[2];
+    acc[0] += a.x; acc[1] += a.y; acc[2] += b.x; acc[3] += b.y; acc[4] += c.x; acc[5] += c.y;
   }
 #pragma unroll
   for (int k = 0; k < 6; ++k) {
@@ -452,12 +535,22 @@ kgs_status kgs_launch_project_bwd(kgs_ctx* ctx, const kgs_gaussians* g, const kg
   kgs_view_stats S = stats ? *stats : kgs_view_stats{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   const uint64_t cap = (uint64_t)cfg.slot_capacity;
   if (nb > 0) {
+    const unsigned sg = (unsigned)std::min<uint64_t>(std::max<uint64_t>((cap + 255) / 256, 1), 4096);
+    hipLaunchKernelGGL(k_zero_word, dim3(1), dim3(1), 0, st, ctx->counters + KGS_CNT_BIG);
+    hipLaunchKernelGGL(k_pair_sum_small, dim3(sg), dim3(256), 0, st, ctx->counters, ctx->perm,
+                       (const uint32_t*)ctx->slot_pairoff, (const uint32_t*)ctx->slot_ntiles,
+                       (const float4*)ctx->pair_grad, ctx->slot_bwd, ctx->big_list);
+    hipLaunchKernelGGL(k_pair_sum_big, dim3(2048), dim3(256), 0, st, (const uint32_t*)ctx->counters,
+                       (const uint32_t*)ctx->big_list, (const uint32_t*)ctx->slot_pairoff,
+                       (const uint32_t*)ctx->slot_ntiles, (const float4*)ctx->pair_grad, ctx->slot_bwd);
 #define KGS_PB(D)                                                                                                  \
-  hipLaunchKernelGGL(k_proj_bwd<D>, dim3((unsigned)nb), dim3(KGS_BLOCK), 0, st, *g, (const CamDev*)ctx->cams, V, P, \
-                     (const uint32_t*)ctx->vis, (const uint32_t*)ctx->blk_cnt, (const uint32_t*)ctx->blk_base, nb,  \
-                     cap, (const uint32_t*)ctx->counters, (const uint32_t*)ctx->slot_gid,                           \
-                     (const uint32_t*)ctx->slot_view, (const uint32_t*)ctx->slot_pairoff,                           \
-                     (const uint32_t*)ctx->slot_ntiles, (const float4*)ctx->pair_grad, ctx->slot_bwd, view_loss, G, S)
+  hipLaunchKernelGGL(k_slot_bwd<D>, dim3(sg), dim3(KGS_BLOCK), 0, st, *g, (const CamDev*)ctx->cams, P,             \
+                     (const uint32_t*)ctx->counters, (const uint32_t*)ctx->slot_gid,                                \
+                     (const uint32_t*)ctx->slot_view, (const uint32_t*)ctx->slot_ntiles, ctx->slot_bwd,            \
+                     ctx->slot_pose);                                                                             \
+  hipLaunchKernelGGL(k_gauss_gather<D>, dim3((unsigned)nb), dim3(KGS_BLOCK), 0, st, (int64_t)g->n, V,             \
+                     (const uint32_t*)ctx->vis, (const uint32_t*)ctx->counters, (const float4*)ctx->slot_bwd,     \
+                     view_loss, G, S)
     switch (g->sh_degree) {
       case 0: KGS_PB(0); break;
       case 1: KGS_PB(1); break;
@@ -467,7 +560,7 @@ kgs_status kgs_launch_project_bwd(kgs_ctx* ctx, const kgs_gaussians* g, const kg
 #undef KGS_PB
     if (G.pose_xi) {
       hipLaunchKernelGGL(k_pose_reduce, dim3(KGS_POSE_BLOCKS, V), dim3(256), 0, st, (const uint32_t*)ctx->counters,
-                         (const uint32_t*)ctx->blk_base, nb, V, (const float4*)ctx->slot_bwd, ctx->pose_partial);
+                         (const uint32_t*)ctx->blk_base, nb, V, (const float2*)ctx->slot_pose, ctx->pose_partial);
       hipLaunchKernelGGL(k_pose_final, dim3(1), dim3(64), 0, st, V, (const double*)ctx->pose_partial,
                          (const CamDev*)ctx->cams, G.pose_xi);
     }

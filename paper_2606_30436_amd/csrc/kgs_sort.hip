@@ -152,7 +152,7 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t* __restric
 // ---------------------------------------------------------------- group scan
 // The depth-sorted slots are cut into groups of 64; a group's pairs are
 // contiguous.  k_group_sum: tile count of every group (one wave per group);
-// k_scan_mid: exclusive scan of the group sums (one block, coalesced rounds);
+// then a device-wide exclusive scan of the group sums;
 // k_slot_offsets: each record's first pair.
 __global__ __launch_bounds__(256) void k_group_sum(const uint32_t* __restrict__ count,
                                                    const uint32_t* __restrict__ perm,
@@ -166,39 +166,6 @@ __global__ __launch_bounds__(256) void k_group_sum(const uint32_t* __restrict__ 
     const uint32_t c = j < n ? ntiles[perm[j]] : 0u;
     const uint32_t t = wave_sum(c);
     if (l == 0) part[g] = t;
-  }
-}
-
-__global__ __launch_bounds__(1024) void k_scan_mid(uint32_t nparts, uint32_t* __restrict__ part) {
-  constexpr uint32_t E = 4;
-  __shared__ uint32_t sh[16];
-  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
-  uint32_t carry = 0;
-  for (uint32_t base = 0; base < nparts; base += 1024 * E) {
-    const uint32_t i0 = base + (uint32_t)tid * E;
-    uint32_t v[E], a = 0;
-#pragma unroll
-    for (uint32_t k = 0; k < E; ++k) {
-      v[k] = i0 + k < nparts ? part[i0 + k] : 0u;
-      a += v[k];
-    }
-    const uint32_t ia = wave_inclusive_scan(a);
-    if (l == 63) sh[w] = ia;
-    __syncthreads();
-    uint32_t off = carry, tot = 0;
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      if (k < w) off += sh[k];
-      tot += sh[k];
-    }
-    uint32_t r = off + ia - a;
-#pragma unroll
-    for (uint32_t k = 0; k < E; ++k) {
-      if (i0 + k < nparts) part[i0 + k] = r;
-      r += v[k];
-    }
-    carry += tot;
-    __syncthreads();
   }
 }
 
@@ -427,15 +394,16 @@ kgs_status kgs_launch_bin_sort(kgs_ctx* ctx, hipStream_t st) {
   while ((1 << view_bits) < V) ++view_bits;
   const int sc = radix_sort<uint64_t>(ctx, ctx->counters, ctx->slot_keys, ctx->slot_vals, 32 + view_bits, st);
   const uint32_t* perm = ctx->slot_vals[sc];
+  ctx->perm = perm;
   // 2. first pair of every record in that order, then the pairs
   const uint32_t n_groups = (uint32_t)((S + 63) / 64);
   const unsigned eg = (unsigned)std::min<uint64_t>(std::max<uint64_t>((n_groups + 3) / 4, 1), 2048);
   hipLaunchKernelGGL(k_group_sum, dim3(eg), dim3(256), 0, st, (const uint32_t*)ctx->counters, perm,
-                     (const uint32_t*)ctx->slot_ntiles, n_groups, ctx->scan_part);
-  hipLaunchKernelGGL(k_scan_mid, dim3(1), dim3(1024), 0, st, n_groups, ctx->scan_part);
+                     (const uint32_t*)ctx->slot_ntiles, n_groups, ctx->group_part);
+  kgs_launch_scan(ctx->group_part, ctx->group_part, n_groups, 1, ~0ull, ~0ull, ctx->scan_part, ctx->scan_totals, st);
   uint32_t* pref = reinterpret_cast<uint32_t*>(ctx->slot_keys[sc ^ 1]);  // free after the record sort
   hipLaunchKernelGGL(k_slot_offsets, dim3(eg), dim3(256), 0, st, (const uint32_t*)ctx->counters, perm,
-                     (const uint32_t*)ctx->scan_part, n_groups, (const uint32_t*)ctx->slot_ntiles, P, pref,
+                     (const uint32_t*)ctx->group_part, n_groups, (const uint32_t*)ctx->slot_ntiles, P, pref,
                      ctx->slot_pairoff);
   const uint64_t chunks = (P + EP_CHUNK - 1) / EP_CHUNK;
   const unsigned pg = (unsigned)std::min<uint64_t>(std::max<uint64_t>(chunks, 1), 4096);

@@ -226,8 +226,12 @@ def _sample_arclength(rng, n, edges, density):
 
 
 def trajectory_gaussians(rng, n, length, edges, density, degree=3):
+    """Gaussians along the trajectory, stored in insertion order: a mapping
+    system spawns them at the keyframes as the camera moves (Sec. 3.3,
+    probabilistic initialisation at incoming keyframes), so the map's index
+    order follows the arc length."""
     s, x, z, _ = trajectory(length)
-    sg = _sample_arclength(rng, n, edges, density)
+    sg = np.sort(_sample_arclength(rng, n, edges, density))
     px, pz, th = _path_frame(sg, s, x, z)
     lat, y, kind = _road_layout(rng, n)
     gx = px + lat * np.cos(th)
