@@ -290,6 +290,52 @@ kgs_status kgs_accumulate_stats(kgs_ctx* ctx, const kgs_view_stats* stats, int64
 kgs_status kgs_densify_prune_decide(kgs_ctx* ctx, const kgs_lifecycle_state* state, int64_t n, double tau_p,
                                     uint8_t* decision, uint32_t* keep_map, uint32_t* n_keep, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Learned prune / keep / densify head.  A small network predicts the plain
+ * criterion's decision (kgs_densify_prune_decide, Sec. 3.3 and App. D) from a
+ * Gaussian's statistics; it is trained on that criterion's decisions, which
+ * stay the fallback and the judge of its agreement.  MLP 16 -> 64 -> 64 -> 3,
+ * ReLU after both hidden layers, logits out; every GEMM takes BF16 operands
+ * (round to nearest even) on the matrix cores with FP32 accumulation.
+ * Parameters: one FP32 device vector theta[KGS_HEAD_PARAMS] laid out as
+ * W1 [64][16], b1 [64], W2 [64][64], b2 [64], W3 [3][64], b3 [3].
+ * Features: [N][KGS_HEAD_FEATURES] BF16 bit patterns (16-byte aligned rows).
+ * ------------------------------------------------------------------------ */
+#define KGS_HEAD_FEATURES 16
+#define KGS_HEAD_PARAMS 5443
+
+/* Bytes of device workspace kgs_head_loss_grad needs (host only). */
+kgs_status kgs_head_workspace_size(size_t* bytes);
+
+/* Features of every Gaussian from a chunk's statistics, before the chunk is
+ * merged (call it before kgs_accumulate_stats, which may reset the sums):
+ *   0 S_d^(i,c) = kappa / n_views      1 L = ln(1 + gamma)     2 S_p^(i,c)
+ *   3 ln(1 + |Omega|)                  4 kappa / |Omega|       5 views seen / n_views
+ *   6 mean |dL/dmu2D| per view seen    7 ln(1 + max radius)    8 opacity
+ *   9-11 log-scales, largest first     12 S_p(i) and 13 S_d(i) of `before` (0 if NULL)
+ *   14 gamma / |Omega|                 15 1 if |Omega| > 0
+ * (App. D: footprint, error mask, densification and pruning scores.)  stats
+ * must hold all six accumulators; features: device [N][16] BF16. */
+kgs_status kgs_head_features(kgs_ctx* ctx, const kgs_gaussians* g, const kgs_view_stats* stats, int32_t n_views,
+                             const kgs_lifecycle_state* before, uint16_t* features, void* stream);
+
+/* logits [N][3] (or NULL) and decision [N] = argmax, lower class on ties (or NULL). */
+kgs_status kgs_head_forward(const float* theta, const uint16_t* features, int64_t n, float* logits,
+                            uint8_t* decision, void* stream);
+
+/* Class-weighted mean cross-entropy L = sum_n w_{y_n} CE_n / sum_n w_{y_n}
+ * against labels [N] (0 KEEP, 1 DENSIFY, 2 PRUNE) with class_w device [3]:
+ * writes grad [KGS_HEAD_PARAMS] = dL/dtheta and loss [1] (device).  The
+ * backward rounds its GEMM operands (dL/dlogits and the masked hidden
+ * gradients) to BF16 as the forward does.  Deterministic. */
+kgs_status kgs_head_loss_grad(const float* theta, const uint16_t* features, const uint8_t* labels, int64_t n,
+                              const float* class_w, void* workspace, size_t workspace_bytes, float* grad, float* loss,
+                              void* stream);
+
+/* One Adam step (bias-corrected, step >= 1) on theta with moments m, v. */
+kgs_status kgs_head_adam(float* theta, float* m, float* v, const float* grad, int32_t step, float lr, float beta1,
+                         float beta2, float eps, void* stream);
+
 /* The whole chunk as described by kgs_chunk_desc. */
 kgs_status kgs_chunk_run(kgs_ctx* ctx, const kgs_chunk_desc* desc, void* stream);
 

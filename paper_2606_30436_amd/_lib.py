@@ -101,6 +101,14 @@ _SIGS = {
     "kgs_counts_read": (c_int32, [c_void_p, P(c_int64), P(c_int64)]),
     "kgs_get_buffers": (c_int32, [c_void_p, P(KgsBuffers)]),
     "kgs_status_string": (ctypes.c_char_p, [c_int32]),
+    "kgs_head_workspace_size": (c_int32, [P(ctypes.c_size_t)]),
+    "kgs_head_features": (c_int32, [c_void_p, P(KgsGaussians), P(KgsViewStats), c_int32, c_void_p, c_void_p,
+                                    c_void_p]),
+    "kgs_head_forward": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p, c_void_p, c_void_p]),
+    "kgs_head_loss_grad": (c_int32, [c_void_p, c_void_p, c_void_p, c_int64, c_void_p, c_void_p, ctypes.c_size_t,
+                                     c_void_p, c_void_p, c_void_p]),
+    "kgs_head_adam": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_float, c_float, c_float, c_float,
+                                c_void_p]),
 }
 
 EXPORTED = tuple(_SIGS)
@@ -275,3 +283,35 @@ def kgs_get_buffers(ctx) -> KgsBuffers:
     b = KgsBuffers()
     check(load().kgs_get_buffers(ctypes.c_void_p(ctx), ctypes.byref(b)), "kgs_get_buffers")
     return b
+
+
+# ---------------------------------------------------------------- learned head
+HEAD_FEATURES = 16
+HEAD_PARAMS = 5443
+
+
+def kgs_head_workspace_size() -> int:
+    b = ctypes.c_size_t()
+    check(load().kgs_head_workspace_size(ctypes.byref(b)), "kgs_head_workspace_size")
+    return b.value
+
+
+def kgs_head_features(ctx, g: KgsGaussians, stats: KgsViewStats, n_views, before, features, stream=None):
+    check(load().kgs_head_features(ctypes.c_void_p(ctx), ctypes.byref(g), ctypes.byref(stats), int(n_views),
+                                   ctypes.byref(before) if before is not None else None, ptr(features),
+                                   stream_handle(stream)), "kgs_head_features")
+
+
+def kgs_head_forward(theta, features, n, logits=None, decision=None, stream=None):
+    check(load().kgs_head_forward(ptr(theta), ptr(features), int(n), ptr(logits), ptr(decision),
+                                  stream_handle(stream)), "kgs_head_forward")
+
+
+def kgs_head_loss_grad(theta, features, labels, n, class_w, workspace, ws_bytes, grad, loss, stream=None):
+    check(load().kgs_head_loss_grad(ptr(theta), ptr(features), ptr(labels), int(n), ptr(class_w), ptr(workspace),
+                                    int(ws_bytes), ptr(grad), ptr(loss), stream_handle(stream)), "kgs_head_loss_grad")
+
+
+def kgs_head_adam(theta, m, v, grad, step, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    check(load().kgs_head_adam(ptr(theta), ptr(m), ptr(v), ptr(grad), int(step), float(lr), float(beta1),
+                               float(beta2), float(eps), stream_handle(stream)), "kgs_head_adam")

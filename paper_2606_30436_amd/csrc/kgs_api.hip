@@ -288,6 +288,47 @@ kgs_status kgs_densify_prune_decide(kgs_ctx* ctx, const kgs_lifecycle_state* sta
   return kgs_launch_decide(ctx, state, n, tau_p, decision, keep_map, n_keep, (hipStream_t)stream);
 }
 
+// ---------------------------------------------------------------- learned head
+kgs_status kgs_head_workspace_size(size_t* bytes) {
+  if (!bytes) return KGS_ERR_INVALID_ARG;
+  *bytes = kgs_head_ws_bytes();
+  return KGS_OK;
+}
+
+static bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+kgs_status kgs_head_features(kgs_ctx* ctx, const kgs_gaussians* g, const kgs_view_stats* stats, int32_t n_views,
+                             const kgs_lifecycle_state* before, uint16_t* features, void* stream) {
+  if (!ctx || !gaussians_ok(ctx, g) || !stats || !features || !aligned16(features) || n_views < 1) return KGS_ERR_INVALID_ARG;
+  if (!stats->kappa_sum || !stats->omega_sum || !stats->gamma_sum || !stats->grad_norm_sum || !stats->view_count ||
+      !stats->max_radius)
+    return KGS_ERR_INVALID_ARG;
+  if (before && (!before->densify || !before->prune_score)) return KGS_ERR_INVALID_ARG;
+  return kgs_launch_head_features(ctx, g, stats, n_views, before, features, (hipStream_t)stream);
+}
+
+kgs_status kgs_head_forward(const float* theta, const uint16_t* features, int64_t n, float* logits,
+                            uint8_t* decision, void* stream) {
+  if (!theta || n < 0 || (n > 0 && !features) || !aligned16(features)) return KGS_ERR_INVALID_ARG;
+  return kgs_launch_head_forward(theta, features, n, logits, decision, (hipStream_t)stream);
+}
+
+kgs_status kgs_head_loss_grad(const float* theta, const uint16_t* features, const uint8_t* labels, int64_t n,
+                              const float* class_w, void* workspace, size_t workspace_bytes, float* grad, float* loss,
+                              void* stream) {
+  if (!theta || n < 1 || !features || !aligned16(features) || !labels || !class_w || !workspace || !grad)
+    return KGS_ERR_INVALID_ARG;
+  if (workspace_bytes < kgs_head_ws_bytes() || ((uintptr_t)workspace & 255u)) return KGS_ERR_INVALID_ARG;
+  return kgs_launch_head_train(theta, features, labels, n, class_w, (char*)workspace, grad, loss, (hipStream_t)stream);
+}
+
+kgs_status kgs_head_adam(float* theta, float* m, float* v, const float* grad, int32_t step, float lr, float beta1,
+                         float beta2, float eps, void* stream) {
+  if (!theta || !m || !v || !grad || step < 1 || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f))
+    return KGS_ERR_INVALID_ARG;
+  return kgs_launch_head_adam(theta, m, v, grad, step, lr, beta1, beta2, eps, (hipStream_t)stream);
+}
+
 static void fill_zero(void* p, uint64_t bytes, hipStream_t st) {
   if (!p || bytes == 0) return;
   const uint64_t words = bytes / 4;

@@ -431,6 +431,18 @@ __device__ __forceinline__ void tile_subblock(int tile_w, int w, int& sx, int& s
 // Host-side kernel launch helpers (defined in kgs_api.hip).
 kgs_status kgs_check_launch();
 
+// Launch helpers of the lifecycle statistics and the learned head.
+const double* kgs_launch_chunk_minmax(kgs_ctx* ctx, const kgs_view_stats* s, int64_t n, hipStream_t st);
+size_t kgs_head_ws_bytes();
+kgs_status kgs_launch_head_forward(const float* theta, const uint16_t* feat, int64_t n, float* logits,
+                                   uint8_t* decision, hipStream_t st);
+kgs_status kgs_launch_head_train(const float* theta, const uint16_t* feat, const uint8_t* labels, int64_t n,
+                                 const float* cw, char* ws, float* grad, float* loss, hipStream_t st);
+kgs_status kgs_launch_head_adam(float* theta, float* m, float* v, const float* grad, int32_t step, float lr,
+                                float b1, float b2, float eps, hipStream_t st);
+kgs_status kgs_launch_head_features(kgs_ctx* ctx, const kgs_gaussians* g, const kgs_view_stats* stats, int V,
+                                    const kgs_lifecycle_state* before, uint16_t* feat, hipStream_t st);
+
 // Device-wide exclusive scan (kgs_scan.hip): W (1 or 2) interleaved u32 values
 // per entry, u64 accumulation, outputs clamped at cap0 / cap1; in may equal
 // out.  part needs W * kgs_scan_tiles(entries) u64, totals W u64.

@@ -165,3 +165,14 @@ kgs_status kgs_launch_decide(kgs_ctx* ctx, const kgs_lifecycle_state* state, int
   }
   return kgs_check_launch();
 }
+
+// min / max of L = ln(1 + gamma) over the active set of a chunk, without
+// touching any state; returns the device address of (min, max).
+const double* kgs_launch_chunk_minmax(kgs_ctx* ctx, const kgs_view_stats* s, int64_t n, hipStream_t st) {
+  const int64_t nb = (n + KGS_BLOCK - 1) / KGS_BLOCK;
+  hipLaunchKernelGGL(k_chunk_scores, dim3((unsigned)nb), dim3(KGS_BLOCK), 0, st, n, 0.0f, INFINITY,
+                     (const uint32_t*)s->kappa_sum, (const uint32_t*)s->omega_sum, (const double*)s->gamma_sum,
+                     (uint8_t*)nullptr, ctx->mm_partial);
+  hipLaunchKernelGGL(k_minmax_final, dim3(1), dim3(1024), 0, st, nb, ctx->mm_partial);
+  return ctx->mm_partial + 2 * nb;
+}

@@ -1,0 +1,139 @@
+"""The learned head's kernels through the C ABI against the network oracle:
+forward logits and decisions, the weighted cross-entropy gradient, Adam, the
+feature kernel, and training on the plain criterion's labels."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import mlp
+from paper_2606_30436_amd import head as hd
+from tests.gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+
+def _data(n, seed):
+    rng = np.random.default_rng(seed)
+    x = rng.normal(0.0, 1.5, (n, 16)).astype(np.float32)
+    x[:, 15] = (rng.uniform(size=n) < 0.7).astype(np.float32)
+    xb = mlp.bf16(x).astype(np.float32)          # features as the kernels read them
+    theta = mlp.init_params(seed).astype(np.float64)
+    theta[1024:1088] = rng.normal(0, 0.1, 64)
+    theta[5184:5248] = rng.normal(0, 0.1, 64)
+    theta[5440:] = rng.normal(0, 0.1, 3)
+    y = rng.integers(0, 3, n).astype(np.uint8)
+    return xb, theta.astype(np.float32), y
+
+
+def _ambiguous(x, theta):
+    """Gaussians where FP32 accumulation could move a hidden value across a
+    BF16 rounding boundary or across zero (the oracle computes in FP64).  The
+    products of BF16 operands are exact in FP32; the bound allows eight FP32
+    roundings of the sum of their magnitudes."""
+    f = mlp.forward(x, theta.astype(np.float64), True)
+    p = mlp.unpack(theta.astype(np.float64))
+    amb = np.zeros(x.shape[0], bool)
+    for z, W, h in ((f["z1"], f["W1"], f["x"]), (f["z2"], f["W2"], f["h1"])):
+        e = 8 * 2.0 ** -24 * (np.abs(h) @ np.abs(W).T + 1e-30)
+        zp = np.maximum(z + e, 0.0)
+        zm = np.maximum(z - e, 0.0)
+        amb |= (mlp.bf16_bits(zp) != mlp.bf16_bits(zm)).any(axis=1)
+    return amb, f
+
+
+def test_head_forward_matches_oracle():
+    n = 5000
+    x, theta, _ = _data(n, 1)
+    h = hd.PruneHead(theta)
+    feats = torch.from_numpy(x).to(torch.bfloat16).cuda()
+    lg, dec = h.forward(feats)
+    torch.cuda.synchronize()
+    lg = lg.cpu().numpy().astype(np.float64)
+    amb, f = _ambiguous(x, theta)
+    ref = f["logits"]
+    scale = np.abs(f["h2"]) @ np.abs(f["W3"]).T + 1.0
+    err = np.abs(lg - ref) / scale
+    say(f"[gpu] head forward: ambiguous {amb.sum()}/{n}, max rel err (clear) {err[~amb].max():.2e}")
+    assert amb.mean() < 0.35
+    assert err[~amb].max() < 1e-5
+    # decisions: argmax of the GPU logits, equal to the oracle's where the top two are apart
+    d = dec.cpu().numpy()
+    assert np.array_equal(d, np.argmax(lg, axis=1))
+    srt = np.sort(ref, axis=1)
+    clear = ~amb & (srt[:, 2] - srt[:, 1] > 1e-4 * scale.max(axis=1))
+    assert np.array_equal(d[clear], np.argmax(ref, axis=1)[clear])
+
+
+def test_head_forward_ragged_and_empty():
+    x, theta, _ = _data(37, 2)
+    h = hd.PruneHead(theta)
+    feats = torch.from_numpy(x).to(torch.bfloat16).cuda()
+    for n in (0, 1, 15, 16, 17, 37):
+        lg, dec = h.forward(feats[:n].contiguous()) if n else h.forward(feats[:0])
+        torch.cuda.synchronize()
+        if n:
+            ref = mlp.forward(x[:n], theta.astype(np.float64), True)["logits"]
+            assert np.abs(lg.cpu().numpy() - ref).max() < 1e-3 * (np.abs(ref).max() + 1)
+
+
+def test_head_gradient_matches_oracle():
+    n = 4096
+    x, theta, y = _data(n, 3)
+    cw = mlp.class_weights(y).astype(np.float32)
+    h = hd.PruneHead(theta)
+    feats = torch.from_numpy(x).to(torch.bfloat16).cuda()
+    loss, grad = h.loss_grad(feats, torch.from_numpy(y).cuda(), torch.from_numpy(cw).cuda())
+    torch.cuda.synchronize()
+    ref_loss, ref_g = mlp.loss_and_grad(x, y, cw.astype(np.float64), theta.astype(np.float64), True)
+    g = grad.cpu().numpy().astype(np.float64)
+    say(f"[gpu] head loss {float(loss.item()):.6f} vs {ref_loss:.6f}")
+    assert abs(float(loss.item()) - ref_loss) <= 1e-5 * abs(ref_loss)
+    for name, lo, hi in (("W1", 0, 1024), ("b1", 1024, 1088), ("W2", 1088, 5184), ("b2", 5184, 5248),
+                         ("W3", 5248, 5440), ("b3", 5440, 5443)):
+        rel = np.linalg.norm(g[lo:hi] - ref_g[lo:hi]) / np.linalg.norm(ref_g[lo:hi])
+        say(f"  {name}: rel {rel:.2e}")
+        assert rel < 2e-3, name
+    # deterministic: a second call gives the same bits
+    g2 = h.loss_grad(feats, torch.from_numpy(y).cuda(), torch.from_numpy(cw).cuda())[1].clone()
+    assert torch.equal(g2, grad)
+
+
+def test_head_adam_matches_oracle():
+    rng = np.random.default_rng(4)
+    theta = rng.normal(0, 0.1, mlp.N_PARAMS).astype(np.float32)
+    h = hd.PruneHead(theta)
+    t64, m64, v64 = theta.astype(np.float64), np.zeros(mlp.N_PARAMS), np.zeros(mlp.N_PARAMS)
+    for step in range(1, 4):
+        g = rng.normal(0, 1e-2, mlp.N_PARAMS).astype(np.float32)
+        h.grad.copy_(torch.from_numpy(g))
+        h.adam(1e-3)
+        t64, m64, v64 = mlp.adam(t64, m64, v64, g.astype(np.float64), step, 1e-3)
+    torch.cuda.synchronize()
+    assert np.abs(h.theta.cpu().numpy() - t64).max() < 1e-6
+
+
+def test_head_training_reduces_the_loss_and_learns_a_threshold_rule():
+    """A rule of the criterion's kind (prune above a score, densify above a
+    count) is learned by the GPU kernels alone."""
+    n = 20000
+    rng = np.random.default_rng(5)
+    x = np.zeros((n, 16), np.float32)
+    x[:, 0] = rng.uniform(0, 10, n)           # S_d-like
+    x[:, 2] = rng.uniform(0, 1, n)            # S_p-like
+    x[:, 3:15] = rng.normal(0, 1, (n, 12))
+    y = np.where(x[:, 2] > 0.8, 2, np.where(x[:, 0] > 5, 1, 0)).astype(np.uint8)
+    feats = torch.from_numpy(mlp.bf16(x).astype(np.float32)).to(torch.bfloat16).cuda()
+    lab = torch.from_numpy(y).cuda()
+    cw = hd.balanced_class_weights(lab)
+    h = hd.PruneHead(seed=7)
+    first = None
+    for it in range(400):
+        loss = float(h.train_step(feats, lab, cw, 3e-3).item()) if it % 50 == 0 else h.train_step(feats, lab, cw, 3e-3)
+        if it == 0:
+            first = loss
+    _, dec = h.forward(feats)
+    torch.cuda.synchronize()
+    acc = float((dec == lab).float().mean())
+    last = float(h.loss.item())
+    say(f"[gpu] head training: loss {first:.3f} -> {last:.3f}, accuracy {acc:.4f}")
+    assert last < 0.25 * first and acc > 0.97
