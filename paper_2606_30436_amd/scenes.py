@@ -315,10 +315,11 @@ def make_c5(seed: int = 5, n: int = 5_000_000, n_chunks: int = 32, views_per_chu
             floater_frac: float = 0.05, n_holes: int = 64) -> Scene:
     """Learned-head workload: 5M Gaussians along a ~10 km trajectory, 32 chunks
     of 16 keyframes.  The returned map has 5% injected floaters (large, faint,
-    in the air) and `n_holes` 5 m stretches of facade removed; `meta['full']`
-    is the index set of the structure-only scene the targets are rendered from
-    (the deleted facade Gaussians are kept at the end of the arrays and
-    excluded from the map by `meta['map_index']`)."""
+    in the air) and `n_holes` 5 m stretches of facade removed:
+    `meta['struct_index']` selects the structure-only scene the targets are
+    rendered from (facade in the holes included, no floaters) and
+    `meta['map_index']` the map (floaters included, the holes' facade
+    Gaussians left out)."""
     rng = np.random.default_rng(seed)
     length = n_chunks * CHUNK_KEYFRAMES * KEYFRAME_SPACING + 120.0
     n_float = int(round(n * floater_frac))

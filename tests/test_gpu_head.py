@@ -137,3 +137,60 @@ def test_head_training_reduces_the_loss_and_learns_a_threshold_rule():
     last = float(h.loss.item())
     say(f"[gpu] head training: loss {first:.3f} -> {last:.3f}, accuracy {acc:.4f}")
     assert last < 0.25 * first and acc > 0.97
+
+
+def test_feature_kernel_matches_host_formulas():
+    """Features of a real chunk against the same formulas on the host from the
+    GPU's statistics (the chunk min / max of L over the active set in FP64)."""
+    from paper_2606_30436_amd import scenes
+    from paper_2606_30436_amd.rasterizer import (GaussianParams, Image, LifecycleState, Rasterizer, ViewStats,
+                                                 device_cameras)
+    sc = scenes.make_c3(seed=21, n=100_000, n_views=3)
+    sc.target = scenes.random_target(22, 3, sc.height, sc.width)
+    R = Rasterizer(sc.width, sc.height, max_views=3, max_gaussians=sc.n, far_z=80.0)
+    g = GaussianParams.from_scene(sc)
+    cams = device_cameras(sc.cams)
+    img = Image.empty(3, sc.height, sc.width)
+    R.project(g, cams)
+    R.bin_sort()
+    R.render_fwd(img)
+    tgt = torch.from_numpy(sc.target).cuda()
+    dl = torch.empty_like(img.color)
+    loss = torch.empty(3, device="cuda")
+    R.loss_l1(tgt, img, dl, loss)
+    st = ViewStats.zeros(sc.n)
+    R.render_bwd(g, cams, None, img, dl, target=tgt, tau_err=0.1, view_loss=loss, grads=g.zeros_like(), stats=st)
+    before = LifecycleState.zeros(sc.n)
+    before.prune_score.uniform_(0, 1)
+    before.densify.copy_((torch.rand(sc.n, device="cuda") > 0.5).to(torch.uint8))
+    f = hd.features(R, g, st, 3, before).float().cpu().numpy()
+    torch.cuda.synchronize()
+    k, om = st.kappa_sum.cpu().numpy().astype(np.float64), st.omega_sum.cpu().numpy().astype(np.float64)
+    gam, vc = st.gamma_sum.cpu().numpy(), st.view_count.cpu().numpy().astype(np.float64)
+    L = np.log1p(gam)
+    act = om > 0
+    lo, hi = L[act].min(), L[act].max()
+    ls = np.sort(sc.log_scales.astype(np.float64), axis=0)[::-1]
+    ref = np.stack([k / 3, L, np.where(act, (L - lo) / (hi - lo), 0), np.log1p(om), np.where(act, k / np.maximum(om, 1), 0),
+                    vc / 3, st.grad_norm_sum.cpu().numpy() / np.maximum(vc, 1), np.log1p(st.max_radius.cpu().numpy()),
+                    1 / (1 + np.exp(-sc.logits.astype(np.float64))), ls[0], ls[1], ls[2],
+                    before.prune_score.cpu().numpy(), before.densify.cpu().numpy(),
+                    np.where(act, gam / np.maximum(om, 1), 0), act.astype(np.float64)], axis=1)
+    say(f"[gpu] features: active {int(act.sum())}/{sc.n}")
+    assert act.sum() > 1000
+    # BF16 keeps 8 significant bits; the FP32 arithmetic of the kernel adds ~1e-6
+    assert np.all(np.abs(f - ref) <= 2 ** -8 * np.abs(ref) + 1e-6)
+
+
+def test_head_gain_over_the_plain_criterion():
+    """Trained by the library's kernels on the criterion's decisions of the
+    first chunks, the head decides the held-out chunks from a cheap pass over a
+    quarter of their views: it must agree with the criterion on nearly every
+    Gaussian while taking a fraction of the criterion's time."""
+    from paper_2606_30436_amd import head_experiment as hx
+    r = hx.run(n=1_000_000, chunks=8, views=16, train_chunks=6, steps=800)
+    say(f"[gpu] head gain: agreement {r['test_global_agreement']}, speedup {r['decision_speedup']}, "
+        f"psnr {r['psnr_db']}, ms {r['ms_per_chunk']}")
+    assert r["train_accuracy"] > 0.85
+    assert r["test_global_agreement"] > 0.95
+    assert r["decision_speedup"] > 2.0
