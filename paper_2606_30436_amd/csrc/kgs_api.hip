@@ -80,7 +80,9 @@ size_t layout(const kgs_config& c, char* base, kgs_ctx* ctx) {
   p = take(4 * 256 * KGS_SORT_BLOCKS * 4);      if (ctx) ctx->radix_hist = (uint32_t*)p;
   p = take(4 * 256 * KGS_MAX_PASSES);           if (ctx) ctx->radix_total = (uint32_t*)p;
   p = take(4 * KGS_SLOT_WORDS * S);             if (ctx) ctx->slot_bwd = (float4*)p;
-  p = take(4 * S);                              if (ctx) ctx->big_list = (uint32_t*)p;
+  p = take(4 * P);                              if (ctx) ctx->pair_slot = (uint32_t*)p;
+  p = take(64 * (P / 64 + 2));                  if (ctx) ctx->seg_head = (float4*)p;
+  p = take(64 * (P / 64 + 2));                  if (ctx) ctx->seg_tail = (float4*)p;
   p = take(24 * S);                             if (ctx) ctx->slot_pose = (float2*)p;
   {
     const int64_t st = std::max(kgs_scan_tiles(V * nb), kgs_scan_tiles(S / 64 + 2)) + 1;

@@ -16,8 +16,6 @@
 #define KGS_MAX_PASSES 8
 #define KGS_POSE_BLOCKS 32            // pieces per view of the pose reduction
 #define KGS_SLOT_WORDS 40             // words of a slot's backward record
-#define KGS_SMALL_SLOT 8              // pair count up to which one lane sums a slot's pairs
-#define KGS_CNT_BIG 4                 // counters[] word: number of queued large slots
 
 // ---------------------------------------------------------------- device camera
 // Pose already applied.  The camera point of a Gaussian is R' mu + t' in
@@ -72,7 +70,9 @@ struct kgs_ctx {
   uint32_t* radix_hist;               // [256][KGS_SORT_BLOCKS * 4] per-wave partitions
   uint32_t* radix_total;              // [KGS_MAX_PASSES][256]
   float4* slot_bwd;                   // [S][KGS_SLOT_WORDS / 4] per-slot backward records
-  uint32_t* big_list;                 // [S] slots whose pairs are summed by a whole wave
+  uint32_t* pair_slot;                // [P] slot of every pair, emission order
+  float4* seg_head;                   // [P / 64 + 1][4] per 64-pair window: its first segment's partial sum
+  float4* seg_tail;                   // [P / 64 + 1][4] and its last segment's
   float2* slot_pose;                  // [S][3] pose contributions (rho, phi) of every slot
   unsigned long long* scan_part;      // tile sums of the device-wide scans
   unsigned long long* scan_totals;    // [2] their totals

@@ -1,6 +1,6 @@
 // Backward of the projection, deterministic throughout:
-//   k_pair_sum_*    per slot, the sum of its pairs' gradient records (they
-//                   are contiguous in emission order);
+//   k_pair_segsum   per slot, the sum of its pairs' gradient records (they
+//   k_pair_fixup    are contiguous in emission order), segmented by slot;
 //   k_slot_bwd      per slot, from its pair sum, the chain rule to the
 //                   Gaussian's parameters and to the view's pose, and the
 //                   view's footprint statistics, as one 160-byte record;
@@ -28,150 +28,141 @@ struct BwdParams {
 // 19 ||dL/dmu2D||, 20 pixel radius (i32), 21-23 dL/dcolour where the colour is
 // not clamped (0 where it is), 24-39 the SH basis at the view direction.
 // ---------------------------------------------------------------- pair sums
-// Per-slot sums of the 12-word pair records [po, po + tiles) (10 record-space
-// gradient terms and the two footprint counts), written into words 0-11 of the
-// slot's backward record.  A slot of up to KGS_SMALL_SLOT pairs is summed by
-// one lane in pair order, four pairs in flight; a larger one is queued and
-// summed by a whole wave (lane-strided partial sums, then a fixed butterfly).
-// Either way the order depends only on the slot's pair count, never on
-// scheduling.
-__device__ __forceinline__ void add_pair(const float4& a, const float4& b, const float4& c, float r[10], uint32_t& om,
-                                         uint32_t& kap) {
-  r[0] += a.x; r[1] += a.y; r[2] += a.z; r[3] += a.w;
-  r[4] += b.x; r[5] += b.y; r[6] += b.z; r[7] += b.w;
-  r[8] += c.x; r[9] += c.y;
-  om += __float_as_uint(c.z);
-  kap += __float_as_uint(c.w);
+// Per-slot sums of the 12-word pair records (10 record-space gradient terms
+// and the two footprint counts), three float4 per slot, by a segmented
+// reduction over the pairs in emission order, where each slot's pairs are
+// contiguous.  One wave takes a window of 64 consecutive pairs (one per lane,
+// coalesced), scans them segmented by slot with DPP row shifts and the two
+// row broadcasts, and the last lane of every segment holds the segment's sum
+// within the window.  A segment wholly inside the window is final; one that
+// crosses a window edge leaves its partial in the window's head / tail record,
+// and k_pair_fixup adds the partials of such a slot in window order.  The
+// adds follow a fixed tree, so the sums are deterministic.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp0(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xf, true));
 }
 
-__device__ __forceinline__ void store_sum(float4* __restrict__ rec, const float r[10], uint32_t om, uint32_t kap) {
-  rec[0] = make_float4(r[0], r[1], r[2], r[3]);
-  rec[1] = make_float4(r[4], r[5], r[6], r[7]);
-  rec[2] = make_float4(r[8], r[9], __uint_as_float(om), __uint_as_float(kap));
+// inclusive scan of x over lanes [sst, l] (sst: first lane of l's segment)
+__device__ __forceinline__ float seg_scan(float x, int l, int sst) {
+  float t;
+  t = dpp0<0x111, 0xf>(x);                 // row_shr:1
+  x = (l - 1 >= sst) ? x + t : x;
+  t = dpp0<0x112, 0xf>(x);                 // row_shr:2
+  x = (l - 2 >= sst) ? x + t : x;
+  t = dpp0<0x114, 0xf>(x);                 // row_shr:4
+  x = (l - 4 >= sst) ? x + t : x;
+  t = dpp0<0x118, 0xf>(x);                 // row_shr:8
+  x = (l - 8 >= sst) ? x + t : x;
+  t = dpp0<0x142, 0xa>(x);                 // row_bcast:15 into rows 1 and 3
+  x = (sst < (l & ~15)) ? x + t : x;
+  t = dpp0<0x143, 0xc>(x);                 // row_bcast:31 into rows 2 and 3
+  x = (sst < 32 && l >= 32) ? x + t : x;
+  return x;
 }
 
-__global__ void k_zero_word(uint32_t* __restrict__ w) { *w = 0u; }
+__device__ __forceinline__ void put_rec(float4* __restrict__ rec, const float x[12], uint32_t slot, uint32_t flag) {
+  rec[0] = make_float4(x[0], x[1], x[2], x[3]);
+  rec[1] = make_float4(x[4], x[5], x[6], x[7]);
+  rec[2] = make_float4(x[8], x[9], x[10], x[11]);
+  rec[3] = make_float4(__uint_as_float(slot), __uint_as_float(flag), 0.f, 0.f);
+}
 
-__global__ __launch_bounds__(256) void k_pair_sum_small(uint32_t* __restrict__ counters,
-                                                        const uint32_t* __restrict__ perm,
-                                                        const uint32_t* __restrict__ slot_pairoff,
-                                                        const uint32_t* __restrict__ slot_ntiles,
-                                                        const float4* __restrict__ pair_grad,
-                                                        float4* __restrict__ slot_bwd, uint32_t* __restrict__ big_list) {
-  __shared__ uint32_t s_wcnt[4], s_base;
-  const uint32_t n = counters[0];
+__device__ __forceinline__ void store_sum(float4* __restrict__ rec, const float x[12]) {
+  // the two counts travelled as floats (exact below 2^24)
+  rec[0] = make_float4(x[0], x[1], x[2], x[3]);
+  rec[1] = make_float4(x[4], x[5], x[6], x[7]);
+  rec[2] = make_float4(x[8], x[9], __uint_as_float((uint32_t)x[10]), __uint_as_float((uint32_t)x[11]));
+}
+
+#define SEG_NONE 0xffffffffu
+
+__global__ __launch_bounds__(256) void k_pair_segsum(const uint32_t* __restrict__ counters,
+                                                     const uint32_t* __restrict__ pair_slot,
+                                                     const float4* __restrict__ pair_grad,
+                                                     float4* __restrict__ slot_sum, float4* __restrict__ seg_head,
+                                                     float4* __restrict__ seg_tail) {
+  const uint32_t np = counters[1];
   const int l = threadIdx.x & 63;
-  // records are walked in depth order, whose pairs are contiguous in memory,
-  // so neighbouring lanes read neighbouring pair records
-  for (uint32_t j0 = blockIdx.x * 256u; j0 < n; j0 += gridDim.x * 256u) {
-    const uint32_t j = j0 + threadIdx.x;
-    const bool act = j < n;
-    const uint32_t s = act ? perm[j] : 0u;
-    const uint32_t t = act ? slot_ntiles[s] : 0u;
-    const bool big = t > KGS_SMALL_SLOT;
-    // queue the large slots: one reservation per block (a single counter
-    // taking one atomic per wave is a serialisation point)
-    const uint64_t bal = ballot64(big);
-    const int w = threadIdx.x >> 6;
-    if (l == 0) s_wcnt[w] = (uint32_t)__popcll(bal);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      const uint32_t tot = s_wcnt[0] + s_wcnt[1] + s_wcnt[2] + s_wcnt[3];
-      s_base = tot ? atomicAdd(&counters[KGS_CNT_BIG], tot) : 0u;
-    }
-    __syncthreads();
-    if (big) {
-      uint32_t off = s_base + mask_lt_count(bal);
-      for (int k = 0; k < w; ++k) off += s_wcnt[k];
-      big_list[off] = s;
-    }
-    __syncthreads();
-    if (!act || big) continue;
-    const float4* pg = pair_grad + (size_t)slot_pairoff[s] * 3;
-    float r[10] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    uint32_t om = 0, kap = 0;
-    for (uint32_t k = 0; k < t; k += 4) {
-      float4 q[4][3];
-#pragma unroll
-      for (uint32_t i = 0; i < 4; ++i) {
-        const bool in = k + i < t;
-        const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
-        q[i][0] = in ? pg[(k + i) * 3] : z;
-        q[i][1] = in ? pg[(k + i) * 3 + 1] : z;
-        q[i][2] = in ? pg[(k + i) * 3 + 2] : z;
-      }
-#pragma unroll
-      for (int i = 0; i < 4; ++i) add_pair(q[i][0], q[i][1], q[i][2], r, om, kap);
-    }
-    store_sum(slot_bwd + (size_t)s * (KGS_SLOT_WORDS / 4), r, om, kap);
-  }
-}
-
-__device__ __forceinline__ float swap_sum32(float lo_keep, float hi_keep) {
-  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(lo_keep), __float_as_uint(hi_keep), false, false);
-  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
-}
-
-__device__ __forceinline__ float swap_sum16(float even_keep, float odd_keep) {
-  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(even_keep), __float_as_uint(odd_keep), false, false);
-  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
-}
-
-template <int CTRL>
-__device__ __forceinline__ float dpp_f(float v) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
-}
-
-// Reduce-scatter of twelve per-lane values over the wave (lane halves, row
-// pairs, mirrored lanes of a row, of a half-row, then the quad): afterwards a
-// lane with valid set holds the wave sum of value idx.
-__device__ __forceinline__ void wave_reduce12(float (&x)[12], int lane, int& idx, bool& valid) {
-  const bool u3 = lane & 8, u2 = lane & 4;
-#pragma unroll
-  for (int k = 0; k < 6; ++k) x[k] = swap_sum32(x[k], x[k + 6]);
-#pragma unroll
-  for (int k = 0; k < 3; ++k) x[k] = swap_sum16(x[k], x[k + 3]);
-  {
-    const float s0 = u3 ? x[0] : x[2], k0 = u3 ? x[2] : x[0];
-    const float s1 = u3 ? x[1] : 0.f, k1 = u3 ? 0.f : x[1];
-    x[0] = k0 + dpp_f<0x140>(s0);
-    x[1] = k1 + dpp_f<0x140>(s1);
-  }
-  {
-    const float s0 = u2 ? x[0] : x[1], k0 = u2 ? x[1] : x[0];
-    x[0] = k0 + dpp_f<0x141>(s0);
-  }
-  x[0] += dpp_f<0xB1>(x[0]);
-  x[0] += dpp_f<0x4E>(x[0]);
-  const int k = (u3 ? 2 : 0) + (u2 ? 1 : 0);
-  valid = k < 3 && (lane & 3) == 0;
-  idx = ((lane & 32) ? 6 : 0) + ((lane & 16) ? 3 : 0) + k;
-}
-
-__global__ __launch_bounds__(256) void k_pair_sum_big(const uint32_t* __restrict__ counters,
-                                                      const uint32_t* __restrict__ big_list,
-                                                      const uint32_t* __restrict__ slot_pairoff,
-                                                      const uint32_t* __restrict__ slot_ntiles,
-                                                      const float4* __restrict__ pair_grad,
-                                                      float4* __restrict__ slot_bwd) {
-  const uint32_t nbig = counters[KGS_CNT_BIG];
-  const int l = threadIdx.x & 63;
-  for (uint32_t q = blockIdx.x * 4 + (threadIdx.x >> 6); q < nbig; q += gridDim.x * 4) {
-    const uint32_t s = big_list[q];
-    const uint32_t t = slot_ntiles[s];
-    const float4* pg = pair_grad + (size_t)slot_pairoff[s] * 3;
-    float r[10] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    uint32_t om = 0, kap = 0;
-    for (uint32_t k = (uint32_t)l; k < t; k += 64) add_pair(pg[k * 3], pg[k * 3 + 1], pg[k * 3 + 2], r, om, kap);
-    // counts stay below 2^24, so they travel through the float reduction exactly
-    float x[12] = {r[0], r[1], r[2], r[3], r[4], r[5], r[6], r[7], r[8], r[9], (float)om, (float)kap};
-    int idx;
-    bool valid;
-    wave_reduce12(x, l, idx, valid);
+  const uint32_t nwin = (np + 63) / 64;
+  for (uint32_t w = blockIdx.x * 4 + (threadIdx.x >> 6); w < nwin; w += gridDim.x * 4) {
+    const uint32_t p = w * 64 + (uint32_t)l;
+    const bool valid = p < np;
+    const uint32_t s = valid ? pair_slot[p] : SEG_NONE;
+    float x[12];
     if (valid) {
-      float* rec = reinterpret_cast<float*>(slot_bwd + (size_t)s * (KGS_SLOT_WORDS / 4));
-      rec[idx] = idx < 10 ? x[0] : __uint_as_float((uint32_t)x[0]);
+      const float4 a = pair_grad[(size_t)p * 3], b = pair_grad[(size_t)p * 3 + 1], c = pair_grad[(size_t)p * 3 + 2];
+      x[0] = a.x; x[1] = a.y; x[2] = a.z; x[3] = a.w;
+      x[4] = b.x; x[5] = b.y; x[6] = b.z; x[7] = b.w;
+      x[8] = c.x; x[9] = c.y;
+      x[10] = (float)__float_as_uint(c.z);
+      x[11] = (float)__float_as_uint(c.w);
+    } else {
+#pragma unroll
+      for (int k = 0; k < 12; ++k) x[k] = 0.f;
     }
+    // slots just before and just after the window (SEG_NONE - 1: none)
+    const uint32_t s_before = w > 0 ? pair_slot[w * 64 - 1] : SEG_NONE - 1u;
+    const uint32_t s_after = w * 64 + 64 < np ? pair_slot[w * 64 + 64] : SEG_NONE - 1u;
+    // both shuffles run in every lane (a lane-conditional shuffle reads 0
+    // from the lanes that skip it)
+    const uint32_t s_up_raw = (uint32_t)__shfl_up((int)s, 1, 64);
+    const uint32_t s_dn_raw = (uint32_t)__shfl_down((int)s, 1, 64);
+    const uint32_t s_up = l > 0 ? s_up_raw : s_before;
+    const uint32_t s_dn = l < 63 ? s_dn_raw : s_after;
+    const bool head = l == 0 || s != s_up;
+    const uint64_t H = ballot64(head);
+    const uint64_t le = l == 63 ? ~0ull : ((1ull << (l + 1)) - 1ull);
+    const int sst = 63 - __clzll((long long)(H & le));
+#pragma unroll
+    for (int k = 0; k < 12; ++k) x[k] = seg_scan(x[k], l, sst);
+    const bool tail = valid && s != s_dn;
+    const bool started = sst > 0 || s != s_before;   // the slot's first pair lies in this window
+    if (tail) {
+      if (started) {
+        store_sum(slot_sum + (size_t)s * (KGS_SLOT_WORDS / 4), x);
+      } else {
+        put_rec(seg_head + (size_t)w * 4, x, s, 1u);  // continued from before, ends here
+      }
+    }
+    if (l == 63) {
+      // the window's last segment goes on past the window
+      const bool open = valid && s == s_dn;
+      if (open && !started) put_rec(seg_head + (size_t)w * 4, x, s, 0u);   // covers the whole window
+      put_rec(seg_tail + (size_t)w * 4, x, (open && started) ? s : SEG_NONE, 0u);
+    }
+  }
+}
+
+// For every window whose last segment starts in it and goes on: add the head
+// partials of the following windows, in window order, up to the one where the
+// slot's pairs end.
+__global__ __launch_bounds__(256) void k_pair_fixup(const uint32_t* __restrict__ counters,
+                                                    const float4* __restrict__ seg_head,
+                                                    const float4* __restrict__ seg_tail,
+                                                    float4* __restrict__ slot_sum) {
+  const uint32_t np = counters[1];
+  const uint32_t nwin = (np + 63) / 64;
+  for (uint32_t w = blockIdx.x * 256 + threadIdx.x; w < nwin; w += gridDim.x * 256) {
+    const float4* t = seg_tail + (size_t)w * 4;
+    const uint32_t slot = __float_as_uint(t[3].x);
+    if (slot == SEG_NONE) continue;
+    float x[12];
+    const float4 a = t[0], b = t[1], c = t[2];
+    x[0] = a.x; x[1] = a.y; x[2] = a.z; x[3] = a.w;
+    x[4] = b.x; x[5] = b.y; x[6] = b.z; x[7] = b.w;
+    x[8] = c.x; x[9] = c.y; x[10] = c.z; x[11] = c.w;
+    for (uint32_t v = w + 1; v < nwin; ++v) {
+      const float4* h = seg_head + (size_t)v * 4;
+      const float4 d = h[3];
+      if (__float_as_uint(d.x) != slot) break;
+      const float4 e = h[0], f = h[1], g = h[2];
+      x[0] += e.x; x[1] += e.y; x[2] += e.z; x[3] += e.w;
+      x[4] += f.x; x[5] += f.y; x[6] += f.z; x[7] += f.w;
+      x[8] += g.x; x[9] += g.y; x[10] += g.z; x[11] += g.w;
+      if (__float_as_uint(d.y) != 0u) break;
+    }
+    store_sum(slot_sum + (size_t)slot * (KGS_SLOT_WORDS / 4), x);
   }
 }
 
@@ -392,7 +383,10 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_slot_bwd(kgs_gaussians g, const C
   const uint32_t n_slots = counters[0];
   for (uint32_t s = blockIdx.x * KGS_BLOCK + threadIdx.x; s < n_slots; s += gridDim.x * KGS_BLOCK) {
     const float4* q = slot_bwd + (size_t)s * (KGS_SLOT_WORDS / 4);
-    const float4 a = q[0], b = q[1], c = q[2];
+    // a slot without pairs has no segment and so no sum written
+    const bool any = slot_ntiles[s] != 0u;
+    const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+    const float4 a = any ? q[0] : z, b = any ? q[1] : z, c = any ? q[2] : z;
     const float r[10] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x, c.y};
     slot_record<DEG>(s, g, cams, P, slot_gid, slot_view, slot_ntiles, r, __float_as_uint(c.z),
                      __float_as_uint(c.w), slot_bwd, slot_pose);
@@ -536,13 +530,14 @@ kgs_status kgs_launch_project_bwd(kgs_ctx* ctx, const kgs_gaussians* g, const kg
   const uint64_t cap = (uint64_t)cfg.slot_capacity;
   if (nb > 0) {
     const unsigned sg = (unsigned)std::min<uint64_t>(std::max<uint64_t>((cap + 255) / 256, 1), 4096);
-    hipLaunchKernelGGL(k_zero_word, dim3(1), dim3(1), 0, st, ctx->counters + KGS_CNT_BIG);
-    hipLaunchKernelGGL(k_pair_sum_small, dim3(sg), dim3(256), 0, st, ctx->counters, ctx->perm,
-                       (const uint32_t*)ctx->slot_pairoff, (const uint32_t*)ctx->slot_ntiles,
-                       (const float4*)ctx->pair_grad, ctx->slot_bwd, ctx->big_list);
-    hipLaunchKernelGGL(k_pair_sum_big, dim3(2048), dim3(256), 0, st, (const uint32_t*)ctx->counters,
-                       (const uint32_t*)ctx->big_list, (const uint32_t*)ctx->slot_pairoff,
-                       (const uint32_t*)ctx->slot_ntiles, (const float4*)ctx->pair_grad, ctx->slot_bwd);
+    const uint64_t wins = ((uint64_t)cfg.pair_capacity + 63) / 64;
+    const unsigned wg = (unsigned)std::min<uint64_t>(std::max<uint64_t>((wins + 3) / 4, 1), 8192);
+    hipLaunchKernelGGL(k_pair_segsum, dim3(wg), dim3(256), 0, st, (const uint32_t*)ctx->counters,
+                       (const uint32_t*)ctx->pair_slot, (const float4*)ctx->pair_grad, ctx->slot_bwd, ctx->seg_head,
+                       ctx->seg_tail);
+    hipLaunchKernelGGL(k_pair_fixup, dim3((unsigned)std::min<uint64_t>(std::max<uint64_t>((wins + 255) / 256, 1), 2048)),
+                       dim3(256), 0, st, (const uint32_t*)ctx->counters, (const float4*)ctx->seg_head,
+                       (const float4*)ctx->seg_tail, ctx->slot_bwd);
 #define KGS_PB(D)                                                                                                  \
   hipLaunchKernelGGL(k_slot_bwd<D>, dim3(sg), dim3(KGS_BLOCK), 0, st, *g, (const CamDev*)ctx->cams, P,             \
                      (const uint32_t*)ctx->counters, (const uint32_t*)ctx->slot_gid,                                \

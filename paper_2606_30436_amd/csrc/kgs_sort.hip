@@ -364,7 +364,8 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_ranges(const uint32_t* __restrict
 
 // ---------------------------------------------------------------- host side
 template <typename K>
-static int radix_sort(kgs_ctx* ctx, const uint32_t* count, K* keys[2], uint32_t* vals[2], int bits, hipStream_t st) {
+static int radix_sort(kgs_ctx* ctx, const uint32_t* count, K* keys[2], uint32_t* vals[2], int bits, hipStream_t st,
+                      const uint32_t* vals_in = nullptr) {
   const int passes = (bits + 7) / 8;
   hipLaunchKernelGGL(k_radix_zero, dim3(passes), dim3(256), 0, st, ctx->radix_total);
   int cur = 0;
@@ -374,7 +375,8 @@ static int radix_sort(kgs_ctx* ctx, const uint32_t* count, K* keys[2], uint32_t*
     hipLaunchKernelGGL(k_radix_scan, dim3(256), dim3(256), 0, st, ctx->radix_hist,
                        (const uint32_t*)(ctx->radix_total + 256 * p));
     hipLaunchKernelGGL(k_radix_scatter<K>, dim3(KGS_SORT_BLOCKS), dim3(256), 0, st, count, (const K*)keys[cur],
-                       (const uint32_t*)vals[cur], 8 * p, (const uint32_t*)ctx->radix_hist, keys[cur ^ 1],
+                       (p == 0 && vals_in) ? vals_in : (const uint32_t*)vals[cur], 8 * p,
+                       (const uint32_t*)ctx->radix_hist, keys[cur ^ 1],
                        vals[cur ^ 1]);
     cur ^= 1;
   }
@@ -409,13 +411,16 @@ kgs_status kgs_launch_bin_sort(kgs_ctx* ctx, hipStream_t st) {
   const unsigned pg = (unsigned)std::min<uint64_t>(std::max<uint64_t>(chunks, 1), 4096);
   hipLaunchKernelGGL(k_emit_pairs, dim3(pg), dim3(256), 0, st, (const uint32_t*)ctx->counters, perm,
                      (const uint32_t*)pref, (const uint32_t*)ctx->slot_view, (const int4*)ctx->slot_pix,
-                     ctx->cfg.tile_w, ctx->cfg.tile_h, ctx->tiles_x, ctx->tiles_y, ctx->keys[0], ctx->vals[0]);
+                     ctx->cfg.tile_w, ctx->cfg.tile_h, ctx->tiles_x, ctx->tiles_y, ctx->keys[0], ctx->pair_slot);
   // 3. pairs by tile (stable)
   // padding pairs carry key 0xffffffff; with n_tiles_all < 2^tile_bits they
   // sort after every real pair
   int tile_bits = 0;
   while ((1u << tile_bits) <= n_tiles_all) ++tile_bits;
-  const int cur = radix_sort<uint32_t>(ctx, ctx->counters + 1, ctx->keys, ctx->vals, std::max(tile_bits, 1), st);
+  // the first pass reads the emission-order slots from pair_slot, which stays
+  // intact for the backward's segmented sums
+  const int cur = radix_sort<uint32_t>(ctx, ctx->counters + 1, ctx->keys, ctx->vals, std::max(tile_bits, 1), st,
+                                       ctx->pair_slot);
   ctx->sorted_buf = cur;
   ctx->passes = (tile_bits + 7) / 8;
   const uint64_t nr = (uint64_t)n_tiles_all * 2;

@@ -180,8 +180,9 @@ def test_chunk_scores_and_decision_match_lifecycle_rules(chunk):
 
 def test_batched_chunk_equals_per_view_loop(chunk):
     """All views in one call against one view per call on a one-view context:
-    images, losses, pose gradients, footprint sums and decisions identical;
-    the parameter gradients, summed in a different order, within FP32 rounding."""
+    images, losses, footprint sums and decisions identical; the parameter and
+    pose gradients, summed in a different order (per-view sums and slot sums
+    whose pairs sit at other offsets of the emission), within FP32 rounding."""
     sc = chunk
     say("[gpu] batched vs per-view loop")
     R = _rast(sc)
@@ -205,7 +206,7 @@ def test_batched_chunk_equals_per_view_loop(chunk):
     p.dec.copy_(dec)
     torch.cuda.synchronize()
     loop = p.outputs()
-    exact = {0, 1, 2, 3, 4, 5, 11, 12, 13, 16, 17, 18, 20}
+    exact = {0, 1, 2, 3, 4, 5, 12, 13, 16, 17, 18, 20}
     for k, (x, y) in enumerate(zip(batched, loop)):
         if k in exact:
             assert torch.equal(x, y), k
