@@ -11,7 +11,7 @@
 
 #define KGS_BLOCK 256                 // threads per block for per-Gaussian / per-tile kernels
 #define KGS_MAX_VIEWS 64
-#define KGS_SORT_BLOCKS 512           // fixed grid of the radix sort passes
+#define KGS_SORT_BLOCKS 1024          // fixed grid (one partition per block) of the radix sort passes
 #define KGS_LOSS_BLOCKS 64            // blocks per view of the loss reduction
 #define KGS_MAX_PASSES 8
 #define KGS_POSE_BLOCKS 32            // pieces per view of the pose reduction
@@ -67,7 +67,7 @@ struct kgs_ctx {
   uint32_t* sorted_slot;              // [P] slot of each sorted pair (the sort's value buffer)
   uint2* ranges;                      // [max_views * max_tiles]
   float4* pair_grad;                  // [P][3] per-pair record-space gradients + counts
-  uint32_t* radix_hist;               // [256][KGS_SORT_BLOCKS * 4] per-wave partitions
+  uint32_t* radix_hist;               // [256][KGS_SORT_BLOCKS] digit counts, then offsets, per partition
   uint32_t* radix_total;              // [KGS_MAX_PASSES][256]
   float4* slot_bwd;                   // [S][KGS_SLOT_WORDS / 4] per-slot backward records
   uint32_t* pair_slot;                // [P] slot of every pair, emission order

@@ -8,66 +8,61 @@
 //      counts gives each record's first pair), one per tile of the record's
 //      rectangle, keyed by the global tile index only;
 //   3. the pairs are sorted stably by tile -- 14 bits at 1242x375 x 8 views,
-//      two 8-bit passes over 4-byte keys and values.
+//      two 7-bit passes over 4-byte keys and values.
 // Stability makes the result identical to one sort by the full key.
 //
-// The radix sort is LSD, reduce-then-scan, with one partition per wave: each
-// wave histograms and scatters its contiguous range on its own (ranks from
-// ballots, running digit offsets in the wave's own LDS row), so the scatter
-// needs no block barriers.  Counts stay on the device, so the sequence can be
-// captured in a graph.
+// The radix sort is LSD, reduce-then-scan, with one contiguous partition per
+// block; a pass of B total bits uses ceil(B / 8) passes of equal digit width
+// (14 bits: two 7-bit passes of 128 buckets).  The scatter ranks a tile of
+// 256 x KPT keys in index order (ballot matching inside a wave, running digit
+// counts per wave, a digit-major prefix over the waves), places the tile in
+// LDS in digit order, and writes it out so that consecutive lanes write
+// consecutive addresses of a digit's run.  Counts stay on the device, so the
+// sequence can be captured in a graph.
 #include <algorithm>
 
 #include "kgs_internal.h"
 
-#define RS_WAVES 4
-#define RS_PARTS (KGS_SORT_BLOCKS * RS_WAVES)
+#define RS_BLOCKS KGS_SORT_BLOCKS
 
-__device__ __forceinline__ void part_range(uint32_t n, uint32_t part, uint32_t& lo, uint32_t& hi) {
-  const uint32_t per = ((n + RS_PARTS - 1) / RS_PARTS + 63u) & ~63u;
-  lo = min(n, part * per);
+// partition of block b: a multiple of 256 keys
+__device__ __forceinline__ void part_range(uint32_t n, uint32_t b, uint32_t& lo, uint32_t& hi) {
+  const uint32_t per = ((n + RS_BLOCKS - 1) / RS_BLOCKS + 255u) & ~255u;
+  lo = min(n, b * per);
   hi = min(n, lo + per);
 }
 
 __global__ void k_radix_zero(uint32_t* __restrict__ total) { total[blockIdx.x * 256 + threadIdx.x] = 0u; }
 
-// per-wave digit histograms: hist[d][part]; each lane keeps RS_KPT loads in flight
-#define RS_KPT 8
+// per-block digit histograms: hist[d][block]
 template <typename K>
 __global__ __launch_bounds__(256) void k_radix_hist(const uint32_t* __restrict__ count, const K* __restrict__ keys,
-                                                    int shift, uint32_t* __restrict__ hist,
+                                                    int shift, uint32_t dmask, uint32_t* __restrict__ hist,
                                                     uint32_t* __restrict__ total) {
-  __shared__ uint32_t h[RS_WAVES][256];
-  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
-#pragma unroll
-  for (int k = 0; k < RS_WAVES; ++k) h[k][tid] = 0u;
+  __shared__ uint32_t h[256];
+  const int tid = threadIdx.x;
+  h[tid] = 0u;
   __syncthreads();
-  const uint32_t part = blockIdx.x * RS_WAVES + w;
   uint32_t lo, hi;
-  part_range(*count, part, lo, hi);
-  for (uint32_t base = lo; base < hi; base += 64 * RS_KPT) {
-    uint32_t d[RS_KPT];
+  part_range(*count, blockIdx.x, lo, hi);
+  for (uint32_t base = lo; base < hi; base += 256 * 8) {
+    uint32_t d[8];
 #pragma unroll
-    for (int q = 0; q < RS_KPT; ++q) {
-      const uint32_t i = base + q * 64 + l;
-      d[q] = i < hi ? (uint32_t)(keys[i] >> shift) & 255u : 256u;
+    for (int q = 0; q < 8; ++q) {
+      const uint32_t i = base + q * 256 + tid;
+      d[q] = i < hi ? (uint32_t)(keys[i] >> shift) & dmask : 256u;
     }
 #pragma unroll
-    for (int q = 0; q < RS_KPT; ++q)
-      if (d[q] < 256u) atomicAdd(&h[w][d[q]], 1u);
+    for (int q = 0; q < 8; ++q)
+      if (d[q] < 256u) atomicAdd(&h[d[q]], 1u);
   }
   __syncthreads();
-  uint32_t sum = 0;
-#pragma unroll
-  for (int k = 0; k < RS_WAVES; ++k) {
-    const uint32_t c = h[k][tid];
-    hist[(size_t)tid * RS_PARTS + blockIdx.x * RS_WAVES + k] = c;
-    sum += c;
-  }
-  if (sum) atomicAdd(&total[tid], sum);
+  const uint32_t c = h[tid];
+  hist[(size_t)tid * RS_BLOCKS + blockIdx.x] = c;
+  if (c) atomicAdd(&total[tid], c);
 }
 
-// one block per digit: exclusive scan of its row of partition counts, plus the
+// one block per digit: exclusive scan of its row of block counts, plus the
 // total of all smaller digits
 __global__ __launch_bounds__(256) void k_radix_scan(uint32_t* __restrict__ hist, const uint32_t* __restrict__ total) {
   __shared__ uint32_t sh[8];
@@ -76,11 +71,11 @@ __global__ __launch_bounds__(256) void k_radix_scan(uint32_t* __restrict__ hist,
   for (int k = tid; k < d; k += 256) pre += total[k];
   pre = wave_sum(pre);
   if (l == 0) sh[4 + w] = pre;
-  constexpr int PER = RS_PARTS / 256;
+  constexpr int PER = RS_BLOCKS / 256;
   uint32_t v[PER], s = 0;
 #pragma unroll
   for (int k = 0; k < PER; ++k) {
-    v[k] = hist[(size_t)d * RS_PARTS + tid * PER + k];
+    v[k] = hist[(size_t)d * RS_BLOCKS + tid * PER + k];
     s += v[k];
   }
   const uint32_t inc = wave_inclusive_scan(s);
@@ -91,33 +86,41 @@ __global__ __launch_bounds__(256) void k_radix_scan(uint32_t* __restrict__ hist,
   off += inc - s;
 #pragma unroll
   for (int k = 0; k < PER; ++k) {
-    hist[(size_t)d * RS_PARTS + tid * PER + k] = off;
+    hist[(size_t)d * RS_BLOCKS + tid * PER + k] = off;
     off += v[k];
   }
 }
 
-// stable scatter: every wave walks its partition RS_KPT x 64 keys at a time
-// (all loads issued first, then ranked in index order)
-template <typename K>
+// Stable scatter of one block's partition, a tile of 256 x KPT keys at a time.
+// Wave w ranks keys [w * 64 KPT, (w + 1) * 64 KPT) of the tile in index order.
+template <typename K, int KPT>
 __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t* __restrict__ count, const K* __restrict__ kin,
-                                                       const uint32_t* __restrict__ vin, int shift,
+                                                       const uint32_t* __restrict__ vin, int shift, int dbits,
                                                        const uint32_t* __restrict__ offsets, K* __restrict__ kout,
                                                        uint32_t* __restrict__ vout) {
-  __shared__ uint32_t run[RS_WAVES][256];
+  constexpr uint32_t TILE = 256 * KPT;
+  __shared__ K lk[TILE];
+  __shared__ uint32_t lv[TILE];
+  __shared__ uint32_t wc[4][256];     // running digit counts of each wave, then the waves' digit prefixes
+  __shared__ uint32_t dstart[256], gofs[256];
+  __shared__ uint32_t sh[4];
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
-  const uint32_t part = blockIdx.x * RS_WAVES + w;
+  const uint32_t R = 1u << dbits, dmask = R - 1u;
+  gofs[tid] = (uint32_t)tid < R ? offsets[(size_t)tid * RS_BLOCKS + blockIdx.x] : 0u;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) run[w][l + 64 * k] = offsets[(size_t)(l + 64 * k) * RS_PARTS + part];
-  __builtin_amdgcn_wave_barrier();
+  for (int k = 0; k < 4; ++k) wc[k][tid] = 0u;
   uint32_t lo, hi;
-  part_range(*count, part, lo, hi);
+  part_range(*count, blockIdx.x, lo, hi);
   const uint64_t lt = (1ull << l) - 1ull;
-  for (uint32_t base = lo; base < hi; base += 64 * RS_KPT) {
-    K kk[RS_KPT];
-    uint32_t vv[RS_KPT];
+  __syncthreads();
+  for (uint32_t tb = lo; tb < hi; tb += TILE) {
+    const uint32_t tn = min(TILE, hi - tb);
+    const uint32_t wb = tb + (uint32_t)w * (64u * KPT);
+    K kk[KPT];
+    uint32_t vv[KPT], rk[KPT];
 #pragma unroll
-    for (int q = 0; q < RS_KPT; ++q) {
-      const uint32_t i = base + q * 64 + l;
+    for (int q = 0; q < KPT; ++q) {
+      const uint32_t i = wb + q * 64 + l;
       kk[q] = 0;
       vv[q] = 0;
       if (i < hi) {
@@ -126,26 +129,59 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t* __restric
       }
     }
 #pragma unroll
-    for (int q = 0; q < RS_KPT; ++q) {
-      const bool valid = base + q * 64 + l < hi;
-      const uint32_t d = valid ? (uint32_t)(kk[q] >> shift) & 255u : 0u;
+    for (int q = 0; q < KPT; ++q) {
+      const bool valid = wb + q * 64 + l < hi;
+      const uint32_t d = (uint32_t)(kk[q] >> shift) & dmask;
       uint64_t peers = ballot64(valid);
-#pragma unroll
-      for (int bit = 0; bit < 8; ++bit) {
-        const uint64_t b = ballot64((d >> bit) & 1u);
-        peers &= ((d >> bit) & 1u) ? b : ~b;
+      for (int bit = 0; bit < dbits; ++bit) {
+        const bool on = (d >> bit) & 1u;
+        const uint64_t b = ballot64(on);
+        peers &= on ? b : ~b;
       }
-      const uint32_t rank = (uint32_t)__popcll(peers & lt);
-      uint32_t pos = 0;
-      if (valid) pos = run[w][d] + rank;
+      const uint32_t r = (uint32_t)__popcll(peers & lt);
+      const uint32_t before = valid ? wc[w][d] : 0u;
       __builtin_amdgcn_wave_barrier();
-      if (valid) {
-        kout[pos] = kk[q];
-        vout[pos] = vv[q];
-        if (rank == 0) run[w][d] += (uint32_t)__popcll(peers);
-      }
+      if (valid && r == 0) wc[w][d] = before + (uint32_t)__popcll(peers);
+      rk[q] = before + r;
       __builtin_amdgcn_wave_barrier();
     }
+    __syncthreads();
+    // digit-major prefix: digit start in the tile, then the waves in order
+    const uint32_t c0 = wc[0][tid], c1 = wc[1][tid], c2 = wc[2][tid], c3 = wc[3][tid];
+    const uint32_t tot = c0 + c1 + c2 + c3;
+    const uint32_t inc = wave_inclusive_scan(tot);
+    if (l == 63) sh[w] = inc;
+    __syncthreads();
+    uint32_t ex = inc - tot;
+    for (int k = 0; k < w; ++k) ex += sh[k];
+    dstart[tid] = ex;
+    wc[0][tid] = ex;
+    wc[1][tid] = ex + c0;
+    wc[2][tid] = ex + c0 + c1;
+    wc[3][tid] = ex + c0 + c1 + c2;
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < KPT; ++q) {
+      if (wb + q * 64 + l < hi) {
+        const uint32_t d = (uint32_t)(kk[q] >> shift) & dmask;
+        const uint32_t pos = wc[w][d] + rk[q];
+        lk[pos] = kk[q];
+        lv[pos] = vv[q];
+      }
+    }
+    __syncthreads();
+    for (uint32_t i = (uint32_t)tid; i < tn; i += 256) {
+      const K key = lk[i];
+      const uint32_t d = (uint32_t)(key >> shift) & dmask;
+      const uint32_t g = gofs[d] + (i - dstart[d]);
+      kout[g] = key;
+      vout[g] = lv[i];
+    }
+    __syncthreads();
+    gofs[tid] += tot;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) wc[k][tid] = 0u;
+    __syncthreads();
   }
 }
 
@@ -367,17 +403,20 @@ template <typename K>
 static int radix_sort(kgs_ctx* ctx, const uint32_t* count, K* keys[2], uint32_t* vals[2], int bits, hipStream_t st,
                       const uint32_t* vals_in = nullptr) {
   const int passes = (bits + 7) / 8;
+  const int dbits = (bits + passes - 1) / passes;
+  const uint32_t dmask = (1u << dbits) - 1u;
+  constexpr int KPT = sizeof(K) == 8 ? 8 : 16;
   hipLaunchKernelGGL(k_radix_zero, dim3(passes), dim3(256), 0, st, ctx->radix_total);
   int cur = 0;
   for (int p = 0; p < passes; ++p) {
-    hipLaunchKernelGGL(k_radix_hist<K>, dim3(KGS_SORT_BLOCKS), dim3(256), 0, st, count, (const K*)keys[cur], 8 * p,
+    const int shift = dbits * p;
+    hipLaunchKernelGGL(k_radix_hist<K>, dim3(RS_BLOCKS), dim3(256), 0, st, count, (const K*)keys[cur], shift, dmask,
                        ctx->radix_hist, ctx->radix_total + 256 * p);
-    hipLaunchKernelGGL(k_radix_scan, dim3(256), dim3(256), 0, st, ctx->radix_hist,
+    hipLaunchKernelGGL(k_radix_scan, dim3(1u << dbits), dim3(256), 0, st, ctx->radix_hist,
                        (const uint32_t*)(ctx->radix_total + 256 * p));
-    hipLaunchKernelGGL(k_radix_scatter<K>, dim3(KGS_SORT_BLOCKS), dim3(256), 0, st, count, (const K*)keys[cur],
-                       (p == 0 && vals_in) ? vals_in : (const uint32_t*)vals[cur], 8 * p,
-                       (const uint32_t*)ctx->radix_hist, keys[cur ^ 1],
-                       vals[cur ^ 1]);
+    hipLaunchKernelGGL((k_radix_scatter<K, KPT>), dim3(RS_BLOCKS), dim3(256), 0, st, count, (const K*)keys[cur],
+                       (p == 0 && vals_in) ? vals_in : (const uint32_t*)vals[cur], shift, dbits,
+                       (const uint32_t*)ctx->radix_hist, keys[cur ^ 1], vals[cur ^ 1]);
     cur ^= 1;
   }
   return cur;
