@@ -194,14 +194,29 @@ __device__ __forceinline__ void slot_record(uint32_t s, const kgs_gaussians& g, 
                      P.tile_h, P.tiles_x, P.tiles_y, p)) {
       float gm[3] = {0.f, 0.f, 0.f}, gls[3] = {0.f, 0.f, 0.f}, gq[4] = {0.f, 0.f, 0.f, 0.f};
       float pose[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      // pixel moments (ge u, ge dy, ge u^2, ge u dy, ge dy^2, ge) summed over
+      // the slot's pixels -> derivatives of log2 alpha = log2 o + P' u^2 +
+      // E' dy^2, u = dx + k dy, in the record's mean, P', k, E' and log2 o
+      // (dx, dy fall with the mean); ge is dL/d(log2 alpha) / ln 2
+      float rr[6];
+      {
+        const float Pq = -h * p.Pc, Eq = -h * p.Ec;
+        const float m0 = r[0] * LN2, m1 = r[1] * LN2;
+        rr[0] = -2.0f * Pq * m0;
+        rr[1] = -2.0f * (Pq * p.kc * m0 + Eq * m1);
+        rr[2] = r[2] * LN2;
+        rr[3] = 2.0f * Pq * (r[3] * LN2);
+        rr[4] = r[4] * LN2;
+        rr[5] = r[5] * LN2;
+      }
       out[17] = __uint_as_float(om);
       out[18] = __uint_as_float(kap);
-      out[19] = sqrtf(r[0] * r[0] + r[1] * r[1]);
+      out[19] = sqrtf(rr[0] * rr[0] + rr[1] * rr[1]);
       out[20] = __int_as_float(max(p.rx, p.ry));
         float Yb_out[16];
         // record space -> pivoted conic (P, k, E) and opacity
-        const float gP = -h * r[2], gk = r[3], gE = -h * r[4];
-        out[10] = r[5] * (1.0f - G.o) / LN2;
+        const float gP = -h * rr[2], gk = rr[3], gE = -h * rr[4];
+        out[10] = r[5] * (1.0f - G.o);
         // P = S11 / det, k = -S01 / S11, E = 1 / S11
         const float gS11 = gP / p.det - (gk * p.kc + gE * p.Ec) * p.Ec;
         const float gS01 = -gk * p.Ec;
@@ -271,8 +286,8 @@ __device__ __forceinline__ void slot_record(uint32_t s, const kgs_gaussians& g, 
         }
         // camera-frame point gradient
         const float tx = p.tx, ty = p.ty, tz = p.tz, iz = 1.0f / tz, iz2 = iz * iz;
-        float gtx = r[0] * c.fx * iz, gty = r[1] * c.fy * iz;
-        float gtz = -(r[0] * c.fx * tx + r[1] * c.fy * ty) * iz2 + r[9];
+        float gtx = rr[0] * c.fx * iz, gty = rr[1] * c.fy * iz;
+        float gtz = -(rr[0] * c.fx * tx + rr[1] * c.fy * ty) * iz2 + r[9];
         gtz += -2.0f * gK * p.K * iz;
         gtz += -(gJ00 * c.fx + gJ11 * c.fy) * iz2;
         gux += -gJ02 * c.fx * iz;

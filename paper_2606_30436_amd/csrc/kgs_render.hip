@@ -23,13 +23,42 @@ struct RenderParams {
   float bg0, bg1, bg2;
 };
 
-// Stage B pairs of [base, end) into LDS and build the per-wave lists.
+// Whether the footprint {log2 alpha >= log2 alpha_min} of a record can reach
+// the pixel-centre box [x0, x1] x [y0, y1] (record coordinates): the minimum
+// of q = A (x + k y)^2 + C y^2 over the box (A = -P', C = -E') against
+// tau = log2 o - log2 alpha_min.  q is convex, so the minimum is 0 with the
+// centre inside the box, else on an edge: y = y0 or y1 at x = clamp(-k y),
+// x = x0 or x1 at y = clamp(-A k x / (A k^2 + C)).  The margin keeps the test
+// conservative against the rounding of the per-pixel evaluation.
+__device__ __forceinline__ bool footprint_meets_box(float x0, float x1, float y0, float y1, const float4& r0,
+                                                    const float4& r1, float log2_amin) {
+  const float A = -r0.z, k = r0.w, C = -r1.x;
+  const float tau = r1.y - log2_amin;
+  if (x0 <= 0.f && x1 >= 0.f && y0 <= 0.f && y1 >= 0.f) return true;
+  const float s = A * k * __builtin_amdgcn_rcpf(fmaf(A * k, k, C));
+  float f;
+  {
+    const float xa = fminf(fmaxf(-k * y0, x0), x1), ua = fmaf(k, y0, xa);
+    const float xb = fminf(fmaxf(-k * y1, x0), x1), ub = fmaf(k, y1, xb);
+    f = fminf(fmaf(A * ua, ua, C * y0 * y0), fmaf(A * ub, ub, C * y1 * y1));
+  }
+  {
+    const float ya = fminf(fmaxf(-s * x0, y0), y1), ua = fmaf(k, ya, x0);
+    const float yb = fminf(fmaxf(-s * x1, y0), y1), ub = fmaf(k, yb, x1);
+    f = fminf(f, fminf(fmaf(A * ua, ua, C * ya * ya), fmaf(A * ub, ub, C * yb * yb)));
+  }
+  return f <= tau + 1e-3f * (1.0f + tau);
+}
+
+// Stage B pairs of [base, end) into LDS and build the per-wave lists: a wave's
+// list holds the pairs whose pixel rectangle meets its 8x8 sub-block and whose
+// footprint reaches the sub-block's pixel centres.
 template <int B>
 __device__ __forceinline__ void stage_batch(uint32_t base, uint32_t end, const uint32_t* __restrict__ sorted_slot,
                                             const float4* __restrict__ slot_rec, int tile_x0, int tile_y0,
-                                            int tile_w, float4* s_r0, float4* s_r1, float4* s_r2,
-                                            uint32_t* s_slot, uint8_t* s_mask, uint8_t (*s_list)[B],
-                                            uint32_t (*s_cnt)[4]) {
+                                            int tile_w, int ox, int oy, float log2_amin, float4* s_r0,
+                                            float4* s_r1, float4* s_r2, uint32_t* s_slot, uint8_t* s_mask,
+                                            uint8_t (*s_list)[B], uint32_t (*s_cnt)[4]) {
   const int tid = threadIdx.x, w = tid >> 6;
   uint32_t m = 0;
   if (tid < B) {
@@ -49,7 +78,10 @@ __device__ __forceinline__ void stage_batch(uint32_t base, uint32_t end, const u
         int sx, sy;
         tile_subblock(tile_w, ww, sx, sy);
         const int bx = tile_x0 + sx, by = tile_y0 + sy;
-        if (xlo <= bx + 7 && xhi >= bx && ylo <= by + 7 && yhi >= by) m |= 1u << ww;
+        if (xlo <= bx + 7 && xhi >= bx && ylo <= by + 7 && yhi >= by) {
+          const float fx0 = (float)(bx - ox) - r0.x, fy0 = (float)(by - oy) - r0.y;
+          if (footprint_meets_box(fx0, fx0 + 7.0f, fy0, fy0 + 7.0f, r0, r1, log2_amin)) m |= 1u << ww;
+        }
       }
     }
     s_mask[tid] = (uint8_t)m;
@@ -102,7 +134,8 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_render_fwd(RenderParams P, const 
   bool done = !inside;
   for (uint32_t base = start; base < end; base += B) {
     if (__syncthreads_count(!done) == 0) break;
-    stage_batch<B>(base, end, sorted_slot, slot_rec, tile_x0, tile_y0, P.tile_w, s_r0, s_r1, s_r2, s_slot, s_mask,
+    stage_batch<B>(base, end, sorted_slot, slot_rec, tile_x0, tile_y0, P.tile_w, pix_origin(P.W), pix_origin(P.H),
+                   P.log2_amin, s_r0, s_r1, s_r2, s_slot, s_mask,
                    s_list, s_cnt);
     const uint32_t len = __builtin_amdgcn_readfirstlane(s_cnt[0][w] + s_cnt[1][w] + s_cnt[2][w] + s_cnt[3][w]);
     const int rel0 = (int)(base - start) + 1;
@@ -297,12 +330,16 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_render_bwd(
   __syncthreads();
   const int bmax = max(max(s_wmax[0], s_wmax[1]), max(s_wmax[2], s_wmax[3]));
   const uint32_t pend = start + (uint32_t)bmax;
-  float T = 1.0f, Ca0 = 0.f, Ca1 = 0.f, Ca2 = 0.f, Da = 0.f;
-  const float LN2 = 0.69314718055994531f;
+  // dL/dalpha_j = T_j (g . c_j) - (g . (C - C_j)) / (1 - alpha_j) + gAT / (1 - alpha_j)
+  // with C the final colour (and depth) and C_j its part from Gaussians up to j;
+  // Rj = gAT - g . C + g . C_j is kept as one running scalar
+  float T = 1.0f;
+  float Rj = gAT - (g0 * Co0 + g1 * Co1 + g2 * Co2 + gD * Do);
   uint32_t base = start;
   for (; base < pend; base += B) {
     __syncthreads();
-    stage_batch<B>(base, end, sorted_slot, slot_rec, tile_x0, tile_y0, P.tile_w, s_r0, s_r1, s_r2, s_slot, s_mask,
+    stage_batch<B>(base, end, sorted_slot, slot_rec, tile_x0, tile_y0, P.tile_w, pix_origin(P.W), pix_origin(P.H),
+                   P.log2_amin, s_r0, s_r1, s_r2, s_slot, s_mask,
                    s_list, s_cnt);
     const uint32_t len = __builtin_amdgcn_readfirstlane(s_cnt[0][w] + s_cnt[1][w] + s_cnt[2][w] + s_cnt[3][w]);
     const int rel0 = (int)(base - start);
@@ -326,29 +363,29 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_render_bwd(
       const float raw = exp2_approx(e);
       const float a = bl ? fminf(raw, P.amax) : 0.f;
       const float wgt = a * T;
-      Ca0 = fmaf(wgt, r2.x, Ca0);
-      Ca1 = fmaf(wgt, r2.y, Ca1);
-      Ca2 = fmaf(wgt, r2.z, Ca2);
-      Da = fmaf(wgt, r1.z, Da);
-      const float om = __builtin_amdgcn_rcpf(1.0f - a);
-      const float dLda = g0 * (T * r2.x - (Co0 - Ca0) * om) + g1 * (T * r2.y - (Co1 - Ca1) * om) +
-                         g2 * (T * r2.z - (Co2 - Ca2) * om) + gD * (T * r1.z - (Do - Da) * om) + gAT * om;
+      const float gc = fmaf(gD, r1.z, fmaf(g2, r2.z, fmaf(g1, r2.y, g0 * r2.x)));
+      Rj = fmaf(wgt, gc, Rj);
+      const float oma = 1.0f - a;
+      const float dLda = fmaf(T, gc, Rj * __builtin_amdgcn_rcpf(oma));
       float x[10];
       x[6] = wgt * g0;
       x[7] = wgt * g1;
       x[8] = wgt * g2;
       x[9] = wgt * gD;
-      // the clamp at alpha_max cuts the derivative of alpha in o and q
-      const float ge = raw < P.amax ? dLda * a * LN2 : 0.f;
-      // d(log2 alpha) / d(mu_x, mu_y, P', k, E')
-      const float pu = 2.0f * r0.z * u;
-      x[0] = -ge * pu;
-      x[1] = -ge * fmaf(pu, r0.w, 2.0f * r1.x * dy);
-      x[2] = ge * u * u;
-      x[3] = ge * pu * dy;
-      x[4] = ge * dy * dy;
+      // ge = dL/d(log2 alpha) / ln 2; the clamp at alpha_max cuts the
+      // derivative of alpha in o and q.  With log2 alpha = log2 o + P' u^2 +
+      // E' dy^2, u = dx + k dy, the pixel's moments (ge u, ge dy, ge u^2,
+      // ge u dy, ge dy^2, ge) give every record-space derivative once the
+      // pair's P', k, E' and ln 2 are applied to their sums.
+      const float ge = raw < P.amax ? dLda * a : 0.f;
+      const float gu = ge * u, gd = ge * dy;
+      x[0] = gu;
+      x[1] = gd;
+      x[2] = gu * u;
+      x[3] = gu * dy;
+      x[4] = gd * dy;
       x[5] = ge;
-      T = T * (1.0f - a);
+      T = T * oma;
       const uint64_t bm = ballot64(bl && M);
       int idx;
       bool valid;
