@@ -76,6 +76,7 @@ size_t layout(const kgs_config& c, char* base, kgs_ctx* ctx) {
   p = take(4 * S);                              if (ctx) ctx->slot_vals[1] = (uint32_t*)p;
   p = take(4 * (S / 64 + 2));                   if (ctx) ctx->group_part = (uint32_t*)p;
   p = take(8 * V * T);                          if (ctx) ctx->ranges = (uint2*)p;
+  p = take(4 * V * T);                          if (ctx) ctx->tile_order = (uint32_t*)p;
   p = take(48 * P);                             if (ctx) ctx->pair_grad = (float4*)p;
   p = take(4 * 256 * KGS_SORT_BLOCKS);          if (ctx) ctx->radix_hist = (uint32_t*)p;
   p = take(4 * 256 * KGS_MAX_PASSES);           if (ctx) ctx->radix_total = (uint32_t*)p;

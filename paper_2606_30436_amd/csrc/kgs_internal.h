@@ -66,6 +66,7 @@ struct kgs_ctx {
   uint32_t* group_part;               // [S / 64 + 2] group partials of the pair-offset scan
   uint32_t* sorted_slot;              // [P] slot of each sorted pair (the sort's value buffer)
   uint2* ranges;                      // [max_views * max_tiles]
+  uint32_t* tile_order;               // [max_views * max_tiles] compositing launch order, heaviest first
   float4* pair_grad;                  // [P][3] per-pair record-space gradients + counts
   uint32_t* radix_hist;               // [256][KGS_SORT_BLOCKS] digit counts, then offsets, per partition
   uint32_t* radix_total;              // [KGS_MAX_PASSES][256]

@@ -108,6 +108,7 @@ __device__ __forceinline__ void stage_batch(uint32_t base, uint32_t end, const u
 
 template <int B>
 __global__ __launch_bounds__(KGS_BLOCK) void k_render_fwd(RenderParams P, const uint2* __restrict__ ranges,
+                                                          const uint32_t* __restrict__ tile_order,
                                                           const uint32_t* __restrict__ sorted_slot,
                                                           const float4* __restrict__ slot_rec,
                                                           float* __restrict__ color, float* __restrict__ depth,
@@ -118,7 +119,7 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_render_fwd(RenderParams P, const 
   __shared__ uint8_t s_mask[B];
   __shared__ uint32_t s_cnt[4][4];
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
-  const int gt = blockIdx.x;
+  const int gt = (int)tile_order[blockIdx.x];
   const int v = gt / P.n_tiles, t = gt - v * P.n_tiles;
   const int tx = t % P.tiles_x, ty = t / P.tiles_x;
   const int tile_x0 = tx * P.tile_w, tile_y0 = ty * P.tile_h;
@@ -258,6 +259,74 @@ __device__ __forceinline__ void wave_reduce10(float (&x)[10], int lane, int& idx
   idx = ((lane & 32) ? 5 : 0) + rel;
 }
 
+// The same for twenty values (two pairs): lane halves, row pairs, mirrored
+// lanes of a row (five values to three), of a half-row (three to two), then
+// the lane pair inside a quad (two to one) and the other quad pair.  Lanes
+// with valid set hold the full wave sum of value idx.
+__device__ __forceinline__ void wave_reduce20(float (&x)[20], int lane, int& idx, bool& valid) {
+  const bool u4 = lane & 16, u3 = lane & 8, u2 = lane & 4, u0 = lane & 1;
+#pragma unroll
+  for (int k = 0; k < 10; ++k) x[k] = f_swap_sum32(x[k], x[k + 10]);
+#pragma unroll
+  for (int k = 0; k < 5; ++k) x[k] = f_swap_sum16(x[k], x[k + 5]);
+  {
+    const float s0 = u3 ? x[0] : x[3], k0 = u3 ? x[3] : x[0];
+    const float s1 = u3 ? x[1] : x[4], k1 = u3 ? x[4] : x[1];
+    const float s2 = u3 ? x[2] : 0.f, k2 = u3 ? 0.f : x[2];
+    x[0] = k0 + f_dpp<0x140>(s0);
+    x[1] = k1 + f_dpp<0x140>(s1);
+    x[2] = k2 + f_dpp<0x140>(s2);
+  }
+  {
+    const float s0 = u2 ? x[0] : x[2], k0 = u2 ? x[2] : x[0];
+    const float s1 = u2 ? x[1] : 0.f, k1 = u2 ? 0.f : x[1];
+    x[0] = k0 + f_dpp<0x141>(s0);
+    x[1] = k1 + f_dpp<0x141>(s1);
+  }
+  {
+    const float s0 = u0 ? x[0] : x[1], k0 = u0 ? x[1] : x[0];
+    x[0] = k0 + f_dpp<0xB1>(s0);
+  }
+  x[0] += f_dpp<0x4E>(x[0]);
+  const int rel = (u3 ? 3 : 0) + (u2 ? 2 : 0) + (u0 ? 1 : 0);
+  valid = (u3 ? rel <= 4 : rel <= 2) && ((lane & 2) == 0);
+  idx = ((lane & 32) ? 10 : 0) + (u4 ? 5 : 0) + rel;
+}
+
+// Per-pixel terms of one blended pair in the backward (lanes that do not blend
+// carry alpha = 0, which zeroes every term and leaves T and Rj unchanged).
+//   dL/dalpha_j = T_j (g . c_j) + Rj / (1 - alpha_j)
+// with Rj = gAT - g . C + g . C_j (C the final colour and depth, C_j its part
+// from Gaussians up to j).  x[0..5] are the moments (ge u, ge dy, ge u^2,
+// ge u dy, ge dy^2, ge) with ge = dL/d(log2 alpha) / ln 2 (zero where alpha is
+// clamped at alpha_max): with log2 alpha = log2 o + P' u^2 + E' dy^2 and
+// u = dx + k dy, the pair's P', k, E' and ln 2 turn their sums into the
+// record-space derivatives.  x[6..9] = alpha_j T_j g (colour and depth).
+__device__ __forceinline__ void blend_terms(float e, float u, float dy, bool bl, const float4& r1, const float4& r2,
+                                            float amax, float g0, float g1, float g2, float gD, float& T, float& Rj,
+                                            float* __restrict__ x) {
+  const float raw = exp2_approx(e);
+  const float a = bl ? fminf(raw, amax) : 0.f;
+  const float wgt = a * T;
+  const float gc = fmaf(gD, r1.z, fmaf(g2, r2.z, fmaf(g1, r2.y, g0 * r2.x)));
+  Rj = fmaf(wgt, gc, Rj);
+  const float oma = 1.0f - a;
+  const float dLda = fmaf(T, gc, Rj * __builtin_amdgcn_rcpf(oma));
+  x[6] = wgt * g0;
+  x[7] = wgt * g1;
+  x[8] = wgt * g2;
+  x[9] = wgt * gD;
+  const float ge = raw < amax ? dLda * a : 0.f;
+  const float gu = ge * u, gd = ge * dy;
+  x[0] = gu;
+  x[1] = gd;
+  x[2] = gu * u;
+  x[3] = gu * dy;
+  x[4] = gd * dy;
+  x[5] = ge;
+  T = T * oma;
+}
+
 // Emission position of the pair (slot, tile (tx, ty)): the slot's first pair
 // plus the tile's row-major rank in the slot's tile rectangle, which is
 // recovered from the record's packed pixel bounds.
@@ -273,20 +342,21 @@ __device__ __forceinline__ uint32_t pair_position(uint32_t first, float xb_f, fl
 
 template <int B>
 __global__ __launch_bounds__(KGS_BLOCK) void k_render_bwd(
-    RenderParams P, const uint2* __restrict__ ranges, const uint32_t* __restrict__ sorted_slot,
+    RenderParams P, const uint2* __restrict__ ranges, const uint32_t* __restrict__ tile_order,
+    const uint32_t* __restrict__ sorted_slot,
     const uint32_t* __restrict__ slot_pairoff, const float4* __restrict__ slot_rec, const float* __restrict__ color,
     const float* __restrict__ depth, const float* __restrict__ tfinal, const int32_t* __restrict__ last,
     const float* __restrict__ dl_dcolor, const float* __restrict__ dl_ddepth, const float* __restrict__ dl_dalpha,
     const float* __restrict__ target, float tau_err, float4* __restrict__ pair_grad) {
   __shared__ float4 s_r0[B], s_r1[B], s_r2[B];
   __shared__ uint32_t s_slot[B];
-  __shared__ uint8_t s_list[4][B];
+  __shared__ __align__(16) uint8_t s_list[4][B];
   __shared__ uint8_t s_mask[B];
   __shared__ uint32_t s_cnt[4][4];
   __shared__ float s_part[4][B][12];
   __shared__ int s_wmax[4];
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
-  const int gt = blockIdx.x;
+  const int gt = (int)tile_order[blockIdx.x];
   const int v = gt / P.n_tiles, t = gt - v * P.n_tiles;
   const int tx = t % P.tiles_x, ty = t / P.tiles_x;
   const int tile_x0 = tx * P.tile_w, tile_y0 = ty * P.tile_h;
@@ -343,58 +413,69 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_render_bwd(
                    s_list, s_cnt);
     const uint32_t len = __builtin_amdgcn_readfirstlane(s_cnt[0][w] + s_cnt[1][w] + s_cnt[2][w] + s_cnt[3][w]);
     const int rel0 = (int)(base - start);
-    for (uint32_t j = 0; j < len; ++j) {
-      const int tt = __builtin_amdgcn_readfirstlane(s_list[w][j]);  // same entry for the whole wave
-      const int krel = rel0 + tt;
-      if (krel >= wmax) break;
-      const float4 r0 = s_r0[tt], r1 = s_r1[tt];
-      float dy, u;
-      const float e = log2_alpha(fpx, fpy, r0, r1.x, r1.y, dy, u);
-      const bool bl = krel < lastp && e >= P.log2_amin;
-      const uint64_t bb = ballot64(bl);
-      if (bb == 0ull) {
-        // no pixel of this wave blends the Gaussian: its partial is zero
-        if (l < 12) s_part[w][tt][l] = 0.f;
-        continue;
+    // list entries two at a time: a pair of entries that both blend shares one
+    // reduction of twenty values; otherwise the one that blends is reduced alone
+    // the wave's list in one register: lane i holds entries 4i .. 4i + 3 (one
+    // byte each), read back by lane index
+    static_assert(B <= 256 && B % 4 == 0, "list entries must pack four to a lane");
+    const uint32_t packed = 4 * l < B ? reinterpret_cast<const uint32_t*>(s_list[w])[l] : 0u;
+    auto entry = [&](uint32_t j) -> int {
+      return (int)((__builtin_amdgcn_readlane(packed, (int)(j >> 2)) >> (8u * (j & 3u))) & 0xffu);
+    };
+    for (uint32_t j = 0; j < len;) {
+      const int ta = entry(j);  // same entry for the whole wave
+      if (rel0 + ta >= wmax) break;
+      const bool has_b = j + 1 < len;
+      const int tb = entry(has_b ? j + 1 : j);
+      const bool use_b = has_b && rel0 + tb < wmax;
+      // both entries' records at once (the second is a repeat of the first when absent)
+      const float4 ra0 = s_r0[ta], ra1 = s_r1[ta], rb0 = s_r0[tb], rb1 = s_r1[tb];
+      float dya, ua, dyb, ub;
+      const float ea = log2_alpha(fpx, fpy, ra0, ra1.x, ra1.y, dya, ua);
+      const float eb = log2_alpha(fpx, fpy, rb0, rb1.x, rb1.y, dyb, ub);
+      const bool bla = rel0 + ta < lastp && ea >= P.log2_amin;
+      const bool blb = use_b && rel0 + tb < lastp && eb >= P.log2_amin;
+      const uint64_t bba = ballot64(bla), bbb = ballot64(blb);
+      if (bba != 0ull && bbb != 0ull) {
+        float x[20];
+        const float4 ra2 = s_r2[ta], rb2 = s_r2[tb];
+        blend_terms(ea, ua, dya, bla, ra1, ra2, P.amax, g0, g1, g2, gD, T, Rj, x);
+        blend_terms(eb, ub, dyb, blb, rb1, rb2, P.amax, g0, g1, g2, gD, T, Rj, x + 10);
+        const uint64_t bma = ballot64(bla && M), bmb = ballot64(blb && M);
+        int idx;
+        bool valid;
+        wave_reduce20(x, l, idx, valid);
+        if (valid) s_part[w][idx < 10 ? ta : tb][idx < 10 ? idx : idx - 10] = x[0];
+        if (l == 0) {
+          s_part[w][ta][10] = __uint_as_float((uint32_t)__popcll(bba));
+          s_part[w][ta][11] = __uint_as_float((uint32_t)__popcll(bma));
+          s_part[w][tb][10] = __uint_as_float((uint32_t)__popcll(bbb));
+          s_part[w][tb][11] = __uint_as_float((uint32_t)__popcll(bmb));
+        }
+      } else if ((bba | bbb) != 0ull) {
+        const bool first = bba != 0ull;
+        const int tt = first ? ta : tb, tz = first ? tb : ta;
+        const bool bl = first ? bla : blb;
+        float x[10];
+        blend_terms(first ? ea : eb, first ? ua : ub, first ? dya : dyb, bl, first ? ra1 : rb1, s_r2[tt], P.amax,
+                    g0, g1, g2, gD, T, Rj, x);
+        const uint64_t bm = ballot64(bl && M);
+        int idx;
+        bool valid;
+        wave_reduce10(x, l, idx, valid);
+        if (valid) s_part[w][tt][idx] = x[0];
+        if (l == 0) {
+          s_part[w][tt][10] = __uint_as_float((uint32_t)__popcll(first ? bba : bbb));
+          s_part[w][tt][11] = __uint_as_float((uint32_t)__popcll(bm));
+        }
+        // the other entry blends nowhere in this wave: its partial is zero
+        if (use_b && l < 12) s_part[w][tz][l] = 0.f;
+      } else {
+        if (l < 12) s_part[w][ta][l] = 0.f;
+        if (use_b && l < 12) s_part[w][tb][l] = 0.f;
       }
-      // from here every lane computes; lanes that do not blend carry a = 0,
-      // which zeroes all their terms and leaves T and the running sums alone
-      const float4 r2 = s_r2[tt];
-      const float raw = exp2_approx(e);
-      const float a = bl ? fminf(raw, P.amax) : 0.f;
-      const float wgt = a * T;
-      const float gc = fmaf(gD, r1.z, fmaf(g2, r2.z, fmaf(g1, r2.y, g0 * r2.x)));
-      Rj = fmaf(wgt, gc, Rj);
-      const float oma = 1.0f - a;
-      const float dLda = fmaf(T, gc, Rj * __builtin_amdgcn_rcpf(oma));
-      float x[10];
-      x[6] = wgt * g0;
-      x[7] = wgt * g1;
-      x[8] = wgt * g2;
-      x[9] = wgt * gD;
-      // ge = dL/d(log2 alpha) / ln 2; the clamp at alpha_max cuts the
-      // derivative of alpha in o and q.  With log2 alpha = log2 o + P' u^2 +
-      // E' dy^2, u = dx + k dy, the pixel's moments (ge u, ge dy, ge u^2,
-      // ge u dy, ge dy^2, ge) give every record-space derivative once the
-      // pair's P', k, E' and ln 2 are applied to their sums.
-      const float ge = raw < P.amax ? dLda * a : 0.f;
-      const float gu = ge * u, gd = ge * dy;
-      x[0] = gu;
-      x[1] = gd;
-      x[2] = gu * u;
-      x[3] = gu * dy;
-      x[4] = gd * dy;
-      x[5] = ge;
-      T = T * oma;
-      const uint64_t bm = ballot64(bl && M);
-      int idx;
-      bool valid;
-      wave_reduce10(x, l, idx, valid);
-      if (valid) s_part[w][tt][idx] = x[0];
-      if (l == 0) {
-        s_part[w][tt][10] = (float)__popcll(bb);
-        s_part[w][tt][11] = (float)__popcll(bm);
-      }
+      if (has_b && !use_b) break;
+      j += use_b ? 2u : 1u;
     }
     __syncthreads();
     if (tid < B) {
@@ -402,20 +483,23 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_render_bwd(
       if (k < end) {
         const int krel = (int)(k - start);
         const uint32_t m = s_mask[tid];
-        float o[12];
+        float o[10];
+        uint32_t c0 = 0u, c1 = 0u;
 #pragma unroll
-        for (int q = 0; q < 12; ++q) o[q] = 0.f;
+        for (int q = 0; q < 10; ++q) o[q] = 0.f;
 #pragma unroll
         for (int ww = 0; ww < 4; ++ww) {
           if (((m >> ww) & 1u) && krel < s_wmax[ww]) {
 #pragma unroll
-            for (int q = 0; q < 12; ++q) o[q] += s_part[ww][tid][q];
+            for (int q = 0; q < 10; ++q) o[q] += s_part[ww][tid][q];
+            c0 += __float_as_uint(s_part[ww][tid][10]);
+            c1 += __float_as_uint(s_part[ww][tid][11]);
           }
         }
         const size_t p = (size_t)pair_position(slot_pairoff[s_slot[tid]], s_r1[tid].w, s_r2[tid].w, tx, ty, P) * 3;
         pair_grad[p] = make_float4(o[0], o[1], o[2], o[3]);
         pair_grad[p + 1] = make_float4(o[4], o[5], o[6], o[7]);
-        pair_grad[p + 2] = make_float4(o[8], o[9], __uint_as_float((uint32_t)o[10]), __uint_as_float((uint32_t)o[11]));
+        pair_grad[p + 2] = make_float4(o[8], o[9], __uint_as_float(c0), __uint_as_float(c1));
       }
     }
   }
@@ -457,6 +541,7 @@ kgs_status kgs_launch_render_fwd(kgs_ctx* ctx, const kgs_image* out, hipStream_t
   (void)s;
 #define KGS_FWD(BB)                                                                                              \
   hipLaunchKernelGGL(k_render_fwd<BB>, dim3(grid), dim3(KGS_BLOCK), 0, st, P, (const uint2*)ctx->ranges,          \
+                     (const uint32_t*)ctx->tile_order,                                                           \
                      (const uint32_t*)ctx->sorted_slot, (const float4*)ctx->slot_rec, out->color, out->depth,      \
                      out->t_final, out->last)
   switch (ctx->cfg.batch) {
@@ -486,6 +571,7 @@ kgs_status kgs_launch_render_bwd(kgs_ctx* ctx, const kgs_image* fwd, const float
   const unsigned grid = (unsigned)(ctx->last_views * ctx->n_tiles);
 #define KGS_BWD(BB)                                                                                              \
   hipLaunchKernelGGL(k_render_bwd<BB>, dim3(grid), dim3(KGS_BLOCK), 0, st, P, (const uint2*)ctx->ranges,          \
+                     (const uint32_t*)ctx->tile_order,                                                           \
                      (const uint32_t*)ctx->sorted_slot, (const uint32_t*)ctx->slot_pairoff,                      \
                      (const float4*)ctx->slot_rec,                                                                \
                      (const float*)fwd->color, (const float*)fwd->depth, (const float*)fwd->t_final,              \

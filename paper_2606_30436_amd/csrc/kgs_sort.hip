@@ -398,6 +398,51 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_ranges(const uint32_t* __restrict
   }
 }
 
+// Launch order of the compositing workgroups: (view, tile) entries by
+// decreasing pair count (log-spaced buckets, 8 per octave), so the longest
+// tiles start first and the launch does not end on a few of them.  The order
+// inside a bucket is whatever the atomics give; it changes only which
+// workgroup runs when, never a result.
+__device__ __forceinline__ uint32_t len_bucket(uint32_t n) {
+  if (n == 0u) return 0u;
+  const uint32_t lz = 31u - (uint32_t)__clz((int)n);
+  const uint32_t frac = lz >= 3u ? (n >> (lz - 3u)) & 7u : (n << (3u - lz)) & 7u;
+  return min(1u + lz * 8u + frac, 255u);
+}
+
+__global__ __launch_bounds__(1024) void k_tile_order(const uint2* __restrict__ ranges, uint32_t n_tiles_all,
+                                                     uint32_t* __restrict__ order) {
+  __shared__ uint32_t cnt[256], off[256];
+  const int tid = threadIdx.x;
+  if (tid < 256) cnt[tid] = 0u;
+  __syncthreads();
+  for (uint32_t i = tid; i < n_tiles_all; i += 1024) {
+    const uint2 r = ranges[i];
+    atomicAdd(&cnt[len_bucket(r.y - r.x)], 1u);
+  }
+  __syncthreads();
+  if (tid < 64) {
+    // buckets in decreasing order: bucket 255 - 4 tid - q
+    uint32_t c[4], t = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      c[q] = cnt[255 - 4 * tid - q];
+      t += c[q];
+    }
+    uint32_t ex = wave_inclusive_scan(t) - t;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      off[255 - 4 * tid - q] = ex;
+      ex += c[q];
+    }
+  }
+  __syncthreads();
+  for (uint32_t i = tid; i < n_tiles_all; i += 1024) {
+    const uint2 r = ranges[i];
+    order[atomicAdd(&off[len_bucket(r.y - r.x)], 1u)] = i;
+  }
+}
+
 // ---------------------------------------------------------------- host side
 template <typename K>
 static int radix_sort(kgs_ctx* ctx, const uint32_t* count, K* keys[2], uint32_t* vals[2], int bits, hipStream_t st,
@@ -468,6 +513,8 @@ kgs_status kgs_launch_bin_sort(kgs_ctx* ctx, hipStream_t st) {
   const unsigned rg = (unsigned)std::min<uint64_t>(std::max<uint64_t>((P + KGS_BLOCK - 1) / KGS_BLOCK, 1), 8192);
   hipLaunchKernelGGL(k_ranges, dim3(rg), dim3(KGS_BLOCK), 0, st, (const uint32_t*)ctx->counters,
                      (const uint32_t*)ctx->keys[cur], n_tiles_all, ctx->ranges);
+  hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, st, (const uint2*)ctx->ranges, n_tiles_all,
+                     ctx->tile_order);
   ctx->sorted_slot = ctx->vals[cur];
   return kgs_check_launch();
 }

@@ -237,3 +237,39 @@ def test_tile_shapes_and_batches_give_identical_images():
                 ref = c
             else:
                 assert np.array_equal(c, ref), (tile, batch)
+
+
+def test_tile_shapes_and_batches_give_the_same_gradients():
+    """The backward over every tile shape and LDS batch: the same gradients up
+    to FP32 summation order (list entries are reduced in pairs or alone
+    depending on where a batch ends), on a scene dense enough for per-wave
+    lists longer than a wavefront."""
+    sc = scenes.make_c1(seed=5, n=80_000)
+    say("[gpu] backward tile / batch invariance")
+    rng = np.random.default_rng(11)
+    V, H, W = sc.n_views, sc.height, sc.width
+    dLdC = torch.from_numpy(rng.normal(size=(V, 3, H, W)).astype(np.float32)).cuda()
+    dLdD = torch.from_numpy((rng.normal(size=(V, H, W)) * 0.05).astype(np.float32)).cuda()
+    ref = None
+    for tile in ((16, 16), (8, 32), (32, 8)):
+        for batch in (32, 64, 128, 256):
+            R = _rast(sc, tile=tile, batch=batch)
+            g, cams, xi, img = run_forward(R, sc)
+            if ref is None:
+                keys = R.buffers()["keys"].numpy()
+                longest = int(np.unique(keys, return_counts=True)[1].max())
+                say(f"  longest tile list {longest}")
+                assert longest > 256
+            grads = g.zeros_like()
+            pose_grad = torch.zeros(V, 6, device="cuda")
+            R.render_bwd(g, cams, xi, img, dLdC, dLdD, grads=grads, pose_grad=pose_grad)
+            torch.cuda.synchronize()
+            out = {k: getattr(grads, k).cpu().numpy().astype(np.float64)
+                   for k in ("means", "log_scales", "quats", "logits", "sh")}
+            out["pose"] = pose_grad.cpu().numpy().astype(np.float64)
+            if ref is None:
+                ref = out
+                continue
+            for k in out:
+                rel = np.linalg.norm(out[k] - ref[k]) / np.linalg.norm(ref[k])
+                assert rel < 1e-5, (tile, batch, k, rel)
