@@ -3,7 +3,8 @@
 // The order the compositing needs is (view, tile, depth, Gaussian index).  It
 // is built in two small sorts instead of one wide one:
 //   1. the projected records (slots, already in (view, Gaussian) order) are
-//      sorted by (view, fp32 depth) -- 38-bit keys over S records;
+//      sorted by (view, fp32 depth) -- 30-bit keys at near 0.2, far 80 and
+//      8 views (the depth bits offset from near), over S records;
 //   2. pairs are emitted in that depth order (a scan of the records' tile
 //      counts gives each record's first pair), one per tile of the record's
 //      rectangle, keyed by the global tile index only;
@@ -20,75 +21,85 @@
 // consecutive addresses of a digit's run.  Counts stay on the device, so the
 // sequence can be captured in a graph.
 #include <algorithm>
+#include <cstring>
 
 #include "kgs_internal.h"
 
-#define RS_BLOCKS KGS_SORT_BLOCKS
-
-// partition of block b: a multiple of 256 keys
-__device__ __forceinline__ void part_range(uint32_t n, uint32_t b, uint32_t& lo, uint32_t& hi) {
-  const uint32_t per = ((n + RS_BLOCKS - 1) / RS_BLOCKS + 255u) & ~255u;
+// partition of block b of nb: a multiple of 256 keys
+__device__ __forceinline__ void part_range(uint32_t n, uint32_t nb, uint32_t b, uint32_t& lo, uint32_t& hi) {
+  const uint32_t per = ((n + nb - 1) / nb + 255u) & ~255u;
   lo = min(n, b * per);
   hi = min(n, lo + per);
 }
 
-__global__ void k_radix_zero(uint32_t* __restrict__ total) { total[blockIdx.x * 256 + threadIdx.x] = 0u; }
+// Lanes of the wave whose valid keys share digit d (ballots over its bits).
+__device__ __forceinline__ uint64_t digit_peers(bool valid, uint32_t d, int dbits) {
+  uint64_t peers = ballot64(valid);
+  for (int bit = 0; bit < dbits; ++bit) {
+    const bool on = (d >> bit) & 1u;
+    const uint64_t b = ballot64(on);
+    peers &= on ? b : ~b;
+  }
+  return peers;
+}
 
-// per-block digit histograms: hist[d][block]
+// per-block digit histograms hist[d][block]; the lowest lane of each group of
+// equal digits adds the group's size (one LDS add per distinct digit)
 template <typename K>
 __global__ __launch_bounds__(256) void k_radix_hist(const uint32_t* __restrict__ count, const K* __restrict__ keys,
-                                                    int shift, uint32_t dmask, uint32_t* __restrict__ hist,
-                                                    uint32_t* __restrict__ total) {
+                                                    int shift, int dbits, uint32_t nb, uint32_t* __restrict__ hist) {
   __shared__ uint32_t h[256];
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, l = tid & 63;
+  const uint32_t dmask = (1u << dbits) - 1u;
+  const uint64_t lt = (1ull << l) - 1ull;
   h[tid] = 0u;
   __syncthreads();
   uint32_t lo, hi;
-  part_range(*count, blockIdx.x, lo, hi);
+  part_range(*count, nb, blockIdx.x, lo, hi);
   for (uint32_t base = lo; base < hi; base += 256 * 8) {
-    uint32_t d[8];
+    K kk[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const uint32_t i = base + q * 256 + tid;
-      d[q] = i < hi ? (uint32_t)(keys[i] >> shift) & dmask : 256u;
+      kk[q] = i < hi ? keys[i] : (K)0;
     }
 #pragma unroll
-    for (int q = 0; q < 8; ++q)
-      if (d[q] < 256u) atomicAdd(&h[d[q]], 1u);
+    for (int q = 0; q < 8; ++q) {
+      const bool valid = base + q * 256 + tid < hi;
+      const uint32_t d = (uint32_t)(kk[q] >> shift) & dmask;
+      const uint64_t peers = digit_peers(valid, d, dbits);
+      if (valid && (peers & lt) == 0ull) atomicAdd(&h[d], (uint32_t)__popcll(peers));
+    }
   }
   __syncthreads();
-  const uint32_t c = h[tid];
-  hist[(size_t)tid * RS_BLOCKS + blockIdx.x] = c;
-  if (c) atomicAdd(&total[tid], c);
+  if ((uint32_t)tid <= dmask) hist[(size_t)tid * nb + blockIdx.x] = h[tid];
 }
 
-// one block per digit: exclusive scan of its row of block counts, plus the
-// total of all smaller digits
-__global__ __launch_bounds__(256) void k_radix_scan(uint32_t* __restrict__ hist, const uint32_t* __restrict__ total) {
-  __shared__ uint32_t sh[8];
+// one block per digit: exclusive scan of its row of block counts (in place)
+// and the row total
+__global__ __launch_bounds__(256) void k_radix_scan(uint32_t* __restrict__ hist, uint32_t nb,
+                                                    uint32_t* __restrict__ total) {
+  __shared__ uint32_t sh[4];
   const int d = blockIdx.x, tid = threadIdx.x, w = tid >> 6, l = tid & 63;
-  uint32_t pre = 0;
-  for (int k = tid; k < d; k += 256) pre += total[k];
-  pre = wave_sum(pre);
-  if (l == 0) sh[4 + w] = pre;
-  constexpr int PER = RS_BLOCKS / 256;
-  uint32_t v[PER], s = 0;
+  const uint32_t per = nb / 256;
+  uint32_t* row = hist + (size_t)d * nb + tid * per;
+  uint32_t v[4], s = 0;
 #pragma unroll
-  for (int k = 0; k < PER; ++k) {
-    v[k] = hist[(size_t)d * RS_BLOCKS + tid * PER + k];
+  for (uint32_t k = 0; k < 4; ++k) {
+    v[k] = k < per ? row[k] : 0u;
     s += v[k];
   }
   const uint32_t inc = wave_inclusive_scan(s);
   if (l == 63) sh[w] = inc;
   __syncthreads();
-  uint32_t off = sh[4] + sh[5] + sh[6] + sh[7];
+  uint32_t off = inc - s;
   for (int k = 0; k < w; ++k) off += sh[k];
-  off += inc - s;
 #pragma unroll
-  for (int k = 0; k < PER; ++k) {
-    hist[(size_t)d * RS_BLOCKS + tid * PER + k] = off;
+  for (uint32_t k = 0; k < 4; ++k) {
+    if (k < per) row[k] = off;
     off += v[k];
   }
+  if (tid == 255) total[d] = off;
 }
 
 // Stable scatter of one block's partition, a tile of 256 x KPT keys at a time.
@@ -96,7 +107,8 @@ __global__ __launch_bounds__(256) void k_radix_scan(uint32_t* __restrict__ hist,
 template <typename K, int KPT>
 __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t* __restrict__ count, const K* __restrict__ kin,
                                                        const uint32_t* __restrict__ vin, int shift, int dbits,
-                                                       const uint32_t* __restrict__ offsets, K* __restrict__ kout,
+                                                       uint32_t nb, const uint32_t* __restrict__ offsets,
+                                                       const uint32_t* __restrict__ total, K* __restrict__ kout,
                                                        uint32_t* __restrict__ vout) {
   constexpr uint32_t TILE = 256 * KPT;
   __shared__ K lk[TILE];
@@ -106,11 +118,20 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t* __restric
   __shared__ uint32_t sh[4];
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
   const uint32_t R = 1u << dbits, dmask = R - 1u;
-  gofs[tid] = (uint32_t)tid < R ? offsets[(size_t)tid * RS_BLOCKS + blockIdx.x] : 0u;
+  {
+    // digit bases: exclusive scan of the digit totals
+    const uint32_t t = (uint32_t)tid < R ? total[tid] : 0u;
+    const uint32_t inc = wave_inclusive_scan(t);
+    if (l == 63) sh[w] = inc;
+    __syncthreads();
+    uint32_t base = inc - t;
+    for (int k = 0; k < w; ++k) base += sh[k];
+    gofs[tid] = (uint32_t)tid < R ? base + offsets[(size_t)tid * nb + blockIdx.x] : 0u;
+  }
 #pragma unroll
   for (int k = 0; k < 4; ++k) wc[k][tid] = 0u;
   uint32_t lo, hi;
-  part_range(*count, blockIdx.x, lo, hi);
+  part_range(*count, nb, blockIdx.x, lo, hi);
   const uint64_t lt = (1ull << l) - 1ull;
   __syncthreads();
   for (uint32_t tb = lo; tb < hi; tb += TILE) {
@@ -132,12 +153,7 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t* __restric
     for (int q = 0; q < KPT; ++q) {
       const bool valid = wb + q * 64 + l < hi;
       const uint32_t d = (uint32_t)(kk[q] >> shift) & dmask;
-      uint64_t peers = ballot64(valid);
-      for (int bit = 0; bit < dbits; ++bit) {
-        const bool on = (d >> bit) & 1u;
-        const uint64_t b = ballot64(on);
-        peers &= on ? b : ~b;
-      }
+      const uint64_t peers = digit_peers(valid, d, dbits);
       const uint32_t r = (uint32_t)__popcll(peers & lt);
       const uint32_t before = valid ? wc[w][d] : 0u;
       __builtin_amdgcn_wave_barrier();
@@ -232,13 +248,21 @@ __global__ __launch_bounds__(256) void k_slot_offsets(const uint32_t* __restrict
 }
 
 // ---------------------------------------------------------------- slot keys
+// (view, depth) key of every record.  Depths are positive FP32 values in
+// [near, far], whose bit patterns are ordered like the values, so the bits
+// minus those of a value just below near keep the order exactly in
+// depth_bits bits (27 for near 0.2, far 80); the view sits above them.
 __global__ __launch_bounds__(KGS_BLOCK) void k_slot_keys(const uint32_t* __restrict__ counters,
                                                          const float4* __restrict__ slot_rec,
-                                                         const uint32_t* __restrict__ slot_view,
-                                                         uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+                                                         const uint32_t* __restrict__ slot_view, uint32_t depth_lo,
+                                                         int depth_bits, uint64_t* __restrict__ keys,
+                                                         uint32_t* __restrict__ vals) {
   const uint32_t n = counters[0];
+  const uint32_t dmax = depth_bits >= 32 ? 0xffffffffu : (1u << depth_bits) - 1u;
   for (uint32_t s = blockIdx.x * KGS_BLOCK + threadIdx.x; s < n; s += gridDim.x * KGS_BLOCK) {
-    keys[s] = ((uint64_t)slot_view[s] << 32) | __float_as_uint(slot_rec[(size_t)s * 3 + 1].z);
+    const uint32_t b = __float_as_uint(slot_rec[(size_t)s * 3 + 1].z);
+    const uint32_t d = b > depth_lo ? min(b - depth_lo, dmax) : 0u;
+    keys[s] = ((uint64_t)slot_view[s] << depth_bits) | d;
     vals[s] = s;
   }
 }
@@ -445,23 +469,23 @@ __global__ __launch_bounds__(1024) void k_tile_order(const uint2* __restrict__ r
 
 // ---------------------------------------------------------------- host side
 template <typename K>
-static int radix_sort(kgs_ctx* ctx, const uint32_t* count, K* keys[2], uint32_t* vals[2], int bits, hipStream_t st,
-                      const uint32_t* vals_in = nullptr) {
+static int radix_sort(kgs_ctx* ctx, const uint32_t* count, uint64_t cap, K* keys[2], uint32_t* vals[2], int bits,
+                      hipStream_t st, const uint32_t* vals_in = nullptr) {
   const int passes = (bits + 7) / 8;
   const int dbits = (bits + passes - 1) / passes;
-  const uint32_t dmask = (1u << dbits) - 1u;
   constexpr int KPT = sizeof(K) == 8 ? 8 : 16;
-  hipLaunchKernelGGL(k_radix_zero, dim3(passes), dim3(256), 0, st, ctx->radix_total);
+  // partitions: fewer for small sorts (a multiple of 256, at most KGS_SORT_BLOCKS)
+  const uint32_t nb = cap >= (8u << 20) ? KGS_SORT_BLOCKS : std::min<uint32_t>(512u, KGS_SORT_BLOCKS);
   int cur = 0;
   for (int p = 0; p < passes; ++p) {
     const int shift = dbits * p;
-    hipLaunchKernelGGL(k_radix_hist<K>, dim3(RS_BLOCKS), dim3(256), 0, st, count, (const K*)keys[cur], shift, dmask,
-                       ctx->radix_hist, ctx->radix_total + 256 * p);
-    hipLaunchKernelGGL(k_radix_scan, dim3(1u << dbits), dim3(256), 0, st, ctx->radix_hist,
-                       (const uint32_t*)(ctx->radix_total + 256 * p));
-    hipLaunchKernelGGL((k_radix_scatter<K, KPT>), dim3(RS_BLOCKS), dim3(256), 0, st, count, (const K*)keys[cur],
-                       (p == 0 && vals_in) ? vals_in : (const uint32_t*)vals[cur], shift, dbits,
-                       (const uint32_t*)ctx->radix_hist, keys[cur ^ 1], vals[cur ^ 1]);
+    uint32_t* total = ctx->radix_total + 256 * p;
+    hipLaunchKernelGGL(k_radix_hist<K>, dim3(nb), dim3(256), 0, st, count, (const K*)keys[cur], shift, dbits, nb,
+                       ctx->radix_hist);
+    hipLaunchKernelGGL(k_radix_scan, dim3(1u << dbits), dim3(256), 0, st, ctx->radix_hist, nb, total);
+    hipLaunchKernelGGL((k_radix_scatter<K, KPT>), dim3(nb), dim3(256), 0, st, count, (const K*)keys[cur],
+                       (p == 0 && vals_in) ? vals_in : (const uint32_t*)vals[cur], shift, dbits, nb,
+                       (const uint32_t*)ctx->radix_hist, (const uint32_t*)total, keys[cur ^ 1], vals[cur ^ 1]);
     cur ^= 1;
   }
   return cur;
@@ -473,12 +497,19 @@ kgs_status kgs_launch_bin_sort(kgs_ctx* ctx, hipStream_t st) {
   const uint64_t S = (uint64_t)ctx->cfg.slot_capacity, P = (uint64_t)ctx->cfg.pair_capacity;
   const unsigned sgrid = (unsigned)std::min<uint64_t>(std::max<uint64_t>((S + KGS_BLOCK - 1) / KGS_BLOCK, 1), 4096);
   // 1. records by (view, depth)
+  uint32_t near_b, far_b;
+  std::memcpy(&near_b, &ctx->cfg.near_z, 4);
+  std::memcpy(&far_b, &ctx->cfg.far_z, 4);
+  const uint32_t depth_lo = near_b > 4096u ? near_b - 4096u : 0u;
+  const uint64_t depth_span = (uint64_t)std::min<uint32_t>(far_b, 0x7f800000u) + 4096u - depth_lo;
+  int depth_bits = 1;
+  while (depth_bits < 32 && (1ull << depth_bits) <= depth_span) ++depth_bits;
   hipLaunchKernelGGL(k_slot_keys, dim3(sgrid), dim3(KGS_BLOCK), 0, st, (const uint32_t*)ctx->counters,
-                     (const float4*)ctx->slot_rec, (const uint32_t*)ctx->slot_view, ctx->slot_keys[0],
-                     ctx->slot_vals[0]);
+                     (const float4*)ctx->slot_rec, (const uint32_t*)ctx->slot_view, depth_lo, depth_bits,
+                     ctx->slot_keys[0], ctx->slot_vals[0]);
   int view_bits = 0;
   while ((1 << view_bits) < V) ++view_bits;
-  const int sc = radix_sort<uint64_t>(ctx, ctx->counters, ctx->slot_keys, ctx->slot_vals, 32 + view_bits, st);
+  const int sc = radix_sort<uint64_t>(ctx, ctx->counters, S, ctx->slot_keys, ctx->slot_vals, depth_bits + view_bits, st);
   const uint32_t* perm = ctx->slot_vals[sc];
   ctx->perm = perm;
   // 2. first pair of every record in that order, then the pairs
@@ -503,7 +534,7 @@ kgs_status kgs_launch_bin_sort(kgs_ctx* ctx, hipStream_t st) {
   while ((1u << tile_bits) <= n_tiles_all) ++tile_bits;
   // the first pass reads the emission-order slots from pair_slot, which stays
   // intact for the backward's segmented sums
-  const int cur = radix_sort<uint32_t>(ctx, ctx->counters + 1, ctx->keys, ctx->vals, std::max(tile_bits, 1), st,
+  const int cur = radix_sort<uint32_t>(ctx, ctx->counters + 1, P, ctx->keys, ctx->vals, std::max(tile_bits, 1), st,
                                        ctx->pair_slot);
   ctx->sorted_buf = cur;
   ctx->passes = (tile_bits + 7) / 8;
