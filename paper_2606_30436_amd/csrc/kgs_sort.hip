@@ -32,15 +32,21 @@ __device__ __forceinline__ void part_range(uint32_t n, uint32_t nb, uint32_t b, 
   hi = min(n, lo + per);
 }
 
-// Lanes of the wave whose valid keys share digit d (ballots over its bits).
-__device__ __forceinline__ uint64_t digit_peers(bool valid, uint32_t d, int dbits) {
-  uint64_t peers = ballot64(valid);
-  for (int bit = 0; bit < dbits; ++bit) {
-    const bool on = (d >> bit) & 1u;
-    const uint64_t b = ballot64(on);
-    peers &= on ? b : ~b;
+// Lanes of the wave whose valid keys share digit d (d < 256): one ballot per
+// bit, all eight unrolled (bits above the digit width are zero in every lane
+// and leave the mask alone).
+__device__ __forceinline__ uint64_t digit_peers(bool valid, uint32_t d) {
+  const uint64_t v = ballot64(valid);
+  uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+#pragma unroll
+  for (int bit = 0; bit < 8; ++bit) {
+    // m: all ones where this lane's bit is set; keep the lanes whose bit agrees
+    const uint32_t m = (uint32_t)((int32_t)(d << (31 - bit)) >> 31);
+    const uint64_t b = ballot64((d >> bit) & 1u);
+    lo &= ~((uint32_t)b ^ m);
+    hi &= ~((uint32_t)(b >> 32) ^ m);
   }
-  return peers;
+  return ((uint64_t)hi << 32) | lo;
 }
 
 // per-block digit histograms hist[d][block]; the lowest lane of each group of
@@ -56,18 +62,31 @@ __global__ __launch_bounds__(256) void k_radix_hist(const uint32_t* __restrict__
   __syncthreads();
   uint32_t lo, hi;
   part_range(*count, nb, blockIdx.x, lo, hi);
-  for (uint32_t base = lo; base < hi; base += 256 * 8) {
-    K kk[8];
+  // 16-byte loads: VW keys per load, four loads per thread in flight
+  constexpr int VW = 16 / sizeof(K), KPI = 4 * VW;
+  for (uint32_t base = lo; base < hi; base += 256 * KPI) {
+    K kk[KPI];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const uint32_t i = base + q * 256 + tid;
-      kk[q] = i < hi ? keys[i] : (K)0;
+    for (int q = 0; q < 4; ++q) {
+      const uint32_t i0 = base + (q * 256 + tid) * VW;
+      if (i0 + VW <= hi) {
+        const uint4 v = *reinterpret_cast<const uint4*>(keys + i0);
+        if constexpr (VW == 4) {
+          kk[q * 4] = (K)v.x; kk[q * 4 + 1] = (K)v.y; kk[q * 4 + 2] = (K)v.z; kk[q * 4 + 3] = (K)v.w;
+        } else {
+          kk[q * 2] = (K)(((uint64_t)v.y << 32) | v.x);
+          kk[q * 2 + 1] = (K)(((uint64_t)v.w << 32) | v.z);
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < VW; ++e) kk[q * VW + e] = i0 + e < hi ? keys[i0 + e] : (K)0;
+      }
     }
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const bool valid = base + q * 256 + tid < hi;
+    for (int q = 0; q < KPI; ++q) {
+      const bool valid = base + ((q / VW) * 256 + tid) * VW + (q % VW) < hi;
       const uint32_t d = (uint32_t)(kk[q] >> shift) & dmask;
-      const uint64_t peers = digit_peers(valid, d, dbits);
+      const uint64_t peers = digit_peers(valid, d);
       if (valid && (peers & lt) == 0ull) atomicAdd(&h[d], (uint32_t)__popcll(peers));
     }
   }
@@ -153,7 +172,7 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t* __restric
     for (int q = 0; q < KPT; ++q) {
       const bool valid = wb + q * 64 + l < hi;
       const uint32_t d = (uint32_t)(kk[q] >> shift) & dmask;
-      const uint64_t peers = digit_peers(valid, d, dbits);
+      const uint64_t peers = digit_peers(valid, d);
       const uint32_t r = (uint32_t)__popcll(peers & lt);
       const uint32_t before = valid ? wc[w][d] : 0u;
       __builtin_amdgcn_wave_barrier();
