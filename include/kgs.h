@@ -194,7 +194,7 @@ typedef struct kgs_chunk_desc {
   float* view_loss;         /* device [V]: mean |C - I| per view */
   kgs_grads grads;
   kgs_view_stats stats;
-  int32_t zero_accumulators; /* != 0: zero grads and stats first (fill kernels) */
+  int32_t zero_accumulators; /* != 0: grads and stats start from zero (the backward writes them instead of adding) */
   float tau_d;
   kgs_lifecycle_state state; /* densify != NULL: kgs_accumulate_stats(reset = 1) after the backward */
   uint8_t* decision;         /* != NULL: kgs_densify_prune_decide after that */

@@ -16,7 +16,7 @@ kgs_status kgs_launch_loss(kgs_ctx*, const float*, const kgs_image*, float*, flo
 kgs_status kgs_launch_render_bwd(kgs_ctx*, const kgs_image*, const float*, const float*, const float*,
                                  const float*, float, hipStream_t);
 kgs_status kgs_launch_project_bwd(kgs_ctx*, const kgs_gaussians*, const kgs_camera*, int, const float*,
-                                  const float*, const kgs_grads*, const kgs_view_stats*, hipStream_t);
+                                  const float*, const kgs_grads*, const kgs_view_stats*, hipStream_t, bool overwrite = false);
 kgs_status kgs_launch_accumulate(kgs_ctx*, const kgs_view_stats*, int64_t, int, const kgs_lifecycle_state*, float,
                                  int, hipStream_t);
 kgs_status kgs_launch_decide(kgs_ctx*, const kgs_lifecycle_state*, int64_t, double, uint8_t*, uint32_t*, uint32_t*,
@@ -346,7 +346,10 @@ kgs_status kgs_chunk_run(kgs_ctx* ctx, const kgs_chunk_desc* d, void* stream) {
   hipStream_t st = (hipStream_t)stream;
   const uint64_t n = (uint64_t)d->gaussians.n;
   const uint64_t K = (uint64_t)(d->gaussians.sh_degree + 1) * (d->gaussians.sh_degree + 1);
-  if (d->zero_accumulators) {
+  // with zero_accumulators the gather writes every Gaussian's gradients and
+  // statistics and the pose reduction writes the pose gradient, so nothing
+  // needs clearing first unless there are no Gaussians to gather over
+  if (d->zero_accumulators && n == 0) {
     fill_zero(d->grads.means, 12 * n, st);
     fill_zero(d->grads.log_scales, 12 * n, st);
     fill_zero(d->grads.quats, 16 * n, st);
@@ -365,8 +368,10 @@ kgs_status kgs_chunk_run(kgs_ctx* ctx, const kgs_chunk_desc* d, void* stream) {
   if ((s = kgs_bin_sort(ctx, stream)) != KGS_OK) return s;
   if ((s = kgs_render_fwd(ctx, &d->image, stream)) != KGS_OK) return s;
   if ((s = kgs_loss_l1(ctx, d->target, &d->image, d->dl_dcolor, d->view_loss, stream)) != KGS_OK) return s;
-  s = kgs_render_bwd(ctx, &d->gaussians, d->cams, d->n_views, d->pose_xi, &d->image, d->dl_dcolor, nullptr, nullptr,
-                     d->target, d->tau_err, d->view_loss, &d->grads, &d->stats, stream);
+  if ((s = kgs_launch_render_bwd(ctx, &d->image, d->dl_dcolor, nullptr, nullptr, d->target, d->tau_err, st)) != KGS_OK)
+    return s;
+  s = kgs_launch_project_bwd(ctx, &d->gaussians, d->cams, d->n_views, d->pose_xi, d->view_loss, &d->grads, &d->stats,
+                             st, d->zero_accumulators != 0 && n > 0);
   if (s != KGS_OK) return s;
   if (d->state.densify) {
     s = kgs_accumulate_stats(ctx, &d->stats, d->gaussians.n, d->n_views, &d->state, d->tau_d, 1, stream);

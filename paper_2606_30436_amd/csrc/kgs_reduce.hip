@@ -415,7 +415,7 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_gauss_gather(int64_t n, int V, co
                                                             const uint32_t* __restrict__ counters,
                                                             const float4* __restrict__ slot_bwd,
                                                             const float* __restrict__ view_loss, kgs_grads gr,
-                                                            kgs_view_stats st) {
+                                                            kgs_view_stats st, int overwrite) {
   constexpr int K = (DEG + 1) * (DEG + 1);
   const int64_t i = (int64_t)blockIdx.x * KGS_BLOCK + threadIdx.x;
   if (i >= n) return;
@@ -455,6 +455,27 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_gauss_gather(int64_t n, int V, co
     s_gn += r[19];
     s_vc += 1u;
     s_mr = max(s_mr, __float_as_int(r[20]));
+  }
+  if (overwrite) {
+    // the outputs start from zero: every Gaussian is written, seen or not
+    if (gr.means)
+      for (int k = 0; k < 3; ++k) gr.means[k * n + i] = acc[k];
+    if (gr.log_scales)
+      for (int k = 0; k < 3; ++k) gr.log_scales[k * n + i] = acc[3 + k];
+    if (gr.quats)
+      for (int k = 0; k < 4; ++k) gr.quats[k * n + i] = acc[6 + k];
+    if (gr.opacity_logits) gr.opacity_logits[i] = acc[10];
+    if (gr.sh)
+#pragma unroll
+      for (int k = 0; k < K; ++k)
+        for (int ch = 0; ch < 3; ++ch) gr.sh[((int64_t)k * 3 + ch) * n + i] = gsh[k][ch];
+    if (st.kappa_sum) st.kappa_sum[i] = s_kap;
+    if (st.omega_sum) st.omega_sum[i] = s_om;
+    if (st.gamma_sum) st.gamma_sum[i] = s_gam;
+    if (st.grad_norm_sum) st.grad_norm_sum[i] = s_gn;
+    if (st.view_count) st.view_count[i] = s_vc;
+    if (st.max_radius) st.max_radius[i] = s_mr;
+    return;
   }
   if (s_vc == 0) return;
   if (gr.means)
@@ -508,7 +529,7 @@ __global__ __launch_bounds__(256) void k_pose_reduce(const uint32_t* __restrict_
 
 // d/dxi = J_l(xi)^T (dL/drho, dL/dphi), summed over the pieces in fixed order.
 __global__ void k_pose_final(int V, const double* __restrict__ partial, const CamDev* __restrict__ cams,
-                             float* __restrict__ grad) {
+                             float* __restrict__ grad, int overwrite) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= V) return;
   double gd[6] = {0, 0, 0, 0, 0, 0};
@@ -518,13 +539,13 @@ __global__ void k_pose_final(int V, const double* __restrict__ partial, const Ca
   for (int j = 0; j < 6; ++j) {
     double s = 0.0;
     for (int k = 0; k < 6; ++k) s += c.Jl[k * 6 + j] * gd[k];
-    grad[v * 6 + j] += (float)s;
+    grad[v * 6 + j] = overwrite ? (float)s : grad[v * 6 + j] + (float)s;
   }
 }
 
 kgs_status kgs_launch_project_bwd(kgs_ctx* ctx, const kgs_gaussians* g, const kgs_camera* cams, int V,
                                   const float* pose_xi, const float* view_loss, const kgs_grads* gr,
-                                  const kgs_view_stats* stats, hipStream_t st) {
+                                  const kgs_view_stats* stats, hipStream_t st, bool overwrite) {
   (void)cams;
   (void)pose_xi;
   const kgs_config& cfg = ctx->cfg;
@@ -560,7 +581,7 @@ kgs_status kgs_launch_project_bwd(kgs_ctx* ctx, const kgs_gaussians* g, const kg
                      ctx->slot_pose);                                                                             \
   hipLaunchKernelGGL(k_gauss_gather<D>, dim3((unsigned)nb), dim3(KGS_BLOCK), 0, st, (int64_t)g->n, V,             \
                      (const uint32_t*)ctx->vis, (const uint32_t*)ctx->counters, (const float4*)ctx->slot_bwd,     \
-                     view_loss, G, S)
+                     view_loss, G, S, overwrite ? 1 : 0)
     switch (g->sh_degree) {
       case 0: KGS_PB(0); break;
       case 1: KGS_PB(1); break;
@@ -572,7 +593,7 @@ kgs_status kgs_launch_project_bwd(kgs_ctx* ctx, const kgs_gaussians* g, const kg
       hipLaunchKernelGGL(k_pose_reduce, dim3(KGS_POSE_BLOCKS, V), dim3(256), 0, st, (const uint32_t*)ctx->counters,
                          (const uint32_t*)ctx->blk_base, nb, V, (const float2*)ctx->slot_pose, ctx->pose_partial);
       hipLaunchKernelGGL(k_pose_final, dim3(1), dim3(64), 0, st, V, (const double*)ctx->pose_partial,
-                         (const CamDev*)ctx->cams, G.pose_xi);
+                         (const CamDev*)ctx->cams, G.pose_xi, overwrite ? 1 : 0);
     }
   }
   return kgs_check_launch();
