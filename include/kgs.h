@@ -166,9 +166,10 @@ typedef struct kgs_lifecycle_state {
 typedef struct kgs_buffers {
   const uint32_t* n_slots;      /* device scalar */
   const uint32_t* n_pairs;      /* device scalar */
-  const float* slot_rec;        /* [S][12]: mu_x-0.5-floor(W/2), mu_y-0.5-floor(H/2), P', k, E', log2 o,
-                                   depth, -, r, g, b, -  with the conic as q = P (dx + k dy)^2 + E dy^2,
-                                   P' = -P log2(e) / 2, E' = -E log2(e) / 2 */
+  const float* slot_rec;        /* [S][16]: mu_x-0.5-floor(W/2), mu_y-0.5-floor(H/2), P', k, E', log2 o,
+                                   depth, -, r, g, b, -, first pair (u32 bits), -, -, -  with the conic as
+                                   q = P (dx + k dy)^2 + E dy^2, P' = -P log2(e) / 2, E' = -E log2(e) / 2;
+                                   64 bytes per record, one aligned line segment per read */
   const uint32_t* slot_gid;     /* [S] Gaussian index */
   const uint32_t* slot_view;    /* [S] view */
   const int32_t* slot_pix;      /* [S][4]: floor(mu_x), floor(mu_y), rx, ry */

@@ -60,7 +60,7 @@ size_t layout(const kgs_config& c, char* base, kgs_ctx* ctx) {
   p = take(8 * V * nb);                         if (ctx) ctx->blk_cnt = (uint32_t*)p;
   p = take(8 * V * nb);                         if (ctx) ctx->blk_base = (uint32_t*)p;
   p = take(4 * 64);                             if (ctx) ctx->counters = (uint32_t*)p;
-  p = take(48 * S);                             if (ctx) ctx->slot_rec = (float4*)p;
+  p = take(64 * S);                             if (ctx) ctx->slot_rec = (float4*)p;
   p = take(4 * S);                              if (ctx) ctx->slot_gid = (uint32_t*)p;
   p = take(4 * S);                              if (ctx) ctx->slot_view = (uint32_t*)p;
   p = take(16 * S);                             if (ctx) ctx->slot_pix = (int4*)p;

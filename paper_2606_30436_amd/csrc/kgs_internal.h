@@ -53,7 +53,7 @@ struct kgs_ctx {
   uint32_t* blk_cnt;                  // [max_views][nb][2] visible count, tile count
   uint32_t* blk_base;                 // [max_views][nb][2] exclusive bases
   uint32_t* counters;                 // [64]: 0 n_slots, 1 n_pairs, 2 status, 3.. scratch
-  float4* slot_rec;                   // [S][3]
+  float4* slot_rec;                   // [S][4] compositing records, 64 bytes (the last: first pair)
   uint32_t* slot_gid;                 // [S]
   uint32_t* slot_view;                // [S]
   int4* slot_pix;                     // [S]

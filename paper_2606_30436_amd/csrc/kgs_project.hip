@@ -246,9 +246,9 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_emit(kgs_gaussians g, const CamDe
       r2 = make_float4(0.f, 0.f, 0.f, pack_bounds(32767, -32768));
       pix = make_int4(-(1 << 30), -(1 << 30), 0, 0);
     }
-    slot_rec[s * 3 + 0] = r0;
-    slot_rec[s * 3 + 1] = r1;
-    slot_rec[s * 3 + 2] = r2;
+    slot_rec[s * 4 + 0] = r0;
+    slot_rec[s * 4 + 1] = r1;
+    slot_rec[s * 4 + 2] = r2;
     slot_gid[s] = (uint32_t)i;
     slot_view[s] = (uint32_t)v;
     slot_pix[s] = pix;

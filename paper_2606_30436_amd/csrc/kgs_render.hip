@@ -53,11 +53,11 @@ __device__ __forceinline__ bool footprint_meets_box(float x0, float x1, float y0
 // Stage B pairs of [base, end) into LDS and build the per-wave lists: a wave's
 // list holds the pairs whose pixel rectangle meets its 8x8 sub-block and whose
 // footprint reaches the sub-block's pixel centres.
-template <int B>
+template <int B, bool FIRST_PAIR>
 __device__ __forceinline__ void stage_batch(uint32_t base, uint32_t end, const uint32_t* __restrict__ sorted_slot,
                                             const float4* __restrict__ slot_rec, int tile_x0, int tile_y0,
                                             int tile_w, int ox, int oy, float log2_amin, float4* s_r0,
-                                            float4* s_r1, float4* s_r2, uint32_t* s_slot, uint8_t* s_mask,
+                                            float4* s_r1, float4* s_r2, uint32_t* s_first, uint8_t* s_mask,
                                             uint8_t (*s_list)[B], uint32_t (*s_cnt)[4]) {
   const int tid = threadIdx.x, w = tid >> 6;
   uint32_t m = 0;
@@ -65,8 +65,9 @@ __device__ __forceinline__ void stage_batch(uint32_t base, uint32_t end, const u
     const uint32_t k = base + tid;
     if (k < end) {
       const uint32_t s = sorted_slot[k];
-      const float4 r0 = slot_rec[(size_t)s * 3], r1 = slot_rec[(size_t)s * 3 + 1], r2 = slot_rec[(size_t)s * 3 + 2];
-      s_slot[tid] = s;
+      const float4* rec = slot_rec + (size_t)s * 4;
+      const float4 r0 = rec[0], r1 = rec[1], r2 = rec[2];
+      if (FIRST_PAIR) s_first[tid] = __float_as_uint(rec[3].x);
       s_r0[tid] = r0;
       s_r1[tid] = r1;
       s_r2[tid] = r2;
@@ -114,7 +115,7 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_render_fwd(RenderParams P, const 
                                                           float* __restrict__ color, float* __restrict__ depth,
                                                           float* __restrict__ tfinal, int32_t* __restrict__ last) {
   __shared__ float4 s_r0[B], s_r1[B], s_r2[B];
-  __shared__ uint32_t s_slot[B];
+  __shared__ uint32_t s_first[B];  // unused by the forward
   __shared__ uint8_t s_list[4][B];
   __shared__ uint8_t s_mask[B];
   __shared__ uint32_t s_cnt[4][4];
@@ -135,8 +136,8 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_render_fwd(RenderParams P, const 
   bool done = !inside;
   for (uint32_t base = start; base < end; base += B) {
     if (__syncthreads_count(!done) == 0) break;
-    stage_batch<B>(base, end, sorted_slot, slot_rec, tile_x0, tile_y0, P.tile_w, pix_origin(P.W), pix_origin(P.H),
-                   P.log2_amin, s_r0, s_r1, s_r2, s_slot, s_mask,
+    stage_batch<B, false>(base, end, sorted_slot, slot_rec, tile_x0, tile_y0, P.tile_w, pix_origin(P.W), pix_origin(P.H),
+                   P.log2_amin, s_r0, s_r1, s_r2, s_first, s_mask,
                    s_list, s_cnt);
     const uint32_t len = __builtin_amdgcn_readfirstlane(s_cnt[0][w] + s_cnt[1][w] + s_cnt[2][w] + s_cnt[3][w]);
     const int rel0 = (int)(base - start) + 1;
@@ -344,12 +345,12 @@ template <int B>
 __global__ __launch_bounds__(KGS_BLOCK) void k_render_bwd(
     RenderParams P, const uint2* __restrict__ ranges, const uint32_t* __restrict__ tile_order,
     const uint32_t* __restrict__ sorted_slot,
-    const uint32_t* __restrict__ slot_pairoff, const float4* __restrict__ slot_rec, const float* __restrict__ color,
+    const float4* __restrict__ slot_rec, const float* __restrict__ color,
     const float* __restrict__ depth, const float* __restrict__ tfinal, const int32_t* __restrict__ last,
     const float* __restrict__ dl_dcolor, const float* __restrict__ dl_ddepth, const float* __restrict__ dl_dalpha,
     const float* __restrict__ target, float tau_err, float4* __restrict__ pair_grad) {
   __shared__ float4 s_r0[B], s_r1[B], s_r2[B];
-  __shared__ uint32_t s_slot[B];
+  __shared__ uint32_t s_first[B];
   __shared__ __align__(16) uint8_t s_list[4][B];
   __shared__ uint8_t s_mask[B];
   __shared__ uint32_t s_cnt[4][4];
@@ -408,8 +409,8 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_render_bwd(
   uint32_t base = start;
   for (; base < pend; base += B) {
     __syncthreads();
-    stage_batch<B>(base, end, sorted_slot, slot_rec, tile_x0, tile_y0, P.tile_w, pix_origin(P.W), pix_origin(P.H),
-                   P.log2_amin, s_r0, s_r1, s_r2, s_slot, s_mask,
+    stage_batch<B, true>(base, end, sorted_slot, slot_rec, tile_x0, tile_y0, P.tile_w, pix_origin(P.W), pix_origin(P.H),
+                   P.log2_amin, s_r0, s_r1, s_r2, s_first, s_mask,
                    s_list, s_cnt);
     const uint32_t len = __builtin_amdgcn_readfirstlane(s_cnt[0][w] + s_cnt[1][w] + s_cnt[2][w] + s_cnt[3][w]);
     const int rel0 = (int)(base - start);
@@ -496,7 +497,7 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_render_bwd(
             c1 += __float_as_uint(s_part[ww][tid][11]);
           }
         }
-        const size_t p = (size_t)pair_position(slot_pairoff[s_slot[tid]], s_r1[tid].w, s_r2[tid].w, tx, ty, P) * 3;
+        const size_t p = (size_t)pair_position(s_first[tid], s_r1[tid].w, s_r2[tid].w, tx, ty, P) * 3;
         pair_grad[p] = make_float4(o[0], o[1], o[2], o[3]);
         pair_grad[p + 1] = make_float4(o[4], o[5], o[6], o[7]);
         pair_grad[p + 2] = make_float4(o[8], o[9], __uint_as_float(c0), __uint_as_float(c1));
@@ -506,7 +507,8 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_render_bwd(
   // pairs behind the tile's last blended Gaussian contribute nothing
   for (uint32_t k = base + tid; k < end; k += KGS_BLOCK) {
     const uint32_t s = sorted_slot[k];
-    const size_t p = (size_t)pair_position(slot_pairoff[s], slot_rec[(size_t)s * 3 + 1].w, slot_rec[(size_t)s * 3 + 2].w,
+    const float4* rec = slot_rec + (size_t)s * 4;
+    const size_t p = (size_t)pair_position(__float_as_uint(rec[3].x), rec[1].w, rec[2].w,
                                            tx, ty, P) * 3;
     const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
     pair_grad[p] = z;
@@ -572,7 +574,7 @@ kgs_status kgs_launch_render_bwd(kgs_ctx* ctx, const kgs_image* fwd, const float
 #define KGS_BWD(BB)                                                                                              \
   hipLaunchKernelGGL(k_render_bwd<BB>, dim3(grid), dim3(KGS_BLOCK), 0, st, P, (const uint2*)ctx->ranges,          \
                      (const uint32_t*)ctx->tile_order,                                                           \
-                     (const uint32_t*)ctx->sorted_slot, (const uint32_t*)ctx->slot_pairoff,                      \
+                     (const uint32_t*)ctx->sorted_slot,                                                           \
                      (const float4*)ctx->slot_rec,                                                                \
                      (const float*)fwd->color, (const float*)fwd->depth, (const float*)fwd->t_final,              \
                      (const int32_t*)fwd->last, dl_dcolor, dl_ddepth, dl_dalpha, target, tau_err, ctx->pair_grad)

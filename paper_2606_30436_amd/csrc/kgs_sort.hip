@@ -248,7 +248,8 @@ __global__ __launch_bounds__(256) void k_slot_offsets(const uint32_t* __restrict
                                                       const uint32_t* __restrict__ part, uint32_t n_groups,
                                                       const uint32_t* __restrict__ ntiles, uint64_t pair_cap,
                                                       uint32_t* __restrict__ pref,
-                                                      uint32_t* __restrict__ slot_pairoff) {
+                                                      uint32_t* __restrict__ slot_pairoff,
+                                                      float4* __restrict__ slot_rec) {
   const uint32_t n = counters[0];
   const uint32_t l = threadIdx.x & 63;
   const uint32_t waves = gridDim.x * 4;
@@ -262,6 +263,8 @@ __global__ __launch_bounds__(256) void k_slot_offsets(const uint32_t* __restrict
     if (j < n) {
       pref[j] = (uint32_t)off;
       slot_pairoff[s] = (uint32_t)off;
+      // also in the record's last 16 bytes, read with the record by the backward
+      slot_rec[(size_t)s * 4 + 3] = make_float4(__uint_as_float((uint32_t)off), 0.f, 0.f, 0.f);
     }
   }
 }
@@ -279,7 +282,7 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_slot_keys(const uint32_t* __restr
   const uint32_t n = counters[0];
   const uint32_t dmax = depth_bits >= 32 ? 0xffffffffu : (1u << depth_bits) - 1u;
   for (uint32_t s = blockIdx.x * KGS_BLOCK + threadIdx.x; s < n; s += gridDim.x * KGS_BLOCK) {
-    const uint32_t b = __float_as_uint(slot_rec[(size_t)s * 3 + 1].z);
+    const uint32_t b = __float_as_uint(slot_rec[(size_t)s * 4 + 1].z);
     const uint32_t d = b > depth_lo ? min(b - depth_lo, dmax) : 0u;
     keys[s] = ((uint64_t)slot_view[s] << depth_bits) | d;
     vals[s] = s;
@@ -540,7 +543,7 @@ kgs_status kgs_launch_bin_sort(kgs_ctx* ctx, hipStream_t st) {
   uint32_t* pref = reinterpret_cast<uint32_t*>(ctx->slot_keys[sc ^ 1]);  // free after the record sort
   hipLaunchKernelGGL(k_slot_offsets, dim3(eg), dim3(256), 0, st, (const uint32_t*)ctx->counters, perm,
                      (const uint32_t*)ctx->group_part, n_groups, (const uint32_t*)ctx->slot_ntiles, P, pref,
-                     ctx->slot_pairoff);
+                     ctx->slot_pairoff, ctx->slot_rec);
   const uint64_t chunks = (P + EP_CHUNK - 1) / EP_CHUNK;
   const unsigned pg = (unsigned)std::min<uint64_t>(std::max<uint64_t>(chunks, 1), 4096);
   hipLaunchKernelGGL(k_emit_pairs, dim3(pg), dim3(256), 0, st, (const uint32_t*)ctx->counters, perm,

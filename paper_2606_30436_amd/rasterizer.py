@@ -250,7 +250,7 @@ class Rasterizer:
             t = u8.view(dtype)
             return (t.view(count, width) if width > 1 else t).cpu()
         out = dict(n_slots=ns, n_pairs=npairs,
-                   slot_rec=grab(b.slot_rec, ns, torch.float32, 12), slot_gid=grab(b.slot_gid, ns, torch.int32),
+                   slot_rec=grab(b.slot_rec, ns, torch.float32, 16), slot_gid=grab(b.slot_gid, ns, torch.int32),
                    slot_view=grab(b.slot_view, ns, torch.int32), slot_pix=grab(b.slot_pix, ns, torch.int32, 4),
                    slot_pairoff=grab(b.slot_pairoff, ns, torch.int32), keys=grab(b.keys, npairs, torch.int32),
                    sorted_slot=grab(b.sorted_slot, npairs, torch.int32), tiles_x=b.tiles_x, tiles_y=b.tiles_y)
