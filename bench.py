@@ -49,7 +49,7 @@ def read_traffic(tile, batch):
     """Per-launch HBM bytes of the compositing backward from the committed
     rocprofv3 counter summary; None if absent, taken on other kernel source or
     on another tile shape / LDS batch than the one timed."""
-    path = os.path.join(ROOT, "profiles", "k_render_bwd_2M_8view_chunk_counters.txt")
+    path = os.path.join(ROOT, "profiles", f"k_render_bwd_2M_8view_chunk_{tile[0]}x{tile[1]}_counters.txt")
     if not os.path.exists(path):
         return None
     vals = {}
