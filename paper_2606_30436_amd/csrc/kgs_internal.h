@@ -15,7 +15,7 @@
 #define KGS_LOSS_BLOCKS 64            // blocks per view of the loss reduction
 #define KGS_MAX_PASSES 8
 #define KGS_POSE_BLOCKS 32            // pieces per view of the pose reduction
-#define KGS_SLOT_WORDS 40             // words of a slot's backward record
+#define KGS_SLOT_WORDS 24             // words of a slot's backward record
 
 // ---------------------------------------------------------------- device camera
 // Pose already applied.  The camera point of a Gaussian is R' mu + t' in

@@ -179,15 +179,22 @@ template <int DEG>
 __global__ __launch_bounds__(KGS_BLOCK) void k_emit(kgs_gaussians g, const CamDev* __restrict__ cams, int V,
                                                     ProjParams P, uint32_t* __restrict__ vis,
                                                     const uint32_t* __restrict__ blk_base, int64_t nb,
-                                                    uint64_t slot_cap, uint64_t pair_cap,
+                                                    uint64_t slot_cap,
                                                     float4* __restrict__ slot_rec, uint32_t* __restrict__ slot_gid,
                                                     uint32_t* __restrict__ slot_view, int4* __restrict__ slot_pix,
-                                                    uint32_t* __restrict__ slot_pairoff,
                                                     uint32_t* __restrict__ slot_ntiles) {
   constexpr int K = (DEG + 1) * (DEG + 1);
-  __shared__ uint32_t scan_sh[16];
+  // visible lanes of each wave, per view: a slot's index is the (view, block)
+  // base plus the visible lanes before it (one barrier for all views)
+  __shared__ uint32_t wcnt[KGS_MAX_VIEWS][4];
+  const int w = threadIdx.x >> 6;
   const int64_t i = (int64_t)blockIdx.x * KGS_BLOCK + threadIdx.x;
   const bool valid = i < g.n;
+  for (int v = 0; v < V; ++v) {
+    const uint64_t bal = ballot64(valid && vis[(int64_t)v * g.n + i] > 0u);
+    if ((threadIdx.x & 63) == 0) wcnt[v][w] = (uint32_t)__popcll(bal);
+  }
+  __syncthreads();
   GaussLocal G;
   bool bad = false;
   G.ok = false;
@@ -195,24 +202,17 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_emit(kgs_gaussians g, const CamDe
   const float hl2e = 0.5f * 1.4426950408889634f;
   for (int v = 0; v < V; ++v) {
     const uint32_t tiles = valid ? vis[(int64_t)v * g.n + i] : 0u;
-    const uint32_t flag = tiles > 0 ? 1u : 0u;
-    uint32_t ea, eb, ta, tb;
-    block_scan2(flag, tiles, scan_sh, ea, eb, ta, tb);
-    if (!flag) continue;
-    const int64_t e = ((int64_t)v * nb + blockIdx.x) * 2;
-    const uint64_t s = (uint64_t)blk_base[e] + ea;
-    const uint64_t po = (uint64_t)blk_base[e + 1] + eb;
+    const uint64_t bal = ballot64(tiles > 0u);
+    if (tiles == 0u) continue;
+    uint32_t below = mask_lt_count(bal);
+    for (int k = 0; k < w; ++k) below += wcnt[v][k];
+    const uint64_t s = (uint64_t)blk_base[((int64_t)v * nb + blockIdx.x) * 2] + below;
     // from here on vis[v][i] names the slot (index + 1), for the backward gather
     vis[(int64_t)v * g.n + i] = s < slot_cap ? (uint32_t)(s + 1) : 0u;
+    // past the slot capacity nothing is written; the pair capacity needs no
+    // check here: an overflow of either zeroes every count after the scan, and
+    // otherwise every slot's pairs fit
     if (s >= slot_cap) continue;
-    if (po + tiles > pair_cap) {
-      // over the pair capacity: the slot exists but emits nothing
-      slot_gid[s] = (uint32_t)i;
-      slot_view[s] = (uint32_t)v;
-      slot_pairoff[s] = 0u;
-      slot_ntiles[s] = 0u;
-      continue;
-    }
     const CamDev& c = cams[v];
     ProjCore p;
     const bool vis_ok = G.ok && project_core(c, G.mu, G.Rq, G.s, G.o, P.near_z, P.far_z, P.eps2d, P.rect_margin,
@@ -252,7 +252,6 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_emit(kgs_gaussians g, const CamDe
     slot_gid[s] = (uint32_t)i;
     slot_view[s] = (uint32_t)v;
     slot_pix[s] = pix;
-    slot_pairoff[s] = (uint32_t)po;
     slot_ntiles[s] = tiles;
   }
 }
@@ -284,9 +283,8 @@ kgs_status kgs_launch_project(kgs_ctx* ctx, const kgs_gaussians* g, const kgs_ca
   if (nb > 0) {
 #define KGS_EMIT(D)                                                                                              \
   hipLaunchKernelGGL(k_emit<D>, dim3((unsigned)nb), dim3(KGS_BLOCK), 0, st, *g, (const CamDev*)ctx->cams, V, P,   \
-                     ctx->vis, (const uint32_t*)ctx->blk_base, nb, (uint64_t)cfg.slot_capacity,  \
-                     (uint64_t)cfg.pair_capacity, ctx->slot_rec, ctx->slot_gid, ctx->slot_view, ctx->slot_pix,    \
-                     ctx->slot_pairoff, ctx->slot_ntiles)
+                     ctx->vis, (const uint32_t*)ctx->blk_base, nb, (uint64_t)cfg.slot_capacity,                \
+                     ctx->slot_rec, ctx->slot_gid, ctx->slot_view, ctx->slot_pix, ctx->slot_ntiles)
     switch (g->sh_degree) {
       case 0: KGS_EMIT(0); break;
       case 1: KGS_EMIT(1); break;

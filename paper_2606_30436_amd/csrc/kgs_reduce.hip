@@ -23,10 +23,12 @@ struct BwdParams {
 };
 
 
-// Slot record (40 words): 0-2 dL/dmean, 3-5 dL/dlog_scale, 6-9 dL/dquat,
+// Slot record (24 words): 0-2 dL/dmean, 3-5 dL/dlog_scale, 6-9 dL/dquat,
 // 10 dL/dlogit, 11-16 pose (rho, phi), 17 |Omega| (u32), 18 kappa (u32),
 // 19 ||dL/dmu2D||, 20 pixel radius (i32), 21-23 dL/dcolour where the colour is
-// not clamped (0 where it is), 24-39 the SH basis at the view direction.
+// not clamped (0 where it is).  The SH basis at the view direction, which the
+// SH gradient needs, is evaluated again by the gather from the mean and the
+// camera rather than stored (16 words per slot written and read back).
 // ---------------------------------------------------------------- pair sums
 // Per-slot sums of the 12-word pair records (10 record-space gradient terms
 // and the two footprint counts), three float4 per slot, by a segmented
@@ -77,6 +79,67 @@ __device__ __forceinline__ void store_sum(float4* __restrict__ rec, const float 
 
 #define SEG_NONE 0xffffffffu
 
+struct SegWindow {
+  uint32_t s, s_before, s_after;
+  float x[12];
+};
+
+__device__ __forceinline__ void seg_load(SegWindow& W, uint32_t w, uint32_t np, int l,
+                                         const uint32_t* __restrict__ pair_slot, const float4* __restrict__ pair_grad) {
+  const uint32_t p = w * 64 + (uint32_t)l;
+  const bool valid = p < np;
+  W.s = valid ? pair_slot[p] : SEG_NONE;
+  if (valid) {
+    const float4 a = pair_grad[(size_t)p * 3], b = pair_grad[(size_t)p * 3 + 1], c = pair_grad[(size_t)p * 3 + 2];
+    W.x[0] = a.x; W.x[1] = a.y; W.x[2] = a.z; W.x[3] = a.w;
+    W.x[4] = b.x; W.x[5] = b.y; W.x[6] = b.z; W.x[7] = b.w;
+    W.x[8] = c.x; W.x[9] = c.y;
+    W.x[10] = (float)__float_as_uint(c.z);
+    W.x[11] = (float)__float_as_uint(c.w);
+  } else {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) W.x[k] = 0.f;
+  }
+  // slots just before and just after the window (SEG_NONE - 1: none)
+  W.s_before = w > 0 ? pair_slot[w * 64 - 1] : SEG_NONE - 1u;
+  W.s_after = w * 64 + 64 < np ? pair_slot[w * 64 + 64] : SEG_NONE - 1u;
+}
+
+__device__ __forceinline__ void seg_window(SegWindow& W, uint32_t w, uint32_t np, int l,
+                                           float4* __restrict__ slot_sum, float4* __restrict__ seg_head,
+                                           float4* __restrict__ seg_tail) {
+  const uint32_t s = W.s;
+  const bool valid = w * 64 + (uint32_t)l < np;
+  // both shuffles run in every lane (a lane-conditional shuffle reads 0
+  // from the lanes that skip it)
+  const uint32_t s_up_raw = (uint32_t)__shfl_up((int)s, 1, 64);
+  const uint32_t s_dn_raw = (uint32_t)__shfl_down((int)s, 1, 64);
+  const uint32_t s_up = l > 0 ? s_up_raw : W.s_before;
+  const uint32_t s_dn = l < 63 ? s_dn_raw : W.s_after;
+  const bool head = l == 0 || s != s_up;
+  const uint64_t H = ballot64(head);
+  const uint64_t le = l == 63 ? ~0ull : ((1ull << (l + 1)) - 1ull);
+  const int sst = 63 - __clzll((long long)(H & le));
+#pragma unroll
+  for (int k = 0; k < 12; ++k) W.x[k] = seg_scan(W.x[k], l, sst);
+  const bool tail = valid && s != s_dn;
+  const bool started = sst > 0 || s != W.s_before;   // the slot's first pair lies in this window
+  if (tail) {
+    if (started) {
+      store_sum(slot_sum + (size_t)s * (KGS_SLOT_WORDS / 4), W.x);
+    } else {
+      put_rec(seg_head + (size_t)w * 4, W.x, s, 1u);  // continued from before, ends here
+    }
+  }
+  if (l == 63) {
+    // the window's last segment goes on past the window
+    const bool open = valid && s == s_dn;
+    if (open && !started) put_rec(seg_head + (size_t)w * 4, W.x, s, 0u);   // covers the whole window
+    put_rec(seg_tail + (size_t)w * 4, W.x, (open && started) ? s : SEG_NONE, 0u);
+  }
+}
+
+// Two windows per wave and round, both loaded before either is scanned.
 __global__ __launch_bounds__(256) void k_pair_segsum(const uint32_t* __restrict__ counters,
                                                      const uint32_t* __restrict__ pair_slot,
                                                      const float4* __restrict__ pair_grad,
@@ -85,52 +148,14 @@ __global__ __launch_bounds__(256) void k_pair_segsum(const uint32_t* __restrict_
   const uint32_t np = counters[1];
   const int l = threadIdx.x & 63;
   const uint32_t nwin = (np + 63) / 64;
-  for (uint32_t w = blockIdx.x * 4 + (threadIdx.x >> 6); w < nwin; w += gridDim.x * 4) {
-    const uint32_t p = w * 64 + (uint32_t)l;
-    const bool valid = p < np;
-    const uint32_t s = valid ? pair_slot[p] : SEG_NONE;
-    float x[12];
-    if (valid) {
-      const float4 a = pair_grad[(size_t)p * 3], b = pair_grad[(size_t)p * 3 + 1], c = pair_grad[(size_t)p * 3 + 2];
-      x[0] = a.x; x[1] = a.y; x[2] = a.z; x[3] = a.w;
-      x[4] = b.x; x[5] = b.y; x[6] = b.z; x[7] = b.w;
-      x[8] = c.x; x[9] = c.y;
-      x[10] = (float)__float_as_uint(c.z);
-      x[11] = (float)__float_as_uint(c.w);
-    } else {
-#pragma unroll
-      for (int k = 0; k < 12; ++k) x[k] = 0.f;
-    }
-    // slots just before and just after the window (SEG_NONE - 1: none)
-    const uint32_t s_before = w > 0 ? pair_slot[w * 64 - 1] : SEG_NONE - 1u;
-    const uint32_t s_after = w * 64 + 64 < np ? pair_slot[w * 64 + 64] : SEG_NONE - 1u;
-    // both shuffles run in every lane (a lane-conditional shuffle reads 0
-    // from the lanes that skip it)
-    const uint32_t s_up_raw = (uint32_t)__shfl_up((int)s, 1, 64);
-    const uint32_t s_dn_raw = (uint32_t)__shfl_down((int)s, 1, 64);
-    const uint32_t s_up = l > 0 ? s_up_raw : s_before;
-    const uint32_t s_dn = l < 63 ? s_dn_raw : s_after;
-    const bool head = l == 0 || s != s_up;
-    const uint64_t H = ballot64(head);
-    const uint64_t le = l == 63 ? ~0ull : ((1ull << (l + 1)) - 1ull);
-    const int sst = 63 - __clzll((long long)(H & le));
-#pragma unroll
-    for (int k = 0; k < 12; ++k) x[k] = seg_scan(x[k], l, sst);
-    const bool tail = valid && s != s_dn;
-    const bool started = sst > 0 || s != s_before;   // the slot's first pair lies in this window
-    if (tail) {
-      if (started) {
-        store_sum(slot_sum + (size_t)s * (KGS_SLOT_WORDS / 4), x);
-      } else {
-        put_rec(seg_head + (size_t)w * 4, x, s, 1u);  // continued from before, ends here
-      }
-    }
-    if (l == 63) {
-      // the window's last segment goes on past the window
-      const bool open = valid && s == s_dn;
-      if (open && !started) put_rec(seg_head + (size_t)w * 4, x, s, 0u);   // covers the whole window
-      put_rec(seg_tail + (size_t)w * 4, x, (open && started) ? s : SEG_NONE, 0u);
-    }
+  const uint32_t stride = gridDim.x * 4;
+  for (uint32_t w0 = blockIdx.x * 4 + (threadIdx.x >> 6); w0 < nwin; w0 += 2 * stride) {
+    const uint32_t w1 = w0 + stride;
+    SegWindow A, B;
+    seg_load(A, w0, np, l, pair_slot, pair_grad);
+    if (w1 < nwin) seg_load(B, w1, np, l, pair_slot, pair_grad);
+    seg_window(A, w0, np, l, slot_sum, seg_head, seg_tail);
+    if (w1 < nwin) seg_window(B, w1, np, l, slot_sum, seg_head, seg_tail);
   }
 }
 
@@ -365,8 +390,6 @@ __device__ __forceinline__ void slot_record(uint32_t s, const kgs_gaussians& g, 
             for (int k = 0; k < 3; ++k) pose[k] += c.R[k * 3] * gv0 + c.R[k * 3 + 1] * gv1 + c.R[k * 3 + 2] * gv2;
           }
         }
-#pragma unroll
-      for (int k = 0; k < K; ++k) out[24 + k] = Yb_out[k];
       out[0] = gm[0]; out[1] = gm[1]; out[2] = gm[2];
       out[3] = gls[0]; out[4] = gls[1]; out[5] = gls[2];
       out[6] = gq[0]; out[7] = gq[1]; out[8] = gq[2]; out[9] = gq[3];
@@ -411,15 +434,22 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_slot_bwd(kgs_gaussians g, const C
 // Per Gaussian, the sum of its slot records over the views in view order
 // (vis names each view's slot), added into the gradients and statistics.
 template <int DEG>
-__global__ __launch_bounds__(KGS_BLOCK) void k_gauss_gather(int64_t n, int V, const uint32_t* __restrict__ vis,
+__global__ __launch_bounds__(KGS_BLOCK) void k_gauss_gather(kgs_gaussians g, int V, const CamDev* __restrict__ cams,
+                                                            const uint32_t* __restrict__ vis,
                                                             const uint32_t* __restrict__ counters,
                                                             const float4* __restrict__ slot_bwd,
                                                             const float* __restrict__ view_loss, kgs_grads gr,
                                                             kgs_view_stats st, int overwrite) {
   constexpr int K = (DEG + 1) * (DEG + 1);
+  const int64_t n = g.n;
   const int64_t i = (int64_t)blockIdx.x * KGS_BLOCK + threadIdx.x;
   if (i >= n) return;
   const uint32_t n_slots = counters[0];
+  float mu[3] = {0.f, 0.f, 0.f};
+  if (DEG > 0) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) mu[k] = g.means[k * n + i];
+  }
   float acc[11];
 #pragma unroll
   for (int k = 0; k < 11; ++k) acc[k] = 0.f;
@@ -436,17 +466,28 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_gauss_gather(int64_t n, int V, co
     const float4* r4 = slot_bwd + (size_t)(u - 1u) * (KGS_SLOT_WORDS / 4);
     float r[KGS_SLOT_WORDS];
 #pragma unroll
-    for (int k = 0; k < (24 + K + 3) / 4; ++k) {
+    for (int k = 0; k < KGS_SLOT_WORDS / 4; ++k) {
       const float4 q = r4[k];
       r[4 * k] = q.x; r[4 * k + 1] = q.y; r[4 * k + 2] = q.z; r[4 * k + 3] = q.w;
     }
 #pragma unroll
     for (int k = 0; k < 11; ++k) acc[k] += r[k];
+    // SH basis at this view's direction (as in the chain rule per slot)
+    float Y[16];
+    Y[0] = 0.f;
+    if (DEG > 0) {
+      float dv[3];
+      cam_offset(cams[v], mu, dv);
+      const float idist = 1.0f / sqrtf(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+      sh_basis(DEG, dv[0] * idist, dv[1] * idist, dv[2] * idist, Y);
+    } else {
+      sh_basis(0, 0.f, 0.f, 1.f, Y);
+    }
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      gsh[k][0] += r[24 + k] * r[21];
-      gsh[k][1] += r[24 + k] * r[22];
-      gsh[k][2] += r[24 + k] * r[23];
+      gsh[k][0] += Y[k] * r[21];
+      gsh[k][1] += Y[k] * r[22];
+      gsh[k][2] += Y[k] * r[23];
     }
     const uint32_t om = __float_as_uint(r[17]);
     s_om += om;
@@ -567,7 +608,7 @@ kgs_status kgs_launch_project_bwd(kgs_ctx* ctx, const kgs_gaussians* g, const kg
   if (nb > 0) {
     const unsigned sg = (unsigned)std::min<uint64_t>(std::max<uint64_t>((cap + 255) / 256, 1), 4096);
     const uint64_t wins = ((uint64_t)cfg.pair_capacity + 63) / 64;
-    const unsigned wg = (unsigned)std::min<uint64_t>(std::max<uint64_t>((wins + 3) / 4, 1), 8192);
+    const unsigned wg = (unsigned)std::min<uint64_t>(std::max<uint64_t>((wins + 7) / 8, 1), 4096);
     hipLaunchKernelGGL(k_pair_segsum, dim3(wg), dim3(256), 0, st, (const uint32_t*)ctx->counters,
                        (const uint32_t*)ctx->pair_slot, (const float4*)ctx->pair_grad, ctx->slot_bwd, ctx->seg_head,
                        ctx->seg_tail);
@@ -579,8 +620,9 @@ kgs_status kgs_launch_project_bwd(kgs_ctx* ctx, const kgs_gaussians* g, const kg
                      (const uint32_t*)ctx->counters, (const uint32_t*)ctx->slot_gid,                                \
                      (const uint32_t*)ctx->slot_view, (const uint32_t*)ctx->slot_ntiles, ctx->slot_bwd,            \
                      ctx->slot_pose);                                                                             \
-  hipLaunchKernelGGL(k_gauss_gather<D>, dim3((unsigned)nb), dim3(KGS_BLOCK), 0, st, (int64_t)g->n, V,             \
-                     (const uint32_t*)ctx->vis, (const uint32_t*)ctx->counters, (const float4*)ctx->slot_bwd,     \
+  hipLaunchKernelGGL(k_gauss_gather<D>, dim3((unsigned)nb), dim3(KGS_BLOCK), 0, st, *g, V,                        \
+                     (const CamDev*)ctx->cams, (const uint32_t*)ctx->vis, (const uint32_t*)ctx->counters,          \
+                     (const float4*)ctx->slot_bwd,                                                                \
                      view_loss, G, S, overwrite ? 1 : 0)
     switch (g->sh_degree) {
       case 0: KGS_PB(0); break;

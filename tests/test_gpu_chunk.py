@@ -77,6 +77,12 @@ def test_chunk_run_equals_the_steps(chunk):
     say(f"[gpu] chunk_run vs steps n={sc.n} V={sc.n_views}")
     R = _rast(sc)
     b = Bufs(sc, R)
+    # zero_accumulators: whatever the accumulators held must not matter
+    for t in (b.grads.means, b.grads.log_scales, b.grads.quats, b.grads.logits, b.grads.sh, b.pose,
+              b.stats.gamma_sum, b.stats.grad_norm_sum):
+        t.fill_(float("nan"))
+    for t in (b.stats.kappa_sum, b.stats.omega_sum, b.stats.view_count, b.stats.max_radius):
+        t.fill_(12345)
     R.chunk_run(b.desc())
     torch.cuda.synchronize()
     assert R.status() == 0
