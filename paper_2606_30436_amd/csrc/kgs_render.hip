@@ -116,7 +116,7 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_render_fwd(RenderParams P, const 
                                                           float* __restrict__ tfinal, int32_t* __restrict__ last) {
   __shared__ float4 s_r0[B], s_r1[B], s_r2[B];
   __shared__ uint32_t s_first[B];  // unused by the forward
-  __shared__ uint8_t s_list[4][B];
+  __shared__ __align__(16) uint8_t s_list[4][B];
   __shared__ uint8_t s_mask[B];
   __shared__ uint32_t s_cnt[4][4];
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
@@ -141,13 +141,17 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_render_fwd(RenderParams P, const 
                    s_list, s_cnt);
     const uint32_t len = __builtin_amdgcn_readfirstlane(s_cnt[0][w] + s_cnt[1][w] + s_cnt[2][w] + s_cnt[3][w]);
     const int rel0 = (int)(base - start) + 1;
-    for (uint32_t j = 0; j < len; ++j) {
-      if (!__any(!done)) break;
-      const int tt = __builtin_amdgcn_readfirstlane(s_list[w][j]);  // same entry for the whole wave
+    // the wave's list packed four entries to a lane, read by lane index; two
+    // entries per round (one saturation check for both)
+    const uint32_t packed = 4 * l < B ? reinterpret_cast<const uint32_t*>(s_list[w])[l] : 0u;
+    auto entry = [&](uint32_t j) -> int {
+      return (int)((__builtin_amdgcn_readlane(packed, (int)(j >> 2)) >> (8u * (j & 3u))) & 0xffu);
+    };
+    auto blend = [&](int tt, bool present) {
       const float4 r0 = s_r0[tt], r1 = s_r1[tt], r2 = s_r2[tt];
       float dy, u;
       const float e = log2_alpha(fpx, fpy, r0, r1.x, r1.y, dy, u);
-      const bool hit = !done && e >= P.log2_amin;
+      const bool hit = present && !done && e >= P.log2_amin;
       const float a = hit ? fminf(exp2_approx(e), P.amax) : 0.f;
       const float Tn = T * (1.0f - a);
       const bool stop = hit && Tn < P.tmin;
@@ -160,6 +164,13 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_render_fwd(RenderParams P, const 
       D = fmaf(wgt, r1.z, D);
       T = take ? Tn : T;
       lst = take ? rel0 + tt : lst;
+    };
+    for (uint32_t j = 0; j < len; j += 2) {
+      if (!__any(!done)) break;
+      const bool has_b = j + 1 < len;
+      const int ta = entry(j), tb = entry(has_b ? j + 1 : j);
+      blend(ta, true);
+      blend(tb, has_b);
     }
   }
   if (inside) {
