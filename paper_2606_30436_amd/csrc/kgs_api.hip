@@ -14,7 +14,8 @@ kgs_status kgs_launch_bin_sort(kgs_ctx*, hipStream_t);
 kgs_status kgs_launch_render_fwd(kgs_ctx*, const kgs_image*, hipStream_t);
 kgs_status kgs_launch_loss(kgs_ctx*, const float*, const kgs_image*, float*, float*, hipStream_t);
 kgs_status kgs_launch_render_bwd(kgs_ctx*, const kgs_image*, const float*, const float*, const float*,
-                                 const float*, float, hipStream_t);
+                                 const float*, float, hipStream_t, bool fuse_l1 = false, float* dl_out = nullptr);
+void kgs_launch_loss_final(kgs_ctx*, float*, hipStream_t);
 kgs_status kgs_launch_project_bwd(kgs_ctx*, const kgs_gaussians*, const kgs_camera*, int, const float*,
                                   const float*, const kgs_grads*, const kgs_view_stats*, hipStream_t, bool overwrite = false);
 kgs_status kgs_launch_accumulate(kgs_ctx*, const kgs_view_stats*, int64_t, int, const kgs_lifecycle_state*, float,
@@ -91,7 +92,7 @@ size_t layout(const kgs_config& c, char* base, kgs_ctx* ctx) {
     p = take(16);                               if (ctx) ctx->scan_totals = (unsigned long long*)p;
   }
   p = take(48 * V * KGS_POSE_BLOCKS);           if (ctx) ctx->pose_partial = (double*)p;
-  p = take(8 * V * KGS_LOSS_BLOCKS);            if (ctx) ctx->loss_partial = (double*)p;
+  p = take(8 * V * T);                          if (ctx) ctx->loss_partial = (double*)p;
   p = take(16 * (nb + 1));                      if (ctx) ctx->mm_partial = (double*)p;
   p = take(4 * (nb + 1));                       if (ctx) ctx->keep_partial = (uint32_t*)p;
   return off;
@@ -367,9 +368,12 @@ kgs_status kgs_chunk_run(kgs_ctx* ctx, const kgs_chunk_desc* d, void* stream) {
   if (s != KGS_OK) return s;
   if ((s = kgs_bin_sort(ctx, stream)) != KGS_OK) return s;
   if ((s = kgs_render_fwd(ctx, &d->image, stream)) != KGS_OK) return s;
-  if ((s = kgs_loss_l1(ctx, d->target, &d->image, d->dl_dcolor, d->view_loss, stream)) != KGS_OK) return s;
-  if ((s = kgs_launch_render_bwd(ctx, &d->image, d->dl_dcolor, nullptr, nullptr, d->target, d->tau_err, st)) != KGS_OK)
+  // the L1 loss and its gradient are formed inside the compositing backward
+  // (the same values and partial sums as kgs_loss_l1), then the per-view losses
+  if ((s = kgs_launch_render_bwd(ctx, &d->image, nullptr, nullptr, nullptr, d->target, d->tau_err, st, true,
+                                 d->dl_dcolor)) != KGS_OK)
     return s;
+  kgs_launch_loss_final(ctx, d->view_loss, st);
   s = kgs_launch_project_bwd(ctx, &d->gaussians, d->cams, d->n_views, d->pose_xi, d->view_loss, &d->grads, &d->stats,
                              st, d->zero_accumulators != 0 && n > 0);
   if (s != KGS_OK) return s;

@@ -12,7 +12,6 @@
 #define KGS_BLOCK 256                 // threads per block for per-Gaussian / per-tile kernels
 #define KGS_MAX_VIEWS 64
 #define KGS_SORT_BLOCKS 1024          // fixed grid (one partition per block) of the radix sort passes
-#define KGS_LOSS_BLOCKS 64            // blocks per view of the loss reduction
 #define KGS_MAX_PASSES 8
 #define KGS_POSE_BLOCKS 32            // pieces per view of the pose reduction
 #define KGS_SLOT_WORDS 24             // words of a slot's backward record
@@ -78,7 +77,7 @@ struct kgs_ctx {
   unsigned long long* scan_part;      // tile sums of the device-wide scans
   unsigned long long* scan_totals;    // [2] their totals
   double* pose_partial;               // [max_views][KGS_POSE_BLOCKS][6]
-  double* loss_partial;               // [max_views][KGS_LOSS_BLOCKS]
+  double* loss_partial;               // [max_views * max_tiles] L1 loss per (view, tile)
   double* mm_partial;                 // [nb][2]
   uint32_t* keep_partial;             // [nb + 1]
   // state

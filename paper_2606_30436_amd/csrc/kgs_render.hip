@@ -187,36 +187,66 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_render_fwd(RenderParams P, const 
 }
 
 // ---------------------------------------------------------------- L1 loss harness
-__global__ __launch_bounds__(256) void k_loss_l1(int W, int H, const float* __restrict__ color,
-                                                 const float* __restrict__ target, float* __restrict__ grad,
-                                                 double* __restrict__ partial) {
-  __shared__ float sh[4];
-  const int v = blockIdx.y;
-  const size_t n3 = (size_t)3 * W * H;
-  const float scale = 1.0f / (float)n3;
-  const float* c = color + (size_t)v * n3;
-  const float* tg = target + (size_t)v * n3;
-  float* g = grad + (size_t)v * n3;
-  float acc = 0.f;
-  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n3; i += (size_t)gridDim.x * 256) {
-    const float d = c[i] - tg[i];
-    acc += fabsf(d);
-    g[i] = d > 0.f ? scale : (d < 0.f ? -scale : 0.f);
-  }
+// One workgroup per (view, tile), pixels mapped to lanes as in the
+// compositing kernels.  Per pixel |dR| + |dG| + |dB| in FP32, summed over the
+// wave by a fixed butterfly, the four waves in order in FP64, one partial per
+// (view, tile); k_loss_final adds the partials of a view in tile order.  The
+// chunk's fused backward forms the same partials in the same order, so both
+// routes give the same bits.
+__device__ __forceinline__ void l1_pixel(const float* __restrict__ color, const float* __restrict__ target,
+                                         size_t cpix, size_t npix, float scale, float& g0, float& g1, float& g2,
+                                         float& acc) {
+  const float d0 = color[cpix] - target[cpix];
+  const float d1 = color[cpix + npix] - target[cpix + npix];
+  const float d2 = color[cpix + 2 * npix] - target[cpix + 2 * npix];
+  acc = (fabsf(d0) + fabsf(d1)) + fabsf(d2);
+  g0 = d0 > 0.f ? scale : (d0 < 0.f ? -scale : 0.f);
+  g1 = d1 > 0.f ? scale : (d1 < 0.f ? -scale : 0.f);
+  g2 = d2 > 0.f ? scale : (d2 < 0.f ? -scale : 0.f);
+}
+
+// the block's per-pixel values acc -> partial[gt] (uses sh[4] and one barrier)
+__device__ __forceinline__ void l1_partial(float acc, float* sh, double* __restrict__ partial, int gt) {
   acc = wave_sum(acc);
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
   __syncthreads();
-  if (threadIdx.x == 0)
-    partial[(size_t)v * gridDim.x + blockIdx.x] = ((double)sh[0] + (double)sh[1]) + ((double)sh[2] + (double)sh[3]);
+  if (threadIdx.x == 0) partial[gt] = ((double)sh[0] + (double)sh[1]) + ((double)sh[2] + (double)sh[3]);
 }
 
-__global__ void k_loss_final(int V, int nblk, double inv_n, const double* __restrict__ partial,
-                             float* __restrict__ view_loss) {
-  const int v = threadIdx.x;
-  if (v >= V) return;
+__global__ __launch_bounds__(KGS_BLOCK) void k_loss_l1(RenderParams P, const float* __restrict__ color,
+                                                       const float* __restrict__ target, float* __restrict__ grad,
+                                                       double* __restrict__ partial) {
+  __shared__ float sh[4];
+  const int gt = blockIdx.x;
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int v = gt / P.n_tiles, t = gt - v * P.n_tiles;
+  const int tx = t % P.tiles_x, ty = t / P.tiles_x;
+  int sx, sy;
+  tile_subblock(P.tile_w, w, sx, sy);
+  const int px = tx * P.tile_w + sx + (l & 7), py = ty * P.tile_h + sy + (l >> 3);
+  const size_t npix = (size_t)P.W * P.H;
+  const float scale = 1.0f / (float)(3 * npix);
+  float acc = 0.f;
+  if (px < P.W && py < P.H) {
+    const size_t cpix = (size_t)v * 3 * npix + (size_t)py * P.W + px;
+    float g0, g1, g2;
+    l1_pixel(color, target, cpix, npix, scale, g0, g1, g2, acc);
+    grad[cpix] = g0;
+    grad[cpix + npix] = g1;
+    grad[cpix + 2 * npix] = g2;
+  }
+  l1_partial(acc, sh, partial, gt);
+}
+
+// one wave per view: lane l adds tiles l, l + 64, ... in order, then a fixed
+// butterfly over the lanes
+__global__ __launch_bounds__(64) void k_loss_final(int n_tiles, double inv_n, const double* __restrict__ partial,
+                                                   float* __restrict__ view_loss) {
+  const int v = blockIdx.x, l = threadIdx.x;
   double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += partial[(size_t)v * nblk + b];
-  view_loss[v] = (float)(s * inv_n);
+  for (int b = l; b < n_tiles; b += 64) s += partial[(size_t)v * n_tiles + b];
+  s = wave_sum(s);
+  if (l == 0) view_loss[v] = (float)(s * inv_n);
 }
 
 // ---------------------------------------------------------------- backward
@@ -359,7 +389,8 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_render_bwd(
     const float4* __restrict__ slot_rec, const float* __restrict__ color,
     const float* __restrict__ depth, const float* __restrict__ tfinal, const int32_t* __restrict__ last,
     const float* __restrict__ dl_dcolor, const float* __restrict__ dl_ddepth, const float* __restrict__ dl_dalpha,
-    const float* __restrict__ target, float tau_err, float4* __restrict__ pair_grad) {
+    const float* __restrict__ target, float tau_err, float4* __restrict__ pair_grad, int fuse_l1,
+    float* __restrict__ dl_out, double* __restrict__ loss_partial) {
   __shared__ float4 s_r0[B], s_r1[B], s_r2[B];
   __shared__ uint32_t s_first[B];
   __shared__ __align__(16) uint8_t s_list[4][B];
@@ -367,6 +398,7 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_render_bwd(
   __shared__ uint32_t s_cnt[4][4];
   __shared__ float s_part[4][B][12];
   __shared__ int s_wmax[4];
+  __shared__ float s_loss[4];
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
   const int gt = (int)tile_order[blockIdx.x];
   const int v = gt / P.n_tiles, t = gt - v * P.n_tiles;
@@ -383,6 +415,7 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_render_bwd(
   int lastp = 0;
   float Co0 = 0.f, Co1 = 0.f, Co2 = 0.f, Do = 0.f, g0 = 0.f, g1 = 0.f, g2 = 0.f, gD = 0.f, gAT = 0.f;
   bool M = false;
+  float l1acc = 0.f;
   if (inside) {
     const size_t npix = (size_t)P.W * P.H;
     const size_t pix = (size_t)v * npix + (size_t)py * P.W + px;
@@ -392,9 +425,20 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_render_bwd(
     Co1 = color[cpix + npix];
     Co2 = color[cpix + 2 * npix];
     Do = depth[pix];
-    g0 = dl_dcolor[cpix];
-    g1 = dl_dcolor[cpix + npix];
-    g2 = dl_dcolor[cpix + 2 * npix];
+    if (fuse_l1) {
+      // the L1 loss against target, its gradient and its per-tile partial,
+      // exactly as the loss kernel forms them
+      l1_pixel(color, target, cpix, npix, 1.0f / (float)(3 * npix), g0, g1, g2, l1acc);
+      if (dl_out) {
+        dl_out[cpix] = g0;
+        dl_out[cpix + npix] = g1;
+        dl_out[cpix + 2 * npix] = g2;
+      }
+    } else {
+      g0 = dl_dcolor[cpix];
+      g1 = dl_dcolor[cpix + npix];
+      g2 = dl_dcolor[cpix + 2 * npix];
+    }
     if (dl_ddepth) gD = dl_ddepth[pix];
     // opacity image A = 1 - T_final: dA/dalpha_j = T_final / (1 - alpha_j)
     if (dl_dalpha) gAT = dl_dalpha[pix] * tfinal[pix];
@@ -404,6 +448,7 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_render_bwd(
       M = err > tau_err;
     }
   }
+  if (fuse_l1) l1_partial(l1acc, s_loss, loss_partial, gt);
   int wmax = lastp;
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) wmax = max(wmax, __shfl_xor(wmax, o, 64));
@@ -567,19 +612,32 @@ kgs_status kgs_launch_render_fwd(kgs_ctx* ctx, const kgs_image* out, hipStream_t
   return kgs_check_launch();
 }
 
+void kgs_launch_loss_final(kgs_ctx* ctx, float* view_loss, hipStream_t st);
+
 kgs_status kgs_launch_loss(kgs_ctx* ctx, const float* target, const kgs_image* img, float* dl_dcolor,
                            float* view_loss, hipStream_t st) {
   const int V = ctx->last_views;
-  hipLaunchKernelGGL(k_loss_l1, dim3(KGS_LOSS_BLOCKS, V), dim3(256), 0, st, ctx->cfg.width, ctx->cfg.height,
+  const RenderParams P = render_params(ctx);
+  hipLaunchKernelGGL(k_loss_l1, dim3((unsigned)(V * ctx->n_tiles)), dim3(KGS_BLOCK), 0, st, P,
                      (const float*)img->color, target, dl_dcolor, ctx->loss_partial);
-  const double inv_n = 1.0 / (3.0 * (double)ctx->cfg.width * (double)ctx->cfg.height);
-  hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, st, V, KGS_LOSS_BLOCKS, inv_n,
-                     (const double*)ctx->loss_partial, view_loss);
+  kgs_launch_loss_final(ctx, view_loss, st);
   return kgs_check_launch();
 }
 
+void kgs_launch_loss_final(kgs_ctx* ctx, float* view_loss, hipStream_t st) {
+  const int V = ctx->last_views;
+  const double inv_n = 1.0 / (3.0 * (double)ctx->cfg.width * (double)ctx->cfg.height);
+  if (V > 0)
+    hipLaunchKernelGGL(k_loss_final, dim3(V), dim3(64), 0, st, ctx->n_tiles, inv_n, (const double*)ctx->loss_partial,
+                       view_loss);
+}
+
+// fuse_l1: the colour gradient is the L1 loss gradient against target, formed
+// here (and written to dl_dcolor if it is not null) together with the loss
+// partials; kgs_launch_loss_final then gives the per-view losses.
 kgs_status kgs_launch_render_bwd(kgs_ctx* ctx, const kgs_image* fwd, const float* dl_dcolor, const float* dl_ddepth,
-                                 const float* dl_dalpha, const float* target, float tau_err, hipStream_t st) {
+                                 const float* dl_dalpha, const float* target, float tau_err, hipStream_t st,
+                                 bool fuse_l1, float* dl_out) {
   const RenderParams P = render_params(ctx);
   const unsigned grid = (unsigned)(ctx->last_views * ctx->n_tiles);
 #define KGS_BWD(BB)                                                                                              \
@@ -588,7 +646,8 @@ kgs_status kgs_launch_render_bwd(kgs_ctx* ctx, const kgs_image* fwd, const float
                      (const uint32_t*)ctx->sorted_slot,                                                           \
                      (const float4*)ctx->slot_rec,                                                                \
                      (const float*)fwd->color, (const float*)fwd->depth, (const float*)fwd->t_final,              \
-                     (const int32_t*)fwd->last, dl_dcolor, dl_ddepth, dl_dalpha, target, tau_err, ctx->pair_grad)
+                     (const int32_t*)fwd->last, dl_dcolor, dl_ddepth, dl_dalpha, target, tau_err, ctx->pair_grad,  \
+                     fuse_l1 ? 1 : 0, dl_out, ctx->loss_partial)
   switch (ctx->cfg.batch) {
     case 32: KGS_BWD(32); break;
     case 64: KGS_BWD(64); break;
