@@ -96,8 +96,10 @@ typedef struct kgs_camera {
  * (appendix, "Level-of-Detail (LoD) Mask Computation": a Gaussian is rendered
  * only inside its level's distance range): camera depths >= far_z are culled. */
 typedef struct kgs_config {
-  int32_t tile_w, tile_h;   /* 16x16, 8x32 or 32x8 */
-  int32_t batch;            /* Gaussians staged per LDS batch: 32, 64, 128 or 256 */
+  int32_t tile_w, tile_h;   /* 16x16, 8x32, 32x8 (four waves per compositing workgroup)
+                               or 32x16, 16x32 (eight waves) */
+  int32_t batch;            /* Gaussians staged per LDS batch: 32, 64, 128 or 256
+                               (at most 128 with 512-pixel tiles) */
   int32_t sh_degree;        /* 0..3 */
   float alpha_min, alpha_max, t_min, near_z, eps2d, guard, rect_margin, far_z;
   float bg[3];
@@ -219,7 +221,8 @@ kgs_status kgs_create(const kgs_config* cfg, void* workspace, size_t bytes, kgs_
 kgs_status kgs_destroy(kgs_ctx* ctx);
 
 /* Change the tile shape and LDS batch of an existing context (the workspace
- * is sized for every supported shape).  Takes effect at the next project. */
+ * is sized for every supported shape).  Takes effect at the next project.
+ * KGS_ERR_INVALID_ARG for a shape or batch the configuration does not allow. */
 kgs_status kgs_set_tiling(kgs_ctx* ctx, int32_t tile_w, int32_t tile_h, int32_t batch);
 
 /* EWA projection of every Gaussian into every view (Sec. 3.2 map

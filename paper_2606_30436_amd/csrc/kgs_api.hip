@@ -32,7 +32,12 @@ kgs_status kgs_check_launch() {
 
 namespace {
 
-bool tile_ok(int w, int h) { return (w == 16 && h == 16) || (w == 8 && h == 32) || (w == 32 && h == 8); }
+bool tile_ok(int w, int h) {
+  return (w == 16 && h == 16) || (w == 8 && h == 32) || (w == 32 && h == 8) || (w == 32 && h == 16) ||
+         (w == 16 && h == 32);
+}
+// 512-pixel tiles (eight waves per workgroup) stage at most 128 records at a time
+bool tiling_ok(int w, int h, int batch) { return tile_ok(w, h) && !(w * h == 512 && batch > 128); }
 bool batch_ok(int b) { return b == 32 || b == 64 || b == 128 || b == 256; }
 
 int tiles_for(int W, int H, int tw, int th) { return ((W + tw - 1) / tw) * ((H + th - 1) / th); }
@@ -100,7 +105,7 @@ size_t layout(const kgs_config& c, char* base, kgs_ctx* ctx) {
 
 kgs_status config_check(const kgs_config* c) {
   if (!c) return KGS_ERR_INVALID_ARG;
-  if (!tile_ok(c->tile_w, c->tile_h) || !batch_ok(c->batch)) return KGS_ERR_INVALID_ARG;
+  if (!tiling_ok(c->tile_w, c->tile_h, c->batch) || !batch_ok(c->batch)) return KGS_ERR_INVALID_ARG;
   if (c->sh_degree < 0 || c->sh_degree > 3) return KGS_ERR_INVALID_ARG;
   if (c->width <= 0 || c->height <= 0 || c->width > 32000 || c->height > 32000) return KGS_ERR_INVALID_ARG;
   if (c->max_views < 1 || c->max_views > KGS_MAX_VIEWS) return KGS_ERR_INVALID_ARG;
@@ -198,7 +203,7 @@ kgs_status kgs_destroy(kgs_ctx* ctx) {
 }
 
 kgs_status kgs_set_tiling(kgs_ctx* ctx, int32_t tile_w, int32_t tile_h, int32_t batch) {
-  if (!ctx || !tile_ok(tile_w, tile_h) || !batch_ok(batch)) return KGS_ERR_INVALID_ARG;
+  if (!ctx || !tiling_ok(tile_w, tile_h, batch) || !batch_ok(batch)) return KGS_ERR_INVALID_ARG;
   ctx->cfg.tile_w = tile_w;
   ctx->cfg.tile_h = tile_h;
   ctx->cfg.batch = batch;

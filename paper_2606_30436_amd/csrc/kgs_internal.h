@@ -420,12 +420,13 @@ __device__ __forceinline__ float log2_alpha(float px, float py, const float4& r0
 
 __device__ __forceinline__ float exp2_approx(float e) { return __builtin_amdgcn_exp2f(e); }
 
-// Pixel of lane `l` of wave `w` in a tile: every tile of 256 pixels is four
-// 8x8 sub-blocks, one per wave.
+// Pixel of lane `l` of wave `w` in a tile: a tile of 64 NW pixels is NW 8x8
+// sub-blocks, one per wave of its workgroup (NW = 4 for 16x16, 32x8, 8x32;
+// NW = 8 for 32x16, 16x32).
 __device__ __forceinline__ void tile_subblock(int tile_w, int w, int& sx, int& sy) {
-  if (tile_w == 16) { sx = (w & 1) * 8; sy = (w >> 1) * 8; }
-  else if (tile_w == 8) { sx = 0; sy = w * 8; }
-  else { sx = w * 8; sy = 0; }
+  const int nsx = tile_w >> 3;  // sub-blocks per tile row, in row-major order
+  sx = (w % nsx) * 8;
+  sy = (w / nsx) * 8;
 }
 
 // Host-side kernel launch helpers (defined in kgs_api.hip).

@@ -53,12 +53,12 @@ __device__ __forceinline__ bool footprint_meets_box(float x0, float x1, float y0
 // Stage B pairs of [base, end) into LDS and build the per-wave lists: a wave's
 // list holds the pairs whose pixel rectangle meets its 8x8 sub-block and whose
 // footprint reaches the sub-block's pixel centres.
-template <int B, bool FIRST_PAIR>
+template <int B, int NW, bool FIRST_PAIR>
 __device__ __forceinline__ void stage_batch(uint32_t base, uint32_t end, const uint32_t* __restrict__ sorted_slot,
                                             const float4* __restrict__ slot_rec, int tile_x0, int tile_y0,
                                             int tile_w, int ox, int oy, float log2_amin, float4* s_r0,
                                             float4* s_r1, float4* s_r2, uint32_t* s_first, uint8_t* s_mask,
-                                            uint8_t (*s_list)[B], uint32_t (*s_cnt)[4]) {
+                                            uint8_t (*s_list)[B], uint32_t (*s_cnt)[NW]) {
   const int tid = threadIdx.x, w = tid >> 6;
   uint32_t m = 0;
   if (tid < B) {
@@ -75,7 +75,7 @@ __device__ __forceinline__ void stage_batch(uint32_t base, uint32_t end, const u
       const int xlo = (int)(int16_t)(xb & 0xffffu), xhi = (int)(int16_t)(xb >> 16);
       const int ylo = (int)(int16_t)(yb & 0xffffu), yhi = (int)(int16_t)(yb >> 16);
 #pragma unroll
-      for (int ww = 0; ww < 4; ++ww) {
+      for (int ww = 0; ww < NW; ++ww) {
         int sx, sy;
         tile_subblock(tile_w, ww, sx, sy);
         const int bx = tile_x0 + sx, by = tile_y0 + sy;
@@ -88,14 +88,14 @@ __device__ __forceinline__ void stage_batch(uint32_t base, uint32_t end, const u
     s_mask[tid] = (uint8_t)m;
   }
 #pragma unroll
-  for (int ww = 0; ww < 4; ++ww) {
+  for (int ww = 0; ww < NW; ++ww) {
     const uint64_t bal = ballot64((m >> ww) & 1u);
     if ((tid & 63) == 0) s_cnt[w][ww] = (uint32_t)__popcll(bal);
   }
   __syncthreads();
   if (tid < B) {
 #pragma unroll
-    for (int ww = 0; ww < 4; ++ww) {
+    for (int ww = 0; ww < NW; ++ww) {
       const uint64_t bal = ballot64((m >> ww) & 1u);
       if ((m >> ww) & 1u) {
         uint32_t pos = mask_lt_count(bal);
@@ -107,8 +107,8 @@ __device__ __forceinline__ void stage_batch(uint32_t base, uint32_t end, const u
   __syncthreads();
 }
 
-template <int B>
-__global__ __launch_bounds__(KGS_BLOCK) void k_render_fwd(RenderParams P, const uint2* __restrict__ ranges,
+template <int B, int NW>
+__global__ __launch_bounds__(64 * NW) void k_render_fwd(RenderParams P, const uint2* __restrict__ ranges,
                                                           const uint32_t* __restrict__ tile_order,
                                                           const uint32_t* __restrict__ sorted_slot,
                                                           const float4* __restrict__ slot_rec,
@@ -116,9 +116,9 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_render_fwd(RenderParams P, const 
                                                           float* __restrict__ tfinal, int32_t* __restrict__ last) {
   __shared__ float4 s_r0[B], s_r1[B], s_r2[B];
   __shared__ uint32_t s_first[B];  // unused by the forward
-  __shared__ __align__(16) uint8_t s_list[4][B];
+  __shared__ __align__(16) uint8_t s_list[NW][B];
   __shared__ uint8_t s_mask[B];
-  __shared__ uint32_t s_cnt[4][4];
+  __shared__ uint32_t s_cnt[NW][NW];
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
   const int gt = (int)tile_order[blockIdx.x];
   const int v = gt / P.n_tiles, t = gt - v * P.n_tiles;
@@ -136,10 +136,13 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_render_fwd(RenderParams P, const 
   bool done = !inside;
   for (uint32_t base = start; base < end; base += B) {
     if (__syncthreads_count(!done) == 0) break;
-    stage_batch<B, false>(base, end, sorted_slot, slot_rec, tile_x0, tile_y0, P.tile_w, pix_origin(P.W), pix_origin(P.H),
+    stage_batch<B, NW, false>(base, end, sorted_slot, slot_rec, tile_x0, tile_y0, P.tile_w, pix_origin(P.W), pix_origin(P.H),
                    P.log2_amin, s_r0, s_r1, s_r2, s_first, s_mask,
                    s_list, s_cnt);
-    const uint32_t len = __builtin_amdgcn_readfirstlane(s_cnt[0][w] + s_cnt[1][w] + s_cnt[2][w] + s_cnt[3][w]);
+    uint32_t len = 0;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) len += s_cnt[k][w];
+    len = __builtin_amdgcn_readfirstlane(len);
     const int rel0 = (int)(base - start) + 1;
     // the wave's list packed four entries to a lane, read by lane index; two
     // entries per round (one saturation check for both)
@@ -205,18 +208,25 @@ __device__ __forceinline__ void l1_pixel(const float* __restrict__ color, const 
   g2 = d2 > 0.f ? scale : (d2 < 0.f ? -scale : 0.f);
 }
 
-// the block's per-pixel values acc -> partial[gt] (uses sh[4] and one barrier)
+// the block's per-pixel values acc -> partial[gt] (uses sh[NW] and one
+// barrier): wave sums by a fixed butterfly, waves added pairwise in FP64
+template <int NW>
 __device__ __forceinline__ void l1_partial(float acc, float* sh, double* __restrict__ partial, int gt) {
   acc = wave_sum(acc);
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
   __syncthreads();
-  if (threadIdx.x == 0) partial[gt] = ((double)sh[0] + (double)sh[1]) + ((double)sh[2] + (double)sh[3]);
+  if (threadIdx.x == 0) {
+    double d = ((double)sh[0] + (double)sh[1]) + ((double)sh[2] + (double)sh[3]);
+    if (NW == 8) d += ((double)sh[4] + (double)sh[5]) + ((double)sh[6] + (double)sh[7]);
+    partial[gt] = d;
+  }
 }
 
-__global__ __launch_bounds__(KGS_BLOCK) void k_loss_l1(RenderParams P, const float* __restrict__ color,
+template <int NW>
+__global__ __launch_bounds__(64 * NW) void k_loss_l1(RenderParams P, const float* __restrict__ color,
                                                        const float* __restrict__ target, float* __restrict__ grad,
                                                        double* __restrict__ partial) {
-  __shared__ float sh[4];
+  __shared__ float sh[NW];
   const int gt = blockIdx.x;
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int v = gt / P.n_tiles, t = gt - v * P.n_tiles;
@@ -235,7 +245,7 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_loss_l1(RenderParams P, const flo
     grad[cpix + npix] = g1;
     grad[cpix + 2 * npix] = g2;
   }
-  l1_partial(acc, sh, partial, gt);
+  l1_partial<NW>(acc, sh, partial, gt);
 }
 
 // one wave per view: lane l adds tiles l, l + 64, ... in order, then a fixed
@@ -382,8 +392,8 @@ __device__ __forceinline__ uint32_t pair_position(uint32_t first, float xb_f, fl
   return first + (uint32_t)((ty - y0) * (x1 - x0) + (tx - x0));
 }
 
-template <int B>
-__global__ __launch_bounds__(KGS_BLOCK) void k_render_bwd(
+template <int B, int NW>
+__global__ __launch_bounds__(64 * NW) void k_render_bwd(
     RenderParams P, const uint2* __restrict__ ranges, const uint32_t* __restrict__ tile_order,
     const uint32_t* __restrict__ sorted_slot,
     const float4* __restrict__ slot_rec, const float* __restrict__ color,
@@ -393,12 +403,12 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_render_bwd(
     float* __restrict__ dl_out, double* __restrict__ loss_partial) {
   __shared__ float4 s_r0[B], s_r1[B], s_r2[B];
   __shared__ uint32_t s_first[B];
-  __shared__ __align__(16) uint8_t s_list[4][B];
+  __shared__ __align__(16) uint8_t s_list[NW][B];
   __shared__ uint8_t s_mask[B];
-  __shared__ uint32_t s_cnt[4][4];
-  __shared__ float s_part[4][B][12];
-  __shared__ int s_wmax[4];
-  __shared__ float s_loss[4];
+  __shared__ uint32_t s_cnt[NW][NW];
+  __shared__ float s_part[NW][B][12];
+  __shared__ int s_wmax[NW];
+  __shared__ float s_loss[NW];
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
   const int gt = (int)tile_order[blockIdx.x];
   const int v = gt / P.n_tiles, t = gt - v * P.n_tiles;
@@ -448,14 +458,16 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_render_bwd(
       M = err > tau_err;
     }
   }
-  if (fuse_l1) l1_partial(l1acc, s_loss, loss_partial, gt);
+  if (fuse_l1) l1_partial<NW>(l1acc, s_loss, loss_partial, gt);
   int wmax = lastp;
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) wmax = max(wmax, __shfl_xor(wmax, o, 64));
   wmax = __builtin_amdgcn_readfirstlane(wmax);
   if (l == 0) s_wmax[w] = wmax;
   __syncthreads();
-  const int bmax = max(max(s_wmax[0], s_wmax[1]), max(s_wmax[2], s_wmax[3]));
+  int bmax = s_wmax[0];
+#pragma unroll
+  for (int k = 1; k < NW; ++k) bmax = max(bmax, s_wmax[k]);
   const uint32_t pend = start + (uint32_t)bmax;
   // dL/dalpha_j = T_j (g . c_j) - (g . (C - C_j)) / (1 - alpha_j) + gAT / (1 - alpha_j)
   // with C the final colour (and depth) and C_j its part from Gaussians up to j;
@@ -465,10 +477,13 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_render_bwd(
   uint32_t base = start;
   for (; base < pend; base += B) {
     __syncthreads();
-    stage_batch<B, true>(base, end, sorted_slot, slot_rec, tile_x0, tile_y0, P.tile_w, pix_origin(P.W), pix_origin(P.H),
+    stage_batch<B, NW, true>(base, end, sorted_slot, slot_rec, tile_x0, tile_y0, P.tile_w, pix_origin(P.W), pix_origin(P.H),
                    P.log2_amin, s_r0, s_r1, s_r2, s_first, s_mask,
                    s_list, s_cnt);
-    const uint32_t len = __builtin_amdgcn_readfirstlane(s_cnt[0][w] + s_cnt[1][w] + s_cnt[2][w] + s_cnt[3][w]);
+    uint32_t len = 0;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) len += s_cnt[k][w];
+    len = __builtin_amdgcn_readfirstlane(len);
     const int rel0 = (int)(base - start);
     // list entries two at a time: a pair of entries that both blend shares one
     // reduction of twenty values; otherwise the one that blends is reduced alone
@@ -545,7 +560,7 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_render_bwd(
 #pragma unroll
         for (int q = 0; q < 10; ++q) o[q] = 0.f;
 #pragma unroll
-        for (int ww = 0; ww < 4; ++ww) {
+        for (int ww = 0; ww < NW; ++ww) {
           if (((m >> ww) & 1u) && krel < s_wmax[ww]) {
 #pragma unroll
             for (int q = 0; q < 10; ++q) o[q] += s_part[ww][tid][q];
@@ -561,7 +576,7 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_render_bwd(
     }
   }
   // pairs behind the tile's last blended Gaussian contribute nothing
-  for (uint32_t k = base + tid; k < end; k += KGS_BLOCK) {
+  for (uint32_t k = base + tid; k < end; k += 64 * NW) {
     const uint32_t s = sorted_slot[k];
     const float4* rec = slot_rec + (size_t)s * 4;
     const size_t p = (size_t)pair_position(__float_as_uint(rec[3].x), rec[1].w, rec[2].w,
@@ -574,6 +589,9 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_render_bwd(
 }
 
 // ---------------------------------------------------------------- host side
+// waves per compositing workgroup: one per 8x8 sub-block of the tile
+static int tile_waves(const kgs_ctx* ctx) { return ctx->cfg.tile_w * ctx->cfg.tile_h / 64; }
+
 static RenderParams render_params(const kgs_ctx* ctx) {
   RenderParams P;
   P.W = ctx->cfg.width;
@@ -597,16 +615,24 @@ kgs_status kgs_launch_render_fwd(kgs_ctx* ctx, const kgs_image* out, hipStream_t
   const unsigned grid = (unsigned)(ctx->last_views * ctx->n_tiles);
   const int s = ctx->sorted_buf;
   (void)s;
-#define KGS_FWD(BB)                                                                                              \
-  hipLaunchKernelGGL(k_render_fwd<BB>, dim3(grid), dim3(KGS_BLOCK), 0, st, P, (const uint2*)ctx->ranges,          \
+#define KGS_FWD(BB, NWV)                                                                                         \
+  hipLaunchKernelGGL((k_render_fwd<BB, NWV>), dim3(grid), dim3(64 * NWV), 0, st, P, (const uint2*)ctx->ranges,   \
                      (const uint32_t*)ctx->tile_order,                                                           \
                      (const uint32_t*)ctx->sorted_slot, (const float4*)ctx->slot_rec, out->color, out->depth,      \
                      out->t_final, out->last)
-  switch (ctx->cfg.batch) {
-    case 32: KGS_FWD(32); break;
-    case 64: KGS_FWD(64); break;
-    case 128: KGS_FWD(128); break;
-    default: KGS_FWD(256); break;
+  if (tile_waves(ctx) == 8) {
+    switch (ctx->cfg.batch) {
+      case 32: KGS_FWD(32, 8); break;
+      case 64: KGS_FWD(64, 8); break;
+      default: KGS_FWD(128, 8); break;
+    }
+  } else {
+    switch (ctx->cfg.batch) {
+      case 32: KGS_FWD(32, 4); break;
+      case 64: KGS_FWD(64, 4); break;
+      case 128: KGS_FWD(128, 4); break;
+      default: KGS_FWD(256, 4); break;
+    }
   }
 #undef KGS_FWD
   return kgs_check_launch();
@@ -618,8 +644,12 @@ kgs_status kgs_launch_loss(kgs_ctx* ctx, const float* target, const kgs_image* i
                            float* view_loss, hipStream_t st) {
   const int V = ctx->last_views;
   const RenderParams P = render_params(ctx);
-  hipLaunchKernelGGL(k_loss_l1, dim3((unsigned)(V * ctx->n_tiles)), dim3(KGS_BLOCK), 0, st, P,
-                     (const float*)img->color, target, dl_dcolor, ctx->loss_partial);
+  if (tile_waves(ctx) == 8)
+    hipLaunchKernelGGL(k_loss_l1<8>, dim3((unsigned)(V * ctx->n_tiles)), dim3(512), 0, st, P,
+                       (const float*)img->color, target, dl_dcolor, ctx->loss_partial);
+  else
+    hipLaunchKernelGGL(k_loss_l1<4>, dim3((unsigned)(V * ctx->n_tiles)), dim3(256), 0, st, P,
+                       (const float*)img->color, target, dl_dcolor, ctx->loss_partial);
   kgs_launch_loss_final(ctx, view_loss, st);
   return kgs_check_launch();
 }
@@ -640,19 +670,27 @@ kgs_status kgs_launch_render_bwd(kgs_ctx* ctx, const kgs_image* fwd, const float
                                  bool fuse_l1, float* dl_out) {
   const RenderParams P = render_params(ctx);
   const unsigned grid = (unsigned)(ctx->last_views * ctx->n_tiles);
-#define KGS_BWD(BB)                                                                                              \
-  hipLaunchKernelGGL(k_render_bwd<BB>, dim3(grid), dim3(KGS_BLOCK), 0, st, P, (const uint2*)ctx->ranges,          \
+#define KGS_BWD(BB, NWV)                                                                                         \
+  hipLaunchKernelGGL((k_render_bwd<BB, NWV>), dim3(grid), dim3(64 * NWV), 0, st, P, (const uint2*)ctx->ranges,   \
                      (const uint32_t*)ctx->tile_order,                                                           \
                      (const uint32_t*)ctx->sorted_slot,                                                           \
                      (const float4*)ctx->slot_rec,                                                                \
                      (const float*)fwd->color, (const float*)fwd->depth, (const float*)fwd->t_final,              \
                      (const int32_t*)fwd->last, dl_dcolor, dl_ddepth, dl_dalpha, target, tau_err, ctx->pair_grad,  \
                      fuse_l1 ? 1 : 0, dl_out, ctx->loss_partial)
-  switch (ctx->cfg.batch) {
-    case 32: KGS_BWD(32); break;
-    case 64: KGS_BWD(64); break;
-    case 128: KGS_BWD(128); break;
-    default: KGS_BWD(256); break;
+  if (tile_waves(ctx) == 8) {
+    switch (ctx->cfg.batch) {
+      case 32: KGS_BWD(32, 8); break;
+      case 64: KGS_BWD(64, 8); break;
+      default: KGS_BWD(128, 8); break;
+    }
+  } else {
+    switch (ctx->cfg.batch) {
+      case 32: KGS_BWD(32, 4); break;
+      case 64: KGS_BWD(64, 4); break;
+      case 128: KGS_BWD(128, 4); break;
+      default: KGS_BWD(256, 4); break;
+    }
   }
 #undef KGS_BWD
   return kgs_check_launch();

@@ -13,8 +13,13 @@ import torch
 from . import _lib as L
 from .scenes import CAMERA_DTYPE
 
-TILE_SHAPES = ((16, 16), (8, 32), (32, 8))
+TILE_SHAPES = ((16, 16), (8, 32), (32, 8), (32, 16), (16, 32))
 BATCHES = (32, 64, 128, 256)
+
+
+def tiling_valid(tile, batch) -> bool:
+    """The library's rule: 512-pixel tiles stage at most 128 records at a time."""
+    return tuple(tile) in TILE_SHAPES and batch in BATCHES and not (tile[0] * tile[1] == 512 and batch > 128)
 
 
 @dataclasses.dataclass

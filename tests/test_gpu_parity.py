@@ -79,7 +79,8 @@ def test_project_records_match_oracle(name):
         assert same.mean() >= 0.995, same.mean()
 
 
-@pytest.mark.parametrize("name,tile", [("c1", (16, 16)), ("c1", (8, 32)), ("tiny", (32, 8))])
+@pytest.mark.parametrize("name,tile", [("c1", (16, 16)), ("c1", (8, 32)), ("tiny", (32, 8)), ("c1", (32, 16)),
+                                       ("tiny", (16, 32))])
 def test_binning_is_bit_exact(name, tile):
     """Sorted (key, Gaussian) list == the integer binning contract applied to
     the GPU's own fp32 centres, extents and depths, sorted on the CPU."""
@@ -228,8 +229,8 @@ def test_tile_shapes_and_batches_give_identical_images():
     sc = _scene("c1")
     say("[gpu] tile invariance")
     ref = None
-    for tile in ((16, 16), (8, 32), (32, 8)):
-        for batch in (32, 256):
+    for tile in ((16, 16), (8, 32), (32, 8), (32, 16), (16, 32)):
+        for batch in (32, 128 if tile[0] * tile[1] == 512 else 256):
             R = _rast(sc, tile=tile, batch=batch)
             _, _, _, img = run_forward(R, sc)
             c = img.color.cpu().numpy()
@@ -240,7 +241,8 @@ def test_tile_shapes_and_batches_give_identical_images():
 
 
 def test_tile_shapes_and_batches_give_the_same_gradients():
-    """The backward over every tile shape and LDS batch: the same gradients up
+    """The backward over every tile shape (four- and eight-wave workgroups) and
+    LDS batch: the same gradients up
     to FP32 summation order (list entries are reduced in pairs or alone
     depending on where a batch ends), on a scene dense enough for per-wave
     lists longer than a wavefront."""
@@ -251,8 +253,10 @@ def test_tile_shapes_and_batches_give_the_same_gradients():
     dLdC = torch.from_numpy(rng.normal(size=(V, 3, H, W)).astype(np.float32)).cuda()
     dLdD = torch.from_numpy((rng.normal(size=(V, H, W)) * 0.05).astype(np.float32)).cuda()
     ref = None
-    for tile in ((16, 16), (8, 32), (32, 8)):
+    for tile in ((16, 16), (8, 32), (32, 8), (32, 16), (16, 32)):
         for batch in (32, 64, 128, 256):
+            if tile[0] * tile[1] == 512 and batch > 128:
+                continue
             R = _rast(sc, tile=tile, batch=batch)
             g, cams, xi, img = run_forward(R, sc)
             if ref is None:

@@ -318,7 +318,7 @@ def test_oracle_matches_tile_free_autograd(seed, degree, pose):
         assert np.allclose(g["pose_xi"], xi.grad.numpy(), rtol=1e-7, atol=1e-9 * (1 + np.abs(xi.grad.numpy()).max()))
 
 
-@pytest.mark.parametrize("tile", [(8, 32), (32, 8)])
+@pytest.mark.parametrize("tile", [(8, 32), (32, 8), (32, 16), (16, 32)])
 def test_oracle_image_is_tile_shape_invariant(tile):
     sc = scenes.tiny_scene(seed=7, n=40, degree=1, W=72, H=56)
     a = oracle.View(sc, 0, CFG).image()
