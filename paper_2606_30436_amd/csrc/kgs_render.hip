@@ -107,18 +107,19 @@ __device__ __forceinline__ void stage_batch(uint32_t base, uint32_t end, const u
   __syncthreads();
 }
 
-template <int B, int NW>
+// Forward: every wave stages the tile's records itself, 64 at a time (one per
+// lane), keeps those that reach its sub-block (rectangle, then the exact
+// footprint test) compacted in its own LDS rows, and composites them; no
+// workgroup barrier, so each wave stops as soon as its own pixels saturate.
+template <int NW>
 __global__ __launch_bounds__(64 * NW) void k_render_fwd(RenderParams P, const uint2* __restrict__ ranges,
-                                                          const uint32_t* __restrict__ tile_order,
-                                                          const uint32_t* __restrict__ sorted_slot,
-                                                          const float4* __restrict__ slot_rec,
-                                                          float* __restrict__ color, float* __restrict__ depth,
-                                                          float* __restrict__ tfinal, int32_t* __restrict__ last) {
-  __shared__ float4 s_r0[B], s_r1[B], s_r2[B];
-  __shared__ uint32_t s_first[B];  // unused by the forward
-  __shared__ __align__(16) uint8_t s_list[NW][B];
-  __shared__ uint8_t s_mask[B];
-  __shared__ uint32_t s_cnt[NW][NW];
+                                                        const uint32_t* __restrict__ tile_order,
+                                                        const uint32_t* __restrict__ sorted_slot,
+                                                        const float4* __restrict__ slot_rec,
+                                                        float* __restrict__ color, float* __restrict__ depth,
+                                                        float* __restrict__ tfinal, int32_t* __restrict__ last) {
+  __shared__ float4 s_r0[NW][64], s_r1[NW][64], s_r2[NW][64];
+  __shared__ int s_pos[NW][64];
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
   const int gt = (int)tile_order[blockIdx.x];
   const int v = gt / P.n_tiles, t = gt - v * P.n_tiles;
@@ -126,34 +127,49 @@ __global__ __launch_bounds__(64 * NW) void k_render_fwd(RenderParams P, const ui
   const int tile_x0 = tx * P.tile_w, tile_y0 = ty * P.tile_h;
   int sx, sy;
   tile_subblock(P.tile_w, w, sx, sy);
-  const int px = tile_x0 + sx + (l & 7), py = tile_y0 + sy + (l >> 3);
+  const int bx = tile_x0 + sx, by = tile_y0 + sy;
+  const int px = bx + (l & 7), py = by + (l >> 3);
   const bool inside = px < P.W && py < P.H;
-  const float fpx = (float)(px - pix_origin(P.W)), fpy = (float)(py - pix_origin(P.H));
+  const int ox = pix_origin(P.W), oy = pix_origin(P.H);
+  const float fpx = (float)(px - ox), fpy = (float)(py - oy);
   const uint2 rg = ranges[gt];
   const uint32_t start = rg.x, end = rg.y;
   float T = 1.0f, c0 = 0.f, c1 = 0.f, c2 = 0.f, D = 0.f;
   int lst = 0;
   bool done = !inside;
-  for (uint32_t base = start; base < end; base += B) {
-    if (__syncthreads_count(!done) == 0) break;
-    stage_batch<B, NW, false>(base, end, sorted_slot, slot_rec, tile_x0, tile_y0, P.tile_w, pix_origin(P.W), pix_origin(P.H),
-                   P.log2_amin, s_r0, s_r1, s_r2, s_first, s_mask,
-                   s_list, s_cnt);
-    uint32_t len = 0;
-#pragma unroll
-    for (int k = 0; k < NW; ++k) len += s_cnt[k][w];
-    len = __builtin_amdgcn_readfirstlane(len);
-    const int rel0 = (int)(base - start) + 1;
-    // the wave's list packed four entries to a lane, read by lane index; two
-    // entries per round (one saturation check for both)
-    const uint32_t packed = 4 * l < B ? reinterpret_cast<const uint32_t*>(s_list[w])[l] : 0u;
-    auto entry = [&](uint32_t j) -> int {
-      return (int)((__builtin_amdgcn_readlane(packed, (int)(j >> 2)) >> (8u * (j & 3u))) & 0xffu);
-    };
-    auto blend = [&](int tt, bool present) {
-      const float4 r0 = s_r0[tt], r1 = s_r1[tt], r2 = s_r2[tt];
+  for (uint32_t base = start; base < end; base += 64) {
+    if (!__any(!done)) break;
+    // stage: lane l takes record base + l and keeps it if it reaches this sub-block
+    const uint32_t k = base + (uint32_t)l;
+    bool keep = false;
+    float4 r0, r1, r2;
+    if (k < end) {
+      const float4* rec = slot_rec + (size_t)sorted_slot[k] * 4;
+      r0 = rec[0];
+      r1 = rec[1];
+      r2 = rec[2];
+      const uint32_t xb = __float_as_uint(r1.w), yb = __float_as_uint(r2.w);
+      const int xlo = (int)(int16_t)(xb & 0xffffu), xhi = (int)(int16_t)(xb >> 16);
+      const int ylo = (int)(int16_t)(yb & 0xffffu), yhi = (int)(int16_t)(yb >> 16);
+      if (xlo <= bx + 7 && xhi >= bx && ylo <= by + 7 && yhi >= by) {
+        const float fx0 = (float)(bx - ox) - r0.x, fy0 = (float)(by - oy) - r0.y;
+        keep = footprint_meets_box(fx0, fx0 + 7.0f, fy0, fy0 + 7.0f, r0, r1, P.log2_amin);
+      }
+    }
+    const uint64_t bal = ballot64(keep);
+    if (keep) {
+      const uint32_t q = mask_lt_count(bal);
+      s_r0[w][q] = r0;
+      s_r1[w][q] = r1;
+      s_r2[w][q] = r2;
+      s_pos[w][q] = (int)(k - start) + 1;
+    }
+    __builtin_amdgcn_wave_barrier();
+    const uint32_t len = (uint32_t)__popcll(bal);
+    auto blend = [&](uint32_t q, bool present) {
+      const float4 a0 = s_r0[w][q], a1 = s_r1[w][q], a2 = s_r2[w][q];
       float dy, u;
-      const float e = log2_alpha(fpx, fpy, r0, r1.x, r1.y, dy, u);
+      const float e = log2_alpha(fpx, fpy, a0, a1.x, a1.y, dy, u);
       const bool hit = present && !done && e >= P.log2_amin;
       const float a = hit ? fminf(exp2_approx(e), P.amax) : 0.f;
       const float Tn = T * (1.0f - a);
@@ -161,20 +177,21 @@ __global__ __launch_bounds__(64 * NW) void k_render_fwd(RenderParams P, const ui
       done = done || stop;
       const bool take = hit && !stop;
       const float wgt = take ? a * T : 0.f;
-      c0 = fmaf(wgt, r2.x, c0);
-      c1 = fmaf(wgt, r2.y, c1);
-      c2 = fmaf(wgt, r2.z, c2);
-      D = fmaf(wgt, r1.z, D);
+      c0 = fmaf(wgt, a2.x, c0);
+      c1 = fmaf(wgt, a2.y, c1);
+      c2 = fmaf(wgt, a2.z, c2);
+      D = fmaf(wgt, a1.z, D);
       T = take ? Tn : T;
-      lst = take ? rel0 + tt : lst;
+      lst = take ? s_pos[w][q] : lst;
     };
+    // two entries per round (one saturation check for both)
     for (uint32_t j = 0; j < len; j += 2) {
       if (!__any(!done)) break;
       const bool has_b = j + 1 < len;
-      const int ta = entry(j), tb = entry(has_b ? j + 1 : j);
-      blend(ta, true);
-      blend(tb, has_b);
+      blend(j, true);
+      blend(has_b ? j + 1 : j, has_b);
     }
+    __builtin_amdgcn_wave_barrier();
   }
   if (inside) {
     const size_t npix = (size_t)P.W * P.H;
@@ -615,25 +632,13 @@ kgs_status kgs_launch_render_fwd(kgs_ctx* ctx, const kgs_image* out, hipStream_t
   const unsigned grid = (unsigned)(ctx->last_views * ctx->n_tiles);
   const int s = ctx->sorted_buf;
   (void)s;
-#define KGS_FWD(BB, NWV)                                                                                         \
-  hipLaunchKernelGGL((k_render_fwd<BB, NWV>), dim3(grid), dim3(64 * NWV), 0, st, P, (const uint2*)ctx->ranges,   \
+#define KGS_FWD(NWV)                                                                                             \
+  hipLaunchKernelGGL((k_render_fwd<NWV>), dim3(grid), dim3(64 * NWV), 0, st, P, (const uint2*)ctx->ranges,       \
                      (const uint32_t*)ctx->tile_order,                                                           \
                      (const uint32_t*)ctx->sorted_slot, (const float4*)ctx->slot_rec, out->color, out->depth,      \
                      out->t_final, out->last)
-  if (tile_waves(ctx) == 8) {
-    switch (ctx->cfg.batch) {
-      case 32: KGS_FWD(32, 8); break;
-      case 64: KGS_FWD(64, 8); break;
-      default: KGS_FWD(128, 8); break;
-    }
-  } else {
-    switch (ctx->cfg.batch) {
-      case 32: KGS_FWD(32, 4); break;
-      case 64: KGS_FWD(64, 4); break;
-      case 128: KGS_FWD(128, 4); break;
-      default: KGS_FWD(256, 4); break;
-    }
-  }
+  if (tile_waves(ctx) == 8) KGS_FWD(8);
+  else KGS_FWD(4);
 #undef KGS_FWD
   return kgs_check_launch();
 }
