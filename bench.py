@@ -117,7 +117,7 @@ def main():
     max_s = max_p = 0
     counts = {}
     for tile in TILE_SHAPES:
-        probe.set_tiling(tile, 128)
+        probe.set_tiling(tile, 64)
         probe.project(g, cams)
         probe.bin_sort()
         torch.cuda.synchronize()
@@ -126,14 +126,14 @@ def main():
         counts[tile] = (s, p)
         max_s, max_p = max(max_s, s), max(max_p, p)
     # targets: renders of the unperturbed scene
-    probe.set_tiling((16, 16), 128)
+    probe.set_tiling((16, 16), 64)
     target_img = Image.empty(V, H, W)
     probe.project(gt, cams)
     probe.bin_sort()
     probe.render_fwd(target_img)
     torch.cuda.synchronize()
     target = target_img.color.clone()
-    probe.set_tiling((16, 16), 128)
+    probe.set_tiling((16, 16), 64)
     probe.project(g, cams)
     probe.bin_sort()
     torch.cuda.synchronize()
@@ -161,10 +161,10 @@ def main():
 
     # ---- autotune tile shape x batch
     if args.tile:
-        best = (tuple(int(x) for x in args.tile.split("x")), args.batch or 128)
+        best = (tuple(int(x) for x in args.tile.split("x")), args.batch or 64)
         table = None
     elif args.no_autotune:
-        best, table = ((16, 16), args.batch or 128), None
+        best, table = ((16, 16), args.batch or 64), None
     else:
         d = desc()
         best, table = autotune(lambda: R.chunk_run(d), R.set_tiling, TILE_SHAPES, BATCHES, reps=3)
@@ -232,7 +232,7 @@ def main():
                 "kernel": "k_render_bwd (compositing backward)", "evaluations": E, "blended": E_b,
                 "kernel_ms": round(stage_ms["render_bwd_pixels"], 4)}
 
-    # ---- plain per-view loop (same library, 16x16 tiles, batch 128, no graph)
+    # ---- plain per-view loop (same library, 16x16 tiles, batch 64, no graph)
     plain_ms = None
     identical = None
     if not args.no_plain:

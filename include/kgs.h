@@ -98,8 +98,9 @@ typedef struct kgs_camera {
 typedef struct kgs_config {
   int32_t tile_w, tile_h;   /* 16x16, 8x32, 32x8 (four waves per compositing workgroup)
                                or 32x16, 16x32 (eight waves) */
-  int32_t batch;            /* Gaussians staged per LDS batch: 32, 64, 128 or 256
-                               (at most 128 with 512-pixel tiles) */
+  int32_t batch;            /* Gaussians staged per LDS batch of the backward: 32, 64
+                               or 128 (at most 64 with 512-pixel tiles); the forward
+                               stages 64 at a time in every wave */
   int32_t sh_degree;        /* 0..3 */
   float alpha_min, alpha_max, t_min, near_z, eps2d, guard, rect_margin, far_z;
   float bg[3];

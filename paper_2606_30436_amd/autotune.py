@@ -39,8 +39,8 @@ def autotune(run: Callable[[], None], set_tiling: Callable, tiles: Iterable, bat
     best, best_ms = None, float("inf")
     for tile in tiles:
         for b in batches:
-            if tile[0] * tile[1] == 512 and b > 128:
-                continue  # not a valid tiling (at most 128 records per stage with 512-pixel tiles)
+            if tile[0] * tile[1] == 512 and b > 64:
+                continue  # not a valid tiling (at most 64 records per stage with 512-pixel tiles)
             set_tiling(tuple(tile), int(b))
             for _ in range(warmup):
                 run()

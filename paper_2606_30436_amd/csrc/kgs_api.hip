@@ -36,9 +36,9 @@ bool tile_ok(int w, int h) {
   return (w == 16 && h == 16) || (w == 8 && h == 32) || (w == 32 && h == 8) || (w == 32 && h == 16) ||
          (w == 16 && h == 32);
 }
-// 512-pixel tiles (eight waves per workgroup) stage at most 128 records at a time
-bool tiling_ok(int w, int h, int batch) { return tile_ok(w, h) && !(w * h == 512 && batch > 128); }
-bool batch_ok(int b) { return b == 32 || b == 64 || b == 128 || b == 256; }
+// 512-pixel tiles (eight waves per workgroup) stage at most 64 records at a time
+bool tiling_ok(int w, int h, int batch) { return tile_ok(w, h) && !(w * h == 512 && batch > 64); }
+bool batch_ok(int b) { return b == 32 || b == 64 || b == 128; }
 
 int tiles_for(int W, int H, int tw, int th) { return ((W + tw - 1) / tw) * ((H + th - 1) / th); }
 

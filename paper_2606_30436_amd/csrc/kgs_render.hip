@@ -50,63 +50,6 @@ __device__ __forceinline__ bool footprint_meets_box(float x0, float x1, float y0
   return f <= tau + 1e-3f * (1.0f + tau);
 }
 
-// Stage B pairs of [base, end) into LDS and build the per-wave lists: a wave's
-// list holds the pairs whose pixel rectangle meets its 8x8 sub-block and whose
-// footprint reaches the sub-block's pixel centres.
-template <int B, int NW, bool FIRST_PAIR>
-__device__ __forceinline__ void stage_batch(uint32_t base, uint32_t end, const uint32_t* __restrict__ sorted_slot,
-                                            const float4* __restrict__ slot_rec, int tile_x0, int tile_y0,
-                                            int tile_w, int ox, int oy, float log2_amin, float4* s_r0,
-                                            float4* s_r1, float4* s_r2, uint32_t* s_first, uint8_t* s_mask,
-                                            uint8_t (*s_list)[B], uint32_t (*s_cnt)[NW]) {
-  const int tid = threadIdx.x, w = tid >> 6;
-  uint32_t m = 0;
-  if (tid < B) {
-    const uint32_t k = base + tid;
-    if (k < end) {
-      const uint32_t s = sorted_slot[k];
-      const float4* rec = slot_rec + (size_t)s * 4;
-      const float4 r0 = rec[0], r1 = rec[1], r2 = rec[2];
-      if (FIRST_PAIR) s_first[tid] = __float_as_uint(rec[3].x);
-      s_r0[tid] = r0;
-      s_r1[tid] = r1;
-      s_r2[tid] = r2;
-      const uint32_t xb = __float_as_uint(r1.w), yb = __float_as_uint(r2.w);
-      const int xlo = (int)(int16_t)(xb & 0xffffu), xhi = (int)(int16_t)(xb >> 16);
-      const int ylo = (int)(int16_t)(yb & 0xffffu), yhi = (int)(int16_t)(yb >> 16);
-#pragma unroll
-      for (int ww = 0; ww < NW; ++ww) {
-        int sx, sy;
-        tile_subblock(tile_w, ww, sx, sy);
-        const int bx = tile_x0 + sx, by = tile_y0 + sy;
-        if (xlo <= bx + 7 && xhi >= bx && ylo <= by + 7 && yhi >= by) {
-          const float fx0 = (float)(bx - ox) - r0.x, fy0 = (float)(by - oy) - r0.y;
-          if (footprint_meets_box(fx0, fx0 + 7.0f, fy0, fy0 + 7.0f, r0, r1, log2_amin)) m |= 1u << ww;
-        }
-      }
-    }
-    s_mask[tid] = (uint8_t)m;
-  }
-#pragma unroll
-  for (int ww = 0; ww < NW; ++ww) {
-    const uint64_t bal = ballot64((m >> ww) & 1u);
-    if ((tid & 63) == 0) s_cnt[w][ww] = (uint32_t)__popcll(bal);
-  }
-  __syncthreads();
-  if (tid < B) {
-#pragma unroll
-    for (int ww = 0; ww < NW; ++ww) {
-      const uint64_t bal = ballot64((m >> ww) & 1u);
-      if ((m >> ww) & 1u) {
-        uint32_t pos = mask_lt_count(bal);
-        for (int k = 0; k < w; ++k) pos += s_cnt[k][ww];
-        s_list[ww][pos] = (uint8_t)tid;
-      }
-    }
-  }
-  __syncthreads();
-}
-
 // Forward: every wave stages the tile's records itself, 64 at a time (one per
 // lane), keeps those that reach its sub-block (rectangle, then the exact
 // footprint test) compacted in its own LDS rows, and composites them; no
@@ -418,11 +361,13 @@ __global__ __launch_bounds__(64 * NW) void k_render_bwd(
     const float* __restrict__ dl_dcolor, const float* __restrict__ dl_ddepth, const float* __restrict__ dl_dalpha,
     const float* __restrict__ target, float tau_err, float4* __restrict__ pair_grad, int fuse_l1,
     float* __restrict__ dl_out, double* __restrict__ loss_partial) {
-  __shared__ float4 s_r0[B], s_r1[B], s_r2[B];
-  __shared__ uint32_t s_first[B];
-  __shared__ __align__(16) uint8_t s_list[NW][B];
-  __shared__ uint8_t s_mask[B];
-  __shared__ uint32_t s_cnt[NW][NW];
+  // B records per batch, R = B / 64 per lane (B = 32: the first half of the lanes)
+  constexpr int R = B >= 64 ? B / 64 : 1;
+  static_assert(B == 32 || B == 64 || B == 128, "batch of 32, 64 or 128 records");
+  // each wave's kept records of the batch, compacted, and their batch indices
+  __shared__ float4 s_r0[NW][B], s_r1[NW][B], s_r2[NW][B];
+  __shared__ __align__(16) uint8_t s_id[NW][B];
+  __shared__ uint64_t s_keep[NW][R];
   __shared__ float s_part[NW][B][12];
   __shared__ int s_wmax[NW];
   __shared__ float s_loss[NW];
@@ -433,9 +378,11 @@ __global__ __launch_bounds__(64 * NW) void k_render_bwd(
   const int tile_x0 = tx * P.tile_w, tile_y0 = ty * P.tile_h;
   int sx, sy;
   tile_subblock(P.tile_w, w, sx, sy);
-  const int px = tile_x0 + sx + (l & 7), py = tile_y0 + sy + (l >> 3);
+  const int bx = tile_x0 + sx, by = tile_y0 + sy;
+  const int px = bx + (l & 7), py = by + (l >> 3);
   const bool inside = px < P.W && py < P.H;
-  const float fpx = (float)(px - pix_origin(P.W)), fpy = (float)(py - pix_origin(P.H));
+  const int ox = pix_origin(P.W), oy = pix_origin(P.H);
+  const float fpx = (float)(px - ox), fpy = (float)(py - oy);
   const uint2 rg = ranges[gt];
   const uint32_t start = rg.x, end = rg.y;
   // per-pixel inputs
@@ -493,32 +440,67 @@ __global__ __launch_bounds__(64 * NW) void k_render_bwd(
   float Rj = gAT - (g0 * Co0 + g1 * Co1 + g2 * Co2 + gD * Do);
   uint32_t base = start;
   for (; base < pend; base += B) {
-    __syncthreads();
-    stage_batch<B, NW, true>(base, end, sorted_slot, slot_rec, tile_x0, tile_y0, P.tile_w, pix_origin(P.W), pix_origin(P.H),
-                   P.log2_amin, s_r0, s_r1, s_r2, s_first, s_mask,
-                   s_list, s_cnt);
+    // stage: every wave reads the batch's records (lane l: records l, l + 64,
+    // ...) and keeps, compacted in order, those that reach its sub-block; the
+    // first wave also keeps what the pair records need
     uint32_t len = 0;
+    float xbw[R], ybw[R];
+    uint32_t firstp[R];
 #pragma unroll
-    for (int k = 0; k < NW; ++k) len += s_cnt[k][w];
-    len = __builtin_amdgcn_readfirstlane(len);
+    for (int r = 0; r < R; ++r) {
+      const int bi = r * 64 + l;
+      const uint32_t k = base + (uint32_t)bi;
+      bool keep = false;
+      float4 r0, r1, r2;
+      xbw[r] = 0.f;
+      ybw[r] = 0.f;
+      firstp[r] = 0u;
+      if (bi < B && k < end) {
+        const float4* rec = slot_rec + (size_t)sorted_slot[k] * 4;
+        r0 = rec[0];
+        r1 = rec[1];
+        r2 = rec[2];
+        if (w == 0) firstp[r] = __float_as_uint(rec[3].x);
+        xbw[r] = r1.w;
+        ybw[r] = r2.w;
+        const uint32_t xb = __float_as_uint(r1.w), yb = __float_as_uint(r2.w);
+        const int xlo = (int)(int16_t)(xb & 0xffffu), xhi = (int)(int16_t)(xb >> 16);
+        const int ylo = (int)(int16_t)(yb & 0xffffu), yhi = (int)(int16_t)(yb >> 16);
+        if (xlo <= bx + 7 && xhi >= bx && ylo <= by + 7 && yhi >= by) {
+          const float fx0 = (float)(bx - ox) - r0.x, fy0 = (float)(by - oy) - r0.y;
+          keep = footprint_meets_box(fx0, fx0 + 7.0f, fy0, fy0 + 7.0f, r0, r1, P.log2_amin);
+        }
+      }
+      const uint64_t bal = ballot64(keep);
+      if (keep) {
+        const uint32_t q = len + mask_lt_count(bal);
+        s_r0[w][q] = r0;
+        s_r1[w][q] = r1;
+        s_r2[w][q] = r2;
+        s_id[w][q] = (uint8_t)bi;
+      }
+      if (l == 0) s_keep[w][r] = bal;
+      len += (uint32_t)__popcll(bal);
+    }
+    __builtin_amdgcn_wave_barrier();
     const int rel0 = (int)(base - start);
-    // list entries two at a time: a pair of entries that both blend shares one
-    // reduction of twenty values; otherwise the one that blends is reduced alone
-    // the wave's list in one register: lane i holds entries 4i .. 4i + 3 (one
-    // byte each), read back by lane index
-    static_assert(B <= 256 && B % 4 == 0, "list entries must pack four to a lane");
-    const uint32_t packed = 4 * l < B ? reinterpret_cast<const uint32_t*>(s_list[w])[l] : 0u;
+    // the wave's list entries (batch indices), four to a lane, read by lane
+    // index; the records of entry j sit at position j of the wave's rows
+    const uint32_t packed = 4 * l < B ? reinterpret_cast<const uint32_t*>(s_id[w])[l] : 0u;
     auto entry = [&](uint32_t j) -> int {
       return (int)((__builtin_amdgcn_readlane(packed, (int)(j >> 2)) >> (8u * (j & 3u))) & 0xffu);
     };
+    // list entries two at a time: a pair of entries that both blend shares one
+    // reduction of twenty values; otherwise the one that blends is reduced alone
     for (uint32_t j = 0; j < len;) {
-      const int ta = entry(j);  // same entry for the whole wave
+      const int ta = entry(j);  // batch index, the same for the whole wave
       if (rel0 + ta >= wmax) break;
       const bool has_b = j + 1 < len;
-      const int tb = entry(has_b ? j + 1 : j);
+      const uint32_t jb = has_b ? j + 1 : j;
+      const int tb = entry(jb);
       const bool use_b = has_b && rel0 + tb < wmax;
       // both entries' records at once (the second is a repeat of the first when absent)
-      const float4 ra0 = s_r0[ta], ra1 = s_r1[ta], rb0 = s_r0[tb], rb1 = s_r1[tb];
+      const float4 ra0 = s_r0[w][j], ra1 = s_r1[w][j], rb0 = s_r0[w][jb], rb1 = s_r1[w][jb];
       float dya, ua, dyb, ub;
       const float ea = log2_alpha(fpx, fpy, ra0, ra1.x, ra1.y, dya, ua);
       const float eb = log2_alpha(fpx, fpy, rb0, rb1.x, rb1.y, dyb, ub);
@@ -527,7 +509,7 @@ __global__ __launch_bounds__(64 * NW) void k_render_bwd(
       const uint64_t bba = ballot64(bla), bbb = ballot64(blb);
       if (bba != 0ull && bbb != 0ull) {
         float x[20];
-        const float4 ra2 = s_r2[ta], rb2 = s_r2[tb];
+        const float4 ra2 = s_r2[w][j], rb2 = s_r2[w][jb];
         blend_terms(ea, ua, dya, bla, ra1, ra2, P.amax, g0, g1, g2, gD, T, Rj, x);
         blend_terms(eb, ub, dyb, blb, rb1, rb2, P.amax, g0, g1, g2, gD, T, Rj, x + 10);
         const uint64_t bma = ballot64(bla && M), bmb = ballot64(blb && M);
@@ -546,8 +528,8 @@ __global__ __launch_bounds__(64 * NW) void k_render_bwd(
         const int tt = first ? ta : tb, tz = first ? tb : ta;
         const bool bl = first ? bla : blb;
         float x[10];
-        blend_terms(first ? ea : eb, first ? ua : ub, first ? dya : dyb, bl, first ? ra1 : rb1, s_r2[tt], P.amax,
-                    g0, g1, g2, gD, T, Rj, x);
+        blend_terms(first ? ea : eb, first ? ua : ub, first ? dya : dyb, bl, first ? ra1 : rb1,
+                    s_r2[w][first ? j : jb], P.amax, g0, g1, g2, gD, T, Rj, x);
         const uint64_t bm = ballot64(bl && M);
         int idx;
         bool valid;
@@ -567,30 +549,36 @@ __global__ __launch_bounds__(64 * NW) void k_render_bwd(
       j += use_b ? 2u : 1u;
     }
     __syncthreads();
-    if (tid < B) {
-      const uint32_t k = base + tid;
-      if (k < end) {
-        const int krel = (int)(k - start);
-        const uint32_t m = s_mask[tid];
-        float o[10];
-        uint32_t c0 = 0u, c1 = 0u;
+    // the first wave sums the waves' partials of every pair in wave order and
+    // writes the pair's record
+    if (w == 0) {
 #pragma unroll
-        for (int q = 0; q < 10; ++q) o[q] = 0.f;
+      for (int r = 0; r < R; ++r) {
+        const int bi = r * 64 + l;
+        const uint32_t k = base + (uint32_t)bi;
+        if (bi < B && k < end) {
+          const int krel = (int)(k - start);
+          float o[10];
+          uint32_t c0 = 0u, c1 = 0u;
 #pragma unroll
-        for (int ww = 0; ww < NW; ++ww) {
-          if (((m >> ww) & 1u) && krel < s_wmax[ww]) {
+          for (int q = 0; q < 10; ++q) o[q] = 0.f;
 #pragma unroll
-            for (int q = 0; q < 10; ++q) o[q] += s_part[ww][tid][q];
-            c0 += __float_as_uint(s_part[ww][tid][10]);
-            c1 += __float_as_uint(s_part[ww][tid][11]);
+          for (int ww = 0; ww < NW; ++ww) {
+            if (((s_keep[ww][r] >> l) & 1ull) && krel < s_wmax[ww]) {
+#pragma unroll
+              for (int q = 0; q < 10; ++q) o[q] += s_part[ww][bi][q];
+              c0 += __float_as_uint(s_part[ww][bi][10]);
+              c1 += __float_as_uint(s_part[ww][bi][11]);
+            }
           }
+          const size_t p = (size_t)pair_position(firstp[r], xbw[r], ybw[r], tx, ty, P) * 3;
+          pair_grad[p] = make_float4(o[0], o[1], o[2], o[3]);
+          pair_grad[p + 1] = make_float4(o[4], o[5], o[6], o[7]);
+          pair_grad[p + 2] = make_float4(o[8], o[9], __uint_as_float(c0), __uint_as_float(c1));
         }
-        const size_t p = (size_t)pair_position(s_first[tid], s_r1[tid].w, s_r2[tid].w, tx, ty, P) * 3;
-        pair_grad[p] = make_float4(o[0], o[1], o[2], o[3]);
-        pair_grad[p + 1] = make_float4(o[4], o[5], o[6], o[7]);
-        pair_grad[p + 2] = make_float4(o[8], o[9], __uint_as_float(c0), __uint_as_float(c1));
       }
     }
+    __syncthreads();
   }
   // pairs behind the tile's last blended Gaussian contribute nothing
   for (uint32_t k = base + tid; k < end; k += 64 * NW) {
@@ -686,15 +674,13 @@ kgs_status kgs_launch_render_bwd(kgs_ctx* ctx, const kgs_image* fwd, const float
   if (tile_waves(ctx) == 8) {
     switch (ctx->cfg.batch) {
       case 32: KGS_BWD(32, 8); break;
-      case 64: KGS_BWD(64, 8); break;
-      default: KGS_BWD(128, 8); break;
+      default: KGS_BWD(64, 8); break;
     }
   } else {
     switch (ctx->cfg.batch) {
       case 32: KGS_BWD(32, 4); break;
       case 64: KGS_BWD(64, 4); break;
-      case 128: KGS_BWD(128, 4); break;
-      default: KGS_BWD(256, 4); break;
+      default: KGS_BWD(128, 4); break;
     }
   }
 #undef KGS_BWD

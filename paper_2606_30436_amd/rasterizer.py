@@ -14,12 +14,12 @@ from . import _lib as L
 from .scenes import CAMERA_DTYPE
 
 TILE_SHAPES = ((16, 16), (8, 32), (32, 8), (32, 16), (16, 32))
-BATCHES = (32, 64, 128, 256)
+BATCHES = (32, 64, 128)
 
 
 def tiling_valid(tile, batch) -> bool:
-    """The library's rule: 512-pixel tiles stage at most 128 records at a time."""
-    return tuple(tile) in TILE_SHAPES and batch in BATCHES and not (tile[0] * tile[1] == 512 and batch > 128)
+    """The library's rule: 512-pixel tiles stage at most 64 records at a time."""
+    return tuple(tile) in TILE_SHAPES and batch in BATCHES and not (tile[0] * tile[1] == 512 and batch > 64)
 
 
 @dataclasses.dataclass
@@ -134,7 +134,7 @@ class Rasterizer:
     """One libkgs context and its workspace."""
 
     def __init__(self, width: int, height: int, max_views: int, max_gaussians: int, slot_capacity: int = 0,
-                 pair_capacity: int = 0, tile=(16, 16), batch: int = 128, device="cuda", **overrides):
+                 pair_capacity: int = 0, tile=(16, 16), batch: int = 64, device="cuda", **overrides):
         cfg = L.kgs_config_default(width, height)
         cfg.tile_w, cfg.tile_h = tile
         cfg.batch = batch

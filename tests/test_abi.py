@@ -66,7 +66,7 @@ def _cfg(**kw):
     return c
 
 
-@pytest.mark.parametrize("bad", [dict(tile_w=12), dict(batch=100), dict(tile_w=32, tile_h=16, batch=256),
+@pytest.mark.parametrize("bad", [dict(tile_w=12), dict(batch=100), dict(tile_w=32, tile_h=16, batch=128), dict(batch=256),
                                  dict(sh_degree=4), dict(max_views=0),
                                  dict(max_views=65), dict(width=0), dict(pair_capacity=2 ** 32), dict(alpha_min=0.0)])
 def test_invalid_configs_are_rejected(bad):
@@ -101,8 +101,8 @@ def test_host_argument_checks_and_call_order():
         assert lib.kgs_project(ctx, ctypes.byref(g), ctypes.c_void_p(8), 1, None, None) == L.KGS_ERR_INVALID_ARG
         assert lib.kgs_set_tiling(ctx, 8, 32, 64) == L.KGS_OK
         assert lib.kgs_set_tiling(ctx, 8, 8, 64) == L.KGS_ERR_INVALID_ARG
-        assert lib.kgs_set_tiling(ctx, 32, 16, 128) == L.KGS_OK
-        assert lib.kgs_set_tiling(ctx, 16, 32, 256) == L.KGS_ERR_INVALID_ARG
+        assert lib.kgs_set_tiling(ctx, 32, 16, 64) == L.KGS_OK
+        assert lib.kgs_set_tiling(ctx, 16, 32, 128) == L.KGS_ERR_INVALID_ARG
         assert lib.kgs_chunk_launch(None, None) == L.KGS_ERR_INVALID_ARG
         assert lib.kgs_status_string(3) == b"device capacity exceeded"
     finally:

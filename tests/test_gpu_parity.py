@@ -34,7 +34,7 @@ def _scene(name):
     raise KeyError(name)
 
 
-def _rast(sc, tile=(16, 16), batch=128, **kw):
+def _rast(sc, tile=(16, 16), batch=64, **kw):
     return Rasterizer(sc.width, sc.height, max_views=sc.n_views, max_gaussians=sc.n, tile=tile, batch=batch, **kw)
 
 
@@ -230,7 +230,7 @@ def test_tile_shapes_and_batches_give_identical_images():
     say("[gpu] tile invariance")
     ref = None
     for tile in ((16, 16), (8, 32), (32, 8), (32, 16), (16, 32)):
-        for batch in (32, 128 if tile[0] * tile[1] == 512 else 256):
+        for batch in (32, 64 if tile[0] * tile[1] == 512 else 128):
             R = _rast(sc, tile=tile, batch=batch)
             _, _, _, img = run_forward(R, sc)
             c = img.color.cpu().numpy()
@@ -254,8 +254,8 @@ def test_tile_shapes_and_batches_give_the_same_gradients():
     dLdD = torch.from_numpy((rng.normal(size=(V, H, W)) * 0.05).astype(np.float32)).cuda()
     ref = None
     for tile in ((16, 16), (8, 32), (32, 8), (32, 16), (16, 32)):
-        for batch in (32, 64, 128, 256):
-            if tile[0] * tile[1] == 512 and batch > 128:
+        for batch in (32, 64, 128):
+            if tile[0] * tile[1] == 512 and batch > 64:
                 continue
             R = _rast(sc, tile=tile, batch=batch)
             g, cams, xi, img = run_forward(R, sc)
