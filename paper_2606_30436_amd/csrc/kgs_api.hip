@@ -84,6 +84,7 @@ size_t layout(const kgs_config& c, char* base, kgs_ctx* ctx) {
   p = take(8 * V * T);                          if (ctx) ctx->ranges = (uint2*)p;
   p = take(4 * V * T);                          if (ctx) ctx->tile_order = (uint32_t*)p;
   p = take(48 * P);                             if (ctx) ctx->pair_grad = (float4*)p;
+  p = take(P + 16);                             if (ctx) ctx->pair_live = (uint8_t*)p;
   p = take(4 * 256 * KGS_SORT_BLOCKS);          if (ctx) ctx->radix_hist = (uint32_t*)p;
   p = take(4 * 256 * KGS_MAX_PASSES);           if (ctx) ctx->radix_total = (uint32_t*)p;
   p = take(4 * KGS_SLOT_WORDS * S);             if (ctx) ctx->slot_bwd = (float4*)p;

@@ -67,6 +67,7 @@ struct kgs_ctx {
   uint2* ranges;                      // [max_views * max_tiles]
   uint32_t* tile_order;               // [max_views * max_tiles] compositing launch order, heaviest first
   float4* pair_grad;                  // [P][3] per-pair record-space gradients + counts
+  uint8_t* pair_live;                 // [P] 1 where the compositing backward wrote the pair's record
   uint32_t* radix_hist;               // [256][KGS_SORT_BLOCKS] digit counts, then offsets, per partition
   uint32_t* radix_total;              // [KGS_MAX_PASSES][256]
   float4* slot_bwd;                   // [S][KGS_SLOT_WORDS / 4] per-slot backward records

@@ -85,11 +85,13 @@ struct SegWindow {
 };
 
 __device__ __forceinline__ void seg_load(SegWindow& W, uint32_t w, uint32_t np, int l,
-                                         const uint32_t* __restrict__ pair_slot, const float4* __restrict__ pair_grad) {
+                                         const uint32_t* __restrict__ pair_slot, const float4* __restrict__ pair_grad,
+                                         const uint8_t* __restrict__ pair_live) {
   const uint32_t p = w * 64 + (uint32_t)l;
   const bool valid = p < np;
   W.s = valid ? pair_slot[p] : SEG_NONE;
-  if (valid) {
+  // a pair the compositing backward did not reach adds nothing (its record is not written)
+  if (valid && pair_live[p] != 0u) {
     const float4 a = pair_grad[(size_t)p * 3], b = pair_grad[(size_t)p * 3 + 1], c = pair_grad[(size_t)p * 3 + 2];
     W.x[0] = a.x; W.x[1] = a.y; W.x[2] = a.z; W.x[3] = a.w;
     W.x[4] = b.x; W.x[5] = b.y; W.x[6] = b.z; W.x[7] = b.w;
@@ -143,6 +145,7 @@ __device__ __forceinline__ void seg_window(SegWindow& W, uint32_t w, uint32_t np
 __global__ __launch_bounds__(256) void k_pair_segsum(const uint32_t* __restrict__ counters,
                                                      const uint32_t* __restrict__ pair_slot,
                                                      const float4* __restrict__ pair_grad,
+                                                     const uint8_t* __restrict__ pair_live,
                                                      float4* __restrict__ slot_sum, float4* __restrict__ seg_head,
                                                      float4* __restrict__ seg_tail) {
   const uint32_t np = counters[1];
@@ -152,8 +155,8 @@ __global__ __launch_bounds__(256) void k_pair_segsum(const uint32_t* __restrict_
   for (uint32_t w0 = blockIdx.x * 4 + (threadIdx.x >> 6); w0 < nwin; w0 += 2 * stride) {
     const uint32_t w1 = w0 + stride;
     SegWindow A, B;
-    seg_load(A, w0, np, l, pair_slot, pair_grad);
-    if (w1 < nwin) seg_load(B, w1, np, l, pair_slot, pair_grad);
+    seg_load(A, w0, np, l, pair_slot, pair_grad, pair_live);
+    if (w1 < nwin) seg_load(B, w1, np, l, pair_slot, pair_grad, pair_live);
     seg_window(A, w0, np, l, slot_sum, seg_head, seg_tail);
     if (w1 < nwin) seg_window(B, w1, np, l, slot_sum, seg_head, seg_tail);
   }
@@ -610,7 +613,8 @@ kgs_status kgs_launch_project_bwd(kgs_ctx* ctx, const kgs_gaussians* g, const kg
     const uint64_t wins = ((uint64_t)cfg.pair_capacity + 63) / 64;
     const unsigned wg = (unsigned)std::min<uint64_t>(std::max<uint64_t>((wins + 7) / 8, 1), 4096);
     hipLaunchKernelGGL(k_pair_segsum, dim3(wg), dim3(256), 0, st, (const uint32_t*)ctx->counters,
-                       (const uint32_t*)ctx->pair_slot, (const float4*)ctx->pair_grad, ctx->slot_bwd, ctx->seg_head,
+                       (const uint32_t*)ctx->pair_slot, (const float4*)ctx->pair_grad,
+                       (const uint8_t*)ctx->pair_live, ctx->slot_bwd, ctx->seg_head,
                        ctx->seg_tail);
     hipLaunchKernelGGL(k_pair_fixup, dim3((unsigned)std::min<uint64_t>(std::max<uint64_t>((wins + 255) / 256, 1), 2048)),
                        dim3(256), 0, st, (const uint32_t*)ctx->counters, (const float4*)ctx->seg_head,

@@ -359,7 +359,8 @@ __global__ __launch_bounds__(64 * NW) void k_render_bwd(
     const float4* __restrict__ slot_rec, const float* __restrict__ color,
     const float* __restrict__ depth, const float* __restrict__ tfinal, const int32_t* __restrict__ last,
     const float* __restrict__ dl_dcolor, const float* __restrict__ dl_ddepth, const float* __restrict__ dl_dalpha,
-    const float* __restrict__ target, float tau_err, float4* __restrict__ pair_grad, int fuse_l1,
+    const float* __restrict__ target, float tau_err, float4* __restrict__ pair_grad,
+    uint8_t* __restrict__ pair_live, int fuse_l1,
     float* __restrict__ dl_out, double* __restrict__ loss_partial) {
   // B records per batch, R = B / 64 per lane (B = 32: the first half of the lanes)
   constexpr int R = B >= 64 ? B / 64 : 1;
@@ -571,26 +572,19 @@ __global__ __launch_bounds__(64 * NW) void k_render_bwd(
               c1 += __float_as_uint(s_part[ww][bi][11]);
             }
           }
-          const size_t p = (size_t)pair_position(firstp[r], xbw[r], ybw[r], tx, ty, P) * 3;
+          const uint32_t pe = pair_position(firstp[r], xbw[r], ybw[r], tx, ty, P);
+          const size_t p = (size_t)pe * 3;
           pair_grad[p] = make_float4(o[0], o[1], o[2], o[3]);
           pair_grad[p + 1] = make_float4(o[4], o[5], o[6], o[7]);
           pair_grad[p + 2] = make_float4(o[8], o[9], __uint_as_float(c0), __uint_as_float(c1));
+          pair_live[pe] = 1u;
         }
       }
     }
     __syncthreads();
   }
-  // pairs behind the tile's last blended Gaussian contribute nothing
-  for (uint32_t k = base + tid; k < end; k += 64 * NW) {
-    const uint32_t s = sorted_slot[k];
-    const float4* rec = slot_rec + (size_t)s * 4;
-    const size_t p = (size_t)pair_position(__float_as_uint(rec[3].x), rec[1].w, rec[2].w,
-                                           tx, ty, P) * 3;
-    const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
-    pair_grad[p] = z;
-    pair_grad[p + 1] = z;
-    pair_grad[p + 2] = z;
-  }
+  // pairs behind the tile's last batch are left unwritten: every pixel of the
+  // tile has stopped before them, and their live flags stay clear
 }
 
 // ---------------------------------------------------------------- host side
@@ -655,6 +649,13 @@ void kgs_launch_loss_final(kgs_ctx* ctx, float* view_loss, hipStream_t st) {
                        view_loss);
 }
 
+// Clears the pairs' live flags (the pair count is read on the device) before
+// the compositing backward sets those of the pairs it writes.
+__global__ __launch_bounds__(256) void k_clear_live(const uint32_t* __restrict__ counters, uint4* __restrict__ live) {
+  const uint32_t n = (counters[1] + 15u) / 16u;
+  for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) live[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
 // fuse_l1: the colour gradient is the L1 loss gradient against target, formed
 // here (and written to dl_dcolor if it is not null) together with the loss
 // partials; kgs_launch_loss_final then gives the per-view losses.
@@ -663,6 +664,9 @@ kgs_status kgs_launch_render_bwd(kgs_ctx* ctx, const kgs_image* fwd, const float
                                  bool fuse_l1, float* dl_out) {
   const RenderParams P = render_params(ctx);
   const unsigned grid = (unsigned)(ctx->last_views * ctx->n_tiles);
+  const uint64_t lw = ((uint64_t)ctx->cfg.pair_capacity + 15) / 16;
+  hipLaunchKernelGGL(k_clear_live, dim3((unsigned)std::min<uint64_t>(std::max<uint64_t>((lw + 255) / 256, 1), 1024)),
+                     dim3(256), 0, st, (const uint32_t*)ctx->counters, (uint4*)ctx->pair_live);
 #define KGS_BWD(BB, NWV)                                                                                         \
   hipLaunchKernelGGL((k_render_bwd<BB, NWV>), dim3(grid), dim3(64 * NWV), 0, st, P, (const uint2*)ctx->ranges,   \
                      (const uint32_t*)ctx->tile_order,                                                           \
@@ -670,7 +674,7 @@ kgs_status kgs_launch_render_bwd(kgs_ctx* ctx, const kgs_image* fwd, const float
                      (const float4*)ctx->slot_rec,                                                                \
                      (const float*)fwd->color, (const float*)fwd->depth, (const float*)fwd->t_final,              \
                      (const int32_t*)fwd->last, dl_dcolor, dl_ddepth, dl_dalpha, target, tau_err, ctx->pair_grad,  \
-                     fuse_l1 ? 1 : 0, dl_out, ctx->loss_partial)
+                     ctx->pair_live, fuse_l1 ? 1 : 0, dl_out, ctx->loss_partial)
   if (tile_waves(ctx) == 8) {
     switch (ctx->cfg.batch) {
       case 32: KGS_BWD(32, 8); break;
