@@ -419,15 +419,31 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_slot_bwd(kgs_gaussians g, const C
                                                         const uint32_t* __restrict__ slot_gid,
                                                         const uint32_t* __restrict__ slot_view,
                                                         const uint32_t* __restrict__ slot_ntiles,
+                                                        const int4* __restrict__ slot_pix,
                                                         float4* __restrict__ slot_bwd,
                                                         float2* __restrict__ slot_pose) {
   const uint32_t n_slots = counters[0];
   for (uint32_t s = blockIdx.x * KGS_BLOCK + threadIdx.x; s < n_slots; s += gridDim.x * KGS_BLOCK) {
-    const float4* q = slot_bwd + (size_t)s * (KGS_SLOT_WORDS / 4);
+    float4* q = slot_bwd + (size_t)s * (KGS_SLOT_WORDS / 4);
     // a slot without pairs has no segment and so no sum written
     const bool any = slot_ntiles[s] != 0u;
     const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
     const float4 a = any ? q[0] : z, b = any ? q[1] : z, c = any ? q[2] : z;
+    if (__float_as_uint(c.z) == 0u) {
+      // no pixel blended the slot: every pixel term of its sum is a zero
+      // (alpha = 0), so are its gradients and pose terms, and what remains is
+      // the radius statistic, the one the projection stored
+      const int4 pix = slot_pix[s];
+      const int rad = any ? max(pix.z, pix.w) : 0;
+#pragma unroll
+      for (int k = 0; k < KGS_SLOT_WORDS / 4; ++k) q[k] = z;
+      q[5].x = __int_as_float(rad);
+      float2* p2 = slot_pose + (size_t)s * 3;
+      p2[0] = make_float2(0.f, 0.f);
+      p2[1] = make_float2(0.f, 0.f);
+      p2[2] = make_float2(0.f, 0.f);
+      continue;
+    }
     const float r[10] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x, c.y};
     slot_record<DEG>(s, g, cams, P, slot_gid, slot_view, slot_ntiles, r, __float_as_uint(c.z),
                      __float_as_uint(c.w), slot_bwd, slot_pose);
@@ -622,8 +638,8 @@ kgs_status kgs_launch_project_bwd(kgs_ctx* ctx, const kgs_gaussians* g, const kg
 #define KGS_PB(D)                                                                                                  \
   hipLaunchKernelGGL(k_slot_bwd<D>, dim3(sg), dim3(KGS_BLOCK), 0, st, *g, (const CamDev*)ctx->cams, P,             \
                      (const uint32_t*)ctx->counters, (const uint32_t*)ctx->slot_gid,                                \
-                     (const uint32_t*)ctx->slot_view, (const uint32_t*)ctx->slot_ntiles, ctx->slot_bwd,            \
-                     ctx->slot_pose);                                                                             \
+                     (const uint32_t*)ctx->slot_view, (const uint32_t*)ctx->slot_ntiles,                          \
+                     (const int4*)ctx->slot_pix, ctx->slot_bwd, ctx->slot_pose);                                                                             \
   hipLaunchKernelGGL(k_gauss_gather<D>, dim3((unsigned)nb), dim3(KGS_BLOCK), 0, st, *g, V,                        \
                      (const CamDev*)ctx->cams, (const uint32_t*)ctx->vis, (const uint32_t*)ctx->counters,          \
                      (const float4*)ctx->slot_bwd,                                                                \
