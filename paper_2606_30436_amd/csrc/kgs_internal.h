@@ -11,6 +11,7 @@
 
 #define KGS_BLOCK 256                 // threads per block for per-Gaussian / per-tile kernels
 #define KGS_MAX_VIEWS 64
+#define KGS_CNT_LIVE 4                  // counters[] word of the live-slot count
 #define KGS_SORT_BLOCKS 1024          // fixed grid (one partition per block) of the radix sort passes
 #define KGS_MAX_PASSES 8
 #define KGS_POSE_BLOCKS 32            // pieces per view of the pose reduction
@@ -51,7 +52,7 @@ struct kgs_ctx {
   uint32_t* vis;                      // [V][N] tile count after counting; slot index + 1 (0: none) after emission
   uint32_t* blk_cnt;                  // [max_views][nb][2] visible count, tile count
   uint32_t* blk_base;                 // [max_views][nb][2] exclusive bases
-  uint32_t* counters;                 // [64]: 0 n_slots, 1 n_pairs, 2 status, 3.. scratch
+  uint32_t* counters;                 // [64]: 0 n_slots, 1 n_pairs, 2 status, 4 live slots, others free
   float4* slot_rec;                   // [S][4] compositing records, 64 bytes (the last: first pair)
   uint32_t* slot_gid;                 // [S]
   uint32_t* slot_view;                // [S]
@@ -75,6 +76,7 @@ struct kgs_ctx {
   float4* seg_head;                   // [P / 64 + 1][4] per 64-pair window: its first segment's partial sum
   float4* seg_tail;                   // [P / 64 + 1][4] and its last segment's
   float2* slot_pose;                  // [S][3] pose contributions (rho, phi) of every slot
+  uint32_t* slot_live;                // [S] slots whose pixels blended somewhere, for the chain rule
   unsigned long long* scan_part;      // tile sums of the device-wide scans
   unsigned long long* scan_totals;    // [2] their totals
   double* pose_partial;               // [max_views][KGS_POSE_BLOCKS][6]

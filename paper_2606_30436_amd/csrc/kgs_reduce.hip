@@ -168,7 +168,9 @@ __global__ __launch_bounds__(256) void k_pair_segsum(const uint32_t* __restrict_
 __global__ __launch_bounds__(256) void k_pair_fixup(const uint32_t* __restrict__ counters,
                                                     const float4* __restrict__ seg_head,
                                                     const float4* __restrict__ seg_tail,
-                                                    float4* __restrict__ slot_sum) {
+                                                    float4* __restrict__ slot_sum, uint32_t* __restrict__ live_count) {
+  // the live-slot queue of the chain rule starts empty (nothing reads it before)
+  if (blockIdx.x == 0 && threadIdx.x == 0) *live_count = 0u;
   const uint32_t np = counters[1];
   const uint32_t nwin = (np + 63) / 64;
   for (uint32_t w = blockIdx.x * 256 + threadIdx.x; w < nwin; w += gridDim.x * 256) {
@@ -195,9 +197,9 @@ __global__ __launch_bounds__(256) void k_pair_fixup(const uint32_t* __restrict__
 }
 
 template <int DEG>
-__device__ __forceinline__ void slot_record(uint32_t s, const kgs_gaussians& g, const CamDev* __restrict__ cams,
-                                            const BwdParams& P, const uint32_t* __restrict__ slot_gid,
-                                            const uint32_t* __restrict__ slot_view,
+__device__ __forceinline__ void slot_record(uint32_t s, uint32_t v, const kgs_gaussians& g,
+                                            const CamDev* __restrict__ cams, const BwdParams& P,
+                                            const uint32_t* __restrict__ slot_gid,
                                             const uint32_t* __restrict__ slot_ntiles, const float r[10],
                                             uint32_t om, uint32_t kap, float4* __restrict__ slot_bwd,
                                             float2* __restrict__ slot_pose) {
@@ -210,7 +212,6 @@ __device__ __forceinline__ void slot_record(uint32_t s, const kgs_gaussians& g, 
 #pragma unroll
     for (int k = 0; k < KGS_SLOT_WORDS; ++k) out[k] = 0.f;
     const int64_t i = slot_gid[s];
-    const uint32_t v = slot_view[s];
     const uint32_t tiles = slot_ntiles[s];
     GaussLocal G;
     bool bad = false;
@@ -411,30 +412,29 @@ __device__ __forceinline__ void slot_record(uint32_t s, const kgs_gaussians& g, 
   }
 }
 
-// Chain rule of every slot, one thread per slot: the pair sum (words 0-11 of
-// its record) becomes the full 160-byte backward record.
-template <int DEG>
-__global__ __launch_bounds__(KGS_BLOCK) void k_slot_bwd(kgs_gaussians g, const CamDev* __restrict__ cams,
-                                                        BwdParams P, const uint32_t* __restrict__ counters,
-                                                        const uint32_t* __restrict__ slot_gid,
-                                                        const uint32_t* __restrict__ slot_view,
-                                                        const uint32_t* __restrict__ slot_ntiles,
-                                                        const int4* __restrict__ slot_pix,
-                                                        float4* __restrict__ slot_bwd,
-                                                        float2* __restrict__ slot_pose) {
+// Slots whose pixels blended nowhere have a zero sum (every pixel term is a
+// zero at alpha = 0), so zero gradients and pose terms, and the radius the
+// projection stored: k_slot_split writes those records at once and queues the
+// others (one atomic per wave; the queue's order does not matter, since every
+// result is written at its slot), and k_slot_live takes the queue with full
+// waves.  counters[KGS_CNT_LIVE] is cleared by k_pair_fixup.
+__global__ __launch_bounds__(KGS_BLOCK) void k_slot_split(uint32_t* __restrict__ counters,
+                                                          const uint32_t* __restrict__ slot_ntiles,
+                                                          const int4* __restrict__ slot_pix,
+                                                          float4* __restrict__ slot_bwd,
+                                                          float2* __restrict__ slot_pose,
+                                                          uint32_t* __restrict__ slot_live) {
   const uint32_t n_slots = counters[0];
+  const int l = threadIdx.x & 63;
   for (uint32_t s = blockIdx.x * KGS_BLOCK + threadIdx.x; s < n_slots; s += gridDim.x * KGS_BLOCK) {
     float4* q = slot_bwd + (size_t)s * (KGS_SLOT_WORDS / 4);
     // a slot without pairs has no segment and so no sum written
     const bool any = slot_ntiles[s] != 0u;
-    const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
-    const float4 a = any ? q[0] : z, b = any ? q[1] : z, c = any ? q[2] : z;
-    if (__float_as_uint(c.z) == 0u) {
-      // no pixel blended the slot: every pixel term of its sum is a zero
-      // (alpha = 0), so are its gradients and pose terms, and what remains is
-      // the radius statistic, the one the projection stored
+    const bool live = any && __float_as_uint(q[2].z) != 0u;
+    if (!live) {
       const int4 pix = slot_pix[s];
       const int rad = any ? max(pix.z, pix.w) : 0;
+      const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
       for (int k = 0; k < KGS_SLOT_WORDS / 4; ++k) q[k] = z;
       q[5].x = __int_as_float(rad);
@@ -442,11 +442,47 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_slot_bwd(kgs_gaussians g, const C
       p2[0] = make_float2(0.f, 0.f);
       p2[1] = make_float2(0.f, 0.f);
       p2[2] = make_float2(0.f, 0.f);
-      continue;
     }
+    const uint64_t bal = ballot64(live);
+    if (bal != 0ull) {
+      const int leader = __ffsll((long long)bal) - 1;
+      uint32_t base = 0u;
+      if (l == leader) base = atomicAdd(&counters[KGS_CNT_LIVE], (uint32_t)__popcll(bal));
+      base = (uint32_t)__shfl((int)base, leader, 64);
+      if (live) slot_live[base + mask_lt_count(bal)] = s;
+    }
+  }
+}
+
+// Chain rule of every queued slot: its pair sum (words 0-11 of its record)
+// becomes the full backward record.
+template <int DEG>
+__global__ __launch_bounds__(KGS_BLOCK) void k_slot_live(kgs_gaussians g, const CamDev* __restrict__ cams,
+                                                         BwdParams P, const uint32_t* __restrict__ counters,
+                                                         const uint32_t* __restrict__ slot_live,
+                                                         const uint32_t* __restrict__ slot_gid,
+                                                         const uint32_t* __restrict__ slot_view,
+                                                         const uint32_t* __restrict__ slot_ntiles,
+                                                         float4* __restrict__ slot_bwd,
+                                                         float2* __restrict__ slot_pose) {
+  const uint32_t n_live = counters[KGS_CNT_LIVE];
+  for (uint32_t j = blockIdx.x * KGS_BLOCK + threadIdx.x; j < n_live; j += gridDim.x * KGS_BLOCK) {
+    const uint32_t s = slot_live[j];
+    const float4* q = slot_bwd + (size_t)s * (KGS_SLOT_WORDS / 4);
+    const float4 a = q[0], b = q[1], c = q[2];
     const float r[10] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x, c.y};
-    slot_record<DEG>(s, g, cams, P, slot_gid, slot_view, slot_ntiles, r, __float_as_uint(c.z),
-                     __float_as_uint(c.w), slot_bwd, slot_pose);
+    // one view at a time across the wave, so that its camera is read with
+    // scalar loads; queued slots keep view order within a wave's share
+    const uint32_t v = slot_view[s];
+    bool pending = true;
+    while (pending) {
+      const uint32_t vu = __builtin_amdgcn_readfirstlane(v);
+      if (v == vu) {
+        slot_record<DEG>(s, vu, g, cams, P, slot_gid, slot_ntiles, r, __float_as_uint(c.z), __float_as_uint(c.w),
+                         slot_bwd, slot_pose);
+        pending = false;
+      }
+    }
   }
 }
 
@@ -634,12 +670,15 @@ kgs_status kgs_launch_project_bwd(kgs_ctx* ctx, const kgs_gaussians* g, const kg
                        ctx->seg_tail);
     hipLaunchKernelGGL(k_pair_fixup, dim3((unsigned)std::min<uint64_t>(std::max<uint64_t>((wins + 255) / 256, 1), 2048)),
                        dim3(256), 0, st, (const uint32_t*)ctx->counters, (const float4*)ctx->seg_head,
-                       (const float4*)ctx->seg_tail, ctx->slot_bwd);
+                       (const float4*)ctx->seg_tail, ctx->slot_bwd, ctx->counters + KGS_CNT_LIVE);
+    hipLaunchKernelGGL(k_slot_split, dim3(sg), dim3(KGS_BLOCK), 0, st, ctx->counters,
+                       (const uint32_t*)ctx->slot_ntiles, (const int4*)ctx->slot_pix, ctx->slot_bwd, ctx->slot_pose,
+                       ctx->slot_live);
 #define KGS_PB(D)                                                                                                  \
-  hipLaunchKernelGGL(k_slot_bwd<D>, dim3(sg), dim3(KGS_BLOCK), 0, st, *g, (const CamDev*)ctx->cams, P,             \
-                     (const uint32_t*)ctx->counters, (const uint32_t*)ctx->slot_gid,                                \
-                     (const uint32_t*)ctx->slot_view, (const uint32_t*)ctx->slot_ntiles,                          \
-                     (const int4*)ctx->slot_pix, ctx->slot_bwd, ctx->slot_pose);                                                                             \
+  hipLaunchKernelGGL(k_slot_live<D>, dim3(sg), dim3(KGS_BLOCK), 0, st, *g, (const CamDev*)ctx->cams, P,            \
+                     (const uint32_t*)ctx->counters, (const uint32_t*)ctx->slot_live,                               \
+                     (const uint32_t*)ctx->slot_gid, (const uint32_t*)ctx->slot_view,                              \
+                     (const uint32_t*)ctx->slot_ntiles, ctx->slot_bwd, ctx->slot_pose);                            \
   hipLaunchKernelGGL(k_gauss_gather<D>, dim3((unsigned)nb), dim3(KGS_BLOCK), 0, st, *g, V,                        \
                      (const CamDev*)ctx->cams, (const uint32_t*)ctx->vis, (const uint32_t*)ctx->counters,          \
                      (const float4*)ctx->slot_bwd,                                                                \
