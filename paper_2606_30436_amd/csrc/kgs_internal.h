@@ -14,7 +14,7 @@
 #define KGS_CNT_LIVE 4                  // counters[] word of the live-slot count
 #define KGS_SORT_BLOCKS 1024          // fixed grid (one partition per block) of the radix sort passes
 #define KGS_MAX_PASSES 8
-#define KGS_POSE_BLOCKS 32            // pieces per view of the pose reduction
+#define KGS_POSE_BLOCKS 256           // pieces per view of the pose reduction
 #define KGS_SLOT_WORDS 24             // words of a slot's backward record
 
 // ---------------------------------------------------------------- device camera

@@ -274,17 +274,19 @@ __global__ __launch_bounds__(256) void k_slot_offsets(const uint32_t* __restrict
 // [near, far], whose bit patterns are ordered like the values, so the bits
 // minus those of a value just below near keep the order exactly in
 // depth_bits bits (27 for near 0.2, far 80); the view sits above them.
+// The keys are 4 bytes wide when view and depth bits fit in 32.
+template <typename K>
 __global__ __launch_bounds__(KGS_BLOCK) void k_slot_keys(const uint32_t* __restrict__ counters,
                                                          const float4* __restrict__ slot_rec,
                                                          const uint32_t* __restrict__ slot_view, uint32_t depth_lo,
-                                                         int depth_bits, uint64_t* __restrict__ keys,
+                                                         int depth_bits, K* __restrict__ keys,
                                                          uint32_t* __restrict__ vals) {
   const uint32_t n = counters[0];
   const uint32_t dmax = depth_bits >= 32 ? 0xffffffffu : (1u << depth_bits) - 1u;
   for (uint32_t s = blockIdx.x * KGS_BLOCK + threadIdx.x; s < n; s += gridDim.x * KGS_BLOCK) {
     const uint32_t b = __float_as_uint(slot_rec[(size_t)s * 4 + 1].z);
     const uint32_t d = b > depth_lo ? min(b - depth_lo, dmax) : 0u;
-    keys[s] = ((uint64_t)slot_view[s] << depth_bits) | d;
+    keys[s] = (K)(((uint64_t)slot_view[s] << depth_bits) | d);
     vals[s] = s;
   }
 }
@@ -526,12 +528,21 @@ kgs_status kgs_launch_bin_sort(kgs_ctx* ctx, hipStream_t st) {
   const uint64_t depth_span = (uint64_t)std::min<uint32_t>(far_b, 0x7f800000u) + 4096u - depth_lo;
   int depth_bits = 1;
   while (depth_bits < 32 && (1ull << depth_bits) <= depth_span) ++depth_bits;
-  hipLaunchKernelGGL(k_slot_keys, dim3(sgrid), dim3(KGS_BLOCK), 0, st, (const uint32_t*)ctx->counters,
-                     (const float4*)ctx->slot_rec, (const uint32_t*)ctx->slot_view, depth_lo, depth_bits,
-                     ctx->slot_keys[0], ctx->slot_vals[0]);
   int view_bits = 0;
   while ((1 << view_bits) < V) ++view_bits;
-  const int sc = radix_sort<uint64_t>(ctx, ctx->counters, S, ctx->slot_keys, ctx->slot_vals, depth_bits + view_bits, st);
+  int sc;
+  if (depth_bits + view_bits <= 32) {
+    uint32_t* k32[2] = {reinterpret_cast<uint32_t*>(ctx->slot_keys[0]), reinterpret_cast<uint32_t*>(ctx->slot_keys[1])};
+    hipLaunchKernelGGL(k_slot_keys<uint32_t>, dim3(sgrid), dim3(KGS_BLOCK), 0, st, (const uint32_t*)ctx->counters,
+                       (const float4*)ctx->slot_rec, (const uint32_t*)ctx->slot_view, depth_lo, depth_bits, k32[0],
+                       ctx->slot_vals[0]);
+    sc = radix_sort<uint32_t>(ctx, ctx->counters, S, k32, ctx->slot_vals, depth_bits + view_bits, st);
+  } else {
+    hipLaunchKernelGGL(k_slot_keys<uint64_t>, dim3(sgrid), dim3(KGS_BLOCK), 0, st, (const uint32_t*)ctx->counters,
+                       (const float4*)ctx->slot_rec, (const uint32_t*)ctx->slot_view, depth_lo, depth_bits,
+                       ctx->slot_keys[0], ctx->slot_vals[0]);
+    sc = radix_sort<uint64_t>(ctx, ctx->counters, S, ctx->slot_keys, ctx->slot_vals, depth_bits + view_bits, st);
+  }
   const uint32_t* perm = ctx->slot_vals[sc];
   ctx->perm = perm;
   // 2. first pair of every record in that order, then the pairs
