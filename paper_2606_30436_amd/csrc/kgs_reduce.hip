@@ -81,6 +81,7 @@ __device__ __forceinline__ void store_sum(float4* __restrict__ rec, const float 
 
 struct SegWindow {
   uint32_t s, s_before, s_after;
+  bool any;   // some pair of the window was written (else every sum in it is zero)
   float x[12];
 };
 
@@ -91,7 +92,9 @@ __device__ __forceinline__ void seg_load(SegWindow& W, uint32_t w, uint32_t np, 
   const bool valid = p < np;
   W.s = valid ? pair_slot[p] : SEG_NONE;
   // a pair the compositing backward did not reach adds nothing (its record is not written)
-  if (valid && pair_live[p] != 0u) {
+  const bool live = valid && pair_live[p] != 0u;
+  W.any = ballot64(live) != 0ull;
+  if (live) {
     const float4 a = pair_grad[(size_t)p * 3], b = pair_grad[(size_t)p * 3 + 1], c = pair_grad[(size_t)p * 3 + 2];
     W.x[0] = a.x; W.x[1] = a.y; W.x[2] = a.z; W.x[3] = a.w;
     W.x[4] = b.x; W.x[5] = b.y; W.x[6] = b.z; W.x[7] = b.w;
@@ -122,8 +125,10 @@ __device__ __forceinline__ void seg_window(SegWindow& W, uint32_t w, uint32_t np
   const uint64_t H = ballot64(head);
   const uint64_t le = l == 63 ? ~0ull : ((1ull << (l + 1)) - 1ull);
   const int sst = 63 - __clzll((long long)(H & le));
+  if (W.any) {
 #pragma unroll
-  for (int k = 0; k < 12; ++k) W.x[k] = seg_scan(W.x[k], l, sst);
+    for (int k = 0; k < 12; ++k) W.x[k] = seg_scan(W.x[k], l, sst);
+  }
   const bool tail = valid && s != s_dn;
   const bool started = sst > 0 || s != W.s_before;   // the slot's first pair lies in this window
   if (tail) {
@@ -519,9 +524,16 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_gauss_gather(kgs_gaussians g, int
     const uint32_t u = vis[(int64_t)v * n + i];
     if (u == 0u || u > n_slots) continue;
     const float4* r4 = slot_bwd + (size_t)(u - 1u) * (KGS_SLOT_WORDS / 4);
-    float r[KGS_SLOT_WORDS];
+    // words 16-23 first: counts, gradient norm, radius, masked colour gradient
+    const float4 q4 = r4[4], q5 = r4[5];
+    const uint32_t om = __float_as_uint(q4.y);
+    s_vc += 1u;
+    s_mr = max(s_mr, __float_as_int(q5.x));
+    // a slot that blended nowhere holds zeros everywhere else
+    if (om == 0u) continue;
+    float r[16];
 #pragma unroll
-    for (int k = 0; k < KGS_SLOT_WORDS / 4; ++k) {
+    for (int k = 0; k < 4; ++k) {
       const float4 q = r4[k];
       r[4 * k] = q.x; r[4 * k + 1] = q.y; r[4 * k + 2] = q.z; r[4 * k + 3] = q.w;
     }
@@ -540,17 +552,14 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_gauss_gather(kgs_gaussians g, int
     }
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      gsh[k][0] += Y[k] * r[21];
-      gsh[k][1] += Y[k] * r[22];
-      gsh[k][2] += Y[k] * r[23];
+      gsh[k][0] += Y[k] * q5.y;
+      gsh[k][1] += Y[k] * q5.z;
+      gsh[k][2] += Y[k] * q5.w;
     }
-    const uint32_t om = __float_as_uint(r[17]);
     s_om += om;
-    s_kap += __float_as_uint(r[18]);
+    s_kap += __float_as_uint(q4.z);
     if (view_loss) s_gam += (double)view_loss[v] * (double)om;
-    s_gn += r[19];
-    s_vc += 1u;
-    s_mr = max(s_mr, __float_as_int(r[20]));
+    s_gn += q4.w;
   }
   if (overwrite) {
     // the outputs start from zero: every Gaussian is written, seen or not
