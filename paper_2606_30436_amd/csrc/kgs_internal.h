@@ -39,6 +39,28 @@ struct CamDev {
 // band) in magnitude.
 __device__ __forceinline__ int pix_origin(int extent) { return extent >> 1; }
 
+// Layout of the record depth-sort key: the view above the bits of the FP32
+// depth minus those of a value just below near (depths are positive, so their
+// bit patterns order like the values); 4-byte keys when both fit in 32 bits.
+struct SlotKeyLayout {
+  uint32_t depth_lo;
+  int depth_bits, view_bits;
+  bool key32() const { return depth_bits + view_bits <= 32; }
+};
+static inline SlotKeyLayout slot_key_layout(float near_z, float far_z, int V) {
+  uint32_t near_b, far_b;
+  __builtin_memcpy(&near_b, &near_z, 4);
+  __builtin_memcpy(&far_b, &far_z, 4);
+  SlotKeyLayout L;
+  L.depth_lo = near_b > 4096u ? near_b - 4096u : 0u;
+  const uint64_t span = (uint64_t)(far_b < 0x7f800000u ? far_b : 0x7f800000u) + 4096u - L.depth_lo;
+  L.depth_bits = 1;
+  while (L.depth_bits < 32 && (1ull << L.depth_bits) <= span) ++L.depth_bits;
+  L.view_bits = 0;
+  while ((1 << L.view_bits) < V) ++L.view_bits;
+  return L;
+}
+
 // ---------------------------------------------------------------- context
 struct kgs_ctx {
   kgs_config cfg;
@@ -77,6 +99,8 @@ struct kgs_ctx {
   float4* seg_tail;                   // [P / 64 + 1][4] and its last segment's
   float2* slot_pose;                  // [S][3] pose contributions (rho, phi) of every slot
   uint32_t* slot_live;                // [S] slots whose pixels blended somewhere, for the chain rule
+  uint32_t* chunk_first;              // [P / 2048 + 2] record owning the first pair of each emission chunk
+  int slot_keys_ready;                // the projection wrote the depth-sort keys; no sort has used them yet
   unsigned long long* scan_part;      // tile sums of the device-wide scans
   unsigned long long* scan_totals;    // [2] their totals
   double* pose_partial;               // [max_views][KGS_POSE_BLOCKS][6]

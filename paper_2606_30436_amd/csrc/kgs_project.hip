@@ -114,6 +114,8 @@ __global__ void k_cam_setup(const kgs_camera* __restrict__ cams, const float* __
 struct ProjParams {
   float alpha_min, log_alpha_min, near_z, far_z, eps2d, rect_margin;
   int tile_w, tile_h, tiles_x, tiles_y;
+  uint32_t depth_lo;        // record depth-sort key layout
+  int depth_bits, key32;
 };
 
 __global__ __launch_bounds__(KGS_BLOCK) void k_count(kgs_gaussians g, const CamDev* __restrict__ cams, int V,
@@ -182,7 +184,8 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_emit(kgs_gaussians g, const CamDe
                                                     uint64_t slot_cap,
                                                     float4* __restrict__ slot_rec, uint32_t* __restrict__ slot_gid,
                                                     uint32_t* __restrict__ slot_view, int4* __restrict__ slot_pix,
-                                                    uint32_t* __restrict__ slot_ntiles) {
+                                                    uint32_t* __restrict__ slot_ntiles, void* __restrict__ slot_keys,
+                                                    uint32_t* __restrict__ slot_vals) {
   constexpr int K = (DEG + 1) * (DEG + 1);
   // visible lanes of each wave, per view: a slot's index is the (view, block)
   // base plus the visible lanes before it (one barrier for all views)
@@ -241,6 +244,15 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_emit(kgs_gaussians g, const CamDe
     slot_view[s] = (uint32_t)v;
     slot_pix[s] = pix;
     slot_ntiles[s] = tiles;
+    // the record's (view, depth) key for the depth sort, from its depth r1.z
+    const uint32_t db = __float_as_uint(r1.z);
+    const uint32_t dmax = P.depth_bits >= 32 ? 0xffffffffu : (1u << P.depth_bits) - 1u;
+    const uint64_t key = ((uint64_t)v << P.depth_bits) | (db > P.depth_lo ? min(db - P.depth_lo, dmax) : 0u);
+    if (P.key32)
+      reinterpret_cast<uint32_t*>(slot_keys)[s] = (uint32_t)key;
+    else
+      reinterpret_cast<uint64_t*>(slot_keys)[s] = key;
+    slot_vals[s] = (uint32_t)s;
   }
   // colours from the view directions (Gaussian mean minus camera centre), once
   // the projections are done: the SH coefficients are read once and never held
@@ -285,6 +297,10 @@ kgs_status kgs_launch_project(kgs_ctx* ctx, const kgs_gaussians* g, const kgs_ca
   P.tile_h = cfg.tile_h;
   P.tiles_x = ctx->tiles_x;
   P.tiles_y = ctx->tiles_y;
+  const SlotKeyLayout KL = slot_key_layout(cfg.near_z, cfg.far_z, V);
+  P.depth_lo = KL.depth_lo;
+  P.depth_bits = KL.depth_bits;
+  P.key32 = KL.key32() ? 1 : 0;
   const int64_t nb = (g->n + KGS_BLOCK - 1) / KGS_BLOCK;
   if (nb > 0)
     hipLaunchKernelGGL(k_count, dim3((unsigned)nb), dim3(KGS_BLOCK), 0, st, *g, (const CamDev*)ctx->cams, V, P,
@@ -297,7 +313,8 @@ kgs_status kgs_launch_project(kgs_ctx* ctx, const kgs_gaussians* g, const kgs_ca
 #define KGS_EMIT(D)                                                                                              \
   hipLaunchKernelGGL(k_emit<D>, dim3((unsigned)nb), dim3(KGS_BLOCK), 0, st, *g, (const CamDev*)ctx->cams, V, P,   \
                      ctx->vis, (const uint32_t*)ctx->blk_base, nb, (uint64_t)cfg.slot_capacity,                \
-                     ctx->slot_rec, ctx->slot_gid, ctx->slot_view, ctx->slot_pix, ctx->slot_ntiles)
+                     ctx->slot_rec, ctx->slot_gid, ctx->slot_view, ctx->slot_pix, ctx->slot_ntiles,            \
+                     (void*)ctx->slot_keys[0], ctx->slot_vals[0])
     switch (g->sh_degree) {
       case 0: KGS_EMIT(0); break;
       case 1: KGS_EMIT(1); break;
@@ -306,5 +323,6 @@ kgs_status kgs_launch_project(kgs_ctx* ctx, const kgs_gaussians* g, const kgs_ca
     }
 #undef KGS_EMIT
   }
+  ctx->slot_keys_ready = 1;
   return kgs_check_launch();
 }

@@ -220,6 +220,10 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t* __restric
   }
 }
 
+// pair emission works in chunks of EP_CHUNK pairs, EP_PPT per thread
+#define EP_PPT 8
+#define EP_CHUNK (256 * EP_PPT)
+
 // ---------------------------------------------------------------- group scan
 // The depth-sorted slots are cut into groups of 64; a group's pairs are
 // contiguous.  k_group_sum: tile count of every group (one wave per group);
@@ -242,14 +246,16 @@ __global__ __launch_bounds__(256) void k_group_sum(const uint32_t* __restrict__ 
 
 // First pair of every record in depth order: pref[j] = part[g] + the exclusive
 // scan of the tile counts inside the 64-record group g = j / 64; the same value
-// is the record's slot_pairoff.
+// is the record's slot_pairoff.  A record whose pairs hold the first pair of an
+// emission chunk also names itself the chunk's first record.
 __global__ __launch_bounds__(256) void k_slot_offsets(const uint32_t* __restrict__ counters,
                                                       const uint32_t* __restrict__ perm,
                                                       const uint32_t* __restrict__ part, uint32_t n_groups,
                                                       const uint32_t* __restrict__ ntiles, uint64_t pair_cap,
                                                       uint32_t* __restrict__ pref,
                                                       uint32_t* __restrict__ slot_pairoff,
-                                                      float4* __restrict__ slot_rec) {
+                                                      float4* __restrict__ slot_rec,
+                                                      uint32_t* __restrict__ chunk_first) {
   const uint32_t n = counters[0];
   const uint32_t l = threadIdx.x & 63;
   const uint32_t waves = gridDim.x * 4;
@@ -265,6 +271,8 @@ __global__ __launch_bounds__(256) void k_slot_offsets(const uint32_t* __restrict
       slot_pairoff[s] = (uint32_t)off;
       // also in the record's last 16 bytes, read with the record by the backward
       slot_rec[(size_t)s * 4 + 3] = make_float4(__uint_as_float((uint32_t)off), 0.f, 0.f, 0.f);
+      const uint64_t e = min(off + (uint64_t)c, pair_cap);
+      for (uint64_t b = (off + EP_CHUNK - 1) / EP_CHUNK; b * EP_CHUNK < e; ++b) chunk_first[b] = j;
     }
   }
 }
@@ -292,38 +300,19 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_slot_keys(const uint32_t* __restr
 }
 
 // ---------------------------------------------------------------- pair emission
-// Balanced by pairs: each round a block takes the next EP_CHUNK pairs.  Two
-// waves find (64-way search over pref) the records that own the first and the
-// last pair, the block stages those records' first-pair offsets in LDS, and
-// each thread emits EP_PPT consecutive pairs, walking forward from a binary
-// search in LDS.  A pair's key is its global tile index, its value the record;
+// Balanced by pairs: each round a block takes the next EP_CHUNK pairs.  The
+// chunk's first record and the next chunk's (named by k_slot_offsets) bound the
+// records that own its pairs, the block stages those records' first-pair
+// offsets in LDS, and each thread emits EP_PPT consecutive pairs, walking
+// forward from a binary search in LDS.  A pair's key is its global tile index, its value the record;
 // pair k of a record is the k-th tile of its rectangle in row-major order, so
 // its emission position is the record's first pair plus that rank.
-#define EP_PPT 8
-#define EP_CHUNK (256 * EP_PPT)
 
 __device__ __forceinline__ uint32_t udiv_small(uint32_t a, uint32_t b) {
   uint32_t q = (uint32_t)((float)a * __frcp_rn((float)b));
   while (q * b > a) --q;
   while ((q + 1) * b <= a) ++q;
   return q;
-}
-
-// Last j in [0, n) with pref[j] <= target, for a whole wave (pref[0] = 0).
-__device__ __forceinline__ uint32_t wave_search_last_le(const uint32_t* __restrict__ pref, uint32_t n,
-                                                        uint32_t target) {
-  const uint32_t l = threadIdx.x & 63;
-  uint32_t lo = 0, hi = n;
-  while (hi - lo > 1) {
-    const uint32_t step = (hi - lo + 63) / 64;
-    const uint32_t pos = lo + l * step;
-    const bool le = pos < hi && pref[pos] <= target;
-    const uint64_t bal = ballot64(le);
-    const uint32_t last = 63u - (uint32_t)__clzll((long long)bal);
-    lo = lo + last * step;
-    hi = min(hi, lo + step);
-  }
-  return lo;
 }
 
 struct EmitSlot {
@@ -348,27 +337,26 @@ __device__ __forceinline__ EmitSlot emit_slot(uint32_t s, const uint32_t* __rest
 __global__ __launch_bounds__(256) void k_emit_pairs(const uint32_t* __restrict__ counters,
                                                     const uint32_t* __restrict__ perm,
                                                     const uint32_t* __restrict__ pref,
+                                                    const uint32_t* __restrict__ chunk_first,
                                                     const uint32_t* __restrict__ slot_view,
                                                     const int4* __restrict__ slot_pix, int tile_w, int tile_h,
                                                     int tiles_x, int tiles_y, uint32_t* __restrict__ keys,
                                                     uint32_t* __restrict__ vals) {
   __shared__ uint32_t s_pref[EP_CHUNK + 1];
-  __shared__ uint32_t s_j[2];
   const uint32_t n = counters[0], np = counters[1];
   const int tid = threadIdx.x;
   const uint32_t tiles_per_view = (uint32_t)(tiles_x * tiles_y);
-  for (uint64_t P0 = (uint64_t)blockIdx.x * EP_CHUNK; P0 < np; P0 += (uint64_t)gridDim.x * EP_CHUNK) {
+  const uint64_t nchunks = ((uint64_t)np + EP_CHUNK - 1) / EP_CHUNK;
+  for (uint64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+    const uint64_t P0 = c * EP_CHUNK;
     const uint32_t p0 = (uint32_t)P0;
     const uint32_t p1 = (uint32_t)min<uint64_t>(P0 + EP_CHUNK, np) - 1u;
-    if (tid < 128) {
-      const uint32_t j = wave_search_last_le(pref, n, tid < 64 ? p0 : p1);
-      if ((tid & 63) == 0) s_j[tid >> 6] = j;
-    }
-    __syncthreads();
-    const uint32_t jlo = s_j[0];
-    // every record in [jlo, jhi] owns a pair of the chunk, so there are at
-    // most EP_CHUNK of them; the clamp only keeps LDS in bounds
-    const uint32_t cnt = min(s_j[1] - jlo + 1u, (uint32_t)EP_CHUNK);
+    // records jlo .. jhi: the owner of p0 up to the owner of the next chunk's
+    // first pair (or the last record); every record owns a pair, so the owner
+    // of p1 is among the first EP_CHUNK of them and the clamp drops none needed
+    const uint32_t jlo = chunk_first[c];
+    const uint32_t jhi = c + 1 < nchunks ? chunk_first[c + 1] : n - 1u;
+    const uint32_t cnt = min(jhi - jlo + 1u, (uint32_t)EP_CHUNK);
     for (uint32_t k = tid; k < cnt; k += 256) s_pref[k] = pref[jlo + k];
     if (tid == 0) s_pref[cnt] = 0xffffffffu;
     __syncthreads();
@@ -520,29 +508,26 @@ kgs_status kgs_launch_bin_sort(kgs_ctx* ctx, hipStream_t st) {
   const uint32_t n_tiles_all = (uint32_t)(V * ctx->n_tiles);
   const uint64_t S = (uint64_t)ctx->cfg.slot_capacity, P = (uint64_t)ctx->cfg.pair_capacity;
   const unsigned sgrid = (unsigned)std::min<uint64_t>(std::max<uint64_t>((S + KGS_BLOCK - 1) / KGS_BLOCK, 1), 4096);
-  // 1. records by (view, depth)
-  uint32_t near_b, far_b;
-  std::memcpy(&near_b, &ctx->cfg.near_z, 4);
-  std::memcpy(&far_b, &ctx->cfg.far_z, 4);
-  const uint32_t depth_lo = near_b > 4096u ? near_b - 4096u : 0u;
-  const uint64_t depth_span = (uint64_t)std::min<uint32_t>(far_b, 0x7f800000u) + 4096u - depth_lo;
-  int depth_bits = 1;
-  while (depth_bits < 32 && (1ull << depth_bits) <= depth_span) ++depth_bits;
-  int view_bits = 0;
-  while ((1 << view_bits) < V) ++view_bits;
+  // 1. records by (view, depth); the projection wrote the keys, unless a sort
+  // since has used them
+  const SlotKeyLayout KL = slot_key_layout(ctx->cfg.near_z, ctx->cfg.far_z, V);
+  const int key_bits = KL.depth_bits + KL.view_bits;
   int sc;
-  if (depth_bits + view_bits <= 32) {
+  if (KL.key32()) {
     uint32_t* k32[2] = {reinterpret_cast<uint32_t*>(ctx->slot_keys[0]), reinterpret_cast<uint32_t*>(ctx->slot_keys[1])};
-    hipLaunchKernelGGL(k_slot_keys<uint32_t>, dim3(sgrid), dim3(KGS_BLOCK), 0, st, (const uint32_t*)ctx->counters,
-                       (const float4*)ctx->slot_rec, (const uint32_t*)ctx->slot_view, depth_lo, depth_bits, k32[0],
-                       ctx->slot_vals[0]);
-    sc = radix_sort<uint32_t>(ctx, ctx->counters, S, k32, ctx->slot_vals, depth_bits + view_bits, st);
+    if (!ctx->slot_keys_ready)
+      hipLaunchKernelGGL(k_slot_keys<uint32_t>, dim3(sgrid), dim3(KGS_BLOCK), 0, st, (const uint32_t*)ctx->counters,
+                         (const float4*)ctx->slot_rec, (const uint32_t*)ctx->slot_view, KL.depth_lo, KL.depth_bits,
+                         k32[0], ctx->slot_vals[0]);
+    sc = radix_sort<uint32_t>(ctx, ctx->counters, S, k32, ctx->slot_vals, key_bits, st);
   } else {
-    hipLaunchKernelGGL(k_slot_keys<uint64_t>, dim3(sgrid), dim3(KGS_BLOCK), 0, st, (const uint32_t*)ctx->counters,
-                       (const float4*)ctx->slot_rec, (const uint32_t*)ctx->slot_view, depth_lo, depth_bits,
-                       ctx->slot_keys[0], ctx->slot_vals[0]);
-    sc = radix_sort<uint64_t>(ctx, ctx->counters, S, ctx->slot_keys, ctx->slot_vals, depth_bits + view_bits, st);
+    if (!ctx->slot_keys_ready)
+      hipLaunchKernelGGL(k_slot_keys<uint64_t>, dim3(sgrid), dim3(KGS_BLOCK), 0, st, (const uint32_t*)ctx->counters,
+                         (const float4*)ctx->slot_rec, (const uint32_t*)ctx->slot_view, KL.depth_lo, KL.depth_bits,
+                         ctx->slot_keys[0], ctx->slot_vals[0]);
+    sc = radix_sort<uint64_t>(ctx, ctx->counters, S, ctx->slot_keys, ctx->slot_vals, key_bits, st);
   }
+  ctx->slot_keys_ready = 0;
   const uint32_t* perm = ctx->slot_vals[sc];
   ctx->perm = perm;
   // 2. first pair of every record in that order, then the pairs
@@ -554,11 +539,11 @@ kgs_status kgs_launch_bin_sort(kgs_ctx* ctx, hipStream_t st) {
   uint32_t* pref = reinterpret_cast<uint32_t*>(ctx->slot_keys[sc ^ 1]);  // free after the record sort
   hipLaunchKernelGGL(k_slot_offsets, dim3(eg), dim3(256), 0, st, (const uint32_t*)ctx->counters, perm,
                      (const uint32_t*)ctx->group_part, n_groups, (const uint32_t*)ctx->slot_ntiles, P, pref,
-                     ctx->slot_pairoff, ctx->slot_rec);
+                     ctx->slot_pairoff, ctx->slot_rec, ctx->chunk_first);
   const uint64_t chunks = (P + EP_CHUNK - 1) / EP_CHUNK;
   const unsigned pg = (unsigned)std::min<uint64_t>(std::max<uint64_t>(chunks, 1), 4096);
   hipLaunchKernelGGL(k_emit_pairs, dim3(pg), dim3(256), 0, st, (const uint32_t*)ctx->counters, perm,
-                     (const uint32_t*)pref, (const uint32_t*)ctx->slot_view, (const int4*)ctx->slot_pix,
+                     (const uint32_t*)pref, (const uint32_t*)ctx->chunk_first, (const uint32_t*)ctx->slot_view, (const int4*)ctx->slot_pix,
                      ctx->cfg.tile_w, ctx->cfg.tile_h, ctx->tiles_x, ctx->tiles_y, ctx->keys[0], ctx->pair_slot);
   // 3. pairs by tile (stable)
   // padding pairs carry key 0xffffffff; with n_tiles_all < 2^tile_bits they
