@@ -437,12 +437,12 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_slot_split(uint32_t* __restrict__
     const bool any = slot_ntiles[s] != 0u;
     const bool live = any && __float_as_uint(q[2].z) != 0u;
     if (!live) {
+      // words 16-23 (counts, gradient norm, radius, colour gradient): the
+      // gather reads no other word of a slot that blended nowhere
       const int4 pix = slot_pix[s];
       const int rad = any ? max(pix.z, pix.w) : 0;
-      const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll
-      for (int k = 0; k < KGS_SLOT_WORDS / 4; ++k) q[k] = z;
-      q[5].x = __int_as_float(rad);
+      q[4] = make_float4(0.f, 0.f, 0.f, 0.f);
+      q[5] = make_float4(__int_as_float(rad), 0.f, 0.f, 0.f);
       float2* p2 = slot_pose + (size_t)s * 3;
       p2[0] = make_float2(0.f, 0.f);
       p2[1] = make_float2(0.f, 0.f);
@@ -632,16 +632,26 @@ __global__ __launch_bounds__(256) void k_pose_reduce(const uint32_t* __restrict_
   if (tid < 6) partial[((size_t)v * KGS_POSE_BLOCKS + b) * 6 + tid] = (sh[0][tid] + sh[1][tid]) + (sh[2][tid] + sh[3][tid]);
 }
 
-// d/dxi = J_l(xi)^T (dL/drho, dL/dphi), summed over the pieces in fixed order.
-__global__ void k_pose_final(int V, const double* __restrict__ partial, const CamDev* __restrict__ cams,
-                             float* __restrict__ grad, int overwrite) {
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= V) return;
-  double gd[6] = {0, 0, 0, 0, 0, 0};
-  for (int b = 0; b < KGS_POSE_BLOCKS; ++b)
-    for (int k = 0; k < 6; ++k) gd[k] += partial[((size_t)v * KGS_POSE_BLOCKS + b) * 6 + k];
-  const CamDev& c = cams[v];
-  for (int j = 0; j < 6; ++j) {
+// d/dxi = J_l(xi)^T (dL/drho, dL/dphi), the pieces summed by a fixed tree
+// (one block per view, one piece per thread).
+__global__ __launch_bounds__(KGS_POSE_BLOCKS) void k_pose_final(const double* __restrict__ partial,
+                                                                const CamDev* __restrict__ cams,
+                                                                float* __restrict__ grad, int overwrite) {
+  static_assert(KGS_POSE_BLOCKS == 256, "one thread per piece, four waves");
+  __shared__ double sh[4][6];
+  const int v = blockIdx.x, tid = threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const double t = wave_sum(partial[((size_t)v * KGS_POSE_BLOCKS + tid) * 6 + k]);
+    if ((tid & 63) == 0) sh[tid >> 6][k] = t;
+  }
+  __syncthreads();
+  if (tid < 6) {
+    const int j = tid;
+    double gd[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) gd[k] = (sh[0][k] + sh[1][k]) + (sh[2][k] + sh[3][k]);
+    const CamDev& c = cams[v];
     double s = 0.0;
     for (int k = 0; k < 6; ++k) s += c.Jl[k * 6 + j] * gd[k];
     grad[v * 6 + j] = overwrite ? (float)s : grad[v * 6 + j] + (float)s;
@@ -702,7 +712,7 @@ kgs_status kgs_launch_project_bwd(kgs_ctx* ctx, const kgs_gaussians* g, const kg
     if (G.pose_xi) {
       hipLaunchKernelGGL(k_pose_reduce, dim3(KGS_POSE_BLOCKS, V), dim3(256), 0, st, (const uint32_t*)ctx->counters,
                          (const uint32_t*)ctx->blk_base, nb, V, (const float2*)ctx->slot_pose, ctx->pose_partial);
-      hipLaunchKernelGGL(k_pose_final, dim3(1), dim3(64), 0, st, V, (const double*)ctx->pose_partial,
+      hipLaunchKernelGGL(k_pose_final, dim3(V), dim3(KGS_POSE_BLOCKS), 0, st, (const double*)ctx->pose_partial,
                          (const CamDev*)ctx->cams, G.pose_xi, overwrite ? 1 : 0);
     }
   }
