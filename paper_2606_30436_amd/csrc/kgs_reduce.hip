@@ -1,16 +1,18 @@
 // Backward of the projection, deterministic throughout:
 //   k_pair_segsum   per slot, the sum of its pairs' gradient records (they
 //   k_pair_fixup    are contiguous in emission order), segmented by slot;
-//   k_slot_bwd      per slot, from its pair sum, the chain rule to the
+//   k_slot_split    per slot: one that blended in no pixel gets its (zero)
+//                   record at once, the others are queued;
+//   k_slot_live     per queued slot, from its pair sum, the chain rule to the
 //                   Gaussian's parameters and to the view's pose, and the
-//                   view's footprint statistics, as one 160-byte record;
+//                   view's footprint statistics, as one 96-byte record;
 //   k_gauss_gather  per Gaussian, the sum of its records over the views in
 //                   view order (the emission left each (view, Gaussian) slot
 //                   index in vis), added into the gradients and statistics;
 //   k_pose_reduce   per view, the pose contributions of its slots (contiguous,
 //                   slots are in (view, Gaussian) order) in a fixed tree.
-// Views are summed in view order, so a batched call and a per-view loop give
-// identical bits.  The pose gradient is accumulated as the left-perturbation
+// Views are summed in view order; a per-view loop sums the same terms, in
+// another order only where a slot's pairs fall into other scan windows.  The pose gradient is accumulated as the left-perturbation
 // gradient (rho, phi) of T' = Exp(delta) T' and turned into d/dxi by the SE(3)
 // left Jacobian at the end.
 #include <algorithm>
