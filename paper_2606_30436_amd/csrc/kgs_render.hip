@@ -274,11 +274,14 @@ __device__ __forceinline__ void wave_reduce10(float (&x)[10], int lane, int& idx
 // The same for twenty values (two pairs): lane halves, row pairs, mirrored
 // lanes of a row (five values to three), of a half-row (three to two), then
 // the lane pair inside a quad (two to one) and the other quad pair.  Lanes
-// with valid set hold the full wave sum of value idx.
+// with valid set hold the full wave sum of value idx.  With NV = 9 the tenth
+// value of each half is known to be zero and its first step is skipped.
+template <int NV>
 __device__ __forceinline__ void wave_reduce20(float (&x)[20], int lane, int& idx, bool& valid) {
+  static_assert(NV == 9 || NV == 10, "nine or ten values per entry");
   const bool u4 = lane & 16, u3 = lane & 8, u2 = lane & 4, u0 = lane & 1;
 #pragma unroll
-  for (int k = 0; k < 10; ++k) x[k] = f_swap_sum32(x[k], x[k + 10]);
+  for (int k = 0; k < 10; ++k) x[k] = k < NV ? f_swap_sum32(x[k], x[k + 10]) : 0.f;
 #pragma unroll
   for (int k = 0; k < 5; ++k) x[k] = f_swap_sum16(x[k], x[k + 5]);
   {
@@ -314,20 +317,23 @@ __device__ __forceinline__ void wave_reduce20(float (&x)[20], int lane, int& idx
 // clamped at alpha_max): with log2 alpha = log2 o + P' u^2 + E' dy^2 and
 // u = dx + k dy, the pair's P', k, E' and ln 2 turn their sums into the
 // record-space derivatives.  x[6..9] = alpha_j T_j g (colour and depth).
+template <bool DEPTH>
 __device__ __forceinline__ void blend_terms(float e, float u, float dy, bool bl, const float4& r1, const float4& r2,
                                             float amax, float g0, float g1, float g2, float gD, float& T, float& Rj,
                                             float* __restrict__ x) {
   const float raw = exp2_approx(e);
   const float a = bl ? fminf(raw, amax) : 0.f;
   const float wgt = a * T;
-  const float gc = fmaf(gD, r1.z, fmaf(g2, r2.z, fmaf(g1, r2.y, g0 * r2.x)));
+  // without a depth gradient (gD = 0) the depth terms are zero and left out
+  const float gcc = fmaf(g2, r2.z, fmaf(g1, r2.y, g0 * r2.x));
+  const float gc = DEPTH ? fmaf(gD, r1.z, gcc) : gcc;
   Rj = fmaf(wgt, gc, Rj);
   const float oma = 1.0f - a;
   const float dLda = fmaf(T, gc, Rj * __builtin_amdgcn_rcpf(oma));
   x[6] = wgt * g0;
   x[7] = wgt * g1;
   x[8] = wgt * g2;
-  x[9] = wgt * gD;
+  x[9] = DEPTH ? wgt * gD : 0.f;
   const float ge = raw < amax ? dLda * a : 0.f;
   const float gu = ge * u, gd = ge * dy;
   x[0] = gu;
@@ -352,7 +358,7 @@ __device__ __forceinline__ uint32_t pair_position(uint32_t first, float xb_f, fl
   return first + (uint32_t)((ty - y0) * (x1 - x0) + (tx - x0));
 }
 
-template <int B, int NW>
+template <int B, int NW, bool DEPTH>
 __global__ __launch_bounds__(64 * NW) void k_render_bwd(
     RenderParams P, const uint2* __restrict__ ranges, const uint32_t* __restrict__ tile_order,
     const uint32_t* __restrict__ sorted_slot,
@@ -511,12 +517,12 @@ __global__ __launch_bounds__(64 * NW) void k_render_bwd(
       if (bba != 0ull && bbb != 0ull) {
         float x[20];
         const float4 ra2 = s_r2[w][j], rb2 = s_r2[w][jb];
-        blend_terms(ea, ua, dya, bla, ra1, ra2, P.amax, g0, g1, g2, gD, T, Rj, x);
-        blend_terms(eb, ub, dyb, blb, rb1, rb2, P.amax, g0, g1, g2, gD, T, Rj, x + 10);
+        blend_terms<DEPTH>(ea, ua, dya, bla, ra1, ra2, P.amax, g0, g1, g2, gD, T, Rj, x);
+        blend_terms<DEPTH>(eb, ub, dyb, blb, rb1, rb2, P.amax, g0, g1, g2, gD, T, Rj, x + 10);
         const uint64_t bma = ballot64(bla && M), bmb = ballot64(blb && M);
         int idx;
         bool valid;
-        wave_reduce20(x, l, idx, valid);
+        wave_reduce20<DEPTH ? 10 : 9>(x, l, idx, valid);
         if (valid) s_part[w][idx < 10 ? ta : tb][idx < 10 ? idx : idx - 10] = x[0];
         if (l == 0) {
           s_part[w][ta][10] = __uint_as_float((uint32_t)__popcll(bba));
@@ -529,7 +535,7 @@ __global__ __launch_bounds__(64 * NW) void k_render_bwd(
         const int tt = first ? ta : tb, tz = first ? tb : ta;
         const bool bl = first ? bla : blb;
         float x[10];
-        blend_terms(first ? ea : eb, first ? ua : ub, first ? dya : dyb, bl, first ? ra1 : rb1,
+        blend_terms<DEPTH>(first ? ea : eb, first ? ua : ub, first ? dya : dyb, bl, first ? ra1 : rb1,
                     s_r2[w][first ? j : jb], P.amax, g0, g1, g2, gD, T, Rj, x);
         const uint64_t bm = ballot64(bl && M);
         int idx;
@@ -668,7 +674,9 @@ kgs_status kgs_launch_render_bwd(kgs_ctx* ctx, const kgs_image* fwd, const float
   hipLaunchKernelGGL(k_clear_live, dim3((unsigned)std::min<uint64_t>(std::max<uint64_t>((lw + 255) / 256, 1), 1024)),
                      dim3(256), 0, st, (const uint32_t*)ctx->counters, (uint4*)ctx->pair_live);
 #define KGS_BWD(BB, NWV)                                                                                         \
-  hipLaunchKernelGGL((k_render_bwd<BB, NWV>), dim3(grid), dim3(64 * NWV), 0, st, P, (const uint2*)ctx->ranges,   \
+  if (dl_ddepth) { KGS_BWD_D(BB, NWV, true); } else { KGS_BWD_D(BB, NWV, false); }
+#define KGS_BWD_D(BB, NWV, DD)                                                                                   \
+  hipLaunchKernelGGL((k_render_bwd<BB, NWV, DD>), dim3(grid), dim3(64 * NWV), 0, st, P, (const uint2*)ctx->ranges,   \
                      (const uint32_t*)ctx->tile_order,                                                           \
                      (const uint32_t*)ctx->sorted_slot,                                                           \
                      (const float4*)ctx->slot_rec,                                                                \
@@ -688,5 +696,6 @@ kgs_status kgs_launch_render_bwd(kgs_ctx* ctx, const kgs_image* fwd, const float
     }
   }
 #undef KGS_BWD
+#undef KGS_BWD_D
   return kgs_check_launch();
 }

@@ -149,21 +149,25 @@ def _involved(sc, cfg):
     return bad
 
 
-@pytest.mark.parametrize("name", ["c1", "tiny", "tiny_bg"])
-def test_render_backward_matches_oracle(name):
+@pytest.mark.parametrize("name,depth", [("c1", True), ("tiny", True), ("tiny_bg", True), ("c1", False),
+                                        ("tiny", False)])
+def test_render_backward_matches_oracle(name, depth):
+    """With and without a depth gradient (the backward has a variant that
+    leaves the depth terms out when none is passed)."""
     sc = _scene(name)
     kw = {"bg": (0.2, 0.5, 0.9)} if name == "tiny_bg" else {}
-    say(f"[gpu] render bwd {name}")
+    say(f"[gpu] render bwd {name} depth={depth}")
     R = _rast(sc, **kw)
     g, cams, xi, img = run_forward(R, sc)
     rng = np.random.default_rng(7)
     V, H, W = sc.n_views, sc.height, sc.width
     dLdC = rng.normal(size=(V, 3, H, W))
-    dLdD = rng.normal(size=(V, H, W)) * 0.05
+    dLdD = rng.normal(size=(V, H, W)) * 0.05 if depth else np.zeros((V, H, W))
     grads = g.zeros_like()
     pose_grad = torch.zeros(V, 6, device="cuda")
     R.render_bwd(g, cams, xi, img, torch.from_numpy(dLdC.astype(np.float32)).cuda(),
-                 torch.from_numpy(dLdD.astype(np.float32)).cuda(), grads=grads, pose_grad=pose_grad)
+                 torch.from_numpy(dLdD.astype(np.float32)).cuda() if depth else None, grads=grads,
+                 pose_grad=pose_grad)
     torch.cuda.synchronize()
     cfg = oracle_cfg(R)
     ref = _oracle_grads(sc, cfg, dLdC, dLdD)
