@@ -101,6 +101,43 @@ def test_binning_is_bit_exact(name, tile):
     assert np.array_equal(gg.astype(np.int64), gids)
 
 
+def _check_binning(R, sc, tile):
+    b = R.buffers()
+    pix = b["slot_pix"].numpy()
+    depth_bits = b["slot_rec"].numpy()[:, 6].copy().view(np.uint32)
+    keys, gids = oracle.bin_keys(b["slot_view"].numpy(), b["slot_gid"].numpy(), pix[:, 0], pix[:, 1], pix[:, 2],
+                                 pix[:, 3], depth_bits, sc.width, sc.height, tile[0], tile[1])
+    ss = b["sorted_slot"].numpy()
+    gk = (b["keys"].numpy().view(np.uint32).astype(np.uint64) << np.uint64(32)) | depth_bits[ss].astype(np.uint64)
+    assert len(gk) == len(keys) == b["n_pairs"]
+    assert np.array_equal(gk, keys)
+    assert np.array_equal(b["slot_gid"].numpy()[ss].astype(np.int64), gids)
+    return b
+
+
+@pytest.mark.parametrize("case", ["second_sort", "wide_keys"])
+def test_binning_bit_exact_on_the_other_sort_paths(case):
+    """The record depth sort in its two other forms: a second sort after one
+    projection (the first consumed the keys the projection wrote, so the sort
+    builds them again from the records), and view plus depth bits above 32
+    (8-byte keys: near 1e-6, far 1e5 and 16 views give 29 + 4 bits)."""
+    say(f"[gpu] binning path {case}")
+    if case == "second_sort":
+        sc = _scene("c1")
+        R = _rast(sc)
+    else:
+        sc = scenes.tiny_scene(seed=6, n=400, degree=1, W=96, H=64, n_views=16, pose_sigma=0.05)
+        R = _rast(sc, near_z=1e-6, far_z=1e5)
+    run_forward(R, sc)
+    first = _check_binning(R, sc, (16, 16))
+    if case == "second_sort":
+        R.bin_sort()
+        torch.cuda.synchronize()
+        again = _check_binning(R, sc, (16, 16))
+        for k in ("keys", "sorted_slot", "slot_pairoff"):
+            assert np.array_equal(first[k].numpy(), again[k].numpy()), k
+
+
 @pytest.mark.parametrize("name", ["c1", "tiny", "tiny_bg"])
 def test_render_forward_matches_oracle(name):
     sc = _scene(name)
