@@ -344,7 +344,9 @@ kgs_status kgs_head_adam(float* theta, float* m, float* v, const float* grad, in
 /* The whole chunk as described by kgs_chunk_desc. */
 kgs_status kgs_chunk_run(kgs_ctx* ctx, const kgs_chunk_desc* desc, void* stream);
 
-/* Record kgs_chunk_run into a HIP graph (stream capture) and launch it. */
+/* Record kgs_chunk_run into a HIP graph (stream capture) and launch it.  The
+ * graph refers to ctx's workspace and state: destroy it before ctx, and run
+ * no other work of ctx concurrently with a launch. */
 kgs_status kgs_chunk_capture(kgs_ctx* ctx, const kgs_chunk_desc* desc, kgs_graph** out);
 kgs_status kgs_chunk_launch(kgs_graph* graph, void* stream);
 kgs_status kgs_graph_destroy(kgs_graph* graph);

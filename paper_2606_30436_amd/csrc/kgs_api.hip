@@ -149,6 +149,7 @@ bool image_ok(const kgs_image* im) { return im && im->color && im->depth && im->
 struct kgs_graph {
   hipGraph_t graph;
   hipGraphExec_t exec;
+  kgs_ctx* ctx;
 };
 
 extern "C" {
@@ -418,12 +419,16 @@ kgs_status kgs_chunk_capture(kgs_ctx* ctx, const kgs_chunk_desc* d, kgs_graph** 
     return s;
   }
   g->graph = graph;
+  g->ctx = ctx;
   *out = g;
   return KGS_OK;
 }
 
 kgs_status kgs_chunk_launch(kgs_graph* g, void* stream) {
   if (!g) return KGS_ERR_INVALID_ARG;
+  // the graph's own sort uses the depth keys its projection writes: a later
+  // sort outside the graph builds them again
+  g->ctx->slot_keys_ready = 0;
   return hipGraphLaunch(g->exec, (hipStream_t)stream) == hipSuccess ? KGS_OK : KGS_ERR_HIP;
 }
 
