@@ -278,3 +278,30 @@ def test_degenerate_inputs():
     ns, npairs = R.counts()
     assert ns == 2 and npairs >= ns
     assert torch.isfinite(b.grads.means).all()
+
+
+def test_eager_sort_after_a_graph_launch():
+    """An eager projection, a graph launch (its sort uses the depth keys its
+    own projection wrote), then an eager sort: the eager sort must build its
+    keys again and give the lists of a fresh projection and sort.  Depths in
+    one octave and one view make the keys 23 bits, three radix passes, so a
+    consumed key buffer would hold pair offsets, not keys."""
+    sc = scenes.tiny_scene(seed=8, n=300, degree=1, W=96, H=64, n_views=1, depth=(1.6, 2.8))
+    say("[gpu] eager sort after a graph launch")
+    R = Rasterizer(sc.width, sc.height, max_views=1, max_gaussians=sc.n, pair_capacity=1 << 16, near_z=1.5,
+                   far_z=2.9)
+    b = Bufs(sc, R)
+    graph = R.chunk_capture(b.desc())
+    R.project(b.g, b.cams, b.xi)
+    R.chunk_launch(graph)
+    R.bin_sort()
+    torch.cuda.synchronize()
+    assert R.status() == 0
+    got = R.buffers()
+    assert got["n_pairs"] > 100
+    R.project(b.g, b.cams, b.xi)
+    R.bin_sort()
+    torch.cuda.synchronize()
+    ref = R.buffers()
+    for k in ("keys", "sorted_slot", "slot_pairoff"):
+        assert np.array_equal(got[k].numpy(), ref[k].numpy()), k
