@@ -135,7 +135,13 @@ __device__ __forceinline__ void seg_window(SegWindow& W, uint32_t w, uint32_t np
   const bool started = sst > 0 || s != W.s_before;   // the slot's first pair lies in this window
   if (tail) {
     if (started) {
-      store_sum(slot_sum + (size_t)s * (KGS_SLOT_WORDS / 4), W.x);
+      // a segment that ends in a window without written pairs lies wholly in
+      // it: its slot blended nowhere, and the chain rule's split reads only the
+      // counts of such a slot
+      if (W.any)
+        store_sum(slot_sum + (size_t)s * (KGS_SLOT_WORDS / 4), W.x);
+      else
+        slot_sum[(size_t)s * (KGS_SLOT_WORDS / 4) + 2] = make_float4(0.f, 0.f, 0.f, 0.f);
     } else {
       put_rec(seg_head + (size_t)w * 4, W.x, s, 1u);  // continued from before, ends here
     }
