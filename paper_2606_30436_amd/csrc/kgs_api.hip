@@ -93,6 +93,7 @@ size_t layout(const kgs_config& c, char* base, kgs_ctx* ctx) {
   p = take(64 * (P / 64 + 2));                  if (ctx) ctx->seg_tail = (float4*)p;
   p = take(24 * S);                             if (ctx) ctx->slot_pose = (float2*)p;
   p = take(4 * S);                              if (ctx) ctx->slot_live = (uint32_t*)p;
+  p = take(4 * S);                              if (ctx) ctx->slot_om = (uint32_t*)p;
   p = take(4 * (P / 2048 + 2));                 if (ctx) ctx->chunk_first = (uint32_t*)p;
   {
     const int64_t st = std::max(kgs_scan_tiles(V * nb), kgs_scan_tiles(S / 64 + 2)) + 1;

@@ -99,6 +99,7 @@ struct kgs_ctx {
   float4* seg_tail;                   // [P / 64 + 1][4] and its last segment's
   float2* slot_pose;                  // [S][3] pose contributions (rho, phi) of every slot
   uint32_t* slot_live;                // [S] slots whose pixels blended somewhere, for the chain rule
+  uint32_t* slot_om;                  // [S] pixels the slot blended (|Omega|), 0 until a backward sums them
   uint32_t* chunk_first;              // [P / 2048 + 2] record owning the first pair of each emission chunk
   int slot_keys_ready;                // the projection wrote the depth-sort keys; no sort has used them yet
   unsigned long long* scan_part;      // tile sums of the device-wide scans

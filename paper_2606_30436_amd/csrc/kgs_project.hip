@@ -185,7 +185,7 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_emit(kgs_gaussians g, const CamDe
                                                     float4* __restrict__ slot_rec, uint32_t* __restrict__ slot_gid,
                                                     uint32_t* __restrict__ slot_view, int4* __restrict__ slot_pix,
                                                     uint32_t* __restrict__ slot_ntiles, void* __restrict__ slot_keys,
-                                                    uint32_t* __restrict__ slot_vals) {
+                                                    uint32_t* __restrict__ slot_vals, uint32_t* __restrict__ slot_om) {
   constexpr int K = (DEG + 1) * (DEG + 1);
   // visible lanes of each wave, per view: a slot's index is the (view, block)
   // base plus the visible lanes before it (one barrier for all views)
@@ -244,6 +244,7 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_emit(kgs_gaussians g, const CamDe
     slot_view[s] = (uint32_t)v;
     slot_pix[s] = pix;
     slot_ntiles[s] = tiles;
+    slot_om[s] = 0u;   // no pixel blended yet (the backward's sums set it)
     // the record's (view, depth) key for the depth sort, from its depth r1.z
     const uint32_t db = __float_as_uint(r1.z);
     const uint32_t dmax = P.depth_bits >= 32 ? 0xffffffffu : (1u << P.depth_bits) - 1u;
@@ -314,7 +315,7 @@ kgs_status kgs_launch_project(kgs_ctx* ctx, const kgs_gaussians* g, const kgs_ca
   hipLaunchKernelGGL(k_emit<D>, dim3((unsigned)nb), dim3(KGS_BLOCK), 0, st, *g, (const CamDev*)ctx->cams, V, P,   \
                      ctx->vis, (const uint32_t*)ctx->blk_base, nb, (uint64_t)cfg.slot_capacity,                \
                      ctx->slot_rec, ctx->slot_gid, ctx->slot_view, ctx->slot_pix, ctx->slot_ntiles,            \
-                     (void*)ctx->slot_keys[0], ctx->slot_vals[0])
+                     (void*)ctx->slot_keys[0], ctx->slot_vals[0], ctx->slot_om)
     switch (g->sh_degree) {
       case 0: KGS_EMIT(0); break;
       case 1: KGS_EMIT(1); break;

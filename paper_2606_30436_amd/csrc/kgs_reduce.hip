@@ -1,8 +1,8 @@
 // Backward of the projection, deterministic throughout:
 //   k_pair_segsum   per slot, the sum of its pairs' gradient records (they
 //   k_pair_fixup    are contiguous in emission order), segmented by slot;
-//   k_slot_split    per slot: one that blended in no pixel gets its (zero)
-//                   record at once, the others are queued;
+//   k_slot_split    queues the slots that blended in some pixel (the others
+//                   have zero sums, and slot_om tells the later kernels so);
 //   k_slot_live     per queued slot, from its pair sum, the chain rule to the
 //                   Gaussian's parameters and to the view's pose, and the
 //                   view's footprint statistics, as one 96-byte record;
@@ -113,8 +113,8 @@ __device__ __forceinline__ void seg_load(SegWindow& W, uint32_t w, uint32_t np, 
 }
 
 __device__ __forceinline__ void seg_window(SegWindow& W, uint32_t w, uint32_t np, int l,
-                                           float4* __restrict__ slot_sum, float4* __restrict__ seg_head,
-                                           float4* __restrict__ seg_tail) {
+                                           float4* __restrict__ slot_sum, uint32_t* __restrict__ slot_om,
+                                           float4* __restrict__ seg_head, float4* __restrict__ seg_tail) {
   const uint32_t s = W.s;
   const bool valid = w * 64 + (uint32_t)l < np;
   // both shuffles run in every lane (a lane-conditional shuffle reads 0
@@ -136,12 +136,10 @@ __device__ __forceinline__ void seg_window(SegWindow& W, uint32_t w, uint32_t np
   if (tail) {
     if (started) {
       // a segment that ends in a window without written pairs lies wholly in
-      // it: its slot blended nowhere, and the chain rule's split reads only the
-      // counts of such a slot
-      if (W.any)
-        store_sum(slot_sum + (size_t)s * (KGS_SLOT_WORDS / 4), W.x);
-      else
-        slot_sum[(size_t)s * (KGS_SLOT_WORDS / 4) + 2] = make_float4(0.f, 0.f, 0.f, 0.f);
+      // it: its slot blended nowhere, and only its count is stored (nothing
+      // reads the sums of such a slot)
+      if (W.any) store_sum(slot_sum + (size_t)s * (KGS_SLOT_WORDS / 4), W.x);
+      slot_om[s] = W.any ? (uint32_t)W.x[10] : 0u;
     } else {
       put_rec(seg_head + (size_t)w * 4, W.x, s, 1u);  // continued from before, ends here
     }
@@ -159,8 +157,8 @@ __global__ __launch_bounds__(256) void k_pair_segsum(const uint32_t* __restrict_
                                                      const uint32_t* __restrict__ pair_slot,
                                                      const float4* __restrict__ pair_grad,
                                                      const uint8_t* __restrict__ pair_live,
-                                                     float4* __restrict__ slot_sum, float4* __restrict__ seg_head,
-                                                     float4* __restrict__ seg_tail) {
+                                                     float4* __restrict__ slot_sum, uint32_t* __restrict__ slot_om,
+                                                     float4* __restrict__ seg_head, float4* __restrict__ seg_tail) {
   const uint32_t np = counters[1];
   const int l = threadIdx.x & 63;
   const uint32_t nwin = (np + 63) / 64;
@@ -170,8 +168,8 @@ __global__ __launch_bounds__(256) void k_pair_segsum(const uint32_t* __restrict_
     SegWindow A, B;
     seg_load(A, w0, np, l, pair_slot, pair_grad, pair_live);
     if (w1 < nwin) seg_load(B, w1, np, l, pair_slot, pair_grad, pair_live);
-    seg_window(A, w0, np, l, slot_sum, seg_head, seg_tail);
-    if (w1 < nwin) seg_window(B, w1, np, l, slot_sum, seg_head, seg_tail);
+    seg_window(A, w0, np, l, slot_sum, slot_om, seg_head, seg_tail);
+    if (w1 < nwin) seg_window(B, w1, np, l, slot_sum, slot_om, seg_head, seg_tail);
   }
 }
 
@@ -181,7 +179,8 @@ __global__ __launch_bounds__(256) void k_pair_segsum(const uint32_t* __restrict_
 __global__ __launch_bounds__(256) void k_pair_fixup(const uint32_t* __restrict__ counters,
                                                     const float4* __restrict__ seg_head,
                                                     const float4* __restrict__ seg_tail,
-                                                    float4* __restrict__ slot_sum, uint32_t* __restrict__ live_count) {
+                                                    float4* __restrict__ slot_sum, uint32_t* __restrict__ slot_om,
+                                                    uint32_t* __restrict__ live_count) {
   // the live-slot queue of the chain rule starts empty (nothing reads it before)
   if (blockIdx.x == 0 && threadIdx.x == 0) *live_count = 0u;
   const uint32_t np = counters[1];
@@ -206,6 +205,7 @@ __global__ __launch_bounds__(256) void k_pair_fixup(const uint32_t* __restrict__
       if (__float_as_uint(d.y) != 0u) break;
     }
     store_sum(slot_sum + (size_t)slot * (KGS_SLOT_WORDS / 4), x);
+    slot_om[slot] = (uint32_t)x[10];
   }
 }
 
@@ -426,36 +426,19 @@ __device__ __forceinline__ void slot_record(uint32_t s, uint32_t v, const kgs_ga
 }
 
 // Slots whose pixels blended nowhere have a zero sum (every pixel term is a
-// zero at alpha = 0), so zero gradients and pose terms, and the radius the
-// projection stored: k_slot_split writes those records at once and queues the
-// others (one atomic per wave; the queue's order does not matter, since every
-// result is written at its slot), and k_slot_live takes the queue with full
-// waves.  counters[KGS_CNT_LIVE] is cleared by k_pair_fixup.
+// zero at alpha = 0), so zero gradients and pose terms, and nothing reads their
+// records: the gather and the pose reduction look at slot_om first.
+// k_slot_split queues the others (one atomic per wave; the queue's order does
+// not matter, since every result is written at its slot), and k_slot_live
+// takes the queue with full waves.  counters[KGS_CNT_LIVE] is cleared by
+// k_pair_fixup.
 __global__ __launch_bounds__(KGS_BLOCK) void k_slot_split(uint32_t* __restrict__ counters,
-                                                          const uint32_t* __restrict__ slot_ntiles,
-                                                          const int4* __restrict__ slot_pix,
-                                                          float4* __restrict__ slot_bwd,
-                                                          float2* __restrict__ slot_pose,
+                                                          const uint32_t* __restrict__ slot_om,
                                                           uint32_t* __restrict__ slot_live) {
   const uint32_t n_slots = counters[0];
   const int l = threadIdx.x & 63;
   for (uint32_t s = blockIdx.x * KGS_BLOCK + threadIdx.x; s < n_slots; s += gridDim.x * KGS_BLOCK) {
-    float4* q = slot_bwd + (size_t)s * (KGS_SLOT_WORDS / 4);
-    // a slot without pairs has no segment and so no sum written
-    const bool any = slot_ntiles[s] != 0u;
-    const bool live = any && __float_as_uint(q[2].z) != 0u;
-    if (!live) {
-      // words 16-23 (counts, gradient norm, radius, colour gradient): the
-      // gather reads no other word of a slot that blended nowhere
-      const int4 pix = slot_pix[s];
-      const int rad = any ? max(pix.z, pix.w) : 0;
-      q[4] = make_float4(0.f, 0.f, 0.f, 0.f);
-      q[5] = make_float4(__int_as_float(rad), 0.f, 0.f, 0.f);
-      float2* p2 = slot_pose + (size_t)s * 3;
-      p2[0] = make_float2(0.f, 0.f);
-      p2[1] = make_float2(0.f, 0.f);
-      p2[2] = make_float2(0.f, 0.f);
-    }
+    const bool live = slot_om[s] != 0u;
     const uint64_t bal = ballot64(live);
     if (bal != 0ull) {
       const int leader = __ffsll((long long)bal) - 1;
@@ -506,6 +489,8 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_gauss_gather(kgs_gaussians g, int
                                                             const uint32_t* __restrict__ vis,
                                                             const uint32_t* __restrict__ counters,
                                                             const float4* __restrict__ slot_bwd,
+                                                            const uint32_t* __restrict__ slot_om,
+                                                            const int4* __restrict__ slot_pix,
                                                             const float* __restrict__ view_loss, kgs_grads gr,
                                                             kgs_view_stats st, int overwrite) {
   constexpr int K = (DEG + 1) * (DEG + 1);
@@ -531,14 +516,19 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_gauss_gather(kgs_gaussians g, int
   for (int v = 0; v < V; ++v) {
     const uint32_t u = vis[(int64_t)v * n + i];
     if (u == 0u || u > n_slots) continue;
+    s_vc += 1u;
+    if (slot_om[u - 1u] == 0u) {
+      // a slot that blended nowhere adds nothing but its radius, which the
+      // projection stored (every slot has a tile, so the radius stands)
+      const int4 pix = slot_pix[u - 1u];
+      s_mr = max(s_mr, max(pix.z, pix.w));
+      continue;
+    }
     const float4* r4 = slot_bwd + (size_t)(u - 1u) * (KGS_SLOT_WORDS / 4);
-    // words 16-23 first: counts, gradient norm, radius, masked colour gradient
+    // words 16-23: counts, gradient norm, radius, masked colour gradient
     const float4 q4 = r4[4], q5 = r4[5];
     const uint32_t om = __float_as_uint(q4.y);
-    s_vc += 1u;
     s_mr = max(s_mr, __float_as_int(q5.x));
-    // a slot that blended nowhere holds zeros everywhere else
-    if (om == 0u) continue;
     float r[16];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -615,6 +605,7 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_gauss_gather(kgs_gaussians g, int
 __global__ __launch_bounds__(256) void k_pose_reduce(const uint32_t* __restrict__ counters,
                                                      const uint32_t* __restrict__ blk_base, int64_t nb, int V,
                                                      const float2* __restrict__ slot_pose,
+                                                     const uint32_t* __restrict__ slot_om,
                                                      double* __restrict__ partial) {
   __shared__ double sh[4][6];
   const int v = blockIdx.y, b = blockIdx.x, tid = threadIdx.x;
@@ -627,6 +618,7 @@ __global__ __launch_bounds__(256) void k_pose_reduce(const uint32_t* __restrict_
   const uint32_t a = lo + b * per, e = min(hi, a + per);
   double acc[6] = {0, 0, 0, 0, 0, 0};
   for (uint32_t s = a + tid; s < e; s += 256) {
+    if (slot_om[s] == 0u) continue;   // no pose terms (and none written)
     const float2* p2 = slot_pose + (size_t)s * 3;
     const float2 a = p2[0], b = p2[1], c = p2[2];
     acc[0] += a.x; acc[1] += a.y; acc[2] += b.x; acc[3] += b.y; acc[4] += c.x; acc[5] += c.y;
@@ -693,14 +685,13 @@ kgs_status kgs_launch_project_bwd(kgs_ctx* ctx, const kgs_gaussians* g, const kg
     const unsigned wg = (unsigned)std::min<uint64_t>(std::max<uint64_t>((wins + 7) / 8, 1), 4096);
     hipLaunchKernelGGL(k_pair_segsum, dim3(wg), dim3(256), 0, st, (const uint32_t*)ctx->counters,
                        (const uint32_t*)ctx->pair_slot, (const float4*)ctx->pair_grad,
-                       (const uint8_t*)ctx->pair_live, ctx->slot_bwd, ctx->seg_head,
+                       (const uint8_t*)ctx->pair_live, ctx->slot_bwd, ctx->slot_om, ctx->seg_head,
                        ctx->seg_tail);
     hipLaunchKernelGGL(k_pair_fixup, dim3((unsigned)std::min<uint64_t>(std::max<uint64_t>((wins + 255) / 256, 1), 2048)),
                        dim3(256), 0, st, (const uint32_t*)ctx->counters, (const float4*)ctx->seg_head,
-                       (const float4*)ctx->seg_tail, ctx->slot_bwd, ctx->counters + KGS_CNT_LIVE);
+                       (const float4*)ctx->seg_tail, ctx->slot_bwd, ctx->slot_om, ctx->counters + KGS_CNT_LIVE);
     hipLaunchKernelGGL(k_slot_split, dim3(sg), dim3(KGS_BLOCK), 0, st, ctx->counters,
-                       (const uint32_t*)ctx->slot_ntiles, (const int4*)ctx->slot_pix, ctx->slot_bwd, ctx->slot_pose,
-                       ctx->slot_live);
+                       (const uint32_t*)ctx->slot_om, ctx->slot_live);
 #define KGS_PB(D)                                                                                                  \
   hipLaunchKernelGGL(k_slot_live<D>, dim3(sg), dim3(KGS_BLOCK), 0, st, *g, (const CamDev*)ctx->cams, P,            \
                      (const uint32_t*)ctx->counters, (const uint32_t*)ctx->slot_live,                               \
@@ -708,8 +699,8 @@ kgs_status kgs_launch_project_bwd(kgs_ctx* ctx, const kgs_gaussians* g, const kg
                      (const uint32_t*)ctx->slot_ntiles, ctx->slot_bwd, ctx->slot_pose);                            \
   hipLaunchKernelGGL(k_gauss_gather<D>, dim3((unsigned)nb), dim3(KGS_BLOCK), 0, st, *g, V,                        \
                      (const CamDev*)ctx->cams, (const uint32_t*)ctx->vis, (const uint32_t*)ctx->counters,          \
-                     (const float4*)ctx->slot_bwd,                                                                \
-                     view_loss, G, S, overwrite ? 1 : 0)
+                     (const float4*)ctx->slot_bwd, (const uint32_t*)ctx->slot_om,                                \
+                     (const int4*)ctx->slot_pix, view_loss, G, S, overwrite ? 1 : 0)
     switch (g->sh_degree) {
       case 0: KGS_PB(0); break;
       case 1: KGS_PB(1); break;
@@ -719,7 +710,8 @@ kgs_status kgs_launch_project_bwd(kgs_ctx* ctx, const kgs_gaussians* g, const kg
 #undef KGS_PB
     if (G.pose_xi) {
       hipLaunchKernelGGL(k_pose_reduce, dim3(KGS_POSE_BLOCKS, V), dim3(256), 0, st, (const uint32_t*)ctx->counters,
-                         (const uint32_t*)ctx->blk_base, nb, V, (const float2*)ctx->slot_pose, ctx->pose_partial);
+                         (const uint32_t*)ctx->blk_base, nb, V, (const float2*)ctx->slot_pose,
+                         (const uint32_t*)ctx->slot_om, ctx->pose_partial);
       hipLaunchKernelGGL(k_pose_final, dim3(V), dim3(KGS_POSE_BLOCKS), 0, st, (const double*)ctx->pose_partial,
                          (const CamDev*)ctx->cams, G.pose_xi, overwrite ? 1 : 0);
     }
