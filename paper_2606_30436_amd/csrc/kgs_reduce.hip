@@ -435,18 +435,27 @@ __device__ __forceinline__ void slot_record(uint32_t s, uint32_t v, const kgs_ga
 __global__ __launch_bounds__(KGS_BLOCK) void k_slot_split(uint32_t* __restrict__ counters,
                                                           const uint32_t* __restrict__ slot_om,
                                                           uint32_t* __restrict__ slot_live) {
+  // a wave takes 512 consecutive slots, eight per lane, and claims its share of
+  // the queue with one atomic
   const uint32_t n_slots = counters[0];
   const int l = threadIdx.x & 63;
-  for (uint32_t s = blockIdx.x * KGS_BLOCK + threadIdx.x; s < n_slots; s += gridDim.x * KGS_BLOCK) {
-    const bool live = slot_om[s] != 0u;
-    const uint64_t bal = ballot64(live);
-    if (bal != 0ull) {
-      const int leader = __ffsll((long long)bal) - 1;
-      uint32_t base = 0u;
-      if (l == leader) base = atomicAdd(&counters[KGS_CNT_LIVE], (uint32_t)__popcll(bal));
-      base = (uint32_t)__shfl((int)base, leader, 64);
-      if (live) slot_live[base + mask_lt_count(bal)] = s;
-    }
+  const uint32_t waves = gridDim.x * (KGS_BLOCK / 64);
+  for (uint32_t wb = (blockIdx.x * (KGS_BLOCK / 64) + (threadIdx.x >> 6)) * 512u; wb < n_slots; wb += waves * 512u) {
+    const uint32_t s0 = wb + (uint32_t)l * 8u;
+    uint32_t m = 0u;
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (s0 + k < n_slots && slot_om[s0 + k] != 0u) m |= 1u << k;
+    const uint32_t c = (uint32_t)__popc(m);
+    const uint32_t inc = wave_inclusive_scan(c);
+    const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
+    if (tot == 0u) continue;
+    uint32_t base = 0u;
+    if (l == 0) base = atomicAdd(&counters[KGS_CNT_LIVE], tot);
+    uint32_t pos = (uint32_t)__shfl((int)base, 0, 64) + inc - c;
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if ((m >> k) & 1u) slot_live[pos++] = s0 + k;
   }
 }
 
