@@ -355,6 +355,9 @@ kgs_status kgs_graph_destroy(kgs_graph* graph);
 kgs_status kgs_status_read(kgs_ctx* ctx, uint32_t* flags);
 kgs_status kgs_status_clear(kgs_ctx* ctx, void* stream);
 kgs_status kgs_counts_read(kgs_ctx* ctx, int64_t* n_slots, int64_t* n_pairs);
+/* Device pointers into the workspace (valid until the next call on ctx).  It
+ * first fills the slot_pairoff view from the records on the null stream and
+ * waits for the device. */
 kgs_status kgs_get_buffers(kgs_ctx* ctx, kgs_buffers* out);
 
 const char* kgs_status_string(kgs_status s);

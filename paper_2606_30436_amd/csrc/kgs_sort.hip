@@ -246,14 +246,13 @@ __global__ __launch_bounds__(256) void k_group_sum(const uint32_t* __restrict__ 
 
 // First pair of every record in depth order: pref[j] = part[g] + the exclusive
 // scan of the tile counts inside the 64-record group g = j / 64; the same value
-// is the record's slot_pairoff.  A record whose pairs hold the first pair of an
+// goes into the record's fourth float4.  A record whose pairs hold the first pair of an
 // emission chunk also names itself the chunk's first record.
 __global__ __launch_bounds__(256) void k_slot_offsets(const uint32_t* __restrict__ counters,
                                                       const uint32_t* __restrict__ perm,
                                                       const uint32_t* __restrict__ part, uint32_t n_groups,
                                                       const uint32_t* __restrict__ ntiles, uint64_t pair_cap,
                                                       uint32_t* __restrict__ pref,
-                                                      uint32_t* __restrict__ slot_pairoff,
                                                       float4* __restrict__ slot_rec,
                                                       uint32_t* __restrict__ chunk_first) {
   const uint32_t n = counters[0];
@@ -268,8 +267,8 @@ __global__ __launch_bounds__(256) void k_slot_offsets(const uint32_t* __restrict
     const uint64_t off = min((uint64_t)part[g] + (incl - c), pair_cap);
     if (j < n) {
       pref[j] = (uint32_t)off;
-      slot_pairoff[s] = (uint32_t)off;
-      // also in the record's last 16 bytes, read with the record by the backward
+      // the record's last 16 bytes, read with the record by the backward (the
+      // debug view slot_pairoff is copied from here on request)
       slot_rec[(size_t)s * 4 + 3] = make_float4(__uint_as_float((uint32_t)off), 0.f, 0.f, 0.f);
       const uint64_t e = min(off + (uint64_t)c, pair_cap);
       for (uint64_t b = (off + EP_CHUNK - 1) / EP_CHUNK; b * EP_CHUNK < e; ++b) chunk_first[b] = j;
@@ -411,6 +410,23 @@ __global__ __launch_bounds__(256) void k_emit_pairs(const uint32_t* __restrict__
   }
 }
 
+// slot_pairoff[s]: the first pair of record s, copied from the record
+__global__ __launch_bounds__(256) void k_pairoff_copy(const uint32_t* __restrict__ counters,
+                                                      const float4* __restrict__ slot_rec,
+                                                      uint32_t* __restrict__ slot_pairoff) {
+  const uint32_t n = counters[0];
+  for (uint32_t s = blockIdx.x * 256 + threadIdx.x; s < n; s += gridDim.x * 256)
+    slot_pairoff[s] = __float_as_uint(slot_rec[(size_t)s * 4 + 3].x);
+}
+
+kgs_status kgs_launch_pairoff_copy(kgs_ctx* ctx, hipStream_t st) {
+  const uint64_t S = (uint64_t)ctx->cfg.slot_capacity;
+  hipLaunchKernelGGL(k_pairoff_copy, dim3((unsigned)std::min<uint64_t>(std::max<uint64_t>((S + 255) / 256, 1), 4096)),
+                     dim3(256), 0, st, (const uint32_t*)ctx->counters, (const float4*)ctx->slot_rec,
+                     ctx->slot_pairoff);
+  return kgs_check_launch();
+}
+
 __global__ void k_fill_u32(uint32_t* __restrict__ p, uint64_t n, uint32_t v) {
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
     p[i] = v;
@@ -539,7 +555,7 @@ kgs_status kgs_launch_bin_sort(kgs_ctx* ctx, hipStream_t st) {
   uint32_t* pref = reinterpret_cast<uint32_t*>(ctx->slot_keys[sc ^ 1]);  // free after the record sort
   hipLaunchKernelGGL(k_slot_offsets, dim3(eg), dim3(256), 0, st, (const uint32_t*)ctx->counters, perm,
                      (const uint32_t*)ctx->group_part, n_groups, (const uint32_t*)ctx->slot_ntiles, P, pref,
-                     ctx->slot_pairoff, ctx->slot_rec, ctx->chunk_first);
+                     ctx->slot_rec, ctx->chunk_first);
   const uint64_t chunks = (P + EP_CHUNK - 1) / EP_CHUNK;
   const unsigned pg = (unsigned)std::min<uint64_t>(std::max<uint64_t>(chunks, 1), 4096);
   hipLaunchKernelGGL(k_emit_pairs, dim3(pg), dim3(256), 0, st, (const uint32_t*)ctx->counters, perm,
