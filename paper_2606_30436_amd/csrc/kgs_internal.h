@@ -101,6 +101,7 @@ struct kgs_ctx {
   uint32_t* slot_live;                // [S] slots whose pixels blended somewhere, for the chain rule
   uint32_t* slot_om;                  // [S] pixels the slot blended (|Omega|), 0 until a backward sums them
   uint32_t* chunk_first;              // [P / 2048 + 2] record owning the first pair of each emission chunk
+  uint4* emit_rec;                    // [S] emission descriptor of each record, in depth order
   int slot_keys_ready;                // the projection wrote the depth-sort keys; no sort has used them yet
   unsigned long long* scan_part;      // tile sums of the device-wide scans
   unsigned long long* scan_totals;    // [2] their totals

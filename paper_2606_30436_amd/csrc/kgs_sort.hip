@@ -224,6 +224,41 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t* __restric
 #define EP_PPT 8
 #define EP_CHUNK (256 * EP_PPT)
 
+struct EmitSlot {
+  uint32_t s, gbase;
+  int x0, y0, rw;
+};
+
+__device__ __forceinline__ EmitSlot emit_slot(uint32_t s, const uint32_t* __restrict__ slot_view,
+                                              const int4* __restrict__ slot_pix, int tile_w, int tile_h,
+                                              int tiles_x, uint32_t tiles_per_view) {
+  const int4 pix = slot_pix[s];
+  EmitSlot e;
+  e.s = s;
+  e.x0 = max(floordiv_i(pix.x - pix.z, tile_w), 0);
+  const int x1 = min(floordiv_i(pix.x + pix.z, tile_w) + 1, tiles_x);
+  e.y0 = max(floordiv_i(pix.y - pix.w, tile_h), 0);
+  e.rw = max(x1 - e.x0, 1);
+  e.gbase = slot_view[s] * tiles_per_view;
+  return e;
+}
+
+// A record's emission descriptor, packed: slot, its view's first global tile,
+// the first tile column and row of its rectangle (16 bits each) and the
+// rectangle's width in tiles.
+__device__ __forceinline__ uint4 pack_emit(const EmitSlot& e) {
+  return make_uint4(e.s, e.gbase, (uint32_t)e.x0 | ((uint32_t)e.y0 << 16), (uint32_t)e.rw);
+}
+__device__ __forceinline__ EmitSlot unpack_emit(uint4 q) {
+  EmitSlot e;
+  e.s = q.x;
+  e.gbase = q.y;
+  e.x0 = (int)(q.z & 0xffffu);
+  e.y0 = (int)(q.z >> 16);
+  e.rw = (int)q.w;
+  return e;
+}
+
 // ---------------------------------------------------------------- group scan
 // The depth-sorted slots are cut into groups of 64; a group's pairs are
 // contiguous.  k_group_sum: tile count of every group (one wave per group);
@@ -246,15 +281,20 @@ __global__ __launch_bounds__(256) void k_group_sum(const uint32_t* __restrict__ 
 
 // First pair of every record in depth order: pref[j] = part[g] + the exclusive
 // scan of the tile counts inside the 64-record group g = j / 64; the same value
-// goes into the record's fourth float4.  A record whose pairs hold the first pair of an
-// emission chunk also names itself the chunk's first record.
+// goes into the record's fourth float4.  A record whose pairs hold the first
+// pair of an emission chunk also names itself the chunk's first record, and
+// every record leaves its emission descriptor at its depth-order position.
 __global__ __launch_bounds__(256) void k_slot_offsets(const uint32_t* __restrict__ counters,
                                                       const uint32_t* __restrict__ perm,
                                                       const uint32_t* __restrict__ part, uint32_t n_groups,
                                                       const uint32_t* __restrict__ ntiles, uint64_t pair_cap,
                                                       uint32_t* __restrict__ pref,
                                                       float4* __restrict__ slot_rec,
-                                                      uint32_t* __restrict__ chunk_first) {
+                                                      uint32_t* __restrict__ chunk_first,
+                                                      const uint32_t* __restrict__ slot_view,
+                                                      const int4* __restrict__ slot_pix, int tile_w, int tile_h,
+                                                      int tiles_x, uint32_t tiles_per_view,
+                                                      uint4* __restrict__ emit_rec) {
   const uint32_t n = counters[0];
   const uint32_t l = threadIdx.x & 63;
   const uint32_t waves = gridDim.x * 4;
@@ -272,6 +312,7 @@ __global__ __launch_bounds__(256) void k_slot_offsets(const uint32_t* __restrict
       slot_rec[(size_t)s * 4 + 3] = make_float4(__uint_as_float((uint32_t)off), 0.f, 0.f, 0.f);
       const uint64_t e = min(off + (uint64_t)c, pair_cap);
       for (uint64_t b = (off + EP_CHUNK - 1) / EP_CHUNK; b * EP_CHUNK < e; ++b) chunk_first[b] = j;
+      emit_rec[j] = pack_emit(emit_slot(s, slot_view, slot_pix, tile_w, tile_h, tiles_x, tiles_per_view));
     }
   }
 }
@@ -314,37 +355,15 @@ __device__ __forceinline__ uint32_t udiv_small(uint32_t a, uint32_t b) {
   return q;
 }
 
-struct EmitSlot {
-  uint32_t s, gbase;
-  int x0, y0, rw;
-};
-
-__device__ __forceinline__ EmitSlot emit_slot(uint32_t s, const uint32_t* __restrict__ slot_view,
-                                              const int4* __restrict__ slot_pix, int tile_w, int tile_h,
-                                              int tiles_x, uint32_t tiles_per_view) {
-  const int4 pix = slot_pix[s];
-  EmitSlot e;
-  e.s = s;
-  e.x0 = max(floordiv_i(pix.x - pix.z, tile_w), 0);
-  const int x1 = min(floordiv_i(pix.x + pix.z, tile_w) + 1, tiles_x);
-  e.y0 = max(floordiv_i(pix.y - pix.w, tile_h), 0);
-  e.rw = max(x1 - e.x0, 1);
-  e.gbase = slot_view[s] * tiles_per_view;
-  return e;
-}
-
 __global__ __launch_bounds__(256) void k_emit_pairs(const uint32_t* __restrict__ counters,
-                                                    const uint32_t* __restrict__ perm,
+                                                    const uint4* __restrict__ emit_rec,
                                                     const uint32_t* __restrict__ pref,
                                                     const uint32_t* __restrict__ chunk_first,
-                                                    const uint32_t* __restrict__ slot_view,
-                                                    const int4* __restrict__ slot_pix, int tile_w, int tile_h,
                                                     int tiles_x, int tiles_y, uint32_t* __restrict__ keys,
                                                     uint32_t* __restrict__ vals) {
   __shared__ uint32_t s_pref[EP_CHUNK + 1];
   const uint32_t n = counters[0], np = counters[1];
   const int tid = threadIdx.x;
-  const uint32_t tiles_per_view = (uint32_t)(tiles_x * tiles_y);
   const uint64_t nchunks = ((uint64_t)np + EP_CHUNK - 1) / EP_CHUNK;
   for (uint64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
     const uint64_t P0 = c * EP_CHUNK;
@@ -367,7 +386,7 @@ __global__ __launch_bounds__(256) void k_emit_pairs(const uint32_t* __restrict__
         if (s_pref[mid] <= pa) a = mid; else b = mid;
       }
       uint32_t jj = a, first = s_pref[jj], next = s_pref[jj + 1];
-      EmitSlot e = emit_slot(perm[jlo + jj], slot_view, slot_pix, tile_w, tile_h, tiles_x, tiles_per_view);
+      EmitSlot e = unpack_emit(emit_rec[jlo + jj]);
       uint32_t ko[EP_PPT], vo[EP_PPT];
 #pragma unroll
       for (int i = 0; i < EP_PPT; ++i) {
@@ -381,7 +400,7 @@ __global__ __launch_bounds__(256) void k_emit_pairs(const uint32_t* __restrict__
               first = next;
               next = s_pref[jj + 1];
             }
-            e = emit_slot(perm[jlo + jj], slot_view, slot_pix, tile_w, tile_h, tiles_x, tiles_per_view);
+            e = unpack_emit(emit_rec[jlo + jj]);
           }
           const uint32_t rk = p - first;
           const uint32_t qy = udiv_small(rk, (uint32_t)e.rw);
@@ -555,12 +574,13 @@ kgs_status kgs_launch_bin_sort(kgs_ctx* ctx, hipStream_t st) {
   uint32_t* pref = reinterpret_cast<uint32_t*>(ctx->slot_keys[sc ^ 1]);  // free after the record sort
   hipLaunchKernelGGL(k_slot_offsets, dim3(eg), dim3(256), 0, st, (const uint32_t*)ctx->counters, perm,
                      (const uint32_t*)ctx->group_part, n_groups, (const uint32_t*)ctx->slot_ntiles, P, pref,
-                     ctx->slot_rec, ctx->chunk_first);
+                     ctx->slot_rec, ctx->chunk_first, (const uint32_t*)ctx->slot_view, (const int4*)ctx->slot_pix,
+                     ctx->cfg.tile_w, ctx->cfg.tile_h, ctx->tiles_x, (uint32_t)ctx->n_tiles, ctx->emit_rec);
   const uint64_t chunks = (P + EP_CHUNK - 1) / EP_CHUNK;
   const unsigned pg = (unsigned)std::min<uint64_t>(std::max<uint64_t>(chunks, 1), 4096);
-  hipLaunchKernelGGL(k_emit_pairs, dim3(pg), dim3(256), 0, st, (const uint32_t*)ctx->counters, perm,
-                     (const uint32_t*)pref, (const uint32_t*)ctx->chunk_first, (const uint32_t*)ctx->slot_view, (const int4*)ctx->slot_pix,
-                     ctx->cfg.tile_w, ctx->cfg.tile_h, ctx->tiles_x, ctx->tiles_y, ctx->keys[0], ctx->pair_slot);
+  hipLaunchKernelGGL(k_emit_pairs, dim3(pg), dim3(256), 0, st, (const uint32_t*)ctx->counters,
+                     (const uint4*)ctx->emit_rec, (const uint32_t*)pref, (const uint32_t*)ctx->chunk_first,
+                     ctx->tiles_x, ctx->tiles_y, ctx->keys[0], ctx->pair_slot);
   // 3. pairs by tile (stable)
   // padding pairs carry key 0xffffffff; with n_tiles_all < 2^tile_bits they
   // sort after every real pair
