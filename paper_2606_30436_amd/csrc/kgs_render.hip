@@ -61,7 +61,8 @@ __global__ __launch_bounds__(64 * NW) void k_render_fwd(RenderParams P, const ui
                                                         const float4* __restrict__ slot_rec,
                                                         float* __restrict__ color, float* __restrict__ depth,
                                                         float* __restrict__ tfinal, int32_t* __restrict__ last) {
-  __shared__ float4 s_r0[NW][64], s_r1[NW][64], s_r2[NW][64];
+  // each kept record's three float4 side by side: one address, three offsets
+  __shared__ float4 s_rec[NW][64][3];
   __shared__ int s_pos[NW][64];
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
   const int gt = (int)tile_order[blockIdx.x];
@@ -102,15 +103,15 @@ __global__ __launch_bounds__(64 * NW) void k_render_fwd(RenderParams P, const ui
     const uint64_t bal = ballot64(keep);
     if (keep) {
       const uint32_t q = mask_lt_count(bal);
-      s_r0[w][q] = r0;
-      s_r1[w][q] = r1;
-      s_r2[w][q] = r2;
+      s_rec[w][q][0] = r0;
+      s_rec[w][q][1] = r1;
+      s_rec[w][q][2] = r2;
       s_pos[w][q] = (int)(k - start) + 1;
     }
     __builtin_amdgcn_wave_barrier();
     const uint32_t len = (uint32_t)__popcll(bal);
     auto blend = [&](uint32_t q, bool present) {
-      const float4 a0 = s_r0[w][q], a1 = s_r1[w][q], a2 = s_r2[w][q];
+      const float4 a0 = s_rec[w][q][0], a1 = s_rec[w][q][1], a2 = s_rec[w][q][2];
       float dy, u;
       const float e = log2_alpha(fpx, fpy, a0, a1.x, a1.y, dy, u);
       const bool hit = present && !done && e >= P.log2_amin;
@@ -372,7 +373,7 @@ __global__ __launch_bounds__(64 * NW) void k_render_bwd(
   constexpr int R = B >= 64 ? B / 64 : 1;
   static_assert(B == 32 || B == 64 || B == 128, "batch of 32, 64 or 128 records");
   // each wave's kept records of the batch, compacted, and their batch indices
-  __shared__ float4 s_r0[NW][B], s_r1[NW][B], s_r2[NW][B];
+  __shared__ float4 s_rec[NW][B][3];
   __shared__ __align__(16) uint8_t s_id[NW][B];
   __shared__ uint64_t s_keep[NW][R];
   __shared__ float s_part[NW][B][12];
@@ -481,9 +482,9 @@ __global__ __launch_bounds__(64 * NW) void k_render_bwd(
       const uint64_t bal = ballot64(keep);
       if (keep) {
         const uint32_t q = len + mask_lt_count(bal);
-        s_r0[w][q] = r0;
-        s_r1[w][q] = r1;
-        s_r2[w][q] = r2;
+        s_rec[w][q][0] = r0;
+        s_rec[w][q][1] = r1;
+        s_rec[w][q][2] = r2;
         s_id[w][q] = (uint8_t)bi;
       }
       if (l == 0) s_keep[w][r] = bal;
@@ -507,7 +508,7 @@ __global__ __launch_bounds__(64 * NW) void k_render_bwd(
       const int tb = entry(jb);
       const bool use_b = has_b && rel0 + tb < wmax;
       // both entries' records at once (the second is a repeat of the first when absent)
-      const float4 ra0 = s_r0[w][j], ra1 = s_r1[w][j], rb0 = s_r0[w][jb], rb1 = s_r1[w][jb];
+      const float4 ra0 = s_rec[w][j][0], ra1 = s_rec[w][j][1], rb0 = s_rec[w][jb][0], rb1 = s_rec[w][jb][1];
       float dya, ua, dyb, ub;
       const float ea = log2_alpha(fpx, fpy, ra0, ra1.x, ra1.y, dya, ua);
       const float eb = log2_alpha(fpx, fpy, rb0, rb1.x, rb1.y, dyb, ub);
@@ -516,7 +517,7 @@ __global__ __launch_bounds__(64 * NW) void k_render_bwd(
       const uint64_t bba = ballot64(bla), bbb = ballot64(blb);
       if (bba != 0ull && bbb != 0ull) {
         float x[20];
-        const float4 ra2 = s_r2[w][j], rb2 = s_r2[w][jb];
+        const float4 ra2 = s_rec[w][j][2], rb2 = s_rec[w][jb][2];
         blend_terms<DEPTH>(ea, ua, dya, bla, ra1, ra2, P.amax, g0, g1, g2, gD, T, Rj, x);
         blend_terms<DEPTH>(eb, ub, dyb, blb, rb1, rb2, P.amax, g0, g1, g2, gD, T, Rj, x + 10);
         const uint64_t bma = ballot64(bla && M), bmb = ballot64(blb && M);
@@ -536,7 +537,7 @@ __global__ __launch_bounds__(64 * NW) void k_render_bwd(
         const bool bl = first ? bla : blb;
         float x[10];
         blend_terms<DEPTH>(first ? ea : eb, first ? ua : ub, first ? dya : dyb, bl, first ? ra1 : rb1,
-                    s_r2[w][first ? j : jb], P.amax, g0, g1, g2, gD, T, Rj, x);
+                    s_rec[w][first ? j : jb][2], P.amax, g0, g1, g2, gD, T, Rj, x);
         const uint64_t bm = ballot64(bl && M);
         int idx;
         bool valid;
