@@ -431,6 +431,7 @@ __global__ __launch_bounds__(64 * NW) void k_render_bwd(
     }
   }
   if (fuse_l1) l1_partial<NW>(l1acc, s_loss, loss_partial, gt);
+  const uint64_t Mbal = ballot64(M);   // the error mask of the wave's pixels
   int wmax = lastp;
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) wmax = max(wmax, __shfl_xor(wmax, o, 64));
@@ -520,7 +521,7 @@ __global__ __launch_bounds__(64 * NW) void k_render_bwd(
         const float4 ra2 = s_rec[w][j][2], rb2 = s_rec[w][jb][2];
         blend_terms<DEPTH>(ea, ua, dya, bla, ra1, ra2, P.amax, g0, g1, g2, gD, T, Rj, x);
         blend_terms<DEPTH>(eb, ub, dyb, blb, rb1, rb2, P.amax, g0, g1, g2, gD, T, Rj, x + 10);
-        const uint64_t bma = ballot64(bla && M), bmb = ballot64(blb && M);
+        const uint64_t bma = bba & Mbal, bmb = bbb & Mbal;
         int idx;
         bool valid;
         wave_reduce20<DEPTH ? 10 : 9>(x, l, idx, valid);
@@ -538,7 +539,7 @@ __global__ __launch_bounds__(64 * NW) void k_render_bwd(
         float x[10];
         blend_terms<DEPTH>(first ? ea : eb, first ? ua : ub, first ? dya : dyb, bl, first ? ra1 : rb1,
                     s_rec[w][first ? j : jb][2], P.amax, g0, g1, g2, gD, T, Rj, x);
-        const uint64_t bm = ballot64(bl && M);
+        const uint64_t bm = (first ? bba : bbb) & Mbal;
         int idx;
         bool valid;
         wave_reduce10(x, l, idx, valid);
