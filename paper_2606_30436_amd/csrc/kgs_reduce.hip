@@ -428,20 +428,20 @@ __device__ __forceinline__ void slot_record(uint32_t s, uint32_t v, const kgs_ga
 // Slots whose pixels blended nowhere have a zero sum (every pixel term is a
 // zero at alpha = 0), so zero gradients and pose terms, and nothing reads their
 // records: the gather and the pose reduction look at slot_om first.
-// k_slot_split queues the others (one atomic per wave; the queue's order does
-// not matter, since every result is written at its slot), and k_slot_live
-// takes the queue with full waves.  counters[KGS_CNT_LIVE] is cleared by
+// k_slot_split queues the others (a wave claims the share of its 512 slots
+// with one atomic; the queue's order does not matter, since every result is
+// written at its slot), and k_slot_live takes the queue with full waves.  counters[KGS_CNT_LIVE] is cleared by
 // k_pair_fixup.
 __global__ __launch_bounds__(KGS_BLOCK) void k_slot_split(uint32_t* __restrict__ counters,
                                                           const uint32_t* __restrict__ slot_om,
                                                           uint32_t* __restrict__ slot_live) {
-  // a wave takes 512 consecutive slots, eight per lane, and claims its share of
-  // the queue with one atomic
+  // a wave takes 512 consecutive slots, eight per lane
   const uint32_t n_slots = counters[0];
   const int l = threadIdx.x & 63;
-  const uint32_t waves = gridDim.x * (KGS_BLOCK / 64);
-  for (uint32_t wb = (blockIdx.x * (KGS_BLOCK / 64) + (threadIdx.x >> 6)) * 512u; wb < n_slots; wb += waves * 512u) {
-    const uint32_t s0 = wb + (uint32_t)l * 8u;
+  const uint64_t waves = (uint64_t)gridDim.x * (KGS_BLOCK / 64);
+  for (uint64_t wb = ((uint64_t)blockIdx.x * (KGS_BLOCK / 64) + (threadIdx.x >> 6)) * 512u; wb < n_slots;
+       wb += waves * 512u) {
+    const uint64_t s0 = wb + (uint64_t)l * 8u;
     uint32_t m = 0u;
 #pragma unroll
     for (int k = 0; k < 8; ++k)
@@ -455,7 +455,7 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_slot_split(uint32_t* __restrict__
     uint32_t pos = (uint32_t)__shfl((int)base, 0, 64) + inc - c;
 #pragma unroll
     for (int k = 0; k < 8; ++k)
-      if ((m >> k) & 1u) slot_live[pos++] = s0 + k;
+      if ((m >> k) & 1u) slot_live[pos++] = (uint32_t)(s0 + k);
   }
 }
 

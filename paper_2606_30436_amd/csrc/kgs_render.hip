@@ -61,9 +61,10 @@ __global__ __launch_bounds__(64 * NW) void k_render_fwd(RenderParams P, const ui
                                                         const float4* __restrict__ slot_rec,
                                                         float* __restrict__ color, float* __restrict__ depth,
                                                         float* __restrict__ tfinal, int32_t* __restrict__ last) {
-  // each kept record's three float4 side by side: one address, three offsets
+  // each kept record's three float4 side by side: one address, three offsets;
+  // r1.w (the x-bounds, used only by the staging test) holds the record's
+  // position in the tile list, plus one
   __shared__ float4 s_rec[NW][64][3];
-  __shared__ int s_pos[NW][64];
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
   const int gt = (int)tile_order[blockIdx.x];
   const int v = gt / P.n_tiles, t = gt - v * P.n_tiles;
@@ -104,9 +105,8 @@ __global__ __launch_bounds__(64 * NW) void k_render_fwd(RenderParams P, const ui
     if (keep) {
       const uint32_t q = mask_lt_count(bal);
       s_rec[w][q][0] = r0;
-      s_rec[w][q][1] = r1;
+      s_rec[w][q][1] = make_float4(r1.x, r1.y, r1.z, __int_as_float((int)(k - start) + 1));
       s_rec[w][q][2] = r2;
-      s_pos[w][q] = (int)(k - start) + 1;
     }
     __builtin_amdgcn_wave_barrier();
     const uint32_t len = (uint32_t)__popcll(bal);
@@ -126,7 +126,7 @@ __global__ __launch_bounds__(64 * NW) void k_render_fwd(RenderParams P, const ui
       c2 = fmaf(wgt, a2.z, c2);
       D = fmaf(wgt, a1.z, D);
       T = take ? Tn : T;
-      lst = take ? s_pos[w][q] : lst;
+      lst = take ? __float_as_int(a1.w) : lst;
     };
     // two entries per round (one saturation check for both)
     for (uint32_t j = 0; j < len; j += 2) {
