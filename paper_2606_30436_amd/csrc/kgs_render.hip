@@ -63,8 +63,9 @@ __global__ __launch_bounds__(64 * NW) void k_render_fwd(RenderParams P, const ui
                                                         float* __restrict__ tfinal, int32_t* __restrict__ last) {
   // each kept record's three float4 side by side: one address, three offsets;
   // r1.w (the x-bounds, used only by the staging test) holds the record's
-  // position in the tile list, plus one
-  __shared__ float4 s_rec[NW][64][3];
+  // position in the tile list, plus one.  Row 64 is never written: a round
+  // reads entry j + 1 even when it does not exist (and ignores it).
+  __shared__ float4 s_rec[NW][65][3];
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
   const int gt = (int)tile_order[blockIdx.x];
   const int v = gt / P.n_tiles, t = gt - v * P.n_tiles;
@@ -79,11 +80,22 @@ __global__ __launch_bounds__(64 * NW) void k_render_fwd(RenderParams P, const ui
   const float fpx = (float)(px - ox), fpy = (float)(py - oy);
   const uint2 rg = ranges[gt];
   const uint32_t start = rg.x, end = rg.y;
-  float T = 1.0f, c0 = 0.f, c1 = 0.f, c2 = 0.f, D = 0.f;
+  // the rows start as zeros: an absent second entry reads finite values, which
+  // its zero weight then leaves out of the sums
+  {
+    const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+    s_rec[w][l][0] = z;
+    s_rec[w][l][1] = z;
+    s_rec[w][l][2] = z;
+    if (l < 3) s_rec[w][64][l] = z;
+  }
+  __builtin_amdgcn_wave_barrier();
+  // T > 0 while the pixel composites; a pixel that saturates (or lies outside
+  // the image) keeps -T, its final transmittance negated
+  float T = inside ? 1.0f : -1.0f, c0 = 0.f, c1 = 0.f, c2 = 0.f, D = 0.f;
   int lst = 0;
-  bool done = !inside;
   for (uint32_t base = start; base < end; base += 64) {
-    if (!__any(!done)) break;
+    if (!__any(T > 0.f)) break;
     // stage: lane l takes record base + l and keeps it if it reaches this sub-block
     const uint32_t k = base + (uint32_t)l;
     bool keep = false;
@@ -114,26 +126,24 @@ __global__ __launch_bounds__(64 * NW) void k_render_fwd(RenderParams P, const ui
       const float4 a0 = s_rec[w][q][0], a1 = s_rec[w][q][1], a2 = s_rec[w][q][2];
       float dy, u;
       const float e = log2_alpha(fpx, fpy, a0, a1.x, a1.y, dy, u);
-      const bool hit = present && !done && e >= P.log2_amin;
+      const bool hit = present && T > 0.f && e >= P.log2_amin;
       const float a = hit ? fminf(exp2_approx(e), P.amax) : 0.f;
       const float Tn = T * (1.0f - a);
       const bool stop = hit && Tn < P.tmin;
-      done = done || stop;
       const bool take = hit && !stop;
       const float wgt = take ? a * T : 0.f;
       c0 = fmaf(wgt, a2.x, c0);
       c1 = fmaf(wgt, a2.y, c1);
       c2 = fmaf(wgt, a2.z, c2);
       D = fmaf(wgt, a1.z, D);
-      T = take ? Tn : T;
+      T = take ? Tn : (stop ? -T : T);
       lst = take ? __float_as_int(a1.w) : lst;
     };
     // two entries per round (one saturation check for both)
     for (uint32_t j = 0; j < len; j += 2) {
-      if (!__any(!done)) break;
-      const bool has_b = j + 1 < len;
+      if (!__any(T > 0.f)) break;
       blend(j, true);
-      blend(has_b ? j + 1 : j, has_b);
+      blend(j + 1, j + 1 < len);
     }
     __builtin_amdgcn_wave_barrier();
   }
@@ -141,6 +151,7 @@ __global__ __launch_bounds__(64 * NW) void k_render_fwd(RenderParams P, const ui
     const size_t npix = (size_t)P.W * P.H;
     const size_t pix = (size_t)v * npix + (size_t)py * P.W + px;
     const size_t cpix = (size_t)v * 3 * npix + (size_t)py * P.W + px;
+    T = fabsf(T);
     color[cpix] = c0 + T * P.bg0;
     color[cpix + npix] = c1 + T * P.bg1;
     color[cpix + 2 * npix] = c2 + T * P.bg2;
