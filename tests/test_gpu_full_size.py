@@ -1,0 +1,172 @@
+"""Parity at the full sizes of the driving configurations, in the launch
+configuration the benchmark times, against the FP64 oracle:
+
+* the single-view 500k-Gaussian corridor (SH3, 1242x375) with the densify
+  statistics: image, every parameter gradient, the pixel footprint, the
+  screen-space mean-gradient norm and the screen radius;
+* the batched 2M-Gaussian, 8-keyframe chunk through the chunk path at 32x16
+  tiles and LDS batch 64 (the tiling the autotuner picks for it), with the
+  lifecycle step as the benchmark runs it: all eight images, every parameter
+  gradient summed over the views, the per-view pose gradients and losses, and
+  the chunk's pruning scores, densify flags and decisions against the chunk
+  rules applied to the oracle's per-view footprints and error counts.
+
+Tolerances as in the parity tests: images 1e-4 away from threshold pixels,
+gradients 1e-3 relative in the 2-norm per tensor."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import lifecycle
+from paper_2606_30436_amd import scenes
+from paper_2606_30436_amd.rasterizer import (GaussianParams, Image, LifecycleState, Rasterizer, ViewStats,
+                                             device_cameras)
+from tests.gpu_util import ambiguous_pixels, oracle_cfg, say
+
+pytestmark = pytest.mark.gpu
+
+FAR = 80.0
+
+
+def _rel(got, ref):
+    got = np.asarray(got, np.float64)
+    ref = np.asarray(ref, np.float64)
+    return float(np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-300))
+
+
+def _image_error(col, oi):
+    ok = ~ambiguous_pixels(oi)
+    return float(np.abs(col - oi["color"]).max(0)[ok].max()), float((~ok).mean())
+
+
+def test_c2_single_view_full_size():
+    sc = scenes.make_c2()
+    say(f"[gpu] C2 full size n={sc.n}")
+    R = Rasterizer(sc.width, sc.height, max_views=1, max_gaussians=sc.n, slot_capacity=sc.n,
+                   pair_capacity=16_000_000, far_z=FAR)
+    g = GaussianParams.from_scene(sc)
+    cams = device_cameras(sc.cams)
+    xi = torch.from_numpy(sc.pose_xi.astype(np.float32)).cuda()
+    R.project(g, cams, xi)
+    R.bin_sort()
+    img = Image.empty(1, sc.height, sc.width)
+    R.render_fwd(img)
+    target = torch.from_numpy(sc.target.astype(np.float32)).cuda()
+    dl = torch.empty_like(img.color)
+    loss = torch.empty(1, device="cuda")
+    R.loss_l1(target, img, dl, loss)
+    st = ViewStats.zeros(sc.n)
+    grads = g.zeros_like()
+    pose = torch.zeros(1, 6, device="cuda")
+    R.render_bwd(g, cams, xi, img, dl, target=target, tau_err=0.1, view_loss=loss, grads=grads, pose_grad=pose,
+                 stats=st)
+    torch.cuda.synchronize()
+    assert R.status() == 0
+    cfg = oracle_cfg(R)
+    ov = oracle.View(sc, 0, cfg)
+    oi = ov.image()
+    err, excl = _image_error(img.color.cpu().numpy()[0], oi)
+    say(f"  image max error {err:.2e}, excluded {excl:.3f}")
+    assert err <= 1e-4 and excl < 0.1
+    an = ov.backward(dl.cpu().numpy()[0].astype(np.float64))
+    for k in ("means", "log_scales", "quats", "logits", "sh"):
+        rel = _rel(getattr(grads, k).cpu().numpy(), an[k])
+        say(f"  {k} rel {rel:.2e}")
+        assert rel < 1e-3, k
+    rel = _rel(pose.cpu().numpy()[0], an["pose_xi"])
+    say(f"  pose rel {rel:.2e}")
+    assert rel < 1e-3
+    # statistics: screen radius exact, mean-gradient norm to 1e-3, footprint
+    # exact away from threshold pixels
+    pr = ov.proj()
+    vis = pr["visible"]
+    rad = np.where(vis, np.maximum(pr["rx"], pr["ry"]), 0)
+    rmis = (st.max_radius.cpu().numpy().astype(np.int64) != rad).mean()
+    say(f"  radius mismatches {rmis:.2e} of the Gaussians")
+    assert rmis < 1e-4
+    gn_ref = np.linalg.norm(an["g2"][:, 0:2], axis=1)
+    rel = _rel(st.grad_norm_sum.cpu().numpy(), gn_ref)
+    say(f"  mean-gradient norm rel {rel:.2e}")
+    assert rel < 1e-3
+    s = ov.stats(sc.target[0], 0.1)
+    om = st.omega_sum.cpu().numpy().astype(np.int64)
+    mism = (om != s["omega"]).mean()
+    say(f"  footprint mismatches {mism:.2e} of the Gaussians")
+    assert mism < 1e-3
+
+
+def test_c3_bench_chunk_full_size():
+    sc = scenes.make_c3()
+    V = sc.n_views
+    # the benchmark's chunk: poses at the keyframes (xi = 0); any target serves
+    # parity (the benchmark renders its targets from the noise-free map)
+    sc.pose_xi = np.zeros((V, 6), np.float32)
+    sc.target = scenes.random_target(31, V, sc.height, sc.width)
+    say(f"[gpu] C3 full chunk n={sc.n} V={V} tiles 32x16 batch 64")
+    R = Rasterizer(sc.width, sc.height, max_views=V, max_gaussians=sc.n, slot_capacity=3_000_000,
+                   pair_capacity=16_000_000, tile=(32, 16), batch=64, far_z=FAR)
+    g = GaussianParams.from_scene(sc)
+    cams = device_cameras(sc.cams)
+    xi = torch.from_numpy(sc.pose_xi.astype(np.float32)).cuda()
+    target = torch.from_numpy(sc.target.astype(np.float32)).cuda()
+    img = Image.empty(V, sc.height, sc.width)
+    dl = torch.empty_like(img.color)
+    loss = torch.empty(V, device="cuda")
+    grads = g.zeros_like()
+    pose = torch.zeros(V, 6, device="cuda")
+    st = ViewStats.zeros(sc.n)
+    state = LifecycleState.zeros(sc.n)
+    dec = torch.empty(sc.n, dtype=torch.uint8, device="cuda")
+    d = R.chunk_desc(g, cams, xi, target, img, dl, loss, grads, pose, st, tau_err=0.1, zero_accumulators=True,
+                     state=state, decision=dec, tau_d=5.0, tau_p=0.99)
+    R.chunk_run(d)
+    torch.cuda.synchronize()
+    assert R.status() == 0
+    cfg = oracle_cfg(R)
+    col = img.color.cpu().numpy()
+    dlv = dl.cpu().numpy().astype(np.float64)
+    ref = {k: 0.0 for k in ("means", "log_scales", "quats", "logits", "sh")}
+    om_ref = np.zeros((V, sc.n), np.int32)
+    ka_ref = np.zeros((V, sc.n), np.int32)
+    lossv = loss.cpu().numpy()
+    pg = pose.cpu().numpy()
+    for v in range(V):
+        ov = oracle.View(sc, v, cfg)
+        oi = ov.image()
+        err, excl = _image_error(col[v], oi)
+        an = ov.backward(dlv[v])
+        prel = _rel(pg[v], an["pose_xi"])
+        say(f"  view {v}: image error {err:.2e} (excluded {excl:.3f}), pose rel {prel:.2e}")
+        assert err <= 1e-4 and excl < 0.25
+        assert prel < 1e-3
+        assert lossv[v] == pytest.approx(np.abs(col[v].astype(np.float64) - sc.target[v]).mean(), rel=1e-5)
+        for k in ref:
+            ref[k] = ref[k] + an[k]
+        sv = ov.stats(sc.target[v], 0.1)
+        om_ref[v] = sv["omega"]
+        ka_ref[v] = sv["kappa"]
+        del ov
+    for k in ref:
+        rel = _rel(getattr(grads, k).cpu().numpy(), ref[k])
+        say(f"  {k} rel {rel:.2e}")
+        assert rel < 1e-3, k
+    # the lifecycle step (the chunk folded its sums into the state and reset
+    # them): the chunk rules on the oracle's counts with the GPU's own losses.
+    # Counts of a Gaussian at the alpha or T threshold may differ by one pixel
+    # between FP32 and FP64; for a Gaussian whose footprint is a few pixels that
+    # moves its log-scaled score by up to ~1e-2, so the bound is on how many
+    # Gaussians move at all.
+    cs = lifecycle.chunk_scores(ka_ref, om_ref, lossv.astype(np.float64))
+    D, Pq = lifecycle.global_update(np.zeros(sc.n, bool), np.zeros(sc.n), cs["sd"], cs["sp"], tau_d=5.0)
+    dref = lifecycle.decide(D, Pq, tau_p=0.99)
+    sp = state.prune_score.cpu().numpy().astype(np.float64)
+    d_sp = np.abs(sp - Pq)
+    say(f"  active {int(cs['active'].sum())}, pruning score max |d| {d_sp.max():.2e}, "
+        f"over 1e-6: {(d_sp > 1e-6).mean():.2e}")
+    assert (d_sp > 1e-6).mean() < 1e-3
+    dd = (state.densify.cpu().numpy().astype(bool) != D).mean()
+    dec_mis = (dec.cpu().numpy() != dref).mean()
+    say(f"  densify flag mismatches {dd:.2e}, decision mismatches {dec_mis:.2e}, "
+        f"pruned {int((dref == lifecycle.PRUNE).sum())}, densified {int((dref == lifecycle.DENSIFY).sum())}")
+    assert dd < 1e-3 and dec_mis < 1e-3
