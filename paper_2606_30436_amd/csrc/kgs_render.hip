@@ -1,20 +1,25 @@
 // Front-to-back compositing (forward), the L1 loss harness and the
 // compositing backward.
 //
-// One workgroup of 256 threads per (view, tile); each wave owns an 8x8
-// sub-block of the tile.  The tile's depth-sorted pairs are staged B at a time
-// into LDS; while staging, each Gaussian's integer pixel rectangle is tested
-// against the four sub-blocks and one compacted list per wave is built, so a
-// wave only evaluates Gaussians that can reach its pixels (outside the
-// rectangle alpha < alpha_min holds by construction of the rectangle, so this
-// changes no result).  A wave stops as soon as all its pixels are saturated.
+// One workgroup per (view, tile); each wave owns an 8x8 sub-block of the tile
+// (four waves for 256-pixel tiles, eight for 512-pixel ones).  Every wave
+// reads the tile's depth-sorted records itself, a batch at a time, tests each
+// against its own sub-block (the integer rectangle, then the exact minimum of
+// the conic over the sub-block's pixel-centre box, with a margin that keeps the
+// test conservative) and keeps a compacted list of those that can reach its
+// pixels, so a wave only evaluates Gaussians that can blend there and no
+// result changes.  The forward shares nothing between waves; a wave stops as
+// soon as all its pixels are saturated.
 //
 // The backward recomputes the same per-pixel sequence front to back (nothing
 // per pixel is stored but T_final and the last blended position), reduces the
-// ten per-pair gradient terms across the wave with a reduce-scatter butterfly,
-// combines the four waves in fixed order through LDS and writes one 48-byte
-// record per pair at the pair's emission position, which keeps each slot's
-// pairs contiguous for the deterministic segmented sum that follows.
+// per-pair gradient terms across the wave with a reduce-scatter butterfly, and
+// after each batch the first wave adds the waves' partials in wave order and
+// writes one 48-byte record per pair at the pair's emission position, which
+// keeps each slot's pairs contiguous for the deterministic segmented sum that
+// follows.  It stops each tile at the last batch any of its pixels reaches;
+// the pairs behind it are never written, and a flag byte per pair tells the
+// segmented sum which ones were.
 #include "kgs_internal.h"
 
 struct RenderParams {
@@ -164,7 +169,7 @@ __global__ __launch_bounds__(64 * NW) void k_render_fwd(RenderParams P, const ui
 // ---------------------------------------------------------------- L1 loss harness
 // One workgroup per (view, tile), pixels mapped to lanes as in the
 // compositing kernels.  Per pixel |dR| + |dG| + |dB| in FP32, summed over the
-// wave by a fixed butterfly, the four waves in order in FP64, one partial per
+// wave by a fixed butterfly, the waves in order in FP64, one partial per
 // (view, tile); k_loss_final adds the partials of a view in tile order.  The
 // chunk's fused backward forms the same partials in the same order, so both
 // routes give the same bits.
