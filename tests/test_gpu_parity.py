@@ -138,6 +138,44 @@ def test_binning_bit_exact_on_the_other_sort_paths(case):
             assert np.array_equal(first[k].numpy(), again[k].numpy()), k
 
 
+def test_sixty_four_views():
+    """The most views a call takes (64): the emission's per-Gaussian view mask
+    uses its top bit and the depth sort 8-byte keys (27 depth + 6 view bits).
+    Binning, every view's image and all gradients against the oracle."""
+    sc = scenes.tiny_scene(seed=9, n=150, degree=1, W=64, H=48, n_views=64, pose_sigma=0.02)
+    say("[gpu] 64 views")
+    R = _rast(sc)
+    g, cams, xi, img = run_forward(R, sc)
+    _check_binning(R, sc, (16, 16))
+    b = R.buffers()
+    assert int(np.max(b["slot_view"].numpy())) == 63
+    cfg = oracle_cfg(R)
+    col = img.color.cpu().numpy()
+    rng = np.random.default_rng(19)
+    dLdC = rng.normal(size=(64, 3, sc.height, sc.width))
+    grads = g.zeros_like()
+    pose_grad = torch.zeros(64, 6, device="cuda")
+    R.render_bwd(g, cams, xi, img, torch.from_numpy(dLdC.astype(np.float32)).cuda(), grads=grads,
+                 pose_grad=pose_grad)
+    torch.cuda.synchronize()
+    ref = {k: 0.0 for k in ("means", "log_scales", "quats", "logits", "sh")}
+    pg = pose_grad.cpu().numpy()
+    for v in range(64):
+        ov = oracle.View(sc, v, cfg)
+        oi = ov.image()
+        ok = ~ambiguous_pixels(oi)
+        assert np.abs(col[v] - oi["color"]).max(0)[ok].max() <= 1e-4, v
+        an = ov.backward(dLdC[v])
+        for k in ref:
+            ref[k] = ref[k] + an[k]
+        assert np.linalg.norm(pg[v] - an["pose_xi"]) <= 1e-3 * np.linalg.norm(an["pose_xi"]) + 1e-9, v
+    for k in ref:
+        got = getattr(grads, k).cpu().numpy().astype(np.float64)
+        rel = np.linalg.norm(got - ref[k]) / np.linalg.norm(ref[k])
+        say(f"  {k} rel {rel:.2e}")
+        assert rel < 1e-3, k
+
+
 @pytest.mark.parametrize("name", ["c1", "tiny", "tiny_bg"])
 def test_render_forward_matches_oracle(name):
     sc = _scene(name)
