@@ -176,6 +176,47 @@ def test_sixty_four_views():
         assert rel < 1e-3, k
 
 
+def test_a_view_that_sees_nothing():
+    """A batched call in which the middle view faces away from every Gaussian:
+    its tile lists, its slot range and its pose pieces are empty.  Its image is
+    the background and its pose gradient zero; the other views and all
+    gradients match the oracle."""
+    sc = scenes.tiny_scene(seed=3, n=60, degree=3, W=70, H=45, n_views=3, pose_sigma=0.0)
+    sc.cams["R"][1] = np.array([-1.0, 0, 0, 0, 1.0, 0, 0, 0, -1.0], np.float32)   # turned around
+    say("[gpu] a view that sees nothing")
+    R = _rast(sc, bg=(0.2, 0.5, 0.9))
+    g, cams, xi, img = run_forward(R, sc)
+    b = R.buffers()
+    views = b["slot_view"].numpy()
+    assert (views == 1).sum() == 0 and (views == 0).sum() > 0 and (views == 2).sum() > 0
+    col = img.color.cpu().numpy()
+    assert np.array_equal(col[1], np.broadcast_to(np.array([0.2, 0.5, 0.9], np.float32)[:, None, None], col[1].shape))
+    assert np.all(img.t_final.cpu().numpy()[1] == 1.0)
+    rng = np.random.default_rng(23)
+    dLdC = rng.normal(size=(3, 3, sc.height, sc.width))
+    grads = g.zeros_like()
+    pose_grad = torch.zeros(3, 6, device="cuda")
+    R.render_bwd(g, cams, xi, img, torch.from_numpy(dLdC.astype(np.float32)).cuda(), grads=grads,
+                 pose_grad=pose_grad)
+    torch.cuda.synchronize()
+    pg = pose_grad.cpu().numpy()
+    assert np.all(pg[1] == 0.0)
+    cfg = oracle_cfg(R)
+    ref = {k: 0.0 for k in ("means", "log_scales", "quats", "logits", "sh")}
+    for v in (0, 2):
+        ov = oracle.View(sc, v, cfg)
+        oi = ov.image()
+        ok = ~ambiguous_pixels(oi)
+        assert np.abs(col[v] - oi["color"]).max(0)[ok].max() <= 1e-4
+        an = ov.backward(dLdC[v])
+        for k in ref:
+            ref[k] = ref[k] + an[k]
+        assert np.linalg.norm(pg[v] - an["pose_xi"]) <= 1e-3 * np.linalg.norm(an["pose_xi"])
+    for k in ref:
+        got = getattr(grads, k).cpu().numpy().astype(np.float64)
+        assert np.linalg.norm(got - ref[k]) <= 1e-3 * np.linalg.norm(ref[k]), k
+
+
 @pytest.mark.parametrize("name", ["c1", "tiny", "tiny_bg"])
 def test_render_forward_matches_oracle(name):
     sc = _scene(name)
