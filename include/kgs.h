@@ -177,10 +177,13 @@ typedef struct kgs_buffers {
   const uint32_t* slot_view;    /* [S] view */
   const int32_t* slot_pix;      /* [S][4]: floor(mu_x), floor(mu_y), rx, ry */
   const uint32_t* slot_pairoff; /* [S] first pair (emission order) */
-  const uint32_t* keys;         /* [P] sorted pair keys: view * tiles + tile (depth order within a tile) */
+  const uint32_t* keys;         /* [P] sorted pair keys: (view << tile_bits) | tile.  Pairs are grouped by
+                                   tile, then view; depth order within a (view, tile) group */
   const uint32_t* sorted_slot;  /* [P] slot of each sorted pair */
-  const uint32_t* ranges;       /* [V*tiles][2] start, end in the sorted pairs */
+  const uint32_t* ranges;       /* [V*tiles][2] start, end in the sorted pairs, index view * tiles + tile */
   int32_t tiles_x, tiles_y;
+  int32_t tile_bits;            /* tiles < 2^tile_bits */
+  int32_t n_views;              /* views of the last kgs_project */
 } kgs_buffers;
 
 /* A whole pass over one chunk of views: zero the accumulators (optional),
@@ -238,9 +241,11 @@ kgs_status kgs_project(kgs_ctx* ctx, const kgs_gaussians* g, const kgs_camera* c
 /* Tile binning and depth sort of the projected records ("sorted Gaussians",
  * appendix, Depth Volume Rendering): the records are radix-sorted by
  * (view, fp32 depth bits), one pair per tile of each record's rectangle is
- * emitted in that order, and the pairs are radix-sorted stably by global tile
- * index; equal depths keep Gaussian-index order.  Then per-tile ranges.
- * Pair overflow sets KGS_FLAG_PAIR_OVERFLOW (at kgs_project). */
+ * emitted in that order, and the pairs are radix-sorted stably by their tile
+ * within the view, which leaves each (view, tile) group contiguous and in
+ * depth order; equal depths keep Gaussian-index order.  Then per-(view, tile)
+ * ranges.  Pair overflow sets KGS_FLAG_PAIR_OVERFLOW (at kgs_project).
+ * KGS_ERR_INVALID_ARG if the tile count per view needs more than 25 bits. */
 kgs_status kgs_bin_sort(kgs_ctx* ctx, void* stream);
 
 /* Front-to-back compositing of every tile of every view (appendix, Depth

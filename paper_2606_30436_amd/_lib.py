@@ -60,7 +60,8 @@ class KgsLifecycleState(ctypes.Structure):
 class KgsBuffers(ctypes.Structure):
     _fields_ = [("n_slots", c_void_p), ("n_pairs", c_void_p), ("slot_rec", c_void_p), ("slot_gid", c_void_p),
                 ("slot_view", c_void_p), ("slot_pix", c_void_p), ("slot_pairoff", c_void_p), ("keys", c_void_p),
-                ("sorted_slot", c_void_p), ("ranges", c_void_p), ("tiles_x", c_int32), ("tiles_y", c_int32)]
+                ("sorted_slot", c_void_p), ("ranges", c_void_p), ("tiles_x", c_int32), ("tiles_y", c_int32),
+                ("tile_bits", c_int32), ("n_views", c_int32)]
 
 
 class KgsChunkDesc(ctypes.Structure):

@@ -86,8 +86,8 @@ size_t layout(const kgs_config& c, char* base, kgs_ctx* ctx) {
   p = take(4 * V * T);                          if (ctx) ctx->tile_order = (uint32_t*)p;
   p = take(48 * P);                             if (ctx) ctx->pair_grad = (float4*)p;
   p = take(P + 16);                             if (ctx) ctx->pair_live = (uint8_t*)p;
-  p = take(4 * 256 * KGS_SORT_BLOCKS);          if (ctx) ctx->radix_hist = (uint32_t*)p;
-  p = take(4 * 256 * KGS_MAX_PASSES);           if (ctx) ctx->radix_total = (uint32_t*)p;
+  p = take(4 * KGS_RADIX_BUCKETS * KGS_SORT_BLOCKS); if (ctx) ctx->radix_hist = (uint32_t*)p;
+  p = take(4 * KGS_RADIX_BUCKETS * KGS_MAX_PASSES); if (ctx) ctx->radix_total = (uint32_t*)p;
   p = take(4 * KGS_SLOT_WORDS * S);             if (ctx) ctx->slot_bwd = (float4*)p;
   p = take(4 * P);                              if (ctx) ctx->pair_slot = (uint32_t*)p;
   p = take(64 * (P / 64 + 2));                  if (ctx) ctx->seg_head = (float4*)p;
@@ -480,6 +480,8 @@ kgs_status kgs_get_buffers(kgs_ctx* ctx, kgs_buffers* b) {
   b->ranges = (const uint32_t*)ctx->ranges;
   b->tiles_x = ctx->tiles_x;
   b->tiles_y = ctx->tiles_y;
+  b->tile_bits = ctx->tile_bits;
+  b->n_views = ctx->last_views;
   return KGS_OK;
 }
 

@@ -14,6 +14,7 @@
 #define KGS_CNT_LIVE 4                  // counters[] word of the live-slot count
 #define KGS_SORT_BLOCKS 1024          // fixed grid (one partition per block) of the radix sort passes
 #define KGS_MAX_PASSES 8
+#define KGS_RADIX_BUCKETS 1024      // widest digit of a radix pass: 10 bits
 #define KGS_POSE_BLOCKS 256           // pieces per view of the pose reduction
 #define KGS_SLOT_WORDS 24             // words of a slot's backward record
 
@@ -91,8 +92,8 @@ struct kgs_ctx {
   uint32_t* tile_order;               // [max_views * max_tiles] compositing launch order, heaviest first
   float4* pair_grad;                  // [P][3] per-pair record-space gradients + counts
   uint8_t* pair_live;                 // [P] 1 where the compositing backward wrote the pair's record
-  uint32_t* radix_hist;               // [256][KGS_SORT_BLOCKS] digit counts, then offsets, per partition
-  uint32_t* radix_total;              // [KGS_MAX_PASSES][256]
+  uint32_t* radix_hist;               // [KGS_RADIX_BUCKETS][KGS_SORT_BLOCKS] digit counts, then offsets, per partition
+  uint32_t* radix_total;              // [KGS_MAX_PASSES][KGS_RADIX_BUCKETS]
   float4* slot_bwd;                   // [S][KGS_SLOT_WORDS / 4] per-slot backward records
   uint32_t* pair_slot;                // [P] slot of every pair, emission order
   float4* seg_head;                   // [P / 64 + 1][4] per 64-pair window: its first segment's partial sum
@@ -113,7 +114,7 @@ struct kgs_ctx {
   int last_views;
   int64_t last_n;
   int last_degree;
-  int passes;
+  int tile_bits;                      // pair keys: (view << tile_bits) | tile, from the last bin_sort
   int sorted_buf;                     // which ping-pong buffer holds the sorted pairs
   const uint32_t* perm;               // slots in (view, depth) order, from the last bin_sort
   int projected, binned;

@@ -32,14 +32,21 @@ __device__ __forceinline__ void part_range(uint32_t n, uint32_t nb, uint32_t b, 
   hi = min(n, lo + per);
 }
 
-// Lanes of the wave whose valid keys share digit d (d < 256): one ballot per
-// bit, all eight unrolled (bits above the digit width are zero in every lane
-// and leave the mask alone).
+// Partition of workgroup b of nb (a multiple of 8).  Workgroups are dealt to
+// the eight XCDs in turn, so this gives each XCD a contiguous run of
+// partitions: a digit's output runs from neighbouring partitions, written by
+// workgroups in flight together, then meet in one L2 instead of eight.
+__device__ __forceinline__ uint32_t xcd_part(uint32_t b, uint32_t nb) { return (b & 7u) * (nb >> 3) + (b >> 3); }
+
+// Lanes of the wave whose valid keys share digit d (d < 2^DB): one ballot per
+// bit, all DB unrolled (bits above the pass's digit width are zero in every
+// lane and leave the mask alone).
+template <int DB>
 __device__ __forceinline__ uint64_t digit_peers(bool valid, uint32_t d) {
   const uint64_t v = ballot64(valid);
   uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
 #pragma unroll
-  for (int bit = 0; bit < 8; ++bit) {
+  for (int bit = 0; bit < DB; ++bit) {
     // m: all ones where this lane's bit is set; keep the lanes whose bit agrees
     const uint32_t m = (uint32_t)((int32_t)(d << (31 - bit)) >> 31);
     const uint64_t b = ballot64((d >> bit) & 1u);
@@ -50,18 +57,21 @@ __device__ __forceinline__ uint64_t digit_peers(bool valid, uint32_t d) {
 }
 
 // per-block digit histograms hist[d][block]; the lowest lane of each group of
-// equal digits adds the group's size (one LDS add per distinct digit)
-template <typename K>
+// equal digits adds the group's size (one LDS add per distinct digit).  DB is
+// the widest digit the kernel takes (8 or 10 bits), dbits the pass's own.
+template <typename K, int DB>
 __global__ __launch_bounds__(256) void k_radix_hist(const uint32_t* __restrict__ count, const K* __restrict__ keys,
                                                     int shift, int dbits, uint32_t nb, uint32_t* __restrict__ hist) {
-  __shared__ uint32_t h[256];
+  constexpr int R = 1 << DB;
+  __shared__ uint32_t h[R];
   const int tid = threadIdx.x, l = tid & 63;
   const uint32_t dmask = (1u << dbits) - 1u;
   const uint64_t lt = (1ull << l) - 1ull;
-  h[tid] = 0u;
+  for (int d = tid; d < R; d += 256) h[d] = 0u;
   __syncthreads();
+  const uint32_t part = xcd_part(blockIdx.x, nb);
   uint32_t lo, hi;
-  part_range(*count, nb, blockIdx.x, lo, hi);
+  part_range(*count, nb, part, lo, hi);
   // 16-byte loads: VW keys per load, four loads per thread in flight
   constexpr int VW = 16 / sizeof(K), KPI = 4 * VW;
   for (uint32_t base = lo; base < hi; base += 256 * KPI) {
@@ -86,12 +96,12 @@ __global__ __launch_bounds__(256) void k_radix_hist(const uint32_t* __restrict__
     for (int q = 0; q < KPI; ++q) {
       const bool valid = base + ((q / VW) * 256 + tid) * VW + (q % VW) < hi;
       const uint32_t d = (uint32_t)(kk[q] >> shift) & dmask;
-      const uint64_t peers = digit_peers(valid, d);
+      const uint64_t peers = digit_peers<DB>(valid, d);
       if (valid && (peers & lt) == 0ull) atomicAdd(&h[d], (uint32_t)__popcll(peers));
     }
   }
   __syncthreads();
-  if ((uint32_t)tid <= dmask) hist[(size_t)tid * nb + blockIdx.x] = h[tid];
+  for (uint32_t d = (uint32_t)tid; d <= dmask; d += 256) hist[(size_t)d * nb + part] = h[d];
 }
 
 // one block per digit: exclusive scan of its row of block counts (in place)
@@ -123,34 +133,48 @@ __global__ __launch_bounds__(256) void k_radix_scan(uint32_t* __restrict__ hist,
 
 // Stable scatter of one block's partition, a tile of 256 x KPT keys at a time.
 // Wave w ranks keys [w * 64 KPT, (w + 1) * 64 KPT) of the tile in index order.
-template <typename K, int KPT>
+// For the block-wide prefixes each thread owns DPT = 2^DB / 256 consecutive
+// digits.
+template <typename K, int KPT, int DB>
 __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t* __restrict__ count, const K* __restrict__ kin,
                                                        const uint32_t* __restrict__ vin, int shift, int dbits,
                                                        uint32_t nb, const uint32_t* __restrict__ offsets,
                                                        const uint32_t* __restrict__ total, K* __restrict__ kout,
                                                        uint32_t* __restrict__ vout) {
   constexpr uint32_t TILE = 256 * KPT;
+  constexpr int R = 1 << DB, DPT = R / 256;
   __shared__ K lk[TILE];
   __shared__ uint32_t lv[TILE];
-  __shared__ uint32_t wc[4][256];     // running digit counts of each wave, then the waves' digit prefixes
-  __shared__ uint32_t dstart[256], gofs[256];
+  __shared__ uint32_t wc[4][R];     // running digit counts of each wave, then the waves' digit prefixes
+  __shared__ uint32_t dstart[R], gofs[R];
   __shared__ uint32_t sh[4];
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
-  const uint32_t R = 1u << dbits, dmask = R - 1u;
+  const uint32_t nd = 1u << dbits, dmask = nd - 1u;
+  const uint32_t d0 = (uint32_t)tid * DPT;
+  const uint32_t part = xcd_part(blockIdx.x, nb);
   {
     // digit bases: exclusive scan of the digit totals
-    const uint32_t t = (uint32_t)tid < R ? total[tid] : 0u;
-    const uint32_t inc = wave_inclusive_scan(t);
+    uint32_t t[DPT], ts = 0;
+#pragma unroll
+    for (int k = 0; k < DPT; ++k) {
+      t[k] = d0 + k < nd ? total[d0 + k] : 0u;
+      ts += t[k];
+    }
+    const uint32_t inc = wave_inclusive_scan(ts);
     if (l == 63) sh[w] = inc;
     __syncthreads();
-    uint32_t base = inc - t;
+    uint32_t base = inc - ts;
     for (int k = 0; k < w; ++k) base += sh[k];
-    gofs[tid] = (uint32_t)tid < R ? base + offsets[(size_t)tid * nb + blockIdx.x] : 0u;
+#pragma unroll
+    for (int k = 0; k < DPT; ++k) {
+      gofs[d0 + k] = d0 + k < nd ? base + offsets[(size_t)(d0 + k) * nb + part] : 0u;
+      base += t[k];
+    }
   }
 #pragma unroll
-  for (int k = 0; k < 4; ++k) wc[k][tid] = 0u;
+  for (int k = 0; k < DPT; ++k) wc[0][d0 + k] = wc[1][d0 + k] = wc[2][d0 + k] = wc[3][d0 + k] = 0u;
   uint32_t lo, hi;
-  part_range(*count, nb, blockIdx.x, lo, hi);
+  part_range(*count, nb, part, lo, hi);
   const uint64_t lt = (1ull << l) - 1ull;
   __syncthreads();
   for (uint32_t tb = lo; tb < hi; tb += TILE) {
@@ -172,7 +196,7 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t* __restric
     for (int q = 0; q < KPT; ++q) {
       const bool valid = wb + q * 64 + l < hi;
       const uint32_t d = (uint32_t)(kk[q] >> shift) & dmask;
-      const uint64_t peers = digit_peers(valid, d);
+      const uint64_t peers = digit_peers<DB>(valid, d);
       const uint32_t r = (uint32_t)__popcll(peers & lt);
       const uint32_t before = valid ? wc[w][d] : 0u;
       __builtin_amdgcn_wave_barrier();
@@ -182,18 +206,29 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t* __restric
     }
     __syncthreads();
     // digit-major prefix: digit start in the tile, then the waves in order
-    const uint32_t c0 = wc[0][tid], c1 = wc[1][tid], c2 = wc[2][tid], c3 = wc[3][tid];
-    const uint32_t tot = c0 + c1 + c2 + c3;
-    const uint32_t inc = wave_inclusive_scan(tot);
+    uint32_t c0[DPT], c1[DPT], c2[DPT], tot[DPT], ts = 0;
+#pragma unroll
+    for (int k = 0; k < DPT; ++k) {
+      c0[k] = wc[0][d0 + k];
+      c1[k] = wc[1][d0 + k];
+      c2[k] = wc[2][d0 + k];
+      tot[k] = c0[k] + c1[k] + c2[k] + wc[3][d0 + k];
+      ts += tot[k];
+    }
+    const uint32_t inc = wave_inclusive_scan(ts);
     if (l == 63) sh[w] = inc;
     __syncthreads();
-    uint32_t ex = inc - tot;
+    uint32_t ex = inc - ts;
     for (int k = 0; k < w; ++k) ex += sh[k];
-    dstart[tid] = ex;
-    wc[0][tid] = ex;
-    wc[1][tid] = ex + c0;
-    wc[2][tid] = ex + c0 + c1;
-    wc[3][tid] = ex + c0 + c1 + c2;
+#pragma unroll
+    for (int k = 0; k < DPT; ++k) {
+      dstart[d0 + k] = ex;
+      wc[0][d0 + k] = ex;
+      wc[1][d0 + k] = ex + c0[k];
+      wc[2][d0 + k] = ex + c0[k] + c1[k];
+      wc[3][d0 + k] = ex + c0[k] + c1[k] + c2[k];
+      ex += tot[k];
+    }
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < KPT; ++q) {
@@ -213,9 +248,11 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t* __restric
       vout[g] = lv[i];
     }
     __syncthreads();
-    gofs[tid] += tot;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) wc[k][tid] = 0u;
+    for (int k = 0; k < DPT; ++k) {
+      gofs[d0 + k] += tot[k];
+      wc[0][d0 + k] = wc[1][d0 + k] = wc[2][d0 + k] = wc[3][d0 + k] = 0u;
+    }
     __syncthreads();
   }
 }
@@ -231,7 +268,7 @@ struct EmitSlot {
 
 __device__ __forceinline__ EmitSlot emit_slot(uint32_t s, const uint32_t* __restrict__ slot_view,
                                               const int4* __restrict__ slot_pix, int tile_w, int tile_h,
-                                              int tiles_x, uint32_t tiles_per_view) {
+                                              int tiles_x, int tile_bits) {
   const int4 pix = slot_pix[s];
   EmitSlot e;
   e.s = s;
@@ -239,11 +276,12 @@ __device__ __forceinline__ EmitSlot emit_slot(uint32_t s, const uint32_t* __rest
   const int x1 = min(floordiv_i(pix.x + pix.z, tile_w) + 1, tiles_x);
   e.y0 = max(floordiv_i(pix.y - pix.w, tile_h), 0);
   e.rw = max(x1 - e.x0, 1);
-  e.gbase = slot_view[s] * tiles_per_view;
+  e.gbase = slot_view[s] << tile_bits;
   return e;
 }
 
-// A record's emission descriptor, packed: slot, its view's first global tile,
+// A record's emission descriptor, packed: slot, its view shifted above the
+// tile bits of the pair keys,
 // the first tile column and row of its rectangle (16 bits each) and the
 // rectangle's width in tiles.
 __device__ __forceinline__ uint4 pack_emit(const EmitSlot& e) {
@@ -293,7 +331,7 @@ __global__ __launch_bounds__(256) void k_slot_offsets(const uint32_t* __restrict
                                                       uint32_t* __restrict__ chunk_first,
                                                       const uint32_t* __restrict__ slot_view,
                                                       const int4* __restrict__ slot_pix, int tile_w, int tile_h,
-                                                      int tiles_x, uint32_t tiles_per_view,
+                                                      int tiles_x, int tile_bits,
                                                       uint4* __restrict__ emit_rec) {
   const uint32_t n = counters[0];
   const uint32_t l = threadIdx.x & 63;
@@ -312,7 +350,7 @@ __global__ __launch_bounds__(256) void k_slot_offsets(const uint32_t* __restrict
       slot_rec[(size_t)s * 4 + 3] = make_float4(__uint_as_float((uint32_t)off), 0.f, 0.f, 0.f);
       const uint64_t e = min(off + (uint64_t)c, pair_cap);
       for (uint64_t b = (off + EP_CHUNK - 1) / EP_CHUNK; b * EP_CHUNK < e; ++b) chunk_first[b] = j;
-      emit_rec[j] = pack_emit(emit_slot(s, slot_view, slot_pix, tile_w, tile_h, tiles_x, tiles_per_view));
+      emit_rec[j] = pack_emit(emit_slot(s, slot_view, slot_pix, tile_w, tile_h, tiles_x, tile_bits));
     }
   }
 }
@@ -344,7 +382,8 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_slot_keys(const uint32_t* __restr
 // chunk's first record and the next chunk's (named by k_slot_offsets) bound the
 // records that own its pairs, the block stages those records' first-pair
 // offsets in LDS, and each thread emits EP_PPT consecutive pairs, walking
-// forward from a binary search in LDS.  A pair's key is its global tile index, its value the record;
+// forward from a binary search in LDS.  A pair's key is (view << tile_bits) |
+// tile, its value the record;
 // pair k of a record is the k-th tile of its rectangle in row-major order, so
 // its emission position is the record's first pair plus that rank.
 
@@ -405,7 +444,7 @@ __global__ __launch_bounds__(256) void k_emit_pairs(const uint32_t* __restrict__
           const uint32_t rk = p - first;
           const uint32_t qy = udiv_small(rk, (uint32_t)e.rw);
           const int ty = e.y0 + (int)qy, tx = e.x0 + (int)(rk - qy * (uint32_t)e.rw);
-          ko[i] = ty < tiles_y ? e.gbase + (uint32_t)(ty * tiles_x + tx) : 0xffffffffu;
+          ko[i] = ty < tiles_y ? e.gbase | (uint32_t)(ty * tiles_x + tx) : 0xffffffffu;
           vo[i] = e.s;
         }
       }
@@ -452,20 +491,26 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, uint64_t n, uint32_t v) {
 }
 
 __global__ __launch_bounds__(KGS_BLOCK) void k_ranges(const uint32_t* __restrict__ counters,
-                                                      const uint32_t* __restrict__ keys, uint32_t n_tiles_all,
+                                                      const uint32_t* __restrict__ keys, int tile_bits,
+                                                      uint32_t tiles_per_view, uint32_t n_views,
                                                       uint2* __restrict__ ranges) {
   const uint32_t n = counters[1];
+  const uint32_t tmask = (1u << tile_bits) - 1u;
+  // view-major index of a key's (view, tile), or ~0 for padding
+  auto dense = [&](uint32_t t) { return (t >> tile_bits) < n_views ? (t >> tile_bits) * tiles_per_view + (t & tmask)
+                                                                   : 0xffffffffu; };
   for (uint32_t k = blockIdx.x * KGS_BLOCK + threadIdx.x; k < n; k += gridDim.x * KGS_BLOCK) {
     const uint32_t t = keys[k];
     const uint32_t tn = k + 1 < n ? keys[k + 1] : 0xffffffffu;
     if (t == tn) continue;
-    // k is the last pair of tile t and k + 1 the first of tile tn
-    if (t < n_tiles_all) ranges[t].y = k + 1;
-    if (tn < n_tiles_all) ranges[tn].x = k + 1;
+    // k is the last pair of group t and k + 1 the first of group tn
+    const uint32_t a = dense(t), b = dense(tn);
+    if (a != 0xffffffffu) ranges[a].y = k + 1;
+    if (b != 0xffffffffu) ranges[b].x = k + 1;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0 && n > 0) {
-    const uint32_t t0 = keys[0];
-    if (t0 < n_tiles_all) ranges[t0].x = 0;
+    const uint32_t t0 = dense(keys[0]);
+    if (t0 != 0xffffffffu) ranges[t0].x = 0;
   }
 }
 
@@ -515,24 +560,40 @@ __global__ __launch_bounds__(1024) void k_tile_order(const uint2* __restrict__ r
 }
 
 // ---------------------------------------------------------------- host side
+// Digit plan of a sort over `bits` key bits: the fewest passes of at most
+// max_dbits (8 or 10) bits each, of equal width.
+static void radix_plan(int bits, int max_dbits, int& passes, int& dbits) {
+  passes = (bits + max_dbits - 1) / max_dbits;
+  dbits = (bits + passes - 1) / passes;
+}
+
+template <typename K, int DB>
+static void radix_pass(kgs_ctx* ctx, const uint32_t* count, uint32_t nb, const K* kin, const uint32_t* vin,
+                       int shift, int dbits, uint32_t* total, K* kout, uint32_t* vout, hipStream_t st) {
+  constexpr int KPT = sizeof(K) == 8 ? 8 : 16;
+  hipLaunchKernelGGL((k_radix_hist<K, DB>), dim3(nb), dim3(256), 0, st, count, kin, shift, dbits, nb,
+                     ctx->radix_hist);
+  hipLaunchKernelGGL(k_radix_scan, dim3(1u << dbits), dim3(256), 0, st, ctx->radix_hist, nb, total);
+  hipLaunchKernelGGL((k_radix_scatter<K, KPT, DB>), dim3(nb), dim3(256), 0, st, count, kin, vin, shift, dbits, nb,
+                     (const uint32_t*)ctx->radix_hist, (const uint32_t*)total, kout, vout);
+}
+
 template <typename K>
 static int radix_sort(kgs_ctx* ctx, const uint32_t* count, uint64_t cap, K* keys[2], uint32_t* vals[2], int bits,
-                      hipStream_t st, const uint32_t* vals_in = nullptr) {
-  const int passes = (bits + 7) / 8;
-  const int dbits = (bits + passes - 1) / passes;
-  constexpr int KPT = sizeof(K) == 8 ? 8 : 16;
+                      int max_dbits, hipStream_t st, const uint32_t* vals_in = nullptr) {
+  int passes, dbits;
+  radix_plan(bits, max_dbits, passes, dbits);
   // partitions: fewer for small sorts (a multiple of 256, at most KGS_SORT_BLOCKS)
   const uint32_t nb = cap >= (8u << 20) ? KGS_SORT_BLOCKS : std::min<uint32_t>(512u, KGS_SORT_BLOCKS);
   int cur = 0;
   for (int p = 0; p < passes; ++p) {
-    const int shift = dbits * p;
-    uint32_t* total = ctx->radix_total + 256 * p;
-    hipLaunchKernelGGL(k_radix_hist<K>, dim3(nb), dim3(256), 0, st, count, (const K*)keys[cur], shift, dbits, nb,
-                       ctx->radix_hist);
-    hipLaunchKernelGGL(k_radix_scan, dim3(1u << dbits), dim3(256), 0, st, ctx->radix_hist, nb, total);
-    hipLaunchKernelGGL((k_radix_scatter<K, KPT>), dim3(nb), dim3(256), 0, st, count, (const K*)keys[cur],
-                       (p == 0 && vals_in) ? vals_in : (const uint32_t*)vals[cur], shift, dbits, nb,
-                       (const uint32_t*)ctx->radix_hist, (const uint32_t*)total, keys[cur ^ 1], vals[cur ^ 1]);
+    const K* kin = keys[cur];
+    const uint32_t* vin = (p == 0 && vals_in) ? vals_in : (const uint32_t*)vals[cur];
+    uint32_t* total = ctx->radix_total + KGS_RADIX_BUCKETS * p;
+    if (dbits > 8)
+      radix_pass<K, 10>(ctx, count, nb, kin, vin, dbits * p, dbits, total, keys[cur ^ 1], vals[cur ^ 1], st);
+    else
+      radix_pass<K, 8>(ctx, count, nb, kin, vin, dbits * p, dbits, total, keys[cur ^ 1], vals[cur ^ 1], st);
     cur ^= 1;
   }
   return cur;
@@ -546,6 +607,11 @@ kgs_status kgs_launch_bin_sort(kgs_ctx* ctx, hipStream_t st) {
   // 1. records by (view, depth); the projection wrote the keys, unless a sort
   // since has used them
   const SlotKeyLayout KL = slot_key_layout(ctx->cfg.near_z, ctx->cfg.far_z, V);
+  // tile bits of the pair keys: tiles < 2^tile_bits, so the padding key
+  // (all ones) sorts after every tile of the view
+  ctx->tile_bits = 1;
+  while ((1u << ctx->tile_bits) <= (uint32_t)ctx->n_tiles) ++ctx->tile_bits;
+  if (ctx->tile_bits + 7 > 32) return KGS_ERR_INVALID_ARG;  // 64 views above the tile bits, padding apart
   const int key_bits = KL.depth_bits + KL.view_bits;
   int sc;
   if (KL.key32()) {
@@ -554,13 +620,13 @@ kgs_status kgs_launch_bin_sort(kgs_ctx* ctx, hipStream_t st) {
       hipLaunchKernelGGL(k_slot_keys<uint32_t>, dim3(sgrid), dim3(KGS_BLOCK), 0, st, (const uint32_t*)ctx->counters,
                          (const float4*)ctx->slot_rec, (const uint32_t*)ctx->slot_view, KL.depth_lo, KL.depth_bits,
                          k32[0], ctx->slot_vals[0]);
-    sc = radix_sort<uint32_t>(ctx, ctx->counters, S, k32, ctx->slot_vals, key_bits, st);
+    sc = radix_sort<uint32_t>(ctx, ctx->counters, S, k32, ctx->slot_vals, key_bits, 8, st);
   } else {
     if (!ctx->slot_keys_ready)
       hipLaunchKernelGGL(k_slot_keys<uint64_t>, dim3(sgrid), dim3(KGS_BLOCK), 0, st, (const uint32_t*)ctx->counters,
                          (const float4*)ctx->slot_rec, (const uint32_t*)ctx->slot_view, KL.depth_lo, KL.depth_bits,
                          ctx->slot_keys[0], ctx->slot_vals[0]);
-    sc = radix_sort<uint64_t>(ctx, ctx->counters, S, ctx->slot_keys, ctx->slot_vals, key_bits, st);
+    sc = radix_sort<uint64_t>(ctx, ctx->counters, S, ctx->slot_keys, ctx->slot_vals, key_bits, 8, st);
   }
   ctx->slot_keys_ready = 0;
   const uint32_t* perm = ctx->slot_vals[sc];
@@ -575,29 +641,24 @@ kgs_status kgs_launch_bin_sort(kgs_ctx* ctx, hipStream_t st) {
   hipLaunchKernelGGL(k_slot_offsets, dim3(eg), dim3(256), 0, st, (const uint32_t*)ctx->counters, perm,
                      (const uint32_t*)ctx->group_part, n_groups, (const uint32_t*)ctx->slot_ntiles, P, pref,
                      ctx->slot_rec, ctx->chunk_first, (const uint32_t*)ctx->slot_view, (const int4*)ctx->slot_pix,
-                     ctx->cfg.tile_w, ctx->cfg.tile_h, ctx->tiles_x, (uint32_t)ctx->n_tiles, ctx->emit_rec);
+                     ctx->cfg.tile_w, ctx->cfg.tile_h, ctx->tiles_x, ctx->tile_bits, ctx->emit_rec);
   const uint64_t chunks = (P + EP_CHUNK - 1) / EP_CHUNK;
   const unsigned pg = (unsigned)std::min<uint64_t>(std::max<uint64_t>(chunks, 1), 4096);
   hipLaunchKernelGGL(k_emit_pairs, dim3(pg), dim3(256), 0, st, (const uint32_t*)ctx->counters,
                      (const uint4*)ctx->emit_rec, (const uint32_t*)pref, (const uint32_t*)ctx->chunk_first,
                      ctx->tiles_x, ctx->tiles_y, ctx->keys[0], ctx->pair_slot);
-  // 3. pairs by tile (stable)
-  // padding pairs carry key 0xffffffff; with n_tiles_all < 2^tile_bits they
-  // sort after every real pair
-  int tile_bits = 0;
-  while ((1u << tile_bits) <= n_tiles_all) ++tile_bits;
-  // the first pass reads the emission-order slots from pair_slot, which stays
-  // intact for the backward's segmented sums
-  const int cur = radix_sort<uint32_t>(ctx, ctx->counters + 1, P, ctx->keys, ctx->vals, std::max(tile_bits, 1), st,
+  // 3. pairs by tile within the view (stable): the view bits above stay in the
+  // keys but out of the sort, so a (view, tile) group stays in emission order
+  const int cur = radix_sort<uint32_t>(ctx, ctx->counters + 1, P, ctx->keys, ctx->vals, ctx->tile_bits, 10, st,
                                        ctx->pair_slot);
   ctx->sorted_buf = cur;
-  ctx->passes = (tile_bits + 7) / 8;
   const uint64_t nr = (uint64_t)n_tiles_all * 2;
   hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)std::min<uint64_t>((nr + 255) / 256, 1024)), dim3(256), 0, st,
                      (uint32_t*)ctx->ranges, nr, 0u);
   const unsigned rg = (unsigned)std::min<uint64_t>(std::max<uint64_t>((P + KGS_BLOCK - 1) / KGS_BLOCK, 1), 8192);
   hipLaunchKernelGGL(k_ranges, dim3(rg), dim3(KGS_BLOCK), 0, st, (const uint32_t*)ctx->counters,
-                     (const uint32_t*)ctx->keys[cur], n_tiles_all, ctx->ranges);
+                     (const uint32_t*)ctx->keys[cur], ctx->tile_bits, (uint32_t)ctx->n_tiles, (uint32_t)V,
+                     ctx->ranges);
   hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, st, (const uint2*)ctx->ranges, n_tiles_all,
                      ctx->tile_order);
   ctx->sorted_slot = ctx->vals[cur];

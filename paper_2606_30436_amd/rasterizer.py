@@ -258,7 +258,9 @@ class Rasterizer:
                    slot_rec=grab(b.slot_rec, ns, torch.float32, 16), slot_gid=grab(b.slot_gid, ns, torch.int32),
                    slot_view=grab(b.slot_view, ns, torch.int32), slot_pix=grab(b.slot_pix, ns, torch.int32, 4),
                    slot_pairoff=grab(b.slot_pairoff, ns, torch.int32), keys=grab(b.keys, npairs, torch.int32),
-                   sorted_slot=grab(b.sorted_slot, npairs, torch.int32), tiles_x=b.tiles_x, tiles_y=b.tiles_y)
+                   sorted_slot=grab(b.sorted_slot, npairs, torch.int32),
+                   ranges=grab(b.ranges, b.n_views * b.tiles_x * b.tiles_y, torch.int32, 2),
+                   tiles_x=b.tiles_x, tiles_y=b.tiles_y, tile_bits=b.tile_bits, n_views=b.n_views)
         return out
 
     # ---------------------------------------------------------- chunk

@@ -29,6 +29,8 @@ def _scene(name):
         return scenes.make_c1()
     if name == "tiny":
         return scenes.tiny_scene(seed=3, n=60, degree=3, W=70, H=45, n_views=2, pose_sigma=0.02)
+    if name == "wide":
+        return scenes.tiny_scene(seed=5, n=300, degree=1, W=600, H=450, n_views=3, pose_sigma=0.03)
     if name == "tiny_bg":
         return scenes.tiny_scene(seed=4, n=80, degree=2, W=53, H=37, n_views=3, pose_sigma=0.03)
     raise KeyError(name)
@@ -80,35 +82,55 @@ def test_project_records_match_oracle(name):
 
 
 @pytest.mark.parametrize("name,tile", [("c1", (16, 16)), ("c1", (8, 32)), ("tiny", (32, 8)), ("c1", (32, 16)),
-                                       ("tiny", (16, 32))])
+                                       ("tiny", (16, 32)), ("wide", (16, 16))])
 def test_binning_is_bit_exact(name, tile):
     """Sorted (key, Gaussian) list == the integer binning contract applied to
-    the GPU's own fp32 centres, extents and depths, sorted on the CPU."""
+    the GPU's own fp32 centres, extents and depths, sorted on the CPU.  The
+    tile counts per view take the pair sort through one pass of 4 to 9 bits
+    (the tiny views, c1) and two passes (1102 tiles of the wide views)."""
     sc = _scene(name)
     say(f"[gpu] binning {name} tile={tile}")
-    R = _rast(sc, tile=tile)
+    R = _rast(sc, tile=tile, pair_capacity=1 << 20)
     run_forward(R, sc)
-    b = R.buffers()
-    pix = b["slot_pix"].numpy()
-    depth_bits = b["slot_rec"].numpy()[:, 6].copy().view(np.uint32)
-    keys, gids = oracle.bin_keys(b["slot_view"].numpy(), b["slot_gid"].numpy(), pix[:, 0], pix[:, 1], pix[:, 2],
-                                 pix[:, 3], depth_bits, sc.width, sc.height, tile[0], tile[1])
-    ss = b["sorted_slot"].numpy()
-    gk = (b["keys"].numpy().view(np.uint32).astype(np.uint64) << np.uint64(32)) | depth_bits[ss].astype(np.uint64)
-    gg = b["slot_gid"].numpy()[ss]
-    assert len(gk) == len(keys) == b["n_pairs"]
-    assert np.array_equal(gk, keys)
-    assert np.array_equal(gg.astype(np.int64), gids)
+    _check_binning(R, sc, tile)
+
+
+def _view_major(b):
+    """The GPU's pairs (grouped by tile, then view) in view-major order.  Checks
+    on the way that each (view, tile) group is one contiguous run and that the
+    run is the group's range, and that every other range is empty."""
+    T = b["tiles_x"] * b["tiles_y"]
+    tb = b["tile_bits"]
+    assert T < (1 << tb) <= 2 * T
+    k = b["keys"].numpy().view(np.uint32).astype(np.int64)
+    view, tile = k >> tb, k & ((1 << tb) - 1)
+    assert (view < b["n_views"]).all() and (tile < T).all()
+    dense = view * T + tile
+    n = len(k)
+    starts = np.flatnonzero(np.r_[True, dense[1:] != dense[:-1]]) if n else np.zeros(0, np.int64)
+    ends = np.r_[starts[1:], n].astype(np.int64) if n else np.zeros(0, np.int64)
+    assert len(np.unique(dense[starts])) == len(starts)
+    r = b["ranges"].numpy().astype(np.int64)
+    assert r.shape == (b["n_views"] * T, 2)
+    assert np.array_equal(r[dense[starts], 0], starts) and np.array_equal(r[dense[starts], 1], ends)
+    empty = np.ones(len(r), bool)
+    empty[dense[starts]] = False
+    assert (r[empty] == 0).all()
+    order = np.argsort(dense, kind="stable")
+    return dense[order], order
 
 
 def _check_binning(R, sc, tile):
+    assert R.status() == 0
     b = R.buffers()
+    assert b["n_pairs"] > 0
     pix = b["slot_pix"].numpy()
     depth_bits = b["slot_rec"].numpy()[:, 6].copy().view(np.uint32)
     keys, gids = oracle.bin_keys(b["slot_view"].numpy(), b["slot_gid"].numpy(), pix[:, 0], pix[:, 1], pix[:, 2],
                                  pix[:, 3], depth_bits, sc.width, sc.height, tile[0], tile[1])
-    ss = b["sorted_slot"].numpy()
-    gk = (b["keys"].numpy().view(np.uint32).astype(np.uint64) << np.uint64(32)) | depth_bits[ss].astype(np.uint64)
+    dense, order = _view_major(b)
+    ss = b["sorted_slot"].numpy()[order]
+    gk = (dense.astype(np.uint64) << np.uint64(32)) | depth_bits[ss].astype(np.uint64)
     assert len(gk) == len(keys) == b["n_pairs"]
     assert np.array_equal(gk, keys)
     assert np.array_equal(b["slot_gid"].numpy()[ss].astype(np.int64), gids)
