@@ -56,10 +56,13 @@ __device__ __forceinline__ uint64_t digit_peers(bool valid, uint32_t d) {
   return ((uint64_t)hi << 32) | lo;
 }
 
-// per-block digit histograms hist[d][block]; the lowest lane of each group of
-// equal digits adds the group's size (one LDS add per distinct digit).  DB is
-// the widest digit the kernel takes (8 or 10 bits), dbits the pass's own.
-template <typename K, int DB>
+// per-block digit histograms hist[d][block].  With AGG the lowest lane of each
+// group of equal digits adds the group's size (one LDS add per distinct
+// digit: for keys whose digits repeat across the wave, like the depth keys'
+// upper digits); without, every key adds one (for keys of many distinct
+// digits, like tiles).  DB is the widest digit the kernel takes (8 or 10
+// bits), dbits the pass's own.
+template <typename K, int DB, bool AGG>
 __global__ __launch_bounds__(256) void k_radix_hist(const uint32_t* __restrict__ count, const K* __restrict__ keys,
                                                     int shift, int dbits, uint32_t nb, uint32_t* __restrict__ hist) {
   constexpr int R = 1 << DB;
@@ -96,8 +99,12 @@ __global__ __launch_bounds__(256) void k_radix_hist(const uint32_t* __restrict__
     for (int q = 0; q < KPI; ++q) {
       const bool valid = base + ((q / VW) * 256 + tid) * VW + (q % VW) < hi;
       const uint32_t d = (uint32_t)(kk[q] >> shift) & dmask;
-      const uint64_t peers = digit_peers<DB>(valid, d);
-      if (valid && (peers & lt) == 0ull) atomicAdd(&h[d], (uint32_t)__popcll(peers));
+      if constexpr (AGG) {
+        const uint64_t peers = digit_peers<DB>(valid, d);
+        if (valid && (peers & lt) == 0ull) atomicAdd(&h[d], (uint32_t)__popcll(peers));
+      } else {
+        if (valid) atomicAdd(&h[d], 1u);
+      }
     }
   }
   __syncthreads();
@@ -571,7 +578,8 @@ template <typename K, int DB>
 static void radix_pass(kgs_ctx* ctx, const uint32_t* count, uint32_t nb, const K* kin, const uint32_t* vin,
                        int shift, int dbits, uint32_t* total, K* kout, uint32_t* vout, hipStream_t st) {
   constexpr int KPT = sizeof(K) == 8 ? 8 : 16;
-  hipLaunchKernelGGL((k_radix_hist<K, DB>), dim3(nb), dim3(256), 0, st, count, kin, shift, dbits, nb,
+  // the 10-bit passes sort tiles, the 8-bit ones depth keys
+  hipLaunchKernelGGL((k_radix_hist<K, DB, DB == 8>), dim3(nb), dim3(256), 0, st, count, kin, shift, dbits, nb,
                      ctx->radix_hist);
   hipLaunchKernelGGL(k_radix_scan, dim3(1u << dbits), dim3(256), 0, st, ctx->radix_hist, nb, total);
   hipLaunchKernelGGL((k_radix_scatter<K, KPT, DB>), dim3(nb), dim3(256), 0, st, count, kin, vin, shift, dbits, nb,
