@@ -522,51 +522,66 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_gauss_gather(kgs_gaussians g, int
   double s_gam = 0.0;
   float s_gn = 0.f;
   int s_mr = 0;
-  for (int v = 0; v < V; ++v) {
-    const uint32_t u = vis[(int64_t)v * n + i];
-    if (u == 0u || u > n_slots) continue;
-    s_vc += 1u;
-    if (slot_om[u - 1u] == 0u) {
-      // a slot that blended nowhere adds nothing but its radius, which the
-      // projection stored (every slot has a tile, so the radius stands)
-      const int4 pix = slot_pix[u - 1u];
-      s_mr = max(s_mr, max(pix.z, pix.w));
-      continue;
-    }
-    const float4* r4 = slot_bwd + (size_t)(u - 1u) * (KGS_SLOT_WORDS / 4);
-    // words 16-23: counts, gradient norm, radius, masked colour gradient
-    const float4 q4 = r4[4], q5 = r4[5];
-    const uint32_t om = __float_as_uint(q4.y);
-    s_mr = max(s_mr, __float_as_int(q5.x));
-    float r[16];
+  // views in groups of eight: the slot indices of a group, then their counts,
+  // are loaded together, so a Gaussian waits on two loads per group instead
+  // of two per view
+  for (int v0 = 0; v0 < V; v0 += 8) {
+    uint32_t uu[8], oo[8];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const float4 q = r4[k];
-      r[4 * k] = q.x; r[4 * k + 1] = q.y; r[4 * k + 2] = q.z; r[4 * k + 3] = q.w;
+    for (int j = 0; j < 8; ++j) {
+      const uint32_t u = v0 + j < V ? vis[(int64_t)(v0 + j) * n + i] : 0u;
+      uu[j] = (u == 0u || u > n_slots) ? 0u : u;
     }
 #pragma unroll
-    for (int k = 0; k < 11; ++k) acc[k] += r[k];
-    // SH basis at this view's direction (as in the chain rule per slot)
-    float Y[16];
-    Y[0] = 0.f;
-    if (DEG > 0) {
-      float dv[3];
-      cam_offset(cams[v], mu, dv);
-      const float idist = 1.0f / sqrtf(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
-      sh_basis(DEG, dv[0] * idist, dv[1] * idist, dv[2] * idist, Y);
-    } else {
-      sh_basis(0, 0.f, 0.f, 1.f, Y);
-    }
+    for (int j = 0; j < 8; ++j) oo[j] = uu[j] ? slot_om[uu[j] - 1u] : 0u;
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      gsh[k][0] += Y[k] * q5.y;
-      gsh[k][1] += Y[k] * q5.z;
-      gsh[k][2] += Y[k] * q5.w;
+    for (int j = 0; j < 8; ++j) {
+      const uint32_t u = uu[j];
+      if (u == 0u) continue;
+      const int v = v0 + j;
+      s_vc += 1u;
+      if (oo[j] == 0u) {
+        // a slot that blended nowhere adds nothing but its radius, which the
+        // projection stored (every slot has a tile, so the radius stands)
+        const int4 pix = slot_pix[u - 1u];
+        s_mr = max(s_mr, max(pix.z, pix.w));
+        continue;
+      }
+      const float4* r4 = slot_bwd + (size_t)(u - 1u) * (KGS_SLOT_WORDS / 4);
+      // words 16-23: counts, gradient norm, radius, masked colour gradient
+      const float4 q4 = r4[4], q5 = r4[5];
+      const uint32_t om = __float_as_uint(q4.y);
+      s_mr = max(s_mr, __float_as_int(q5.x));
+      float r[16];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const float4 q = r4[k];
+        r[4 * k] = q.x; r[4 * k + 1] = q.y; r[4 * k + 2] = q.z; r[4 * k + 3] = q.w;
+      }
+#pragma unroll
+      for (int k = 0; k < 11; ++k) acc[k] += r[k];
+      // SH basis at this view's direction (as in the chain rule per slot)
+      float Y[16];
+      Y[0] = 0.f;
+      if (DEG > 0) {
+        float dv[3];
+        cam_offset(cams[v], mu, dv);
+        const float idist = 1.0f / sqrtf(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+        sh_basis(DEG, dv[0] * idist, dv[1] * idist, dv[2] * idist, Y);
+      } else {
+        sh_basis(0, 0.f, 0.f, 1.f, Y);
+      }
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        gsh[k][0] += Y[k] * q5.y;
+        gsh[k][1] += Y[k] * q5.z;
+        gsh[k][2] += Y[k] * q5.w;
+      }
+      s_om += om;
+      s_kap += __float_as_uint(q4.z);
+      if (view_loss) s_gam += (double)view_loss[v] * (double)om;
+      s_gn += q4.w;
     }
-    s_om += om;
-    s_kap += __float_as_uint(q4.z);
-    if (view_loss) s_gam += (double)view_loss[v] * (double)om;
-    s_gn += q4.w;
   }
   if (overwrite) {
     // the outputs start from zero: every Gaussian is written, seen or not
