@@ -375,7 +375,40 @@ __device__ __forceinline__ uint32_t pair_position(uint32_t first, float xb_f, fl
   return first + (uint32_t)((ty - y0) * (x1 - x0) + (tx - x0));
 }
 
-template <int B, int NW, bool DEPTH>
+// PPL pixels per lane: a wave covers a block of 8 PPL x 8 pixels, lane l the
+// pixels (8 p + l % 8, l / 8), p < PPL, of its block.  With two pixels per
+// lane a list entry's ten terms are summed over the lane's two pixels before
+// the one reduction over the wave, so the reductions per pixel halve; the
+// block is tested against the footprint as a whole.
+template <int PPL>
+__device__ __forceinline__ void wave_block(int tile_w, int w, int& sx, int& sy) {
+  const int nsx = tile_w / (8 * PPL);  // blocks per tile row, in row-major order
+  sx = (w % nsx) * (8 * PPL);
+  sy = (w / nsx) * 8;
+}
+
+// the wave's per-pixel L1 values -> partial[gt], in the order of l1_partial:
+// one butterfly per 8x8 sub-block, the NW PPL sub-blocks in row-major order
+template <int NW, int PPL>
+__device__ __forceinline__ void l1_partial_px(const float (&acc)[PPL], float* sh, double* __restrict__ partial,
+                                              int gt) {
+  constexpr int NS = NW * PPL;
+  static_assert(NS == 4 || NS == 8, "four or eight sub-blocks per tile");
+  const int w = threadIdx.x >> 6;
+#pragma unroll
+  for (int p = 0; p < PPL; ++p) {
+    const float a = wave_sum(acc[p]);
+    if ((threadIdx.x & 63) == 0) sh[w * PPL + p] = a;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double d = ((double)sh[0] + (double)sh[1]) + ((double)sh[2] + (double)sh[3]);
+    if (NS == 8) d += ((double)sh[4] + (double)sh[5]) + ((double)sh[6] + (double)sh[7]);
+    partial[gt] = d;
+  }
+}
+
+template <int B, int NW, bool DEPTH, int PPL>
 __global__ __launch_bounds__(64 * NW) void k_render_bwd(
     RenderParams P, const uint2* __restrict__ ranges, const uint32_t* __restrict__ tile_order,
     const uint32_t* __restrict__ sorted_slot,
@@ -387,68 +420,84 @@ __global__ __launch_bounds__(64 * NW) void k_render_bwd(
     float* __restrict__ dl_out, double* __restrict__ loss_partial) {
   // B records per batch, R = B / 64 per lane (B = 32: the first half of the lanes)
   constexpr int R = B >= 64 ? B / 64 : 1;
+  constexpr int BW = 8 * PPL;  // width of a wave's block
   static_assert(B == 32 || B == 64 || B == 128, "batch of 32, 64 or 128 records");
+  static_assert(PPL == 1 || PPL == 2, "one or two pixels per lane");
   // each wave's kept records of the batch, compacted, and their batch indices
   __shared__ float4 s_rec[NW][B][3];
   __shared__ __align__(16) uint8_t s_id[NW][B];
   __shared__ uint64_t s_keep[NW][R];
   __shared__ float s_part[NW][B][12];
   __shared__ int s_wmax[NW];
-  __shared__ float s_loss[NW];
+  __shared__ float s_loss[NW * PPL];
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
   const int gt = (int)tile_order[blockIdx.x];
   const int v = gt / P.n_tiles, t = gt - v * P.n_tiles;
   const int tx = t % P.tiles_x, ty = t / P.tiles_x;
   const int tile_x0 = tx * P.tile_w, tile_y0 = ty * P.tile_h;
   int sx, sy;
-  tile_subblock(P.tile_w, w, sx, sy);
+  wave_block<PPL>(P.tile_w, w, sx, sy);
   const int bx = tile_x0 + sx, by = tile_y0 + sy;
-  const int px = bx + (l & 7), py = by + (l >> 3);
-  const bool inside = px < P.W && py < P.H;
+  const int py = by + (l >> 3);
   const int ox = pix_origin(P.W), oy = pix_origin(P.H);
-  const float fpx = (float)(px - ox), fpy = (float)(py - oy);
+  const float fpy = (float)(py - oy);
   const uint2 rg = ranges[gt];
   const uint32_t start = rg.x, end = rg.y;
   // per-pixel inputs
-  int lastp = 0;
-  float Co0 = 0.f, Co1 = 0.f, Co2 = 0.f, Do = 0.f, g0 = 0.f, g1 = 0.f, g2 = 0.f, gD = 0.f, gAT = 0.f;
-  bool M = false;
-  float l1acc = 0.f;
-  if (inside) {
-    const size_t npix = (size_t)P.W * P.H;
-    const size_t pix = (size_t)v * npix + (size_t)py * P.W + px;
-    const size_t cpix = (size_t)v * 3 * npix + (size_t)py * P.W + px;
-    lastp = last[pix];
-    Co0 = color[cpix];
-    Co1 = color[cpix + npix];
-    Co2 = color[cpix + 2 * npix];
-    Do = depth[pix];
-    if (fuse_l1) {
-      // the L1 loss against target, its gradient and its per-tile partial,
-      // exactly as the loss kernel forms them
-      l1_pixel(color, target, cpix, npix, 1.0f / (float)(3 * npix), g0, g1, g2, l1acc);
-      if (dl_out) {
-        dl_out[cpix] = g0;
-        dl_out[cpix + npix] = g1;
-        dl_out[cpix + 2 * npix] = g2;
+  // dL/dalpha_j = T_j (g . c_j) - (g . (C - C_j)) / (1 - alpha_j) + gAT / (1 - alpha_j)
+  // with C the final colour (and depth) and C_j its part from Gaussians up to j;
+  // Rj = gAT - g . C + g . C_j is kept as one running scalar per pixel
+  int lastp[PPL];
+  float fpx[PPL], g0[PPL], g1[PPL], g2[PPL], gD[PPL], T[PPL], Rj[PPL], l1acc[PPL];
+  uint64_t Mbal[PPL];  // the error mask of the wave's pixels
+  int wmax = 0;
+#pragma unroll
+  for (int p = 0; p < PPL; ++p) {
+    const int px = bx + 8 * p + (l & 7);
+    fpx[p] = (float)(px - ox);
+    lastp[p] = 0;
+    float Co0 = 0.f, Co1 = 0.f, Co2 = 0.f, Do = 0.f, gAT = 0.f;
+    g0[p] = g1[p] = g2[p] = gD[p] = 0.f;
+    l1acc[p] = 0.f;
+    bool M = false;
+    if (px < P.W && py < P.H) {
+      const size_t npix = (size_t)P.W * P.H;
+      const size_t pix = (size_t)v * npix + (size_t)py * P.W + px;
+      const size_t cpix = (size_t)v * 3 * npix + (size_t)py * P.W + px;
+      lastp[p] = last[pix];
+      Co0 = color[cpix];
+      Co1 = color[cpix + npix];
+      Co2 = color[cpix + 2 * npix];
+      Do = depth[pix];
+      if (fuse_l1) {
+        // the L1 loss against target, its gradient and its per-tile partial,
+        // exactly as the loss kernel forms them
+        l1_pixel(color, target, cpix, npix, 1.0f / (float)(3 * npix), g0[p], g1[p], g2[p], l1acc[p]);
+        if (dl_out) {
+          dl_out[cpix] = g0[p];
+          dl_out[cpix + npix] = g1[p];
+          dl_out[cpix + 2 * npix] = g2[p];
+        }
+      } else {
+        g0[p] = dl_dcolor[cpix];
+        g1[p] = dl_dcolor[cpix + npix];
+        g2[p] = dl_dcolor[cpix + 2 * npix];
       }
-    } else {
-      g0 = dl_dcolor[cpix];
-      g1 = dl_dcolor[cpix + npix];
-      g2 = dl_dcolor[cpix + 2 * npix];
+      if (dl_ddepth) gD[p] = dl_ddepth[pix];
+      // opacity image A = 1 - T_final: dA/dalpha_j = T_final / (1 - alpha_j)
+      if (dl_dalpha) gAT = dl_dalpha[pix] * tfinal[pix];
+      if (target) {
+        const float err = fabsf(target[cpix] - Co0) + fabsf(target[cpix + npix] - Co1) +
+                          fabsf(target[cpix + 2 * npix] - Co2);
+        M = err > tau_err;
+      }
     }
-    if (dl_ddepth) gD = dl_ddepth[pix];
-    // opacity image A = 1 - T_final: dA/dalpha_j = T_final / (1 - alpha_j)
-    if (dl_dalpha) gAT = dl_dalpha[pix] * tfinal[pix];
-    if (target) {
-      const float err = fabsf(target[cpix] - Co0) + fabsf(target[cpix + npix] - Co1) +
-                        fabsf(target[cpix + 2 * npix] - Co2);
-      M = err > tau_err;
-    }
+    Mbal[p] = ballot64(M);
+    T[p] = 1.0f;
+    Rj[p] = gAT - (g0[p] * Co0 + g1[p] * Co1 + g2[p] * Co2 + gD[p] * Do);
+    wmax = max(wmax, lastp[p]);
   }
-  if (fuse_l1) l1_partial<NW>(l1acc, s_loss, loss_partial, gt);
-  const uint64_t Mbal = ballot64(M);   // the error mask of the wave's pixels
-  int wmax = lastp;
+  if (fuse_l1) l1_partial_px<NW, PPL>(l1acc, s_loss, loss_partial, gt);
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) wmax = max(wmax, __shfl_xor(wmax, o, 64));
   wmax = __builtin_amdgcn_readfirstlane(wmax);
@@ -458,15 +507,10 @@ __global__ __launch_bounds__(64 * NW) void k_render_bwd(
 #pragma unroll
   for (int k = 1; k < NW; ++k) bmax = max(bmax, s_wmax[k]);
   const uint32_t pend = start + (uint32_t)bmax;
-  // dL/dalpha_j = T_j (g . c_j) - (g . (C - C_j)) / (1 - alpha_j) + gAT / (1 - alpha_j)
-  // with C the final colour (and depth) and C_j its part from Gaussians up to j;
-  // Rj = gAT - g . C + g . C_j is kept as one running scalar
-  float T = 1.0f;
-  float Rj = gAT - (g0 * Co0 + g1 * Co1 + g2 * Co2 + gD * Do);
   uint32_t base = start;
   for (; base < pend; base += B) {
     // stage: every wave reads the batch's records (lane l: records l, l + 64,
-    // ...) and keeps, compacted in order, those that reach its sub-block; the
+    // ...) and keeps, compacted in order, those that reach its block; the
     // first wave also keeps what the pair records need
     uint32_t len = 0;
     float xbw[R], ybw[R];
@@ -491,9 +535,9 @@ __global__ __launch_bounds__(64 * NW) void k_render_bwd(
         const uint32_t xb = __float_as_uint(r1.w), yb = __float_as_uint(r2.w);
         const int xlo = (int)(int16_t)(xb & 0xffffu), xhi = (int)(int16_t)(xb >> 16);
         const int ylo = (int)(int16_t)(yb & 0xffffu), yhi = (int)(int16_t)(yb >> 16);
-        if (xlo <= bx + 7 && xhi >= bx && ylo <= by + 7 && yhi >= by) {
+        if (xlo <= bx + BW - 1 && xhi >= bx && ylo <= by + 7 && yhi >= by) {
           const float fx0 = (float)(bx - ox) - r0.x, fy0 = (float)(by - oy) - r0.y;
-          keep = footprint_meets_box(fx0, fx0 + 7.0f, fy0, fy0 + 7.0f, r0, r1, P.log2_amin);
+          keep = footprint_meets_box(fx0, fx0 + (float)(BW - 1), fy0, fy0 + 7.0f, r0, r1, P.log2_amin);
         }
       }
       const uint64_t bal = ballot64(keep);
@@ -526,43 +570,84 @@ __global__ __launch_bounds__(64 * NW) void k_render_bwd(
       const bool use_b = has_b && rel0 + tb < wmax;
       // both entries' records at once (the second is a repeat of the first when absent)
       const float4 ra0 = s_rec[w][j][0], ra1 = s_rec[w][j][1], rb0 = s_rec[w][jb][0], rb1 = s_rec[w][jb][1];
-      float dya, ua, dyb, ub;
-      const float ea = log2_alpha(fpx, fpy, ra0, ra1.x, ra1.y, dya, ua);
-      const float eb = log2_alpha(fpx, fpy, rb0, rb1.x, rb1.y, dyb, ub);
-      const bool bla = rel0 + ta < lastp && ea >= P.log2_amin;
-      const bool blb = use_b && rel0 + tb < lastp && eb >= P.log2_amin;
-      const uint64_t bba = ballot64(bla), bbb = ballot64(blb);
+      float ea[PPL], ua[PPL], dya[PPL], eb[PPL], ub[PPL], dyb[PPL];
+      bool bla[PPL], blb[PPL];
+      bool anya = false, anyb = false;
+#pragma unroll
+      for (int p = 0; p < PPL; ++p) {
+        ea[p] = log2_alpha(fpx[p], fpy, ra0, ra1.x, ra1.y, dya[p], ua[p]);
+        eb[p] = log2_alpha(fpx[p], fpy, rb0, rb1.x, rb1.y, dyb[p], ub[p]);
+        bla[p] = rel0 + ta < lastp[p] && ea[p] >= P.log2_amin;
+        blb[p] = use_b && rel0 + tb < lastp[p] && eb[p] >= P.log2_amin;
+        anya |= bla[p];
+        anyb |= blb[p];
+      }
+      const uint64_t bba = ballot64(anya), bbb = ballot64(anyb);
+      // blended pixels of the wave, and those under the error mask
+      uint32_t na = 0u, nma = 0u, nb = 0u, nmb = 0u;
+#pragma unroll
+      for (int p = 0; p < PPL; ++p) {
+        const uint64_t ba = PPL == 1 ? bba : ballot64(bla[p]), bb = PPL == 1 ? bbb : ballot64(blb[p]);
+        na += (uint32_t)__popcll(ba);
+        nma += (uint32_t)__popcll(ba & Mbal[p]);
+        nb += (uint32_t)__popcll(bb);
+        nmb += (uint32_t)__popcll(bb & Mbal[p]);
+      }
       if (bba != 0ull && bbb != 0ull) {
         float x[20];
         const float4 ra2 = s_rec[w][j][2], rb2 = s_rec[w][jb][2];
-        blend_terms<DEPTH>(ea, ua, dya, bla, ra1, ra2, P.amax, g0, g1, g2, gD, T, Rj, x);
-        blend_terms<DEPTH>(eb, ub, dyb, blb, rb1, rb2, P.amax, g0, g1, g2, gD, T, Rj, x + 10);
-        const uint64_t bma = bba & Mbal, bmb = bbb & Mbal;
+#pragma unroll
+        for (int p = 0; p < PPL; ++p) {
+          if (p == 0) {
+            blend_terms<DEPTH>(ea[p], ua[p], dya[p], bla[p], ra1, ra2, P.amax, g0[p], g1[p], g2[p], gD[p], T[p],
+                               Rj[p], x);
+            blend_terms<DEPTH>(eb[p], ub[p], dyb[p], blb[p], rb1, rb2, P.amax, g0[p], g1[p], g2[p], gD[p], T[p],
+                               Rj[p], x + 10);
+          } else {
+            float y[20];
+            blend_terms<DEPTH>(ea[p], ua[p], dya[p], bla[p], ra1, ra2, P.amax, g0[p], g1[p], g2[p], gD[p], T[p],
+                               Rj[p], y);
+            blend_terms<DEPTH>(eb[p], ub[p], dyb[p], blb[p], rb1, rb2, P.amax, g0[p], g1[p], g2[p], gD[p], T[p],
+                               Rj[p], y + 10);
+#pragma unroll
+            for (int k = 0; k < 20; ++k) x[k] += y[k];
+          }
+        }
         int idx;
         bool valid;
         wave_reduce20<DEPTH ? 10 : 9>(x, l, idx, valid);
         if (valid) s_part[w][idx < 10 ? ta : tb][idx < 10 ? idx : idx - 10] = x[0];
         if (l == 0) {
-          s_part[w][ta][10] = __uint_as_float((uint32_t)__popcll(bba));
-          s_part[w][ta][11] = __uint_as_float((uint32_t)__popcll(bma));
-          s_part[w][tb][10] = __uint_as_float((uint32_t)__popcll(bbb));
-          s_part[w][tb][11] = __uint_as_float((uint32_t)__popcll(bmb));
+          s_part[w][ta][10] = __uint_as_float(na);
+          s_part[w][ta][11] = __uint_as_float(nma);
+          s_part[w][tb][10] = __uint_as_float(nb);
+          s_part[w][tb][11] = __uint_as_float(nmb);
         }
       } else if ((bba | bbb) != 0ull) {
         const bool first = bba != 0ull;
         const int tt = first ? ta : tb, tz = first ? tb : ta;
-        const bool bl = first ? bla : blb;
+        const float4 q1 = first ? ra1 : rb1, q2 = s_rec[w][first ? j : jb][2];
         float x[10];
-        blend_terms<DEPTH>(first ? ea : eb, first ? ua : ub, first ? dya : dyb, bl, first ? ra1 : rb1,
-                    s_rec[w][first ? j : jb][2], P.amax, g0, g1, g2, gD, T, Rj, x);
-        const uint64_t bm = (first ? bba : bbb) & Mbal;
+#pragma unroll
+        for (int p = 0; p < PPL; ++p) {
+          if (p == 0) {
+            blend_terms<DEPTH>(first ? ea[p] : eb[p], first ? ua[p] : ub[p], first ? dya[p] : dyb[p],
+                               first ? bla[p] : blb[p], q1, q2, P.amax, g0[p], g1[p], g2[p], gD[p], T[p], Rj[p], x);
+          } else {
+            float y[10];
+            blend_terms<DEPTH>(first ? ea[p] : eb[p], first ? ua[p] : ub[p], first ? dya[p] : dyb[p],
+                               first ? bla[p] : blb[p], q1, q2, P.amax, g0[p], g1[p], g2[p], gD[p], T[p], Rj[p], y);
+#pragma unroll
+            for (int k = 0; k < 10; ++k) x[k] += y[k];
+          }
+        }
         int idx;
         bool valid;
         wave_reduce10(x, l, idx, valid);
         if (valid) s_part[w][tt][idx] = x[0];
         if (l == 0) {
-          s_part[w][tt][10] = __uint_as_float((uint32_t)__popcll(first ? bba : bbb));
-          s_part[w][tt][11] = __uint_as_float((uint32_t)__popcll(bm));
+          s_part[w][tt][10] = __uint_as_float(first ? na : nb);
+          s_part[w][tt][11] = __uint_as_float(first ? nma : nmb);
         }
         // the other entry blends nowhere in this wave: its partial is zero
         if (use_b && l < 12) s_part[w][tz][l] = 0.f;
@@ -691,26 +776,34 @@ kgs_status kgs_launch_render_bwd(kgs_ctx* ctx, const kgs_image* fwd, const float
   const uint64_t lw = ((uint64_t)ctx->cfg.pair_capacity + 15) / 16;
   hipLaunchKernelGGL(k_clear_live, dim3((unsigned)std::min<uint64_t>(std::max<uint64_t>((lw + 255) / 256, 1), 1024)),
                      dim3(256), 0, st, (const uint32_t*)ctx->counters, (uint4*)ctx->pair_live);
-#define KGS_BWD(BB, NWV)                                                                                         \
-  if (dl_ddepth) { KGS_BWD_D(BB, NWV, true); } else { KGS_BWD_D(BB, NWV, false); }
-#define KGS_BWD_D(BB, NWV, DD)                                                                                   \
-  hipLaunchKernelGGL((k_render_bwd<BB, NWV, DD>), dim3(grid), dim3(64 * NWV), 0, st, P, (const uint2*)ctx->ranges,   \
-                     (const uint32_t*)ctx->tile_order,                                                           \
+#define KGS_BWD(BB, NWV, PX)                                                                                     \
+  if (dl_ddepth) { KGS_BWD_D(BB, NWV, true, PX); } else { KGS_BWD_D(BB, NWV, false, PX); }
+#define KGS_BWD_D(BB, NWV, DD, PX)                                                                               \
+  hipLaunchKernelGGL((k_render_bwd<BB, NWV, DD, PX>), dim3(grid), dim3(64 * NWV), 0, st, P,                      \
+                     (const uint2*)ctx->ranges, (const uint32_t*)ctx->tile_order,                                \
                      (const uint32_t*)ctx->sorted_slot,                                                           \
                      (const float4*)ctx->slot_rec,                                                                \
                      (const float*)fwd->color, (const float*)fwd->depth, (const float*)fwd->t_final,              \
                      (const int32_t*)fwd->last, dl_dcolor, dl_ddepth, dl_dalpha, target, tau_err, ctx->pair_grad,  \
                      ctx->pair_live, fuse_l1 ? 1 : 0, dl_out, ctx->loss_partial)
-  if (tile_waves(ctx) == 8) {
+  // two pixels per lane wherever the tile is at least 16 wide (a wave per 16x8
+  // block); the 8-wide tile keeps one (a wave per 8x8 block)
+  if (ctx->cfg.tile_w < 16) {
     switch (ctx->cfg.batch) {
-      case 32: KGS_BWD(32, 8); break;
-      default: KGS_BWD(64, 8); break;
+      case 32: KGS_BWD(32, 4, 1); break;
+      case 64: KGS_BWD(64, 4, 1); break;
+      default: KGS_BWD(128, 4, 1); break;
+    }
+  } else if (tile_waves(ctx) == 8) {
+    switch (ctx->cfg.batch) {
+      case 32: KGS_BWD(32, 4, 2); break;
+      default: KGS_BWD(64, 4, 2); break;
     }
   } else {
     switch (ctx->cfg.batch) {
-      case 32: KGS_BWD(32, 4); break;
-      case 64: KGS_BWD(64, 4); break;
-      default: KGS_BWD(128, 4); break;
+      case 32: KGS_BWD(32, 2, 2); break;
+      case 64: KGS_BWD(64, 2, 2); break;
+      default: KGS_BWD(128, 2, 2); break;
     }
   }
 #undef KGS_BWD
