@@ -106,7 +106,9 @@ typedef struct kgs_config {
   float bg[3];
   int32_t width, height;    /* image size of every view */
   int32_t max_views;        /* 1..64 views per call */
-  int32_t pad_;
+  int32_t px_per_lane;      /* compositing backward: pixels per lane, 1 (a wave per 8x8 block) or 2 (a
+                               wave per 16x8 block, tiles at least 16 wide); 0 picks 2 where the
+                               launch has at least 4096 such waves (16 per CU), else 1 */
   int64_t max_gaussians;
   int64_t slot_capacity;    /* visible (view, Gaussian) records per call */
   int64_t pair_capacity;    /* (tile, Gaussian) pairs per call, < 2^32 */

@@ -30,7 +30,7 @@ class KgsConfig(ctypes.Structure):
     _fields_ = [("tile_w", c_int32), ("tile_h", c_int32), ("batch", c_int32), ("sh_degree", c_int32),
                 ("alpha_min", c_float), ("alpha_max", c_float), ("t_min", c_float), ("near_z", c_float),
                 ("eps2d", c_float), ("guard", c_float), ("rect_margin", c_float), ("far_z", c_float), ("bg", c_float * 3),
-                ("width", c_int32), ("height", c_int32), ("max_views", c_int32), ("pad_", c_int32),
+                ("width", c_int32), ("height", c_int32), ("max_views", c_int32), ("px_per_lane", c_int32),
                 ("max_gaussians", c_int64), ("slot_capacity", c_int64), ("pair_capacity", c_int64)]
 
 

@@ -113,6 +113,7 @@ kgs_status config_check(const kgs_config* c) {
   if (!c) return KGS_ERR_INVALID_ARG;
   if (!tiling_ok(c->tile_w, c->tile_h, c->batch) || !batch_ok(c->batch)) return KGS_ERR_INVALID_ARG;
   if (c->sh_degree < 0 || c->sh_degree > 3) return KGS_ERR_INVALID_ARG;
+  if (c->px_per_lane < 0 || c->px_per_lane > 2) return KGS_ERR_INVALID_ARG;
   if (c->width <= 0 || c->height <= 0 || c->width > 32000 || c->height > 32000) return KGS_ERR_INVALID_ARG;
   if (c->max_views < 1 || c->max_views > KGS_MAX_VIEWS) return KGS_ERR_INVALID_ARG;
   if (c->max_gaussians < 0 || c->max_gaussians >= (int64_t(1) << 32)) return KGS_ERR_INVALID_ARG;

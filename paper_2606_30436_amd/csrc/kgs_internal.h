@@ -15,6 +15,7 @@
 #define KGS_SORT_BLOCKS 1024          // fixed grid (one partition per block) of the radix sort passes
 #define KGS_MAX_PASSES 8
 #define KGS_RADIX_BUCKETS 1024      // widest digit of a radix pass: 10 bits
+#define KGS_BWD_TWO_PX_MIN_WAVES 4096  // compositing backward, px_per_lane 0: two pixels per lane from 16 waves per CU
 #define KGS_POSE_BLOCKS 256           // pieces per view of the pose reduction
 #define KGS_SLOT_WORDS 24             // words of a slot's backward record
 

@@ -786,13 +786,26 @@ kgs_status kgs_launch_render_bwd(kgs_ctx* ctx, const kgs_image* fwd, const float
                      (const float*)fwd->color, (const float*)fwd->depth, (const float*)fwd->t_final,              \
                      (const int32_t*)fwd->last, dl_dcolor, dl_ddepth, dl_dalpha, target, tau_err, ctx->pair_grad,  \
                      ctx->pair_live, fuse_l1 ? 1 : 0, dl_out, ctx->loss_partial)
-  // two pixels per lane wherever the tile is at least 16 wide (a wave per 16x8
-  // block); the 8-wide tile keeps one (a wave per 8x8 block)
-  if (ctx->cfg.tile_w < 16) {
-    switch (ctx->cfg.batch) {
-      case 32: KGS_BWD(32, 4, 1); break;
-      case 64: KGS_BWD(64, 4, 1); break;
-      default: KGS_BWD(128, 4, 1); break;
+  // two pixels per lane (a wave per 16x8 block) where the tile is at least 16
+  // wide and, unless the configuration asks for it, the launch still has
+  // waves to spare: at least 16 per CU (one view at 1242x375 has 3744, eight
+  // views 30k).  Otherwise one pixel per lane, a wave per 8x8 block, twice the
+  // waves.
+  const uint64_t waves2 = (uint64_t)grid * (uint64_t)(ctx->cfg.tile_w * ctx->cfg.tile_h / 128);
+  const int ppl = ctx->cfg.px_per_lane;
+  const bool two = ctx->cfg.tile_w >= 16 && (ppl == 2 || (ppl == 0 && waves2 >= KGS_BWD_TWO_PX_MIN_WAVES));
+  if (!two) {
+    if (tile_waves(ctx) == 8) {
+      switch (ctx->cfg.batch) {
+        case 32: KGS_BWD(32, 8, 1); break;
+        default: KGS_BWD(64, 8, 1); break;
+      }
+    } else {
+      switch (ctx->cfg.batch) {
+        case 32: KGS_BWD(32, 4, 1); break;
+        case 64: KGS_BWD(64, 4, 1); break;
+        default: KGS_BWD(128, 4, 1); break;
+      }
     }
   } else if (tile_waves(ctx) == 8) {
     switch (ctx->cfg.batch) {

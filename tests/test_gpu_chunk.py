@@ -72,10 +72,14 @@ def _rast(sc, **kw):
     return Rasterizer(sc.width, sc.height, max_views=sc.n_views, max_gaussians=sc.n, far_z=FAR, **kw)
 
 
-def test_chunk_run_equals_the_steps(chunk):
+@pytest.mark.parametrize("px", [1, 2])
+def test_chunk_run_equals_the_steps(chunk, px):
+    """The chunk (loss fused into the compositing backward) against the steps
+    called one by one (the loss kernel on its own), with one and two pixels per
+    lane in the backward."""
     sc = chunk
-    say(f"[gpu] chunk_run vs steps n={sc.n} V={sc.n_views}")
-    R = _rast(sc)
+    say(f"[gpu] chunk_run vs steps n={sc.n} V={sc.n_views} px_per_lane={px}")
+    R = _rast(sc, px_per_lane=px)
     b = Bufs(sc, R)
     # zero_accumulators: whatever the accumulators held must not matter
     for t in (b.grads.means, b.grads.log_scales, b.grads.quats, b.grads.logits, b.grads.sh, b.pose,
@@ -112,7 +116,7 @@ def test_graph_replays_equal_eager_runs(chunk):
     chunk_run on the same values, bit for bit."""
     sc = chunk
     say("[gpu] graph replays")
-    R = _rast(sc)
+    R = _rast(sc, px_per_lane=2)
     b = Bufs(sc, R)
     d = b.desc()
     graph = R.chunk_capture(d)

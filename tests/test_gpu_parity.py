@@ -287,15 +287,17 @@ def _involved(sc, cfg):
     return bad
 
 
+@pytest.mark.parametrize("px", [1, 2])
 @pytest.mark.parametrize("name,depth", [("c1", True), ("tiny", True), ("tiny_bg", True), ("c1", False),
                                         ("tiny", False)])
-def test_render_backward_matches_oracle(name, depth):
+def test_render_backward_matches_oracle(name, depth, px):
     """With and without a depth gradient (the backward has a variant that
-    leaves the depth terms out when none is passed)."""
+    leaves the depth terms out when none is passed), with one and two pixels
+    per lane."""
     sc = _scene(name)
     kw = {"bg": (0.2, 0.5, 0.9)} if name == "tiny_bg" else {}
-    say(f"[gpu] render bwd {name} depth={depth}")
-    R = _rast(sc, **kw)
+    say(f"[gpu] render bwd {name} depth={depth} px_per_lane={px}")
+    R = _rast(sc, px_per_lane=px, **kw)
     g, cams, xi, img = run_forward(R, sc)
     rng = np.random.default_rng(7)
     V, H, W = sc.n_views, sc.height, sc.width
@@ -395,27 +397,26 @@ def test_tile_shapes_and_batches_give_the_same_gradients():
     dLdC = torch.from_numpy(rng.normal(size=(V, 3, H, W)).astype(np.float32)).cuda()
     dLdD = torch.from_numpy((rng.normal(size=(V, H, W)) * 0.05).astype(np.float32)).cuda()
     ref = None
-    for tile in ((16, 16), (8, 32), (32, 8), (32, 16), (16, 32)):
-        for batch in (32, 64, 128):
-            if tile[0] * tile[1] == 512 and batch > 64:
-                continue
-            R = _rast(sc, tile=tile, batch=batch)
-            g, cams, xi, img = run_forward(R, sc)
-            if ref is None:
-                keys = R.buffers()["keys"].numpy()
-                longest = int(np.unique(keys, return_counts=True)[1].max())
-                say(f"  longest tile list {longest}")
-                assert longest > 256
-            grads = g.zeros_like()
-            pose_grad = torch.zeros(V, 6, device="cuda")
-            R.render_bwd(g, cams, xi, img, dLdC, dLdD, grads=grads, pose_grad=pose_grad)
-            torch.cuda.synchronize()
-            out = {k: getattr(grads, k).cpu().numpy().astype(np.float64)
-                   for k in ("means", "log_scales", "quats", "logits", "sh")}
-            out["pose"] = pose_grad.cpu().numpy().astype(np.float64)
-            if ref is None:
-                ref = out
-                continue
-            for k in out:
-                rel = np.linalg.norm(out[k] - ref[k]) / np.linalg.norm(ref[k])
-                assert rel < 1e-5, (tile, batch, k, rel)
+    cases = [(t, b, x) for t in ((16, 16), (8, 32), (32, 8), (32, 16), (16, 32)) for b in (32, 64, 128)
+             for x in (1, 2) if not (t[0] * t[1] == 512 and b > 64) and not (t[0] < 16 and x == 2)]
+    for tile, batch, px in cases:
+        R = _rast(sc, tile=tile, batch=batch, px_per_lane=px)
+        g, cams, xi, img = run_forward(R, sc)
+        if ref is None:
+            keys = R.buffers()["keys"].numpy()
+            longest = int(np.unique(keys, return_counts=True)[1].max())
+            say(f"  longest tile list {longest}")
+            assert longest > 256
+        grads = g.zeros_like()
+        pose_grad = torch.zeros(V, 6, device="cuda")
+        R.render_bwd(g, cams, xi, img, dLdC, dLdD, grads=grads, pose_grad=pose_grad)
+        torch.cuda.synchronize()
+        out = {k: getattr(grads, k).cpu().numpy().astype(np.float64)
+               for k in ("means", "log_scales", "quats", "logits", "sh")}
+        out["pose"] = pose_grad.cpu().numpy().astype(np.float64)
+        if ref is None:
+            ref = out
+            continue
+        for k in out:
+            rel = np.linalg.norm(out[k] - ref[k]) / np.linalg.norm(ref[k])
+            assert rel < 1e-5, (tile, batch, px, k, rel)
