@@ -97,7 +97,8 @@ typedef struct kgs_camera {
  * only inside its level's distance range): camera depths >= far_z are culled. */
 typedef struct kgs_config {
   int32_t tile_w, tile_h;   /* 16x16, 8x32, 32x8 (four waves per compositing workgroup)
-                               or 32x16, 16x32 (eight waves) */
+                               or 32x16, 16x32 (eight waves); the backward with two
+                               pixels per lane runs half as many */
   int32_t batch;            /* Gaussians staged per LDS batch of the backward: 32, 64
                                or 128 (at most 64 with 512-pixel tiles); the forward
                                stages 64 at a time in every wave */
