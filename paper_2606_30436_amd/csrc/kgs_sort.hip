@@ -1,20 +1,24 @@
 // Tile binning and depth sort.
 //
-// The order the compositing needs is (view, tile, depth, Gaussian index).  It
-// is built in two small sorts instead of one wide one:
+// The compositing needs, for every (view, tile), the Gaussians that touch it
+// in (depth, Gaussian index) order.  That is built in two small sorts instead
+// of one wide one:
 //   1. the projected records (slots, already in (view, Gaussian) order) are
 //      sorted by (view, fp32 depth) -- 30-bit keys at near 0.2, far 80 and
 //      8 views (the depth bits offset from near), over S records;
 //   2. pairs are emitted in that depth order (a scan of the records' tile
 //      counts gives each record's first pair), one per tile of the record's
-//      rectangle, keyed by the global tile index only;
-//   3. the pairs are sorted stably by tile -- 14 bits at 1242x375 x 8 views,
-//      two 7-bit passes over 4-byte keys and values.
-// Stability makes the result identical to one sort by the full key.
+//      rectangle, keyed by (view << tile_bits) | tile;
+//   3. the pairs are sorted stably by the tile bits only -- 936 tiles per view
+//      at 1242x375 and 32x16 tiles, one 10-bit pass over 4-byte keys and
+//      values.  Emission order is view-major, so every (view, tile) group
+//      comes out contiguous and in depth order (the groups ordered by tile,
+//      then view); stability makes each group identical to its run in one
+//      sort by the full key.
 //
 // The radix sort is LSD, reduce-then-scan, with one contiguous partition per
-// block; a pass of B total bits uses ceil(B / 8) passes of equal digit width
-// (14 bits: two 7-bit passes of 128 buckets).  The scatter ranks a tile of
+// block; B key bits take the fewest passes of at most 8 (depth keys) or 10
+// (tile keys) bits, of equal width.  The scatter ranks a tile of
 // 256 x KPT keys in index order (ballot matching inside a wave, running digit
 // counts per wave, a digit-major prefix over the waves), places the tile in
 // LDS in digit order, and writes it out so that consecutive lanes write
