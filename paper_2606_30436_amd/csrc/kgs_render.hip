@@ -185,16 +185,26 @@ __device__ __forceinline__ void l1_pixel(const float* __restrict__ color, const 
   g2 = d2 > 0.f ? scale : (d2 < 0.f ? -scale : 0.f);
 }
 
-// the block's per-pixel values acc -> partial[gt] (uses sh[NW] and one
-// barrier): wave sums by a fixed butterfly, waves added pairwise in FP64
-template <int NW>
-__device__ __forceinline__ void l1_partial(float acc, float* sh, double* __restrict__ partial, int gt) {
-  acc = wave_sum(acc);
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+// the block's per-pixel values acc -> partial[gt] (uses sh[NW PPL] and one
+// barrier).  A wave holds PPL pixels per lane, the p-th of each lane in the
+// p-th 8x8 sub-block of its block; each sub-block is summed by a fixed
+// butterfly, and the NW PPL sub-blocks, in row-major order, are added pairwise
+// in FP64.  With either pixel layout the partial has the same bits.
+template <int NW, int PPL>
+__device__ __forceinline__ void l1_partial(const float (&acc)[PPL], float* sh, double* __restrict__ partial,
+                                           int gt) {
+  constexpr int NS = NW * PPL;
+  static_assert(NS == 4 || NS == 8, "four or eight sub-blocks per tile");
+  const int w = threadIdx.x >> 6;
+#pragma unroll
+  for (int p = 0; p < PPL; ++p) {
+    const float a = wave_sum(acc[p]);
+    if ((threadIdx.x & 63) == 0) sh[w * PPL + p] = a;
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
     double d = ((double)sh[0] + (double)sh[1]) + ((double)sh[2] + (double)sh[3]);
-    if (NW == 8) d += ((double)sh[4] + (double)sh[5]) + ((double)sh[6] + (double)sh[7]);
+    if (NS == 8) d += ((double)sh[4] + (double)sh[5]) + ((double)sh[6] + (double)sh[7]);
     partial[gt] = d;
   }
 }
@@ -213,16 +223,16 @@ __global__ __launch_bounds__(64 * NW) void k_loss_l1(RenderParams P, const float
   const int px = tx * P.tile_w + sx + (l & 7), py = ty * P.tile_h + sy + (l >> 3);
   const size_t npix = (size_t)P.W * P.H;
   const float scale = 1.0f / (float)(3 * npix);
-  float acc = 0.f;
+  float acc[1] = {0.f};
   if (px < P.W && py < P.H) {
     const size_t cpix = (size_t)v * 3 * npix + (size_t)py * P.W + px;
     float g0, g1, g2;
-    l1_pixel(color, target, cpix, npix, scale, g0, g1, g2, acc);
+    l1_pixel(color, target, cpix, npix, scale, g0, g1, g2, acc[0]);
     grad[cpix] = g0;
     grad[cpix + npix] = g1;
     grad[cpix + 2 * npix] = g2;
   }
-  l1_partial<NW>(acc, sh, partial, gt);
+  l1_partial<NW, 1>(acc, sh, partial, gt);
 }
 
 // one wave per view: lane l adds tiles l, l + 64, ... in order, then a fixed
@@ -387,27 +397,6 @@ __device__ __forceinline__ void wave_block(int tile_w, int w, int& sx, int& sy) 
   sy = (w / nsx) * 8;
 }
 
-// the wave's per-pixel L1 values -> partial[gt], in the order of l1_partial:
-// one butterfly per 8x8 sub-block, the NW PPL sub-blocks in row-major order
-template <int NW, int PPL>
-__device__ __forceinline__ void l1_partial_px(const float (&acc)[PPL], float* sh, double* __restrict__ partial,
-                                              int gt) {
-  constexpr int NS = NW * PPL;
-  static_assert(NS == 4 || NS == 8, "four or eight sub-blocks per tile");
-  const int w = threadIdx.x >> 6;
-#pragma unroll
-  for (int p = 0; p < PPL; ++p) {
-    const float a = wave_sum(acc[p]);
-    if ((threadIdx.x & 63) == 0) sh[w * PPL + p] = a;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double d = ((double)sh[0] + (double)sh[1]) + ((double)sh[2] + (double)sh[3]);
-    if (NS == 8) d += ((double)sh[4] + (double)sh[5]) + ((double)sh[6] + (double)sh[7]);
-    partial[gt] = d;
-  }
-}
-
 template <int B, int NW, bool DEPTH, int PPL>
 __global__ __launch_bounds__(64 * NW) void k_render_bwd(
     RenderParams P, const uint2* __restrict__ ranges, const uint32_t* __restrict__ tile_order,
@@ -497,7 +486,7 @@ __global__ __launch_bounds__(64 * NW) void k_render_bwd(
     Rj[p] = gAT - (g0[p] * Co0 + g1[p] * Co1 + g2[p] * Co2 + gD[p] * Do);
     wmax = max(wmax, lastp[p]);
   }
-  if (fuse_l1) l1_partial_px<NW, PPL>(l1acc, s_loss, loss_partial, gt);
+  if (fuse_l1) l1_partial<NW, PPL>(l1acc, s_loss, loss_partial, gt);
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) wmax = max(wmax, __shfl_xor(wmax, o, 64));
   wmax = __builtin_amdgcn_readfirstlane(wmax);
@@ -721,8 +710,6 @@ static RenderParams render_params(const kgs_ctx* ctx) {
 kgs_status kgs_launch_render_fwd(kgs_ctx* ctx, const kgs_image* out, hipStream_t st) {
   const RenderParams P = render_params(ctx);
   const unsigned grid = (unsigned)(ctx->last_views * ctx->n_tiles);
-  const int s = ctx->sorted_buf;
-  (void)s;
 #define KGS_FWD(NWV)                                                                                             \
   hipLaunchKernelGGL((k_render_fwd<NWV>), dim3(grid), dim3(64 * NWV), 0, st, P, (const uint2*)ctx->ranges,       \
                      (const uint32_t*)ctx->tile_order,                                                           \
