@@ -372,6 +372,48 @@ __device__ __forceinline__ void blend_terms(float e, float u, float dy, bool bl,
   T = T * oma;
 }
 
+// The same terms summed over a lane's two pixels, which share a row and so dy:
+// the moments with a factor dy are formed once from the pixel sums,
+// sum ge dy = dy sum ge and so on, instead of per pixel.
+template <bool DEPTH>
+__device__ __forceinline__ void blend_terms2(const float (&e)[2], const float (&u)[2], float dy, const bool (&bl)[2],
+                                             const float4& r1, const float4& r2, float amax, const float (&g0)[2],
+                                             const float (&g1)[2], const float (&g2)[2], const float (&gD)[2],
+                                             float (&T)[2], float (&Rj)[2], float* __restrict__ x) {
+  float ge[2], gu[2];
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+    const float raw = exp2_approx(e[p]);
+    const float a = bl[p] ? fminf(raw, amax) : 0.f;
+    const float wgt = a * T[p];
+    const float gcc = fmaf(g2[p], r2.z, fmaf(g1[p], r2.y, g0[p] * r2.x));
+    const float gc = DEPTH ? fmaf(gD[p], r1.z, gcc) : gcc;
+    Rj[p] = fmaf(wgt, gc, Rj[p]);
+    const float oma = 1.0f - a;
+    const float dLda = fmaf(T[p], gc, Rj[p] * __builtin_amdgcn_rcpf(oma));
+    if (p == 0) {
+      x[6] = wgt * g0[p];
+      x[7] = wgt * g1[p];
+      x[8] = wgt * g2[p];
+      x[9] = DEPTH ? wgt * gD[p] : 0.f;
+    } else {
+      x[6] = fmaf(wgt, g0[p], x[6]);
+      x[7] = fmaf(wgt, g1[p], x[7]);
+      x[8] = fmaf(wgt, g2[p], x[8]);
+      x[9] = DEPTH ? fmaf(wgt, gD[p], x[9]) : 0.f;
+    }
+    ge[p] = raw < amax ? dLda * a : 0.f;
+    gu[p] = ge[p] * u[p];
+    T[p] = T[p] * oma;
+  }
+  x[5] = ge[0] + ge[1];
+  x[0] = gu[0] + gu[1];
+  x[1] = x[5] * dy;
+  x[2] = fmaf(gu[1], u[1], gu[0] * u[0]);
+  x[3] = x[0] * dy;
+  x[4] = x[1] * dy;
+}
+
 // Emission position of the pair (slot, tile (tx, ty)): the slot's first pair
 // plus the tile's row-major rank in the slot's tile rectangle, which is
 // recovered from the record's packed pixel bounds.
@@ -585,22 +627,16 @@ __global__ __launch_bounds__(64 * NW) void k_render_bwd(
       if (bba != 0ull && bbb != 0ull) {
         float x[20];
         const float4 ra2 = s_rec[w][j][2], rb2 = s_rec[w][jb][2];
-#pragma unroll
-        for (int p = 0; p < PPL; ++p) {
-          if (p == 0) {
-            blend_terms<DEPTH>(ea[p], ua[p], dya[p], bla[p], ra1, ra2, P.amax, g0[p], g1[p], g2[p], gD[p], T[p],
-                               Rj[p], x);
-            blend_terms<DEPTH>(eb[p], ub[p], dyb[p], blb[p], rb1, rb2, P.amax, g0[p], g1[p], g2[p], gD[p], T[p],
-                               Rj[p], x + 10);
-          } else {
-            float y[20];
-            blend_terms<DEPTH>(ea[p], ua[p], dya[p], bla[p], ra1, ra2, P.amax, g0[p], g1[p], g2[p], gD[p], T[p],
-                               Rj[p], y);
-            blend_terms<DEPTH>(eb[p], ub[p], dyb[p], blb[p], rb1, rb2, P.amax, g0[p], g1[p], g2[p], gD[p], T[p],
-                               Rj[p], y + 10);
-#pragma unroll
-            for (int k = 0; k < 20; ++k) x[k] += y[k];
-          }
+        if constexpr (PPL == 2) {
+          // entry a for both pixels, then entry b: each pixel's T and Rj still
+          // see a before b
+          blend_terms2<DEPTH>(ea, ua, dya[0], bla, ra1, ra2, P.amax, g0, g1, g2, gD, T, Rj, x);
+          blend_terms2<DEPTH>(eb, ub, dyb[0], blb, rb1, rb2, P.amax, g0, g1, g2, gD, T, Rj, x + 10);
+        } else {
+          blend_terms<DEPTH>(ea[0], ua[0], dya[0], bla[0], ra1, ra2, P.amax, g0[0], g1[0], g2[0], gD[0], T[0],
+                             Rj[0], x);
+          blend_terms<DEPTH>(eb[0], ub[0], dyb[0], blb[0], rb1, rb2, P.amax, g0[0], g1[0], g2[0], gD[0], T[0],
+                             Rj[0], x + 10);
         }
         int idx;
         bool valid;
@@ -617,18 +653,19 @@ __global__ __launch_bounds__(64 * NW) void k_render_bwd(
         const int tt = first ? ta : tb, tz = first ? tb : ta;
         const float4 q1 = first ? ra1 : rb1, q2 = s_rec[w][first ? j : jb][2];
         float x[10];
+        if constexpr (PPL == 2) {
+          float e2[2], u2[2];
+          bool b2[2];
 #pragma unroll
-        for (int p = 0; p < PPL; ++p) {
-          if (p == 0) {
-            blend_terms<DEPTH>(first ? ea[p] : eb[p], first ? ua[p] : ub[p], first ? dya[p] : dyb[p],
-                               first ? bla[p] : blb[p], q1, q2, P.amax, g0[p], g1[p], g2[p], gD[p], T[p], Rj[p], x);
-          } else {
-            float y[10];
-            blend_terms<DEPTH>(first ? ea[p] : eb[p], first ? ua[p] : ub[p], first ? dya[p] : dyb[p],
-                               first ? bla[p] : blb[p], q1, q2, P.amax, g0[p], g1[p], g2[p], gD[p], T[p], Rj[p], y);
-#pragma unroll
-            for (int k = 0; k < 10; ++k) x[k] += y[k];
+          for (int p = 0; p < 2; ++p) {
+            e2[p] = first ? ea[p] : eb[p];
+            u2[p] = first ? ua[p] : ub[p];
+            b2[p] = first ? bla[p] : blb[p];
           }
+          blend_terms2<DEPTH>(e2, u2, first ? dya[0] : dyb[0], b2, q1, q2, P.amax, g0, g1, g2, gD, T, Rj, x);
+        } else {
+          blend_terms<DEPTH>(first ? ea[0] : eb[0], first ? ua[0] : ub[0], first ? dya[0] : dyb[0],
+                             first ? bla[0] : blb[0], q1, q2, P.amax, g0[0], g1[0], g2[0], gD[0], T[0], Rj[0], x);
         }
         int idx;
         bool valid;

@@ -193,4 +193,7 @@ def test_head_gain_over_the_plain_criterion():
         f"psnr {r['psnr_db']}, ms {r['ms_per_chunk']}")
     assert r["train_accuracy"] > 0.85
     assert r["test_global_agreement"] > 0.95
-    assert r["decision_speedup"] > 2.0
+    # the criterion's own pass (the compositing backward over every view) is what
+    # the head saves; 2.0x at this size now that the backward takes two pixels
+    # per lane, so the bound leaves room for timing noise
+    assert r["decision_speedup"] > 1.5
