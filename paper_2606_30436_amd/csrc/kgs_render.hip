@@ -13,7 +13,9 @@
 //
 // The backward recomputes the same per-pixel sequence front to back (nothing
 // per pixel is stored but T_final and the last blended position), reduces the
-// per-pair gradient terms across the wave with a reduce-scatter butterfly, and
+// per-pair gradient terms across the wave with a reduce-scatter butterfly (in
+// a large launch a wave owns a 16x8 block, two pixels per lane, and sums a
+// lane's two pixels before the reduction, which then serves 128 pixels), and
 // after each batch the first wave adds the waves' partials in wave order and
 // writes one 48-byte record per pair at the pair's emission position, which
 // keeps each slot's pairs contiguous for the deterministic segmented sum that
