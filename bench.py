@@ -77,6 +77,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tile", type=str, default=None, help="e.g. 16x16 (skips the autotuner)")
     ap.add_argument("--batch", type=int, default=None)
+    ap.add_argument("--px-per-lane", type=int, default=0,
+                    help="compositing backward pixels per lane (0: the library's choice)")
     ap.add_argument("--stage-reps", type=int, default=5)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES device-to-device three times (HBM counter calibration) and exit")
@@ -144,6 +146,7 @@ def main():
     log(f"[bench] counts {counts} visible/view {visible}")
 
     R = Rasterizer(W, H, V, N, slot_capacity=int(max_s * 1.25) + 1024, pair_capacity=int(max_p * 1.25) + 4096,
+                   px_per_lane=args.px_per_lane,
                    far_z=FAR)
     img = Image.empty(V, H, W)
     dl = torch.empty_like(img.color)
