@@ -74,7 +74,8 @@ def render(params: dict, cam, degree: int, cfg, xi: torch.Tensor):
     t = Rp @ mu + tp[:, None]
     tx, ty, tz = t
     o = torch.sigmoid(params["logits"])
-    vis = (tz > cfg.near) & (o >= cfg.alpha_min)
+    # near plane; the single-level distance mask keeps camera depths below far
+    vis = (tz > cfg.near) & (tz < cfg.far) & (o >= cfg.alpha_min)
     Rq = quat_rot(params["quats"])
     s = torch.exp(params["log_scales"])
     M = Rq * s[None, :, :]

@@ -107,3 +107,25 @@ def test_view_statistics_feed_the_chunk_scores():
     s = lifecycle.chunk_scores(np.array(kap), np.array(om), np.array(loss))
     assert np.allclose(s["sd"], (kap[0] + kap[1]) / 2)
     assert np.allclose(s["s_tilde"], loss[0] * om[0] + loss[1] * om[1])
+
+
+def test_chunk_scores_hand_worked_example():
+    """Two chunks of two views and five Gaussians, worked out by hand from the
+    appendix's score definitions (arithmetic in the fixture's comments)."""
+    ex = json.load(open(os.path.join(GOLD, "chunk_scores_worked.json")))
+    D, P = np.zeros(5, bool), np.zeros(5)
+    for ch in ex["chunks"]:
+        s = lifecycle.chunk_scores(np.array(ch["kappa"]), np.array(ch["omega"]), np.array(ch["view_loss"]))
+        assert np.array_equal(s["sd"], ch["sd"])
+        assert np.allclose(s["s_tilde"], ch["s_tilde"], rtol=1e-15, atol=1e-15)
+        assert np.array_equal(s["active"], np.array(ch["active"], bool))
+        assert np.allclose(s["sp"], ch["sp"], rtol=1e-14, atol=1e-15)
+        # the same scores from per-Gaussian sums over the views
+        ss = lifecycle.chunk_scores_from_sums(np.sum(ch["kappa"], 0), np.sum(ch["omega"], 0),
+                                              (np.array(ch["view_loss"])[:, None] * np.array(ch["omega"])).sum(0),
+                                              len(ch["view_loss"]))
+        assert np.allclose(ss["sp"], ch["sp"], rtol=1e-14, atol=1e-15) and np.array_equal(ss["sd"], ch["sd"])
+        D, P = lifecycle.global_update(D, P, s["sd"], s["sp"])
+    assert np.array_equal(D, np.array(ex["densify"], bool))
+    assert np.allclose(P, ex["prune_score"], rtol=1e-14, atol=1e-15)
+    assert np.array_equal(lifecycle.decide(D, P), ex["decision"])

@@ -266,6 +266,41 @@ def test_alpha_min_threshold(sign):
         assert val == 0.0
 
 
+# ------------------------------------------------------------ far plane
+@pytest.mark.parametrize("mean_z,t_z,kept", [
+    (9.999, 0.0, True),          # just inside the mask
+    (10.0, 0.0, False),          # exactly at far: culled (the mask keeps z < far)
+    (10.001, 0.0, False),        # beyond
+    (10.0, -2.0 ** -30, True)])  # FP64 z = far - 2^-30 is kept; its FP32 rounding equals far
+def test_far_plane_cull_closed_form(mean_z, t_z, kept):
+    """Single-level distance mask (appendix, LoD mask): a Gaussian is rendered
+    only while its camera depth is below far, decided on the FP64 camera point.
+    A kept Gaussian's image is the closed form of a camera-facing isotropic
+    Gaussian; a culled one leaves the image empty.  The tile-free renderer,
+    which has its own far-plane test, agrees."""
+    far, f, W, H = 10.0, 300.0, 40, 32
+    ls = np.float32(math.log(0.05))
+    logit = np.float32(0.7)
+    cfg = OracleConfig(far=far)
+    sc = _one_gaussian([0, 0, mean_z], [ls] * 3, [1, 0, 0, 0], logit, f=f, W=W, H=H, t=np.array([0.0, 0.0, t_z]))
+    z = float(np.float32(mean_z)) + float(np.float32(t_z))
+    assert (z < far) == kept
+    v = oracle.View(sc, 0, cfg)
+    img = v.image()
+    assert bool(v.proj()["visible"][0]) == kept
+    o = 1 / (1 + math.exp(-float(logit)))
+    sig2 = math.exp(2 * float(ls)) * f * f / (z * z) + cfg.eps2d
+    py, px = np.mgrid[0:H, 0:W] + 0.5
+    raw = o * np.exp(-((px - W / 2) ** 2 + (py - H / 2) ** 2) / (2 * sig2))
+    alpha = np.where(raw >= 1 / 255, np.minimum(0.99, raw), 0.0) if kept else np.zeros((H, W))
+    assert alpha.max() > 0.3 or not kept
+    assert np.allclose(img["color"][0], 0.7 * alpha, atol=2e-7)
+    assert np.allclose(img["depth"], alpha * z, atol=1e-12)
+    C, D, _ = brute.render(_torch_params(sc), sc.cams[0], 0, cfg, torch.zeros(6, dtype=torch.float64))
+    assert np.allclose(C.detach().numpy(), img["color"], atol=1e-12)
+    assert np.allclose(D.detach().numpy(), img["depth"], atol=1e-12)
+
+
 def test_zero_opacity_invariance():
     sc = scenes.tiny_scene(seed=5, n=20, degree=2)
     v0 = oracle.View(sc, 0, CFG)
@@ -295,18 +330,31 @@ def _torch_params(sc):
             for k in ("means", "log_scales", "quats", "logits", "sh")}
 
 
-@pytest.mark.parametrize("seed,degree,pose", [(0, 0, 0.0), (1, 1, 0.02), (2, 3, 0.05), (3, 2, 0.0)])
-def test_oracle_matches_tile_free_autograd(seed, degree, pose):
+BG = (0.2, 0.55, 0.9)
+
+
+@pytest.mark.parametrize("seed,degree,pose,far,bg", [
+    (0, 0, 0.0, 1e30, (0.0, 0.0, 0.0)), (1, 1, 0.02, 1e30, (0.0, 0.0, 0.0)), (2, 3, 0.05, 1e30, (0.0, 0.0, 0.0)),
+    (3, 2, 0.0, 1e30, (0.0, 0.0, 0.0)),
+    # a non-zero background: C = sum T_j alpha_j c_j + T_final bg, and its share of dL/dalpha
+    (4, 1, 0.03, 1e30, BG), (5, 3, 0.0, 1e30, BG),
+    # the distance mask in the middle of the depth range (2-6 m), with a background
+    (6, 2, 0.02, 4.0, BG), (7, 0, 0.0, 3.5, (0.0, 0.0, 0.0))])
+def test_oracle_matches_tile_free_autograd(seed, degree, pose, far, bg):
+    cfg = OracleConfig(far=far, bg=bg)
     sc = scenes.tiny_scene(seed=seed, n=18, degree=degree, n_views=2, pose_sigma=pose)
     rng = np.random.default_rng(seed)
+    if far < 1e29:
+        z = sc.means[2]
+        assert (z < far - 0.1).sum() >= 3 and (z > far + 0.1).sum() >= 3  # both sides of the mask are populated
     for v in range(2):
         wC = rng.normal(size=(3, sc.height, sc.width))
         wD = rng.normal(size=(sc.height, sc.width))
-        ov = oracle.View(sc, v, CFG)
+        ov = oracle.View(sc, v, cfg)
         img = ov.image()
         P = _torch_params(sc)
         xi = torch.tensor(sc.pose_xi[v].astype(np.float64), requires_grad=True)
-        C, D, _ = brute.render(P, sc.cams[v], degree, CFG, xi)
+        C, D, _ = brute.render(P, sc.cams[v], degree, cfg, xi)
         assert np.allclose(C.detach().numpy(), img["color"], atol=1e-10)
         assert np.allclose(D.detach().numpy(), img["depth"], atol=1e-9)
         L = (C * torch.tensor(wC)).sum() + (D * torch.tensor(wD)).sum()
@@ -333,10 +381,11 @@ def _loss(sc, v, cfg, params, wC, wD):
     return float((img["color"] * wC).sum() + (img["depth"] * wD).sum())
 
 
-@pytest.mark.parametrize("seed", [11, 12])
-def test_backward_matches_fp64_central_differences(seed):
-    """Smooth configuration (thresholds off): analytic gradient == central FD."""
-    cfg = OracleConfig.smooth()
+@pytest.mark.parametrize("seed,bg", [(11, (0.0, 0.0, 0.0)), (12, (0.0, 0.0, 0.0)), (13, (0.8, 0.3, 0.6))])
+def test_backward_matches_fp64_central_differences(seed, bg):
+    """Smooth configuration (thresholds off): analytic gradient == central FD.
+    The background case checks the T_final * bg term of dL/dalpha."""
+    cfg = OracleConfig.smooth(bg=bg)
     sc = scenes.tiny_scene(seed=seed, n=6, degree=3, W=24, H=20, n_views=1, pose_sigma=0.03,
                            log_scale_mu=-1.6)
     rng = np.random.default_rng(seed)
