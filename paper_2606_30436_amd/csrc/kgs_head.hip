@@ -338,7 +338,7 @@ __global__ __launch_bounds__(256) void k_head_adam(float* __restrict__ theta, fl
 
 // Features of the head from a chunk's statistics (the layout is documented
 // with kgs_head_features in kgs.h).
-__global__ __launch_bounds__(KGS_BLOCK) void k_head_features(kgs_gaussians g, kgs_view_stats st, float inv_views,
+__global__ __launch_bounds__(KGS_BLOCK) void k_head_features(kgs_gaussians g, kgs_view_stats st, int n_views,
                                                              const double* __restrict__ mm,
                                                              const uint8_t* __restrict__ densify,
                                                              const double* __restrict__ prune_score,
@@ -357,12 +357,13 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_head_features(kgs_gaussians g, kg
   if (ls[1] < ls[2]) { const float t = ls[1]; ls[1] = ls[2]; ls[2] = t; }
   if (ls[0] < ls[1]) { const float t = ls[0]; ls[0] = ls[1]; ls[1] = t; }
   float f[KGS_HEAD_FEATURES];
-  f[0] = kap * inv_views;
+  // S_d^(i,c) as the FP64 quotient rounded once (no float reciprocal of |V_c|)
+  f[0] = (float)((double)st.kappa_sum[i] / (double)n_views);
   f[1] = (float)L;
   f[2] = (float)sp;
   f[3] = log1pf(om);
   f[4] = om > 0.f ? kap / om : 0.f;
-  f[5] = vc * inv_views;
+  f[5] = (float)((double)st.view_count[i] / (double)n_views);
   f[6] = st.grad_norm_sum[i] / fmaxf(vc, 1.0f);
   f[7] = log1pf((float)max(st.max_radius[i], 0));
   f[8] = 1.0f / (1.0f + __expf(-g.opacity_logits[i]));
@@ -423,7 +424,7 @@ kgs_status kgs_launch_head_features(kgs_ctx* ctx, const kgs_gaussians* g, const 
   const int64_t n = g->n, nb = (n + KGS_BLOCK - 1) / KGS_BLOCK;
   if (nb == 0) return KGS_OK;
   const double* mm = kgs_launch_chunk_minmax(ctx, stats, n, st);
-  hipLaunchKernelGGL(k_head_features, dim3((unsigned)nb), dim3(KGS_BLOCK), 0, st, *g, *stats, 1.0f / (float)V, mm,
+  hipLaunchKernelGGL(k_head_features, dim3((unsigned)nb), dim3(KGS_BLOCK), 0, st, *g, *stats, V, mm,
                      before ? (const uint8_t*)before->densify : (const uint8_t*)nullptr,
                      before ? (const double*)before->prune_score : (const double*)nullptr, feat);
   return kgs_check_launch();

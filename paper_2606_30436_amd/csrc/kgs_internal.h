@@ -226,7 +226,8 @@ __device__ __forceinline__ bool project_core(const CamDev& c, const float mu[3],
   p.tx = (float)X;
   p.ty = (float)Y;
   p.tz = (float)Z;
-  if (!(p.tz > near_z) || !(p.tz < far_z)) return false;
+  // near plane and the single-level distance mask, decided on the FP64 camera depth
+  if (!(Z > (double)near_z) || !(Z < (double)far_z)) return false;
   const float iz = 1.0f / p.tz;
   float ux = p.tx * iz, uy = p.ty * iz;
   p.clx = 0;

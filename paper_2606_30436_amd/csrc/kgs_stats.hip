@@ -5,7 +5,7 @@
 // below any FP32 rounding.
 #include "kgs_internal.h"
 
-__global__ __launch_bounds__(KGS_BLOCK) void k_chunk_scores(int64_t n, float inv_views, float tau_d,
+__global__ __launch_bounds__(KGS_BLOCK) void k_chunk_scores(int64_t n, int n_views, double tau_d,
                                                             const uint32_t* __restrict__ kappa_sum,
                                                             const uint32_t* __restrict__ omega_sum,
                                                             const double* __restrict__ gamma_sum,
@@ -15,9 +15,10 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_chunk_scores(int64_t n, float inv
   const int64_t i = (int64_t)blockIdx.x * KGS_BLOCK + threadIdx.x;
   double lo = INFINITY, hi = -INFINITY;
   if (i < n) {
-    // S_d^(i,c) = (1/|V_c|) sum_v kappa_v(i);  S_d(i) |= S_d^(i,c) > tau_d
-    const float sd = (float)kappa_sum[i] * inv_views;
-    if (sd > tau_d) densify[i] = 1;
+    // S_d^(i,c) = (1/|V_c|) sum_v kappa_v(i);  S_d(i) |= S_d^(i,c) > tau_d.  The quotient is
+    // taken in FP64 (exact for kappa = tau_d |V_c|, where a float reciprocal of |V_c| rounds
+    // 5 |V_c| / |V_c| up past 5 for |V_c| = 15, 30, 60, 63), so the strict test is the oracle's.
+    if (densify && (double)kappa_sum[i] / (double)n_views > tau_d) densify[i] = 1;
     if (omega_sum[i] > 0) {
       const double L = log1p(gamma_sum[i]);
       lo = L;
@@ -140,7 +141,7 @@ kgs_status kgs_launch_accumulate(kgs_ctx* ctx, const kgs_view_stats* s, int64_t 
                                  const kgs_lifecycle_state* state, float tau_d, int reset, hipStream_t st) {
   const int64_t nb = (n + KGS_BLOCK - 1) / KGS_BLOCK;
   if (nb == 0) return KGS_OK;
-  hipLaunchKernelGGL(k_chunk_scores, dim3((unsigned)nb), dim3(KGS_BLOCK), 0, st, n, 1.0f / (float)V, tau_d,
+  hipLaunchKernelGGL(k_chunk_scores, dim3((unsigned)nb), dim3(KGS_BLOCK), 0, st, n, V, (double)tau_d,
                      (const uint32_t*)s->kappa_sum, (const uint32_t*)s->omega_sum, (const double*)s->gamma_sum,
                      state->densify, ctx->mm_partial);
   hipLaunchKernelGGL(k_minmax_final, dim3(1), dim3(1024), 0, st, nb, ctx->mm_partial);
@@ -170,7 +171,7 @@ kgs_status kgs_launch_decide(kgs_ctx* ctx, const kgs_lifecycle_state* state, int
 // touching any state; returns the device address of (min, max).
 const double* kgs_launch_chunk_minmax(kgs_ctx* ctx, const kgs_view_stats* s, int64_t n, hipStream_t st) {
   const int64_t nb = (n + KGS_BLOCK - 1) / KGS_BLOCK;
-  hipLaunchKernelGGL(k_chunk_scores, dim3((unsigned)nb), dim3(KGS_BLOCK), 0, st, n, 0.0f, INFINITY,
+  hipLaunchKernelGGL(k_chunk_scores, dim3((unsigned)nb), dim3(KGS_BLOCK), 0, st, n, 1, 0.0,
                      (const uint32_t*)s->kappa_sum, (const uint32_t*)s->omega_sum, (const double*)s->gamma_sum,
                      (uint8_t*)nullptr, ctx->mm_partial);
   hipLaunchKernelGGL(k_minmax_final, dim3(1), dim3(1024), 0, st, nb, ctx->mm_partial);

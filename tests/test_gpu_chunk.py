@@ -309,3 +309,29 @@ def test_eager_sort_after_a_graph_launch():
     ref = R.buffers()
     for k in ("keys", "sorted_slot", "slot_pairoff"):
         assert np.array_equal(got[k].numpy(), ref[k].numpy()), k
+
+
+@pytest.mark.parametrize("V", [15, 30, 60, 63])
+def test_densify_tie_at_tau_d_times_views(V):
+    """S_d^(i,c) = kappa / |V_c| against tau_d = 5 at kappa = 5|V_c| - 1, 5|V_c|, 5|V_c| + 1 (Sec. 3.3's strict
+    test): only the last densifies.  Hand-filled statistics through kgs_accumulate_stats, no rendering.  A float
+    reciprocal of |V_c| rounds 5|V_c| / |V_c| above 5 for these view counts."""
+    say(f"densify tie, |V_c| = {V}")
+    R = Rasterizer(64, 32, max_views=1, max_gaussians=1024)
+    kap = np.array([5 * V - 1, 5 * V, 5 * V + 1, 0, 5 * V, 10 * V], np.int32)
+    n = len(kap)
+    st = ViewStats.zeros(n)
+    st.kappa_sum.copy_(torch.from_numpy(kap))
+    st.omega_sum.copy_(torch.from_numpy(np.array([10, 10, 10, 0, 3, 40], np.int32)))
+    st.gamma_sum.copy_(torch.from_numpy(np.array([1.0, 2.0, 3.0, 0.0, 0.5, 4.0])))
+    state = LifecycleState.zeros(n)
+    R.accumulate_stats(st, V, state, tau_d=5.0, reset=True)
+    dec, _, _ = R.decide(state, tau_p=0.99, keep_map=False)
+    torch.cuda.synchronize()
+    ref = lifecycle.chunk_scores_from_sums(kap, [10, 10, 10, 0, 3, 40], [1.0, 2.0, 3.0, 0.0, 0.5, 4.0], V)
+    D, P = lifecycle.global_update(np.zeros(n, bool), np.zeros(n), ref["sd"], ref["sp"], 5.0)
+    assert list(D) == [False, False, True, False, False, True]
+    assert np.array_equal(state.densify.cpu().numpy().astype(bool), D)
+    assert np.abs(state.prune_score.cpu().numpy() - P).max() <= 1e-12
+    assert np.array_equal(dec.cpu().numpy(), lifecycle.decide(D, P, 0.99))
+    R.close()

@@ -420,3 +420,26 @@ def test_tile_shapes_and_batches_give_the_same_gradients():
         for k in out:
             rel = np.linalg.norm(out[k] - ref[k]) / np.linalg.norm(ref[k])
             assert rel < 1e-5, (tile, batch, px, k, rel)
+
+
+@pytest.mark.parametrize("mean_z,t_z,kept", [(9.999, 0.0, True), (10.0, 0.0, False), (10.001, 0.0, False),
+                                             (10.0, -2.0 ** -30, True)])
+def test_far_plane_boundary(mean_z, t_z, kept):
+    """The distance mask at far = 10: depths just inside are rendered, at and beyond far are culled, and the
+    decision is taken on the FP64 camera depth (10 - 2^-30 is kept although its FP32 rounding equals far)."""
+    say(f"[gpu] far plane mean_z={mean_z} t_z={t_z}")
+    W, H, f = 40, 32, 300.0
+    sh = np.zeros((1, 3, 1), np.float32)
+    sh[0, :, 0] = (np.array([0.7, 0.4, 0.2]) - 0.5) * 2 * math.sqrt(math.pi)
+    cam = scenes.make_camera(np.eye(3), np.array([0.0, 0.0, t_z]), f, f, W / 2, H / 2, W, H)
+    sc = scenes.Scene(np.array([[0.0], [0.0], [mean_z]], np.float32), np.full((3, 1), math.log(0.05), np.float32),
+                      np.array([[1.0], [0.0], [0.0], [0.0]], np.float32), np.array([0.7], np.float32), sh, 0,
+                      scenes.stack_cameras([cam]), np.zeros((1, 6), np.float32))
+    R = _rast(sc, far_z=10.0)
+    _, _, _, img = run_forward(R, sc)
+    n_slots, _ = R.counts()
+    assert R.status() == 0 and n_slots == int(kept)
+    oi = oracle.View(sc, 0, oracle_cfg(R)).image()
+    assert np.abs(img.color[0].cpu().numpy() - oi["color"]).max() <= 1e-6
+    assert (np.abs(oi["color"]).max() > 0.1) == kept
+    R.close()
