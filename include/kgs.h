@@ -7,7 +7,8 @@
  *   * Plain C types only.  Arrays are caller-owned DEVICE memory unless a
  *     comment says "host".  Nothing here allocates device memory: every
  *     scratch buffer lives in the caller-allocated workspace handed to
- *     kgs_create.
+ *     kgs_create, except the 1 MiB static device array of
+ *     kgs_accumulate_stats_static (library-owned, one per GPU).
  *   * Work is enqueued on the caller's stream (hipStream_t passed as void*;
  *     NULL means the default stream).  Calls return after enqueueing; results
  *     are valid after the stream is synchronised.
@@ -295,6 +296,20 @@ kgs_status kgs_project_bwd(kgs_ctx* ctx, const kgs_gaussians* g, const kgs_camer
  * (kappa, omega, gamma) are zeroed afterwards. */
 kgs_status kgs_accumulate_stats(kgs_ctx* ctx, const kgs_view_stats* stats, int64_t n, int32_t n_views,
                                 const kgs_lifecycle_state* state, float tau_d, int32_t reset, void* stream);
+
+/* kgs_accumulate_stats for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments and results as kgs_accumulate_stats, no context:
+ * the min / max partials of the chunk's L live in a static device array that
+ * the library holds on each GPU it runs on until the process ends (1 MiB), so
+ * nothing is allocated.  n may be at most KGS_ACCUMULATE_STATIC_MAX_N
+ * (65535 blocks of 256 Gaussians), else KGS_ERR_INVALID_ARG.  The array keeps
+ * the last call's contents and needs no clearing; calls that overlap on one
+ * GPU (concurrent streams, threads) share it and race.  KGS_ERR_HIP if the
+ * array's device address cannot be obtained on the current device. */
+#define KGS_ACCUMULATE_STATIC_MAX_N 16776960LL
+kgs_status kgs_accumulate_stats_static(const kgs_view_stats* stats, int64_t n, int32_t n_views,
+                                       const kgs_lifecycle_state* state, float tau_d, int32_t reset, void* stream);
 
 /* decision[i] = PRUNE if prune_score > tau_p, else DENSIFY if densify, else
  * KEEP (Sec. 3.3).  keep_map (or NULL): exclusive prefix count of survivors;

@@ -91,6 +91,8 @@ _SIGS = {
                                   P(KgsViewStats), c_void_p]),
     "kgs_accumulate_stats": (c_int32, [c_void_p, P(KgsViewStats), c_int64, c_int32, P(KgsLifecycleState), c_float,
                                        c_int32, c_void_p]),
+    "kgs_accumulate_stats_static": (c_int32, [P(KgsViewStats), c_int64, c_int32, P(KgsLifecycleState), c_float,
+                                              c_int32, c_void_p]),
     "kgs_densify_prune_decide": (c_int32, [c_void_p, P(KgsLifecycleState), c_int64, c_double, c_void_p, c_void_p,
                                            c_void_p, c_void_p]),
     "kgs_chunk_run": (c_int32, [c_void_p, P(KgsChunkDesc), c_void_p]),
@@ -237,6 +239,15 @@ def kgs_accumulate_stats(ctx, stats: KgsViewStats, n, n_views, state: KgsLifecyc
                          stream=None):
     check(load().kgs_accumulate_stats(ctypes.c_void_p(ctx), ctypes.byref(stats), n, n_views, ctypes.byref(state),
                                       float(tau_d), int(reset), stream_handle(stream)), "kgs_accumulate_stats")
+
+
+ACCUMULATE_STATIC_MAX_N = 16776960
+
+
+def kgs_accumulate_stats_static(stats: KgsViewStats, n, n_views, state: KgsLifecycleState, tau_d, reset=0,
+                                stream=None):
+    check(load().kgs_accumulate_stats_static(ctypes.byref(stats), n, n_views, ctypes.byref(state), float(tau_d),
+                                             int(reset), stream_handle(stream)), "kgs_accumulate_stats_static")
 
 
 def kgs_densify_prune_decide(ctx, state: KgsLifecycleState, n, tau_p, decision, keep_map=None, n_keep=None,

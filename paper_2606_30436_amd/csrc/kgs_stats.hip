@@ -3,6 +3,8 @@
 // Per-Gaussian streams over [N] arrays: HBM bound.  L, S_p and the min / max
 // over the active set are FP64 so the prune threshold test is decided far
 // below any FP32 rounding.
+#include <mutex>
+
 #include "kgs_internal.h"
 
 __global__ __launch_bounds__(KGS_BLOCK) void k_chunk_scores(int64_t n, int n_views, double tau_d,
@@ -137,17 +139,64 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_keep_map(int64_t n, const uint8_t
   if (i < n) keep_map[i] = base[blockIdx.x] + ea;
 }
 
-kgs_status kgs_launch_accumulate(kgs_ctx* ctx, const kgs_view_stats* s, int64_t n, int V,
-                                 const kgs_lifecycle_state* state, float tau_d, int reset, hipStream_t st) {
+// The chunk close with its min / max partials in mm (2 nb + 2 doubles, nb = blocks of 256 over n).  Every
+// partial is written before it is read, so mm needs no clearing.
+static kgs_status launch_accumulate_mm(const kgs_view_stats* s, int64_t n, int V, const kgs_lifecycle_state* state,
+                                       float tau_d, int reset, double* mm, hipStream_t st) {
   const int64_t nb = (n + KGS_BLOCK - 1) / KGS_BLOCK;
   if (nb == 0) return KGS_OK;
   hipLaunchKernelGGL(k_chunk_scores, dim3((unsigned)nb), dim3(KGS_BLOCK), 0, st, n, V, (double)tau_d,
                      (const uint32_t*)s->kappa_sum, (const uint32_t*)s->omega_sum, (const double*)s->gamma_sum,
-                     state->densify, ctx->mm_partial);
-  hipLaunchKernelGGL(k_minmax_final, dim3(1), dim3(1024), 0, st, nb, ctx->mm_partial);
+                     state->densify, mm);
+  hipLaunchKernelGGL(k_minmax_final, dim3(1), dim3(1024), 0, st, nb, mm);
   hipLaunchKernelGGL(k_chunk_prune, dim3((unsigned)nb), dim3(KGS_BLOCK), 0, st, n, nb, s->kappa_sum, s->omega_sum,
-                     s->gamma_sum, (const double*)ctx->mm_partial, state->prune_score, reset);
+                     s->gamma_sum, (const double*)mm, state->prune_score, reset);
   return kgs_check_launch();
+}
+
+kgs_status kgs_launch_accumulate(kgs_ctx* ctx, const kgs_view_stats* s, int64_t n, int V,
+                                 const kgs_lifecycle_state* state, float tau_d, int reset, hipStream_t st) {
+  return launch_accumulate_mm(s, n, V, state, tau_d, reset, ctx->mm_partial, st);
+}
+
+// ------------------------------------------------------------------------------------------------
+// The chunk close for callers that cannot allocate (graph capture, serving loops): its min / max
+// partials live in a library-owned static device array instead of a workspace.  Each GPU holds its
+// own copy for the life of the process; host code reaches it only through the address that
+// hipGetSymbolAddress returns on that device (the array's name is a host-side stand-in there).
+#define KGS_STATIC_MAX_BLOCKS 65535
+#define KGS_STATIC_MAX_DEVICES 64
+static __device__ __align__(256) double scratch[2 * KGS_STATIC_MAX_BLOCKS + 2];
+
+static std::mutex g_scratch_mu;
+static double* g_scratch_dev[KGS_STATIC_MAX_DEVICES];
+
+// Device address of this GPU's copy of `scratch`, looked up once per device with it current.
+static kgs_status static_scratch(double** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return KGS_ERR_HIP;
+  if (dev < 0 || dev >= KGS_STATIC_MAX_DEVICES) return KGS_ERR_HIP;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return KGS_ERR_HIP;
+    g_scratch_dev[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_dev[dev];
+  return KGS_OK;
+}
+
+extern "C" kgs_status kgs_accumulate_stats_static(const kgs_view_stats* stats, int64_t n, int32_t n_views,
+                                                  const kgs_lifecycle_state* state, float tau_d, int32_t reset,
+                                                  void* stream) {
+  if (!stats || !state || n < 0 || n > KGS_ACCUMULATE_STATIC_MAX_N || n_views < 1) return KGS_ERR_INVALID_ARG;
+  if (!stats->kappa_sum || !stats->omega_sum || !stats->gamma_sum || !state->densify || !state->prune_score)
+    return KGS_ERR_INVALID_ARG;
+  if (n == 0) return KGS_OK;
+  double* mm = nullptr;
+  const kgs_status e = static_scratch(&mm);
+  if (e != KGS_OK) return e;
+  return launch_accumulate_mm(stats, n, n_views, state, tau_d, reset, mm, (hipStream_t)stream);
 }
 
 kgs_status kgs_launch_decide(kgs_ctx* ctx, const kgs_lifecycle_state* state, int64_t n, double tau_p,

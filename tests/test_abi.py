@@ -113,3 +113,16 @@ def test_library_refuses_to_run_without_its_build(tmp_path, monkeypatch):
     monkeypatch.setattr(L, "_lib", None)
     with pytest.raises(RuntimeError, match="no fallback"):
         L.load(str(tmp_path / "missing.so"))
+
+
+def test_static_chunk_close_host_checks():
+    """The allocation-free chunk close rejects bad arguments on the host (no
+    device address is looked up, nothing is launched)."""
+    lib = L.load()
+    st, s = L.KgsViewStats(), L.KgsLifecycleState()
+    assert lib.kgs_accumulate_stats_static(ctypes.byref(st), 10, 2, ctypes.byref(s), 5.0, 0, None) == L.KGS_ERR_INVALID_ARG
+    st.kappa_sum = st.omega_sum = st.gamma_sum = 8
+    s.densify = s.prune_score = 8
+    for n, V in ((L.ACCUMULATE_STATIC_MAX_N + 1, 2), (-1, 2), (10, 0)):
+        assert lib.kgs_accumulate_stats_static(ctypes.byref(st), n, V, ctypes.byref(s), 5.0, 0, None) == L.KGS_ERR_INVALID_ARG
+    assert lib.kgs_accumulate_stats_static(None, 10, 2, ctypes.byref(s), 5.0, 0, None) == L.KGS_ERR_INVALID_ARG
