@@ -34,6 +34,45 @@ FAR = 80.0
 FLOP_TEST, FLOP_BLEND = 10, 52
 # non-packed FP32 VALU peak: 256 CUs x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
 PEAK_ALU_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
+HBM_BYTES_PER_S = 8e12
+# the forward's blend of an entry (exp2, clamp, weight, three colour and one depth FMA, T update)
+FLOP_FWD_BLEND = 20
+SH_K = 16  # SH degree 3
+
+
+def chunk_roofline(stage_ms: dict, ms: float, N: int, S: int, P: int, P_live: int, E: int, E_b: int,
+                   npix: int) -> dict:
+    """Per-stage roofline of the chunk: T_roof = sum over stages of max(algorithmic bytes / 8 TB/s,
+    counted flop / ALU peak), against the chunk's measured time.  'survey' charges every stage the
+    per-unit figures of the hot-path plan (every pair gathered and reduced, a 4-pass 24 B/pair sort
+    of 46-bit keys); 'strict' charges only the pairs some pixel of their tile still needs (P_live)
+    and one read and write of the sort's keys and values."""
+    par = 44 + 12 * SH_K  # bytes of one Gaussian's parameters
+    peak = PEAK_ALU_TFLOPS * 1e12
+
+    def stage(nbytes, flop=0.0):
+        t_b, t_f = nbytes / HBM_BYTES_PER_S, flop / peak
+        return {"bound": "alu" if t_f > t_b else "hbm", "bytes": int(nbytes), "flop": int(flop),
+                "t_roof_ms": round(1e3 * max(t_b, t_f), 5)}
+
+    out = {}
+    for mode, pp, sort_bytes in (("survey", P, 96 * P), ("strict", P_live, 16 * (S + P))):
+        st = {
+            "project": stage(N * par + 60 * S),
+            "bin": stage(16 * S + 12 * P),
+            "sort": stage(sort_bytes),
+            "ranges": stage(8 * P),
+            "render_fwd": stage(48 * pp + 24 * npix, FLOP_TEST * E + FLOP_FWD_BLEND * E_b),
+            "loss": stage(36 * npix),
+            "render_bwd_pixels": stage(48 * pp + 48 * npix, FLOP_TEST * E + FLOP_BLEND * E_b),
+            "project_bwd": stage(48 * pp + 60 * S + 2 * N * par),
+            "stats_decide": stage(30 * N),
+        }
+        t = sum(v["t_roof_ms"] for v in st.values())
+        out[mode] = {"t_roof_ms": round(t, 4), "frac": round(t / ms, 4), "stages": st}
+    measured = dict(stage_ms)
+    out["stage_ms_measured"] = {k: round(v, 4) for k, v in measured.items()}
+    return out
 
 
 def log(*a):
@@ -225,6 +264,10 @@ def main():
     log(f"[bench] stages {json.dumps({k: round(v, 3) for k, v in stage_ms.items()})}")
     n_slots, n_pairs = R.counts()
     E = int(img.last.to(torch.int64).sum().item())
+    # pairs some pixel of their tile still needs: per (view, tile) the largest 1 + last position
+    tw, th = best[0]
+    lp = torch.nn.functional.pad(img.last.to(torch.int64), (0, (-W) % tw, 0, (-H) % th))
+    P_live = int(lp.view(V, lp.shape[1] // th, th, lp.shape[2] // tw, tw).amax(dim=(2, 4)).sum().item())
     E_b = int(stats.omega_sum.to(torch.int64).sum().item()) // args.stage_reps
     flop = FLOP_TEST * E + FLOP_BLEND * E_b
     t_bwd = stage_ms["render_bwd_pixels"] / 1e3
@@ -234,13 +277,19 @@ def main():
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_ALU_TFLOPS, 4), "traffic": traffic,
                 "kernel": "k_render_bwd (compositing backward)", "evaluations": E, "blended": E_b,
                 "kernel_ms": round(stage_ms["render_bwd_pixels"], 4)}
+    chunk_roof = chunk_roofline(stage_ms, ms, N, n_slots, n_pairs, P_live, E, E_b, V * W * H)
+    roofline["chunk_frac"] = chunk_roof["survey"]["frac"]
+    roofline["chunk_frac_strict"] = chunk_roof["strict"]["frac"]
+    log(f"[bench] chunk roofline: survey {chunk_roof['survey']['t_roof_ms']} ms ({chunk_roof['survey']['frac']}), "
+        f"strict {chunk_roof['strict']['t_roof_ms']} ms ({chunk_roof['strict']['frac']}), live pairs {P_live}")
 
-    # ---- plain per-view loop (same library, 16x16 tiles, batch 64, no graph)
-    plain_ms = None
+    # ---- plain per-view loop (same library, 16x16 tiles, batch 128, no graph), with and
+    # without a host read of the pair count between projection and sort
+    plain_ms = plain_nr_ms = None
     identical = None
     if not args.no_plain:
         P1 = Rasterizer(W, H, 1, N, slot_capacity=int(max_s * 1.25) + 1024,
-                        pair_capacity=int(max_p * 1.25) + 4096, far_z=FAR)
+                        pair_capacity=int(max_p * 1.25) + 4096, tile=(16, 16), batch=128, far_z=FAR)
         pimg = Image.empty(V, H, W)
         pdl = torch.empty_like(pimg.color)
         ploss = torch.empty(V, device=dev)
@@ -250,14 +299,15 @@ def main():
         pstate = LifecycleState.zeros(N)
         cam_bytes = cams.view(V, -1)
 
-        def plain_chunk():
+        def plain_chunk(host_read=True):
             for t in (pgr.means, pgr.log_scales, pgr.quats, pgr.logits, pgr.sh, ppose, pst.kappa_sum, pst.omega_sum,
                       pst.gamma_sum, pst.grad_norm_sum, pst.view_count, pst.max_radius):
                 t.zero_()
             for v in range(V):
                 vi = Image(pimg.color[v:v + 1], pimg.depth[v:v + 1], pimg.t_final[v:v + 1], pimg.last[v:v + 1])
                 P1.project(g, cam_bytes[v])
-                P1.counts()  # host read of the pair count before sorting
+                if host_read:
+                    P1.counts()  # host read of the pair count before sorting, as a naive loop would
                 P1.bin_sort()
                 P1.render_fwd(vi)
                 P1.loss_l1(target[v:v + 1], vi, pdl[v:v + 1], ploss[v:v + 1])
@@ -266,18 +316,22 @@ def main():
             P1.accumulate_stats(pst, V, pstate, reset=True)
             return P1.decide(pstate, keep_map=False)[0]
 
-        for _ in range(2):
-            plain_chunk()
-        torch.cuda.synchronize()
         reps = max(3, args.steps // 4)
-        ev0.record(stream)
-        for _ in range(reps):
-            pdec = plain_chunk()
-        ev1.record(stream)
-        torch.cuda.synchronize()
-        plain_ms = ev0.elapsed_time(ev1) / reps
+        timed = {}
+        for host_read in (True, False):
+            for _ in range(2):
+                plain_chunk(host_read)
+            torch.cuda.synchronize()
+            ev0.record(stream)
+            for _ in range(reps):
+                pdec = plain_chunk(host_read)
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            timed[host_read] = ev0.elapsed_time(ev1) / reps
+        plain_ms, plain_nr_ms = timed[True], timed[False]
         identical = bool(torch.equal(pimg.color, batched_color)) and bool(torch.equal(pdec, batched_dec))
-        log(f"[bench] plain {plain_ms:.3f} ms/chunk, identical outputs {identical}")
+        log(f"[bench] plain {plain_ms:.3f} ms/chunk ({plain_nr_ms:.3f} without the host read), "
+            f"identical outputs {identical}")
         del P1
 
     def psnr(a, b):
@@ -306,6 +360,22 @@ def main():
                "kind": "oracle", "sample": f"the full workload: all {V} views of the chunk, fwd + stats + bwd, FP64",
                "seconds": round(ot, 2)}
         log(f"[bench] cpu oracle {ot:.1f}s")
+        # one core: one view of the chunk (the fourth keyframe), the same three steps
+        v1 = 3
+        threads = oracle.num_threads()
+        oracle.set_num_threads(1)
+        ot0 = time.perf_counter()
+        ov = oracle.View(sc, v1, ocfg)
+        ov.image()
+        ov.stats(tgt[v1], 0.1)
+        ov.backward(gC[v1])
+        del ov
+        ot1 = time.perf_counter() - ot0
+        oracle.set_num_threads(threads)
+        cpu["one_core"] = {"value": round(W * H / ot1 / 1e6, 4), "unit": "Mpix/s", "cores": 1,
+                           "sample": f"view {v1} of the chunk ({visible[v1]} visible Gaussians), fwd + stats + bwd, "
+                                     "FP64, one thread", "seconds": round(ot1, 2)}
+        log(f"[bench] cpu oracle one core, one view {ot1:.1f}s")
 
     mpix = V * W * H / (ms / 1e3) / 1e6
     out = {
@@ -316,12 +386,18 @@ def main():
                                "1242x375, SH3, FP32, one HIP graph per chunk",
                    "n_gaussians": N, "n_views": V, "width": W, "height": H, "far_z": FAR,
                    "tile": list(best[0]), "batch": best[1], "visible_per_view": visible, "slots": n_slots,
-                   "pairs": n_pairs, "plain_ms_per_chunk": None if plain_ms is None else round(plain_ms, 4),
+                   "pairs": n_pairs, "live_pairs": P_live,
+                   "plain_loop": "per view: project, host read of the pair count, sort, fwd, loss, bwd; then "
+                                 "stats + decide; 16x16 tiles, batch 128, no graph",
+                   "plain_ms_per_chunk": None if plain_ms is None else round(plain_ms, 4),
                    "speedup_vs_plain": None if plain_ms is None else round(plain_ms / ms, 3),
+                   "plain_ms_per_chunk_no_host_read": None if plain_nr_ms is None else round(plain_nr_ms, 4),
+                   "speedup_vs_plain_no_host_read": None if plain_nr_ms is None else round(plain_nr_ms / ms, 3),
                    "outputs_identical_to_plain": identical, "psnr_vs_target_db": round(psnr_b, 3),
                    "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
                    "autotune_ms": table},
         "roofline": roofline,
+        "chunk_roofline": chunk_roof,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

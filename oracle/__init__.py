@@ -91,6 +91,7 @@ def lib():
                                        ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                        _u64, _i64, ctypes.c_int64]
             L.orc_num_threads.restype = ctypes.c_int
+            L.orc_set_num_threads.argtypes = [ctypes.c_int]
             _lib = L
     return _lib
 
@@ -207,7 +208,7 @@ class View:
     def proj(self) -> dict:
         rec = np.empty((self.n, 10))
         irec = np.empty((self.n, 9), np.int64)
-        misc = np.empty((self.n, 6))
+        misc = np.empty((self.n, 9))
         lib().orc_view_proj(self._h, _ptr(rec, _d), _ptr(irec, _i64), _ptr(misc, _d))
         return dict(mu=rec[:, 0:2], conic=rec[:, 2:5], opacity=rec[:, 5], color=rec[:, 6:9],
                     depth=rec[:, 9], visible=irec[:, 0].astype(bool), fxi=irec[:, 1], fyi=irec[:, 2],
@@ -293,3 +294,8 @@ def bin_keys(view, gid, fxi, fyi, rx, ry, depth_bits, W, H, TW, TH, cap=None):
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's OpenMP regions from now on (for timing)."""
+    lib().orc_set_num_threads(int(n))

@@ -235,6 +235,11 @@ typedef struct {
   double col[3];
   int colmask[3];
   double Y[16];
+  /* diagnostics only (not used by the method): distance of the far test, of the
+   * pixel centre from an integer (pixels), and of the extent before its ceil
+   * from an integer (relative) -- the places where a re-evaluation in another
+   * precision may take the other side of an integer decision */
+  double m_far, m_cen, m_ext;
 } orc_proj;
 
 static void quat_to_rot(const double q[4], double R[9]) {
@@ -274,10 +279,12 @@ typedef struct {
 static void project_one(const orc_view* v, int64_t i, orc_proj* p) {
   const int64_t n = v->n;
   memset(p, 0, sizeof *p);
+  p->m_cen = p->m_ext = INFINITY;
   double mu[3] = {v->means[i], v->means[n + i], v->means[2 * n + i]};
   for (int r = 0; r < 3; ++r)
     p->t[r] = v->Rp[r * 3 + 0] * mu[0] + v->Rp[r * 3 + 1] * mu[1] + v->Rp[r * 3 + 2] * mu[2] + v->tp[r];
   const double tx = p->t[0], ty = p->t[1], tz = p->t[2];
+  p->m_far = fabs(tz - v->cfg.far_z) / v->cfg.far_z;
   /* near plane, and the single-level distance mask (culled at and beyond far_z) */
   if (!(tz > v->cfg.near_z) || !(tz < v->cfg.far_z)) return;
   p->o = 1.0 / (1.0 + exp(-(double)v->logits[i]));
@@ -343,8 +350,11 @@ static void project_one(const orc_view* v, int64_t i, orc_proj* p) {
   /* opacity-aware extents: alpha >= alpha_min needs q <= 2 ln(o / alpha_min),
    * and on that ellipse |dx| <= sqrt(qmax Sxx), |dy| <= sqrt(qmax Syy). */
   const double qmax = 2.0 * log(p->o / v->cfg.alpha_min);
-  double ex = ceil(sqrt(qmax * S00) * (1.0 + v->cfg.rect_margin));
-  double ey = ceil(sqrt(qmax * S11) * (1.0 + v->cfg.rect_margin));
+  const double ax = sqrt(qmax * S00) * (1.0 + v->cfg.rect_margin), ay = sqrt(qmax * S11) * (1.0 + v->cfg.rect_margin);
+  double ex = ceil(ax);
+  double ey = ceil(ay);
+  p->m_ext = fmin(fabs(ax - nearbyint(ax)) / fmax(ax, 1.0), fabs(ay - nearbyint(ay)) / fmax(ay, 1.0));
+  p->m_cen = fmin(fabs(p->mu[0] - nearbyint(p->mu[0])), fabs(p->mu[1] - nearbyint(p->mu[1])));
   if (ex > ORC_BIG) ex = ORC_BIG;
   if (ey > ORC_BIG) ey = ORC_BIG;
   p->rx = (int64_t)ex;
@@ -394,11 +404,32 @@ static void eval_pair(const orc_proj* p, double px, double py, double* dx, doubl
 
 static double relmargin(double a, double b) { return fabs(a - b) / fabs(b); }
 
+/* Relative distance of a positive z from the nearest boundary at which its
+ * round-to-nearest FP32 value changes (the midpoints to the neighbouring floats). */
+static double fp32_rounding_margin(double z) {
+  const float f = (float)z;
+  const double up = 0.5 * ((double)f + (double)nextafterf(f, INFINITY));
+  const double dn = 0.5 * ((double)f + (double)nextafterf(f, 0.0f));
+  return fmin(fabs(z - up), fabs(z - dn)) / z;
+}
+
+static uint32_t fp32_bits(double z) {
+  const float f = (float)z;
+  uint32_t b;
+  memcpy(&b, &f, 4);
+  return b;
+}
+
 /* Composite one pixel front to back; fills outputs and the decision margins:
  *   m[0]  min relative distance of an evaluated alpha from alpha_min
  *   m[1]  min relative distance of a candidate transmittance from T_min
  *   m[2]  min relative distance of a blended alpha from the alpha_max clamp
- *   m[3]  min relative depth gap of consecutive blended Gaussians */
+ *   m[3]  depth-order hazard: over consecutive contributing Gaussians (alpha >=
+ *         alpha_min, up to and including the one that stops the pixel) whose
+ *         FP32 depth keys are equal or one unit apart, the min relative distance
+ *         of either FP64 depth from an FP32 rounding boundary (infinite if no
+ *         such pair).  Only such a pair can change order when another
+ *         evaluation of the same FP64 depth rounds to a neighbouring key. */
 static void composite_pixel(const orc_view* v, int px, int py, double* col, double* dep, double* T_out,
                             int32_t* last, int32_t* nb, double m[4]) {
   const int tile = (py / v->TH) * v->TX + (px / v->TW);
@@ -422,8 +453,11 @@ static void composite_pixel(const orc_view* v, int px, int py, double* col, doub
       if (r < m[1]) m[1] = r;
     }
     if (prevz >= 0.0) {
-      r = fabs(p->depth - prevz) / prevz;
-      if (r < m[3]) m[3] = r;
+      const uint32_t a0 = fp32_bits(prevz), a1 = fp32_bits(p->depth);
+      if ((a0 > a1 ? a0 - a1 : a1 - a0) <= 1u) {
+        r = fmin(fp32_rounding_margin(prevz), fp32_rounding_margin(p->depth));
+        if (r < m[3]) m[3] = r;
+      }
     }
     prevz = p->depth;
     if (Tn < v->cfg.t_min) break;
@@ -573,8 +607,10 @@ void orc_view_gauss_margins(const orc_view* v, double* out) {
 
 /* Per-Gaussian projection outputs.  rec: [n][10] = mu_x, mu_y, conic a, b, c,
  * opacity, r, g, b, depth; irec: [n][8] = visible, fxi, fyi, rx, ry, x0..y1 packed
- * as x0, x1, y0, y1 in the last four; misc: [n][6] = per-Gaussian margins
- * (near plane, alpha_min cull, guard band x, guard band y, colour clamp, det). */
+ * as x0, x1, y0, y1 in the last four; misc: [n][9] = per-Gaussian margins
+ * (near plane, alpha_min cull, guard band x, guard band y, colour clamp, det,
+ * far plane (relative), pixel centre from an integer, extent from an integer
+ * (relative)). */
 void orc_view_proj(const orc_view* v, double* rec, int64_t* irec, double* misc) {
   for (int64_t i = 0; i < v->n; ++i) {
     const orc_proj* p = &v->P[i];
@@ -590,7 +626,7 @@ void orc_view_proj(const orc_view* v, double* rec, int64_t* irec, double* misc) 
       r[5] = p->x0; r[6] = p->x1; r[7] = p->y0; r[8] = p->y1;
     }
     if (misc) {
-      double* r = misc + i * 6;
+      double* r = misc + i * 9;
       const double hx = 0.5 * v->W / v->fx, hy = 0.5 * v->H / v->fy;
       const double mx = (0.5 * v->W - v->cx) / v->fx, my = (0.5 * v->H - v->cy) / v->fy;
       double ux = p->t[0] / p->t[2], uy = p->t[1] / p->t[2];
@@ -605,6 +641,7 @@ void orc_view_proj(const orc_view* v, double* rec, int64_t* irec, double* misc) 
       r[0] = fabs(p->t[2] - v->cfg.near_z);
       r[1] = relmargin(p->o, v->cfg.alpha_min);
       r[2] = gx; r[3] = gy; r[4] = cm; r[5] = p->det;
+      r[6] = p->m_far; r[7] = p->m_cen; r[8] = p->m_ext;
     }
   }
 }
@@ -1001,6 +1038,15 @@ int64_t orc_bin_keys(int64_t n_slots, const int32_t* view, const int64_t* gid, c
   for (int64_t e = 0; e < np; ++e) keys[e] = tmp[e].key, gids[e] = tmp[e].gid;
   free(tmp);
   return np;
+}
+
+/* Threads of the OpenMP regions that follow (timing of the oracle on fewer cores). */
+void orc_set_num_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
 }
 
 int orc_num_threads(void) {

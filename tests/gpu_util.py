@@ -22,7 +22,16 @@ LOG2E = 1.4426950408889634
 # before it reaches T_min.  The margins keep a factor of ten on both.
 MARGIN_ALPHA = 2e-4
 MARGIN_T = 2e-3
-MARGIN_DEPTH = 1e-6
+# Both sides order a pixel's Gaussians by the FP32 rounding of an FP64 camera
+# depth, ties by index.  The two FP64 depths differ by ~1e-14 relative at
+# kilometre map coordinates, so an order can differ only where two contributing
+# Gaussians' FP32 keys are equal or adjacent AND one FP64 depth lies that close
+# to an FP32 rounding boundary (the oracle's fourth margin plane).  1e-9 keeps
+# five orders of magnitude.
+MARGIN_DEPTH = 1e-9
+# Largest share of pixels (images) or Gaussians (gradients, counts) whose
+# comparison may fail; every failure must in addition sit at a margin.
+MAX_MISMATCH_SHARE = 1e-3
 
 
 def say(*a):
@@ -78,21 +87,59 @@ def involved_gaussians(ov) -> np.ndarray:
     return pr["visible"] & (own | (m[:, 4] < 1e-4) | (m[:, 2] < 1e-5) | (m[:, 3] < 1e-5))
 
 
-def grad_close(name, got, ref, include, rel_norm=1e-3, rel_elem=1e-3, max_bad=1e-2):
-    """Norm-wise ||d|| <= rel_norm ||g|| over every Gaussian, and element-wise
-    |d| <= rel_elem (|g| + 0.01 rms(g)) over the included ones (a fraction
-    max_bad may fail: Gaussians behind a threshold flip of another Gaussian)."""
+def affected_gaussians(ov, oi=None) -> np.ndarray:
+    """Gaussians whose gradient may legitimately differ between FP32 and FP64:
+    those at a threshold themselves (involved_gaussians) and those whose
+    rectangle holds a pixel at a margin (a flip there changes every gradient
+    blended at that pixel)."""
+    oi = ov.image() if oi is None else oi
+    pr = ov.proj()
+    return involved_gaussians(ov) | (rect_hits(ambiguous_pixels(oi), pr["fxi"], pr["fyi"], pr["rx"], pr["ry"])
+                                     & pr["visible"])
+
+
+def grad_close(name, got, ref, flagged, rel_norm=1e-3, rel_elem=1e-3):
+    """Norm-wise ||d|| <= rel_norm ||g|| over every Gaussian, and per Gaussian
+    |d| <= rel_elem (||g_i|| + 0.01 rms(g)) for every component of its gradient
+    in this tensor (||g_i|| the norm of that Gaussian's components: a quaternion
+    gradient is projected orthogonal to q, so one component can be small next to
+    the others).  A Gaussian that fails must be flagged (affected_gaussians), and
+    at most MAX_MISMATCH_SHARE of the Gaussians may fail.  Returns the relative
+    error and the number of Gaussians that failed."""
     got = np.asarray(got, np.float64)
     ref = np.asarray(ref, np.float64)
     d = got - ref
     nr = np.linalg.norm(ref)
     if nr == 0:
         assert np.abs(got).max(initial=0) < 1e-12, name
-        return 0
+        return 0.0, 0
     rel = np.linalg.norm(d) / nr
     assert rel <= rel_norm, (name, rel)
     rms = math.sqrt(np.mean(ref * ref))
-    di, ri = d[..., include], ref[..., include]
-    bad = np.abs(di) > rel_elem * (np.abs(ri) + 0.01 * rms)
-    assert bad.mean() <= max_bad, (name, int(bad.sum()), bad.size, float(np.abs(di).max()))
-    return rel
+    n = ref.shape[-1]
+    gnorm = np.sqrt((ref.reshape(-1, n) ** 2).sum(0))
+    bad_g = (np.abs(d.reshape(-1, n)) > rel_elem * (gnorm + 0.01 * rms)).any(0)
+    unexplained = bad_g & ~np.asarray(flagged, bool)
+    assert not unexplained.any(), (name, int(unexplained.sum()), np.flatnonzero(unexplained)[:8])
+    assert bad_g.mean() <= MAX_MISMATCH_SHARE, (name, int(bad_g.sum()), bad_g.size)
+    return rel, int(bad_g.sum())
+
+
+def compare_image(got_color, oi, tol=1e-4, got_depth=None, got_tfinal=None) -> tuple:
+    """Every pixel compared: colour (and depth relative to max(1, D), final
+    transmittance) within tol of the oracle; a pixel outside it must be at a
+    margin (ambiguous_pixels), and at most MAX_MISMATCH_SHARE of the pixels may
+    be.  Returns (max error over the pixels within tolerance, failing pixels,
+    pixels at a margin)."""
+    amb = ambiguous_pixels(oi)
+    dc = np.abs(np.asarray(got_color, np.float64) - oi["color"]).max(0)
+    bad = dc > tol
+    if got_depth is not None:
+        bad |= np.abs(np.asarray(got_depth, np.float64) - oi["depth"]) > tol * np.maximum(1.0, oi["depth"])
+    if got_tfinal is not None:
+        bad |= np.abs(np.asarray(got_tfinal, np.float64) - oi["tfinal"]) > tol
+    unexplained = bad & ~amb
+    assert not unexplained.any(), (int(unexplained.sum()), float(dc[unexplained].max()),
+                                   np.argwhere(unexplained)[:4].tolist())
+    assert bad.mean() <= MAX_MISMATCH_SHARE, (int(bad.sum()), bad.size)
+    return float(dc[~bad].max(initial=0.0)), int(bad.sum()), int(amb.sum())

@@ -22,7 +22,7 @@ from oracle import lifecycle
 from paper_2606_30436_amd import scenes
 from paper_2606_30436_amd.rasterizer import (GaussianParams, Image, LifecycleState, Rasterizer, ViewStats,
                                              device_cameras)
-from tests.gpu_util import ambiguous_pixels, oracle_cfg, say
+from tests.gpu_util import MAX_MISMATCH_SHARE, affected_gaussians, compare_image, grad_close, oracle_cfg, say
 
 pytestmark = pytest.mark.gpu
 
@@ -35,9 +35,6 @@ def _rel(got, ref):
     return float(np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-300))
 
 
-def _image_error(col, oi):
-    ok = ~ambiguous_pixels(oi)
-    return float(np.abs(col - oi["color"]).max(0)[ok].max()), float((~ok).mean())
 
 
 def test_c2_single_view_full_size():
@@ -66,14 +63,18 @@ def test_c2_single_view_full_size():
     cfg = oracle_cfg(R)
     ov = oracle.View(sc, 0, cfg)
     oi = ov.image()
-    err, excl = _image_error(img.color.cpu().numpy()[0], oi)
-    say(f"  image max error {err:.2e}, excluded {excl:.3f}")
-    assert err <= 1e-4 and excl < 0.1
+    err, nbad, namb = compare_image(img.color.cpu().numpy()[0], oi)
+    say(f"  image max error {err:.2e}; pixels outside tolerance {nbad} (all at a margin), at a margin {namb}")
+    # dL/dC of the L1 harness, element by element: sign(C - I) / (3 H W) for the view
+    npx = 3 * sc.height * sc.width
+    col = img.color.cpu().numpy()[0].astype(np.float64)
+    want = np.sign(col - sc.target[0]) / npx
+    assert np.array_equal(dl.cpu().numpy()[0].astype(np.float64), want.astype(np.float32).astype(np.float64))
     an = ov.backward(dl.cpu().numpy()[0].astype(np.float64))
+    flagged = affected_gaussians(ov, oi)
     for k in ("means", "log_scales", "quats", "logits", "sh"):
-        rel = _rel(getattr(grads, k).cpu().numpy(), an[k])
-        say(f"  {k} rel {rel:.2e}")
-        assert rel < 1e-3, k
+        rel, nb = grad_close(k, getattr(grads, k).cpu().numpy(), an[k], flagged)
+        say(f"  {k} rel {rel:.2e}, Gaussians outside tolerance {nb} (all flagged; {int(flagged.sum())} flagged)")
     rel = _rel(pose.cpu().numpy()[0], an["pose_xi"])
     say(f"  pose rel {rel:.2e}")
     assert rel < 1e-3
@@ -82,18 +83,19 @@ def test_c2_single_view_full_size():
     pr = ov.proj()
     vis = pr["visible"]
     rad = np.where(vis, np.maximum(pr["rx"], pr["ry"]), 0)
-    rmis = (st.max_radius.cpu().numpy().astype(np.int64) != rad).mean()
-    say(f"  radius mismatches {rmis:.2e} of the Gaussians")
-    assert rmis < 1e-4
+    rdiff = st.max_radius.cpu().numpy().astype(np.int64) != rad
+    say(f"  radius mismatches {int(rdiff.sum())} of the Gaussians")
+    # the radius is the larger integer extent: it differs only where an extent's argument sits next to an integer
+    assert (pr["margins"][rdiff, 8] <= 1e-4).all()
     gn_ref = np.linalg.norm(an["g2"][:, 0:2], axis=1)
     rel = _rel(st.grad_norm_sum.cpu().numpy(), gn_ref)
     say(f"  mean-gradient norm rel {rel:.2e}")
     assert rel < 1e-3
     s = ov.stats(sc.target[0], 0.1)
     om = st.omega_sum.cpu().numpy().astype(np.int64)
-    mism = (om != s["omega"]).mean()
-    say(f"  footprint mismatches {mism:.2e} of the Gaussians")
-    assert mism < 1e-3
+    mism = om != s["omega"]
+    say(f"  footprint mismatches {int(mism.sum())} of the Gaussians")
+    assert not (mism & ~flagged).any() and mism.mean() <= MAX_MISMATCH_SHARE
 
 
 def test_c3_bench_chunk_full_size():
@@ -131,14 +133,19 @@ def test_c3_bench_chunk_full_size():
     ka_ref = np.zeros((V, sc.n), np.int32)
     lossv = loss.cpu().numpy()
     pg = pose.cpu().numpy()
+    flagged = np.zeros(sc.n, bool)
+    npx = 3 * sc.height * sc.width
     for v in range(V):
         ov = oracle.View(sc, v, cfg)
         oi = ov.image()
-        err, excl = _image_error(col[v], oi)
+        err, nbad, namb = compare_image(col[v], oi)
+        # dL/dC of the fused L1 loss: sign(C - I) / (3 H W) per view, element by element
+        want = (np.sign(col[v].astype(np.float64) - sc.target[v]) / npx).astype(np.float32)
+        assert np.array_equal(dl.cpu().numpy()[v], want)
         an = ov.backward(dlv[v])
+        flagged |= affected_gaussians(ov, oi)
         prel = _rel(pg[v], an["pose_xi"])
-        say(f"  view {v}: image error {err:.2e} (excluded {excl:.3f}), pose rel {prel:.2e}")
-        assert err <= 1e-4 and excl < 0.25
+        say(f"  view {v}: image error {err:.2e} (outside tolerance {nbad}, at a margin {namb}), pose rel {prel:.2e}")
         assert prel < 1e-3
         assert lossv[v] == pytest.approx(np.abs(col[v].astype(np.float64) - sc.target[v]).mean(), rel=1e-5)
         for k in ref:
@@ -148,9 +155,8 @@ def test_c3_bench_chunk_full_size():
         ka_ref[v] = sv["kappa"]
         del ov
     for k in ref:
-        rel = _rel(getattr(grads, k).cpu().numpy(), ref[k])
-        say(f"  {k} rel {rel:.2e}")
-        assert rel < 1e-3, k
+        rel, nb = grad_close(k, getattr(grads, k).cpu().numpy(), ref[k], flagged)
+        say(f"  {k} rel {rel:.2e}, Gaussians outside tolerance {nb} (all flagged; {int(flagged.sum())} flagged)")
     # the lifecycle step (the chunk folded its sums into the state and reset
     # them): the chunk rules on the oracle's counts with the GPU's own losses.
     # Counts of a Gaussian at the alpha or T threshold may differ by one pixel

@@ -18,8 +18,8 @@ from oracle import OracleConfig, lifecycle
 from paper_2606_30436_amd import scenes
 from paper_2606_30436_amd.rasterizer import (GaussianParams, Image, LifecycleState, Rasterizer, ViewStats,
                                              device_cameras)
-from tests.gpu_util import (LOG2E, ambiguous_pixels, grad_close, involved_gaussians, oracle_cfg, rect_hits,
-                            run_forward, say)
+from tests.gpu_util import (LOG2E, MAX_MISMATCH_SHARE, affected_gaussians, ambiguous_pixels, compare_image,
+                            grad_close, involved_gaussians, oracle_cfg, rect_hits, run_forward, say)
 
 pytestmark = pytest.mark.gpu
 
@@ -56,9 +56,16 @@ def test_project_records_match_oracle(name):
         pix = b["slot_pix"].numpy()[sel]
         pr = oracle.View(sc, v, cfg).proj()
         vis = np.nonzero(pr["visible"])[0]
-        # visible sets agree except for Gaussians at a culling margin
+        # visible sets agree; a Gaussian on one side only must sit at a culling margin of its own (near / far
+        # plane, alpha_min cull, determinant) or at an integer decision of its rectangle (centre or extent next
+        # to an integer, which can empty the rectangle at the image border)
+        m = pr["margins"]
+        z = np.abs(m[:, 0]) + cfg.near
+        at_margin = ((m[:, 0] <= 1e-9 * z) | (m[:, 6] <= 1e-9) | (m[:, 1] <= 1e-5) | (np.abs(m[:, 5]) <= 1e-6)
+                     | (m[:, 7] <= 1e-3) | (m[:, 8] <= 1e-4))
         diff = np.setxor1d(gid, vis)
-        assert len(diff) <= max(2, 1e-3 * len(vis)), diff
+        say(f"  view {v}: visible {len(vis)}, on one side only {len(diff)}")
+        assert at_margin[diff].all(), diff[~at_margin[diff]]
         common, ig, io = np.intersect1d(gid, vis, return_indices=True)
         r = rec[ig]
         mu = r[:, 0:2] + 0.5 + np.array([sc.width // 2, sc.height // 2])
@@ -76,9 +83,11 @@ def test_project_records_match_oracle(name):
         assert np.allclose(2.0 ** r[:, 5], pr["opacity"][common], rtol=1e-5)
         assert np.allclose(r[:, 6], pr["depth"][common], rtol=1e-6)
         assert np.allclose(r[:, 8:11], pr["color"][common], atol=2e-5)
-        # integer centre and extents: equal except where FP64 sits next to an integer
+        # integer centre and extents: equal, except where the FP64 centre or extent sits next to an integer
         same = (pix[ig] == np.stack([pr["fxi"], pr["fyi"], pr["rx"], pr["ry"]], 1)[common]).all(1)
-        assert same.mean() >= 0.995, same.mean()
+        near_int = (m[common, 7] <= 1e-3) | (m[common, 8] <= 1e-4)
+        say(f"  view {v}: integer centre / extent differences {int((~same).sum())} of {len(common)}")
+        assert near_int[~same].all(), common[~same & ~near_int]
 
 
 @pytest.mark.parametrize("name,tile", [("c1", (16, 16)), ("c1", (8, 32)), ("tiny", (32, 8)), ("c1", (32, 16)),
@@ -185,8 +194,7 @@ def test_sixty_four_views():
     for v in range(64):
         ov = oracle.View(sc, v, cfg)
         oi = ov.image()
-        ok = ~ambiguous_pixels(oi)
-        assert np.abs(col[v] - oi["color"]).max(0)[ok].max() <= 1e-4, v
+        compare_image(col[v], oi)
         an = ov.backward(dLdC[v])
         for k in ref:
             ref[k] = ref[k] + an[k]
@@ -228,8 +236,7 @@ def test_a_view_that_sees_nothing():
     for v in (0, 2):
         ov = oracle.View(sc, v, cfg)
         oi = ov.image()
-        ok = ~ambiguous_pixels(oi)
-        assert np.abs(col[v] - oi["color"]).max(0)[ok].max() <= 1e-4
+        compare_image(col[v], oi)
         an = ov.backward(dLdC[v])
         for k in ref:
             ref[k] = ref[k] + an[k]
@@ -250,19 +257,15 @@ def test_render_forward_matches_oracle(name):
     col = img.color.cpu().numpy().astype(np.float64)
     dep = img.depth.cpu().numpy().astype(np.float64)
     tf = img.t_final.cpu().numpy().astype(np.float64)
-    excluded = 0
-    total = 0
+    failed = margin = total = 0
     for v in range(sc.n_views):
         oi = oracle.View(sc, v, cfg).image()
-        ok = ~ambiguous_pixels(oi)
-        excluded += int((~ok).sum())
-        total += ok.size
-        dc = np.abs(col[v] - oi["color"]).max(0)
-        assert dc[ok].max() <= 1e-4, dc[ok].max()
-        assert (np.abs(dep[v] - oi["depth"])[ok] <= 1e-4 * np.maximum(1.0, oi["depth"][ok])).all()
-        assert np.abs(tf[v] - oi["tfinal"])[ok].max() <= 1e-4
-    say(f"  excluded near-threshold pixels: {excluded}/{total}")
-    assert excluded <= 0.05 * total
+        err, nbad, namb = compare_image(col[v], oi, got_depth=dep[v], got_tfinal=tf[v])
+        failed += nbad
+        margin += namb
+        total += oi["depth"].size
+        say(f"  view {v}: max error {err:.2e}")
+    say(f"  pixels outside tolerance (all at a margin): {failed}/{total}; pixels at a margin: {margin}")
 
 
 def _oracle_grads(sc, cfg, dLdC, dLdD):
@@ -284,6 +287,13 @@ def _involved(sc, cfg):
     bad = np.zeros(sc.n, bool)
     for v in range(sc.n_views):
         bad |= involved_gaussians(oracle.View(sc, v, cfg))
+    return bad
+
+
+def _affected(sc, cfg):
+    bad = np.zeros(sc.n, bool)
+    for v in range(sc.n_views):
+        bad |= affected_gaussians(oracle.View(sc, v, cfg))
     return bad
 
 
@@ -311,15 +321,14 @@ def test_render_backward_matches_oracle(name, depth, px):
     torch.cuda.synchronize()
     cfg = oracle_cfg(R)
     ref = _oracle_grads(sc, cfg, dLdC, dLdD)
-    bad = _involved(sc, cfg)
-    say(f"  Gaussians at a threshold: {int(bad.sum())}/{sc.n}")
-    assert bad.mean() <= 0.1
-    inc = ~bad
+    flagged = _affected(sc, cfg)
     rels = {}
     for k in ("means", "log_scales", "quats", "logits", "sh"):
         got = getattr(grads, k).cpu().numpy()
-        rels[k] = grad_close(k, got, ref[k], inc)
-    say("  relative gradient error " + " ".join(f"{k}={v:.2e}" for k, v in rels.items()))
+        rels[k] = grad_close(k, got, ref[k], flagged)
+    say(f"  Gaussians flagged at a margin: {int(flagged.sum())}/{sc.n}")
+    say("  relative gradient error (Gaussians outside tolerance) "
+        + " ".join(f"{k}={v[0]:.2e} ({v[1]})" for k, v in rels.items()))
     pg = pose_grad.cpu().numpy()
     d = np.linalg.norm(pg - ref["pose_xi"], axis=1) / np.linalg.norm(ref["pose_xi"], axis=1)
     say(f"  pose gradient relative error per view {d}")
@@ -345,7 +354,7 @@ def test_statistics_match_oracle(name):
     cfg = oracle_cfg(R)
     om = np.zeros(sc.n, np.int64)
     ka = np.zeros(sc.n, np.int64)
-    bad = _involved(sc, cfg)
+    bad = _affected(sc, cfg)
     lossv = loss.cpu().numpy()
     col = img.color.cpu().numpy()
     for v in range(V):
@@ -357,12 +366,14 @@ def test_statistics_match_oracle(name):
         bad |= rect_hits(s["mask_margin"] < 1e-4, pr["fxi"], pr["fyi"], pr["rx"], pr["ry"]) & pr["visible"]
         ref_loss = np.abs(col[v].astype(np.float64) - sc.target[v]).mean()
         assert lossv[v] == pytest.approx(ref_loss, rel=1e-5)
-    inc = ~bad
     gom = st.omega_sum.cpu().numpy()
     gka = st.kappa_sum.cpu().numpy()
-    mism = ((gom != om) | (gka != ka)) & inc
-    say(f"  excluded {int(bad.sum())}/{sc.n}, count mismatches {int(mism.sum())}")
-    assert mism.sum() <= max(1, 1e-3 * inc.sum())
+    mism = (gom != om) | (gka != ka)
+    say(f"  flagged at a margin {int(bad.sum())}/{sc.n}, count mismatches {int(mism.sum())}")
+    # every count that differs belongs to a Gaussian at a threshold or whose rectangle holds a pixel at the
+    # error-mask threshold
+    assert not (mism & ~bad).any(), np.flatnonzero(mism & ~bad)[:8]
+    assert mism.mean() <= MAX_MISMATCH_SHARE
     assert (gka <= gom).all()
     gam = st.gamma_sum.cpu().numpy()
     # gamma = sum_v L_v |Omega_v|, with the GPU's own per-view losses

@@ -488,3 +488,35 @@ def test_oracle_tile_lists_follow_the_binning_contract():
                                  pr["ry"][vis], pr["depth"][vis].astype(np.float32).view(np.uint32), 70, 45, 16, 16)
     tile, gid = v.pairs()
     assert np.array_equal(keys >> np.uint64(32), tile.astype(np.uint64)) and np.array_equal(gids, gid)
+
+
+@pytest.mark.parametrize("gap_ulps,t_z,hazard", [(1, 0.0, True), (0, 0.0, True), (2, 0.0, False),
+                                                 (1, 2.0 ** -25, True)])
+def test_depth_order_hazard_margin(gap_ulps, t_z, hazard):
+    """The image's fourth margin plane flags a pixel only where two consecutive
+    contributing Gaussians have FP32 depth keys equal or one unit apart, and then
+    measures how close either FP64 depth lies to an FP32 rounding boundary.  At
+    depth 4 the float spacing is 2^-22 below and 2^-21 above, so a float-exact 4
+    sits 2^-23 from the boundary below; a camera shift of 2^-25 moves it."""
+    z0 = np.float32(4.0)
+    z1 = z0
+    for _ in range(gap_ulps):
+        z1 = np.nextafter(z1, np.float32(np.inf))
+    sh = np.zeros((1, 3, 2), np.float32)
+    cam = scenes.make_camera(np.eye(3), np.array([0.0, 0.0, t_z]), 40.0, 40.0, 16.5, 16.5, 32, 32)
+    sc = scenes.Scene(np.array([[0.0, 0.0], [0.0, 0.0], [z0, z1]], np.float32), np.full((3, 2), -2.5, np.float32),
+                      np.tile(np.array([[1], [0], [0], [0]], np.float32), (1, 2)), np.full(2, 0.0, np.float32), sh, 0,
+                      scenes.stack_cameras([cam]), np.zeros((1, 6), np.float32))
+    m3 = oracle.View(sc, 0, CFG).image()["margins"][3][16, 16]
+    if not hazard:
+        assert m3 == np.inf
+        return
+    d0, d1 = float(z0) + t_z, float(z1) + t_z
+    # distance from the nearest rounding boundary, by hand from the float spacing around 4
+    def margin(d):
+        f = np.float32(d)
+        lo, hi = float(np.nextafter(f, np.float32(0))), float(np.nextafter(f, np.float32(np.inf)))
+        return min(abs(d - (float(f) + hi) / 2), abs(d - (float(f) + lo) / 2)) / d
+    assert m3 == pytest.approx(min(margin(d0), margin(d1)), rel=1e-12)
+    if t_z == 0.0:
+        assert m3 == pytest.approx(2.0 ** -23 / 4.0, rel=1e-12)  # half of the 2^-22 spacing below 4
