@@ -10,6 +10,8 @@ Modules
   lifecycle.py   chunk scores, global OR / max rules and the decision (NumPy FP64)
   brute.py       tile-free compositing in plain PyTorch FP64 with autograd
   mlp.py         the prune/keep/densify network with BF16 rounding, FP64 GEMMs
+  mapping_loss.py  the mapping loss (L1 + D-SSIM, depth L1, isotropy) and its
+                 gradients in plain PyTorch FP64
 
 Every function cites the passage of the paper it follows; readings of passages
 the paper leaves open are the constants of OracleConfig.
