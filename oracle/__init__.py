@@ -12,6 +12,9 @@ Modules
   mlp.py         the prune/keep/densify network with BF16 rounding, FP64 GEMMs
   mapping_loss.py  the mapping loss (L1 + D-SSIM, depth L1, isotropy) and its
                  gradients in plain PyTorch FP64
+  init_prob.py   probabilistic initialisation (DoG, depth gradient, residual
+                 against the render, 3x3 suppression, unprojection, level and
+                 voxel quantisation) in NumPy FP64
 
 Every function cites the passage of the paper it follows; readings of passages
 the paper leaves open are the constants of OracleConfig.
