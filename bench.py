@@ -38,6 +38,10 @@ HBM_BYTES_PER_S = 8e12
 # the forward's blend of an entry (exp2, clamp, weight, three colour and one depth FMA, T update)
 FLOP_FWD_BLEND = 20
 SH_K = 16  # SH degree 3
+# mapping loss per pixel and channel: the products x^2, y^2, xy (3), five maps filtered by the separable
+# 11-tap window (2 x 11 FMA each: 220), SSIM and its three derivative maps (35), those three filtered
+# (132), the gradient (8)
+MAPLOSS_FLOP_PER_PX_CH = 3 + 220 + 35 + 132 + 8
 
 
 def chunk_roofline(stage_ms: dict, ms: float, N: int, S: int, P: int, P_live: int, E: int, E_b: int,
@@ -339,6 +343,47 @@ def main():
         return 10 * math.log10(1.0 / mse) if mse > 0 else float("inf")
     psnr_b = psnr(batched_color.clamp(0, 1), target.clamp(0, 1))
 
+    # ---- the adjacent rows of the mapping step on this chunk, each timed on its own
+    def timed(fn, reps=10):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    adjacent = {}
+    # mapping loss (0.8 L1 + 0.2 D-SSIM and the depth L1 against renders of the noise-free map)
+    tgt_depth = torch.empty(V, H, W, device=dev)
+    R.project(gt, cams)
+    R.bin_sort()
+    timg = Image(torch.empty_like(img.color), tgt_depth, torch.empty_like(img.t_final), torch.empty_like(img.last))
+    R.render_fwd(timg)
+    R.project(g, cams)
+    R.bin_sort()
+    R.render_fwd(img)
+    ml_dl, ml_dd = torch.empty_like(img.color), torch.empty_like(img.depth)
+    ml_loss, ml_geo = torch.empty(V, device=dev), torch.empty(V, device=dev)
+    t_ml = timed(lambda: R.loss_mapping(V, img, target, ml_dl, ml_loss, target_depth=tgt_depth, dl_ddepth=ml_dd,
+                                        geo_loss=ml_geo))
+    px_ch = 3 * V * W * H
+    flop_ml = MAPLOSS_FLOP_PER_PX_CH * px_ch + 3 * V * W * H
+    bytes_ml = 12 * px_ch + 12 * V * W * H
+    adjacent["mapping_loss"] = {
+        "ms": round(t_ml, 4), "bound": "alu", "flop": int(flop_ml), "bytes": int(bytes_ml),
+        "achieved_tflops": round(flop_ml / (t_ml / 1e3) / 1e12, 3),
+        "frac": round(flop_ml / (t_ml / 1e3) / 1e12 / PEAK_ALU_TFLOPS, 4),
+        "photometric_loss_per_view": [round(float(x), 5) for x in ml_loss.cpu().tolist()]}
+    iso_loss = torch.empty(1, device=dev)
+    iso_grad = torch.zeros(3, N, device=dev)
+    t_iso = timed(lambda: R.loss_iso(g, iso_loss, iso_grad))
+    adjacent["isotropy"] = {"ms": round(t_iso, 4), "bound": "hbm", "bytes": 36 * N,
+                            "frac": round(36 * N / (t_iso / 1e3) / HBM_BYTES_PER_S, 4)}
+    log(f"[bench] adjacent rows {json.dumps(adjacent)}")
+
     # ---- CPU oracle baseline (the whole chunk, FP64, all host threads)
     cpu = None
     if not args.no_cpu:
@@ -398,6 +443,7 @@ def main():
                    "autotune_ms": table},
         "roofline": roofline,
         "chunk_roofline": chunk_roof,
+        "adjacent_rows": adjacent,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

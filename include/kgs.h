@@ -262,6 +262,73 @@ kgs_status kgs_render_fwd(kgs_ctx* ctx, const kgs_image* out, void* stream);
 kgs_status kgs_loss_l1(kgs_ctx* ctx, const float* target, const kgs_image* img, float* dl_dcolor,
                        float* view_loss, void* stream);
 
+/* Mapping loss of the sliding-window optimisation (Sec. 3.2, Eq. mapping loss;
+ * appendix "Rendering Objectives") over n_views rendered views:
+ *   view_loss[v] = L_photo,v = w_l1 mean|I - C| + w_ssim (1 - mean SSIM(I, C))
+ *   geo_loss[v]  = L_geo,v   = mean|D_target - D|        (if target_depth)
+ * means over the view's 3 H W (colour) or H W (depth) values; SSIM with an
+ * 11x11 Gaussian window (sigma 1.5), C1 = 0.01^2, C2 = 0.03^2, per channel,
+ * zero padding.  Gradients of sum_v (L_photo,v + lambda_g L_geo,v) are
+ * WRITTEN: dl_dcolor [V][3][H][W]; dl_ddepth [V][H][W] when target_depth is
+ * given (required then).  The paper's weights are w_l1 = 0.8, w_ssim = 0.2,
+ * lambda_g = 0.01.  img: colour [V][3][H][W] (and depth [V][H][W]) of the
+ * configured image size; target [V][3][H][W]; target_depth [V][H][W] or NULL;
+ * geo_loss [V] or NULL.  Uses the workspace; deterministic. */
+kgs_status kgs_loss_mapping(kgs_ctx* ctx, int32_t n_views, const kgs_image* img, const float* target,
+                            const float* target_depth, float w_l1, float w_ssim, float lambda_g, float* dl_dcolor,
+                            float* dl_ddepth, float* view_loss, float* geo_loss, void* stream);
+
+/* Isotropy regulariser (appendix "Rendering Objectives"):
+ *   L_iso = sum_i sum_k |s_ik - mean_k s_ik|,  s = exp(log_scales)
+ * written to loss (device scalar, unweighted); lambda_iso dL_iso/dlog_scales
+ * is ADDED to grad_log_scales [3][N] (or NULL).  The paper's lambda_iso = 10. */
+kgs_status kgs_loss_iso(kgs_ctx* ctx, const kgs_gaussians* g, float lambda_iso, float* grad_log_scales, float* loss,
+                        void* stream);
+
+/* ------------------------------------------------------------------------
+ * Probabilistic Gaussian initialisation (Sec. 3.3, "Probabilistic Gaussian
+ * Initialization") with the level-of-detail voxel rule of Sec. 3.2
+ * ("Hierarchical Anchor Management"), for a batch of keyframes:
+ *   DoG  = min(|(G_s1 - G_s2) * I|, 1),   I the mean of the three channels
+ *   P    = min(0.9 DoG + 0.1 norm(||grad D||), 1)   (lambda = 0.9, hyper-parameter table)
+ *   P_kf = max(P - P^, 0)    with P^ the same map of the rendered colour and depth
+ * A pixel spawns if P_kf > 0 is not below any in-image 3x3 neighbour (the
+ * suppression), u < P_kf for the caller's uniform u, and its depth is
+ * positive.  It is unprojected at its pixel centre, x = R^T (d K^-1 (x+.5,
+ * y+.5, 1) - t), and quantised at the level l of its camera distance,
+ * voxel = floor(x / eps_l).  Readings: s1 = 1, s2 = 1.6, blur radius
+ * round(3 s) with the border pixel repeated; central depth differences inside
+ * the image, one-sided on its border; min-max normalisation per image;
+ * eps = (0.1, 0.25, 1, 5, 25) m (the printed third size, 0.1, read as 1) and
+ * level l for camera distances below 100 eps_l (the last level unbounded).
+ * Every decision is taken in FP64.
+ * ------------------------------------------------------------------------ */
+typedef struct kgs_spawn_list {
+  int32_t* pixel;    /* [capacity][2]: keyframe, pixel index y * width + x */
+  int32_t* level;    /* [capacity]: level 0..4 */
+  int32_t* voxel;    /* [capacity][3]: floor(x / eps_level) */
+  float* point;      /* [capacity][3]: the unprojected world point */
+  float* color;      /* [capacity][3]: the keyframe's colour at the pixel (or NULL) */
+  uint32_t* count;   /* device scalar: spawning pixels, which may exceed capacity (then only the first
+                        capacity, in (keyframe, row, column) order, are written) */
+  int64_t capacity;
+} kgs_spawn_list;
+
+/* Bytes of device workspace kgs_init_spawn needs (host only). */
+kgs_status kgs_init_workspace_size(int32_t width, int32_t height, int32_t n_views, size_t* bytes);
+
+/* color [V][3][H][W] in [0, 1]; depth [V][H][W] (the depth prior D, metres);
+ * rendered [V][3][H][W] and rendered_depth [V][H][W] (the map's render of each
+ * keyframe) or both NULL (a first keyframe: P_kf = P); uniforms [V][H][W] in
+ * [0, 1); cams: device [V] world->camera pinhole cameras; workspace of
+ * kgs_init_workspace_size bytes, 256-byte aligned; p_kf [V][H][W] (FP32 copy
+ * of P_kf) or NULL.  Writes the spawning pixels to out in (keyframe, row,
+ * column) order.  Deterministic. */
+kgs_status kgs_init_spawn(const float* color, const float* depth, const float* rendered, const float* rendered_depth,
+                          const float* uniforms, const kgs_camera* cams, int32_t n_views, int32_t width,
+                          int32_t height, void* workspace, size_t workspace_bytes, float* p_kf,
+                          const kgs_spawn_list* out, void* stream);
+
 /* Backward of render_fwd and project for the last projected views, plus the
  * per-view footprint statistics (appendix, densification and pruning
  * scores: Omega_v(i), M_v, kappa_v(i), gamma_v(i) = L_v |Omega_v(i)|).

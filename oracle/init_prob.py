@@ -142,10 +142,20 @@ def spawn_candidates(color, depth, cam, u, rendered=None, rendered_depth=None) -
     idx = np.floor(X / eps[None, :]).astype(np.int64) if len(lev) else np.zeros((3, 0), np.int64)
     # margins: how close each decision came to its threshold (relative where it has a scale)
     m_u = np.abs(u - Pk)
+    q = np.pad(Pk, 1, mode="constant", constant_values=np.nan)
+    m_nms = np.full(Pk.shape, np.inf)
+    for dy in (-1, 0, 1):
+        for dx in (-1, 0, 1):
+            if dy or dx:
+                nb = q[1 + dy:1 + dy + H, 1 + dx:1 + dx + W]
+                gap = np.abs(Pk - nb) / np.maximum(np.maximum(Pk, nb), 1e-300)
+                both_clipped = (Pk == 1.0) & (nb == 1.0)   # exact on every side: min(., 1)
+                gap = np.where(np.isnan(nb) | both_clipped, np.inf, gap)
+                m_nms = np.minimum(m_nms, gap)
     with np.errstate(invalid="ignore"):
         frac = X / eps[None, :] - np.floor(X / eps[None, :]) if len(lev) else np.zeros((3, 0))
     m_floor = np.minimum(frac, 1.0 - frac).min(axis=0) if len(lev) else np.zeros(0)
     bands = np.array([dm for dm in DMAX if np.isfinite(dm)])
     m_level = (np.abs(dist[:, None] - bands[None, :]) / bands[None, :]).min(axis=1) if len(lev) else np.zeros(0)
     return dict(P=P, P_kf=Pk, keep=keep, spawn=spawn, pixel=pix, point=X.T, level=lev, voxel=idx.T,
-                margin_u=m_u, margin_floor=m_floor, margin_level=m_level)
+                margin_u=m_u, margin_nms=m_nms, margin_floor=m_floor, margin_level=m_level)

@@ -75,6 +75,30 @@ def iso_loss(log_scales: torch.Tensor) -> torch.Tensor:
     return (s - s.mean(dim=0, keepdim=True)).abs().sum()
 
 
+def ssim_gradient_term_scale(color, target) -> np.ndarray:
+    """Diagnostic for comparisons in another arithmetic (not part of the loss):
+    dL/dC of the D-SSIM term is the sum of three parts -- through the local
+    mean, through the local second moment and through the local cross moment
+    of C -- which cancel almost exactly where the image is flat.  Returns, per
+    element of color [V, 3, H, W], w_ssim / (3 H W) times the sum of the three
+    parts' magnitudes, each part taken by autograd through its own copy of C."""
+    col = np.asarray(color, np.float64)
+    tgt = np.asarray(target, np.float64)
+    V, _, H, W = col.shape
+    out = np.zeros_like(col)
+    for v in range(V):
+        xa, xb, xc = (torch.tensor(col[v], requires_grad=True) for _ in range(3))
+        y = torch.tensor(tgt[v])
+        mx, my = _blur(xa), _blur(y)
+        sxx = _blur(xb * xb) - mx * mx
+        syy = _blur(y * y) - my * my
+        sxy = _blur(xc * y) - mx * my
+        s = ((2 * mx * my + C1) * (2 * sxy + C2)) / ((mx * mx + my * my + C1) * (sxx + syy + C2))
+        s.sum().backward()
+        out[v] = (xa.grad.abs() + xb.grad.abs() + xc.grad.abs()).numpy() * W_SSIM / (3 * H * W)
+    return out
+
+
 def mapping_loss(color, target, depth=None, target_depth=None, log_scales=None, lambda_g=LAMBDA_G,
                  lambda_iso=LAMBDA_ISO) -> dict:
     """color, target: [V, 3, H, W]; depth, target_depth: [V, H, W] or None; log_scales [3, N] or None

@@ -57,6 +57,11 @@ class KgsLifecycleState(ctypes.Structure):
     _fields_ = [("densify", c_void_p), ("prune_score", c_void_p)]
 
 
+class KgsSpawnList(ctypes.Structure):
+    _fields_ = [("pixel", c_void_p), ("level", c_void_p), ("voxel", c_void_p), ("point", c_void_p),
+                ("color", c_void_p), ("count", c_void_p), ("capacity", c_int64)]
+
+
 class KgsBuffers(ctypes.Structure):
     _fields_ = [("n_slots", c_void_p), ("n_pairs", c_void_p), ("slot_rec", c_void_p), ("slot_gid", c_void_p),
                 ("slot_view", c_void_p), ("slot_pix", c_void_p), ("slot_pairoff", c_void_p), ("keys", c_void_p),
@@ -82,6 +87,12 @@ _SIGS = {
     "kgs_bin_sort": (c_int32, [c_void_p, c_void_p]),
     "kgs_render_fwd": (c_int32, [c_void_p, P(KgsImage), c_void_p]),
     "kgs_loss_l1": (c_int32, [c_void_p, c_void_p, P(KgsImage), c_void_p, c_void_p, c_void_p]),
+    "kgs_loss_mapping": (c_int32, [c_void_p, c_int32, P(KgsImage), c_void_p, c_void_p, c_float, c_float, c_float,
+                                   c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "kgs_loss_iso": (c_int32, [c_void_p, P(KgsGaussians), c_float, c_void_p, c_void_p, c_void_p]),
+    "kgs_init_workspace_size": (c_int32, [c_int32, c_int32, c_int32, P(ctypes.c_size_t)]),
+    "kgs_init_spawn": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_int32,
+                                 c_int32, c_void_p, ctypes.c_size_t, c_void_p, P(KgsSpawnList), c_void_p]),
     "kgs_render_bwd": (c_int32, [c_void_p, P(KgsGaussians), c_void_p, c_int32, c_void_p, P(KgsImage), c_void_p,
                                  c_void_p, c_void_p, c_void_p, c_float, c_void_p, P(KgsGrads), P(KgsViewStats),
                                  c_void_p]),
@@ -210,6 +221,32 @@ def kgs_render_fwd(ctx, img: KgsImage, stream=None):
 def kgs_loss_l1(ctx, target, img: KgsImage, dl_dcolor, view_loss, stream=None):
     check(load().kgs_loss_l1(ctypes.c_void_p(ctx), ptr(target), ctypes.byref(img), ptr(dl_dcolor), ptr(view_loss),
                              stream_handle(stream)), "kgs_loss_l1")
+
+
+def kgs_loss_mapping(ctx, n_views, img: KgsImage, target, target_depth, w_l1, w_ssim, lambda_g, dl_dcolor, dl_ddepth,
+                     view_loss, geo_loss, stream=None):
+    check(load().kgs_loss_mapping(ctypes.c_void_p(ctx), int(n_views), ctypes.byref(img), ptr(target), ptr(target_depth),
+                                  float(w_l1), float(w_ssim), float(lambda_g), ptr(dl_dcolor), ptr(dl_ddepth),
+                                  ptr(view_loss), ptr(geo_loss), stream_handle(stream)), "kgs_loss_mapping")
+
+
+def kgs_loss_iso(ctx, g: KgsGaussians, lambda_iso, grad_log_scales, loss, stream=None):
+    check(load().kgs_loss_iso(ctypes.c_void_p(ctx), ctypes.byref(g), float(lambda_iso), ptr(grad_log_scales), ptr(loss),
+                              stream_handle(stream)), "kgs_loss_iso")
+
+
+def kgs_init_workspace_size(width, height, n_views) -> int:
+    n = ctypes.c_size_t()
+    check(load().kgs_init_workspace_size(int(width), int(height), int(n_views), ctypes.byref(n)),
+          "kgs_init_workspace_size")
+    return int(n.value)
+
+
+def kgs_init_spawn(color, depth, rendered, rendered_depth, uniforms, cams, n_views, width, height, workspace,
+                   workspace_bytes, p_kf, out: KgsSpawnList, stream=None):
+    check(load().kgs_init_spawn(ptr(color), ptr(depth), ptr(rendered), ptr(rendered_depth), ptr(uniforms), ptr(cams),
+                                int(n_views), int(width), int(height), ptr(workspace), int(workspace_bytes), ptr(p_kf),
+                                ctypes.byref(out), stream_handle(stream)), "kgs_init_spawn")
 
 
 def kgs_render_bwd(ctx, g: KgsGaussians, cams, n_views, pose_xi, img: KgsImage, dl_dcolor, dl_ddepth, dl_dalpha,

@@ -104,6 +104,8 @@ size_t layout(const kgs_config& c, char* base, kgs_ctx* ctx) {
   }
   p = take(48 * V * KGS_POSE_BLOCKS);           if (ctx) ctx->pose_partial = (double*)p;
   p = take(8 * V * T);                          if (ctx) ctx->loss_partial = (double*)p;
+  p = take(4 * 9 * V * (int64_t)c.width * c.height); if (ctx) ctx->ssim_aux = (float*)p;
+  p = take(8 * 9 * V * (int64_t)kgs_maploss_tiles(c.width, c.height)); if (ctx) ctx->ssim_partial = (double*)p;
   p = take(16 * (nb + 1));                      if (ctx) ctx->mm_partial = (double*)p;
   p = take(4 * (nb + 1));                       if (ctx) ctx->keep_partial = (uint32_t*)p;
   return off;
@@ -257,6 +259,47 @@ kgs_status kgs_loss_l1(kgs_ctx* ctx, const float* target, const kgs_image* img, 
   if (!ctx || !target || !img || !img->color || !dl_dcolor || !view_loss) return KGS_ERR_INVALID_ARG;
   if (!ctx->projected) return KGS_ERR_STATE;
   return kgs_launch_loss(ctx, target, img, dl_dcolor, view_loss, (hipStream_t)stream);
+}
+
+kgs_status kgs_loss_mapping(kgs_ctx* ctx, int32_t n_views, const kgs_image* img, const float* target,
+                            const float* target_depth, float w_l1, float w_ssim, float lambda_g, float* dl_dcolor,
+                            float* dl_ddepth, float* view_loss, float* geo_loss, void* stream) {
+  if (!ctx || !img || !img->color || !target || !dl_dcolor || !view_loss) return KGS_ERR_INVALID_ARG;
+  if (n_views < 1 || n_views > ctx->cfg.max_views) return KGS_ERR_INVALID_ARG;
+  if (target_depth && (!img->depth || !dl_ddepth)) return KGS_ERR_INVALID_ARG;
+  if (!(w_l1 >= 0.f) || !(w_ssim >= 0.f) || !(lambda_g >= 0.f)) return KGS_ERR_INVALID_ARG;
+  return kgs_launch_loss_mapping(ctx, n_views, target, target_depth, img, w_l1, w_ssim, lambda_g, dl_dcolor,
+                                 dl_ddepth, view_loss, geo_loss, (hipStream_t)stream);
+}
+
+kgs_status kgs_loss_iso(kgs_ctx* ctx, const kgs_gaussians* g, float lambda_iso, float* grad_log_scales, float* loss,
+                        void* stream) {
+  if (!ctx || !g || !g->log_scales || !loss || g->n < 0 || g->n > ctx->cfg.max_gaussians) return KGS_ERR_INVALID_ARG;
+  if (!(lambda_iso >= 0.f)) return KGS_ERR_INVALID_ARG;
+  return kgs_launch_loss_iso(ctx, g, lambda_iso, grad_log_scales, loss, (hipStream_t)stream);
+}
+
+kgs_status kgs_init_workspace_size(int32_t width, int32_t height, int32_t n_views, size_t* bytes) {
+  if (!bytes || width <= 0 || height <= 0 || width > 32000 || height > 32000 || n_views < 1 || n_views > 65535)
+    return KGS_ERR_INVALID_ARG;
+  *bytes = kgs_init_ws_bytes(width, height, n_views);
+  return KGS_OK;
+}
+
+kgs_status kgs_init_spawn(const float* color, const float* depth, const float* rendered, const float* rendered_depth,
+                          const float* uniforms, const kgs_camera* cams, int32_t n_views, int32_t width,
+                          int32_t height, void* workspace, size_t workspace_bytes, float* p_kf,
+                          const kgs_spawn_list* out, void* stream) {
+  if (!color || !depth || !uniforms || !cams || !workspace || !out) return KGS_ERR_INVALID_ARG;
+  if (!out->pixel || !out->level || !out->voxel || !out->point || !out->count || out->capacity < 0)
+    return KGS_ERR_INVALID_ARG;
+  if ((rendered == nullptr) != (rendered_depth == nullptr)) return KGS_ERR_INVALID_ARG;
+  size_t need = 0;
+  if (kgs_init_workspace_size(width, height, n_views, &need) != KGS_OK || workspace_bytes < need)
+    return KGS_ERR_INVALID_ARG;
+  if (((uintptr_t)workspace & 255) != 0) return KGS_ERR_INVALID_ARG;
+  return kgs_launch_init_spawn(color, depth, rendered, rendered_depth, uniforms, cams, n_views, width, height,
+                               (char*)workspace, p_kf, out, (hipStream_t)stream);
 }
 
 kgs_status kgs_render_bwd(kgs_ctx* ctx, const kgs_gaussians* g, const kgs_camera* cams, int32_t n_views,

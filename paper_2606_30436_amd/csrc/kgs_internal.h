@@ -109,6 +109,8 @@ struct kgs_ctx {
   unsigned long long* scan_totals;    // [2] their totals
   double* pose_partial;               // [max_views][KGS_POSE_BLOCKS][6]
   double* loss_partial;               // [max_views * max_tiles] L1 loss per (view, tile)
+  float* ssim_aux;                    // [max_views][3][3][H][W] SSIM derivative maps of the mapping loss
+  double* ssim_partial;               // [max_views][3][mapping-loss tiles][3] per-tile loss sums
   double* mm_partial;                 // [nb][2]
   uint32_t* keep_partial;             // [nb + 1]
   // state
@@ -466,6 +468,17 @@ kgs_status kgs_check_launch();
 
 // Launch helpers of the lifecycle statistics and the learned head.
 const double* kgs_launch_chunk_minmax(kgs_ctx* ctx, const kgs_view_stats* s, int64_t n, hipStream_t st);
+int kgs_maploss_tiles(int W, int H);
+size_t kgs_init_ws_bytes(int W, int H, int V);
+kgs_status kgs_launch_init_spawn(const float* color, const float* depth, const float* rcolor, const float* rdepth,
+                                 const float* u, const kgs_camera* cams, int V, int W, int H, char* ws,
+                                 float* pkf_out, const kgs_spawn_list* out, hipStream_t st);
+kgs_status kgs_launch_loss_mapping(kgs_ctx* ctx, int V, const float* target, const float* target_depth,
+                                   const kgs_image* img, float w_l1, float w_ssim, float lambda_g,
+                                   float* dl_dcolor, float* dl_ddepth, float* view_loss, float* geo_loss,
+                                   hipStream_t st);
+kgs_status kgs_launch_loss_iso(kgs_ctx* ctx, const kgs_gaussians* g, float lambda, float* grad, float* loss,
+                               hipStream_t st);
 size_t kgs_head_ws_bytes();
 kgs_status kgs_launch_head_forward(const float* theta, const uint16_t* feat, int64_t n, float* logits,
                                    uint8_t* decision, hipStream_t st);

@@ -199,6 +199,14 @@ class Rasterizer:
     def loss_l1(self, target, img: Image, dl_dcolor, view_loss, stream=None):
         L.kgs_loss_l1(self.ctx, target, img.c(), dl_dcolor, view_loss, stream)
 
+    def loss_mapping(self, n_views, img: Image, target, dl_dcolor, view_loss, target_depth=None, dl_ddepth=None,
+                     geo_loss=None, w_l1=0.8, w_ssim=0.2, lambda_g=0.01, stream=None):
+        L.kgs_loss_mapping(self.ctx, n_views, img.c(), target, target_depth, w_l1, w_ssim, lambda_g, dl_dcolor,
+                           dl_ddepth, view_loss, geo_loss, stream)
+
+    def loss_iso(self, g: GaussianParams, loss, grad_log_scales=None, lambda_iso=10.0, stream=None):
+        L.kgs_loss_iso(self.ctx, g.c(), lambda_iso, grad_log_scales, loss, stream)
+
     def render_bwd(self, g: GaussianParams, cams, pose_xi, img: Image, dl_dcolor, dl_ddepth=None, target=None,
                    tau_err=0.1, view_loss=None, grads: Optional[GaussianParams] = None, pose_grad=None,
                    stats: Optional[ViewStats] = None, stream=None, dl_dalpha=None):
