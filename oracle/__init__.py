@@ -15,6 +15,9 @@ Modules
   init_prob.py   probabilistic initialisation (DoG, depth gradient, residual
                  against the render, 3x3 suppression, unprojection, level and
                  voxel quantisation) in NumPy FP64
+  map_maint.py   map maintenance: voxel keys and the spatial-hash insertion of
+                 new anchors, their attributes, densify points, prune
+                 compaction, rigid alignment and re-voxelisation
 
 Every function cites the passage of the paper it follows; readings of passages
 the paper leaves open are the constants of OracleConfig.
