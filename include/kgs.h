@@ -329,6 +329,90 @@ kgs_status kgs_init_spawn(const float* color, const float* depth, const float* r
                           int32_t height, void* workspace, size_t workspace_bytes, float* p_kf,
                           const kgs_spawn_list* out, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Map maintenance (appendix "Dynamic Map Expansion" and "Global Map
+ * Alignment"; Sec. 3.3 densify / prune decisions acting on the map).  With
+ * explicit Gaussians an anchor is one Gaussian.
+ *   * A voxel is (level l, idx = floor(x / eps_l)); its 64-bit key packs l in
+ *     bits 60..62 and idx + 2^19 in three 20-bit fields (indices outside
+ *     [-2^19, 2^19) give the key ~0, which is skipped).
+ *   * The spatial hash is a caller-allocated table of 2^log2_capacity slots
+ *     (kgs_map_table_bytes), cleared once with kgs_map_table_clear; it maps each
+ *     occupied voxel to its anchor.
+ *   * A batch insertion creates one anchor per new voxel, numbered n_anchors_in,
+ *     n_anchors_in + 1, ... in the order of each new voxel's first candidate;
+ *     a voxel already present keeps its anchor.  Deterministic.
+ *   * New Gaussians (readings): mean idx eps_l, log-scales ln(eps_l), identity
+ *     rotation, opacity 0.1, SH degree-0 colour of the spawning pixel, higher
+ *     bands zero.
+ *   * Densify points (reading): mu +- s_max a_max of every Gaussian whose
+ *     decision is DENSIFY (its largest scale along its axis), + before -, in
+ *     Gaussian order; their level from the distance to a camera centre.
+ *   * Poses are world->camera (R, t); alignment moves the Gaussians of keyframe m
+ *     by p' = R_new^T (R_old p + t_old - t_new) and turns them by R_new^T R_old.
+ *   * Re-voxelisation keeps, of the anchors sharing a voxel at their level, the
+ *     one with the lowest index.
+ * Status bits (device word, OR-ed): 1 the hash table is full, 2 the parameter
+ * arrays are full.  Every integer decision is taken in FP64.
+ * ------------------------------------------------------------------------ */
+
+/* Writable structure-of-arrays Gaussians of capacity n (the stride of every plane). */
+typedef struct kgs_gaussians_out {
+  float* means;
+  float* log_scales;
+  float* quats;
+  float* opacity_logits;
+  float* sh;
+  int64_t n;
+  int32_t sh_degree;
+  int32_t pad_;
+} kgs_gaussians_out;
+
+/* Bytes of a table of 2^log2_capacity slots, log2_capacity in 4..31 (host only). */
+kgs_status kgs_map_table_bytes(int32_t log2_capacity, size_t* bytes);
+/* Mark every slot empty. */
+kgs_status kgs_map_table_clear(void* table, int32_t log2_capacity, void* stream);
+/* Bytes of device workspace the insertion, densify-point and re-voxelisation
+ * calls need for up to max_items keys or Gaussians (host only). */
+kgs_status kgs_map_workspace_size(int64_t max_items, size_t* bytes);
+/* keys[i] of (level[i], voxel[i][3]). */
+kgs_status kgs_map_voxel_keys(const int32_t* level, const int32_t* voxel, int64_t n, uint64_t* keys, void* stream);
+/* Insert keys[n].  anchor[i] (or NULL): the anchor of key i (~0 for a skipped
+ * key or a full table); created[k] (or NULL): the key index that created
+ * anchor n_anchors_in + k; n_anchors_in / n_anchors_out: device scalars (must
+ * not alias); status: device word. */
+kgs_status kgs_map_insert(void* table, int32_t log2_capacity, const uint64_t* keys, int64_t n,
+                          const uint32_t* n_anchors_in, uint32_t* anchor, uint32_t* created, uint32_t* n_anchors_out,
+                          uint32_t* status, void* workspace, size_t workspace_bytes, void* stream);
+/* Parameters of the anchors n_anchors_in .. n_anchors_out - 1 created by an
+ * insertion, from the level, voxel and colour [3] of their creating key; written
+ * at their anchor index in out (status bit 2 past out->n). */
+kgs_status kgs_map_spawn(const uint32_t* created, const uint32_t* n_anchors_in, const uint32_t* n_anchors_out,
+                         const int32_t* level, const int32_t* voxel, const float* color, int64_t n_candidates,
+                         const kgs_gaussians_out* out, uint32_t* status, void* stream);
+/* Densify points of the DENSIFY decisions: level [cap], voxel [cap][3],
+ * point [cap][3], source [cap] (the Gaussian); count: device scalar, the full
+ * number (2 per Gaussian), of which the first capacity are written.
+ * centre: host [3] camera centre for the levels. */
+kgs_status kgs_map_densify_points(const kgs_gaussians* g, const uint8_t* decision, const double centre[3],
+                                  int64_t capacity, int32_t* level, int32_t* voxel, float* point, uint32_t* source,
+                                  uint32_t* count, void* workspace, size_t workspace_bytes, void* stream);
+/* Survivors of the decision (not PRUNE) gathered to out at keep_map[i] (the
+ * exclusive prefix count kgs_densify_prune_decide writes). */
+kgs_status kgs_map_compact(const kgs_gaussians* g, const uint8_t* decision, const uint32_t* keep_map,
+                           const kgs_gaussians_out* out, void* stream);
+/* In place: Gaussian i of keyframe m = keyframe_of[i] (-1: none) moves with
+ * T_new^(m) (T_old^(m))^-1; old_poses / new_poses: device [n_keyframes]
+ * cameras (only R and t are used). */
+kgs_status kgs_map_align(float* means, float* quats, int64_t n, const int32_t* keyframe_of, const kgs_camera* old_poses,
+                         const kgs_camera* new_poses, int32_t n_keyframes, void* stream);
+/* Re-voxelise n anchors (means [3][n], level [n]) into a freshly cleared table:
+ * keep[i] = 1 for the lowest index of each voxel, anchor[i] = the survivor's
+ * new index (rank among the survivors), n_keep (device) their number. */
+kgs_status kgs_map_revoxelize(const float* means, const int32_t* level, int64_t n, void* table, int32_t log2_capacity,
+                              uint8_t* keep, uint32_t* anchor, uint32_t* n_keep, uint32_t* status, void* workspace,
+                              size_t workspace_bytes, void* stream);
+
 /* Backward of render_fwd and project for the last projected views, plus the
  * per-view footprint statistics (appendix, densification and pruning
  * scores: Omega_v(i), M_v, kappa_v(i), gamma_v(i) = L_v |Omega_v(i)|).

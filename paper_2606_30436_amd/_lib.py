@@ -62,6 +62,11 @@ class KgsSpawnList(ctypes.Structure):
                 ("color", c_void_p), ("count", c_void_p), ("capacity", c_int64)]
 
 
+class KgsGaussiansOut(ctypes.Structure):
+    _fields_ = [("means", c_void_p), ("log_scales", c_void_p), ("quats", c_void_p), ("opacity_logits", c_void_p),
+                ("sh", c_void_p), ("n", c_int64), ("sh_degree", c_int32), ("pad_", c_int32)]
+
+
 class KgsBuffers(ctypes.Structure):
     _fields_ = [("n_slots", c_void_p), ("n_pairs", c_void_p), ("slot_rec", c_void_p), ("slot_gid", c_void_p),
                 ("slot_view", c_void_p), ("slot_pix", c_void_p), ("slot_pairoff", c_void_p), ("keys", c_void_p),
@@ -91,6 +96,20 @@ _SIGS = {
                                    c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "kgs_loss_iso": (c_int32, [c_void_p, P(KgsGaussians), c_float, c_void_p, c_void_p, c_void_p]),
     "kgs_init_workspace_size": (c_int32, [c_int32, c_int32, c_int32, P(ctypes.c_size_t)]),
+    "kgs_map_table_bytes": (c_int32, [c_int32, P(ctypes.c_size_t)]),
+    "kgs_map_table_clear": (c_int32, [c_void_p, c_int32, c_void_p]),
+    "kgs_map_workspace_size": (c_int32, [c_int64, P(ctypes.c_size_t)]),
+    "kgs_map_voxel_keys": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p, c_void_p]),
+    "kgs_map_insert": (c_int32, [c_void_p, c_int32, c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p,
+                                 c_void_p, c_void_p, ctypes.c_size_t, c_void_p]),
+    "kgs_map_spawn": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int64,
+                                P(KgsGaussiansOut), c_void_p, c_void_p]),
+    "kgs_map_densify_points": (c_int32, [P(KgsGaussians), c_void_p, P(c_double), c_int64, c_void_p, c_void_p,
+                                         c_void_p, c_void_p, c_void_p, c_void_p, ctypes.c_size_t, c_void_p]),
+    "kgs_map_compact": (c_int32, [P(KgsGaussians), c_void_p, c_void_p, P(KgsGaussiansOut), c_void_p]),
+    "kgs_map_align": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_int32, c_void_p]),
+    "kgs_map_revoxelize": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p, c_int32, c_void_p, c_void_p, c_void_p,
+                                     c_void_p, c_void_p, ctypes.c_size_t, c_void_p]),
     "kgs_init_spawn": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_int32,
                                  c_int32, c_void_p, ctypes.c_size_t, c_void_p, P(KgsSpawnList), c_void_p]),
     "kgs_render_bwd": (c_int32, [c_void_p, P(KgsGaussians), c_void_p, c_int32, c_void_p, P(KgsImage), c_void_p,
@@ -247,6 +266,64 @@ def kgs_init_spawn(color, depth, rendered, rendered_depth, uniforms, cams, n_vie
     check(load().kgs_init_spawn(ptr(color), ptr(depth), ptr(rendered), ptr(rendered_depth), ptr(uniforms), ptr(cams),
                                 int(n_views), int(width), int(height), ptr(workspace), int(workspace_bytes), ptr(p_kf),
                                 ctypes.byref(out), stream_handle(stream)), "kgs_init_spawn")
+
+
+def kgs_map_table_bytes(log2_capacity) -> int:
+    n = ctypes.c_size_t()
+    check(load().kgs_map_table_bytes(int(log2_capacity), ctypes.byref(n)), "kgs_map_table_bytes")
+    return int(n.value)
+
+
+def kgs_map_table_clear(table, log2_capacity, stream=None):
+    check(load().kgs_map_table_clear(ptr(table), int(log2_capacity), stream_handle(stream)), "kgs_map_table_clear")
+
+
+def kgs_map_workspace_size(max_items) -> int:
+    n = ctypes.c_size_t()
+    check(load().kgs_map_workspace_size(int(max_items), ctypes.byref(n)), "kgs_map_workspace_size")
+    return int(n.value)
+
+
+def kgs_map_voxel_keys(level, voxel, n, keys, stream=None):
+    check(load().kgs_map_voxel_keys(ptr(level), ptr(voxel), int(n), ptr(keys), stream_handle(stream)),
+          "kgs_map_voxel_keys")
+
+
+def kgs_map_insert(table, log2_capacity, keys, n, n_in, anchor, created, n_out, status, workspace, ws_bytes,
+                   stream=None):
+    check(load().kgs_map_insert(ptr(table), int(log2_capacity), ptr(keys), int(n), ptr(n_in), ptr(anchor), ptr(created),
+                                ptr(n_out), ptr(status), ptr(workspace), int(ws_bytes), stream_handle(stream)),
+          "kgs_map_insert")
+
+
+def kgs_map_spawn(created, n_in, n_out, level, voxel, color, n_candidates, out: KgsGaussiansOut, status, stream=None):
+    check(load().kgs_map_spawn(ptr(created), ptr(n_in), ptr(n_out), ptr(level), ptr(voxel), ptr(color),
+                               int(n_candidates), ctypes.byref(out), ptr(status), stream_handle(stream)), "kgs_map_spawn")
+
+
+def kgs_map_densify_points(g: KgsGaussians, decision, centre, capacity, level, voxel, point, source, count, workspace,
+                           ws_bytes, stream=None):
+    c = (c_double * 3)(*[float(x) for x in centre])
+    check(load().kgs_map_densify_points(ctypes.byref(g), ptr(decision), c, int(capacity), ptr(level), ptr(voxel),
+                                        ptr(point), ptr(source), ptr(count), ptr(workspace), int(ws_bytes),
+                                        stream_handle(stream)), "kgs_map_densify_points")
+
+
+def kgs_map_compact(g: KgsGaussians, decision, keep_map, out: KgsGaussiansOut, stream=None):
+    check(load().kgs_map_compact(ctypes.byref(g), ptr(decision), ptr(keep_map), ctypes.byref(out),
+                                 stream_handle(stream)), "kgs_map_compact")
+
+
+def kgs_map_align(means, quats, n, keyframe_of, old_poses, new_poses, n_keyframes, stream=None):
+    check(load().kgs_map_align(ptr(means), ptr(quats), int(n), ptr(keyframe_of), ptr(old_poses), ptr(new_poses),
+                               int(n_keyframes), stream_handle(stream)), "kgs_map_align")
+
+
+def kgs_map_revoxelize(means, level, n, table, log2_capacity, keep, anchor, n_keep, status, workspace, ws_bytes,
+                       stream=None):
+    check(load().kgs_map_revoxelize(ptr(means), ptr(level), int(n), ptr(table), int(log2_capacity), ptr(keep),
+                                    ptr(anchor), ptr(n_keep), ptr(status), ptr(workspace), int(ws_bytes),
+                                    stream_handle(stream)), "kgs_map_revoxelize")
 
 
 def kgs_render_bwd(ctx, g: KgsGaussians, cams, n_views, pose_xi, img: KgsImage, dl_dcolor, dl_ddepth, dl_dalpha,

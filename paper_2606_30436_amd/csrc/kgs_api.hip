@@ -302,6 +302,98 @@ kgs_status kgs_init_spawn(const float* color, const float* depth, const float* r
                                (char*)workspace, p_kf, out, (hipStream_t)stream);
 }
 
+// ---------------------------------------------------------------- map maintenance
+namespace {
+bool log2_cap_ok(int32_t l) { return l >= 4 && l <= 31; }
+bool map_ws_ok(const void* ws, size_t bytes, int64_t n) {
+  return ws && ((uintptr_t)ws & 255) == 0 && n >= 0 && bytes >= kgs_map_ws_bytes(n);
+}
+bool gout_ok(const kgs_gaussians_out* o) {
+  return o && o->means && o->log_scales && o->quats && o->opacity_logits && o->sh && o->n >= 0 && o->sh_degree >= 0 &&
+         o->sh_degree <= 3;
+}
+}  // namespace
+
+kgs_status kgs_map_table_bytes(int32_t log2_capacity, size_t* bytes) {
+  if (!bytes || !log2_cap_ok(log2_capacity)) return KGS_ERR_INVALID_ARG;
+  *bytes = kgs_map_slot_bytes() << log2_capacity;
+  return KGS_OK;
+}
+
+kgs_status kgs_map_table_clear(void* table, int32_t log2_capacity, void* stream) {
+  if (!table || !log2_cap_ok(log2_capacity)) return KGS_ERR_INVALID_ARG;
+  kgs_launch_map_clear(table, 1ull << log2_capacity, (hipStream_t)stream);
+  return kgs_check_launch();
+}
+
+kgs_status kgs_map_workspace_size(int64_t max_items, size_t* bytes) {
+  if (!bytes || max_items < 0 || max_items >= (int64_t(1) << 32)) return KGS_ERR_INVALID_ARG;
+  *bytes = kgs_map_ws_bytes(max_items);
+  return KGS_OK;
+}
+
+kgs_status kgs_map_voxel_keys(const int32_t* level, const int32_t* voxel, int64_t n, uint64_t* keys, void* stream) {
+  if (n < 0 || (n > 0 && (!level || !voxel || !keys))) return KGS_ERR_INVALID_ARG;
+  return kgs_launch_map_voxel_keys(level, voxel, n, (unsigned long long*)keys, (hipStream_t)stream);
+}
+
+kgs_status kgs_map_insert(void* table, int32_t log2_capacity, const uint64_t* keys, int64_t n,
+                          const uint32_t* n_anchors_in, uint32_t* anchor, uint32_t* created, uint32_t* n_anchors_out,
+                          uint32_t* status, void* workspace, size_t workspace_bytes, void* stream) {
+  if (!table || !log2_cap_ok(log2_capacity) || !n_anchors_in || !n_anchors_out || !status) return KGS_ERR_INVALID_ARG;
+  if (n < 0 || n >= (int64_t(1) << 32) || (n > 0 && !keys) || n_anchors_in == n_anchors_out) return KGS_ERR_INVALID_ARG;
+  if (!map_ws_ok(workspace, workspace_bytes, n)) return KGS_ERR_INVALID_ARG;
+  return kgs_launch_map_insert(table, 1ull << log2_capacity, (const unsigned long long*)keys, n, n_anchors_in, anchor,
+                               created, n_anchors_out, status, (char*)workspace, (hipStream_t)stream);
+}
+
+kgs_status kgs_map_spawn(const uint32_t* created, const uint32_t* n_anchors_in, const uint32_t* n_anchors_out,
+                         const int32_t* level, const int32_t* voxel, const float* color, int64_t n_candidates,
+                         const kgs_gaussians_out* out, uint32_t* status, void* stream) {
+  if (!created || !n_anchors_in || !n_anchors_out || !level || !voxel || !color || !gout_ok(out) || !status ||
+      n_candidates < 0)
+    return KGS_ERR_INVALID_ARG;
+  return kgs_launch_map_spawn(created, n_anchors_in, n_anchors_out, level, voxel, color, n_candidates, out, status,
+                              (hipStream_t)stream);
+}
+
+kgs_status kgs_map_densify_points(const kgs_gaussians* g, const uint8_t* decision, const double centre[3],
+                                  int64_t capacity, int32_t* level, int32_t* voxel, float* point, uint32_t* source,
+                                  uint32_t* count, void* workspace, size_t workspace_bytes, void* stream) {
+  if (!g || !g->means || !g->log_scales || !g->quats || !decision || !centre || !level || !voxel || !point ||
+      !source || !count || capacity < 0)
+    return KGS_ERR_INVALID_ARG;
+  if (!map_ws_ok(workspace, workspace_bytes, g->n)) return KGS_ERR_INVALID_ARG;
+  return kgs_launch_map_densify(g, decision, centre, capacity, level, voxel, point, source, count, (char*)workspace,
+                                (hipStream_t)stream);
+}
+
+kgs_status kgs_map_compact(const kgs_gaussians* g, const uint8_t* decision, const uint32_t* keep_map,
+                           const kgs_gaussians_out* out, void* stream) {
+  if (!g || !g->means || !g->log_scales || !g->quats || !g->opacity_logits || !g->sh || g->n < 0 || !decision ||
+      !keep_map || !gout_ok(out) || out->sh_degree != g->sh_degree)
+    return KGS_ERR_INVALID_ARG;
+  return kgs_launch_map_compact(g, decision, keep_map, out, (hipStream_t)stream);
+}
+
+kgs_status kgs_map_align(float* means, float* quats, int64_t n, const int32_t* keyframe_of, const kgs_camera* old_poses,
+                         const kgs_camera* new_poses, int32_t n_keyframes, void* stream) {
+  if (n < 0 || n_keyframes < 1 || (n > 0 && (!means || !quats || !keyframe_of || !old_poses || !new_poses)))
+    return KGS_ERR_INVALID_ARG;
+  return kgs_launch_map_align(means, quats, n, keyframe_of, old_poses, new_poses, n_keyframes, (hipStream_t)stream);
+}
+
+kgs_status kgs_map_revoxelize(const float* means, const int32_t* level, int64_t n, void* table, int32_t log2_capacity,
+                              uint8_t* keep, uint32_t* anchor, uint32_t* n_keep, uint32_t* status, void* workspace,
+                              size_t workspace_bytes, void* stream) {
+  if (!table || !log2_cap_ok(log2_capacity) || !n_keep || !status || n < 0 || n >= (int64_t(1) << 32))
+    return KGS_ERR_INVALID_ARG;
+  if (n > 0 && (!means || !level || !keep || !anchor)) return KGS_ERR_INVALID_ARG;
+  if (!map_ws_ok(workspace, workspace_bytes, n)) return KGS_ERR_INVALID_ARG;
+  return kgs_launch_map_revoxelize(means, level, n, table, 1ull << log2_capacity, keep, anchor, n_keep, status,
+                                   (char*)workspace, (hipStream_t)stream);
+}
+
 kgs_status kgs_render_bwd(kgs_ctx* ctx, const kgs_gaussians* g, const kgs_camera* cams, int32_t n_views,
                           const float* pose_xi, const kgs_image* fwd, const float* dl_dcolor, const float* dl_ddepth,
                           const float* dl_dalpha, const float* target, float tau_err, const float* view_loss,

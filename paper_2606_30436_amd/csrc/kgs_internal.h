@@ -470,6 +470,27 @@ kgs_status kgs_check_launch();
 const double* kgs_launch_chunk_minmax(kgs_ctx* ctx, const kgs_view_stats* s, int64_t n, hipStream_t st);
 int kgs_maploss_tiles(int W, int H);
 size_t kgs_init_ws_bytes(int W, int H, int V);
+size_t kgs_map_ws_bytes(int64_t n);
+size_t kgs_map_slot_bytes();
+void kgs_launch_map_clear(void* table, uint64_t cap, hipStream_t st);
+kgs_status kgs_launch_map_insert(void* table, uint64_t cap, const unsigned long long* keys, int64_t n,
+                                 const uint32_t* n_in, uint32_t* anchor, uint32_t* created, uint32_t* n_out,
+                                 uint32_t* status, char* ws, hipStream_t st);
+kgs_status kgs_launch_map_voxel_keys(const int32_t* level, const int32_t* vox, int64_t n, unsigned long long* keys,
+                                     hipStream_t st);
+kgs_status kgs_launch_map_spawn(const uint32_t* created, const uint32_t* n_in, const uint32_t* n_out,
+                                const int32_t* level, const int32_t* vox, const float* color, int64_t n_cand,
+                                const kgs_gaussians_out* g, uint32_t* status, hipStream_t st);
+kgs_status kgs_launch_map_densify(const kgs_gaussians* g, const uint8_t* decision, const double centre[3],
+                                  int64_t cap, int32_t* level, int32_t* vox, float* point, uint32_t* source,
+                                  uint32_t* count, char* ws, hipStream_t st);
+kgs_status kgs_launch_map_compact(const kgs_gaussians* g, const uint8_t* decision, const uint32_t* keep_map,
+                                  const kgs_gaussians_out* out, hipStream_t st);
+kgs_status kgs_launch_map_align(float* means, float* quats, int64_t n, const int32_t* keyframe_of,
+                                const kgs_camera* old_pose, const kgs_camera* new_pose, int n_kf, hipStream_t st);
+kgs_status kgs_launch_map_revoxelize(const float* means, const int32_t* level, int64_t n, void* table, uint64_t cap,
+                                     uint8_t* keep, uint32_t* anchor, uint32_t* n_keep, uint32_t* status, char* ws,
+                                     hipStream_t st);
 kgs_status kgs_launch_init_spawn(const float* color, const float* depth, const float* rcolor, const float* rdepth,
                                  const float* u, const kgs_camera* cams, int V, int W, int H, char* ws,
                                  float* pkf_out, const kgs_spawn_list* out, hipStream_t st);

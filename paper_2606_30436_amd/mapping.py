@@ -50,3 +50,50 @@ class Initializer:
         assert 1 <= V <= self.V and tuple(color.shape[1:]) == (3, self.H, self.W)
         L.kgs_init_spawn(color, depth, rendered, rendered_depth, uniforms, cams, V, self.W, self.H, self.workspace,
                          self.ws_bytes, p_kf, out.c(capacity), stream)
+
+
+def gaussians_out(means, log_scales, quats, logits, sh, sh_degree: int) -> L.KgsGaussiansOut:
+    """Writable structure-of-arrays Gaussians (capacity = the planes' length)."""
+    o = L.KgsGaussiansOut()
+    o.means, o.log_scales, o.quats = means.data_ptr(), log_scales.data_ptr(), quats.data_ptr()
+    o.opacity_logits, o.sh = logits.data_ptr(), sh.data_ptr()
+    o.n, o.sh_degree = int(means.shape[-1]), int(sh_degree)
+    return o
+
+
+class VoxelMap:
+    """The spatial hash of occupied voxels and the workspace of the map calls."""
+
+    def __init__(self, log2_capacity: int, max_items: int, device="cuda"):
+        self.log2 = int(log2_capacity)
+        self.table = torch.empty(L.kgs_map_table_bytes(self.log2), dtype=torch.uint8, device=device)
+        self.ws_bytes = L.kgs_map_workspace_size(max_items)
+        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
+        self.status = torch.zeros(1, dtype=torch.int32, device=device)
+        self.max_items = int(max_items)
+        self.clear()
+
+    def clear(self, stream=None):
+        L.kgs_map_table_clear(self.table, self.log2, stream)
+
+    def keys(self, level, voxel, stream=None):
+        out = torch.empty(int(level.shape[0]), dtype=torch.int64, device=level.device)
+        L.kgs_map_voxel_keys(level, voxel, int(level.shape[0]), out, stream)
+        return out
+
+    def insert(self, keys, n_in, n_out, anchor=None, created=None, stream=None):
+        n = int(keys.shape[0])
+        assert n <= self.max_items
+        L.kgs_map_insert(self.table, self.log2, keys, n, n_in, anchor, created, n_out, self.status, self.workspace,
+                         self.ws_bytes, stream)
+
+    def densify_points(self, g, decision, centre, capacity, level, voxel, point, source, count, stream=None):
+        assert g.n <= self.max_items
+        L.kgs_map_densify_points(g.c(), decision, centre, capacity, level, voxel, point, source, count,
+                                 self.workspace, self.ws_bytes, stream)
+
+    def revoxelize(self, means, level, keep, anchor, n_keep, stream=None):
+        n = int(means.shape[-1])
+        assert n <= self.max_items
+        L.kgs_map_revoxelize(means, level, n, self.table, self.log2, keep, anchor, n_keep, self.status, self.workspace,
+                             self.ws_bytes, stream)
