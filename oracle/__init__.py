@@ -18,6 +18,10 @@ Modules
   map_maint.py   map maintenance: voxel keys and the spatial-hash insertion of
                  new anchors, their attributes, densify points, prune
                  compaction, rigid alignment and re-voxelisation
+  anchors.py     anchor decoding (the decoder network with BF16 rounding
+                 points, position and scale composition, the level-of-detail
+                 opacity mask); the per-anchor union footprint statistics are
+                 View.anchor_stats in the C oracle
 
 Every function cites the passage of the paper it follows; readings of passages
 the paper leaves open are the constants of OracleConfig.
@@ -90,6 +94,8 @@ def lib():
             L.orc_view_proj.argtypes = [ctypes.c_void_p, _d, _i64, _d]
             L.orc_view_pairs.argtypes = [ctypes.c_void_p, _i32, _i64]
             L.orc_view_stats.argtypes = [ctypes.c_void_p, _f, ctypes.c_double, _i32, _i32, _u8, _d]
+            L.orc_view_anchor_stats.argtypes = [ctypes.c_void_p, _i64, ctypes.c_int64, _f, ctypes.c_double, _i64,
+                                                _i64]
             L.orc_view_backward.argtypes = [ctypes.c_void_p, _d, _d, _d, _d, _d, _d, _d, _d, _d]
             L.orc_se3_exp.argtypes = [_d, _d]
             L.orc_se3_exp_deriv.argtypes = [_d, ctypes.c_int, _d]
@@ -240,6 +246,18 @@ class View:
         lib().orc_view_stats(self._h, _ptr(t, _f), float(tau_err), _ptr(omega, _i32), _ptr(kappa, _i32),
                              _ptr(mask, _u8), _ptr(mm, _d))
         return dict(omega=omega, kappa=kappa, mask=mask.astype(bool), mask_margin=mm)
+
+    def anchor_stats(self, anchor_of, n_anchor: int, target: np.ndarray, tau_err: float = 0.1) -> dict:
+        """Per-anchor |Omega_v(a)| and kappa_v(a): the union of the blended pixels of
+        the Gaussians g with anchor_of[g] == a (appendix, densification and
+        pruning scores of an anchor)."""
+        a = np.ascontiguousarray(anchor_of, np.int64)
+        t = np.ascontiguousarray(target, np.float32)
+        om = np.zeros(int(n_anchor), np.int64)
+        ka = np.zeros(int(n_anchor), np.int64)
+        lib().orc_view_anchor_stats(self._h, _ptr(a, _i64), int(n_anchor), _ptr(t, _f), float(tau_err),
+                                    _ptr(om, _i64), _ptr(ka, _i64))
+        return dict(omega=om, kappa=ka)
 
     def backward(self, dLdC: np.ndarray, dLdD=None) -> dict:
         """Gradients of L with dL/dC (3,H,W) and dL/dD (H,W) given; exact

@@ -696,6 +696,66 @@ void orc_view_stats(const orc_view* v, const float* target, double tau_err, int3
     }
 }
 
+static int cmp_i64(const void* a, const void* b) {
+  const int64_t x = *(const int64_t*)a, y = *(const int64_t*)b;
+  return (x > y) - (x < y);
+}
+
+/* Per-anchor footprint statistics (appendix, "Densification Score" and
+ * "Pruning Score": Omega_v(i) is the set of pixels where the decoded Gaussians
+ * of anchor i contribute): Gaussian g belongs to anchor anchor_of[g]; an
+ * anchor's footprint is the union of its Gaussians' blended pixels, so a pixel
+ * counts once for an anchor however many of its Gaussians blend there.
+ * omega_a [n_anchor] += |Omega_v(a)|, kappa_a [n_anchor] += the pixels of that
+ * union with ||I - I^||_1 > tau_err. */
+void orc_view_anchor_stats(const orc_view* v, const int64_t* anchor_of, int64_t n_anchor, const float* target,
+                           double tau_err, int64_t* omega_a, int64_t* kappa_a) {
+  const int64_t npix = (int64_t)v->W * v->H;
+  int64_t longest = 1;
+  for (int64_t t = 0; t < (int64_t)v->TX * v->TY; ++t)
+    if (v->tile_off[t + 1] - v->tile_off[t] > longest) longest = v->tile_off[t + 1] - v->tile_off[t];
+#pragma omp parallel
+  {
+    int64_t* seen = (int64_t*)malloc(sizeof(int64_t) * (size_t)longest);
+#pragma omp for schedule(dynamic, 4)
+    for (int py = 0; py < v->H; ++py)
+      for (int px = 0; px < v->W; ++px) {
+        const int64_t pix = (int64_t)py * v->W + px;
+        double err = 0.0;
+        for (int ch = 0; ch < 3; ++ch) err += fabs((double)target[ch * npix + pix] - v->color[ch * npix + pix]);
+        const int M = err > tau_err;
+        const int tile = (py / v->TH) * v->TX + (px / v->TW);
+        double T = 1.0;
+        int64_t m = 0;
+        for (int64_t e = v->tile_off[tile]; e < v->tile_off[tile + 1]; ++e) {
+          const int64_t gi = v->tile_list[e];
+          const orc_proj* p = &v->P[gi];
+          double dx, dy, q, raw;
+          eval_pair(p, px + 0.5, py + 0.5, &dx, &dy, &q, &raw);
+          if (raw < v->cfg.alpha_min) continue;
+          double a = raw < v->cfg.alpha_max ? raw : v->cfg.alpha_max;
+          double Tn = T * (1.0 - a);
+          if (Tn < v->cfg.t_min) break;
+          seen[m++] = anchor_of[gi];
+          T = Tn;
+        }
+        qsort(seen, (size_t)m, sizeof(int64_t), cmp_i64);
+        for (int64_t k = 0; k < m; ++k) {
+          if (k > 0 && seen[k] == seen[k - 1]) continue;
+          const int64_t an = seen[k];
+          if (an < 0 || an >= n_anchor) continue;
+#pragma omp atomic update
+          omega_a[an] += 1;
+          if (M) {
+#pragma omp atomic update
+            kappa_a[an] += 1;
+          }
+        }
+      }
+    free(seen);
+  }
+}
+
 /* ------------------------------------------------------------- backward */
 typedef struct {
   double mu[2], conic[3], o, col[3], z;
