@@ -413,6 +413,58 @@ kgs_status kgs_map_revoxelize(const float* means, const int32_t* level, int64_t 
                               uint8_t* keep, uint32_t* anchor, uint32_t* n_keep, uint32_t* status, void* workspace,
                               size_t workspace_bytes, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Anchors (appendix "Voxelized Representation and MLP Decoding" and
+ * "Level-of-Detail (LoD) Mask Computation"; per-anchor scores of appendix
+ * "Densification Score" / "Pruning Score").
+ * An anchor i holds a position p_i, a feature f_i in R^32, a local scale
+ * l_i = exp(log_l_i) and K offsets O_ik; its level l_i selects the distance
+ * band [D_min, D_max) in which it is rendered (D_max = 100 eps_level,
+ * eps = (0.1, 0.25, 1, 5, 25), D_min the previous level's D_max).
+ * Decoding for a camera centre c: d = |p - c|, d^ = (p - c) / d; one network
+ *   36 inputs (f, d^, d) -> 32 ReLU -> 14 K outputs, child k taking outputs
+ *   14k..14k+13 as (alpha, colour[3], rotation[4], ds[3], dO[3]);
+ *   theta = W1 [32][36], b1 [32], W2 [14K][32], b2 [14K] (FP32, row major);
+ *   BF16 operands on the matrix cores, FP32 accumulation.
+ * Child k of anchor a is Gaussian a K + k, with
+ *   mean p + (O_k + dO_k) * l,  log-scale log l + log sigmoid(ds),
+ *   rotation as decoded, opacity tanh(alpha) * (1 inside the band, else 0)
+ *   (logit -100 when not positive), colour sigmoid(.) as a degree-0 SH
+ *   coefficient (c - 0.5) / Y_00.
+ * ------------------------------------------------------------------------ */
+typedef struct kgs_anchors {
+  const float* p;         /* [3][A] */
+  const float* feat;      /* [A][32], 16-byte aligned rows */
+  const float* log_l;     /* [3][A] */
+  const float* offsets;   /* [K][3][A] */
+  const int32_t* level;   /* [A], 0..4 */
+  int64_t n;              /* A */
+  int32_t k;              /* children per anchor, 1..16 */
+  int32_t pad_;
+} kgs_anchors;
+#define KGS_DECODER_PARAMS(K) (32 * 36 + 32 + 14 * (K) * 32 + 14 * (K))
+
+/* The Gaussians one view sees: out (sh_degree 0, capacity out->n >= A K)
+ * receives child a K + k of every anchor; camera: device pointer to the view's
+ * camera (its centre -R^T t).  Deterministic. */
+kgs_status kgs_anchor_decode(const kgs_anchors* a, const float* theta, const kgs_camera* camera,
+                             const kgs_gaussians_out* out, void* stream);
+
+/* Per-anchor footprint statistics of the last projected, binned and rendered
+ * views (fwd: their kgs_render_fwd outputs): for every anchor a, |Omega_v(a)|
+ * is the number of pixels where at least one Gaussian g with anchor_of[g] == a
+ * is blended, and kappa_v(a) those of them where the error mask is set
+ * (sum over channels of |target - colour| > tau_err).  Added to the chunk sums
+ * of stats (arrays of n_anchors): omega_sum += |Omega_v|, kappa_sum += kappa_v,
+ * gamma_sum += view_loss[v] |Omega_v| (if view_loss and gamma_sum).
+ * anchor_of [N] of the projected Gaussians; counts: device scratch of
+ * 2 V n_anchors u32 (per-view counts, zeroed by the call); status [2] u32:
+ * bit 4 of status[0] if a sub-block's anchors could not be split to fit (its
+ * counts are then incomplete), status[1] counts the re-walks. */
+kgs_status kgs_anchor_stats(kgs_ctx* ctx, const kgs_image* fwd, const uint32_t* anchor_of, int64_t n_anchors,
+                            const float* target, float tau_err, const float* view_loss, uint32_t* counts,
+                            const kgs_view_stats* stats, uint32_t* status, void* stream);
+
 /* Backward of render_fwd and project for the last projected views, plus the
  * per-view footprint statistics (appendix, densification and pruning
  * scores: Omega_v(i), M_v, kappa_v(i), gamma_v(i) = L_v |Omega_v(i)|).

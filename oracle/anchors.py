@@ -83,6 +83,9 @@ def decode(anchors: dict, theta, K: int, centre) -> dict:
     z1 = bf16(x) @ bf16(W1).T + b1                                # [A][32]
     h = np.maximum(z1, 0.0)
     y = bf16(h) @ bf16(W2).T + b2                                 # [A][14K]
+    # sums of the magnitudes of what each accumulation adds (bounds another arithmetic's rounding)
+    z1_abs = np.abs(bf16(x)) @ np.abs(bf16(W1)).T + np.abs(b1)
+    y_abs = np.abs(bf16(h)) @ np.abs(bf16(W2)).T + np.abs(b2)
     yk = y.reshape(A, K, OUTC)
     alpha = np.tanh(yk[..., 0])
     col = 1.0 / (1.0 + np.exp(-yk[..., 1:4]))
@@ -99,7 +102,7 @@ def decode(anchors: dict, theta, K: int, centre) -> dict:
     n = A * K
     out = dict(means=xk.reshape(n, 3).T.copy(), log_scales=log_s.reshape(n, 3).T.copy(),
                quats=q.reshape(n, 4).T.copy(), logits=logit.reshape(n), sh=((col.reshape(n, 3).T - 0.5) / Y00)[None],
-               raw=y, alpha_masked=at, distance=d)
+               raw=y, alpha_masked=at, distance=d, z1=z1, z1_abs=z1_abs, y_abs=y_abs)
     # BF16 rounding margins: distance of each rounded value from a rounding boundary, relative
     out["margin_hidden"] = _bf16_margin(h).min(axis=1)
     out["margin_input"] = _bf16_margin(x).min(axis=1)

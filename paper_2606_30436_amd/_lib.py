@@ -67,6 +67,15 @@ class KgsGaussiansOut(ctypes.Structure):
                 ("sh", c_void_p), ("n", c_int64), ("sh_degree", c_int32), ("pad_", c_int32)]
 
 
+class KgsAnchors(ctypes.Structure):
+    _fields_ = [("p", c_void_p), ("feat", c_void_p), ("log_l", c_void_p), ("offsets", c_void_p), ("level", c_void_p),
+                ("n", c_int64), ("k", c_int32), ("pad_", c_int32)]
+
+
+def decoder_params(K: int) -> int:
+    return 32 * 36 + 32 + 14 * K * 32 + 14 * K
+
+
 class KgsBuffers(ctypes.Structure):
     _fields_ = [("n_slots", c_void_p), ("n_pairs", c_void_p), ("slot_rec", c_void_p), ("slot_gid", c_void_p),
                 ("slot_view", c_void_p), ("slot_pix", c_void_p), ("slot_pairoff", c_void_p), ("keys", c_void_p),
@@ -96,6 +105,9 @@ _SIGS = {
                                    c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "kgs_loss_iso": (c_int32, [c_void_p, P(KgsGaussians), c_float, c_void_p, c_void_p, c_void_p]),
     "kgs_init_workspace_size": (c_int32, [c_int32, c_int32, c_int32, P(ctypes.c_size_t)]),
+    "kgs_anchor_decode": (c_int32, [P(KgsAnchors), c_void_p, c_void_p, P(KgsGaussiansOut), c_void_p]),
+    "kgs_anchor_stats": (c_int32, [c_void_p, P(KgsImage), c_void_p, c_int64, c_void_p, c_float, c_void_p, c_void_p,
+                                   P(KgsViewStats), c_void_p, c_void_p]),
     "kgs_map_table_bytes": (c_int32, [c_int32, P(ctypes.c_size_t)]),
     "kgs_map_table_clear": (c_int32, [c_void_p, c_int32, c_void_p]),
     "kgs_map_workspace_size": (c_int32, [c_int64, P(ctypes.c_size_t)]),
@@ -266,6 +278,18 @@ def kgs_init_spawn(color, depth, rendered, rendered_depth, uniforms, cams, n_vie
     check(load().kgs_init_spawn(ptr(color), ptr(depth), ptr(rendered), ptr(rendered_depth), ptr(uniforms), ptr(cams),
                                 int(n_views), int(width), int(height), ptr(workspace), int(workspace_bytes), ptr(p_kf),
                                 ctypes.byref(out), stream_handle(stream)), "kgs_init_spawn")
+
+
+def kgs_anchor_decode(a: KgsAnchors, theta, camera, out: KgsGaussiansOut, stream=None):
+    check(load().kgs_anchor_decode(ctypes.byref(a), ptr(theta), ptr(camera), ctypes.byref(out), stream_handle(stream)),
+          "kgs_anchor_decode")
+
+
+def kgs_anchor_stats(ctx, img: KgsImage, anchor_of, n_anchors, target, tau_err, view_loss, counts,
+                     stats: KgsViewStats, status, stream=None):
+    check(load().kgs_anchor_stats(ctypes.c_void_p(ctx), ctypes.byref(img), ptr(anchor_of), int(n_anchors), ptr(target),
+                                  float(tau_err), ptr(view_loss), ptr(counts), ctypes.byref(stats), ptr(status),
+                                  stream_handle(stream)), "kgs_anchor_stats")
 
 
 def kgs_map_table_bytes(log2_capacity) -> int:

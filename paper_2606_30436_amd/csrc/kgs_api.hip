@@ -394,6 +394,28 @@ kgs_status kgs_map_revoxelize(const float* means, const int32_t* level, int64_t 
                                    (char*)workspace, (hipStream_t)stream);
 }
 
+kgs_status kgs_anchor_decode(const kgs_anchors* a, const float* theta, const kgs_camera* camera,
+                             const kgs_gaussians_out* out, void* stream) {
+  if (!a || !theta || !camera || !out || a->n < 0 || a->k < 1 || a->k > 16) return KGS_ERR_INVALID_ARG;
+  if (a->n > 0 && (!a->p || !a->feat || !a->log_l || !a->offsets || !a->level)) return KGS_ERR_INVALID_ARG;
+  if (((uintptr_t)a->feat & 15) != 0) return KGS_ERR_INVALID_ARG;
+  if (!out->means || !out->log_scales || !out->quats || !out->opacity_logits || !out->sh || out->sh_degree != 0 ||
+      out->n < a->n * a->k)
+    return KGS_ERR_INVALID_ARG;
+  return kgs_launch_anchor_decode(a, theta, *camera, out, (hipStream_t)stream);
+}
+
+kgs_status kgs_anchor_stats(kgs_ctx* ctx, const kgs_image* fwd, const uint32_t* anchor_of, int64_t n_anchors,
+                            const float* target, float tau_err, const float* view_loss, uint32_t* counts,
+                            const kgs_view_stats* stats, uint32_t* status, void* stream) {
+  if (!ctx || !fwd || !fwd->color || !anchor_of || !target || !counts || !stats || !status || n_anchors < 0 ||
+      n_anchors >= (int64_t(1) << 32) - 1)
+    return KGS_ERR_INVALID_ARG;
+  if (!ctx->binned) return KGS_ERR_STATE;
+  return kgs_launch_anchor_stats(ctx, fwd, anchor_of, n_anchors, target, tau_err, view_loss, counts, stats, status,
+                                 (hipStream_t)stream);
+}
+
 kgs_status kgs_render_bwd(kgs_ctx* ctx, const kgs_gaussians* g, const kgs_camera* cams, int32_t n_views,
                           const float* pose_xi, const kgs_image* fwd, const float* dl_dcolor, const float* dl_ddepth,
                           const float* dl_dalpha, const float* target, float tau_err, const float* view_loss,

@@ -470,6 +470,11 @@ kgs_status kgs_check_launch();
 const double* kgs_launch_chunk_minmax(kgs_ctx* ctx, const kgs_view_stats* s, int64_t n, hipStream_t st);
 int kgs_maploss_tiles(int W, int H);
 size_t kgs_init_ws_bytes(int W, int H, int V);
+kgs_status kgs_launch_anchor_decode(const kgs_anchors* a, const float* theta, const kgs_camera& cam,
+                                    const kgs_gaussians_out* out, hipStream_t st);
+kgs_status kgs_launch_anchor_stats(kgs_ctx* ctx, const kgs_image* fwd, const uint32_t* anchor_of, int64_t n_anchor,
+                                   const float* target, float tau_err, const float* view_loss, uint32_t* counts,
+                                   const kgs_view_stats* stats, uint32_t* status, hipStream_t st);
 size_t kgs_map_ws_bytes(int64_t n);
 size_t kgs_map_slot_bytes();
 void kgs_launch_map_clear(void* table, uint64_t cap, hipStream_t st);
@@ -509,6 +514,61 @@ kgs_status kgs_launch_head_adam(float* theta, float* m, float* v, const float* g
                                 float b1, float b2, float eps, hipStream_t st);
 kgs_status kgs_launch_head_features(kgs_ctx* ctx, const kgs_gaussians* g, const kgs_view_stats* stats, int V,
                                     const kgs_lifecycle_state* before, uint16_t* feat, hipStream_t st);
+
+// ---------------------------------------------------------------- compositing (kgs_render.hip, kgs_anchor.hip)
+struct RenderParams {
+  int W, H, tile_w, tile_h, tiles_x, tiles_y, n_tiles;
+  float log2_amin, amax, tmin;
+  float bg0, bg1, bg2;
+};
+
+// Whether the footprint {log2 alpha >= log2 alpha_min} of a record can reach
+// the pixel-centre box [x0, x1] x [y0, y1] (record coordinates): the minimum
+// of q = A (x + k y)^2 + C y^2 over the box (A = -P', C = -E') against
+// tau = log2 o - log2 alpha_min.  q is convex, so the minimum is 0 with the
+// centre inside the box, else on an edge: y = y0 or y1 at x = clamp(-k y),
+// x = x0 or x1 at y = clamp(-A k x / (A k^2 + C)).  The margin keeps the test
+// conservative against the rounding of the per-pixel evaluation.
+__device__ __forceinline__ bool footprint_meets_box(float x0, float x1, float y0, float y1, const float4& r0,
+                                                    const float4& r1, float log2_amin) {
+  const float A = -r0.z, k = r0.w, C = -r1.x;
+  const float tau = r1.y - log2_amin;
+  if (x0 <= 0.f && x1 >= 0.f && y0 <= 0.f && y1 >= 0.f) return true;
+  const float s = A * k * __builtin_amdgcn_rcpf(fmaf(A * k, k, C));
+  float f;
+  {
+    const float xa = fminf(fmaxf(-k * y0, x0), x1), ua = fmaf(k, y0, xa);
+    const float xb = fminf(fmaxf(-k * y1, x0), x1), ub = fmaf(k, y1, xb);
+    f = fminf(fmaf(A * ua, ua, C * y0 * y0), fmaf(A * ub, ub, C * y1 * y1));
+  }
+  {
+    const float ya = fminf(fmaxf(-s * x0, y0), y1), ua = fmaf(k, ya, x0);
+    const float yb = fminf(fmaxf(-s * x1, y0), y1), ub = fmaf(k, yb, x1);
+    f = fminf(f, fminf(fmaf(A * ua, ua, C * ya * ya), fmaf(A * ub, ub, C * yb * yb)));
+  }
+  return f <= tau + 1e-3f * (1.0f + tau);
+}
+
+static inline int tile_waves(const kgs_ctx* ctx) { return ctx->cfg.tile_w * ctx->cfg.tile_h / 64; }
+
+static inline RenderParams render_params(const kgs_ctx* ctx) {
+  RenderParams P;
+  P.W = ctx->cfg.width;
+  P.H = ctx->cfg.height;
+  P.tile_w = ctx->cfg.tile_w;
+  P.tile_h = ctx->cfg.tile_h;
+  P.tiles_x = ctx->tiles_x;
+  P.tiles_y = ctx->tiles_y;
+  P.n_tiles = ctx->n_tiles;
+  P.log2_amin = log2f(ctx->cfg.alpha_min);
+  P.amax = ctx->cfg.alpha_max;
+  P.tmin = ctx->cfg.t_min;
+  P.bg0 = ctx->cfg.bg[0];
+  P.bg1 = ctx->cfg.bg[1];
+  P.bg2 = ctx->cfg.bg[2];
+  return P;
+}
+
 
 // Device-wide exclusive scan (kgs_scan.hip): W (1 or 2) interleaved u32 values
 // per entry, u64 accumulation, outputs clamped at cap0 / cap1; in may equal

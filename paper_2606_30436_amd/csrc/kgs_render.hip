@@ -24,39 +24,6 @@
 // segmented sum which ones were.
 #include "kgs_internal.h"
 
-struct RenderParams {
-  int W, H, tile_w, tile_h, tiles_x, tiles_y, n_tiles;
-  float log2_amin, amax, tmin;
-  float bg0, bg1, bg2;
-};
-
-// Whether the footprint {log2 alpha >= log2 alpha_min} of a record can reach
-// the pixel-centre box [x0, x1] x [y0, y1] (record coordinates): the minimum
-// of q = A (x + k y)^2 + C y^2 over the box (A = -P', C = -E') against
-// tau = log2 o - log2 alpha_min.  q is convex, so the minimum is 0 with the
-// centre inside the box, else on an edge: y = y0 or y1 at x = clamp(-k y),
-// x = x0 or x1 at y = clamp(-A k x / (A k^2 + C)).  The margin keeps the test
-// conservative against the rounding of the per-pixel evaluation.
-__device__ __forceinline__ bool footprint_meets_box(float x0, float x1, float y0, float y1, const float4& r0,
-                                                    const float4& r1, float log2_amin) {
-  const float A = -r0.z, k = r0.w, C = -r1.x;
-  const float tau = r1.y - log2_amin;
-  if (x0 <= 0.f && x1 >= 0.f && y0 <= 0.f && y1 >= 0.f) return true;
-  const float s = A * k * __builtin_amdgcn_rcpf(fmaf(A * k, k, C));
-  float f;
-  {
-    const float xa = fminf(fmaxf(-k * y0, x0), x1), ua = fmaf(k, y0, xa);
-    const float xb = fminf(fmaxf(-k * y1, x0), x1), ub = fmaf(k, y1, xb);
-    f = fminf(fmaf(A * ua, ua, C * y0 * y0), fmaf(A * ub, ub, C * y1 * y1));
-  }
-  {
-    const float ya = fminf(fmaxf(-s * x0, y0), y1), ua = fmaf(k, ya, x0);
-    const float yb = fminf(fmaxf(-s * x1, y0), y1), ub = fmaf(k, yb, x1);
-    f = fminf(f, fminf(fmaf(A * ua, ua, C * ya * ya), fmaf(A * ub, ub, C * yb * yb)));
-  }
-  return f <= tau + 1e-3f * (1.0f + tau);
-}
-
 // Forward: every wave stages the tile's records itself, 64 at a time (one per
 // lane), keeps those that reach its sub-block (rectangle, then the exact
 // footprint test) compacted in its own LDS rows, and composites them; no
@@ -726,26 +693,6 @@ __global__ __launch_bounds__(64 * NW) void k_render_bwd(
 
 // ---------------------------------------------------------------- host side
 // waves per compositing workgroup: one per 8x8 sub-block of the tile
-static int tile_waves(const kgs_ctx* ctx) { return ctx->cfg.tile_w * ctx->cfg.tile_h / 64; }
-
-static RenderParams render_params(const kgs_ctx* ctx) {
-  RenderParams P;
-  P.W = ctx->cfg.width;
-  P.H = ctx->cfg.height;
-  P.tile_w = ctx->cfg.tile_w;
-  P.tile_h = ctx->cfg.tile_h;
-  P.tiles_x = ctx->tiles_x;
-  P.tiles_y = ctx->tiles_y;
-  P.n_tiles = ctx->n_tiles;
-  P.log2_amin = log2f(ctx->cfg.alpha_min);
-  P.amax = ctx->cfg.alpha_max;
-  P.tmin = ctx->cfg.t_min;
-  P.bg0 = ctx->cfg.bg[0];
-  P.bg1 = ctx->cfg.bg[1];
-  P.bg2 = ctx->cfg.bg[2];
-  return P;
-}
-
 kgs_status kgs_launch_render_fwd(kgs_ctx* ctx, const kgs_image* out, hipStream_t st) {
   const RenderParams P = render_params(ctx);
   const unsigned grid = (unsigned)(ctx->last_views * ctx->n_tiles);

@@ -5,6 +5,7 @@ from __future__ import annotations
 
 import dataclasses
 
+import numpy as np
 import torch
 
 from . import _lib as L
@@ -97,3 +98,45 @@ class VoxelMap:
         assert n <= self.max_items
         L.kgs_map_revoxelize(means, level, n, self.table, self.log2, keep, anchor, n_keep, self.status, self.workspace,
                              self.ws_bytes, stream)
+
+
+@dataclasses.dataclass
+class Anchors:
+    """Device anchors (kgs_anchors): p [3][A], feat [A][32], log_l [3][A], offsets [K][3][A], level [A]."""
+    p: torch.Tensor
+    feat: torch.Tensor
+    log_l: torch.Tensor
+    offsets: torch.Tensor
+    level: torch.Tensor
+
+    @property
+    def n(self) -> int:
+        return int(self.p.shape[1])
+
+    @property
+    def k(self) -> int:
+        return int(self.offsets.shape[0])
+
+    @staticmethod
+    def from_arrays(p, feat, log_l, offsets, level, device="cuda") -> "Anchors":
+        f = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(device)
+        return Anchors(f(p), f(feat), f(log_l), f(offsets),
+                       torch.from_numpy(np.ascontiguousarray(level, np.int32)).to(device))
+
+    def c(self) -> L.KgsAnchors:
+        a = L.KgsAnchors()
+        a.p, a.feat, a.log_l = self.p.data_ptr(), self.feat.data_ptr(), self.log_l.data_ptr()
+        a.offsets, a.level, a.n, a.k = self.offsets.data_ptr(), self.level.data_ptr(), self.n, self.k
+        return a
+
+
+def decode_anchors(anchors: Anchors, theta, camera, out, stream=None):
+    """kgs_anchor_decode into a degree-0 GaussianParams `out` of at least A K Gaussians."""
+    o = gaussians_out(out.means, out.log_scales, out.quats, out.logits, out.sh, 0)
+    L.kgs_anchor_decode(anchors.c(), theta, camera, o, stream)
+
+
+def anchor_stats(R, img, anchor_of, n_anchors, target, view_loss, counts, stats, status, tau_err=0.1, stream=None):
+    """kgs_anchor_stats for the views R last rendered."""
+    L.kgs_anchor_stats(R.ctx, img.c(), anchor_of, n_anchors, target, tau_err, view_loss, counts, stats.c(), status,
+                       stream)

@@ -393,3 +393,39 @@ def tiny_scene(seed: int = 0, n: int = 24, W: int = 40, H: int = 32, degree: int
 
 def random_target(seed: int, n_views: int, H: int, W: int) -> np.ndarray:
     return np.random.default_rng(seed).uniform(0.0, 1.0, (n_views, 3, H, W)).astype(np.float32)
+
+
+# Spawn-time levels of the anchor scene: the band of the distance from which the
+# anchor was first seen (10, 25, 100, 500 m: voxels of 0.1, 0.25, 1, 5, 25 m).
+ANCHOR_LEVEL_EDGES = (10.0, 25.0, 100.0, 500.0)
+ANCHOR_VOXEL = (0.1, 0.25, 1.0, 5.0, 25.0)
+
+
+def make_anchor_scene(seed: int = 6, n_anchors: int = 200_000, k: int = 10, n_views: int = 8) -> dict:
+    """Voxel anchors along the 1 km trajectory (Scaffold-style map, appendix
+    'Voxelized Representation and MLP Decoding'): positions laid out like the
+    trajectory Gaussians, each anchor seen first from a keyframe 3-60 m behind
+    it, which sets its level and its local scale (the level's voxel size); a
+    32-dim feature N(0, 0.5^2), k offsets N(0, 1) in units of the local scale,
+    and a decoder whose output biases give opacity tanh(1), rotation near the
+    identity and half-scale children.  Cameras: the first chunk's keyframes."""
+    rng = np.random.default_rng(seed)
+    length = 1080.0
+    means, _, _, _, _, sg, _ = trajectory_gaussians(rng, n_anchors, length, C3_EDGES, C3_DENSITY, degree=0)
+    s, x, z, _ = trajectory(length)
+    s_seen = np.maximum(sg - rng.uniform(3.0, 60.0, n_anchors), 0.0)
+    px, pz, _ = _path_frame(s_seen, s, x, z)
+    dist = np.sqrt((means[0] - px) ** 2 + (means[1] - 0.0) ** 2 + (means[2] - pz) ** 2)
+    level = np.searchsorted(np.array(ANCHOR_LEVEL_EDGES), dist, side="right").astype(np.int32)
+    log_l = (np.log(np.array(ANCHOR_VOXEL)[level])[None, :] + rng.normal(0.0, 0.2, (3, n_anchors))).astype(np.float32)
+    feat = rng.normal(0.0, 0.5, (n_anchors, 32)).astype(np.float32)
+    offsets = rng.normal(0.0, 1.0, (k, 3, n_anchors)).astype(np.float32)
+    W1 = rng.normal(0.0, 1.0 / math.sqrt(36.0), (32, 36))
+    b1 = rng.normal(0.0, 0.1, 32)
+    W2 = rng.normal(0.0, 0.5 / math.sqrt(32.0), (14 * k, 32))
+    child = np.array([1.0, 0, 0, 0, 1.0, 0, 0, 0, 0, 0, 0, 0, 0, 0])
+    b2 = np.tile(child, k) + rng.normal(0.0, 0.05, 14 * k)
+    theta = np.concatenate([W1.ravel(), b1, W2.ravel(), b2]).astype(np.float32)
+    cams = trajectory_cameras(chunk_view_arclengths(0, n_views), length)
+    return dict(p=means, feat=feat, log_l=log_l, offsets=offsets, level=level, theta=theta, k=k, cams=cams,
+                width=1242, height=375)

@@ -32,7 +32,7 @@ STRUCTS = {
     "kgs_camera": L.KgsCamera, "kgs_config": L.KgsConfig, "kgs_gaussians": L.KgsGaussians,
     "kgs_image": L.KgsImage, "kgs_grads": L.KgsGrads, "kgs_view_stats": L.KgsViewStats,
     "kgs_lifecycle_state": L.KgsLifecycleState, "kgs_buffers": L.KgsBuffers, "kgs_chunk_desc": L.KgsChunkDesc,
-    "kgs_spawn_list": L.KgsSpawnList, "kgs_gaussians_out": L.KgsGaussiansOut,
+    "kgs_spawn_list": L.KgsSpawnList, "kgs_gaussians_out": L.KgsGaussiansOut, "kgs_anchors": L.KgsAnchors,
 }
 
 
