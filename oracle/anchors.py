@@ -21,7 +21,9 @@ Readings where the paper is silent:
   * The decoded Gaussian enters the rasterizer with SH degree 0 (its colour is
     already view dependent): coefficient (c - 0.5) / Y_00; opacity logit
     ln(alpha~ / (1 - alpha~)), and a child with alpha~ <= 0 gets the logit -100
-    (fully transparent, culled).
+    (fully transparent, culled).  Inside the band alpha~ = tanh(y), and the
+    logit is formed from y as ln((e^{2y} - 1) / 2), the same number without the
+    cancellation of 1 - tanh y near 1 (see tanh_logit).
   * Child k of anchor a is Gaussian a K + k.
   * The network runs on the matrix cores with BF16 operands: the 36 inputs, both
     weight matrices and the 32 hidden activations are rounded to BF16 (nearest,
@@ -51,6 +53,14 @@ def unpack(theta, K):
     W2 = t[o:o + OUTC * K * HID].reshape(OUTC * K, HID); o += OUTC * K * HID
     b2 = t[o:o + OUTC * K]
     return W1, b1, W2, b2
+
+
+def tanh_logit(y):
+    """ln(a / (1 - a)) for a = tanh(y), y > 0.  Since 1 - tanh y = 2 / (e^{2y} + 1), the ratio is
+    (e^{2y} - 1) / 2 exactly; this form keeps its precision where tanh y rounds to 1."""
+    y = np.maximum(np.asarray(y, np.float64), 1e-300)
+    with np.errstate(over="ignore", divide="ignore"):
+        return np.where(y < 0.5, np.log(0.5 * np.expm1(2.0 * y)), 2.0 * y - math.log(2.0) + np.log1p(-np.exp(-2.0 * y)))
 
 
 def lod_mask(distance, level):
@@ -97,8 +107,7 @@ def decode(anchors: dict, theta, K: int, centre) -> dict:
     xk = p.T[:, None, :] + (Ok + dO) * l[:, None, :]
     log_s = log_l.T[:, None, :] + np.log(ds)
     at = alpha * lod_mask(d, level)[:, None]
-    with np.errstate(divide="ignore"):
-        logit = np.where(at > 0, np.log(np.maximum(at, 1e-300) / (1.0 - at)), -100.0)
+    logit = np.where(at > 0, tanh_logit(yk[..., 0]), -100.0)
     n = A * K
     out = dict(means=xk.reshape(n, 3).T.copy(), log_scales=log_s.reshape(n, 3).T.copy(),
                quats=q.reshape(n, 4).T.copy(), logits=logit.reshape(n), sh=((col.reshape(n, 3).T - 0.5) / Y00)[None],

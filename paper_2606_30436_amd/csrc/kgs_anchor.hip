@@ -9,7 +9,8 @@
 //   x_k = p_i + (O_k + dO_k) * l_i,  s_k = l_i * sigmoid(ds_k),
 //   alpha~ = tanh(alpha) * M_l(d)   (1 inside the level's distance band, else 0),
 //   colour = sigmoid(.)  written as a degree-0 SH coefficient (c - 0.5) / Y_00,
-//   opacity logit ln(alpha~ / (1 - alpha~)), -100 when alpha~ <= 0.
+//   opacity logit ln(alpha~ / (1 - alpha~)) (formed from the raw output, see tanh_logit),
+//   -100 when alpha~ <= 0.
 // Both products run on the matrix cores (v_mfma_f32_16x16x16_bf16, BF16
 // operands, FP32 accumulation); anchors are the N dimension, so the hidden
 // tile is directly the second product's B operand.  A wave decodes 16 anchors
@@ -63,6 +64,12 @@ __device__ __forceinline__ f32x4_t ad_mfma(bf16x4_t a, bf16x4_t b, f32x4_t c) {
 
 __device__ __forceinline__ float log_sigmoid(float z) {
   return z >= 0.f ? -log1pf(expf(-z)) : z - log1pf(expf(z));
+}
+
+// ln(tanh y / (1 - tanh y)) for y > 0, without forming 1 - tanh y (which cancels as tanh y -> 1): the ratio
+// is (e^{2y} - 1) / 2, so the logit is ln(expm1(2y) / 2), or 2y - ln 2 + ln(1 - e^{-2y}) once e^{2y} is large.
+__device__ __forceinline__ float tanh_logit(float y) {
+  return y < 0.5f ? logf(0.5f * expm1f(2.0f * y)) : 2.0f * y - 0.69314718055994531f + log1pf(-expf(-2.0f * y));
 }
 
 struct DecodeParams {
@@ -148,8 +155,7 @@ __global__ __launch_bounds__(256) void k_anchor_decode(DecodeParams P, const flo
       const double dd = sqrt(e0 * e0 + e1 * e1 + e2 * e2);
       const int lev = A.level[ga];
       const bool in_band = lev >= 0 && lev < 5 && dd >= P.dmin[lev] && dd < P.dmax[lev];
-      const float alpha = in_band ? tanhf(y[0]) : 0.f;
-      G.opacity_logits[j] = alpha > 0.f ? logf(alpha / (1.0f - alpha)) : -100.0f;
+      G.opacity_logits[j] = in_band && y[0] > 0.f ? tanh_logit(y[0]) : -100.0f;
       for (int ch = 0; ch < 3; ++ch) {
         const float col = 1.0f / (1.0f + expf(-y[1 + ch]));
         G.sh[(int64_t)ch * N + j] = (col - 0.5f) / 0.28209479177387814f;

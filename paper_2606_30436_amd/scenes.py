@@ -421,7 +421,8 @@ def make_anchor_scene(seed: int = 6, n_anchors: int = 200_000, k: int = 10, n_vi
     feat = rng.normal(0.0, 0.5, (n_anchors, 32)).astype(np.float32)
     offsets = rng.normal(0.0, 1.0, (k, 3, n_anchors)).astype(np.float32)
     W1 = rng.normal(0.0, 1.0 / math.sqrt(36.0), (32, 36))
-    b1 = rng.normal(0.0, 0.1, 32)
+    W1[:, 35] *= 0.01                                    # the distance input reaches 1 km: weight it like a
+    b1 = rng.normal(0.0, 0.1, 32)                        # metre-scale input of the other columns' size
     W2 = rng.normal(0.0, 0.5 / math.sqrt(32.0), (14 * k, 32))
     child = np.array([1.0, 0, 0, 0, 1.0, 0, 0, 0, 0, 0, 0, 0, 0, 0])
     b2 = np.tile(child, k) + rng.normal(0.0, 0.05, 14 * k)

@@ -68,6 +68,22 @@ def test_network_layout_against_explicit_loops():
         assert np.allclose(out["raw"][a], y, rtol=0, atol=1e-12)
 
 
+def test_tanh_logit():
+    """ln(tanh y / (1 - tanh y)) three ways: the plain quotient where tanh is far from 1, the asymptote 2y - ln 2
+    where e^{-2y} vanishes in FP64, and 60-digit decimal arithmetic of ln((e^{2y} - 1) / 2) in between."""
+    import decimal
+    y = np.array([1e-3, 0.1, 0.49, 0.5, 0.51, 1.0, 2.5])
+    t = np.tanh(y)
+    assert np.allclose(an.tanh_logit(y), np.log(t / (1 - t)), rtol=1e-12, atol=0)
+    for big in (30.0, 400.0, 1e4):
+        assert an.tanh_logit(np.array([big]))[0] == pytest.approx(2 * big - math.log(2.0), rel=1e-15)
+    ctx = decimal.Context(prec=60)
+    for v in (0.3, 0.75, 3.0, 9.5, 17.0):
+        e = ctx.exp(ctx.multiply(decimal.Decimal(2), decimal.Decimal(v)))
+        ref = float(ctx.ln(ctx.divide(ctx.subtract(e, 1), 2)))
+        assert an.tanh_logit(np.array([v]))[0] == pytest.approx(ref, rel=1e-14)
+
+
 def test_lod_mask_bands():
     d = np.array([0.0, 9.999, 10.0, 24.9, 25.0, 99.0, 100.0, 499.0, 500.0, 1e5])
     for lev, inside in [(0, [1, 1, 0, 0, 0, 0, 0, 0, 0, 0]), (1, [0, 0, 1, 1, 0, 0, 0, 0, 0, 0]),
