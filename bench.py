@@ -42,6 +42,7 @@ SH_K = 16  # SH degree 3
 # 11-tap window (2 x 11 FMA each: 220), SSIM and its three derivative maps (35), those three filtered
 # (132), the gradient (8)
 MAPLOSS_FLOP_PER_PX_CH = 3 + 220 + 35 + 132 + 8
+FIT_NOISE = 0.02   # standard deviation of the pixel noise on the equal-PSNR fit's targets
 
 
 def chunk_roofline(stage_ms: dict, ms: float, N: int, S: int, P: int, P_live: int, E: int, E_b: int,
@@ -123,6 +124,8 @@ def main():
     ap.add_argument("--px-per-lane", type=int, default=0,
                     help="compositing backward pixels per lane (0: the library's choice)")
     ap.add_argument("--stage-reps", type=int, default=5)
+    ap.add_argument("--no-fit", action="store_true")
+    ap.add_argument("--fit-steps", type=int, default=200)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES device-to-device three times (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -338,6 +341,29 @@ def main():
             f"identical outputs {identical}")
         del P1
 
+    # ---- equal-PSNR fit: 200 Adam steps from the perturbed map, batched graph against the plain loop
+    fit_res = None
+    if not args.no_fit:
+        from paper_2606_30436_amd.fit import fit
+        cap = dict(slot_capacity=int(max_s * 1.5) + 1024, pair_capacity=int(max_p * 1.5) + 4096)
+
+        def both(tgt):
+            fb = fit(sc, tgt, "batched", iters=args.fit_steps, tile=best[0], batch=best[1], far_z=FAR, **cap)
+            fp = fit(sc, tgt, "plain", iters=args.fit_steps, tile=best[0], batch=best[1], far_z=FAR, **cap)
+            return {"psnr_start_db": round(fb["psnr_start_db"], 4), "batched_psnr_db": round(fb["psnr_db"], 4),
+                    "plain_psnr_db": round(fp["psnr_db"], 4), "delta_db": round(fb["psnr_db"] - fp["psnr_db"], 4),
+                    "batched_ms_per_step": round(fb["ms_per_step"], 3), "plain_ms_per_step": round(fp["ms_per_step"], 3)}
+
+        # a keyframe is not exactly the render of any map: the targets carry sensor-like pixel noise
+        noise = np.random.default_rng(99).normal(0.0, FIT_NOISE, tuple(target.shape)).astype(np.float32)
+        noisy = (target + torch.from_numpy(noise).to(dev)).clamp_(0.0, 1.0)
+        del noise
+        fit_res = dict(both(noisy), iterations=args.fit_steps,
+                       target=f"renders of the unperturbed map + N(0, {FIT_NOISE}^2) pixel noise, clamped to [0, 1]")
+        fit_res["noise_free_target"] = both(target)
+        del noisy
+        log(f"[bench] fit {json.dumps(fit_res)}")
+
     def psnr(a, b):
         mse = float(((a - b) ** 2).mean().item())
         return 10 * math.log10(1.0 / mse) if mse > 0 else float("inf")
@@ -382,6 +408,74 @@ def main():
     t_iso = timed(lambda: R.loss_iso(g, iso_loss, iso_grad))
     adjacent["isotropy"] = {"ms": round(t_iso, 4), "bound": "hbm", "bytes": 36 * N,
                             "frac": round(36 * N / (t_iso / 1e3) / HBM_BYTES_PER_S, 4)}
+
+    def hbm_row(ms_, nbytes, **extra):
+        return dict(ms=round(ms_, 4), bound="hbm", bytes=int(nbytes),
+                    frac=round(nbytes / (ms_ / 1e3) / HBM_BYTES_PER_S, 4), **extra)
+
+    # probabilistic initialisation on the chunk's keyframes: the noise-free renders as the keyframes, the
+    # current map's renders as the rendered map
+    from paper_2606_30436_amd.mapping import (Anchors, Initializer, SpawnList, VoxelMap, anchor_stats,
+                                              decode_anchors, gaussians_out)
+    init = Initializer(W, H, V)
+    spawn_cap = V * W * H
+    spawn = SpawnList.empty(spawn_cap)
+    uni = torch.from_numpy(np.random.default_rng(9).uniform(size=(V, H, W)).astype(np.float32)).to(dev)
+    t_init = timed(lambda: init.spawn(target, tgt_depth, uni, cams, spawn, spawn_cap, rendered=img.color,
+                                      rendered_depth=img.depth))
+    n_spawn = int(spawn.count.item())
+    # 36 B per pixel in (keyframe and render colour and depth, the uniform), the FP64 maps written and read
+    # once (40 B), the spawning pixels' records out
+    adjacent["init_spawn"] = hbm_row(t_init, (36 + 40) * V * W * H + 40 * n_spawn, spawning_pixels=n_spawn)
+    # the keyframes' spawning pixels into an empty voxel map, then their new Gaussians
+    vmap = VoxelMap(22, max(n_spawn, 1))
+    keys = vmap.keys(spawn.level[:n_spawn], spawn.voxel[:n_spawn])
+    n0 = torch.zeros(1, dtype=torch.int32, device=dev)
+    n1 = torch.zeros(1, dtype=torch.int32, device=dev)
+    anchor_ids = torch.empty(max(n_spawn, 1), dtype=torch.int32, device=dev)
+    created = torch.empty(max(n_spawn, 1), dtype=torch.int32, device=dev)
+
+    def map_insert():
+        vmap.clear()
+        vmap.insert(keys, n0, n1, anchor_ids, created)
+    t_ins = timed(map_insert)
+    # per candidate: key 8 B, slot read + claim 16 B, index and anchor out 8 B; the 2^22-slot clear
+    adjacent["map_insert"] = hbm_row(t_ins, 32 * n_spawn + 16 * (1 << 22), candidates=n_spawn,
+                                     new_anchors=int(n1.item()))
+    # decoded Gaussians of 200k voxel anchors with 10 children each (2M Gaussians) for one keyframe, and
+    # their per-anchor union footprints after compositing
+    asc = scenes.make_anchor_scene()
+    A_n, K_n = len(asc["level"]), asc["k"]
+    anc = Anchors.from_arrays(asc["p"], asc["feat"], asc["log_l"], asc["offsets"], asc["level"])
+    theta_a = torch.from_numpy(asc["theta"]).to(dev)
+    acams = device_cameras(asc["cams"]).view(len(asc["cams"]), -1)
+    dec = GaussianParams(torch.empty(3, A_n * K_n, device=dev), torch.empty(3, A_n * K_n, device=dev),
+                         torch.empty(4, A_n * K_n, device=dev), torch.empty(A_n * K_n, device=dev),
+                         torch.empty(1, 3, A_n * K_n, device=dev), 0)
+    t_dec = timed(lambda: decode_anchors(anc, theta_a, acams[4], dec))
+    # per anchor 276 B in (p, f, log l, 10 offsets, level), per child 56 B out
+    adjacent["anchor_decode"] = hbm_row(t_dec, 276 * A_n + 56 * A_n * K_n, anchors=A_n, children=K_n,
+                                        view="the fifth keyframe")
+    RA = Rasterizer(W, H, 1, A_n * K_n, slot_capacity=A_n * K_n, pair_capacity=40_000_000, tile=best[0],
+                    batch=best[1])
+    RA.project(dec, acams[4])
+    RA.bin_sort()
+    aimg = Image.empty(1, H, W)
+    RA.render_fwd(aimg)
+    a_of = torch.arange(A_n * K_n, device=dev, dtype=torch.int32) // K_n
+    ast = ViewStats.zeros(A_n)
+    acounts = torch.zeros(2 * A_n, dtype=torch.int32, device=dev)
+    astatus = torch.zeros(2, dtype=torch.int32, device=dev)
+    t_ast = timed(lambda: anchor_stats(RA, aimg, a_of, A_n, target[4:5], None, acounts, ast, astatus))
+    E_a = int(aimg.last.to(torch.int64).sum().item())
+    # every evaluated entry is tested (10 flop) and blended entries update T (6 flop); the ballots and
+    # unions are the overhead this count leaves out
+    flop_a = FLOP_TEST * E_a
+    adjacent["anchor_stats"] = dict(ms=round(t_ast, 4), bound="alu", flop=int(flop_a), evaluations=E_a,
+                                    achieved_tflops=round(flop_a / (t_ast / 1e3) / 1e12, 3),
+                                    frac=round(flop_a / (t_ast / 1e3) / 1e12 / PEAK_ALU_TFLOPS, 4),
+                                    rewalks=int(astatus[1].item()))
+    del RA
     log(f"[bench] adjacent rows {json.dumps(adjacent)}")
 
     # ---- CPU oracle baseline (the whole chunk, FP64, all host threads)
@@ -439,6 +533,7 @@ def main():
                    "plain_ms_per_chunk_no_host_read": None if plain_nr_ms is None else round(plain_nr_ms, 4),
                    "speedup_vs_plain_no_host_read": None if plain_nr_ms is None else round(plain_nr_ms / ms, 3),
                    "outputs_identical_to_plain": identical, "psnr_vs_target_db": round(psnr_b, 3),
+                   "equal_psnr_fit": fit_res,
                    "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
                    "autotune_ms": table},
         "roofline": roofline,

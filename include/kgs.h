@@ -413,6 +413,13 @@ kgs_status kgs_map_revoxelize(const float* means, const int32_t* level, int64_t 
                               uint8_t* keep, uint32_t* anchor, uint32_t* n_keep, uint32_t* status, void* workspace,
                               size_t workspace_bytes, void* stream);
 
+/* One Adam step (bias-corrected, step >= 1) over n map parameters: the
+ * gradient steps of the sliding-window optimisation (Sec. 3.2; the paper
+ * names no optimiser).  m and v are the caller's moment buffers (zeroed before
+ * step 1). */
+kgs_status kgs_adam(float* theta, float* m, float* v, const float* grad, int64_t n, int32_t step, float lr, float beta1,
+                    float beta2, float eps, void* stream);
+
 /* ------------------------------------------------------------------------
  * Anchors (appendix "Voxelized Representation and MLP Decoding" and
  * "Level-of-Detail (LoD) Mask Computation"; per-anchor scores of appendix

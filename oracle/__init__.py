@@ -22,6 +22,7 @@ Modules
                  points, position and scale composition, the level-of-detail
                  opacity mask); the per-anchor union footprint statistics are
                  View.anchor_stats in the C oracle
+  optim.py       Adam with bias correction (the map's gradient steps)
 
 Every function cites the passage of the paper it follows; readings of passages
 the paper leaves open are the constants of OracleConfig.

@@ -105,6 +105,8 @@ _SIGS = {
                                    c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "kgs_loss_iso": (c_int32, [c_void_p, P(KgsGaussians), c_float, c_void_p, c_void_p, c_void_p]),
     "kgs_init_workspace_size": (c_int32, [c_int32, c_int32, c_int32, P(ctypes.c_size_t)]),
+    "kgs_adam": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_int64, c_int32, c_float, c_float, c_float,
+                           c_float, c_void_p]),
     "kgs_anchor_decode": (c_int32, [P(KgsAnchors), c_void_p, c_void_p, P(KgsGaussiansOut), c_void_p]),
     "kgs_anchor_stats": (c_int32, [c_void_p, P(KgsImage), c_void_p, c_int64, c_void_p, c_float, c_void_p, c_void_p,
                                    P(KgsViewStats), c_void_p, c_void_p]),
@@ -278,6 +280,11 @@ def kgs_init_spawn(color, depth, rendered, rendered_depth, uniforms, cams, n_vie
     check(load().kgs_init_spawn(ptr(color), ptr(depth), ptr(rendered), ptr(rendered_depth), ptr(uniforms), ptr(cams),
                                 int(n_views), int(width), int(height), ptr(workspace), int(workspace_bytes), ptr(p_kf),
                                 ctypes.byref(out), stream_handle(stream)), "kgs_init_spawn")
+
+
+def kgs_adam(theta, m, v, grad, n, step, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    check(load().kgs_adam(ptr(theta), ptr(m), ptr(v), ptr(grad), int(n), int(step), float(lr), float(beta1),
+                          float(beta2), float(eps), stream_handle(stream)), "kgs_adam")
 
 
 def kgs_anchor_decode(a: KgsAnchors, theta, camera, out: KgsGaussiansOut, stream=None):

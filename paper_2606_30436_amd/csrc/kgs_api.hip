@@ -394,6 +394,14 @@ kgs_status kgs_map_revoxelize(const float* means, const int32_t* level, int64_t 
                                    (char*)workspace, (hipStream_t)stream);
 }
 
+kgs_status kgs_adam(float* theta, float* m, float* v, const float* grad, int64_t n, int32_t step, float lr, float beta1,
+                    float beta2, float eps, void* stream) {
+  if (n < 0 || step < 1 || (n > 0 && (!theta || !m || !v || !grad)) || !(lr >= 0.f) || !(beta1 >= 0.f && beta1 < 1.f) ||
+      !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
+    return KGS_ERR_INVALID_ARG;
+  return kgs_launch_adam(theta, m, v, grad, n, step, lr, beta1, beta2, eps, (hipStream_t)stream);
+}
+
 kgs_status kgs_anchor_decode(const kgs_anchors* a, const float* theta, const kgs_camera* camera,
                              const kgs_gaussians_out* out, void* stream) {
   if (!a || !theta || !camera || !out || a->n < 0 || a->k < 1 || a->k > 16) return KGS_ERR_INVALID_ARG;

@@ -470,6 +470,8 @@ kgs_status kgs_check_launch();
 const double* kgs_launch_chunk_minmax(kgs_ctx* ctx, const kgs_view_stats* s, int64_t n, hipStream_t st);
 int kgs_maploss_tiles(int W, int H);
 size_t kgs_init_ws_bytes(int W, int H, int V);
+kgs_status kgs_launch_adam(float* theta, float* m, float* v, const float* g, int64_t n, int32_t step, float lr,
+                           float b1, float b2, float eps, hipStream_t st);
 kgs_status kgs_launch_anchor_decode(const kgs_anchors* a, const float* theta, const kgs_camera& cam,
                                     const kgs_gaussians_out* out, hipStream_t st);
 kgs_status kgs_launch_anchor_stats(kgs_ctx* ctx, const kgs_image* fwd, const uint32_t* anchor_of, int64_t n_anchor,
