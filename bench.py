@@ -125,6 +125,7 @@ def main():
                     help="compositing backward pixels per lane (0: the library's choice)")
     ap.add_argument("--stage-reps", type=int, default=5)
     ap.add_argument("--no-fit", action="store_true")
+    ap.add_argument("--no-adjacent", action="store_true", help="skip the timed rows of the other mapping kernels")
     ap.add_argument("--fit-steps", type=int, default=200)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES device-to-device three times (HBM counter calibration) and exit")
@@ -381,101 +382,105 @@ def main():
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps
 
-    adjacent = {}
-    # mapping loss (0.8 L1 + 0.2 D-SSIM and the depth L1 against renders of the noise-free map)
-    tgt_depth = torch.empty(V, H, W, device=dev)
-    R.project(gt, cams)
-    R.bin_sort()
-    timg = Image(torch.empty_like(img.color), tgt_depth, torch.empty_like(img.t_final), torch.empty_like(img.last))
-    R.render_fwd(timg)
-    R.project(g, cams)
-    R.bin_sort()
-    R.render_fwd(img)
-    ml_dl, ml_dd = torch.empty_like(img.color), torch.empty_like(img.depth)
-    ml_loss, ml_geo = torch.empty(V, device=dev), torch.empty(V, device=dev)
-    t_ml = timed(lambda: R.loss_mapping(V, img, target, ml_dl, ml_loss, target_depth=tgt_depth, dl_ddepth=ml_dd,
-                                        geo_loss=ml_geo))
-    px_ch = 3 * V * W * H
-    flop_ml = MAPLOSS_FLOP_PER_PX_CH * px_ch + 3 * V * W * H
-    bytes_ml = 12 * px_ch + 12 * V * W * H
-    adjacent["mapping_loss"] = {
-        "ms": round(t_ml, 4), "bound": "alu", "flop": int(flop_ml), "bytes": int(bytes_ml),
-        "achieved_tflops": round(flop_ml / (t_ml / 1e3) / 1e12, 3),
-        "frac": round(flop_ml / (t_ml / 1e3) / 1e12 / PEAK_ALU_TFLOPS, 4),
-        "photometric_loss_per_view": [round(float(x), 5) for x in ml_loss.cpu().tolist()]}
-    iso_loss = torch.empty(1, device=dev)
-    iso_grad = torch.zeros(3, N, device=dev)
-    t_iso = timed(lambda: R.loss_iso(g, iso_loss, iso_grad))
-    adjacent["isotropy"] = {"ms": round(t_iso, 4), "bound": "hbm", "bytes": 36 * N,
-                            "frac": round(36 * N / (t_iso / 1e3) / HBM_BYTES_PER_S, 4)}
+    def adjacent_rows():
+        adjacent = {}
+        # mapping loss (0.8 L1 + 0.2 D-SSIM and the depth L1 against renders of the noise-free map)
+        tgt_depth = torch.empty(V, H, W, device=dev)
+        R.project(gt, cams)
+        R.bin_sort()
+        timg = Image(torch.empty_like(img.color), tgt_depth, torch.empty_like(img.t_final), torch.empty_like(img.last))
+        R.render_fwd(timg)
+        R.project(g, cams)
+        R.bin_sort()
+        R.render_fwd(img)
+        ml_dl, ml_dd = torch.empty_like(img.color), torch.empty_like(img.depth)
+        ml_loss, ml_geo = torch.empty(V, device=dev), torch.empty(V, device=dev)
+        t_ml = timed(lambda: R.loss_mapping(V, img, target, ml_dl, ml_loss, target_depth=tgt_depth, dl_ddepth=ml_dd,
+                                            geo_loss=ml_geo))
+        px_ch = 3 * V * W * H
+        flop_ml = MAPLOSS_FLOP_PER_PX_CH * px_ch + 3 * V * W * H
+        bytes_ml = 12 * px_ch + 12 * V * W * H
+        adjacent["mapping_loss"] = {
+            "ms": round(t_ml, 4), "bound": "alu", "flop": int(flop_ml), "bytes": int(bytes_ml),
+            "achieved_tflops": round(flop_ml / (t_ml / 1e3) / 1e12, 3),
+            "frac": round(flop_ml / (t_ml / 1e3) / 1e12 / PEAK_ALU_TFLOPS, 4),
+            "photometric_loss_per_view": [round(float(x), 5) for x in ml_loss.cpu().tolist()]}
+        iso_loss = torch.empty(1, device=dev)
+        iso_grad = torch.zeros(3, N, device=dev)
+        t_iso = timed(lambda: R.loss_iso(g, iso_loss, iso_grad))
+        adjacent["isotropy"] = {"ms": round(t_iso, 4), "bound": "hbm", "bytes": 36 * N,
+                                "frac": round(36 * N / (t_iso / 1e3) / HBM_BYTES_PER_S, 4)}
 
-    def hbm_row(ms_, nbytes, **extra):
-        return dict(ms=round(ms_, 4), bound="hbm", bytes=int(nbytes),
-                    frac=round(nbytes / (ms_ / 1e3) / HBM_BYTES_PER_S, 4), **extra)
+        def hbm_row(ms_, nbytes, **extra):
+            return dict(ms=round(ms_, 4), bound="hbm", bytes=int(nbytes),
+                        frac=round(nbytes / (ms_ / 1e3) / HBM_BYTES_PER_S, 4), **extra)
 
-    # probabilistic initialisation on the chunk's keyframes: the noise-free renders as the keyframes, the
-    # current map's renders as the rendered map
-    from paper_2606_30436_amd.mapping import (Anchors, Initializer, SpawnList, VoxelMap, anchor_stats,
-                                              decode_anchors, gaussians_out)
-    init = Initializer(W, H, V)
-    spawn_cap = V * W * H
-    spawn = SpawnList.empty(spawn_cap)
-    uni = torch.from_numpy(np.random.default_rng(9).uniform(size=(V, H, W)).astype(np.float32)).to(dev)
-    t_init = timed(lambda: init.spawn(target, tgt_depth, uni, cams, spawn, spawn_cap, rendered=img.color,
-                                      rendered_depth=img.depth))
-    n_spawn = int(spawn.count.item())
-    # 36 B per pixel in (keyframe and render colour and depth, the uniform), the FP64 maps written and read
-    # once (40 B), the spawning pixels' records out
-    adjacent["init_spawn"] = hbm_row(t_init, (36 + 40) * V * W * H + 40 * n_spawn, spawning_pixels=n_spawn)
-    # the keyframes' spawning pixels into an empty voxel map, then their new Gaussians
-    vmap = VoxelMap(22, max(n_spawn, 1))
-    keys = vmap.keys(spawn.level[:n_spawn], spawn.voxel[:n_spawn])
-    n0 = torch.zeros(1, dtype=torch.int32, device=dev)
-    n1 = torch.zeros(1, dtype=torch.int32, device=dev)
-    anchor_ids = torch.empty(max(n_spawn, 1), dtype=torch.int32, device=dev)
-    created = torch.empty(max(n_spawn, 1), dtype=torch.int32, device=dev)
+        # probabilistic initialisation on the chunk's keyframes: the noise-free renders as the keyframes, the
+        # current map's renders as the rendered map
+        from paper_2606_30436_amd.mapping import (Anchors, Initializer, SpawnList, VoxelMap, anchor_stats,
+                                                  decode_anchors, gaussians_out)
+        init = Initializer(W, H, V)
+        spawn_cap = V * W * H
+        spawn = SpawnList.empty(spawn_cap)
+        uni = torch.from_numpy(np.random.default_rng(9).uniform(size=(V, H, W)).astype(np.float32)).to(dev)
+        t_init = timed(lambda: init.spawn(target, tgt_depth, uni, cams, spawn, spawn_cap, rendered=img.color,
+                                          rendered_depth=img.depth))
+        n_spawn = int(spawn.count.item())
+        # 36 B per pixel in (keyframe and render colour and depth, the uniform), the FP64 maps written and read
+        # once (40 B), the spawning pixels' records out
+        adjacent["init_spawn"] = hbm_row(t_init, (36 + 40) * V * W * H + 40 * n_spawn, spawning_pixels=n_spawn)
+        # the keyframes' spawning pixels into an empty voxel map, then their new Gaussians
+        vmap = VoxelMap(22, max(n_spawn, 1))
+        keys = vmap.keys(spawn.level[:n_spawn], spawn.voxel[:n_spawn])
+        n0 = torch.zeros(1, dtype=torch.int32, device=dev)
+        n1 = torch.zeros(1, dtype=torch.int32, device=dev)
+        anchor_ids = torch.empty(max(n_spawn, 1), dtype=torch.int32, device=dev)
+        created = torch.empty(max(n_spawn, 1), dtype=torch.int32, device=dev)
 
-    def map_insert():
-        vmap.clear()
-        vmap.insert(keys, n0, n1, anchor_ids, created)
-    t_ins = timed(map_insert)
-    # per candidate: key 8 B, slot read + claim 16 B, index and anchor out 8 B; the 2^22-slot clear
-    adjacent["map_insert"] = hbm_row(t_ins, 32 * n_spawn + 16 * (1 << 22), candidates=n_spawn,
-                                     new_anchors=int(n1.item()))
-    # decoded Gaussians of 200k voxel anchors with 10 children each (2M Gaussians) for one keyframe, and
-    # their per-anchor union footprints after compositing
-    asc = scenes.make_anchor_scene()
-    A_n, K_n = len(asc["level"]), asc["k"]
-    anc = Anchors.from_arrays(asc["p"], asc["feat"], asc["log_l"], asc["offsets"], asc["level"])
-    theta_a = torch.from_numpy(asc["theta"]).to(dev)
-    acams = device_cameras(asc["cams"]).view(len(asc["cams"]), -1)
-    dec = GaussianParams(torch.empty(3, A_n * K_n, device=dev), torch.empty(3, A_n * K_n, device=dev),
-                         torch.empty(4, A_n * K_n, device=dev), torch.empty(A_n * K_n, device=dev),
-                         torch.empty(1, 3, A_n * K_n, device=dev), 0)
-    t_dec = timed(lambda: decode_anchors(anc, theta_a, acams[4], dec))
-    # per anchor 276 B in (p, f, log l, 10 offsets, level), per child 56 B out
-    adjacent["anchor_decode"] = hbm_row(t_dec, 276 * A_n + 56 * A_n * K_n, anchors=A_n, children=K_n,
-                                        view="the fifth keyframe")
-    RA = Rasterizer(W, H, 1, A_n * K_n, slot_capacity=A_n * K_n, pair_capacity=40_000_000, tile=best[0],
-                    batch=best[1])
-    RA.project(dec, acams[4])
-    RA.bin_sort()
-    aimg = Image.empty(1, H, W)
-    RA.render_fwd(aimg)
-    a_of = torch.arange(A_n * K_n, device=dev, dtype=torch.int32) // K_n
-    ast = ViewStats.zeros(A_n)
-    acounts = torch.zeros(2 * A_n, dtype=torch.int32, device=dev)
-    astatus = torch.zeros(2, dtype=torch.int32, device=dev)
-    t_ast = timed(lambda: anchor_stats(RA, aimg, a_of, A_n, target[4:5], None, acounts, ast, astatus))
-    E_a = int(aimg.last.to(torch.int64).sum().item())
-    # every evaluated entry is tested (10 flop) and blended entries update T (6 flop); the ballots and
-    # unions are the overhead this count leaves out
-    flop_a = FLOP_TEST * E_a
-    adjacent["anchor_stats"] = dict(ms=round(t_ast, 4), bound="alu", flop=int(flop_a), evaluations=E_a,
-                                    achieved_tflops=round(flop_a / (t_ast / 1e3) / 1e12, 3),
-                                    frac=round(flop_a / (t_ast / 1e3) / 1e12 / PEAK_ALU_TFLOPS, 4),
-                                    rewalks=int(astatus[1].item()))
-    del RA
+        def map_insert():
+            vmap.clear()
+            vmap.insert(keys, n0, n1, anchor_ids, created)
+        t_ins = timed(map_insert)
+        # per candidate: key 8 B, slot read + claim 16 B, index and anchor out 8 B; the 2^22-slot clear
+        adjacent["map_insert"] = hbm_row(t_ins, 32 * n_spawn + 16 * (1 << 22), candidates=n_spawn,
+                                         new_anchors=int(n1.item()))
+        # decoded Gaussians of 200k voxel anchors with 10 children each (2M Gaussians) for one keyframe, and
+        # their per-anchor union footprints after compositing
+        asc = scenes.make_anchor_scene()
+        A_n, K_n = len(asc["level"]), asc["k"]
+        anc = Anchors.from_arrays(asc["p"], asc["feat"], asc["log_l"], asc["offsets"], asc["level"])
+        theta_a = torch.from_numpy(asc["theta"]).to(dev)
+        acams = device_cameras(asc["cams"]).view(len(asc["cams"]), -1)
+        dec = GaussianParams(torch.empty(3, A_n * K_n, device=dev), torch.empty(3, A_n * K_n, device=dev),
+                             torch.empty(4, A_n * K_n, device=dev), torch.empty(A_n * K_n, device=dev),
+                             torch.empty(1, 3, A_n * K_n, device=dev), 0)
+        t_dec = timed(lambda: decode_anchors(anc, theta_a, acams[4], dec))
+        # per anchor 276 B in (p, f, log l, 10 offsets, level), per child 56 B out
+        adjacent["anchor_decode"] = hbm_row(t_dec, 276 * A_n + 56 * A_n * K_n, anchors=A_n, children=K_n,
+                                            view="the fifth keyframe")
+        RA = Rasterizer(W, H, 1, A_n * K_n, slot_capacity=A_n * K_n, pair_capacity=40_000_000, tile=best[0],
+                        batch=best[1])
+        RA.project(dec, acams[4])
+        RA.bin_sort()
+        aimg = Image.empty(1, H, W)
+        RA.render_fwd(aimg)
+        a_of = torch.arange(A_n * K_n, device=dev, dtype=torch.int32) // K_n
+        ast = ViewStats.zeros(A_n)
+        acounts = torch.zeros(2 * A_n, dtype=torch.int32, device=dev)
+        astatus = torch.zeros(2, dtype=torch.int32, device=dev)
+        t_ast = timed(lambda: anchor_stats(RA, aimg, a_of, A_n, target[4:5], None, acounts, ast, astatus))
+        E_a = int(aimg.last.to(torch.int64).sum().item())
+        # every evaluated entry is tested (10 flop) and blended entries update T (6 flop); the ballots and
+        # unions are the overhead this count leaves out
+        flop_a = FLOP_TEST * E_a
+        adjacent["anchor_stats"] = dict(ms=round(t_ast, 4), bound="alu", flop=int(flop_a), evaluations=E_a,
+                                        achieved_tflops=round(flop_a / (t_ast / 1e3) / 1e12, 3),
+                                        frac=round(flop_a / (t_ast / 1e3) / 1e12 / PEAK_ALU_TFLOPS, 4),
+                                        rewalks=int(astatus[1].item()))
+        del RA
+        return adjacent
+
+    adjacent = {} if args.no_adjacent else adjacent_rows()
     log(f"[bench] adjacent rows {json.dumps(adjacent)}")
 
     # ---- CPU oracle baseline (the whole chunk, FP64, all host threads)
