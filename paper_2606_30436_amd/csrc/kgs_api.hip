@@ -97,6 +97,7 @@ size_t layout(const kgs_config& c, char* base, kgs_ctx* ctx) {
   p = take(4 * S);                              if (ctx) ctx->slot_om = (uint32_t*)p;
   p = take(4 * (P / 2048 + 2));                 if (ctx) ctx->chunk_first = (uint32_t*)p;
   p = take(16 * S);                             if (ctx) ctx->emit_rec = (uint4*)p;
+  p = take(16 * S);                             if (ctx) ctx->emit_desc = (uint4*)p;
   {
     const int64_t st = std::max(kgs_scan_tiles(V * nb), kgs_scan_tiles(S / 64 + 2)) + 1;
     p = take(16 * st);                          if (ctx) ctx->scan_part = (unsigned long long*)p;

@@ -104,6 +104,7 @@ struct kgs_ctx {
   uint32_t* slot_om;                  // [S] pixels the slot blended (|Omega|), 0 until a backward sums them
   uint32_t* chunk_first;              // [P / 2048 + 2] record owning the first pair of each emission chunk
   uint4* emit_rec;                    // [S] emission descriptor of each record, in depth order
+  uint4* emit_desc;                   // [S] the same without the record index, in record order (projection)
   int slot_keys_ready;                // the projection wrote the depth-sort keys; no sort has used them yet
   unsigned long long* scan_part;      // tile sums of the device-wide scans
   unsigned long long* scan_totals;    // [2] their totals
@@ -549,6 +550,14 @@ __device__ __forceinline__ bool footprint_meets_box(float x0, float x1, float y0
     f = fminf(f, fminf(fmaf(A * ua, ua, C * ya * ya), fmaf(A * ub, ub, C * yb * yb)));
   }
   return f <= tau + 1e-3f * (1.0f + tau);
+}
+
+// Bits of the tile index in a pair key: tiles < 2^bits, so the padding key
+// (all ones) sorts after every tile of its view.
+static inline int kgs_tile_bits(int n_tiles) {
+  int b = 1;
+  while ((1u << b) <= (uint32_t)n_tiles) ++b;
+  return b;
 }
 
 static inline int tile_waves(const kgs_ctx* ctx) { return ctx->cfg.tile_w * ctx->cfg.tile_h / 64; }

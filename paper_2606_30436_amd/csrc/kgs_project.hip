@@ -185,7 +185,8 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_emit(kgs_gaussians g, const CamDe
                                                     float4* __restrict__ slot_rec, uint32_t* __restrict__ slot_gid,
                                                     uint32_t* __restrict__ slot_view, int4* __restrict__ slot_pix,
                                                     uint32_t* __restrict__ slot_ntiles, void* __restrict__ slot_keys,
-                                                    uint32_t* __restrict__ slot_vals, uint32_t* __restrict__ slot_om) {
+                                                    uint32_t* __restrict__ slot_om, uint4* __restrict__ emit_desc,
+                                                    int tile_bits) {
   constexpr int K = (DEG + 1) * (DEG + 1);
   // visible lanes of each wave, per view: a slot's index is the (view, block)
   // base plus the visible lanes before it (one barrier for all views)
@@ -193,9 +194,24 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_emit(kgs_gaussians g, const CamDe
   const int w = threadIdx.x >> 6;
   const int64_t i = (int64_t)blockIdx.x * KGS_BLOCK + threadIdx.x;
   const bool valid = i < g.n;
-  for (int v = 0; v < V; ++v) {
-    const uint64_t bal = ballot64(valid && vis[(int64_t)v * g.n + i] > 0u);
-    if ((threadIdx.x & 63) == 0) wcnt[v][w] = (uint32_t)__popcll(bal);
+  // the tile counts of views v0 .. v0 + 7, loaded together; those of the first
+  // eight views (all of them in most calls) stay in registers for the emission
+  auto load8 = [&](int v0, uint32_t (&t)[8]) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) t[j] = (valid && v0 + j < V) ? vis[(int64_t)(v0 + j) * g.n + i] : 0u;
+  };
+  uint32_t t8[8];
+  for (int v0 = 0; v0 < V; v0 += 8) {
+    uint32_t t[8];
+    load8(v0, t);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      if (v0 + j < V) {
+        const uint64_t bal = ballot64(t[j] > 0u);
+        if ((threadIdx.x & 63) == 0) wcnt[v0 + j][w] = (uint32_t)__popcll(bal);
+      }
+      if (v0 == 0) t8[j] = t[j];
+    }
   }
   __syncthreads();
   GaussLocal G;
@@ -204,56 +220,76 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_emit(kgs_gaussians g, const CamDe
   if (valid) load_gaussian(g, i, P.alpha_min, G, bad);
   const float hl2e = 0.5f * 1.4426950408889634f;
   uint64_t seen = 0ull;   // views whose slot holds a projected record
-  for (int v = 0; v < V; ++v) {
-    const uint32_t tiles = valid ? vis[(int64_t)v * g.n + i] : 0u;
-    const uint64_t bal = ballot64(tiles > 0u);
-    if (tiles == 0u) continue;
-    uint32_t below = mask_lt_count(bal);
-    for (int k = 0; k < w; ++k) below += wcnt[v][k];
-    const uint64_t s = (uint64_t)blk_base[((int64_t)v * nb + blockIdx.x) * 2] + below;
-    // from here on vis[v][i] names the slot (index + 1), for the backward gather
-    vis[(int64_t)v * g.n + i] = s < slot_cap ? (uint32_t)(s + 1) : 0u;
-    // past the slot capacity nothing is written; the pair capacity needs no
-    // check here: an overflow of either zeroes every count after the scan, and
-    // otherwise every slot's pairs fit
-    if (s >= slot_cap) continue;
-    const CamDev& c = cams[v];
-    ProjCore p;
-    const bool vis_ok = G.ok && project_core(c, G.mu, G.Rq, G.s, G.o, P.near_z, P.far_z, P.eps2d, P.rect_margin,
-                                             P.log_alpha_min, P.tile_w, P.tile_h, P.tiles_x, P.tiles_y, p);
-    float4 r0, r1;
-    int4 pix;
-    float* r2p = reinterpret_cast<float*>(slot_rec + s * 4 + 2);
-    if (vis_ok) {
-      r0 = make_float4(p.rmx, p.rmy, -hl2e * p.Pc, p.kc);
-      r1 = make_float4(-hl2e * p.Ec, __log2f(G.o), p.tz, pack_bounds(p.fxi - p.rx, p.fxi + p.rx));
-      r2p[3] = pack_bounds(p.fyi - p.ry, p.fyi + p.ry);   // the colour follows below
-      pix = make_int4(p.fxi, p.fyi, p.rx, p.ry);
-      seen |= 1ull << v;
+  for (int v0 = 0; v0 < V; v0 += 8) {
+    uint32_t tg[8];
+    if (v0 == 0) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) tg[j] = t8[j];
     } else {
-      // the counting pass saw this Gaussian visible but the re-projection does
-      // not: write a record that never blends and an empty rectangle
-      r0 = make_float4(0.f, 0.f, 0.f, 0.f);
-      r1 = make_float4(0.f, -INFINITY, 1.0f, pack_bounds(32767, -32768));
-      slot_rec[s * 4 + 2] = make_float4(0.f, 0.f, 0.f, pack_bounds(32767, -32768));
-      pix = make_int4(-(1 << 30), -(1 << 30), 0, 0);
+      load8(v0, tg);
     }
-    slot_rec[s * 4 + 0] = r0;
-    slot_rec[s * 4 + 1] = r1;
-    slot_gid[s] = (uint32_t)i;
-    slot_view[s] = (uint32_t)v;
-    slot_pix[s] = pix;
-    slot_ntiles[s] = tiles;
-    slot_om[s] = 0u;   // no pixel blended yet (the backward's sums set it)
-    // the record's (view, depth) key for the depth sort, from its depth r1.z
-    const uint32_t db = __float_as_uint(r1.z);
-    const uint32_t dmax = P.depth_bits >= 32 ? 0xffffffffu : (1u << P.depth_bits) - 1u;
-    const uint64_t key = ((uint64_t)v << P.depth_bits) | (db > P.depth_lo ? min(db - P.depth_lo, dmax) : 0u);
-    if (P.key32)
-      reinterpret_cast<uint32_t*>(slot_keys)[s] = (uint32_t)key;
-    else
-      reinterpret_cast<uint64_t*>(slot_keys)[s] = key;
-    slot_vals[s] = (uint32_t)s;
+    const int nv = min(8, V - v0);
+    for (int j = 0; j < nv; ++j) {
+      const int v = v0 + j;
+      // view v's count is tg[0]: the group's counts shift down one register per view
+      const uint32_t tiles = tg[0];
+#pragma unroll
+      for (int k = 0; k < 7; ++k) tg[k] = tg[k + 1];
+      const uint64_t bal = ballot64(tiles > 0u);
+      if (tiles == 0u) continue;
+      uint32_t below = mask_lt_count(bal);
+      for (int k = 0; k < w; ++k) below += wcnt[v][k];
+      const uint64_t s = (uint64_t)blk_base[((int64_t)v * nb + blockIdx.x) * 2] + below;
+      // from here on vis[v][i] names the slot (index + 1), for the backward gather
+      vis[(int64_t)v * g.n + i] = s < slot_cap ? (uint32_t)(s + 1) : 0u;
+      // past the slot capacity nothing is written; the pair capacity needs no
+      // check here: an overflow of either zeroes every count after the scan, and
+      // otherwise every slot's pairs fit
+      if (s >= slot_cap) continue;
+      const CamDev& c = cams[v];
+      ProjCore p;
+      const bool vis_ok = G.ok && project_core(c, G.mu, G.Rq, G.s, G.o, P.near_z, P.far_z, P.eps2d, P.rect_margin,
+                                               P.log_alpha_min, P.tile_w, P.tile_h, P.tiles_x, P.tiles_y, p);
+      float4 r0, r1;
+      int4 pix;
+      uint4 desc;   // the pair emission's view of the record: key base, first tile, rectangle width, tile count
+      float* r2p = reinterpret_cast<float*>(slot_rec + s * 4 + 2);
+      if (vis_ok) {
+        r0 = make_float4(p.rmx, p.rmy, -hl2e * p.Pc, p.kc);
+        r1 = make_float4(-hl2e * p.Ec, __log2f(G.o), p.tz, pack_bounds(p.fxi - p.rx, p.fxi + p.rx));
+        r2p[3] = pack_bounds(p.fyi - p.ry, p.fyi + p.ry);   // the colour follows below
+        pix = make_int4(p.fxi, p.fyi, p.rx, p.ry);
+        desc = make_uint4((uint32_t)v << tile_bits, (uint32_t)p.x0 | ((uint32_t)p.y0 << 16), (uint32_t)(p.x1 - p.x0),
+                          tiles);
+        seen |= 1ull << v;
+      } else {
+        // the counting pass saw this Gaussian visible but the re-projection does
+        // not: write a record that never blends and an empty rectangle
+        r0 = make_float4(0.f, 0.f, 0.f, 0.f);
+        r1 = make_float4(0.f, -INFINITY, 1.0f, pack_bounds(32767, -32768));
+        slot_rec[s * 4 + 2] = make_float4(0.f, 0.f, 0.f, pack_bounds(32767, -32768));
+        pix = make_int4(-(1 << 30), -(1 << 30), 0, 0);
+        // its pairs (as many as the count gave) go down the first tile column; they never blend
+        desc = make_uint4((uint32_t)v << tile_bits, 0u, 1u, tiles);
+      }
+      slot_rec[s * 4 + 0] = r0;
+      slot_rec[s * 4 + 1] = r1;
+      slot_gid[s] = (uint32_t)i;
+      slot_view[s] = (uint32_t)v;
+      slot_pix[s] = pix;
+      slot_ntiles[s] = tiles;
+      emit_desc[s] = desc;
+      slot_om[s] = 0u;   // no pixel blended yet (the backward's sums set it)
+      // the record's (view, depth) key for the depth sort, from its depth r1.z
+      const uint32_t db = __float_as_uint(r1.z);
+      const uint32_t dmax = P.depth_bits >= 32 ? 0xffffffffu : (1u << P.depth_bits) - 1u;
+      const uint64_t key = ((uint64_t)v << P.depth_bits) | (db > P.depth_lo ? min(db - P.depth_lo, dmax) : 0u);
+      if (P.key32)
+        reinterpret_cast<uint32_t*>(slot_keys)[s] = (uint32_t)key;
+      else
+        reinterpret_cast<uint64_t*>(slot_keys)[s] = key;
+      // the sort's values start as the record indices themselves (its first pass generates them)
+    }
   }
   // colours from the view directions (Gaussian mean minus camera centre), once
   // the projections are done: the SH coefficients are read once and never held
@@ -315,7 +351,7 @@ kgs_status kgs_launch_project(kgs_ctx* ctx, const kgs_gaussians* g, const kgs_ca
   hipLaunchKernelGGL(k_emit<D>, dim3((unsigned)nb), dim3(KGS_BLOCK), 0, st, *g, (const CamDev*)ctx->cams, V, P,   \
                      ctx->vis, (const uint32_t*)ctx->blk_base, nb, (uint64_t)cfg.slot_capacity,                \
                      ctx->slot_rec, ctx->slot_gid, ctx->slot_view, ctx->slot_pix, ctx->slot_ntiles,            \
-                     (void*)ctx->slot_keys[0], ctx->slot_vals[0], ctx->slot_om)
+                     (void*)ctx->slot_keys[0], ctx->slot_om, ctx->emit_desc, kgs_tile_bits(ctx->n_tiles))
     switch (g->sh_degree) {
       case 0: KGS_EMIT(0); break;
       case 1: KGS_EMIT(1); break;

@@ -8,7 +8,9 @@
 //      8 views (the depth bits offset from near), over S records;
 //   2. pairs are emitted in that depth order (a scan of the records' tile
 //      counts gives each record's first pair), one per tile of the record's
-//      rectangle, keyed by (view << tile_bits) | tile;
+//      rectangle, keyed by (view << tile_bits) | tile; the projection left
+//      each record's tile rectangle and count in one 16-byte descriptor, the
+//      only thing these steps gather per record;
 //   3. the pairs are sorted stably by the tile bits only -- 936 tiles per view
 //      at 1242x375 and 32x16 tiles, one 10-bit pass over 4-byte keys and
 //      values.  Emission order is view-major, so every (view, tile) group
@@ -17,8 +19,10 @@
 //      sort by the full key.
 //
 // The radix sort is LSD, reduce-then-scan, with one contiguous partition per
-// block; B key bits take the fewest passes of at most 8 (depth keys) or 10
-// (tile keys) bits, of equal width.  The scatter ranks a tile of
+// block; B key bits take the fewest passes of at most 10 bits, of equal
+// width (three for the 30-bit record keys, one for the tile keys).  The first
+// pass of the record sort takes the records' own indices as its values.  The
+// scatter ranks a tile of
 // 256 x KPT keys in index order (ballot matching inside a wave, running digit
 // counts per wave, a digit-major prefix over the waves), places the tile in
 // LDS in digit order, and writes it out so that consecutive lanes write
@@ -28,6 +32,9 @@
 #include <cstring>
 
 #include "kgs_internal.h"
+
+// widest digit of the record (depth) sort: 30-bit keys take three passes
+#define KGS_DEPTH_DIGIT_BITS 10
 
 // partition of block b of nb: a multiple of 256 keys
 __device__ __forceinline__ void part_range(uint32_t n, uint32_t nb, uint32_t b, uint32_t& lo, uint32_t& hi) {
@@ -142,11 +149,12 @@ __global__ __launch_bounds__(256) void k_radix_scan(uint32_t* __restrict__ hist,
   if (tid == 255) total[d] = off;
 }
 
-// Stable scatter of one block's partition, a tile of 256 x KPT keys at a time.
+// Stable scatter of one block's partition, a tile of 256 x KPT keys at a time
+// (IDV: no values in, the keys' input positions are the values).
 // Wave w ranks keys [w * 64 KPT, (w + 1) * 64 KPT) of the tile in index order.
 // For the block-wide prefixes each thread owns DPT = 2^DB / 256 consecutive
 // digits.
-template <typename K, int KPT, int DB>
+template <typename K, int KPT, int DB, bool IDV>
 __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t* __restrict__ count, const K* __restrict__ kin,
                                                        const uint32_t* __restrict__ vin, int shift, int dbits,
                                                        uint32_t nb, const uint32_t* __restrict__ offsets,
@@ -200,7 +208,7 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t* __restric
       vv[q] = 0;
       if (i < hi) {
         kk[q] = kin[i];
-        vv[q] = vin[i];
+        vv[q] = IDV ? i : vin[i];
       }
     }
 #pragma unroll
@@ -276,28 +284,10 @@ struct EmitSlot {
   uint32_t s, gbase;
   int x0, y0, rw;
 };
-
-__device__ __forceinline__ EmitSlot emit_slot(uint32_t s, const uint32_t* __restrict__ slot_view,
-                                              const int4* __restrict__ slot_pix, int tile_w, int tile_h,
-                                              int tiles_x, int tile_bits) {
-  const int4 pix = slot_pix[s];
-  EmitSlot e;
-  e.s = s;
-  e.x0 = max(floordiv_i(pix.x - pix.z, tile_w), 0);
-  const int x1 = min(floordiv_i(pix.x + pix.z, tile_w) + 1, tiles_x);
-  e.y0 = max(floordiv_i(pix.y - pix.w, tile_h), 0);
-  e.rw = max(x1 - e.x0, 1);
-  e.gbase = slot_view[s] << tile_bits;
-  return e;
-}
-
-// A record's emission descriptor, packed: slot, its view shifted above the
-// tile bits of the pair keys,
-// the first tile column and row of its rectangle (16 bits each) and the
-// rectangle's width in tiles.
-__device__ __forceinline__ uint4 pack_emit(const EmitSlot& e) {
-  return make_uint4(e.s, e.gbase, (uint32_t)e.x0 | ((uint32_t)e.y0 << 16), (uint32_t)e.rw);
-}
+// A record's emission descriptor (emit_rec): its index, its view shifted
+// above the tile bits of the pair keys, the first tile column and row of its
+// rectangle (16 bits each) and the rectangle's width in tiles.  The projection
+// leaves the last three, with the tile count, in emit_desc in record order.
 __device__ __forceinline__ EmitSlot unpack_emit(uint4 q) {
   EmitSlot e;
   e.s = q.x;
@@ -336,13 +326,10 @@ __global__ __launch_bounds__(256) void k_group_sum(const uint32_t* __restrict__ 
 __global__ __launch_bounds__(256) void k_slot_offsets(const uint32_t* __restrict__ counters,
                                                       const uint32_t* __restrict__ perm,
                                                       const uint32_t* __restrict__ part, uint32_t n_groups,
-                                                      const uint32_t* __restrict__ ntiles, uint64_t pair_cap,
+                                                      const uint4* __restrict__ emit_desc, uint64_t pair_cap,
                                                       uint32_t* __restrict__ pref,
                                                       float4* __restrict__ slot_rec,
                                                       uint32_t* __restrict__ chunk_first,
-                                                      const uint32_t* __restrict__ slot_view,
-                                                      const int4* __restrict__ slot_pix, int tile_w, int tile_h,
-                                                      int tiles_x, int tile_bits,
                                                       uint4* __restrict__ emit_rec) {
   const uint32_t n = counters[0];
   const uint32_t l = threadIdx.x & 63;
@@ -351,7 +338,8 @@ __global__ __launch_bounds__(256) void k_slot_offsets(const uint32_t* __restrict
     if (g * 64 >= n) break;
     const uint32_t j = g * 64 + l;
     const uint32_t s = j < n ? perm[j] : 0u;
-    const uint32_t c = j < n ? ntiles[s] : 0u;
+    const uint4 d = j < n ? emit_desc[s] : make_uint4(0u, 0u, 0u, 0u);
+    const uint32_t c = d.w;
     const uint32_t incl = wave_inclusive_scan(c);
     const uint64_t off = min((uint64_t)part[g] + (incl - c), pair_cap);
     if (j < n) {
@@ -361,7 +349,7 @@ __global__ __launch_bounds__(256) void k_slot_offsets(const uint32_t* __restrict
       slot_rec[(size_t)s * 4 + 3] = make_float4(__uint_as_float((uint32_t)off), 0.f, 0.f, 0.f);
       const uint64_t e = min(off + (uint64_t)c, pair_cap);
       for (uint64_t b = (off + EP_CHUNK - 1) / EP_CHUNK; b * EP_CHUNK < e; ++b) chunk_first[b] = j;
-      emit_rec[j] = pack_emit(emit_slot(s, slot_view, slot_pix, tile_w, tile_h, tiles_x, tile_bits));
+      emit_rec[j] = make_uint4(s, d.x, d.y, d.z);
     }
   }
 }
@@ -376,15 +364,13 @@ template <typename K>
 __global__ __launch_bounds__(KGS_BLOCK) void k_slot_keys(const uint32_t* __restrict__ counters,
                                                          const float4* __restrict__ slot_rec,
                                                          const uint32_t* __restrict__ slot_view, uint32_t depth_lo,
-                                                         int depth_bits, K* __restrict__ keys,
-                                                         uint32_t* __restrict__ vals) {
+                                                         int depth_bits, K* __restrict__ keys) {
   const uint32_t n = counters[0];
   const uint32_t dmax = depth_bits >= 32 ? 0xffffffffu : (1u << depth_bits) - 1u;
   for (uint32_t s = blockIdx.x * KGS_BLOCK + threadIdx.x; s < n; s += gridDim.x * KGS_BLOCK) {
     const uint32_t b = __float_as_uint(slot_rec[(size_t)s * 4 + 1].z);
     const uint32_t d = b > depth_lo ? min(b - depth_lo, dmax) : 0u;
     keys[s] = (K)(((uint64_t)slot_view[s] << depth_bits) | d);
-    vals[s] = s;
   }
 }
 
@@ -578,34 +564,47 @@ static void radix_plan(int bits, int max_dbits, int& passes, int& dbits) {
   dbits = (bits + passes - 1) / passes;
 }
 
-template <typename K, int DB>
+// KPT keys per thread in a scatter tile: 16 (8 for 8-byte keys).
+template <typename K, int KPT, int DB, bool AGG>
 static void radix_pass(kgs_ctx* ctx, const uint32_t* count, uint32_t nb, const K* kin, const uint32_t* vin,
                        int shift, int dbits, uint32_t* total, K* kout, uint32_t* vout, hipStream_t st) {
-  constexpr int KPT = sizeof(K) == 8 ? 8 : 16;
-  // the 10-bit passes sort tiles, the 8-bit ones depth keys
-  hipLaunchKernelGGL((k_radix_hist<K, DB, DB == 8>), dim3(nb), dim3(256), 0, st, count, kin, shift, dbits, nb,
+  hipLaunchKernelGGL((k_radix_hist<K, DB, AGG>), dim3(nb), dim3(256), 0, st, count, kin, shift, dbits, nb,
                      ctx->radix_hist);
   hipLaunchKernelGGL(k_radix_scan, dim3(1u << dbits), dim3(256), 0, st, ctx->radix_hist, nb, total);
-  hipLaunchKernelGGL((k_radix_scatter<K, KPT, DB>), dim3(nb), dim3(256), 0, st, count, kin, vin, shift, dbits, nb,
-                     (const uint32_t*)ctx->radix_hist, (const uint32_t*)total, kout, vout);
+  if (vin)
+    hipLaunchKernelGGL((k_radix_scatter<K, KPT, DB, false>), dim3(nb), dim3(256), 0, st, count, kin, vin, shift,
+                       dbits, nb, (const uint32_t*)ctx->radix_hist, (const uint32_t*)total, kout, vout);
+  else
+    hipLaunchKernelGGL((k_radix_scatter<K, KPT, DB, true>), dim3(nb), dim3(256), 0, st, count, kin, vin, shift,
+                       dbits, nb, (const uint32_t*)ctx->radix_hist, (const uint32_t*)total, kout, vout);
 }
 
+// vals_in: the values of the first pass (null: the key positions); agg: the
+// histograms count runs of equal digits (keys whose digits repeat, like the
+// depth keys' views and exponents) rather than single keys.
 template <typename K>
 static int radix_sort(kgs_ctx* ctx, const uint32_t* count, uint64_t cap, K* keys[2], uint32_t* vals[2], int bits,
-                      int max_dbits, hipStream_t st, const uint32_t* vals_in = nullptr) {
+                      int max_dbits, bool agg, hipStream_t st, const uint32_t* vals_in) {
   int passes, dbits;
   radix_plan(bits, max_dbits, passes, dbits);
-  // partitions: fewer for small sorts (a multiple of 256, at most KGS_SORT_BLOCKS)
+  // partitions: fewer for small sorts (a multiple of 256, at most KGS_SORT_BLOCKS): more would only add
+  // histogram rows, the passes of a 2M-record sort being latency bound either way
   const uint32_t nb = cap >= (8u << 20) ? KGS_SORT_BLOCKS : std::min<uint32_t>(512u, KGS_SORT_BLOCKS);
+  constexpr int KPT = sizeof(K) == 8 ? 8 : 16;
   int cur = 0;
   for (int p = 0; p < passes; ++p) {
     const K* kin = keys[cur];
-    const uint32_t* vin = (p == 0 && vals_in) ? vals_in : (const uint32_t*)vals[cur];
+    const uint32_t* vin = p == 0 ? vals_in : (const uint32_t*)vals[cur];
     uint32_t* total = ctx->radix_total + KGS_RADIX_BUCKETS * p;
-    if (dbits > 8)
-      radix_pass<K, 10>(ctx, count, nb, kin, vin, dbits * p, dbits, total, keys[cur ^ 1], vals[cur ^ 1], st);
-    else
-      radix_pass<K, 8>(ctx, count, nb, kin, vin, dbits * p, dbits, total, keys[cur ^ 1], vals[cur ^ 1], st);
+    K* ko = keys[cur ^ 1];
+    uint32_t* vo = vals[cur ^ 1];
+#define KGS_RPASS(DB, AG) radix_pass<K, KPT, DB, AG>(ctx, count, nb, kin, vin, dbits * p, dbits, total, ko, vo, st)
+    if (dbits > 8) {
+      if (agg) KGS_RPASS(10, true); else KGS_RPASS(10, false);
+    } else {
+      if (agg) KGS_RPASS(8, true); else KGS_RPASS(8, false);
+    }
+#undef KGS_RPASS
     cur ^= 1;
   }
   return cur;
@@ -619,10 +618,7 @@ kgs_status kgs_launch_bin_sort(kgs_ctx* ctx, hipStream_t st) {
   // 1. records by (view, depth); the projection wrote the keys, unless a sort
   // since has used them
   const SlotKeyLayout KL = slot_key_layout(ctx->cfg.near_z, ctx->cfg.far_z, V);
-  // tile bits of the pair keys: tiles < 2^tile_bits, so the padding key
-  // (all ones) sorts after every tile of the view
-  ctx->tile_bits = 1;
-  while ((1u << ctx->tile_bits) <= (uint32_t)ctx->n_tiles) ++ctx->tile_bits;
+  ctx->tile_bits = kgs_tile_bits(ctx->n_tiles);
   if (ctx->tile_bits + 7 > 32) return KGS_ERR_INVALID_ARG;  // 64 views above the tile bits, padding apart
   const int key_bits = KL.depth_bits + KL.view_bits;
   int sc;
@@ -631,14 +627,16 @@ kgs_status kgs_launch_bin_sort(kgs_ctx* ctx, hipStream_t st) {
     if (!ctx->slot_keys_ready)
       hipLaunchKernelGGL(k_slot_keys<uint32_t>, dim3(sgrid), dim3(KGS_BLOCK), 0, st, (const uint32_t*)ctx->counters,
                          (const float4*)ctx->slot_rec, (const uint32_t*)ctx->slot_view, KL.depth_lo, KL.depth_bits,
-                         k32[0], ctx->slot_vals[0]);
-    sc = radix_sort<uint32_t>(ctx, ctx->counters, S, k32, ctx->slot_vals, key_bits, 8, st);
+                         k32[0]);
+    sc = radix_sort<uint32_t>(ctx, ctx->counters, S, k32, ctx->slot_vals, key_bits, KGS_DEPTH_DIGIT_BITS, true, st,
+                              nullptr);
   } else {
     if (!ctx->slot_keys_ready)
       hipLaunchKernelGGL(k_slot_keys<uint64_t>, dim3(sgrid), dim3(KGS_BLOCK), 0, st, (const uint32_t*)ctx->counters,
                          (const float4*)ctx->slot_rec, (const uint32_t*)ctx->slot_view, KL.depth_lo, KL.depth_bits,
-                         ctx->slot_keys[0], ctx->slot_vals[0]);
-    sc = radix_sort<uint64_t>(ctx, ctx->counters, S, ctx->slot_keys, ctx->slot_vals, key_bits, 8, st);
+                         ctx->slot_keys[0]);
+    sc = radix_sort<uint64_t>(ctx, ctx->counters, S, ctx->slot_keys, ctx->slot_vals, key_bits, KGS_DEPTH_DIGIT_BITS,
+                              true, st, nullptr);
   }
   ctx->slot_keys_ready = 0;
   const uint32_t* perm = ctx->slot_vals[sc];
@@ -651,9 +649,8 @@ kgs_status kgs_launch_bin_sort(kgs_ctx* ctx, hipStream_t st) {
   kgs_launch_scan(ctx->group_part, ctx->group_part, n_groups, 1, ~0ull, ~0ull, ctx->scan_part, ctx->scan_totals, st);
   uint32_t* pref = reinterpret_cast<uint32_t*>(ctx->slot_keys[sc ^ 1]);  // free after the record sort
   hipLaunchKernelGGL(k_slot_offsets, dim3(eg), dim3(256), 0, st, (const uint32_t*)ctx->counters, perm,
-                     (const uint32_t*)ctx->group_part, n_groups, (const uint32_t*)ctx->slot_ntiles, P, pref,
-                     ctx->slot_rec, ctx->chunk_first, (const uint32_t*)ctx->slot_view, (const int4*)ctx->slot_pix,
-                     ctx->cfg.tile_w, ctx->cfg.tile_h, ctx->tiles_x, ctx->tile_bits, ctx->emit_rec);
+                     (const uint32_t*)ctx->group_part, n_groups, (const uint4*)ctx->emit_desc, P, pref,
+                     ctx->slot_rec, ctx->chunk_first, ctx->emit_rec);
   const uint64_t chunks = (P + EP_CHUNK - 1) / EP_CHUNK;
   const unsigned pg = (unsigned)std::min<uint64_t>(std::max<uint64_t>(chunks, 1), 4096);
   hipLaunchKernelGGL(k_emit_pairs, dim3(pg), dim3(256), 0, st, (const uint32_t*)ctx->counters,
@@ -661,7 +658,7 @@ kgs_status kgs_launch_bin_sort(kgs_ctx* ctx, hipStream_t st) {
                      ctx->tiles_x, ctx->tiles_y, ctx->keys[0], ctx->pair_slot);
   // 3. pairs by tile within the view (stable): the view bits above stay in the
   // keys but out of the sort, so a (view, tile) group stays in emission order
-  const int cur = radix_sort<uint32_t>(ctx, ctx->counters + 1, P, ctx->keys, ctx->vals, ctx->tile_bits, 10, st,
+  const int cur = radix_sort<uint32_t>(ctx, ctx->counters + 1, P, ctx->keys, ctx->vals, ctx->tile_bits, 10, false, st,
                                        ctx->pair_slot);
   ctx->sorted_buf = cur;
   const uint64_t nr = (uint64_t)n_tiles_all * 2;
