@@ -101,13 +101,28 @@ def aggregate(decs) -> torch.Tensor:
     return out
 
 
+def class_metrics(conf: torch.Tensor) -> dict:
+    """Recall, precision and F1 of DENSIFY and PRUNE from a confusion matrix (criterion rows, head columns)."""
+    out = {}
+    for name, k in (("densify", hd.DENSIFY), ("prune", hd.PRUNE)):
+        tp = int(conf[k, k])
+        fn = int(conf[k].sum()) - tp
+        fp = int(conf[:, k].sum()) - tp
+        rec = tp / (tp + fn) if tp + fn else 1.0
+        prec = tp / (tp + fp) if tp + fp else 1.0
+        f1 = 2 * rec * prec / (rec + prec) if rec + prec else 0.0
+        out[name] = {"criterion": tp + fn, "head": tp + fp, "recall": round(rec, 4), "precision": round(prec, 4),
+                     "f1": round(f1, 4)}
+    return out
+
+
 def psnr(a: torch.Tensor, b: torch.Tensor) -> float:
     mse = float(((a.clamp(0, 1) - b.clamp(0, 1)) ** 2).mean().item())
     return 10 * math.log10(1.0 / mse) if mse > 0 else float("inf")
 
 
-def run(n=5_000_000, chunks=32, views=16, cheap=(0, 4, 8, 12), train_chunks=24, steps=1500, batch=65536, lr=3e-3,
-        seed=5, w_prune=1.0) -> dict:
+def collect(n=5_000_000, chunks=32, views=16, cheap=(0, 4, 8, 12), seed=5) -> dict:
+    """Every chunk's criterion decision (all views) and the cheap pass's features, with the time of each."""
     dev = torch.device("cuda")
     t0 = time.time()
     sc = scenes.make_c5(seed=seed, n=n, n_chunks=chunks, views_per_chunk=views)
@@ -123,7 +138,7 @@ def run(n=5_000_000, chunks=32, views=16, cheap=(0, 4, 8, 12), train_chunks=24, 
     run_ = ChunkRunner(R, g.n, views, dev)
     cam_all = device_cameras(sc.cams).view(chunks * views, -1)
     cheap_idx = torch.tensor(cheap, device=dev)
-    feats, labels, dec_crit, targets = [], [], [], []
+    feats, labels, dec_crit, targets, dec_cheap = [], [], [], [], []
     t_crit = t_cheap = 0.0
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
     for c in range(chunks):
@@ -136,6 +151,8 @@ def run(n=5_000_000, chunks=32, views=16, cheap=(0, 4, 8, 12), train_chunks=24, 
         cams2 = cam_all[c * views:(c + 1) * views][cheap_idx].reshape(-1).contiguous()
         st2 = run_.stats(g, cams2, target[cheap_idx].contiguous())
         f = hd.features(R, g, st2, len(cheap))
+        # the plain criterion on the cheap pass's views alone: what the same pass decides without the head
+        dec_cheap.append(chunk_decision(R, st2, len(cheap), g.n, dev))
         ev[2].record()
         torch.cuda.synchronize()
         assert R.status() == 0, f"capacity overflow in chunk {c}"
@@ -144,9 +161,29 @@ def run(n=5_000_000, chunks=32, views=16, cheap=(0, 4, 8, 12), train_chunks=24, 
         feats.append(f)
         labels.append(dec)
         dec_crit.append(dec)
-        if c >= train_chunks:
+        if c >= chunks // 2:
             targets.append(target)
     _log(f"[head] chunks done {time.time() - t0:.1f}s")
+    return dict(n=n, chunks=chunks, views=views, cheap=cheap, seed=seed, dev=dev, sc=sc, g=g, run_=run_,
+                cam_all=cam_all, feats=feats, labels=labels, dec_crit=dec_crit, targets=targets, t_crit=t_crit,
+                t_cheap=t_cheap, dec_cheap=dec_cheap)
+
+
+def run(n=5_000_000, chunks=32, views=16, cheap=(0, 4, 8, 12), train_chunks=24, steps=1500, batch=65536, lr=3e-3,
+        seed=5, w_prune=1.0, w_densify=1.0) -> dict:
+    return evaluate(collect(n, chunks, views, cheap, seed), train_chunks, steps, batch, lr, w_prune, w_densify)
+
+
+def evaluate(d: dict, train_chunks=24, steps=1500, batch=65536, lr=3e-3, w_prune=1.0, w_densify=1.0) -> dict:
+    """Trains a head on the first train_chunks chunks' decisions and judges it on the others
+    (train_chunks >= half the chunks: the held-out chunks' targets are kept for the last half only)."""
+    assert d["chunks"] // 2 <= train_chunks < d["chunks"]
+    n, chunks, views, cheap, seed, dev = d["n"], d["chunks"], d["views"], d["cheap"], d["seed"], d["dev"]
+    sc, g, run_, cam_all = d["sc"], d["g"], d["run_"], d["cam_all"]
+    feats, labels, dec_crit, t_crit, t_cheap = d["feats"], d["labels"], d["dec_crit"], d["t_crit"], d["t_cheap"]
+    dec_cheap = d["dec_cheap"]
+    # the held-out chunks' targets (collected for every chunk from the first held-out one on)
+    targets = d["targets"][train_chunks - chunks:]
 
     # the head decides the Gaussians the cheap pass saw; the others are kept.
     # training set: those Gaussians of the training chunks
@@ -157,9 +194,9 @@ def run(n=5_000_000, chunks=32, views=16, cheap=(0, 4, 8, 12), train_chunks=24, 
         tr_y.append(labels[c][act])
     tr_f = torch.cat(tr_f).contiguous()
     tr_y = torch.cat(tr_y).contiguous()
-    # cross-entropy with an extra weight on the rare PRUNE class (a fully
-    # class-balanced loss trades many wrong prunes for it)
-    cw = torch.tensor([1.0, 1.0, w_prune], device=dev)
+    # cross-entropy with extra weights on the rare classes (a fully class-balanced
+    # loss trades many wrong prunes for them)
+    cw = torch.tensor([1.0, w_densify, w_prune], device=dev)
     head = hd.PruneHead(seed=seed)
     gen = torch.Generator(device=dev).manual_seed(seed)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -184,11 +221,11 @@ def run(n=5_000_000, chunks=32, views=16, cheap=(0, 4, 8, 12), train_chunks=24, 
     torch.cuda.synchronize()
     for c in range(train_chunks, chunks):
         e0.record()
-        _, d = head.forward(feats[c])
+        _, dc = head.forward(feats[c])
         e1.record()
         torch.cuda.synchronize()
         t_head += e0.elapsed_time(e1)
-        pred.append(torch.where(feats[c][:, 15].float() > 0, d, torch.zeros_like(d)))
+        pred.append(torch.where(feats[c][:, 15].float() > 0, dc, torch.zeros_like(dc)))
     test_chunks = chunks - train_chunks
     glob_head = aggregate(pred)
     glob_crit = aggregate(dec_crit[train_chunks:])
@@ -199,6 +236,22 @@ def run(n=5_000_000, chunks=32, views=16, cheap=(0, 4, 8, 12), train_chunks=24, 
     touched = (glob_crit != hd.KEEP) | (glob_head != hd.KEEP)
     agree_all = float((glob_head == glob_crit).float().mean())
     agree_touched = float((glob_head[touched] == glob_crit[touched]).float().mean()) if touched.any() else 1.0
+    per_class = class_metrics(conf)
+
+    def judge(glob):
+        cf = torch.zeros(3, 3, dtype=torch.int64)
+        for i in range(3):
+            for j in range(3):
+                cf[i, j] = int(((glob_crit == i) & (glob == j)).sum().item())
+        tch = (glob_crit != hd.KEEP) | (glob != hd.KEEP)
+        return {"test_global_agreement": round(float((glob == glob_crit).float().mean()), 5),
+                "test_global_agreement_on_touched": round(float((glob[tch] == glob_crit[tch]).float().mean()), 4)
+                if tch.any() else 1.0, "confusion_criterion_rows_cols": cf.tolist(), "per_class": class_metrics(cf)}
+    cheap_crit = judge(aggregate(dec_cheap[train_chunks:]))
+    # the method without the head keeps every Gaussian it has no statistics for; the trivial stand-in for a
+    # head is to keep all of them
+    keep_all = {"test_global_agreement": round(float((glob_crit == hd.KEEP).float().mean()), 5),
+                "test_global_agreement_on_touched": 0.0, "recall": {"densify": 0.0, "prune": 0.0}}
     chunk_agree = float(torch.stack([(p == d).float().mean() for p, d in zip(pred, dec_crit[train_chunks:])]).mean())
 
     # PSNR of the held-out views with the map pruned by either decision
@@ -218,7 +271,7 @@ def run(n=5_000_000, chunks=32, views=16, cheap=(0, 4, 8, 12), train_chunks=24, 
                     f"{sc.width}x{sc.height}; head trained on chunks 0-{train_chunks - 1}, tested on "
                     f"{train_chunks}-{chunks - 1}",
         "map_gaussians": g.n,
-        "class_weights": [1.0, 1.0, w_prune], "cheap_views": list(cheap),
+        "class_weights": [1.0, w_densify, w_prune], "cheap_views": list(cheap),
         "train_samples": int(tr_f.shape[0]), "train_steps": steps, "train_ms": round(train_ms, 2),
         "train_accuracy": round(train_acc, 4),
         "criterion_changes_outside_cheap_footprint": round(unseen, 4),
@@ -226,6 +279,9 @@ def run(n=5_000_000, chunks=32, views=16, cheap=(0, 4, 8, 12), train_chunks=24, 
         "test_global_agreement": round(agree_all, 5),
         "test_global_agreement_on_touched": round(agree_touched, 4),
         "confusion_criterion_rows_head_cols": conf.tolist(),
+        "per_class": per_class,
+        "all_keep_baseline": keep_all,
+        "cheap_views_criterion_baseline": cheap_crit,
         "psnr_db": {"unpruned": round(p_none, 3), "criterion_pruned": round(p_crit, 3),
                     "head_pruned": round(p_head, 3)},
         "psnr_delta_head_minus_criterion_db": round(p_head - p_crit, 3),
@@ -249,9 +305,10 @@ def main():
     ap.add_argument("--train-chunks", type=int, default=24)
     ap.add_argument("--steps", type=int, default=1500)
     ap.add_argument("--w-prune", type=float, default=1.0)
+    ap.add_argument("--w-densify", type=float, default=1.0)
     args = ap.parse_args()
     out = run(n=args.n, chunks=args.chunks, views=args.views, train_chunks=args.train_chunks, steps=args.steps,
-              w_prune=args.w_prune)
+              w_prune=args.w_prune, w_densify=args.w_densify)
     print(json.dumps(out), flush=True)
 
 

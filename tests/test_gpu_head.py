@@ -25,20 +25,28 @@ def _data(n, seed):
     return xb, theta.astype(np.float32), y
 
 
-def _ambiguous(x, theta):
-    """Gaussians where FP32 accumulation could move a hidden value across a
-    BF16 rounding boundary or across zero (the oracle computes in FP64).  The
-    products of BF16 operands are exact in FP32; the bound allows eight FP32
-    roundings of the sum of their magnitudes."""
+ACC = 8 * 2.0 ** -24    # eight FP32 roundings of a sum, relative to the sum of the magnitudes it adds
+
+
+def _logit_bound(x, theta):
+    """Per Gaussian and logit, how far the GPU's logits may lie from the FP64 oracle's.  The products of BF16
+    operands are exact in FP32 and each sum may be off by ACC times the sum of the magnitudes it adds; a hidden
+    unit whose interval of possible sums holds a BF16 rounding boundary (or zero) may round to the neighbouring
+    BF16 value, one BF16 unit away, and that difference is carried through the next layers' magnitudes.  Also
+    returns which Gaussians have such a unit."""
     f = mlp.forward(x, theta.astype(np.float64), True)
-    p = mlp.unpack(theta.astype(np.float64))
+    b = mlp.unpack(theta.astype(np.float64))
+    d_in = np.zeros_like(f["x"])                 # the inputs are the kernels' BF16 features, exactly
     amb = np.zeros(x.shape[0], bool)
-    for z, W, h in ((f["z1"], f["W1"], f["x"]), (f["z2"], f["W2"], f["h1"])):
-        e = 8 * 2.0 ** -24 * (np.abs(h) @ np.abs(W).T + 1e-30)
-        zp = np.maximum(z + e, 0.0)
-        zm = np.maximum(z - e, 0.0)
-        amb |= (mlp.bf16_bits(zp) != mlp.bf16_bits(zm)).any(axis=1)
-    return amb, f
+    for z, W, bias, h_in in ((f["z1"], f["W1"], b["b1"], f["x"]), (f["z2"], f["W2"], b["b2"], f["h1"])):
+        dz = d_in @ np.abs(W).T + ACC * (np.abs(h_in) @ np.abs(W).T + np.abs(bias) + 1e-30)
+        lo, hi = np.maximum(z - dz, 0.0), np.maximum(z + dz, 0.0)
+        flips = mlp.bf16_bits(lo) != mlp.bf16_bits(hi)
+        amb |= flips.any(axis=1)
+        # a flip moves the BF16 value by at most the gap between the two roundings of the interval's ends
+        d_in = np.abs(mlp.bf16(hi) - mlp.bf16(lo))
+    bound = d_in @ np.abs(f["W3"]).T + ACC * (np.abs(f["h2"]) @ np.abs(f["W3"]).T + np.abs(b["b3"]) + 1e-30)
+    return bound, amb, f
 
 
 def test_head_forward_matches_oracle():
@@ -49,19 +57,23 @@ def test_head_forward_matches_oracle():
     lg, dec = h.forward(feats)
     torch.cuda.synchronize()
     lg = lg.cpu().numpy().astype(np.float64)
-    amb, f = _ambiguous(x, theta)
+    bound, amb, f = _logit_bound(x, theta)
     ref = f["logits"]
-    scale = np.abs(f["h2"]) @ np.abs(f["W3"]).T + 1.0
-    err = np.abs(lg - ref) / scale
-    say(f"[gpu] head forward: ambiguous {amb.sum()}/{n}, max rel err (clear) {err[~amb].max():.2e}")
-    assert amb.mean() < 0.35
-    assert err[~amb].max() < 1e-5
-    # decisions: argmax of the GPU logits, equal to the oracle's where the top two are apart
+    err = np.abs(lg - ref)
+    say(f"[gpu] head forward: Gaussians with a unit at a BF16 boundary {amb.sum()}/{n}; "
+        f"max err / bound {np.max(err / bound):.3f}; max err elsewhere {err[~amb].max():.2e}")
+    # every Gaussian, every logit: within the propagated rounding bound
+    assert (err <= bound).all(), np.flatnonzero((err > bound).any(axis=1))[:8]
+    # decisions: the argmax of the GPU logits, and the oracle's wherever the top two are further apart than the
+    # bounds of both
     d = dec.cpu().numpy()
     assert np.array_equal(d, np.argmax(lg, axis=1))
-    srt = np.sort(ref, axis=1)
-    clear = ~amb & (srt[:, 2] - srt[:, 1] > 1e-4 * scale.max(axis=1))
-    assert np.array_equal(d[clear], np.argmax(ref, axis=1)[clear])
+    top = np.argsort(ref, axis=1)
+    r = np.arange(n)
+    clear = ref[r, top[:, 2]] - ref[r, top[:, 1]] > bound[r, top[:, 2]] + bound[r, top[:, 1]]
+    say(f"  decisions compared {int(clear.sum())}/{n}")
+    assert clear.mean() > 0.99
+    assert np.array_equal(d[clear], top[clear, 2])
 
 
 def test_head_forward_ragged_and_empty():
@@ -92,7 +104,7 @@ def test_head_gradient_matches_oracle():
                          ("W3", 5248, 5440), ("b3", 5440, 5443)):
         rel = np.linalg.norm(g[lo:hi] - ref_g[lo:hi]) / np.linalg.norm(ref_g[lo:hi])
         say(f"  {name}: rel {rel:.2e}")
-        assert rel < 2e-3, name
+        assert rel < 1e-3, name
     # deterministic: a second call gives the same bits
     g2 = h.loss_grad(feats, torch.from_numpy(y).cuda(), torch.from_numpy(cw).cuda())[1].clone()
     assert torch.equal(g2, grad)
@@ -183,17 +195,32 @@ def test_feature_kernel_matches_host_formulas():
 
 
 def test_head_gain_over_the_plain_criterion():
-    """Trained by the library's kernels on the criterion's decisions of the
-    first chunks, the head decides the held-out chunks from a cheap pass over a
-    quarter of their views: it must agree with the criterion on nearly every
-    Gaussian while taking a fraction of the criterion's time."""
+    """Trained by the library's kernels on the criterion's decisions of the first chunks (all 16 views), the
+    head decides the held-out chunks from a cheap pass over 4 of their views.  Judged per class against the
+    full criterion, beside the two ways to decide without it: keep everything, or apply the plain criterion
+    to the same cheap pass.  The bars sit below what this configuration measures (densify recall 0.63,
+    precision 0.54, F1 0.58 against 0.45 for the criterion on the cheap views; agreement on the Gaussians
+    either side changes 0.41 against 0.29)."""
     from paper_2606_30436_amd import head_experiment as hx
-    r = hx.run(n=1_000_000, chunks=8, views=16, train_chunks=6, steps=800)
-    say(f"[gpu] head gain: agreement {r['test_global_agreement']}, speedup {r['decision_speedup']}, "
-        f"psnr {r['psnr_db']}, ms {r['ms_per_chunk']}")
+    r = hx.run(n=1_000_000, chunks=8, views=16, train_chunks=6, steps=800, w_densify=3.0)
+    pc, cb, ka = r["per_class"], r["cheap_views_criterion_baseline"], r["all_keep_baseline"]
+    say(f"[gpu] head gain: agreement {r['test_global_agreement']} (keep-all {ka['test_global_agreement']}, "
+        f"cheap criterion {cb['test_global_agreement']}), on touched {r['test_global_agreement_on_touched']} "
+        f"(cheap criterion {cb['test_global_agreement_on_touched']}); densify {pc['densify']} vs "
+        f"{cb['per_class']['densify']}; prune {pc['prune']}; confusion {r['confusion_criterion_rows_head_cols']}; "
+        f"psnr {r['psnr_db']}; speedup {r['decision_speedup']}")
+    conf = np.array(r["confusion_criterion_rows_head_cols"])
+    assert conf.sum() == r["map_gaussians"]
+    assert conf[hd.DENSIFY].sum() == pc["densify"]["criterion"] and conf[:, hd.DENSIFY].sum() == pc["densify"]["head"]
+    # densify: the head finds most of the criterion's densifications and most of its own are right
+    assert pc["densify"]["recall"] > 0.5 and pc["densify"]["precision"] > 0.45
+    # better than deciding from the same cheap pass without it, and than keeping everything
+    assert pc["densify"]["f1"] > cb["per_class"]["densify"]["f1"] + 0.05
+    assert r["test_global_agreement_on_touched"] > cb["test_global_agreement_on_touched"] + 0.05
+    assert r["test_global_agreement_on_touched"] > ka["test_global_agreement_on_touched"] + 0.3
+    assert r["test_global_agreement"] > ka["test_global_agreement"]
+    # pruning with the head costs no image quality against the unpruned map
+    assert r["psnr_db"]["head_pruned"] >= r["psnr_db"]["unpruned"] - 0.05
     assert r["train_accuracy"] > 0.85
-    assert r["test_global_agreement"] > 0.95
-    # the criterion's own pass (the compositing backward over every view) is what
-    # the head saves; 2.0x at this size now that the backward takes two pixels
-    # per lane, so the bound leaves room for timing noise
+    # the criterion's own pass (the compositing backward over every view) is what the head saves
     assert r["decision_speedup"] > 1.5
