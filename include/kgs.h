@@ -476,13 +476,14 @@ kgs_status kgs_anchor_stats(kgs_ctx* ctx, const kgs_image* fwd, const uint32_t* 
  * per-view footprint statistics (appendix, densification and pruning
  * scores: Omega_v(i), M_v, kappa_v(i), gamma_v(i) = L_v |Omega_v(i)|).
  * dl_dcolor [V][3][H][W] (required), dl_ddepth [V][H][W] (or NULL),
- * dl_dalpha [V][H][W] (or NULL) for the opacity image 1 - t_final;
+ * dl_dtfinal [V][H][W] (or NULL): the gradient with respect to the final
+ * transmittance t_final (the opacity image is 1 - t_final);
  * target [V][3][H][W] or NULL (then kappa is not counted); view_loss [V] or
  * NULL (then gamma is not accumulated).  g, cams and pose_xi must be those of
  * the matching kgs_project.  grads and stats are ADDED to. */
 kgs_status kgs_render_bwd(kgs_ctx* ctx, const kgs_gaussians* g, const kgs_camera* cams, int32_t n_views,
                           const float* pose_xi, const kgs_image* fwd, const float* dl_dcolor,
-                          const float* dl_ddepth, const float* dl_dalpha, const float* target, float tau_err,
+                          const float* dl_ddepth, const float* dl_dtfinal, const float* target, float tau_err,
                           const float* view_loss, const kgs_grads* grads, const kgs_view_stats* stats,
                           void* stream);
 
@@ -493,7 +494,7 @@ kgs_status kgs_render_bwd(kgs_ctx* ctx, const kgs_gaussians* g, const kgs_camera
  * views, the chain rule to the parameters and the pose, and the statistics.
  * Called in this order they equal kgs_render_bwd. */
 kgs_status kgs_render_bwd_pixels(kgs_ctx* ctx, const kgs_image* fwd, const float* dl_dcolor, const float* dl_ddepth,
-                                 const float* dl_dalpha, const float* target, float tau_err, void* stream);
+                                 const float* dl_dtfinal, const float* target, float tau_err, void* stream);
 kgs_status kgs_project_bwd(kgs_ctx* ctx, const kgs_gaussians* g, const kgs_camera* cams, int32_t n_views,
                            const float* pose_xi, const float* view_loss, const kgs_grads* grads,
                            const kgs_view_stats* stats, void* stream);

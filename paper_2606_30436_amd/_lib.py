@@ -357,19 +357,19 @@ def kgs_map_revoxelize(means, level, n, table, log2_capacity, keep, anchor, n_ke
                                     stream_handle(stream)), "kgs_map_revoxelize")
 
 
-def kgs_render_bwd(ctx, g: KgsGaussians, cams, n_views, pose_xi, img: KgsImage, dl_dcolor, dl_ddepth, dl_dalpha,
+def kgs_render_bwd(ctx, g: KgsGaussians, cams, n_views, pose_xi, img: KgsImage, dl_dcolor, dl_ddepth, dl_dtfinal,
                    target, tau_err, view_loss, grads: KgsGrads, stats: KgsViewStats | None, stream=None):
     check(load().kgs_render_bwd(ctypes.c_void_p(ctx), ctypes.byref(g), ptr(cams), n_views, ptr(pose_xi),
-                                ctypes.byref(img), ptr(dl_dcolor), ptr(dl_ddepth), ptr(dl_dalpha), ptr(target),
+                                ctypes.byref(img), ptr(dl_dcolor), ptr(dl_ddepth), ptr(dl_dtfinal), ptr(target),
                                 float(tau_err),
                                 ptr(view_loss), ctypes.byref(grads),
                                 ctypes.byref(stats) if stats is not None else None, stream_handle(stream)),
           "kgs_render_bwd")
 
 
-def kgs_render_bwd_pixels(ctx, img: KgsImage, dl_dcolor, dl_ddepth, dl_dalpha, target, tau_err, stream=None):
+def kgs_render_bwd_pixels(ctx, img: KgsImage, dl_dcolor, dl_ddepth, dl_dtfinal, target, tau_err, stream=None):
     check(load().kgs_render_bwd_pixels(ctypes.c_void_p(ctx), ctypes.byref(img), ptr(dl_dcolor), ptr(dl_ddepth),
-                                       ptr(dl_dalpha), ptr(target), float(tau_err), stream_handle(stream)),
+                                       ptr(dl_dtfinal), ptr(target), float(tau_err), stream_handle(stream)),
           "kgs_render_bwd_pixels")
 
 

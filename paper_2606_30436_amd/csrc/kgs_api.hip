@@ -427,23 +427,23 @@ kgs_status kgs_anchor_stats(kgs_ctx* ctx, const kgs_image* fwd, const uint32_t* 
 
 kgs_status kgs_render_bwd(kgs_ctx* ctx, const kgs_gaussians* g, const kgs_camera* cams, int32_t n_views,
                           const float* pose_xi, const kgs_image* fwd, const float* dl_dcolor, const float* dl_ddepth,
-                          const float* dl_dalpha, const float* target, float tau_err, const float* view_loss,
+                          const float* dl_dtfinal, const float* target, float tau_err, const float* view_loss,
                           const kgs_grads* grads,
                           const kgs_view_stats* stats, void* stream) {
   if (!ctx || !gaussians_ok(ctx, g) || !cams || !image_ok(fwd) || !dl_dcolor || !grads) return KGS_ERR_INVALID_ARG;
   if (!ctx->binned) return KGS_ERR_STATE;
   if (n_views != ctx->last_views || g->n != ctx->last_n || g->sh_degree != ctx->last_degree) return KGS_ERR_STATE;
   hipStream_t st = (hipStream_t)stream;
-  kgs_status s = kgs_launch_render_bwd(ctx, fwd, dl_dcolor, dl_ddepth, dl_dalpha, target, tau_err, st);
+  kgs_status s = kgs_launch_render_bwd(ctx, fwd, dl_dcolor, dl_ddepth, dl_dtfinal, target, tau_err, st);
   if (s != KGS_OK) return s;
   return kgs_launch_project_bwd(ctx, g, cams, n_views, pose_xi, view_loss, grads, stats, st);
 }
 
 kgs_status kgs_render_bwd_pixels(kgs_ctx* ctx, const kgs_image* fwd, const float* dl_dcolor, const float* dl_ddepth,
-                                 const float* dl_dalpha, const float* target, float tau_err, void* stream) {
+                                 const float* dl_dtfinal, const float* target, float tau_err, void* stream) {
   if (!ctx || !image_ok(fwd) || !dl_dcolor) return KGS_ERR_INVALID_ARG;
   if (!ctx->binned) return KGS_ERR_STATE;
-  return kgs_launch_render_bwd(ctx, fwd, dl_dcolor, dl_ddepth, dl_dalpha, target, tau_err, (hipStream_t)stream);
+  return kgs_launch_render_bwd(ctx, fwd, dl_dcolor, dl_ddepth, dl_dtfinal, target, tau_err, (hipStream_t)stream);
 }
 
 kgs_status kgs_project_bwd(kgs_ctx* ctx, const kgs_gaussians* g, const kgs_camera* cams, int32_t n_views,

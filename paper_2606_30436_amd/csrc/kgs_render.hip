@@ -414,7 +414,7 @@ __global__ __launch_bounds__(64 * NW) void k_render_bwd(
     const uint32_t* __restrict__ sorted_slot,
     const float4* __restrict__ slot_rec, const float* __restrict__ color,
     const float* __restrict__ depth, const float* __restrict__ tfinal, const int32_t* __restrict__ last,
-    const float* __restrict__ dl_dcolor, const float* __restrict__ dl_ddepth, const float* __restrict__ dl_dalpha,
+    const float* __restrict__ dl_dcolor, const float* __restrict__ dl_ddepth, const float* __restrict__ dl_dtfinal,
     const float* __restrict__ target, float tau_err, float4* __restrict__ pair_grad,
     uint8_t* __restrict__ pair_live, int fuse_l1,
     float* __restrict__ dl_out, double* __restrict__ loss_partial) {
@@ -484,8 +484,8 @@ __global__ __launch_bounds__(64 * NW) void k_render_bwd(
         g2[p] = dl_dcolor[cpix + 2 * npix];
       }
       if (dl_ddepth) gD[p] = dl_ddepth[pix];
-      // opacity image A = 1 - T_final: dA/dalpha_j = T_final / (1 - alpha_j)
-      if (dl_dalpha) gAT = dl_dalpha[pix] * tfinal[pix];
+      // the final transmittance: dT_final/dalpha_j = -T_final / (1 - alpha_j)
+      if (dl_dtfinal) gAT = -dl_dtfinal[pix] * tfinal[pix];
       if (target) {
         const float err = fabsf(target[cpix] - Co0) + fabsf(target[cpix + npix] - Co1) +
                           fabsf(target[cpix + 2 * npix] - Co2);
@@ -742,7 +742,7 @@ __global__ __launch_bounds__(256) void k_clear_live(const uint32_t* __restrict__
 // here (and written to dl_dcolor if it is not null) together with the loss
 // partials; kgs_launch_loss_final then gives the per-view losses.
 kgs_status kgs_launch_render_bwd(kgs_ctx* ctx, const kgs_image* fwd, const float* dl_dcolor, const float* dl_ddepth,
-                                 const float* dl_dalpha, const float* target, float tau_err, hipStream_t st,
+                                 const float* dl_dtfinal, const float* target, float tau_err, hipStream_t st,
                                  bool fuse_l1, float* dl_out) {
   const RenderParams P = render_params(ctx);
   const unsigned grid = (unsigned)(ctx->last_views * ctx->n_tiles);
@@ -757,7 +757,7 @@ kgs_status kgs_launch_render_bwd(kgs_ctx* ctx, const kgs_image* fwd, const float
                      (const uint32_t*)ctx->sorted_slot,                                                           \
                      (const float4*)ctx->slot_rec,                                                                \
                      (const float*)fwd->color, (const float*)fwd->depth, (const float*)fwd->t_final,              \
-                     (const int32_t*)fwd->last, dl_dcolor, dl_ddepth, dl_dalpha, target, tau_err, ctx->pair_grad,  \
+                     (const int32_t*)fwd->last, dl_dcolor, dl_ddepth, dl_dtfinal, target, tau_err, ctx->pair_grad,  \
                      ctx->pair_live, fuse_l1 ? 1 : 0, dl_out, ctx->loss_partial)
   // two pixels per lane (a wave per 16x8 block) where the tile is at least 16
   // wide and, unless the configuration asks for it, the launch still has

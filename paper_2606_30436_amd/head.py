@@ -32,12 +32,6 @@ def he_init(seed: int) -> np.ndarray:
     return np.concatenate(parts).astype(np.float32)
 
 
-def balanced_class_weights(labels: torch.Tensor) -> torch.Tensor:
-    cnt = torch.bincount(labels.to(torch.int64), minlength=3).double()
-    w = torch.where(cnt > 0, cnt.sum() / (3.0 * cnt.clamp_min(1)), torch.zeros_like(cnt))
-    return w.float()
-
-
 def features(R: Rasterizer, g: GaussianParams, stats: ViewStats, n_views: int,
              before: Optional[LifecycleState] = None, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
     """[N][16] BF16 features of every Gaussian from a chunk's statistics."""

@@ -2,7 +2,8 @@
 
 render(params, cams, pose_xi, rasterizer) returns colour [V,3,H,W], depth
 [V,H,W] (sum_j T_j alpha_j z_j, the appendix's depth volume rendering) and the
-opacity image 1 - T_final [V,H,W]; backward gives gradients for the Gaussian
+final transmittance T_final [V,H,W] (the opacity image is 1 - T_final); backward
+gives gradients for the Gaussian
 means, log-scales, quaternions, opacity logits, SH coefficients and the 6-DoF
 pose tangent of every view.  Nothing per pixel is kept between the passes
 but the final transmittance and the last blended position: the backward
@@ -42,10 +43,10 @@ class KgsRasterFn(torch.autograd.Function):
         ctx.generation = R.generation
         ctx.recompute = recompute
         ctx.has_pose = pose_xi is not None
-        return img.color, img.depth, 1.0 - img.t_final
+        return img.color, img.depth, img.t_final
 
     @staticmethod
-    def backward(ctx, g_color, g_depth, g_alpha):
+    def backward(ctx, g_color, g_depth, g_tfinal):
         R, g, xi, cams, img = ctx.R, ctx.g, ctx.xi, ctx.cams, ctx.img
         if ctx.recompute or R.generation != ctx.generation:
             R.project(g, cams, xi)
@@ -55,8 +56,8 @@ class KgsRasterFn(torch.autograd.Function):
         pose_grad = torch.zeros(V, 6, device=g.means.device) if ctx.has_pose else None
         gc = g_color.contiguous() if g_color is not None else torch.zeros_like(img.color)
         gd = g_depth.contiguous() if g_depth is not None else None
-        ga = g_alpha.contiguous() if g_alpha is not None else None
-        R.render_bwd(g, cams, xi, img, gc, gd, grads=grads, pose_grad=pose_grad, dl_dalpha=ga)
+        gt = g_tfinal.contiguous() if g_tfinal is not None else None
+        R.render_bwd(g, cams, xi, img, gc, gd, grads=grads, pose_grad=pose_grad, dl_dtfinal=gt)
         return (grads.means, grads.log_scales, grads.quats, grads.logits, grads.sh, pose_grad, None, None, None, None)
 
 

@@ -209,14 +209,14 @@ class Rasterizer:
 
     def render_bwd(self, g: GaussianParams, cams, pose_xi, img: Image, dl_dcolor, dl_ddepth=None, target=None,
                    tau_err=0.1, view_loss=None, grads: Optional[GaussianParams] = None, pose_grad=None,
-                   stats: Optional[ViewStats] = None, stream=None, dl_dalpha=None):
+                   stats: Optional[ViewStats] = None, stream=None, dl_dtfinal=None):
         V = cams.numel() // CAMERA_DTYPE.itemsize
-        L.kgs_render_bwd(self.ctx, g.c(), cams, V, pose_xi, img.c(), dl_dcolor, dl_ddepth, dl_dalpha, target, tau_err,
+        L.kgs_render_bwd(self.ctx, g.c(), cams, V, pose_xi, img.c(), dl_dcolor, dl_ddepth, dl_dtfinal, target, tau_err,
                          view_loss, grads_c(grads, pose_grad), stats.c() if stats is not None else None, stream)
 
     def render_bwd_pixels(self, img: Image, dl_dcolor, dl_ddepth=None, target=None, tau_err=0.1, stream=None,
-                          dl_dalpha=None):
-        L.kgs_render_bwd_pixels(self.ctx, img.c(), dl_dcolor, dl_ddepth, dl_dalpha, target, tau_err, stream)
+                          dl_dtfinal=None):
+        L.kgs_render_bwd_pixels(self.ctx, img.c(), dl_dcolor, dl_ddepth, dl_dtfinal, target, tau_err, stream)
 
     def project_bwd(self, g: GaussianParams, cams, pose_xi, view_loss=None, grads: Optional[GaussianParams] = None,
                     pose_grad=None, stats: Optional[ViewStats] = None, stream=None):

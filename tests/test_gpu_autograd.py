@@ -32,13 +32,13 @@ def test_autograd_matches_fp64_tile_free_autograd(seed, bg):
     P = _params(sc)
     xi = torch.from_numpy(sc.pose_xi).cuda().requires_grad_(True)
     cams = device_cameras(sc.cams)
-    C, D, A = render(P, cams, xi, R, sc.sh_degree)
+    C, D, Tf = render(P, cams, xi, R, sc.sh_degree)
     rng = np.random.default_rng(seed)
     wC = rng.normal(size=C.shape)
     wD = rng.normal(size=D.shape) * 0.05
-    wA = rng.normal(size=A.shape)
+    wT = rng.normal(size=Tf.shape)
     L = (C * torch.from_numpy(wC).float().cuda()).sum() + (D * torch.from_numpy(wD).float().cuda()).sum() + \
-        (A * torch.from_numpy(wA).float().cuda()).sum()
+        (Tf * torch.from_numpy(wT).float().cuda()).sum()
     L.backward()
     cfg = OracleConfig(bg=bg)
     ref = {k: torch.tensor(getattr(sc, k).astype(np.float64), requires_grad=True)
@@ -48,7 +48,9 @@ def test_autograd_matches_fp64_tile_free_autograd(seed, bg):
     for v in range(2):
         Cr, Dr, Ar = brute.render(ref, sc.cams[v], sc.sh_degree, cfg, xr[v])
         assert np.abs(Cr.detach().numpy() - C[v].detach().cpu().numpy()).max() < 2e-3
-        Lr = Lr + (Cr * torch.tensor(wC[v])).sum() + (Dr * torch.tensor(wD[v])).sum() + (Ar * torch.tensor(wA[v])).sum()
+        # the tile-free reference gives the opacity image A = 1 - T_final
+        Lr = Lr + (Cr * torch.tensor(wC[v])).sum() + (Dr * torch.tensor(wD[v])).sum() + \
+            ((1.0 - Ar) * torch.tensor(wT[v])).sum()
     Lr.backward()
     for k in ref:
         got = P[k].grad.detach().cpu().numpy().astype(np.float64)
@@ -70,8 +72,8 @@ def test_recompute_in_backward_equals_stored_lists():
     for recompute in (True, False):
         P = _params(sc)
         xi = torch.from_numpy(sc.pose_xi).cuda().requires_grad_(True)
-        C, D, A = render(P, cams, xi, R, sc.sh_degree, recompute=recompute)
-        (C.square().sum() + 0.01 * D.sum() + A.sum()).backward()
+        C, D, Tf = render(P, cams, xi, R, sc.sh_degree, recompute=recompute)
+        (C.square().sum() + 0.01 * D.sum() + Tf.sum()).backward()
         grads.append([P[k].grad.clone() for k in P] + [xi.grad.clone()])
     for a, b in zip(*grads):
         assert torch.equal(a, b)

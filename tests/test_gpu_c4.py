@@ -134,7 +134,7 @@ def test_c4_full_chunk(c4):
     rng = np.random.default_rng(44)
     wC = rng.normal(size=(V, 3, sc.height, sc.width)).astype(np.float32) * np.float32(1e-3)
     wD = rng.normal(size=(V, sc.height, sc.width)).astype(np.float32) * np.float32(1e-5)
-    C, D, A = render(P, cams, xi, R, 3)
+    C, D, _ = render(P, cams, xi, R, 3)
     ((C * torch.from_numpy(wC).cuda()).sum() + (D * torch.from_numpy(wD).cuda()).sum()).backward()
     torch.cuda.synchronize()
     assert R.status() == 0

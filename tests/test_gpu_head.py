@@ -136,7 +136,7 @@ def test_head_training_reduces_the_loss_and_learns_a_threshold_rule():
     y = np.where(x[:, 2] > 0.8, 2, np.where(x[:, 0] > 5, 1, 0)).astype(np.uint8)
     feats = torch.from_numpy(mlp.bf16(x).astype(np.float32)).to(torch.bfloat16).cuda()
     lab = torch.from_numpy(y).cuda()
-    cw = hd.balanced_class_weights(lab)
+    cw = torch.from_numpy(mlp.class_weights(y)).float().cuda()   # balanced weights, computed by the oracle
     h = hd.PruneHead(seed=7)
     first = None
     for it in range(400):
