@@ -85,6 +85,7 @@ struct DecodeLds {
   float b1[AD_HID];
   float b2[AD_OUTPAD];
   float out[4][16][AD_LDO];           // per-wave output tile, anchor-major
+  float anc[4][16][10];               // per wave and anchor: p, log l, l (3 each), band flag
 };
 
 __global__ __launch_bounds__(256) void k_anchor_decode(DecodeParams P, const float* __restrict__ theta,
@@ -125,6 +126,20 @@ __global__ __launch_bounds__(256) void k_anchor_decode(DecodeParams P, const flo
       d = sqrt(e0 * e0 + e1 * e1 + e2 * e2);
       if (b == 0) x2 = ad_pack4((float)(e0 / d), (float)(e1 / d), (float)(e2 / d), (float)d);
     }
+    // what the children of anchor a share, once per anchor: position, local scale and the band test
+    if (b == 0) {
+      float* q = s.anc[w][a];
+      const int lev = ok ? A.level[g] : -1;
+      const bool in_band = ok && lev >= 0 && lev < 5 && d >= P.dmin[lev] && d < P.dmax[lev];
+#pragma unroll
+      for (int dim = 0; dim < 3; ++dim) {
+        const float ll = ok ? A.log_l[dim * n + g] : 0.f;
+        q[dim] = ok ? A.p[dim * n + g] : 0.f;
+        q[3 + dim] = ll;
+        q[6 + dim] = expf(ll);
+      }
+      q[9] = in_band ? 1.f : 0.f;
+    }
     bf16x4_t h[2];
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
@@ -151,21 +166,17 @@ __global__ __launch_bounds__(256) void k_anchor_decode(DecodeParams P, const flo
       const int64_t j = ga * K + k;
       if (j >= N) continue;
       const float* y = &s.out[w][aa][AD_OUT * k];
-      const double e0 = (double)A.p[ga] - P.cx, e1 = (double)A.p[n + ga] - P.cy, e2 = (double)A.p[2 * n + ga] - P.cz;
-      const double dd = sqrt(e0 * e0 + e1 * e1 + e2 * e2);
-      const int lev = A.level[ga];
-      const bool in_band = lev >= 0 && lev < 5 && dd >= P.dmin[lev] && dd < P.dmax[lev];
-      G.opacity_logits[j] = in_band && y[0] > 0.f ? tanh_logit(y[0]) : -100.0f;
+      const float* q = s.anc[w][aa];
+      G.opacity_logits[j] = q[9] != 0.f && y[0] > 0.f ? tanh_logit(y[0]) : -100.0f;
       for (int ch = 0; ch < 3; ++ch) {
         const float col = 1.0f / (1.0f + expf(-y[1 + ch]));
         G.sh[(int64_t)ch * N + j] = (col - 0.5f) / 0.28209479177387814f;
       }
       for (int q = 0; q < 4; ++q) G.quats[(int64_t)q * N + j] = y[4 + q];
       for (int dim = 0; dim < 3; ++dim) {
-        const float ll = A.log_l[dim * n + ga], lv = expf(ll);
-        G.log_scales[(int64_t)dim * N + j] = ll + log_sigmoid(y[8 + dim]);
+        G.log_scales[(int64_t)dim * N + j] = q[3 + dim] + log_sigmoid(y[8 + dim]);
         const float off = A.offsets[((int64_t)k * 3 + dim) * n + ga] + y[11 + dim];
-        G.means[(int64_t)dim * N + j] = A.p[dim * n + ga] + off * lv;
+        G.means[(int64_t)dim * N + j] = q[dim] + off * q[6 + dim];
       }
     }
     __builtin_amdgcn_wave_barrier();
@@ -386,7 +397,8 @@ kgs_status kgs_launch_anchor_decode(const kgs_anchors* a, const float* theta, co
   P.K = a->k;
   if (a->n == 0) return KGS_OK;
   const int64_t tiles = (a->n + 15) / 16;
-  const unsigned grid = (unsigned)std::min<int64_t>((tiles + 3) / 4, 4096);
+  // each block stages the weights once; a few blocks per CU, each wave looping over tiles of 16 anchors
+  const unsigned grid = (unsigned)std::min<int64_t>((tiles + 3) / 4, 1024);
   hipLaunchKernelGGL(k_anchor_decode, dim3(grid), dim3(256), 0, st, P, theta, *a, *out);
   return kgs_check_launch();
 }
