@@ -17,7 +17,9 @@
 // first filters x, y and their products and writes the three derivative maps,
 // the second filters those and forms the gradient.  Each is a 32x16 output tile
 // per (view, channel) with a 5-pixel halo staged in LDS, the separable window
-// run along rows, then columns.  Bound: plain FP32 ALU (about 400 flop per
+// run along rows (a thread takes four neighbouring outputs of a row from its 14
+// inputs, read once into registers), then columns (two neighbouring rows per
+// thread), so each LDS value read serves several taps.  Bound: plain FP32 ALU (about 400 flop per
 // pixel and channel against 44 bytes of HBM traffic).
 #include <cmath>
 
@@ -85,42 +87,62 @@ __global__ __launch_bounds__(256) void k_ssim_fwd(MapLossParams P, const float* 
     sy[r][c] = b;
   }
   __syncthreads();
-  // rows: the five products filtered along x for every halo row
-  for (int i = threadIdx.x; i < ML_RH * ML_TW; i += 256) {
-    const int r = i / ML_TW, c = i - r * ML_TW;
-    float ax = 0.f, ay = 0.f, axx = 0.f, ayy = 0.f, axy = 0.f;
+  // rows: the five products filtered along x for every halo row; a thread
+  // takes four neighbouring outputs of a row, reading its 14 inputs once
+  if (threadIdx.x < ML_RH * (ML_TW / 4)) {
+    const int r = threadIdx.x / (ML_TW / 4), c0 = 4 * (threadIdx.x - r * (ML_TW / 4));
+    float a[14], b[14], aa[14], bb[14], ab[14];
 #pragma unroll
-    for (int k = 0; k < 11; ++k) {
-      const float a = sx[r][c + k], b = sy[r][c + k], wk = P.w[k];
-      ax = fmaf(wk, a, ax);
-      ay = fmaf(wk, b, ay);
-      axx = fmaf(wk, a * a, axx);
-      ayy = fmaf(wk, b * b, ayy);
-      axy = fmaf(wk, a * b, axy);
+    for (int i = 0; i < 14; ++i) {
+      a[i] = sx[r][c0 + i];
+      b[i] = sy[r][c0 + i];
+      aa[i] = a[i] * a[i];
+      bb[i] = b[i] * b[i];
+      ab[i] = a[i] * b[i];
     }
-    hq[0][r][c] = ax;
-    hq[1][r][c] = ay;
-    hq[2][r][c] = axx;
-    hq[3][r][c] = ayy;
-    hq[4][r][c] = axy;
-  }
-  __syncthreads();
-  float s_sum = 0.f, l1_sum = 0.f, geo_sum = 0.f;
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int oy = (threadIdx.x >> 5) + 8 * h, ox = threadIdx.x & 31;
-    const int px = tx * ML_TW + ox, py = ty * ML_TH + oy;
-    if (px < P.W && py < P.H) {
-      float mx = 0.f, my = 0.f, exx = 0.f, eyy = 0.f, exy = 0.f;
+    for (int o = 0; o < 4; ++o) {
+      float ax = 0.f, ay = 0.f, axx = 0.f, ayy = 0.f, axy = 0.f;
 #pragma unroll
       for (int k = 0; k < 11; ++k) {
         const float wk = P.w[k];
-        mx = fmaf(wk, hq[0][oy + k][ox], mx);
-        my = fmaf(wk, hq[1][oy + k][ox], my);
-        exx = fmaf(wk, hq[2][oy + k][ox], exx);
-        eyy = fmaf(wk, hq[3][oy + k][ox], eyy);
-        exy = fmaf(wk, hq[4][oy + k][ox], exy);
+        ax = fmaf(wk, a[o + k], ax);
+        ay = fmaf(wk, b[o + k], ay);
+        axx = fmaf(wk, aa[o + k], axx);
+        ayy = fmaf(wk, bb[o + k], ayy);
+        axy = fmaf(wk, ab[o + k], axy);
       }
+      hq[0][r][c0 + o] = ax;
+      hq[1][r][c0 + o] = ay;
+      hq[2][r][c0 + o] = axx;
+      hq[3][r][c0 + o] = ayy;
+      hq[4][r][c0 + o] = axy;
+    }
+  }
+  __syncthreads();
+  // columns: a thread takes two neighbouring rows of a column, reading its 12 inputs of each map once
+  float s_sum = 0.f, l1_sum = 0.f, geo_sum = 0.f;
+  const int ox = threadIdx.x & 31, oy0 = 2 * (threadIdx.x >> 5);
+  float col[5][2];
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    float t[12];
+#pragma unroll
+    for (int i = 0; i < 12; ++i) t[i] = hq[m][oy0 + i][ox];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      float acc = 0.f;
+#pragma unroll
+      for (int k = 0; k < 11; ++k) acc = fmaf(P.w[k], t[h + k], acc);
+      col[m][h] = acc;
+    }
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int oy = oy0 + h;
+    const int px = tx * ML_TW + ox, py = ty * ML_TH + oy;
+    if (px < P.W && py < P.H) {
+      const float mx = col[0][h], my = col[1][h], exx = col[2][h], eyy = col[3][h], exy = col[4][h];
       const float a1 = 2.f * mx * my + P.c1, a2 = 2.f * (exy - mx * my) + P.c2;
       const float b1 = mx * mx + my * my + P.c1, b2 = (exx - mx * mx) + (eyy - my * my) + P.c2;
       const float inv_d = 1.0f / (b1 * b2);
@@ -170,37 +192,49 @@ __global__ __launch_bounds__(256) void k_ssim_bwd(MapLossParams P, const float* 
     sa[2][r][c] = a2;
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < ML_RH * ML_TW; i += 256) {
-    const int r = i / ML_TW, c = i - r * ML_TW;
-    float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+  // rows, four neighbouring outputs per thread (as in the first pass)
+  if (threadIdx.x < ML_RH * (ML_TW / 4)) {
+    const int r = threadIdx.x / (ML_TW / 4), c0 = 4 * (threadIdx.x - r * (ML_TW / 4));
 #pragma unroll
-    for (int k = 0; k < 11; ++k) {
-      const float wk = P.w[k];
-      a0 = fmaf(wk, sa[0][r][c + k], a0);
-      a1 = fmaf(wk, sa[1][r][c + k], a1);
-      a2 = fmaf(wk, sa[2][r][c + k], a2);
+    for (int m = 0; m < 3; ++m) {
+      float t[14];
+#pragma unroll
+      for (int i = 0; i < 14; ++i) t[i] = sa[m][r][c0 + i];
+#pragma unroll
+      for (int o = 0; o < 4; ++o) {
+        float acc = 0.f;
+#pragma unroll
+        for (int k = 0; k < 11; ++k) acc = fmaf(P.w[k], t[o + k], acc);
+        hq[m][r][c0 + o] = acc;
+      }
     }
-    hq[0][r][c] = a0;
-    hq[1][r][c] = a1;
-    hq[2][r][c] = a2;
   }
   __syncthreads();
   const float* X = img + ((size_t)v * 3 + ch) * npix;
   const float* Y = target + ((size_t)v * 3 + ch) * npix;
   float* G = dl_dcolor + ((size_t)v * 3 + ch) * npix;
+  // columns, two neighbouring rows per thread
+  const int ox = threadIdx.x & 31, oy0 = 2 * (threadIdx.x >> 5);
+  float col[3][2];
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    float t[12];
+#pragma unroll
+    for (int i = 0; i < 12; ++i) t[i] = hq[m][oy0 + i][ox];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      float acc = 0.f;
+#pragma unroll
+      for (int k = 0; k < 11; ++k) acc = fmaf(P.w[k], t[h + k], acc);
+      col[m][h] = acc;
+    }
+  }
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
-    const int oy = (threadIdx.x >> 5) + 8 * h, ox = threadIdx.x & 31;
+    const int oy = oy0 + h;
     const int px = tx * ML_TW + ox, py = ty * ML_TH + oy;
     if (px < P.W && py < P.H) {
-      float ga = 0.f, gb = 0.f, gc = 0.f;
-#pragma unroll
-      for (int k = 0; k < 11; ++k) {
-        const float wk = P.w[k];
-        ga = fmaf(wk, hq[0][oy + k][ox], ga);
-        gb = fmaf(wk, hq[1][oy + k][ox], gb);
-        gc = fmaf(wk, hq[2][oy + k][ox], gc);
-      }
+      const float ga = col[0][h], gb = col[1][h], gc = col[2][h];
       const size_t q = (size_t)py * P.W + px;
       const float x = X[q], y = Y[q];
       G[q] = P.g_ssim * (ga + 2.f * x * gb + y * gc) + P.g_l1 * sgnf(x - y);

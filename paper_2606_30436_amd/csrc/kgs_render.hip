@@ -572,26 +572,27 @@ __global__ __launch_bounds__(64 * NW) void k_render_bwd(
       const float4 ra0 = s_rec[w][j][0], ra1 = s_rec[w][j][1], rb0 = s_rec[w][jb][0], rb1 = s_rec[w][jb][1];
       float ea[PPL], ua[PPL], dya[PPL], eb[PPL], ub[PPL], dyb[PPL];
       bool bla[PPL], blb[PPL];
-      bool anya = false, anyb = false;
+      // one ballot per entry and pixel of the lane; the entry blends in the wave if any of them is set
+      uint64_t bal_a[PPL], bal_b[PPL], bba = 0ull, bbb = 0ull;
 #pragma unroll
       for (int p = 0; p < PPL; ++p) {
         ea[p] = log2_alpha(fpx[p], fpy, ra0, ra1.x, ra1.y, dya[p], ua[p]);
         eb[p] = log2_alpha(fpx[p], fpy, rb0, rb1.x, rb1.y, dyb[p], ub[p]);
         bla[p] = rel0 + ta < lastp[p] && ea[p] >= P.log2_amin;
         blb[p] = use_b && rel0 + tb < lastp[p] && eb[p] >= P.log2_amin;
-        anya |= bla[p];
-        anyb |= blb[p];
+        bal_a[p] = ballot64(bla[p]);
+        bal_b[p] = ballot64(blb[p]);
+        bba |= bal_a[p];
+        bbb |= bal_b[p];
       }
-      const uint64_t bba = ballot64(anya), bbb = ballot64(anyb);
       // blended pixels of the wave, and those under the error mask
       uint32_t na = 0u, nma = 0u, nb = 0u, nmb = 0u;
 #pragma unroll
       for (int p = 0; p < PPL; ++p) {
-        const uint64_t ba = PPL == 1 ? bba : ballot64(bla[p]), bb = PPL == 1 ? bbb : ballot64(blb[p]);
-        na += (uint32_t)__popcll(ba);
-        nma += (uint32_t)__popcll(ba & Mbal[p]);
-        nb += (uint32_t)__popcll(bb);
-        nmb += (uint32_t)__popcll(bb & Mbal[p]);
+        na += (uint32_t)__popcll(bal_a[p]);
+        nma += (uint32_t)__popcll(bal_a[p] & Mbal[p]);
+        nb += (uint32_t)__popcll(bal_b[p]);
+        nmb += (uint32_t)__popcll(bal_b[p] & Mbal[p]);
       }
       if (bba != 0ull && bbb != 0ull) {
         float x[20];
