@@ -135,6 +135,120 @@ __global__ __launch_bounds__(64 * NW) void k_render_fwd(RenderParams P, const ui
   }
 }
 
+// Forward with two pixels per lane: a wave composites a 16x8 block, lane l the
+// pixels (l % 8, l / 8) and (8 + l % 8, l / 8) of it, so one staging round, one
+// record read from LDS and one loop step serve two pixels.  Each pixel's
+// arithmetic is that of k_render_fwd, so the images are the same bits; the
+// wave stops when both of every lane's pixels have saturated.
+template <int NW>
+__global__ __launch_bounds__(64 * NW) void k_render_fwd2(RenderParams P, const uint2* __restrict__ ranges,
+                                                         const uint32_t* __restrict__ tile_order,
+                                                         const uint32_t* __restrict__ sorted_slot,
+                                                         const float4* __restrict__ slot_rec,
+                                                         float* __restrict__ color, float* __restrict__ depth,
+                                                         float* __restrict__ tfinal, int32_t* __restrict__ last) {
+  __shared__ float4 s_rec[NW][65][3];
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  const int gt = (int)tile_order[blockIdx.x];
+  const int v = gt / P.n_tiles, t = gt - v * P.n_tiles;
+  const int tx = t % P.tiles_x, ty = t / P.tiles_x;
+  const int nsx = P.tile_w / 16;   // 16x8 blocks per tile row, in row-major order
+  const int bx = tx * P.tile_w + (w % nsx) * 16, by = ty * P.tile_h + (w / nsx) * 8;
+  const int py = by + (l >> 3);
+  const int ox = pix_origin(P.W), oy = pix_origin(P.H);
+  const float fpy = (float)(py - oy);
+  int px[2];
+  float fpx[2], T[2], c0[2], c1[2], c2[2], D[2];
+  int lst[2];
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+    px[p] = bx + 8 * p + (l & 7);
+    fpx[p] = (float)(px[p] - ox);
+    T[p] = px[p] < P.W && py < P.H ? 1.0f : -1.0f;
+    c0[p] = c1[p] = c2[p] = D[p] = 0.f;
+    lst[p] = 0;
+  }
+  const uint2 rg = ranges[gt];
+  const uint32_t start = rg.x, end = rg.y;
+  {
+    const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+    s_rec[w][l][0] = z;
+    s_rec[w][l][1] = z;
+    s_rec[w][l][2] = z;
+    if (l < 3) s_rec[w][64][l] = z;
+  }
+  __builtin_amdgcn_wave_barrier();
+  for (uint32_t base = start; base < end; base += 64) {
+    if (!__any(T[0] > 0.f || T[1] > 0.f)) break;
+    const uint32_t k = base + (uint32_t)l;
+    bool keep = false;
+    float4 r0, r1, r2;
+    if (k < end) {
+      const float4* rec = slot_rec + (size_t)sorted_slot[k] * 4;
+      r0 = rec[0];
+      r1 = rec[1];
+      r2 = rec[2];
+      const uint32_t xb = __float_as_uint(r1.w), yb = __float_as_uint(r2.w);
+      const int xlo = (int)(int16_t)(xb & 0xffffu), xhi = (int)(int16_t)(xb >> 16);
+      const int ylo = (int)(int16_t)(yb & 0xffffu), yhi = (int)(int16_t)(yb >> 16);
+      if (xlo <= bx + 15 && xhi >= bx && ylo <= by + 7 && yhi >= by) {
+        const float fx0 = (float)(bx - ox) - r0.x, fy0 = (float)(by - oy) - r0.y;
+        keep = footprint_meets_box(fx0, fx0 + 15.0f, fy0, fy0 + 7.0f, r0, r1, P.log2_amin);
+      }
+    }
+    const uint64_t bal = ballot64(keep);
+    if (keep) {
+      const uint32_t q = mask_lt_count(bal);
+      s_rec[w][q][0] = r0;
+      s_rec[w][q][1] = make_float4(r1.x, r1.y, r1.z, __int_as_float((int)(k - start) + 1));
+      s_rec[w][q][2] = r2;
+    }
+    __builtin_amdgcn_wave_barrier();
+    const uint32_t len = (uint32_t)__popcll(bal);
+    auto blend = [&](uint32_t q, bool present) {
+      const float4 a0 = s_rec[w][q][0], a1 = s_rec[w][q][1], a2 = s_rec[w][q][2];
+#pragma unroll
+      for (int p = 0; p < 2; ++p) {
+        float dy, u;
+        const float e = log2_alpha(fpx[p], fpy, a0, a1.x, a1.y, dy, u);
+        const bool hit = present && T[p] > 0.f && e >= P.log2_amin;
+        const float a = hit ? fminf(exp2_approx(e), P.amax) : 0.f;
+        const float Tn = T[p] * (1.0f - a);
+        const bool stop = hit && Tn < P.tmin;
+        const bool take = hit && !stop;
+        const float wgt = take ? a * T[p] : 0.f;
+        c0[p] = fmaf(wgt, a2.x, c0[p]);
+        c1[p] = fmaf(wgt, a2.y, c1[p]);
+        c2[p] = fmaf(wgt, a2.z, c2[p]);
+        D[p] = fmaf(wgt, a1.z, D[p]);
+        T[p] = take ? Tn : (stop ? -T[p] : T[p]);
+        lst[p] = take ? __float_as_int(a1.w) : lst[p];
+      }
+    };
+    for (uint32_t j = 0; j < len; j += 2) {
+      if (!__any(T[0] > 0.f || T[1] > 0.f)) break;
+      blend(j, true);
+      blend(j + 1, j + 1 < len);
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  const size_t npix = (size_t)P.W * P.H;
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+    if (px[p] < P.W && py < P.H) {
+      const size_t pix = (size_t)v * npix + (size_t)py * P.W + px[p];
+      const size_t cpix = (size_t)v * 3 * npix + (size_t)py * P.W + px[p];
+      const float Tf = fabsf(T[p]);
+      color[cpix] = c0[p] + Tf * P.bg0;
+      color[cpix + npix] = c1[p] + Tf * P.bg1;
+      color[cpix + 2 * npix] = c2[p] + Tf * P.bg2;
+      depth[pix] = D[p];
+      tfinal[pix] = Tf;
+      last[pix] = lst[p];
+    }
+  }
+}
+
 // ---------------------------------------------------------------- L1 loss harness
 // One workgroup per (view, tile), pixels mapped to lanes as in the
 // compositing kernels.  Per pixel |dR| + |dG| + |dB| in FP32, summed over the
@@ -693,6 +807,16 @@ __global__ __launch_bounds__(64 * NW) void k_render_bwd(
 }
 
 // ---------------------------------------------------------------- host side
+// Two pixels per lane (a wave per 16x8 block) where the tile is at least 16
+// wide and, unless the configuration asks for it, the launch still has waves
+// to spare: at least 16 per CU (one view at 1242x375 has 3744, eight views
+// 30k).  Otherwise one pixel per lane, a wave per 8x8 block, twice the waves.
+static bool two_px_per_lane(const kgs_ctx* ctx, unsigned grid) {
+  const uint64_t waves2 = (uint64_t)grid * (uint64_t)(ctx->cfg.tile_w * ctx->cfg.tile_h / 128);
+  const int ppl = ctx->cfg.px_per_lane;
+  return ctx->cfg.tile_w >= 16 && (ppl == 2 || (ppl == 0 && waves2 >= KGS_BWD_TWO_PX_MIN_WAVES));
+}
+
 // waves per compositing workgroup: one per 8x8 sub-block of the tile
 kgs_status kgs_launch_render_fwd(kgs_ctx* ctx, const kgs_image* out, hipStream_t st) {
   const RenderParams P = render_params(ctx);
@@ -702,9 +826,21 @@ kgs_status kgs_launch_render_fwd(kgs_ctx* ctx, const kgs_image* out, hipStream_t
                      (const uint32_t*)ctx->tile_order,                                                           \
                      (const uint32_t*)ctx->sorted_slot, (const float4*)ctx->slot_rec, out->color, out->depth,      \
                      out->t_final, out->last)
-  if (tile_waves(ctx) == 8) KGS_FWD(8);
-  else KGS_FWD(4);
+#define KGS_FWD2(NWV)                                                                                            \
+  hipLaunchKernelGGL((k_render_fwd2<NWV>), dim3(grid), dim3(64 * NWV), 0, st, P, (const uint2*)ctx->ranges,      \
+                     (const uint32_t*)ctx->tile_order,                                                           \
+                     (const uint32_t*)ctx->sorted_slot, (const float4*)ctx->slot_rec, out->color, out->depth,      \
+                     out->t_final, out->last)
+  // two pixels per lane on the same rule as the backward (tiles at least 16 wide, a launch with waves to spare)
+  if (two_px_per_lane(ctx, grid)) {
+    if (tile_waves(ctx) == 8) KGS_FWD2(4);
+    else KGS_FWD2(2);
+  } else {
+    if (tile_waves(ctx) == 8) KGS_FWD(8);
+    else KGS_FWD(4);
+  }
 #undef KGS_FWD
+#undef KGS_FWD2
   return kgs_check_launch();
 }
 
@@ -760,14 +896,7 @@ kgs_status kgs_launch_render_bwd(kgs_ctx* ctx, const kgs_image* fwd, const float
                      (const float*)fwd->color, (const float*)fwd->depth, (const float*)fwd->t_final,              \
                      (const int32_t*)fwd->last, dl_dcolor, dl_ddepth, dl_dtfinal, target, tau_err, ctx->pair_grad,  \
                      ctx->pair_live, fuse_l1 ? 1 : 0, dl_out, ctx->loss_partial)
-  // two pixels per lane (a wave per 16x8 block) where the tile is at least 16
-  // wide and, unless the configuration asks for it, the launch still has
-  // waves to spare: at least 16 per CU (one view at 1242x375 has 3744, eight
-  // views 30k).  Otherwise one pixel per lane, a wave per 8x8 block, twice the
-  // waves.
-  const uint64_t waves2 = (uint64_t)grid * (uint64_t)(ctx->cfg.tile_w * ctx->cfg.tile_h / 128);
-  const int ppl = ctx->cfg.px_per_lane;
-  const bool two = ctx->cfg.tile_w >= 16 && (ppl == 2 || (ppl == 0 && waves2 >= KGS_BWD_TWO_PX_MIN_WAVES));
+  const bool two = two_px_per_lane(ctx, grid);
   if (!two) {
     if (tile_waves(ctx) == 8) {
       switch (ctx->cfg.batch) {
