@@ -135,13 +135,13 @@ __global__ __launch_bounds__(64 * NW) void k_render_fwd(RenderParams P, const ui
   }
 }
 
-// Forward with two pixels per lane: a wave composites a 16x8 block, lane l the
-// pixels (l % 8, l / 8) and (8 + l % 8, l / 8) of it, so one staging round, one
-// record read from LDS and one loop step serve two pixels.  Each pixel's
+// Forward with PPL pixels per lane: a wave composites an (8 PPL)x8 block, lane l
+// the pixels (8 p + l % 8, l / 8), p < PPL, of it, so one staging round, one
+// record read from LDS and one loop step serve PPL pixels.  Each pixel's
 // arithmetic is that of k_render_fwd, so the images are the same bits; the
-// wave stops when both of every lane's pixels have saturated.
-template <int NW>
-__global__ __launch_bounds__(64 * NW) void k_render_fwd2(RenderParams P, const uint2* __restrict__ ranges,
+// wave stops when all of every lane's pixels have saturated.
+template <int NW, int PPL>
+__global__ __launch_bounds__(64 * NW) void k_render_fwdn(RenderParams P, const uint2* __restrict__ ranges,
                                                          const uint32_t* __restrict__ tile_order,
                                                          const uint32_t* __restrict__ sorted_slot,
                                                          const float4* __restrict__ slot_rec,
@@ -152,16 +152,23 @@ __global__ __launch_bounds__(64 * NW) void k_render_fwd2(RenderParams P, const u
   const int gt = (int)tile_order[blockIdx.x];
   const int v = gt / P.n_tiles, t = gt - v * P.n_tiles;
   const int tx = t % P.tiles_x, ty = t / P.tiles_x;
-  const int nsx = P.tile_w / 16;   // 16x8 blocks per tile row, in row-major order
-  const int bx = tx * P.tile_w + (w % nsx) * 16, by = ty * P.tile_h + (w / nsx) * 8;
+  constexpr int BW = 8 * PPL;        // block width
+  const int nsx = P.tile_w / BW;     // blocks per tile row, in row-major order
+  const int bx = tx * P.tile_w + (w % nsx) * BW, by = ty * P.tile_h + (w / nsx) * 8;
   const int py = by + (l >> 3);
   const int ox = pix_origin(P.W), oy = pix_origin(P.H);
   const float fpy = (float)(py - oy);
-  int px[2];
-  float fpx[2], T[2], c0[2], c1[2], c2[2], D[2];
-  int lst[2];
+  int px[PPL];
+  float fpx[PPL], T[PPL], c0[PPL], c1[PPL], c2[PPL], D[PPL];
+  int lst[PPL];
+  auto any_open = [&]() {
+    bool o = false;
 #pragma unroll
-  for (int p = 0; p < 2; ++p) {
+    for (int p = 0; p < PPL; ++p) o = o || T[p] > 0.f;
+    return __any(o);
+  };
+#pragma unroll
+  for (int p = 0; p < PPL; ++p) {
     px[p] = bx + 8 * p + (l & 7);
     fpx[p] = (float)(px[p] - ox);
     T[p] = px[p] < P.W && py < P.H ? 1.0f : -1.0f;
@@ -179,7 +186,7 @@ __global__ __launch_bounds__(64 * NW) void k_render_fwd2(RenderParams P, const u
   }
   __builtin_amdgcn_wave_barrier();
   for (uint32_t base = start; base < end; base += 64) {
-    if (!__any(T[0] > 0.f || T[1] > 0.f)) break;
+    if (!any_open()) break;
     const uint32_t k = base + (uint32_t)l;
     bool keep = false;
     float4 r0, r1, r2;
@@ -191,9 +198,9 @@ __global__ __launch_bounds__(64 * NW) void k_render_fwd2(RenderParams P, const u
       const uint32_t xb = __float_as_uint(r1.w), yb = __float_as_uint(r2.w);
       const int xlo = (int)(int16_t)(xb & 0xffffu), xhi = (int)(int16_t)(xb >> 16);
       const int ylo = (int)(int16_t)(yb & 0xffffu), yhi = (int)(int16_t)(yb >> 16);
-      if (xlo <= bx + 15 && xhi >= bx && ylo <= by + 7 && yhi >= by) {
+      if (xlo <= bx + BW - 1 && xhi >= bx && ylo <= by + 7 && yhi >= by) {
         const float fx0 = (float)(bx - ox) - r0.x, fy0 = (float)(by - oy) - r0.y;
-        keep = footprint_meets_box(fx0, fx0 + 15.0f, fy0, fy0 + 7.0f, r0, r1, P.log2_amin);
+        keep = footprint_meets_box(fx0, fx0 + (float)(BW - 1), fy0, fy0 + 7.0f, r0, r1, P.log2_amin);
       }
     }
     const uint64_t bal = ballot64(keep);
@@ -208,7 +215,7 @@ __global__ __launch_bounds__(64 * NW) void k_render_fwd2(RenderParams P, const u
     auto blend = [&](uint32_t q, bool present) {
       const float4 a0 = s_rec[w][q][0], a1 = s_rec[w][q][1], a2 = s_rec[w][q][2];
 #pragma unroll
-      for (int p = 0; p < 2; ++p) {
+      for (int p = 0; p < PPL; ++p) {
         float dy, u;
         const float e = log2_alpha(fpx[p], fpy, a0, a1.x, a1.y, dy, u);
         const bool hit = present && T[p] > 0.f && e >= P.log2_amin;
@@ -226,7 +233,7 @@ __global__ __launch_bounds__(64 * NW) void k_render_fwd2(RenderParams P, const u
       }
     };
     for (uint32_t j = 0; j < len; j += 2) {
-      if (!__any(T[0] > 0.f || T[1] > 0.f)) break;
+      if (!any_open()) break;
       blend(j, true);
       blend(j + 1, j + 1 < len);
     }
@@ -234,7 +241,7 @@ __global__ __launch_bounds__(64 * NW) void k_render_fwd2(RenderParams P, const u
   }
   const size_t npix = (size_t)P.W * P.H;
 #pragma unroll
-  for (int p = 0; p < 2; ++p) {
+  for (int p = 0; p < PPL; ++p) {
     if (px[p] < P.W && py < P.H) {
       const size_t pix = (size_t)v * npix + (size_t)py * P.W + px[p];
       const size_t cpix = (size_t)v * 3 * npix + (size_t)py * P.W + px[p];
@@ -827,11 +834,13 @@ kgs_status kgs_launch_render_fwd(kgs_ctx* ctx, const kgs_image* out, hipStream_t
                      (const uint32_t*)ctx->sorted_slot, (const float4*)ctx->slot_rec, out->color, out->depth,      \
                      out->t_final, out->last)
 #define KGS_FWD2(NWV)                                                                                            \
-  hipLaunchKernelGGL((k_render_fwd2<NWV>), dim3(grid), dim3(64 * NWV), 0, st, P, (const uint2*)ctx->ranges,      \
+  hipLaunchKernelGGL((k_render_fwdn<NWV, 2>), dim3(grid), dim3(64 * NWV), 0, st, P,                             \
+                     (const uint2*)ctx->ranges,                                                                  \
                      (const uint32_t*)ctx->tile_order,                                                           \
                      (const uint32_t*)ctx->sorted_slot, (const float4*)ctx->slot_rec, out->color, out->depth,      \
                      out->t_final, out->last)
   // two pixels per lane on the same rule as the backward (tiles at least 16 wide, a launch with waves to spare)
+  // (four pixels per lane, a wave per 32x8 block, measured 2.8x slower on the bench chunk)
   if (two_px_per_lane(ctx, grid)) {
     if (tile_waves(ctx) == 8) KGS_FWD2(4);
     else KGS_FWD2(2);
