@@ -641,7 +641,9 @@ __global__ __launch_bounds__(64 * NW) void k_render_bwd(
       const int bi = r * 64 + l;
       const uint32_t k = base + (uint32_t)bi;
       bool keep = false;
-      float4 r0, r1, r2;
+      // defined on every path: left unset where no record is read, the 64-record
+      // variants kept r2 in scratch memory (a store and a reload per record)
+      float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0;
       xbw[r] = 0.f;
       ybw[r] = 0.f;
       firstp[r] = 0u;
