@@ -306,6 +306,11 @@ class Rasterizer:
     def chunk_launch(self, graph: int, stream=None):
         L.kgs_chunk_launch(graph, stream)
 
+    def chunk_release(self, graph: int):
+        """Destroy one captured chunk (e.g. after a tiling change made it stale)."""
+        self.graphs.remove(graph)
+        L.kgs_graph_destroy(graph)
+
 
 def _copy_device(dst: int, src: int, nbytes: int):
     """Device-to-device byte copy through torch (marshalling of workspace views)."""
