@@ -217,18 +217,18 @@ def main():
         best, table = ((16, 16), args.batch or 64), None
     else:
         # each candidate is timed as what is deployed: its chunk captured as a graph, then replayed
-        state = {"graph": None}
+        cand = {"graph": None}
 
         def set_tiling(tile, batch):
             R.set_tiling(tile, batch)
-            if state["graph"] is not None:
-                R.chunk_release(state["graph"])
-            state["graph"] = None
+            if cand["graph"] is not None:
+                R.chunk_release(cand["graph"])
+            cand["graph"] = None
 
         def run_graph():
-            if state["graph"] is None:
-                state["graph"] = R.chunk_capture(desc())
-            R.chunk_launch(state["graph"])
+            if cand["graph"] is None:
+                cand["graph"] = R.chunk_capture(desc())
+            R.chunk_launch(cand["graph"])
         best, table = autotune(run_graph, set_tiling, TILE_SHAPES, BATCHES, reps=5)
         log(f"[bench] autotune best {best}")
     R.set_tiling(best[0], best[1])
