@@ -132,7 +132,10 @@ __device__ __forceinline__ int floordiv_i(int a, int b) {
   return q;
 }
 
-__device__ __forceinline__ uint64_t ballot64(int pred) { return __ballot(pred); }
+// lanes of the wave where pred holds (of those active); the compiler builtin
+// takes the condition as a lane mask, so a compare feeds it without a round
+// trip through a vector register
+__device__ __forceinline__ uint64_t ballot64(bool pred) { return __builtin_amdgcn_ballot_w64(pred); }
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 

@@ -110,7 +110,7 @@ __global__ __launch_bounds__(64 * NW) void k_render_fwd(RenderParams P, const ui
       c1 = fmaf(wgt, a2.y, c1);
       c2 = fmaf(wgt, a2.z, c2);
       D = fmaf(wgt, a1.z, D);
-      T = take ? Tn : (stop ? -T : T);
+      T = stop ? -T : Tn;   // a lane that does not blend has a = 0, so Tn = T exactly
       lst = take ? __float_as_int(a1.w) : lst;
     };
     // two entries per round (one saturation check for both)
@@ -228,7 +228,7 @@ __global__ __launch_bounds__(64 * NW) void k_render_fwdn(RenderParams P, const u
         c1[p] = fmaf(wgt, a2.y, c1[p]);
         c2[p] = fmaf(wgt, a2.z, c2[p]);
         D[p] = fmaf(wgt, a1.z, D[p]);
-        T[p] = take ? Tn : (stop ? -T[p] : T[p]);
+        T[p] = stop ? -T[p] : Tn;   // a pixel that does not blend has a = 0, so Tn = T exactly
         lst[p] = take ? __float_as_int(a1.w) : lst[p];
       }
     };
@@ -425,8 +425,10 @@ __device__ __forceinline__ void wave_reduce20(float (&x)[20], int lane, int& idx
   idx = ((lane & 32) ? 10 : 0) + (u4 ? 5 : 0) + rel;
 }
 
-// Per-pixel terms of one blended pair in the backward (lanes that do not blend
-// carry alpha = 0, which zeroes every term and leaves T and Rj unchanged).
+// Per-pixel terms of one blended pair in the backward.  Lanes that do not blend
+// come with e = -inf: exp2 gives alpha = 0, which zeroes every term and leaves
+// T and Rj unchanged (the blend mask is applied to e once, so no lane mask has
+// to live across the reduction's branches).
 //   dL/dalpha_j = T_j (g . c_j) + Rj / (1 - alpha_j)
 // with Rj = gAT - g . C + g . C_j (C the final colour and depth, C_j its part
 // from Gaussians up to j).  x[0..5] are the moments (ge u, ge dy, ge u^2,
@@ -435,11 +437,11 @@ __device__ __forceinline__ void wave_reduce20(float (&x)[20], int lane, int& idx
 // u = dx + k dy, the pair's P', k, E' and ln 2 turn their sums into the
 // record-space derivatives.  x[6..9] = alpha_j T_j g (colour and depth).
 template <bool DEPTH>
-__device__ __forceinline__ void blend_terms(float e, float u, float dy, bool bl, const float4& r1, const float4& r2,
+__device__ __forceinline__ void blend_terms(float e, float u, float dy, const float4& r1, const float4& r2,
                                             float amax, float g0, float g1, float g2, float gD, float& T, float& Rj,
                                             float* __restrict__ x) {
   const float raw = exp2_approx(e);
-  const float a = bl ? fminf(raw, amax) : 0.f;
+  const float a = fminf(raw, amax);
   const float wgt = a * T;
   // without a depth gradient (gD = 0) the depth terms are zero and left out
   const float gcc = fmaf(g2, r2.z, fmaf(g1, r2.y, g0 * r2.x));
@@ -466,7 +468,7 @@ __device__ __forceinline__ void blend_terms(float e, float u, float dy, bool bl,
 // the moments with a factor dy are formed once from the pixel sums,
 // sum ge dy = dy sum ge and so on, instead of per pixel.
 template <bool DEPTH>
-__device__ __forceinline__ void blend_terms2(const float (&e)[2], const float (&u)[2], float dy, const bool (&bl)[2],
+__device__ __forceinline__ void blend_terms2(const float (&e)[2], const float (&u)[2], float dy,
                                              const float4& r1, const float4& r2, float amax, const float (&g0)[2],
                                              const float (&g1)[2], const float (&g2)[2], const float (&gD)[2],
                                              float (&T)[2], float (&Rj)[2], float* __restrict__ x) {
@@ -474,7 +476,7 @@ __device__ __forceinline__ void blend_terms2(const float (&e)[2], const float (&
 #pragma unroll
   for (int p = 0; p < 2; ++p) {
     const float raw = exp2_approx(e[p]);
-    const float a = bl[p] ? fminf(raw, amax) : 0.f;
+    const float a = fminf(raw, amax);
     const float wgt = a * T[p];
     const float gcc = fmaf(g2[p], r2.z, fmaf(g1[p], r2.y, g0[p] * r2.x));
     const float gc = DEPTH ? fmaf(gD[p], r1.z, gcc) : gcc;
@@ -694,19 +696,24 @@ __global__ __launch_bounds__(64 * NW) void k_render_bwd(
       // both entries' records at once (the second is a repeat of the first when absent)
       const float4 ra0 = s_rec[w][j][0], ra1 = s_rec[w][j][1], rb0 = s_rec[w][jb][0], rb1 = s_rec[w][jb][1];
       float ea[PPL], ua[PPL], dya[PPL], eb[PPL], ub[PPL], dyb[PPL];
-      bool bla[PPL], blb[PPL];
       // one ballot per entry and pixel of the lane; the entry blends in the wave if any of them is set
       uint64_t bal_a[PPL], bal_b[PPL], bba = 0ull, bbb = 0ull;
 #pragma unroll
       for (int p = 0; p < PPL; ++p) {
         ea[p] = log2_alpha(fpx[p], fpy, ra0, ra1.x, ra1.y, dya[p], ua[p]);
         eb[p] = log2_alpha(fpx[p], fpy, rb0, rb1.x, rb1.y, dyb[p], ub[p]);
-        bla[p] = rel0 + ta < lastp[p] && ea[p] >= P.log2_amin;
-        blb[p] = use_b && rel0 + tb < lastp[p] && eb[p] >= P.log2_amin;
-        bal_a[p] = ballot64(bla[p]);
-        bal_b[p] = ballot64(blb[p]);
+        // each ballot of a single compare, the masks combined in scalar registers
+        // (a ballot of a combined condition goes through a vector register)
+        const bool ina = rel0 + ta < lastp[p], inb = rel0 + tb < lastp[p];
+        const bool hta = ea[p] >= P.log2_amin, htb = eb[p] >= P.log2_amin;
+        const bool bla = ina & hta, blb = use_b & inb & htb;
+        bal_a[p] = ballot64(ina) & ballot64(hta);
+        bal_b[p] = ballot64(inb) & ballot64(htb) & (0ull - (uint64_t)use_b);
         bba |= bal_a[p];
         bbb |= bal_b[p];
+        // a pixel that does not blend the entry takes alpha = exp2(-inf) = 0 in the terms below
+        ea[p] = bla ? ea[p] : -INFINITY;
+        eb[p] = blb ? eb[p] : -INFINITY;
       }
       // blended pixels of the wave, and those under the error mask
       uint32_t na = 0u, nma = 0u, nb = 0u, nmb = 0u;
@@ -723,12 +730,12 @@ __global__ __launch_bounds__(64 * NW) void k_render_bwd(
         if constexpr (PPL == 2) {
           // entry a for both pixels, then entry b: each pixel's T and Rj still
           // see a before b
-          blend_terms2<DEPTH>(ea, ua, dya[0], bla, ra1, ra2, P.amax, g0, g1, g2, gD, T, Rj, x);
-          blend_terms2<DEPTH>(eb, ub, dyb[0], blb, rb1, rb2, P.amax, g0, g1, g2, gD, T, Rj, x + 10);
+          blend_terms2<DEPTH>(ea, ua, dya[0], ra1, ra2, P.amax, g0, g1, g2, gD, T, Rj, x);
+          blend_terms2<DEPTH>(eb, ub, dyb[0], rb1, rb2, P.amax, g0, g1, g2, gD, T, Rj, x + 10);
         } else {
-          blend_terms<DEPTH>(ea[0], ua[0], dya[0], bla[0], ra1, ra2, P.amax, g0[0], g1[0], g2[0], gD[0], T[0],
+          blend_terms<DEPTH>(ea[0], ua[0], dya[0], ra1, ra2, P.amax, g0[0], g1[0], g2[0], gD[0], T[0],
                              Rj[0], x);
-          blend_terms<DEPTH>(eb[0], ub[0], dyb[0], blb[0], rb1, rb2, P.amax, g0[0], g1[0], g2[0], gD[0], T[0],
+          blend_terms<DEPTH>(eb[0], ub[0], dyb[0], rb1, rb2, P.amax, g0[0], g1[0], g2[0], gD[0], T[0],
                              Rj[0], x + 10);
         }
         int idx;
@@ -748,17 +755,15 @@ __global__ __launch_bounds__(64 * NW) void k_render_bwd(
         float x[10];
         if constexpr (PPL == 2) {
           float e2[2], u2[2];
-          bool b2[2];
 #pragma unroll
           for (int p = 0; p < 2; ++p) {
             e2[p] = first ? ea[p] : eb[p];
             u2[p] = first ? ua[p] : ub[p];
-            b2[p] = first ? bla[p] : blb[p];
           }
-          blend_terms2<DEPTH>(e2, u2, first ? dya[0] : dyb[0], b2, q1, q2, P.amax, g0, g1, g2, gD, T, Rj, x);
+          blend_terms2<DEPTH>(e2, u2, first ? dya[0] : dyb[0], q1, q2, P.amax, g0, g1, g2, gD, T, Rj, x);
         } else {
-          blend_terms<DEPTH>(first ? ea[0] : eb[0], first ? ua[0] : ub[0], first ? dya[0] : dyb[0],
-                             first ? bla[0] : blb[0], q1, q2, P.amax, g0[0], g1[0], g2[0], gD[0], T[0], Rj[0], x);
+          blend_terms<DEPTH>(first ? ea[0] : eb[0], first ? ua[0] : ub[0], first ? dya[0] : dyb[0], q1, q2,
+                             P.amax, g0[0], g1[0], g2[0], gD[0], T[0], Rj[0], x);
         }
         int idx;
         bool valid;
