@@ -219,7 +219,6 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_emit(kgs_gaussians g, const CamDe
   G.ok = false;
   if (valid) load_gaussian(g, i, P.alpha_min, G, bad);
   const float hl2e = 0.5f * 1.4426950408889634f;
-  uint64_t seen = 0ull;   // views whose slot holds a projected record
   for (int v0 = 0; v0 < V; v0 += 8) {
     uint32_t tg[8];
     if (v0 == 0) {
@@ -250,30 +249,48 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_emit(kgs_gaussians g, const CamDe
       ProjCore p;
       const bool vis_ok = G.ok && project_core(c, G.mu, G.Rq, G.s, G.o, P.near_z, P.far_z, P.eps2d, P.rect_margin,
                                                P.log_alpha_min, P.tile_w, P.tile_h, P.tiles_x, P.tiles_y, p);
-      float4 r0, r1;
+      float4 r0, r1, r2;
       int4 pix;
       uint4 desc;   // the pair emission's view of the record: key base, first tile, rectangle width, tile count
-      float* r2p = reinterpret_cast<float*>(slot_rec + s * 4 + 2);
       if (vis_ok) {
         r0 = make_float4(p.rmx, p.rmy, -hl2e * p.Pc, p.kc);
         r1 = make_float4(-hl2e * p.Ec, __log2f(G.o), p.tz, pack_bounds(p.fxi - p.rx, p.fxi + p.rx));
-        r2p[3] = pack_bounds(p.fyi - p.ry, p.fyi + p.ry);   // the colour follows below
         pix = make_int4(p.fxi, p.fyi, p.rx, p.ry);
         desc = make_uint4((uint32_t)v << tile_bits, (uint32_t)p.x0 | ((uint32_t)p.y0 << 16), (uint32_t)(p.x1 - p.x0),
                           tiles);
-        seen |= 1ull << v;
+        // the colour from the view direction (Gaussian mean minus camera centre),
+        // so the record is written in three whole float4 stores; the SH
+        // coefficients are read per visible view (the later views' reads hit
+        // the cache), which overlaps their latency with the projections at the
+        // cost of registers (two waves per SIMD: faster than a separate colour
+        // pass at four)
+        float dv[3];
+        cam_offset(c, G.mu, dv);
+        const float inv = 1.0f / sqrtf(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+        float Y[16];
+        sh_basis(DEG, dv[0] * inv, dv[1] * inv, dv[2] * inv, Y);
+        float col[3];
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+          float acc = 0.5f;
+#pragma unroll
+          for (int k = 0; k < K; ++k) acc += Y[k] * g.sh[(int64_t)(k * 3 + ch) * g.n + i];
+          col[ch] = fmaxf(acc, 0.0f);
+        }
+        r2 = make_float4(col[0], col[1], col[2], pack_bounds(p.fyi - p.ry, p.fyi + p.ry));
       } else {
         // the counting pass saw this Gaussian visible but the re-projection does
         // not: write a record that never blends and an empty rectangle
         r0 = make_float4(0.f, 0.f, 0.f, 0.f);
         r1 = make_float4(0.f, -INFINITY, 1.0f, pack_bounds(32767, -32768));
-        slot_rec[s * 4 + 2] = make_float4(0.f, 0.f, 0.f, pack_bounds(32767, -32768));
+        r2 = make_float4(0.f, 0.f, 0.f, pack_bounds(32767, -32768));
         pix = make_int4(-(1 << 30), -(1 << 30), 0, 0);
         // its pairs (as many as the count gave) go down the first tile column; they never blend
         desc = make_uint4((uint32_t)v << tile_bits, 0u, 1u, tiles);
       }
       slot_rec[s * 4 + 0] = r0;
       slot_rec[s * 4 + 1] = r1;
+      slot_rec[s * 4 + 2] = r2;
       slot_gid[s] = (uint32_t)i;
       slot_view[s] = (uint32_t)v;
       slot_pix[s] = pix;
@@ -289,31 +306,6 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_emit(kgs_gaussians g, const CamDe
       else
         reinterpret_cast<uint64_t*>(slot_keys)[s] = key;
       // the sort's values start as the record indices themselves (its first pass generates them)
-    }
-  }
-  // colours from the view directions (Gaussian mean minus camera centre), once
-  // the projections are done: the SH coefficients are read once and never held
-  // together with the projection state
-  if (seen != 0ull) {
-    float shc[K * 3];
-#pragma unroll
-    for (int k = 0; k < K * 3; ++k) shc[k] = g.sh[(int64_t)k * g.n + i];
-    for (int v = 0; v < V; ++v) {
-      if (((seen >> v) & 1ull) == 0ull) continue;
-      const uint64_t s = vis[(int64_t)v * g.n + i] - 1u;
-      float dv[3];
-      cam_offset(cams[v], G.mu, dv);
-      const float inv = 1.0f / sqrtf(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
-      float Y[16];
-      sh_basis(DEG, dv[0] * inv, dv[1] * inv, dv[2] * inv, Y);
-      float* r2p = reinterpret_cast<float*>(slot_rec + s * 4 + 2);
-#pragma unroll
-      for (int ch = 0; ch < 3; ++ch) {
-        float acc = 0.5f;
-#pragma unroll
-        for (int k = 0; k < K; ++k) acc += Y[k] * shc[k * 3 + ch];
-        r2p[ch] = fmaxf(acc, 0.0f);
-      }
     }
   }
 }
