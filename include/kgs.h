@@ -492,7 +492,9 @@ kgs_status kgs_render_bwd(kgs_ctx* ctx, const kgs_gaussians* g, const kgs_camera
  * each pixel's sequence, writes per-pair gradients and footprint counts into
  * the workspace).  kgs_project_bwd: per Gaussian, the sum over its pairs and
  * views, the chain rule to the parameters and the pose, and the statistics.
- * Called in this order they equal kgs_render_bwd. */
+ * Called in this order they equal kgs_render_bwd; kgs_project_bwd returns
+ * KGS_ERR_STATE unless kgs_render_bwd_pixels has run since the last
+ * kgs_project / kgs_bin_sort / kgs_set_tiling. */
 kgs_status kgs_render_bwd_pixels(kgs_ctx* ctx, const kgs_image* fwd, const float* dl_dcolor, const float* dl_ddepth,
                                  const float* dl_dtfinal, const float* target, float tau_err, void* stream);
 kgs_status kgs_project_bwd(kgs_ctx* ctx, const kgs_gaussians* g, const kgs_camera* cams, int32_t n_views,

@@ -221,6 +221,7 @@ kgs_status kgs_set_tiling(kgs_ctx* ctx, int32_t tile_w, int32_t tile_h, int32_t 
   set_tiling(ctx);
   ctx->projected = 0;
   ctx->binned = 0;
+  ctx->pixels_done = 0;
   return KGS_OK;
 }
 
@@ -238,6 +239,7 @@ kgs_status kgs_project(kgs_ctx* ctx, const kgs_gaussians* g, const kgs_camera* c
   const kgs_status s = kgs_launch_project(ctx, g, cams, n_views, pose_xi, st);
   ctx->projected = (s == KGS_OK);
   ctx->binned = 0;
+  ctx->pixels_done = 0;
   return s;
 }
 
@@ -246,6 +248,7 @@ kgs_status kgs_bin_sort(kgs_ctx* ctx, void* stream) {
   if (!ctx->projected) return KGS_ERR_STATE;
   const kgs_status s = kgs_launch_bin_sort(ctx, (hipStream_t)stream);
   ctx->binned = (s == KGS_OK);
+  ctx->pixels_done = 0;
   return s;
 }
 
@@ -436,6 +439,7 @@ kgs_status kgs_render_bwd(kgs_ctx* ctx, const kgs_gaussians* g, const kgs_camera
   hipStream_t st = (hipStream_t)stream;
   kgs_status s = kgs_launch_render_bwd(ctx, fwd, dl_dcolor, dl_ddepth, dl_dtfinal, target, tau_err, st);
   if (s != KGS_OK) return s;
+  ctx->pixels_done = 1;
   return kgs_launch_project_bwd(ctx, g, cams, n_views, pose_xi, view_loss, grads, stats, st);
 }
 
@@ -443,14 +447,18 @@ kgs_status kgs_render_bwd_pixels(kgs_ctx* ctx, const kgs_image* fwd, const float
                                  const float* dl_dtfinal, const float* target, float tau_err, void* stream) {
   if (!ctx || !image_ok(fwd) || !dl_dcolor) return KGS_ERR_INVALID_ARG;
   if (!ctx->binned) return KGS_ERR_STATE;
-  return kgs_launch_render_bwd(ctx, fwd, dl_dcolor, dl_ddepth, dl_dtfinal, target, tau_err, (hipStream_t)stream);
+  const kgs_status s = kgs_launch_render_bwd(ctx, fwd, dl_dcolor, dl_ddepth, dl_dtfinal, target, tau_err,
+                                             (hipStream_t)stream);
+  ctx->pixels_done = (s == KGS_OK);
+  return s;
 }
 
 kgs_status kgs_project_bwd(kgs_ctx* ctx, const kgs_gaussians* g, const kgs_camera* cams, int32_t n_views,
                            const float* pose_xi, const float* view_loss, const kgs_grads* grads,
                            const kgs_view_stats* stats, void* stream) {
   if (!ctx || !gaussians_ok(ctx, g) || !cams || !grads) return KGS_ERR_INVALID_ARG;
-  if (!ctx->binned) return KGS_ERR_STATE;
+  // the per-pair records and live flags it sums come from kgs_render_bwd_pixels on this binning
+  if (!ctx->binned || !ctx->pixels_done) return KGS_ERR_STATE;
   if (n_views != ctx->last_views || g->n != ctx->last_n || g->sh_degree != ctx->last_degree) return KGS_ERR_STATE;
   return kgs_launch_project_bwd(ctx, g, cams, n_views, pose_xi, view_loss, grads, stats, (hipStream_t)stream);
 }

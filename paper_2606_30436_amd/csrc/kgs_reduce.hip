@@ -136,10 +136,13 @@ __device__ __forceinline__ void seg_window(SegWindow& W, uint32_t w, uint32_t np
   if (tail) {
     if (started) {
       // a segment that ends in a window without written pairs lies wholly in
-      // it: its slot blended nowhere, and only its count is stored (nothing
-      // reads the sums of such a slot)
-      if (W.any) store_sum(slot_sum + (size_t)s * (KGS_SLOT_WORDS / 4), W.x);
-      slot_om[s] = W.any ? (uint32_t)W.x[10] : 0u;
+      // it: its slot blended nowhere, and its count keeps the zero the
+      // compositing backward cleared it to (nothing reads the sums of such a
+      // slot)
+      if (W.any) {
+        store_sum(slot_sum + (size_t)s * (KGS_SLOT_WORDS / 4), W.x);
+        slot_om[s] = (uint32_t)W.x[10];
+      }
     } else {
       put_rec(seg_head + (size_t)w * 4, W.x, s, 1u);  // continued from before, ends here
     }

@@ -884,11 +884,15 @@ void kgs_launch_loss_final(kgs_ctx* ctx, float* view_loss, hipStream_t st) {
                        view_loss);
 }
 
-// Clears the pairs' live flags (the pair count is read on the device) before
-// the compositing backward sets those of the pairs it writes.
-__global__ __launch_bounds__(256) void k_clear_live(const uint32_t* __restrict__ counters, uint4* __restrict__ live) {
-  const uint32_t n = (counters[1] + 15u) / 16u;
+// Clears the pairs' live flags and the slots' blended-pixel counts (the counts
+// are read on the device) before the compositing backward sets the flags of
+// the pairs it writes; the segmented pair sums then write the counts of the
+// slots with a written pair only.
+__global__ __launch_bounds__(256) void k_clear_live(const uint32_t* __restrict__ counters, uint4* __restrict__ live,
+                                                    uint32_t* __restrict__ slot_om) {
+  const uint32_t n = (counters[1] + 15u) / 16u, ns = counters[0];
   for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) live[i] = make_uint4(0u, 0u, 0u, 0u);
+  for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < ns; i += gridDim.x * 256) slot_om[i] = 0u;
 }
 
 // fuse_l1: the colour gradient is the L1 loss gradient against target, formed
@@ -901,7 +905,7 @@ kgs_status kgs_launch_render_bwd(kgs_ctx* ctx, const kgs_image* fwd, const float
   const unsigned grid = (unsigned)(ctx->last_views * ctx->n_tiles);
   const uint64_t lw = ((uint64_t)ctx->cfg.pair_capacity + 15) / 16;
   hipLaunchKernelGGL(k_clear_live, dim3((unsigned)std::min<uint64_t>(std::max<uint64_t>((lw + 255) / 256, 1), 1024)),
-                     dim3(256), 0, st, (const uint32_t*)ctx->counters, (uint4*)ctx->pair_live);
+                     dim3(256), 0, st, (const uint32_t*)ctx->counters, (uint4*)ctx->pair_live, ctx->slot_om);
 #define KGS_BWD(BB, NWV, PX)                                                                                     \
   if (dl_ddepth) { KGS_BWD_D(BB, NWV, true, PX); } else { KGS_BWD_D(BB, NWV, false, PX); }
 #define KGS_BWD_D(BB, NWV, DD, PX)                                                                               \

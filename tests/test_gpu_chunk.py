@@ -110,6 +110,45 @@ def test_chunk_run_equals_the_steps(chunk, px):
     _same(one, b.outputs())
 
 
+def test_split_backward_equals_the_full_call_and_keeps_its_order(chunk):
+    """render_bwd_pixels then project_bwd equal render_bwd bit for bit, twice in
+    a row with another loss gradient (each backward clears the slots'
+    blended-pixel counts before its pair sums write those of the slots it
+    reaches); project_bwd before render_bwd_pixels on a binning is refused."""
+    from paper_2606_30436_amd import _lib as L
+    sc = chunk
+    say(f"[gpu] split backward n={sc.n} V={sc.n_views}")
+    R = _rast(sc)
+    b = Bufs(sc, R)
+    R.project(b.g, b.cams, b.xi)
+    R.bin_sort()
+    R.render_fwd(b.img)
+    R.loss_l1(b.target, b.img, b.dl, b.loss)
+    with pytest.raises(L.KgsError) as e:
+        R.project_bwd(b.g, b.cams, b.xi, b.loss, b.grads, b.pose, b.stats)
+    assert e.value.code == L.KGS_ERR_STATE
+    acc = (b.grads.means, b.grads.log_scales, b.grads.quats, b.grads.logits, b.grads.sh, b.pose, b.stats.kappa_sum,
+           b.stats.omega_sum, b.stats.gamma_sum, b.stats.grad_norm_sum, b.stats.view_count, b.stats.max_radius)
+    dl0 = b.dl.clone()
+    for scale in (1.0, -3.0):
+        dl = dl0 * scale
+        outs = []
+        for split in (False, True):
+            for t in acc:
+                t.zero_()
+            if split:
+                R.render_bwd_pixels(b.img, dl, None, b.target, 0.1)
+                R.project_bwd(b.g, b.cams, b.xi, b.loss, b.grads, b.pose, b.stats)
+            else:
+                R.render_bwd(b.g, b.cams, b.xi, b.img, dl, target=b.target, tau_err=0.1, view_loss=b.loss,
+                             grads=b.grads, pose_grad=b.pose, stats=b.stats)
+            torch.cuda.synchronize()
+            outs.append([t.clone() for t in acc])
+        for x, y in zip(*outs):
+            assert torch.equal(x, y)
+    assert R.status() == 0
+
+
 def test_graph_replays_equal_eager_runs(chunk):
     """Capture once; between replays the means change in place (eager torch
     work) and the lifecycle state is reset; every replay must equal an eager
