@@ -431,34 +431,49 @@ __device__ __forceinline__ void slot_record(uint32_t s, uint32_t v, const kgs_ga
 // Slots whose pixels blended nowhere have a zero sum (every pixel term is a
 // zero at alpha = 0), so zero gradients and pose terms, and nothing reads their
 // records: the gather and the pose reduction look at slot_om first.
-// k_slot_split queues the others (a wave claims the share of its 512 slots
-// with one atomic; the queue's order does not matter, since every result is
-// written at its slot), and k_slot_live takes the queue with full waves.  counters[KGS_CNT_LIVE] is cleared by
-// k_pair_fixup.
+// k_slot_split queues the others: a block takes 2048 consecutive slots, eight
+// per thread (two 16-byte loads), ranks them with a block scan and claims its
+// share of the queue with one atomic (the queue's order does not matter, since
+// every result is written at its slot); k_slot_live takes the queue with full
+// waves.  counters[KGS_CNT_LIVE] is cleared by k_pair_fixup.
 __global__ __launch_bounds__(KGS_BLOCK) void k_slot_split(uint32_t* __restrict__ counters,
                                                           const uint32_t* __restrict__ slot_om,
                                                           uint32_t* __restrict__ slot_live) {
-  // a wave takes 512 consecutive slots, eight per lane
+  __shared__ uint32_t s_wave[KGS_BLOCK / 64];
+  __shared__ uint32_t s_base;
   const uint32_t n_slots = counters[0];
-  const int l = threadIdx.x & 63;
-  const uint64_t waves = (uint64_t)gridDim.x * (KGS_BLOCK / 64);
-  for (uint64_t wb = ((uint64_t)blockIdx.x * (KGS_BLOCK / 64) + (threadIdx.x >> 6)) * 512u; wb < n_slots;
-       wb += waves * 512u) {
-    const uint64_t s0 = wb + (uint64_t)l * 8u;
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  constexpr uint32_t PER_BLOCK = KGS_BLOCK * 8u;
+  for (uint64_t bb = (uint64_t)blockIdx.x * PER_BLOCK; bb < n_slots; bb += (uint64_t)gridDim.x * PER_BLOCK) {
+    const uint64_t s0 = bb + (uint64_t)tid * 8u;
     uint32_t m = 0u;
+    if (s0 + 8u <= n_slots) {
+      const uint4* q = reinterpret_cast<const uint4*>(slot_om + s0);
+      const uint4 a = q[0], b = q[1];
+      m = (a.x != 0u ? 1u : 0u) | (a.y != 0u ? 2u : 0u) | (a.z != 0u ? 4u : 0u) | (a.w != 0u ? 8u : 0u) |
+          (b.x != 0u ? 16u : 0u) | (b.y != 0u ? 32u : 0u) | (b.z != 0u ? 64u : 0u) | (b.w != 0u ? 128u : 0u);
+    } else {
 #pragma unroll
-    for (int k = 0; k < 8; ++k)
-      if (s0 + k < n_slots && slot_om[s0 + k] != 0u) m |= 1u << k;
+      for (int k = 0; k < 8; ++k)
+        if (s0 + k < n_slots && slot_om[s0 + k] != 0u) m |= 1u << k;
+    }
     const uint32_t c = (uint32_t)__popc(m);
     const uint32_t inc = wave_inclusive_scan(c);
-    const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
-    if (tot == 0u) continue;
-    uint32_t base = 0u;
-    if (l == 0) base = atomicAdd(&counters[KGS_CNT_LIVE], tot);
-    uint32_t pos = (uint32_t)__shfl((int)base, 0, 64) + inc - c;
+    if (l == 63) s_wave[w] = inc;
+    __syncthreads();
+    if (tid == 0) {
+      uint32_t tot = 0u;
+#pragma unroll
+      for (int k = 0; k < KGS_BLOCK / 64; ++k) tot += s_wave[k];
+      s_base = tot ? atomicAdd(&counters[KGS_CNT_LIVE], tot) : 0u;
+    }
+    __syncthreads();
+    uint32_t pos = s_base + inc - c;
+    for (int k = 0; k < w; ++k) pos += s_wave[k];
 #pragma unroll
     for (int k = 0; k < 8; ++k)
       if ((m >> k) & 1u) slot_live[pos++] = (uint32_t)(s0 + k);
+    __syncthreads();   // s_wave and s_base are rewritten by the next round
   }
 }
 
@@ -717,7 +732,9 @@ kgs_status kgs_launch_project_bwd(kgs_ctx* ctx, const kgs_gaussians* g, const kg
     hipLaunchKernelGGL(k_pair_fixup, dim3((unsigned)std::min<uint64_t>(std::max<uint64_t>((wins + 255) / 256, 1), 2048)),
                        dim3(256), 0, st, (const uint32_t*)ctx->counters, (const float4*)ctx->seg_head,
                        (const float4*)ctx->seg_tail, ctx->slot_bwd, ctx->slot_om, ctx->counters + KGS_CNT_LIVE);
-    hipLaunchKernelGGL(k_slot_split, dim3(sg), dim3(KGS_BLOCK), 0, st, ctx->counters,
+    const unsigned spg = (unsigned)std::min<uint64_t>(std::max<uint64_t>((cap + 8 * KGS_BLOCK - 1) / (8 * KGS_BLOCK), 1),
+                                                      4096);
+    hipLaunchKernelGGL(k_slot_split, dim3(spg), dim3(KGS_BLOCK), 0, st, ctx->counters,
                        (const uint32_t*)ctx->slot_om, ctx->slot_live);
 #define KGS_PB(D)                                                                                                  \
   hipLaunchKernelGGL(k_slot_live<D>, dim3(sg), dim3(KGS_BLOCK), 0, st, *g, (const CamDev*)ctx->cams, P,            \
