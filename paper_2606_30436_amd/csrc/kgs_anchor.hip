@@ -24,11 +24,15 @@
 // FP32 evaluation, so the same Gaussians blend), and each wave ORs the 64-bit
 // ballot of "blended here" of every entry into an LDS hash table keyed by the
 // entry's anchor: a pixel then counts once per anchor however many of its
-// children blend there.  At the end of the walk each table entry adds the
-// popcount of its union (and of the union with the error mask) to the anchor's
-// counters -- integer atomics, so the sums do not depend on their order.  A
-// sub-block whose distinct anchors do not fit the table is walked again for
-// each half of the anchors (split by hash bits) until every part fits.
+// children blend there.  The ballots of a batch's entries are kept one per
+// lane and inserted together after the batch (lane j inserts entry j: a key
+// claimed by compare-and-swap, the ballot ORed in atomically), so the table
+// probes of a batch overlap instead of following one another.  At the end of
+// the walk each table entry adds the popcount of its union (and of the union
+// with the error mask) to the anchor's counters -- integer atomics, so the sums
+// do not depend on their order.  A sub-block whose distinct anchors do not fit
+// the table is walked again for each half of the anchors (split by hash bits)
+// until every part fits.
 #include <cmath>
 
 #include "kgs_internal.h"
@@ -217,6 +221,7 @@ __global__ __launch_bounds__(64 * NW) void k_anchor_footprint(AnchorStatParams A
   __shared__ uint32_t s_key[NW][AS_TCAP];
   __shared__ uint64_t s_mask[NW][AS_TCAP];
   __shared__ uint32_t s_stack[NW][64];
+  __shared__ uint32_t s_used[NW];
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
   const int gt = blockIdx.x;
   const int v = gt / P.n_tiles, t = gt - v * P.n_tiles;
@@ -250,9 +255,12 @@ __global__ __launch_bounds__(64 * NW) void k_anchor_footprint(AnchorStatParams A
     const uint32_t item = s_stack[w][sp];
     const uint32_t part = item & 0xffffu, bits = item >> 16;
     const uint32_t pmask = bits >= 32 ? 0xffffffffu : ((1u << bits) - 1u);
-    for (int q = l; q < AS_TCAP; q += 64) s_key[w][q] = AS_EMPTY;
+    for (int q = l; q < AS_TCAP; q += 64) {
+      s_key[w][q] = AS_EMPTY;
+      s_mask[w][q] = 0ull;
+    }
+    if (l == 0) s_used[w] = 0u;
     __builtin_amdgcn_wave_barrier();
-    int used = 0;
     bool overflow = false;
     float T = inside ? 1.0f : -1.0f;
     for (uint32_t base = start; base < end && !overflow; base += 64) {
@@ -285,6 +293,9 @@ __global__ __launch_bounds__(64 * NW) void k_anchor_footprint(AnchorStatParams A
       }
       __builtin_amdgcn_wave_barrier();
       const uint32_t len = (uint32_t)__popcll(bal);
+      // lane j keeps the ballot of entry j (the pixels where it blends)
+      uint64_t my_tb = 0ull;
+      uint32_t nd = 0;
       for (uint32_t j = 0; j < len; ++j) {
         if (!__any(T > 0.f)) break;
         const float4 a0 = s_rec[w][j][0], a1 = s_rec[w][j][1];
@@ -295,35 +306,31 @@ __global__ __launch_bounds__(64 * NW) void k_anchor_footprint(AnchorStatParams A
         const float Tn = T * (1.0f - a);
         const bool stop = hit && Tn < P.tmin;
         const bool take = hit && !stop;
-        T = take ? Tn : (stop ? -T : T);
+        T = stop ? -T : Tn;   // a pixel that does not blend has a = 0, so Tn = T exactly
         const uint64_t tb = ballot64(take);
-        const uint32_t anc = __float_as_uint(s_rec[w][j][2].w);
-        if (tb == 0 || anc >= (uint32_t)n_anchor || (as_mix(anc) & pmask) != part) continue;
-        // wave-uniform insertion: every lane reads the same slots; lane 0 writes
-        uint32_t h = (as_mix(anc) >> bits) & (AS_TCAP - 1);
-        for (int probe = 0; probe < AS_TCAP; ++probe) {
-          const uint32_t key = s_key[w][h];
-          if (key == anc) {
-            if (l == 0) s_mask[w][h] |= tb;
-            break;
-          }
-          if (key == AS_EMPTY) {
-            if (used >= AS_TCAP * 3 / 4) {
-              overflow = true;
+        my_tb = (uint32_t)l == j ? tb : my_tb;
+        nd = j + 1;
+      }
+      // the batch's entries into the table, one per lane
+      bool over = false;
+      if ((uint32_t)l < nd && my_tb != 0ull) {
+        const uint32_t anc = __float_as_uint(s_rec[w][l][2].w);
+        if (anc < (uint32_t)n_anchor && (as_mix(anc) & pmask) == part) {
+          uint32_t h = (as_mix(anc) >> bits) & (AS_TCAP - 1);
+          for (int probe = 0; probe < AS_TCAP; ++probe) {
+            const uint32_t key = atomicCAS(&s_key[w][h], AS_EMPTY, anc);
+            if (key == AS_EMPTY || key == anc) {
+              // a new key counts against the table's fill limit; at most 64
+              // claims per batch past the limit still leave free slots
+              if (key == AS_EMPTY && atomicAdd(&s_used[w], 1u) >= AS_TCAP * 3 / 4) over = true;
+              atomicOr(reinterpret_cast<unsigned long long*>(&s_mask[w][h]), (unsigned long long)my_tb);
               break;
             }
-            if (l == 0) {
-              s_key[w][h] = anc;
-              s_mask[w][h] = tb;
-            }
-            ++used;
-            break;
+            h = (h + 1) & (AS_TCAP - 1);
           }
-          h = (h + 1) & (AS_TCAP - 1);
         }
-        __builtin_amdgcn_wave_barrier();
-        if (overflow) break;
       }
+      overflow = __any(over);
       __builtin_amdgcn_wave_barrier();
     }
     if (overflow) {

@@ -167,6 +167,48 @@ def test_anchor_footprints_match_oracle(tile):
     assert np.allclose(st.gamma_sum.cpu().numpy()[ok], gam[ok], rtol=1e-6, atol=0)
 
 
+def test_anchor_footprints_with_table_overflow():
+    """1500 faint Gaussians (opacity about 0.01) stacked over a 24x16 image, each its own anchor: every
+    8x8 sub-block meets more distinct anchors than its table holds, so it is walked again for parts of the
+    anchors (split by hash bits).  The counts must still equal the oracle's union statistics."""
+    sc = scenes.tiny_scene(seed=19, n=1500, W=24, H=16, degree=0, depth=(3.0, 5.0), log_scale_mu=-0.5,
+                           log_scale_sigma=0.1, spread=0.2)
+    sc.logits = np.random.default_rng(20).normal(-4.6, 0.2, sc.n).astype(np.float32)
+    A = sc.n
+    anchor_of = np.arange(A)
+    V, H, W = sc.n_views, sc.height, sc.width
+    say(f"[gpu] anchor footprints with table overflow A={A} {W}x{H}")
+    R = Rasterizer(W, H, max_views=V, max_gaussians=sc.n, tile=(16, 16))
+    g = GaussianParams.from_scene(sc)
+    cams = device_cameras(sc.cams)
+    R.project(g, cams)
+    R.bin_sort()
+    img = Image.empty(V, H, W)
+    R.render_fwd(img)
+    target = torch.from_numpy(sc.target).cuda()
+    st = ViewStats.zeros(A)
+    counts = torch.zeros(2 * V * A, dtype=torch.int32, device="cuda")
+    status = torch.zeros(2, dtype=torch.int32, device="cuda")
+    anchor_stats(R, img, torch.from_numpy(anchor_of.astype(np.int32)).cuda(), A, target, None, counts, st, status)
+    torch.cuda.synchronize()
+    assert R.status() == 0 and int(status[0].item()) == 0
+    assert int(status[1].item()) > 0, "no sub-block overflowed its table"
+    ov = oracle.View(sc, 0, oracle_cfg(R))
+    s = ov.anchor_stats(anchor_of, A, sc.target[0], 0.1)
+    pr = ov.proj()
+    bad_g = affected_gaussians(ov) | (rect_hits(ov.stats(sc.target[0], 0.1)["mask_margin"] < 1e-4, pr["fxi"],
+                                                pr["fyi"], pr["rx"], pr["ry"]) & pr["visible"])
+    gom, gka = st.omega_sum.cpu().numpy(), st.kappa_sum.cpu().numpy()
+    mism = (gom != s["omega"]) | (gka != s["kappa"])
+    say(f"  re-walks {int(status[1].item())}, anchors with a footprint {int((s['omega'] > 0).sum())}, "
+        f"mismatches {int(mism.sum())} (flagged {int(bad_g.sum())})")
+    assert (s["omega"] > 0).sum() > 400
+    assert not (mism & ~bad_g).any(), np.flatnonzero(mism & ~bad_g)[:8]
+    # every Gaussian here shares a pixel with one near a threshold, so the flags exclude nothing: the
+    # counts must match outright, up to the flip share allowed elsewhere
+    assert mism.mean() <= MAX_MISMATCH_SHARE
+
+
 def test_anchor_chunk_full_size():
     """200k anchors with 10 children each (2M Gaussians per view) along the 1 km trajectory, the first chunk's
     8 keyframes: per view decode, project, bin + sort, composite, per-anchor footprints, against the oracle's
