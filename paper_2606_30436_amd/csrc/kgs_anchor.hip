@@ -66,14 +66,18 @@ __device__ __forceinline__ f32x4_t ad_mfma(bf16x4_t a, bf16x4_t b, f32x4_t c) {
   return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
 
+// ln sigmoid(z) = min(z, 0) - ln(1 + e^{-|z|}), branch-free; the hardware exp2 / log2 (a few ulp) are far
+// inside the decoded values' tolerance
 __device__ __forceinline__ float log_sigmoid(float z) {
-  return z >= 0.f ? -log1pf(expf(-z)) : z - log1pf(expf(z));
+  return fminf(z, 0.f) - __logf(1.0f + __expf(-fabsf(z)));
 }
+
+__device__ __forceinline__ float sigmoid(float z) { return __fdividef(1.0f, 1.0f + __expf(-z)); }
 
 // ln(tanh y / (1 - tanh y)) for y > 0, without forming 1 - tanh y (which cancels as tanh y -> 1): the ratio
 // is (e^{2y} - 1) / 2, so the logit is ln(expm1(2y) / 2), or 2y - ln 2 + ln(1 - e^{-2y}) once e^{2y} is large.
 __device__ __forceinline__ float tanh_logit(float y) {
-  return y < 0.5f ? logf(0.5f * expm1f(2.0f * y)) : 2.0f * y - 0.69314718055994531f + log1pf(-expf(-2.0f * y));
+  return y < 0.5f ? __logf(0.5f * expm1f(2.0f * y)) : 2.0f * y - 0.69314718055994531f + __logf(1.0f - __expf(-2.0f * y));
 }
 
 struct DecodeParams {
@@ -173,7 +177,7 @@ __global__ __launch_bounds__(256) void k_anchor_decode(DecodeParams P, const flo
       const float* q = s.anc[w][aa];
       G.opacity_logits[j] = q[9] != 0.f && y[0] > 0.f ? tanh_logit(y[0]) : -100.0f;
       for (int ch = 0; ch < 3; ++ch) {
-        const float col = 1.0f / (1.0f + expf(-y[1 + ch]));
+        const float col = sigmoid(y[1 + ch]);
         G.sh[(int64_t)ch * N + j] = (col - 0.5f) / 0.28209479177387814f;
       }
       for (int q = 0; q < 4; ++q) G.quats[(int64_t)q * N + j] = y[4 + q];
