@@ -126,11 +126,9 @@ struct kgs_ctx {
 };
 
 // ---------------------------------------------------------------- helpers
-__device__ __forceinline__ int floordiv_i(int a, int b) {
-  int q = a / b;
-  if ((a % b != 0) && ((a < 0) != (b < 0))) --q;
-  return q;
-}
+// floor(a / b) for b a power of two (every tile width and height is): an
+// arithmetic shift, which rounds toward minus infinity like the floor
+__device__ __forceinline__ int floordiv_pow2(int a, int b) { return a >> __builtin_ctz((unsigned)b); }
 
 // lanes of the wave where pred holds (of those active); the compiler builtin
 // takes the condition as a lane mask, so a compare feeds it without a round
@@ -293,8 +291,8 @@ __device__ __forceinline__ bool project_core(const CamDev& c, const float mu[3],
   p.ry = (int)ey;
   p.fxi = (int)floor(mxd);
   p.fyi = (int)floor(myd);
-  int x0 = floordiv_i(p.fxi - p.rx, tile_w), x1 = floordiv_i(p.fxi + p.rx, tile_w) + 1;
-  int y0 = floordiv_i(p.fyi - p.ry, tile_h), y1 = floordiv_i(p.fyi + p.ry, tile_h) + 1;
+  int x0 = floordiv_pow2(p.fxi - p.rx, tile_w), x1 = floordiv_pow2(p.fxi + p.rx, tile_w) + 1;
+  int y0 = floordiv_pow2(p.fyi - p.ry, tile_h), y1 = floordiv_pow2(p.fyi + p.ry, tile_h) + 1;
   p.x0 = max(x0, 0);
   p.y0 = max(y0, 0);
   p.x1 = min(x1, tiles_x);

@@ -514,8 +514,8 @@ __device__ __forceinline__ uint32_t pair_position(uint32_t first, float xb_f, fl
   const uint32_t xb = __float_as_uint(xb_f), yb = __float_as_uint(yb_f);
   const int xlo = (int)(int16_t)(xb & 0xffffu), xhi = (int)(int16_t)(xb >> 16);
   const int ylo = (int)(int16_t)(yb & 0xffffu);
-  const int x0 = max(floordiv_i(xlo, P.tile_w), 0), x1 = min(floordiv_i(xhi, P.tile_w) + 1, P.tiles_x);
-  const int y0 = max(floordiv_i(ylo, P.tile_h), 0);
+  const int x0 = max(floordiv_pow2(xlo, P.tile_w), 0), x1 = min(floordiv_pow2(xhi, P.tile_w) + 1, P.tiles_x);
+  const int y0 = max(floordiv_pow2(ylo, P.tile_h), 0);
   return first + (uint32_t)((ty - y0) * (x1 - x0) + (tx - x0));
 }
 
