@@ -327,9 +327,11 @@ def main():
     log(f"[bench] chunk roofline: survey {chunk_roof['survey']['t_roof_ms']} ms ({chunk_roof['survey']['frac']}), "
         f"strict {chunk_roof['strict']['t_roof_ms']} ms ({chunk_roof['strict']['frac']}), live pairs {P_live}")
 
-    # ---- plain per-view loop (same library, 16x16 tiles, batch 128, no graph), with and
-    # without a host read of the pair count between projection and sort
+    # ---- plain per-view loop (same library, no graph), with and without a host read of the
+    # pair count between projection and sort; timed at 16x16 tiles with batch 128 and at the
+    # batched chunk's tiling, and the faster of the two taken
     plain_ms = plain_nr_ms = None
+    plain_table = None
     identical = None
     if not args.no_plain:
         P1 = Rasterizer(W, H, 1, N, slot_capacity=int(max_s * 1.25) + 1024,
@@ -361,21 +363,30 @@ def main():
             return P1.decide(pstate, keep_map=False)[0]
 
         reps = max(3, args.steps // 4)
-        timed = {}
-        for host_read in (True, False):
-            for _ in range(2):
-                plain_chunk(host_read)
-            torch.cuda.synchronize()
-            ev0.record(stream)
-            for _ in range(reps):
-                pdec = plain_chunk(host_read)
-            ev1.record(stream)
-            torch.cuda.synchronize()
-            timed[host_read] = ev0.elapsed_time(ev1) / reps
-        plain_ms, plain_nr_ms = timed[True], timed[False]
-        identical = bool(torch.equal(pimg.color, batched_color)) and bool(torch.equal(pdec, batched_dec))
-        log(f"[bench] plain {plain_ms:.3f} ms/chunk ({plain_nr_ms:.3f} without the host read), "
-            f"identical outputs {identical}")
+        plain_tilings = [((16, 16), 128)]
+        if (tuple(best[0]), best[1]) not in plain_tilings:
+            plain_tilings.append((tuple(best[0]), best[1]))
+        plain_table = {}
+        identical = True
+        for tiling in plain_tilings:
+            P1.set_tiling(*tiling)
+            timed = {}
+            for host_read in (True, False):
+                for _ in range(2):
+                    plain_chunk(host_read)
+                torch.cuda.synchronize()
+                ev0.record(stream)
+                for _ in range(reps):
+                    pdec = plain_chunk(host_read)
+                ev1.record(stream)
+                torch.cuda.synchronize()
+                timed[host_read] = ev0.elapsed_time(ev1) / reps
+            plain_table[f"{tiling[0][0]}x{tiling[0][1]}/{tiling[1]}"] = [round(timed[True], 4), round(timed[False], 4)]
+            identical = identical and bool(torch.equal(pimg.color, batched_color)) and bool(torch.equal(pdec, batched_dec))
+        plain_ms = min(v[0] for v in plain_table.values())
+        plain_nr_ms = min(v[1] for v in plain_table.values())
+        log(f"[bench] plain {plain_ms:.3f} ms/chunk ({plain_nr_ms:.3f} without the host read; per tiling, with / "
+            f"without: {plain_table}), identical outputs {identical}")
         del P1
 
     # ---- equal-PSNR fit: 200 Adam steps from the perturbed map, batched graph against the plain loop
@@ -575,7 +586,9 @@ def main():
                    "tile": list(best[0]), "batch": best[1], "visible_per_view": visible, "slots": n_slots,
                    "pairs": n_pairs, "live_pairs": P_live,
                    "plain_loop": "per view: project, host read of the pair count, sort, fwd, loss, bwd; then "
-                                 "stats + decide; 16x16 tiles, batch 128, no graph",
+                                 "stats + decide; no graph; the faster of 16x16 tiles with batch 128 and the "
+                                 "batched chunk's tiling",
+                   "plain_ms_per_tiling": plain_table,
                    "plain_ms_per_chunk": None if plain_ms is None else round(plain_ms, 4),
                    "speedup_vs_plain": None if plain_ms is None else round(plain_ms / ms, 3),
                    "plain_ms_per_chunk_no_host_read": None if plain_nr_ms is None else round(plain_nr_ms, 4),
