@@ -2,7 +2,9 @@
 // compositing backward.
 //
 // One workgroup per (view, tile); each wave owns an 8x8 sub-block of the tile
-// (four waves for 256-pixel tiles, eight for 512-pixel ones).  Every wave
+// (four waves for 256-pixel tiles, eight for 512-pixel ones), or in a launch
+// large enough to fill the device a 16x8 block with two pixels per lane (half
+// the waves).  Every wave
 // reads the tile's depth-sorted records itself, a batch at a time, tests each
 // against its own sub-block (the integer rectangle, then the exact minimum of
 // the conic over the sub-block's pixel-centre box, with a margin that keeps the
