@@ -498,6 +498,27 @@ def main():
         # per candidate: key 8 B, slot read + claim 16 B, index and anchor out 8 B; the 2^22-slot clear
         adjacent["map_insert"] = hbm_row(t_ins, 32 * n_spawn + 16 * (1 << 22), candidates=n_spawn,
                                          new_anchors=int(n1.item()))
+        # map maintenance on the chunk's 2M Gaussians: the survivors of the chunk's decision gathered into a
+        # compacted map, and every Gaussian moved rigidly with its keyframe's pose update (Gaussian i tied to
+        # keyframe i mod V, each keyframe's pose replaced by the next one's)
+        from paper_2606_30436_amd import _lib as L
+        dec_m, keep_m, nk_m = R.decide(state, keep_map=True)
+        n_keep = int(nk_m.item())
+        cm = [torch.empty(3, max(n_keep, 1), device=dev), torch.empty(3, max(n_keep, 1), device=dev),
+              torch.empty(4, max(n_keep, 1), device=dev), torch.empty(max(n_keep, 1), device=dev),
+              torch.empty(16, 3, max(n_keep, 1), device=dev)]
+        cm_out = gaussians_out(*cm, sh_degree=3)
+        t_cmp = timed(lambda: L.kgs_map_compact(g.c(), dec_m, keep_m, cm_out))
+        # decision byte and keep-map entry per Gaussian, 236 B read and 236 B written per survivor
+        adjacent["map_compact"] = hbm_row(t_cmp, 5 * N + 2 * 236 * n_keep, survivors=n_keep)
+        al_means, al_quats = g.means.clone(), g.quats.clone()
+        kf_of = torch.arange(N, device=dev, dtype=torch.int32) % V
+        cam_rows = cams.view(V, -1)
+        new_poses = torch.cat([cam_rows[1:], cam_rows[:1]]).reshape(-1).contiguous()
+        t_al = timed(lambda: L.kgs_map_align(al_means, al_quats, N, kf_of, cams, new_poses, V))
+        # mean and quaternion read and written, keyframe index read
+        adjacent["map_align"] = hbm_row(t_al, 60 * N, gaussians=N)
+        del cm, cm_out, al_means, al_quats
         # decoded Gaussians of 200k voxel anchors with 10 children each (2M Gaussians) for one keyframe, and
         # their per-anchor union footprints after compositing
         asc = scenes.make_anchor_scene()
