@@ -533,6 +533,24 @@ def main():
         # per anchor 276 B in (p, f, log l, 10 offsets, level), per child 56 B out
         adjacent["anchor_decode"] = hbm_row(t_dec, 276 * A_n + 56 * A_n * K_n, anchors=A_n, children=K_n,
                                             view="the fifth keyframe")
+        # the anchors re-voxelised (after an alignment moved them): a freshly cleared 2^19-slot table, the
+        # lowest index of each voxel kept, survivors renumbered
+        rvm = VoxelMap(19, A_n)
+        rv_means = torch.from_numpy(np.ascontiguousarray(asc["p"], dtype=np.float32)).to(dev)
+        rv_level = torch.from_numpy(np.ascontiguousarray(asc["level"], dtype=np.int32)).to(dev)
+        rv_keep = torch.empty(A_n, dtype=torch.uint8, device=dev)
+        rv_anchor = torch.empty(A_n, dtype=torch.int32, device=dev)
+        rv_n = torch.zeros(1, dtype=torch.int32, device=dev)
+
+        def revoxelize():
+            rvm.clear()
+            rvm.revoxelize(rv_means, rv_level, rv_keep, rv_anchor, rv_n)
+        t_rv = timed(revoxelize)
+        # per anchor: mean and level in, the voxel's slot probed and claimed (16 B), keep flag and new index out;
+        # the 8 MB table clear
+        adjacent["map_revoxelize"] = hbm_row(t_rv, (16 + 16 + 5) * A_n + 16 * (1 << 19), anchors=A_n,
+                                             survivors=int(rv_n.item()))
+        del rvm
         RA = Rasterizer(W, H, 1, A_n * K_n, slot_capacity=A_n * K_n, pair_capacity=40_000_000, tile=best[0],
                         batch=best[1])
         RA.project(dec, acams[4])
