@@ -120,6 +120,7 @@ struct kgs_ctx {
   int last_degree;
   int tile_bits;                      // pair keys: (view << tile_bits) | tile, from the last bin_sort
   int sorted_buf;                     // which ping-pong buffer holds the sorted pairs
+  int pair_keys_written;              // 0: the sorted keys were not written (single-pass tile sort)
   const uint32_t* perm;               // slots in (view, depth) order, from the last bin_sort
   int projected, binned, pixels_done;   // call order: project, bin_sort, (render_fwd,) render_bwd_pixels, project_bwd
   int proj_tile_w, proj_tile_h;

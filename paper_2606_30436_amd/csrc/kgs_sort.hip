@@ -150,11 +150,12 @@ __global__ __launch_bounds__(256) void k_radix_scan(uint32_t* __restrict__ hist,
 }
 
 // Stable scatter of one block's partition, a tile of 256 x KPT keys at a time
-// (IDV: no values in, the keys' input positions are the values).
+// (IDV: no values in, the keys' input positions are the values; WK: the keys
+// are written out, which the last pass of the tile sort skips).
 // Wave w ranks keys [w * 64 KPT, (w + 1) * 64 KPT) of the tile in index order.
 // For the block-wide prefixes each thread owns DPT = 2^DB / 256 consecutive
 // digits.
-template <typename K, int KPT, int DB, bool IDV>
+template <typename K, int KPT, int DB, bool IDV, bool WK>
 __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t* __restrict__ count, const K* __restrict__ kin,
                                                        const uint32_t* __restrict__ vin, int shift, int dbits,
                                                        uint32_t nb, const uint32_t* __restrict__ offsets,
@@ -263,7 +264,7 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t* __restric
       const K key = lk[i];
       const uint32_t d = (uint32_t)(key >> shift) & dmask;
       const uint32_t g = gofs[d] + (i - dstart[d]);
-      kout[g] = key;
+      if (WK) kout[g] = key;
       vout[g] = lv[i];
     }
     __syncthreads();
@@ -474,6 +475,35 @@ __global__ __launch_bounds__(256) void k_pairoff_copy(const uint32_t* __restrict
     slot_pairoff[s] = __float_as_uint(slot_rec[(size_t)s * 4 + 3].x);
 }
 
+// The sorted pair keys, for the debug view, when the single-pass tile sort did
+// not write them: padding (all ones) everywhere, then (view << tile_bits) | tile
+// over each (view, tile) range (one block per range).
+__global__ __launch_bounds__(256) void k_keys_fill(const uint32_t* __restrict__ counters, uint32_t* __restrict__ keys) {
+  const uint32_t n = counters[1];
+  for (uint32_t k = blockIdx.x * 256 + threadIdx.x; k < n; k += gridDim.x * 256) keys[k] = 0xffffffffu;
+}
+
+__global__ __launch_bounds__(256) void k_keys_from_ranges(const uint2* __restrict__ ranges, uint32_t tiles_per_view,
+                                                          int tile_bits, uint32_t* __restrict__ keys) {
+  const uint32_t r = blockIdx.x, v = r / tiles_per_view, t = r - v * tiles_per_view;
+  const uint2 g = ranges[r];
+  for (uint32_t k = g.x + threadIdx.x; k < g.y; k += 256) keys[k] = (v << tile_bits) | t;
+}
+
+kgs_status kgs_launch_pair_keys(kgs_ctx* ctx, hipStream_t st) {
+  if (ctx->pair_keys_written || !ctx->binned) return KGS_OK;
+  uint32_t* keys = ctx->keys[ctx->sorted_buf];
+  const uint64_t P = (uint64_t)ctx->cfg.pair_capacity;
+  hipLaunchKernelGGL(k_keys_fill, dim3((unsigned)std::min<uint64_t>(std::max<uint64_t>((P + 255) / 256, 1), 4096)),
+                     dim3(256), 0, st, (const uint32_t*)ctx->counters, keys);
+  const uint32_t n_ranges = (uint32_t)(ctx->last_views * ctx->n_tiles);
+  if (n_ranges > 0)
+    hipLaunchKernelGGL(k_keys_from_ranges, dim3(n_ranges), dim3(256), 0, st, (const uint2*)ctx->ranges,
+                       (uint32_t)ctx->n_tiles, ctx->tile_bits, keys);
+  ctx->pair_keys_written = 1;
+  return kgs_check_launch();
+}
+
 kgs_status kgs_launch_pairoff_copy(kgs_ctx* ctx, hipStream_t st) {
   const uint64_t S = (uint64_t)ctx->cfg.slot_capacity;
   hipLaunchKernelGGL(k_pairoff_copy, dim3((unsigned)std::min<uint64_t>(std::max<uint64_t>((S + 255) / 256, 1), 4096)),
@@ -523,6 +553,67 @@ __device__ __forceinline__ uint32_t len_bucket(uint32_t n) {
   return min(1u + lz * 8u + frac, 255u);
 }
 
+// Ranges of a single-pass tile sort, whose sorted keys are not written: tile
+// t's pairs are the run [S_t, S_t + n_t) (S the exclusive sum of the digit
+// totals, in digit order, as the scatter placed them), and inside the run the
+// views come in order (emission is view-major and the sort stable).  A slot's
+// view follows from its index, slots being view-major: view >= v exactly when
+// the slot is at least view v's first slot.  So each (view, tile) range is two
+// binary searches in its tile's run.  Every range is written (empty ones as
+// (0, 0)).
+__global__ __launch_bounds__(256) void k_ranges_by_slot(const uint32_t* __restrict__ counters,
+                                                        const uint32_t* __restrict__ total, int n_digits,
+                                                        const uint32_t* __restrict__ sorted_slot,
+                                                        const uint32_t* __restrict__ blk_base, int64_t nb,
+                                                        uint32_t tiles_per_view, uint32_t n_views,
+                                                        uint2* __restrict__ ranges) {
+  __shared__ uint32_t s_start[KGS_RADIX_BUCKETS];
+  __shared__ uint32_t s_vb[KGS_MAX_VIEWS + 1];
+  __shared__ uint32_t s_w[4];
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  const uint32_t n_slots = counters[0];
+  // digit starts: exclusive scan of the totals, four digits per thread
+  {
+    uint32_t t[4], ts = 0u;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int d = 4 * tid + k;
+      t[k] = d < n_digits ? total[d] : 0u;
+      ts += t[k];
+    }
+    const uint32_t inc = wave_inclusive_scan(ts);
+    if (l == 63) s_w[w] = inc;
+    __syncthreads();
+    uint32_t ex = inc - ts;
+    for (int k = 0; k < w; ++k) ex += s_w[k];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      s_start[4 * tid + k] = ex;
+      ex += t[k];
+    }
+  }
+  for (uint32_t v = tid; v <= n_views; v += 256)
+    s_vb[v] = v < n_views ? min(blk_base[((int64_t)v * nb) * 2], n_slots) : n_slots;
+  __syncthreads();
+  const uint32_t n_ranges = tiles_per_view * n_views;
+  for (uint32_t r = blockIdx.x * 256 + tid; r < n_ranges; r += gridDim.x * 256) {
+    const uint32_t v = r / tiles_per_view, t = r - v * tiles_per_view;
+    const uint32_t a = s_start[t], e = a + total[t];
+    // first position in [a, e) whose slot is at least `bound`
+    auto first_at_least = [&](uint32_t bound) {
+      uint32_t lo = a, hi = e;
+      while (lo < hi) {
+        const uint32_t mid = lo + ((hi - lo) >> 1);
+        if (sorted_slot[mid] < bound) lo = mid + 1; else hi = mid;
+      }
+      return lo;
+    };
+    const uint32_t lo = first_at_least(s_vb[v]), hi = first_at_least(s_vb[v + 1]);
+    ranges[r] = lo < hi ? make_uint2(lo, hi) : make_uint2(0u, 0u);   // an empty range is (0, 0), as k_ranges leaves it
+  }
+}
+
+
 __global__ __launch_bounds__(1024) void k_tile_order(const uint2* __restrict__ ranges, uint32_t n_tiles_all,
                                                      uint32_t* __restrict__ order) {
   __shared__ uint32_t cnt[256], off[256];
@@ -567,16 +658,20 @@ static void radix_plan(int bits, int max_dbits, int& passes, int& dbits) {
 // KPT keys per thread in a scatter tile: 16 (8 for 8-byte keys).
 template <typename K, int KPT, int DB, bool AGG>
 static void radix_pass(kgs_ctx* ctx, const uint32_t* count, uint32_t nb, const K* kin, const uint32_t* vin,
-                       int shift, int dbits, uint32_t* total, K* kout, uint32_t* vout, hipStream_t st) {
+                       int shift, int dbits, uint32_t* total, K* kout, uint32_t* vout, bool write_keys,
+                       hipStream_t st) {
   hipLaunchKernelGGL((k_radix_hist<K, DB, AGG>), dim3(nb), dim3(256), 0, st, count, kin, shift, dbits, nb,
                      ctx->radix_hist);
   hipLaunchKernelGGL(k_radix_scan, dim3(1u << dbits), dim3(256), 0, st, ctx->radix_hist, nb, total);
-  if (vin)
-    hipLaunchKernelGGL((k_radix_scatter<K, KPT, DB, false>), dim3(nb), dim3(256), 0, st, count, kin, vin, shift,
-                       dbits, nb, (const uint32_t*)ctx->radix_hist, (const uint32_t*)total, kout, vout);
-  else
-    hipLaunchKernelGGL((k_radix_scatter<K, KPT, DB, true>), dim3(nb), dim3(256), 0, st, count, kin, vin, shift,
-                       dbits, nb, (const uint32_t*)ctx->radix_hist, (const uint32_t*)total, kout, vout);
+#define KGS_SCATTER(IDV, WK)                                                                                      \
+  hipLaunchKernelGGL((k_radix_scatter<K, KPT, DB, IDV, WK>), dim3(nb), dim3(256), 0, st, count, kin, vin, shift,  \
+                     dbits, nb, (const uint32_t*)ctx->radix_hist, (const uint32_t*)total, kout, vout)
+  if (vin) {
+    if (write_keys) KGS_SCATTER(false, true); else KGS_SCATTER(false, false);
+  } else {
+    if (write_keys) KGS_SCATTER(true, true); else KGS_SCATTER(true, false);
+  }
+#undef KGS_SCATTER
 }
 
 // vals_in: the values of the first pass (null: the key positions); agg: the
@@ -584,7 +679,7 @@ static void radix_pass(kgs_ctx* ctx, const uint32_t* count, uint32_t nb, const K
 // depth keys' views and exponents) rather than single keys.
 template <typename K>
 static int radix_sort(kgs_ctx* ctx, const uint32_t* count, uint64_t cap, K* keys[2], uint32_t* vals[2], int bits,
-                      int max_dbits, bool agg, hipStream_t st, const uint32_t* vals_in) {
+                      int max_dbits, bool agg, hipStream_t st, const uint32_t* vals_in, bool last_keys = true) {
   int passes, dbits;
   radix_plan(bits, max_dbits, passes, dbits);
   // partitions: fewer for small sorts (a multiple of 256, at most KGS_SORT_BLOCKS): more would only add
@@ -598,7 +693,8 @@ static int radix_sort(kgs_ctx* ctx, const uint32_t* count, uint64_t cap, K* keys
     uint32_t* total = ctx->radix_total + KGS_RADIX_BUCKETS * p;
     K* ko = keys[cur ^ 1];
     uint32_t* vo = vals[cur ^ 1];
-#define KGS_RPASS(DB, AG) radix_pass<K, KPT, DB, AG>(ctx, count, nb, kin, vin, dbits * p, dbits, total, ko, vo, st)
+    const bool wk = last_keys || p + 1 < passes;
+#define KGS_RPASS(DB, AG) radix_pass<K, KPT, DB, AG>(ctx, count, nb, kin, vin, dbits * p, dbits, total, ko, vo, wk, st)
     if (dbits > 8) {
       if (agg) KGS_RPASS(10, true); else KGS_RPASS(10, false);
     } else {
@@ -658,16 +754,30 @@ kgs_status kgs_launch_bin_sort(kgs_ctx* ctx, hipStream_t st) {
                      ctx->tiles_x, ctx->tiles_y, ctx->keys[0], ctx->pair_slot);
   // 3. pairs by tile within the view (stable): the view bits above stay in the
   // keys but out of the sort, so a (view, tile) group stays in emission order
+  // With one pass (tile bits <= 10) the sorted keys are not written: the
+  // ranges come from the digit totals and the slots; with two, from the keys.
+  int tpasses, tdbits;
+  radix_plan(ctx->tile_bits, 10, tpasses, tdbits);
+  const bool one_pass = tpasses == 1;
   const int cur = radix_sort<uint32_t>(ctx, ctx->counters + 1, P, ctx->keys, ctx->vals, ctx->tile_bits, 10, false, st,
-                                       ctx->pair_slot);
+                                       ctx->pair_slot, !one_pass);
   ctx->sorted_buf = cur;
-  const uint64_t nr = (uint64_t)n_tiles_all * 2;
-  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)std::min<uint64_t>((nr + 255) / 256, 1024)), dim3(256), 0, st,
-                     (uint32_t*)ctx->ranges, nr, 0u);
-  const unsigned rg = (unsigned)std::min<uint64_t>(std::max<uint64_t>((P + KGS_BLOCK - 1) / KGS_BLOCK, 1), 8192);
-  hipLaunchKernelGGL(k_ranges, dim3(rg), dim3(KGS_BLOCK), 0, st, (const uint32_t*)ctx->counters,
-                     (const uint32_t*)ctx->keys[cur], ctx->tile_bits, (uint32_t)ctx->n_tiles, (uint32_t)V,
-                     ctx->ranges);
+  ctx->pair_keys_written = one_pass ? 0 : 1;
+  if (one_pass) {
+    const int64_t nbp = (ctx->last_n + KGS_BLOCK - 1) / KGS_BLOCK;   // the projection's blocks per view
+    const unsigned rg = (unsigned)std::min<uint64_t>(std::max<uint64_t>((n_tiles_all + 255) / 256, 1), 1024);
+    hipLaunchKernelGGL(k_ranges_by_slot, dim3(rg), dim3(256), 0, st, (const uint32_t*)ctx->counters,
+                       (const uint32_t*)ctx->radix_total, 1 << tdbits, (const uint32_t*)ctx->vals[cur],
+                       (const uint32_t*)ctx->blk_base, nbp, (uint32_t)ctx->n_tiles, (uint32_t)V, ctx->ranges);
+  } else {
+    const uint64_t nr = (uint64_t)n_tiles_all * 2;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)std::min<uint64_t>((nr + 255) / 256, 1024)), dim3(256), 0, st,
+                       (uint32_t*)ctx->ranges, nr, 0u);
+    const unsigned rg = (unsigned)std::min<uint64_t>(std::max<uint64_t>((P + KGS_BLOCK - 1) / KGS_BLOCK, 1), 8192);
+    hipLaunchKernelGGL(k_ranges, dim3(rg), dim3(KGS_BLOCK), 0, st, (const uint32_t*)ctx->counters,
+                       (const uint32_t*)ctx->keys[cur], ctx->tile_bits, (uint32_t)ctx->n_tiles, (uint32_t)V,
+                       ctx->ranges);
+  }
   hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, st, (const uint2*)ctx->ranges, n_tiles_all,
                      ctx->tile_order);
   ctx->sorted_slot = ctx->vals[cur];
