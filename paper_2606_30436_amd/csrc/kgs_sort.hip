@@ -725,15 +725,16 @@ kgs_status kgs_launch_bin_sort(kgs_ctx* ctx, hipStream_t st) {
                          (const float4*)ctx->slot_rec, (const uint32_t*)ctx->slot_view, KL.depth_lo, KL.depth_bits,
                          k32[0]);
     sc = radix_sort<uint32_t>(ctx, ctx->counters, S, k32, ctx->slot_vals, key_bits, KGS_DEPTH_DIGIT_BITS, true, st,
-                              nullptr);
+                              nullptr, false);
   } else {
     if (!ctx->slot_keys_ready)
       hipLaunchKernelGGL(k_slot_keys<uint64_t>, dim3(sgrid), dim3(KGS_BLOCK), 0, st, (const uint32_t*)ctx->counters,
                          (const float4*)ctx->slot_rec, (const uint32_t*)ctx->slot_view, KL.depth_lo, KL.depth_bits,
                          ctx->slot_keys[0]);
     sc = radix_sort<uint64_t>(ctx, ctx->counters, S, ctx->slot_keys, ctx->slot_vals, key_bits, KGS_DEPTH_DIGIT_BITS,
-                              true, st, nullptr);
+                              true, st, nullptr, false);
   }
+  // only the order is used: the last pass writes no keys (the buffer is scratch afterwards)
   ctx->slot_keys_ready = 0;
   const uint32_t* perm = ctx->slot_vals[sc];
   ctx->perm = perm;
