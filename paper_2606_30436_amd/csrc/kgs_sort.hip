@@ -599,17 +599,24 @@ __global__ __launch_bounds__(256) void k_ranges_by_slot(const uint32_t* __restri
   for (uint32_t r = blockIdx.x * 256 + tid; r < n_ranges; r += gridDim.x * 256) {
     const uint32_t v = r / tiles_per_view, t = r - v * tiles_per_view;
     const uint32_t a = s_start[t], e = a + total[t];
-    // first position in [a, e) whose slot is at least `bound`
-    auto first_at_least = [&](uint32_t bound) {
-      uint32_t lo = a, hi = e;
-      while (lo < hi) {
-        const uint32_t mid = lo + ((hi - lo) >> 1);
-        if (sorted_slot[mid] < bound) lo = mid + 1; else hi = mid;
+    // the first positions in [a, e) whose slot is at least view v's first slot
+    // and at least view v + 1's: two binary searches, stepped together so that
+    // their dependent loads overlap
+    const uint32_t b0 = s_vb[v], b1 = s_vb[v + 1];
+    uint32_t lo0 = a, hi0 = e, lo1 = a, hi1 = e;
+    while (lo0 < hi0 || lo1 < hi1) {
+      const bool go0 = lo0 < hi0, go1 = lo1 < hi1;
+      const uint32_t m0 = lo0 + ((hi0 - lo0) >> 1), m1 = lo1 + ((hi1 - lo1) >> 1);
+      const uint32_t x0 = go0 ? sorted_slot[m0] : 0u, x1 = go1 ? sorted_slot[m1] : 0u;
+      if (go0) {
+        if (x0 < b0) lo0 = m0 + 1; else hi0 = m0;
       }
-      return lo;
-    };
-    const uint32_t lo = first_at_least(s_vb[v]), hi = first_at_least(s_vb[v + 1]);
-    ranges[r] = lo < hi ? make_uint2(lo, hi) : make_uint2(0u, 0u);   // an empty range is (0, 0), as k_ranges leaves it
+      if (go1) {
+        if (x1 < b1) lo1 = m1 + 1; else hi1 = m1;
+      }
+    }
+    // an empty range is (0, 0), as k_ranges leaves it
+    ranges[r] = lo0 < lo1 ? make_uint2(lo0, lo1) : make_uint2(0u, 0u);
   }
 }
 
