@@ -13,6 +13,7 @@ kgs_status kgs_launch_project(kgs_ctx*, const kgs_gaussians*, const kgs_camera*,
 kgs_status kgs_launch_bin_sort(kgs_ctx*, hipStream_t);
 kgs_status kgs_launch_pairoff_copy(kgs_ctx*, hipStream_t);
 kgs_status kgs_launch_pair_keys(kgs_ctx*, hipStream_t);
+kgs_status kgs_launch_slot_view_copy(kgs_ctx*, hipStream_t);
 kgs_status kgs_launch_render_fwd(kgs_ctx*, const kgs_image*, hipStream_t);
 kgs_status kgs_launch_loss(kgs_ctx*, const float*, const kgs_image*, float*, float*, hipStream_t);
 kgs_status kgs_launch_render_bwd(kgs_ctx*, const kgs_image*, const float*, const float*, const float*,
@@ -642,10 +643,11 @@ kgs_status kgs_counts_read(kgs_ctx* ctx, int64_t* n_slots, int64_t* n_pairs) {
 
 kgs_status kgs_get_buffers(kgs_ctx* ctx, kgs_buffers* b) {
   if (!ctx || !b) return KGS_ERR_INVALID_ARG;
-  // the per-record first pairs live in the records, and a single-pass tile sort
-  // leaves the sorted keys implicit in the ranges: the flat views are filled here
+  // the per-record first pairs live in the records, the slots' views in their
+  // emission descriptors, and a single-pass tile sort leaves the sorted keys
+  // implicit in the ranges: the flat views are filled here
   if (kgs_launch_pairoff_copy(ctx, nullptr) != KGS_OK || kgs_launch_pair_keys(ctx, nullptr) != KGS_OK ||
-      hipDeviceSynchronize() != hipSuccess)
+      kgs_launch_slot_view_copy(ctx, nullptr) != KGS_OK || hipDeviceSynchronize() != hipSuccess)
     return KGS_ERR_HIP;
   b->n_slots = ctx->counters;
   b->n_pairs = ctx->counters + 1;

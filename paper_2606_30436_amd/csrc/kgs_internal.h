@@ -79,10 +79,10 @@ struct kgs_ctx {
   uint32_t* counters;                 // [64]: 0 n_slots, 1 n_pairs, 2 status, 4 live slots, others free
   float4* slot_rec;                   // [S][4] compositing records, 64 bytes (the last: first pair)
   uint32_t* slot_gid;                 // [S]
-  uint32_t* slot_view;                // [S]
+  uint32_t* slot_view;                // [S] debug view only (filled from emit_desc on request)
+  uint32_t* slot_ntiles;              // [S] tiles of each slot's rectangle (also in emit_desc.w)
   int4* slot_pix;                     // [S]
   uint32_t* slot_pairoff;             // [S]
-  uint32_t* slot_ntiles;              // [S]
   uint32_t* keys[2];                  // [P] ping-pong: global tile index of each pair
   uint32_t* vals[2];                  // [P] ping-pong (pair emission position)
   uint64_t* slot_keys[2];             // [S] ping-pong: (view << 32) | depth bits
@@ -101,7 +101,7 @@ struct kgs_ctx {
   float4* seg_tail;                   // [P / 64 + 1][4] and its last segment's
   float2* slot_pose;                  // [S][3] pose contributions (rho, phi) of every slot
   uint32_t* slot_live;                // [S] slots whose pixels blended somewhere, for the chain rule
-  uint32_t* slot_om;                  // [S] pixels the slot blended (|Omega|), 0 until a backward sums them
+  uint32_t* slot_om;                  // [S] pixels the slot blended (|Omega|): cleared by each compositing backward, set by its pair sums
   uint32_t* chunk_first;              // [P / 2048 + 2] record owning the first pair of each emission chunk
   uint4* emit_rec;                    // [S] emission descriptor of each record, in depth order
   uint4* emit_desc;                   // [S] the same without the record index, in record order (projection)

@@ -183,9 +183,8 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_emit(kgs_gaussians g, const CamDe
                                                     const uint32_t* __restrict__ blk_base, int64_t nb,
                                                     uint64_t slot_cap,
                                                     float4* __restrict__ slot_rec, uint32_t* __restrict__ slot_gid,
-                                                    uint32_t* __restrict__ slot_view, int4* __restrict__ slot_pix,
-                                                    uint32_t* __restrict__ slot_ntiles, void* __restrict__ slot_keys,
-                                                    uint32_t* __restrict__ slot_om, uint4* __restrict__ emit_desc,
+                                                    int4* __restrict__ slot_pix, uint32_t* __restrict__ slot_ntiles,
+                                                    void* __restrict__ slot_keys, uint4* __restrict__ emit_desc,
                                                     int tile_bits) {
   constexpr int K = (DEG + 1) * (DEG + 1);
   // visible lanes of each wave, per view: a slot's index is the (view, block)
@@ -292,11 +291,9 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_emit(kgs_gaussians g, const CamDe
       slot_rec[s * 4 + 1] = r1;
       slot_rec[s * 4 + 2] = r2;
       slot_gid[s] = (uint32_t)i;
-      slot_view[s] = (uint32_t)v;
       slot_pix[s] = pix;
-      slot_ntiles[s] = tiles;
-      emit_desc[s] = desc;
-      slot_om[s] = 0u;   // no pixel blended yet (the backward's sums set it)
+      slot_ntiles[s] = tiles;   // dense, for the group sums' gather in depth order
+      emit_desc[s] = desc;      // also the slot's view (above the tile bits) and tile count for the later steps
       // the record's (view, depth) key for the depth sort, from its depth r1.z
       const uint32_t db = __float_as_uint(r1.z);
       const uint32_t dmax = P.depth_bits >= 32 ? 0xffffffffu : (1u << P.depth_bits) - 1u;
@@ -342,8 +339,8 @@ kgs_status kgs_launch_project(kgs_ctx* ctx, const kgs_gaussians* g, const kgs_ca
 #define KGS_EMIT(D)                                                                                              \
   hipLaunchKernelGGL(k_emit<D>, dim3((unsigned)nb), dim3(KGS_BLOCK), 0, st, *g, (const CamDev*)ctx->cams, V, P,   \
                      ctx->vis, (const uint32_t*)ctx->blk_base, nb, (uint64_t)cfg.slot_capacity,                \
-                     ctx->slot_rec, ctx->slot_gid, ctx->slot_view, ctx->slot_pix, ctx->slot_ntiles,            \
-                     (void*)ctx->slot_keys[0], ctx->slot_om, ctx->emit_desc, kgs_tile_bits(ctx->n_tiles))
+                     ctx->slot_rec, ctx->slot_gid, ctx->slot_pix, ctx->slot_ntiles, (void*)ctx->slot_keys[0],  \
+                     ctx->emit_desc, kgs_tile_bits(ctx->n_tiles))
     switch (g->sh_degree) {
       case 0: KGS_EMIT(0); break;
       case 1: KGS_EMIT(1); break;

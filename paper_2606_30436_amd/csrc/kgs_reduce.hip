@@ -215,8 +215,7 @@ __global__ __launch_bounds__(256) void k_pair_fixup(const uint32_t* __restrict__
 template <int DEG>
 __device__ __forceinline__ void slot_record(uint32_t s, uint32_t v, const kgs_gaussians& g,
                                             const CamDev* __restrict__ cams, const BwdParams& P,
-                                            const uint32_t* __restrict__ slot_gid,
-                                            const uint32_t* __restrict__ slot_ntiles, const float r[10],
+                                            const uint32_t* __restrict__ slot_gid, uint32_t tiles, const float r[10],
                                             uint32_t om, uint32_t kap, float4* __restrict__ slot_bwd,
                                             float2* __restrict__ slot_pose) {
   constexpr int K = (DEG + 1) * (DEG + 1);
@@ -228,7 +227,6 @@ __device__ __forceinline__ void slot_record(uint32_t s, uint32_t v, const kgs_ga
 #pragma unroll
     for (int k = 0; k < KGS_SLOT_WORDS; ++k) out[k] = 0.f;
     const int64_t i = slot_gid[s];
-    const uint32_t tiles = slot_ntiles[s];
     GaussLocal G;
     bool bad = false;
     load_gaussian(g, i, P.alpha_min, G, bad);
@@ -484,8 +482,7 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_slot_live(kgs_gaussians g, const 
                                                          BwdParams P, const uint32_t* __restrict__ counters,
                                                          const uint32_t* __restrict__ slot_live,
                                                          const uint32_t* __restrict__ slot_gid,
-                                                         const uint32_t* __restrict__ slot_view,
-                                                         const uint32_t* __restrict__ slot_ntiles,
+                                                         const uint4* __restrict__ emit_desc, int tile_bits,
                                                          float4* __restrict__ slot_bwd,
                                                          float2* __restrict__ slot_pose) {
   const uint32_t n_live = counters[KGS_CNT_LIVE];
@@ -494,14 +491,16 @@ __global__ __launch_bounds__(KGS_BLOCK) void k_slot_live(kgs_gaussians g, const 
     const float4* q = slot_bwd + (size_t)s * (KGS_SLOT_WORDS / 4);
     const float4 a = q[0], b = q[1], c = q[2];
     const float r[10] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x, c.y};
+    // the slot's view and tile count, from the projection's emission descriptor;
     // one view at a time across the wave, so that its camera is read with
     // scalar loads; queued slots keep view order within a wave's share
-    const uint32_t v = slot_view[s];
+    const uint4 dsc = emit_desc[s];
+    const uint32_t v = dsc.x >> tile_bits;
     bool pending = true;
     while (pending) {
       const uint32_t vu = __builtin_amdgcn_readfirstlane(v);
       if (v == vu) {
-        slot_record<DEG>(s, vu, g, cams, P, slot_gid, slot_ntiles, r, __float_as_uint(c.z), __float_as_uint(c.w),
+        slot_record<DEG>(s, vu, g, cams, P, slot_gid, dsc.w, r, __float_as_uint(c.z), __float_as_uint(c.w),
                          slot_bwd, slot_pose);
         pending = false;
       }
@@ -739,8 +738,8 @@ kgs_status kgs_launch_project_bwd(kgs_ctx* ctx, const kgs_gaussians* g, const kg
 #define KGS_PB(D)                                                                                                  \
   hipLaunchKernelGGL(k_slot_live<D>, dim3(sg), dim3(KGS_BLOCK), 0, st, *g, (const CamDev*)ctx->cams, P,            \
                      (const uint32_t*)ctx->counters, (const uint32_t*)ctx->slot_live,                               \
-                     (const uint32_t*)ctx->slot_gid, (const uint32_t*)ctx->slot_view,                              \
-                     (const uint32_t*)ctx->slot_ntiles, ctx->slot_bwd, ctx->slot_pose);                            \
+                     (const uint32_t*)ctx->slot_gid, (const uint4*)ctx->emit_desc, kgs_tile_bits(ctx->n_tiles),   \
+                     ctx->slot_bwd, ctx->slot_pose);                                                               \
   hipLaunchKernelGGL(k_gauss_gather<D>, dim3((unsigned)nb), dim3(KGS_BLOCK), 0, st, *g, V,                        \
                      (const CamDev*)ctx->cams, (const uint32_t*)ctx->vis, (const uint32_t*)ctx->counters,          \
                      (const float4*)ctx->slot_bwd, (const uint32_t*)ctx->slot_om,                                \

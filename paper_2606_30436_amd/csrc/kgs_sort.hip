@@ -360,18 +360,19 @@ __global__ __launch_bounds__(256) void k_slot_offsets(const uint32_t* __restrict
 // [near, far], whose bit patterns are ordered like the values, so the bits
 // minus those of a value just below near keep the order exactly in
 // depth_bits bits (27 for near 0.2, far 80); the view sits above them.
-// The keys are 4 bytes wide when view and depth bits fit in 32.
+// The keys are 4 bytes wide when view and depth bits fit in 32.  The view is
+// the one the projection left above the tile bits of the emission descriptor.
 template <typename K>
 __global__ __launch_bounds__(KGS_BLOCK) void k_slot_keys(const uint32_t* __restrict__ counters,
                                                          const float4* __restrict__ slot_rec,
-                                                         const uint32_t* __restrict__ slot_view, uint32_t depth_lo,
-                                                         int depth_bits, K* __restrict__ keys) {
+                                                         const uint4* __restrict__ emit_desc, int tile_bits,
+                                                         uint32_t depth_lo, int depth_bits, K* __restrict__ keys) {
   const uint32_t n = counters[0];
   const uint32_t dmax = depth_bits >= 32 ? 0xffffffffu : (1u << depth_bits) - 1u;
   for (uint32_t s = blockIdx.x * KGS_BLOCK + threadIdx.x; s < n; s += gridDim.x * KGS_BLOCK) {
     const uint32_t b = __float_as_uint(slot_rec[(size_t)s * 4 + 1].z);
     const uint32_t d = b > depth_lo ? min(b - depth_lo, dmax) : 0u;
-    keys[s] = (K)(((uint64_t)slot_view[s] << depth_bits) | d);
+    keys[s] = (K)(((uint64_t)(emit_desc[s].x >> tile_bits) << depth_bits) | d);
   }
 }
 
@@ -501,6 +502,23 @@ kgs_status kgs_launch_pair_keys(kgs_ctx* ctx, hipStream_t st) {
     hipLaunchKernelGGL(k_keys_from_ranges, dim3(n_ranges), dim3(256), 0, st, (const uint2*)ctx->ranges,
                        (uint32_t)ctx->n_tiles, ctx->tile_bits, keys);
   ctx->pair_keys_written = 1;
+  return kgs_check_launch();
+}
+
+// slot_view[s] for the debug view: the projection keeps each slot's view only
+// in its emission descriptor, above the tile bits.
+__global__ __launch_bounds__(256) void k_slot_view_copy(const uint32_t* __restrict__ counters,
+                                                        const uint4* __restrict__ emit_desc, int tile_bits,
+                                                        uint32_t* __restrict__ slot_view) {
+  const uint32_t n = counters[0];
+  for (uint32_t s = blockIdx.x * 256 + threadIdx.x; s < n; s += gridDim.x * 256) slot_view[s] = emit_desc[s].x >> tile_bits;
+}
+
+kgs_status kgs_launch_slot_view_copy(kgs_ctx* ctx, hipStream_t st) {
+  const uint64_t S = (uint64_t)ctx->cfg.slot_capacity;
+  hipLaunchKernelGGL(k_slot_view_copy, dim3((unsigned)std::min<uint64_t>(std::max<uint64_t>((S + 255) / 256, 1), 4096)),
+                     dim3(256), 0, st, (const uint32_t*)ctx->counters, (const uint4*)ctx->emit_desc,
+                     kgs_tile_bits(ctx->n_tiles), ctx->slot_view);
   return kgs_check_launch();
 }
 
@@ -729,15 +747,15 @@ kgs_status kgs_launch_bin_sort(kgs_ctx* ctx, hipStream_t st) {
     uint32_t* k32[2] = {reinterpret_cast<uint32_t*>(ctx->slot_keys[0]), reinterpret_cast<uint32_t*>(ctx->slot_keys[1])};
     if (!ctx->slot_keys_ready)
       hipLaunchKernelGGL(k_slot_keys<uint32_t>, dim3(sgrid), dim3(KGS_BLOCK), 0, st, (const uint32_t*)ctx->counters,
-                         (const float4*)ctx->slot_rec, (const uint32_t*)ctx->slot_view, KL.depth_lo, KL.depth_bits,
-                         k32[0]);
+                         (const float4*)ctx->slot_rec, (const uint4*)ctx->emit_desc, ctx->tile_bits, KL.depth_lo,
+                         KL.depth_bits, k32[0]);
     sc = radix_sort<uint32_t>(ctx, ctx->counters, S, k32, ctx->slot_vals, key_bits, KGS_DEPTH_DIGIT_BITS, true, st,
                               nullptr, false);
   } else {
     if (!ctx->slot_keys_ready)
       hipLaunchKernelGGL(k_slot_keys<uint64_t>, dim3(sgrid), dim3(KGS_BLOCK), 0, st, (const uint32_t*)ctx->counters,
-                         (const float4*)ctx->slot_rec, (const uint32_t*)ctx->slot_view, KL.depth_lo, KL.depth_bits,
-                         ctx->slot_keys[0]);
+                         (const float4*)ctx->slot_rec, (const uint4*)ctx->emit_desc, ctx->tile_bits, KL.depth_lo,
+                         KL.depth_bits, ctx->slot_keys[0]);
     sc = radix_sort<uint64_t>(ctx, ctx->counters, S, ctx->slot_keys, ctx->slot_vals, key_bits, KGS_DEPTH_DIGIT_BITS,
                               true, st, nullptr, false);
   }
