@@ -400,6 +400,7 @@ def main():
             fp = fit(sc, tgt, "plain", iters=args.fit_steps, tile=best[0], batch=best[1], far_z=FAR, **cap)
             return {"psnr_start_db": round(fb["psnr_start_db"], 4), "batched_psnr_db": round(fb["psnr_db"], 4),
                     "plain_psnr_db": round(fp["psnr_db"], 4), "delta_db": round(fb["psnr_db"] - fp["psnr_db"], 4),
+                    "batched_l1_last_step": round(fb["l1_last_step"], 6), "plain_l1_last_step": round(fp["l1_last_step"], 6),
                     "batched_ms_per_step": round(fb["ms_per_step"], 3), "plain_ms_per_step": round(fp["ms_per_step"], 3)}
 
         # a keyframe is not exactly the render of any map: the targets carry sensor-like pixel noise

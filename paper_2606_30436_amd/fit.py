@@ -32,7 +32,8 @@ def psnr(color: torch.Tensor, target: torch.Tensor) -> float:
 def fit(sc, target: torch.Tensor, mode: str, iters: int = 200, tile=(32, 16), batch: int = 64, far_z: float = 80.0,
         slot_capacity: int = 0, pair_capacity: int = 0) -> dict:
     """mode 'batched' (one graph launch per step) or 'plain' (per-view calls).  Returns the final PSNR, the
-    PSNR before the first step and the time per step (gradient plus Adam)."""
+    PSNR before the first step, the chunk's L1 loss at the last step (the objective, summed over the views)
+    and the time per step (gradient plus Adam)."""
     V, H, W = sc.n_views, sc.height, sc.width
     dev = target.device
     g = GaussianParams.from_scene(sc)
@@ -53,8 +54,9 @@ def fit(sc, target: torch.Tensor, mode: str, iters: int = 200, tile=(32, 16), ba
         graph = R.chunk_capture(desc)
         step_fn = lambda: R.chunk_launch(graph)
     else:
-        R = Rasterizer(W, H, 1, sc.n, slot_capacity=slot_capacity, pair_capacity=pair_capacity, tile=(16, 16),
-                       batch=128, far_z=far_z)
+        # the same tiling as the batched run, so that the two differ only in batching
+        R = Rasterizer(W, H, 1, sc.n, slot_capacity=slot_capacity, pair_capacity=pair_capacity, tile=tile,
+                       batch=batch, far_z=far_z)
         cam_rows = cams.view(V, -1)
 
         def step_fn():
@@ -92,5 +94,6 @@ def fit(sc, target: torch.Tensor, mode: str, iters: int = 200, tile=(32, 16), ba
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     assert R.status() == 0, f"capacity status {R.status()}"
+    l1 = float(loss.double().sum().item())
     p1 = psnr(render_all(), target)
-    return dict(psnr_db=p1, psnr_start_db=p0, ms_per_step=1e3 * dt / iters, iterations=iters)
+    return dict(psnr_db=p1, psnr_start_db=p0, l1_last_step=l1, ms_per_step=1e3 * dt / iters, iterations=iters)
