@@ -521,10 +521,18 @@ kgs_status kgs_launch_head_features(kgs_ctx* ctx, const kgs_gaussians* g, const 
                                     const kgs_lifecycle_state* before, uint16_t* feat, hipStream_t st);
 
 // ---------------------------------------------------------------- compositing (kgs_render.hip, kgs_anchor.hip)
+// a compile-time flag passed as a value (selects a variant of a generic lambda)
+template <bool V>
+struct BoolC {
+  static constexpr bool value = V;
+};
+
 struct RenderParams {
   int W, H, tile_w, tile_h, tiles_x, tiles_y, n_tiles;
   float log2_amin, amax, tmin;
   float bg0, bg1, bg2;
+  // a record with log2 o below this reaches alpha_max at no pixel (see render_params)
+  float log2_amax_lo;
 };
 
 // Whether the footprint {log2 alpha >= log2 alpha_min} of a record can reach
@@ -579,6 +587,11 @@ static inline RenderParams render_params(const kgs_ctx* ctx) {
   P.bg0 = ctx->cfg.bg[0];
   P.bg1 = ctx->cfg.bg[1];
   P.bg2 = ctx->cfg.bg[2];
+  // log2 alpha <= log2 o at every pixel (the quadratic form is negative
+  // semi-definite and its rounded terms keep their signs), and the hardware
+  // exp2 errs by a few ulp, far below the 1e-3 margin: below this bound
+  // exp2(log2 alpha) < alpha_max, so the clamp at alpha_max is the identity
+  P.log2_amax_lo = log2f(ctx->cfg.alpha_max) - 1e-3f;
   return P;
 }
 

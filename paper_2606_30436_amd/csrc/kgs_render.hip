@@ -438,12 +438,12 @@ __device__ __forceinline__ void wave_reduce20(float (&x)[20], int lane, int& idx
 // clamped at alpha_max): with log2 alpha = log2 o + P' u^2 + E' dy^2 and
 // u = dx + k dy, the pair's P', k, E' and ln 2 turn their sums into the
 // record-space derivatives.  x[6..9] = alpha_j T_j g (colour and depth).
-template <bool DEPTH>
+template <bool DEPTH, bool CLAMP>
 __device__ __forceinline__ void blend_terms(float e, float u, float dy, const float4& r1, const float4& r2,
                                             float amax, float g0, float g1, float g2, float gD, float& T, float& Rj,
                                             float* __restrict__ x) {
   const float raw = exp2_approx(e);
-  const float a = fminf(raw, amax);
+  const float a = CLAMP ? fminf(raw, amax) : raw;
   const float wgt = a * T;
   // without a depth gradient (gD = 0) the depth terms are zero and left out
   const float gcc = fmaf(g2, r2.z, fmaf(g1, r2.y, g0 * r2.x));
@@ -455,7 +455,7 @@ __device__ __forceinline__ void blend_terms(float e, float u, float dy, const fl
   x[7] = wgt * g1;
   x[8] = wgt * g2;
   x[9] = DEPTH ? wgt * gD : 0.f;
-  const float ge = raw < amax ? dLda * a : 0.f;
+  const float ge = !CLAMP || raw < amax ? dLda * a : 0.f;
   const float gu = ge * u, gd = ge * dy;
   x[0] = gu;
   x[1] = gd;
@@ -468,8 +468,10 @@ __device__ __forceinline__ void blend_terms(float e, float u, float dy, const fl
 
 // The same terms summed over a lane's two pixels, which share a row and so dy:
 // the moments with a factor dy are formed once from the pixel sums,
-// sum ge dy = dy sum ge and so on, instead of per pixel.
-template <bool DEPTH>
+// sum ge dy = dy sum ge and so on, instead of per pixel.  Without CLAMP the
+// caller knows that no record of the batch reaches alpha_max, and the clamp
+// and its zero derivative are left out (the same values).
+template <bool DEPTH, bool CLAMP>
 __device__ __forceinline__ void blend_terms2(const float (&e)[2], const float (&u)[2], float dy,
                                              const float4& r1, const float4& r2, float amax, const float (&g0)[2],
                                              const float (&g1)[2], const float (&g2)[2], const float (&gD)[2],
@@ -478,7 +480,7 @@ __device__ __forceinline__ void blend_terms2(const float (&e)[2], const float (&
 #pragma unroll
   for (int p = 0; p < 2; ++p) {
     const float raw = exp2_approx(e[p]);
-    const float a = fminf(raw, amax);
+    const float a = CLAMP ? fminf(raw, amax) : raw;
     const float wgt = a * T[p];
     const float gcc = fmaf(g2[p], r2.z, fmaf(g1[p], r2.y, g0[p] * r2.x));
     const float gc = DEPTH ? fmaf(gD[p], r1.z, gcc) : gcc;
@@ -496,7 +498,7 @@ __device__ __forceinline__ void blend_terms2(const float (&e)[2], const float (&
       x[8] = fmaf(wgt, g2[p], x[8]);
       x[9] = DEPTH ? fmaf(wgt, gD[p], x[9]) : 0.f;
     }
-    ge[p] = raw < amax ? dLda * a : 0.f;
+    ge[p] = !CLAMP || raw < amax ? dLda * a : 0.f;
     gu[p] = ge[p] * u[p];
     T[p] = T[p] * oma;
   }
@@ -640,6 +642,7 @@ __global__ __launch_bounds__(64 * NW) void k_render_bwd(
     uint32_t len = 0;
     float xbw[R], ybw[R];
     uint32_t firstp[R];
+    uint64_t clamp_bal = 0ull;  // kept records that may reach alpha_max somewhere
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int bi = r * 64 + l;
@@ -668,6 +671,7 @@ __global__ __launch_bounds__(64 * NW) void k_render_bwd(
         }
       }
       const uint64_t bal = ballot64(keep);
+      clamp_bal |= bal & ballot64(r1.y >= P.log2_amax_lo);
       if (keep) {
         const uint32_t q = len + mask_lt_count(bal);
         s_rec[w][q][0] = r0;
@@ -687,103 +691,110 @@ __global__ __launch_bounds__(64 * NW) void k_render_bwd(
       return (int)((__builtin_amdgcn_readlane(packed, (int)(j >> 2)) >> (8u * (j & 3u))) & 0xffu);
     };
     // list entries two at a time: a pair of entries that both blend shares one
-    // reduction of twenty values; otherwise the one that blends is reduced alone
-    for (uint32_t j = 0; j < len;) {
-      const int ta = entry(j);  // batch index, the same for the whole wave
-      if (rel0 + ta >= wmax) break;
-      const bool has_b = j + 1 < len;
-      const uint32_t jb = has_b ? j + 1 : j;
-      const int tb = entry(jb);
-      const bool use_b = has_b && rel0 + tb < wmax;
-      // both entries' records at once (the second is a repeat of the first when absent)
-      const float4 ra0 = s_rec[w][j][0], ra1 = s_rec[w][j][1], rb0 = s_rec[w][jb][0], rb1 = s_rec[w][jb][1];
-      float ea[PPL], ua[PPL], dya[PPL], eb[PPL], ub[PPL], dyb[PPL];
-      // one ballot per entry and pixel of the lane; the entry blends in the wave if any of them is set
-      uint64_t bal_a[PPL], bal_b[PPL], bba = 0ull, bbb = 0ull;
+    // reduction of twenty values; otherwise the one that blends is reduced alone.
+    // Batches in which no kept record can reach alpha_max (nearly all) take the
+    // variant without the clamp.
+    auto entries = [&](auto clamp_tag) {
+      constexpr bool CL = decltype(clamp_tag)::value;
+      for (uint32_t j = 0; j < len;) {
+        const int ta = entry(j);  // batch index, the same for the whole wave
+        if (rel0 + ta >= wmax) break;
+        const bool has_b = j + 1 < len;
+        const uint32_t jb = has_b ? j + 1 : j;
+        const int tb = entry(jb);
+        const bool use_b = has_b && rel0 + tb < wmax;
+        // both entries' records at once (the second is a repeat of the first when absent)
+        const float4 ra0 = s_rec[w][j][0], ra1 = s_rec[w][j][1], rb0 = s_rec[w][jb][0], rb1 = s_rec[w][jb][1];
+        float ea[PPL], ua[PPL], dya[PPL], eb[PPL], ub[PPL], dyb[PPL];
+        // one ballot per entry and pixel of the lane; the entry blends in the wave if any of them is set
+        uint64_t bal_a[PPL], bal_b[PPL], bba = 0ull, bbb = 0ull;
 #pragma unroll
-      for (int p = 0; p < PPL; ++p) {
-        ea[p] = log2_alpha(fpx[p], fpy, ra0, ra1.x, ra1.y, dya[p], ua[p]);
-        eb[p] = log2_alpha(fpx[p], fpy, rb0, rb1.x, rb1.y, dyb[p], ub[p]);
-        // each ballot of a single compare, the masks combined in scalar registers
-        // (a ballot of a combined condition goes through a vector register)
-        const bool ina = rel0 + ta < lastp[p], inb = rel0 + tb < lastp[p];
-        const bool hta = ea[p] >= P.log2_amin, htb = eb[p] >= P.log2_amin;
-        const bool bla = ina & hta, blb = use_b & inb & htb;
-        bal_a[p] = ballot64(ina) & ballot64(hta);
-        bal_b[p] = ballot64(inb) & ballot64(htb) & (0ull - (uint64_t)use_b);
-        bba |= bal_a[p];
-        bbb |= bal_b[p];
-        // a pixel that does not blend the entry takes alpha = exp2(-inf) = 0 in the terms below
-        ea[p] = bla ? ea[p] : -INFINITY;
-        eb[p] = blb ? eb[p] : -INFINITY;
-      }
-      // blended pixels of the wave, and those under the error mask
-      uint32_t na = 0u, nma = 0u, nb = 0u, nmb = 0u;
-#pragma unroll
-      for (int p = 0; p < PPL; ++p) {
-        na += (uint32_t)__popcll(bal_a[p]);
-        nma += (uint32_t)__popcll(bal_a[p] & Mbal[p]);
-        nb += (uint32_t)__popcll(bal_b[p]);
-        nmb += (uint32_t)__popcll(bal_b[p] & Mbal[p]);
-      }
-      if (bba != 0ull && bbb != 0ull) {
-        float x[20];
-        const float4 ra2 = s_rec[w][j][2], rb2 = s_rec[w][jb][2];
-        if constexpr (PPL == 2) {
-          // entry a for both pixels, then entry b: each pixel's T and Rj still
-          // see a before b
-          blend_terms2<DEPTH>(ea, ua, dya[0], ra1, ra2, P.amax, g0, g1, g2, gD, T, Rj, x);
-          blend_terms2<DEPTH>(eb, ub, dyb[0], rb1, rb2, P.amax, g0, g1, g2, gD, T, Rj, x + 10);
-        } else {
-          blend_terms<DEPTH>(ea[0], ua[0], dya[0], ra1, ra2, P.amax, g0[0], g1[0], g2[0], gD[0], T[0],
-                             Rj[0], x);
-          blend_terms<DEPTH>(eb[0], ub[0], dyb[0], rb1, rb2, P.amax, g0[0], g1[0], g2[0], gD[0], T[0],
-                             Rj[0], x + 10);
+        for (int p = 0; p < PPL; ++p) {
+          ea[p] = log2_alpha(fpx[p], fpy, ra0, ra1.x, ra1.y, dya[p], ua[p]);
+          eb[p] = log2_alpha(fpx[p], fpy, rb0, rb1.x, rb1.y, dyb[p], ub[p]);
+          // each ballot of a single compare, the masks combined in scalar registers
+          // (a ballot of a combined condition goes through a vector register)
+          const bool ina = rel0 + ta < lastp[p], inb = rel0 + tb < lastp[p];
+          const bool hta = ea[p] >= P.log2_amin, htb = eb[p] >= P.log2_amin;
+          const bool bla = ina & hta, blb = use_b & inb & htb;
+          bal_a[p] = ballot64(ina) & ballot64(hta);
+          bal_b[p] = ballot64(inb) & ballot64(htb) & (0ull - (uint64_t)use_b);
+          bba |= bal_a[p];
+          bbb |= bal_b[p];
+          // a pixel that does not blend the entry takes alpha = exp2(-inf) = 0 in the terms below
+          ea[p] = bla ? ea[p] : -INFINITY;
+          eb[p] = blb ? eb[p] : -INFINITY;
         }
-        int idx;
-        bool valid;
-        wave_reduce20<DEPTH ? 10 : 9>(x, l, idx, valid);
-        if (valid) s_part[w][idx < 10 ? ta : tb][idx < 10 ? idx : idx - 10] = x[0];
-        if (l == 0) {
-          s_part[w][ta][10] = __uint_as_float(na);
-          s_part[w][ta][11] = __uint_as_float(nma);
-          s_part[w][tb][10] = __uint_as_float(nb);
-          s_part[w][tb][11] = __uint_as_float(nmb);
-        }
-      } else if ((bba | bbb) != 0ull) {
-        const bool first = bba != 0ull;
-        const int tt = first ? ta : tb, tz = first ? tb : ta;
-        const float4 q1 = first ? ra1 : rb1, q2 = s_rec[w][first ? j : jb][2];
-        float x[10];
-        if constexpr (PPL == 2) {
-          float e2[2], u2[2];
+        // blended pixels of the wave, and those under the error mask
+        uint32_t na = 0u, nma = 0u, nb = 0u, nmb = 0u;
 #pragma unroll
-          for (int p = 0; p < 2; ++p) {
-            e2[p] = first ? ea[p] : eb[p];
-            u2[p] = first ? ua[p] : ub[p];
+        for (int p = 0; p < PPL; ++p) {
+          na += (uint32_t)__popcll(bal_a[p]);
+          nma += (uint32_t)__popcll(bal_a[p] & Mbal[p]);
+          nb += (uint32_t)__popcll(bal_b[p]);
+          nmb += (uint32_t)__popcll(bal_b[p] & Mbal[p]);
+        }
+        if (bba != 0ull && bbb != 0ull) {
+          float x[20];
+          const float4 ra2 = s_rec[w][j][2], rb2 = s_rec[w][jb][2];
+          if constexpr (PPL == 2) {
+            // entry a for both pixels, then entry b: each pixel's T and Rj still
+            // see a before b
+            blend_terms2<DEPTH, CL>(ea, ua, dya[0], ra1, ra2, P.amax, g0, g1, g2, gD, T, Rj, x);
+            blend_terms2<DEPTH, CL>(eb, ub, dyb[0], rb1, rb2, P.amax, g0, g1, g2, gD, T, Rj, x + 10);
+          } else {
+            blend_terms<DEPTH, CL>(ea[0], ua[0], dya[0], ra1, ra2, P.amax, g0[0], g1[0], g2[0], gD[0], T[0],
+                               Rj[0], x);
+            blend_terms<DEPTH, CL>(eb[0], ub[0], dyb[0], rb1, rb2, P.amax, g0[0], g1[0], g2[0], gD[0], T[0],
+                               Rj[0], x + 10);
           }
-          blend_terms2<DEPTH>(e2, u2, first ? dya[0] : dyb[0], q1, q2, P.amax, g0, g1, g2, gD, T, Rj, x);
+          int idx;
+          bool valid;
+          wave_reduce20<DEPTH ? 10 : 9>(x, l, idx, valid);
+          if (valid) s_part[w][idx < 10 ? ta : tb][idx < 10 ? idx : idx - 10] = x[0];
+          if (l == 0) {
+            s_part[w][ta][10] = __uint_as_float(na);
+            s_part[w][ta][11] = __uint_as_float(nma);
+            s_part[w][tb][10] = __uint_as_float(nb);
+            s_part[w][tb][11] = __uint_as_float(nmb);
+          }
+        } else if ((bba | bbb) != 0ull) {
+          const bool first = bba != 0ull;
+          const int tt = first ? ta : tb, tz = first ? tb : ta;
+          const float4 q1 = first ? ra1 : rb1, q2 = s_rec[w][first ? j : jb][2];
+          float x[10];
+          if constexpr (PPL == 2) {
+            float e2[2], u2[2];
+#pragma unroll
+            for (int p = 0; p < 2; ++p) {
+              e2[p] = first ? ea[p] : eb[p];
+              u2[p] = first ? ua[p] : ub[p];
+            }
+            blend_terms2<DEPTH, CL>(e2, u2, first ? dya[0] : dyb[0], q1, q2, P.amax, g0, g1, g2, gD, T, Rj, x);
+          } else {
+            blend_terms<DEPTH, CL>(first ? ea[0] : eb[0], first ? ua[0] : ub[0], first ? dya[0] : dyb[0], q1, q2,
+                               P.amax, g0[0], g1[0], g2[0], gD[0], T[0], Rj[0], x);
+          }
+          int idx;
+          bool valid;
+          wave_reduce10(x, l, idx, valid);
+          if (valid) s_part[w][tt][idx] = x[0];
+          if (l == 0) {
+            s_part[w][tt][10] = __uint_as_float(first ? na : nb);
+            s_part[w][tt][11] = __uint_as_float(first ? nma : nmb);
+          }
+          // the other entry blends nowhere in this wave: its partial is zero
+          if (use_b && l < 12) s_part[w][tz][l] = 0.f;
         } else {
-          blend_terms<DEPTH>(first ? ea[0] : eb[0], first ? ua[0] : ub[0], first ? dya[0] : dyb[0], q1, q2,
-                             P.amax, g0[0], g1[0], g2[0], gD[0], T[0], Rj[0], x);
+          if (l < 12) s_part[w][ta][l] = 0.f;
+          if (use_b && l < 12) s_part[w][tb][l] = 0.f;
         }
-        int idx;
-        bool valid;
-        wave_reduce10(x, l, idx, valid);
-        if (valid) s_part[w][tt][idx] = x[0];
-        if (l == 0) {
-          s_part[w][tt][10] = __uint_as_float(first ? na : nb);
-          s_part[w][tt][11] = __uint_as_float(first ? nma : nmb);
-        }
-        // the other entry blends nowhere in this wave: its partial is zero
-        if (use_b && l < 12) s_part[w][tz][l] = 0.f;
-      } else {
-        if (l < 12) s_part[w][ta][l] = 0.f;
-        if (use_b && l < 12) s_part[w][tb][l] = 0.f;
+        if (has_b && !use_b) break;
+        j += use_b ? 2u : 1u;
       }
-      if (has_b && !use_b) break;
-      j += use_b ? 2u : 1u;
-    }
+    };
+    if (clamp_bal) entries(BoolC<true>{});
+    else entries(BoolC<false>{});
     __syncthreads();
     // the first wave sums the waves' partials of every pair in wave order and
     // writes the pair's record
