@@ -33,6 +33,12 @@ def _scene(name):
         return scenes.tiny_scene(seed=5, n=300, degree=1, W=600, H=450, n_views=3, pose_sigma=0.03)
     if name == "tiny_bg":
         return scenes.tiny_scene(seed=4, n=80, degree=2, W=53, H=37, n_views=3, pose_sigma=0.03)
+    if name == "tiny_opaque":
+        # opacities sigmoid(N(3, 1.5)): about one Gaussian in seven at or above alpha_max = 0.99, so
+        # that the compositing passes meet the clamp (and the backward its variant with the clamp)
+        sc = scenes.tiny_scene(seed=6, n=80, degree=2, W=61, H=43, n_views=2, pose_sigma=0.02)
+        sc.logits[:] = np.random.default_rng(16).normal(3.0, 1.5, sc.n).astype(np.float32)
+        return sc
     raise KeyError(name)
 
 
@@ -246,7 +252,7 @@ def test_a_view_that_sees_nothing():
         assert np.linalg.norm(got - ref[k]) <= 1e-3 * np.linalg.norm(ref[k]), k
 
 
-@pytest.mark.parametrize("name", ["c1", "tiny", "tiny_bg"])
+@pytest.mark.parametrize("name", ["c1", "tiny", "tiny_bg", "tiny_opaque"])
 def test_render_forward_matches_oracle(name):
     sc = _scene(name)
     kw = {"bg": (0.2, 0.5, 0.9)} if name == "tiny_bg" else {}
@@ -299,12 +305,14 @@ def _affected(sc, cfg):
 
 @pytest.mark.parametrize("px", [1, 2])
 @pytest.mark.parametrize("name,depth", [("c1", True), ("tiny", True), ("tiny_bg", True), ("c1", False),
-                                        ("tiny", False)])
+                                        ("tiny", False), ("tiny_opaque", True), ("tiny_opaque", False)])
 def test_render_backward_matches_oracle(name, depth, px):
     """With and without a depth gradient (the backward has a variant that
     leaves the depth terms out when none is passed), with one and two pixels
-    per lane."""
+    per lane, and with opacities at the alpha_max clamp."""
     sc = _scene(name)
+    if name == "tiny_opaque":
+        assert (1.0 / (1.0 + np.exp(-sc.logits.astype(np.float64))) >= 0.99).sum() >= 5
     kw = {"bg": (0.2, 0.5, 0.9)} if name == "tiny_bg" else {}
     say(f"[gpu] render bwd {name} depth={depth} px_per_lane={px}")
     R = _rast(sc, px_per_lane=px, **kw)
