@@ -160,6 +160,20 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
+// threads of the small per-view reductions (the loss finals)
+#define KGS_FINAL_THREADS 256
+
+// Sum over a KGS_FINAL_THREADS workgroup in a fixed order: a butterfly in each
+// wave, then the four wave sums as (w0 + w1) + (w2 + w3).  Thread 0 gets the
+// total; sh holds four values.  Every thread of the workgroup must call it.
+__device__ __forceinline__ double block_sum_fixed(double v, double* sh) {
+  static_assert(KGS_FINAL_THREADS == 256, "four waves");
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
 // Block-wide (256 threads) exclusive scan of two u32 values in thread order.
 // Returns the exclusive prefixes and the block totals.  Uses 16 words of LDS.
 __device__ __forceinline__ void block_scan2(uint32_t a, uint32_t b, uint32_t* sh, uint32_t& ea, uint32_t& eb,

@@ -242,23 +242,27 @@ __global__ __launch_bounds__(256) void k_ssim_bwd(MapLossParams P, const float* 
   }
 }
 
-// One wave per view: the (channel, tile) partials summed in a fixed order.
-__global__ __launch_bounds__(64) void k_maploss_final(int n_tiles, double inv_n3, double inv_n, float w_l1,
-                                                      float w_ssim, const double* __restrict__ partial,
-                                                      float* __restrict__ view_loss, float* __restrict__ geo_loss) {
+// One workgroup per view: the (channel, tile) partials summed in a fixed order
+// (per thread, then a fixed tree over the workgroup).
+__global__ __launch_bounds__(KGS_FINAL_THREADS) void k_maploss_final(int n_tiles, double inv_n3, double inv_n,
+                                                                     float w_l1, float w_ssim,
+                                                                     const double* __restrict__ partial,
+                                                                     float* __restrict__ view_loss,
+                                                                     float* __restrict__ geo_loss) {
+  __shared__ double sh[3][KGS_FINAL_THREADS / 64];
   const int v = blockIdx.x, l = threadIdx.x;
   double s = 0.0, a = 0.0, g = 0.0;
   for (int ch = 0; ch < 3; ++ch) {
     const double* p = partial + ((size_t)v * 3 + ch) * n_tiles * 3;
-    for (int t = l; t < n_tiles; t += 64) {
+    for (int t = l; t < n_tiles; t += KGS_FINAL_THREADS) {
       s += p[3 * t];
       a += p[3 * t + 1];
       g += p[3 * t + 2];
     }
   }
-  s = wave_sum(s);
-  a = wave_sum(a);
-  g = wave_sum(g);
+  s = block_sum_fixed(s, sh[0]);
+  a = block_sum_fixed(a, sh[1]);
+  g = block_sum_fixed(g, sh[2]);
   if (l == 0) {
     view_loss[v] = (float)((double)w_l1 * a * inv_n3 + (double)w_ssim * s * inv_n3);
     if (geo_loss) geo_loss[v] = (float)(g * inv_n);
@@ -340,7 +344,7 @@ kgs_status kgs_launch_loss_mapping(kgs_ctx* ctx, int V, const float* target, con
                      ctx->ssim_aux, ctx->ssim_partial);
   hipLaunchKernelGGL(k_ssim_bwd, grid, dim3(256), 0, st, P, (const float*)img->color, target,
                      (const float*)ctx->ssim_aux, dl_dcolor);
-  hipLaunchKernelGGL(k_maploss_final, dim3((unsigned)V), dim3(64), 0, st, P.n_tiles, 1.0 / (3.0 * npix), 1.0 / npix,
+  hipLaunchKernelGGL(k_maploss_final, dim3((unsigned)V), dim3(KGS_FINAL_THREADS), 0, st, P.n_tiles, 1.0 / (3.0 * npix), 1.0 / npix,
                      w_l1, w_ssim, (const double*)ctx->ssim_partial, view_loss,
                      with_depth ? geo_loss : (float*)nullptr);
   return kgs_check_launch();

@@ -327,14 +327,17 @@ __global__ __launch_bounds__(64 * NW) void k_loss_l1(RenderParams P, const float
   l1_partial<NW, 1>(acc, sh, partial, gt);
 }
 
-// one wave per view: lane l adds tiles l, l + 64, ... in order, then a fixed
-// butterfly over the lanes
-__global__ __launch_bounds__(64) void k_loss_final(int n_tiles, double inv_n, const double* __restrict__ partial,
-                                                   float* __restrict__ view_loss) {
+// one workgroup of KGS_FINAL_THREADS per view: thread l adds tiles l, l + 256,
+// ... in order, then a fixed butterfly over each wave and the four wave sums
+// in a fixed tree (a single wave walking all the tiles was latency-bound)
+__global__ __launch_bounds__(KGS_FINAL_THREADS) void k_loss_final(int n_tiles, double inv_n,
+                                                                  const double* __restrict__ partial,
+                                                                  float* __restrict__ view_loss) {
+  __shared__ double sh[KGS_FINAL_THREADS / 64];
   const int v = blockIdx.x, l = threadIdx.x;
   double s = 0.0;
-  for (int b = l; b < n_tiles; b += 64) s += partial[(size_t)v * n_tiles + b];
-  s = wave_sum(s);
+  for (int b = l; b < n_tiles; b += KGS_FINAL_THREADS) s += partial[(size_t)v * n_tiles + b];
+  s = block_sum_fixed(s, sh);
   if (l == 0) view_loss[v] = (float)(s * inv_n);
 }
 
@@ -893,7 +896,8 @@ void kgs_launch_loss_final(kgs_ctx* ctx, float* view_loss, hipStream_t st) {
   const int V = ctx->last_views;
   const double inv_n = 1.0 / (3.0 * (double)ctx->cfg.width * (double)ctx->cfg.height);
   if (V > 0)
-    hipLaunchKernelGGL(k_loss_final, dim3(V), dim3(64), 0, st, ctx->n_tiles, inv_n, (const double*)ctx->loss_partial,
+    hipLaunchKernelGGL(k_loss_final, dim3(V), dim3(KGS_FINAL_THREADS), 0, st, ctx->n_tiles, inv_n,
+                       (const double*)ctx->loss_partial,
                        view_loss);
 }
 
