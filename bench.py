@@ -131,8 +131,8 @@ def main():
                     help="only copy BYTES device-to-device three times (HBM counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the multi-GPU layout is described in DESIGN.md, not run)", file=sys.stderr)
+        print(f"bench.py: one GPU only; --gpus {args.gpus} is not supported "
+              "(sharding the views over GPUs is a design, not run)", file=sys.stderr)
         sys.exit(2)
 
     import torch

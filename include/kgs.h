@@ -535,7 +535,7 @@ kgs_status kgs_densify_prune_decide(kgs_ctx* ctx, const kgs_lifecycle_state* sta
  * Learned prune / keep / densify head.  A small network predicts the plain
  * criterion's decision (kgs_densify_prune_decide, Sec. 3.3 and App. D) from a
  * Gaussian's statistics; it is trained on that criterion's decisions, which
- * stay the fallback and the judge of its agreement.  MLP 16 -> 64 -> 64 -> 3,
+ * stay the fallback and the reference for its agreement.  MLP 16 -> 64 -> 64 -> 3,
  * ReLU after both hidden layers, logits out; every GEMM takes BF16 operands
  * (round to nearest even) on the matrix cores with FP32 accumulation.
  * Parameters: one FP32 device vector theta[KGS_HEAD_PARAMS] laid out as

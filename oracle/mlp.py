@@ -3,7 +3,7 @@ the GPU path made explicit.  TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
 
 The learned part replaces the plain multi-view criterion of Sec. 3.3 / App. D
 with a small classifier over per-Gaussian statistics; the criterion's decision
-(KEEP 0, DENSIFY 1, PRUNE 2) is its training label and the judge of its
+(KEEP 0, DENSIFY 1, PRUNE 2) is its training label and the reference for its
 agreement.  The paper does not state the network, its activation or its loss.
 Readings:
   * MLP 16 -> 64 -> 64 -> 3, ReLU after the two hidden layers, logits out;
